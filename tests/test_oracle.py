@@ -1,0 +1,390 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test checks the oracle against something the paper or mathematics
+fixes: closed forms (a two-atom system solved by hand, the far-field and
+contact limits of the damped Coulomb kernel, the Fermi midpoint), invariants
+stated in the paper (symmetry and positive definiteness of D, zero row sums of
+Kbar - P, the D-symmetry of A, real spectrum), exact limits (static conductor
+limit, high-frequency expansion), independent algorithms (LU vs the modal
+eigen-decomposition, k-d tree vs all-pairs neighbour search) and the
+structure sizes the paper prints.
+"""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse
+
+from oracle import wfq_oracle as O
+import wfq_inputs as wi
+from wfq_inputs import geometry as geo
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+G = wi.workloads.GRAPHENE
+FCC = wi.workloads.FCC_METAL
+
+
+def small_problem(seed=7, radius=9.0, params=G):
+    xyz = geo.jitter(geo.graphene_disk(radius), 0.02, seed)
+    return O.Problem(xyz, params)
+
+
+# ----------------------------------------------------------------- damped Coulomb kernel D = T
+
+def test_coulomb_far_field_is_bare_coulomb():
+    # erf(x) -> 1 for x >> 1, so D_ij -> 1 / r_ij (the damping only acts at short range).
+    ri, rj = np.zeros(3), np.array([40.0, 0.0, 0.0])
+    assert O.coulomb_element(ri, rj, 0.6, 0.6) == pytest.approx(1.0 / 40.0, rel=1e-15)
+
+
+def test_coulomb_contact_limit_is_hardness():
+    # Widths are fixed so that D_ij -> eta as r_ij -> 0 (width-from-hardness equation).
+    eta = 0.5947
+    for h in (1e-3, 1e-5):
+        v = O.coulomb_element(np.zeros(3), np.array([h, 0, 0]), eta, eta)
+        assert v == pytest.approx(eta, rel=2 * h * h)   # erf(x)/x = 2/sqrt(pi) (1 - x^2/3 + ...)
+
+
+def test_coulomb_series_at_small_argument():
+    # erf(x)/x = (2/sqrt(pi)) (1 - x^2/3 + x^4/10 - ...), x = r / sqrt(d_i^2 + d_j^2), two different species.
+    ei, ej = 0.6, 0.3
+    di, dj = math.sqrt(2 / math.pi) / ei, math.sqrt(2 / math.pi) / ej
+    s = math.sqrt(di * di + dj * dj)
+    r = 0.05
+    x = r / s
+    expect = 2 / math.sqrt(math.pi) / s * (1 - x * x / 3 + x ** 4 / 10 - x ** 6 / 42)
+    assert O.coulomb_element(np.zeros(3), np.array([0, r, 0]), ei, ej) == pytest.approx(expect, rel=1e-13)
+
+
+def test_coulomb_matrix_symmetric_positive_definite():
+    P = small_problem()
+    T = P.T
+    assert np.array_equal(T, T.T)
+    assert np.allclose(np.diag(T), P.eta)
+    np.linalg.cholesky(T)  # D is SPD (Gaussian overlap in the 1/r metric)
+
+
+def test_coulomb_rows_match_elements():
+    P = small_problem()
+    rng = np.random.default_rng(0)
+    for i, j in rng.integers(0, P.n, size=(20, 2)):
+        assert P.T[i, j] == pytest.approx(O.coulomb_element(P.xyz[i], P.xyz[j], P.eta[i], P.eta[j]), rel=1e-14)
+
+
+# ----------------------------------------------------------------- Fermi damping, Kbar, L
+
+def test_fermi_midpoint_and_limits():
+    r0, d, s = 2.0, 12.0, 1.1
+    assert O.fermi(s * r0, r0, d, s) == 0.5
+    assert O.fermi(1e-9, r0, d, s) < 1e-5           # short range: Drude regime (f -> 0)
+    assert 1.0 - O.fermi(50.0, r0, d, s) < 1e-100   # long range: tunnelling switched off
+
+
+def test_fermi_values_graphene_by_hand():
+    # 1 - f(r) = 1 / (1 + exp(d (r / (s r0) - 1))), evaluated by hand for d = 12, s = 1.1, r0 = 1.42 A.
+    r0 = 1.42
+    for r, expect in ((1.42, 1.0 / (1.0 + math.exp(12 * (1 / 1.1 - 1)))),
+                      (2.4595, 1.0 / (1.0 + math.exp(12 * (2.4595 / 1.562 - 1))))):
+        assert 1.0 - O.fermi(r, r0, 12.0, 1.1) == pytest.approx(expect, rel=1e-13)
+    assert 1.0 - O.fermi(1.42, r0, 12, 1.1) == pytest.approx(0.74855, abs=1e-5)   # exp(-12/11) = 0.33596...
+
+
+def test_cutoff_radius_definition():
+    r0, d, s, eps = 2.68, 12.0, 1.1, 1e-12
+    rc = O.cutoff_radius(r0, d, s, eps)
+    assert 1.0 - O.fermi(rc, r0, d, s) == pytest.approx(eps, rel=1e-9)
+    # graphene: 36 ideal-lattice neighbours inside r_c (shells 3+6+3+6+6+6+6)
+    lat = O.angstrom_to_bohr(geo.graphene_disk(12.0))
+    c = np.argmin(np.sum(lat ** 2, axis=1))
+    rcg = O.cutoff_radius(1.42 / O.BOHR_A, 12, 1.1, 1e-12)
+    r = np.sqrt(np.sum((lat - lat[c]) ** 2, axis=1))
+    assert np.sum((r > 0) & (r < rcg)) == 36
+
+
+def test_kbar_tree_matches_all_pairs():
+    P = small_problem()
+    K = O.kbar_matrix(P.xyz, P.r0, P.fd, P.fs, P.rc).toarray()
+    Kb = O.kbar_rows_bruteforce(P.xyz, P.r0, P.fd, P.fs, P.rc, np.arange(P.n))
+    assert np.array_equal(K != 0, Kb != 0)
+    assert np.allclose(K, Kb, rtol=1e-14, atol=0)
+
+
+def test_laplacian_structure():
+    P = small_problem()
+    L = P.L.toarray()
+    assert np.array_equal(L, L.T)
+    assert np.max(np.abs(L.sum(axis=1))) < 1e-14 * np.max(np.abs(L))   # rows of Kbar - P sum to zero
+    off = L - np.diag(np.diag(L))
+    assert np.all(off <= 0)
+    w = np.linalg.eigvalsh(L)
+    assert w[0] > -1e-12 and abs(w[0]) < 1e-12     # PSD, singular
+    assert w[1] > 1e-6                               # connected: the zero eigenvalue is simple
+
+
+def test_laplacian_rows_bruteforce():
+    P = small_problem()
+    rows = np.array([0, 5, P.n - 1])
+    assert np.allclose(O.laplacian_rows_bruteforce(P.xyz, P.r0, P.fd, P.fs, P.rc, rows),
+                       P.L.toarray()[rows], rtol=1e-14, atol=1e-16)
+
+
+# ----------------------------------------------------------------- shift, operator algebra
+
+def test_shift_matches_paper_forms():
+    # z = -i omega / w(omega)  and  z = -(omega / (2 n0 tau)) (omega tau + i), with 2 n0 -> W.
+    W, tau = 0.0289, 170.0
+    om = np.array([1e-3, 0.011, 0.05, 0.2])
+    z = O.shift(om, W, tau)
+    assert np.allclose(z, -1j * om / O.drude_factor(om, W, tau), rtol=1e-15)
+    assert np.allclose(z, -(om / (W * tau)) * (om * tau + 1j), rtol=1e-15)
+    assert np.all(z.imag < 0) and np.all(z.real < 0)
+
+
+def test_operator_d_symmetry():
+    # D A = A^T D (Eq. a-matrix-d) for A = (Kbar - P) D, hence T M = M^T T for M = L T + z I.
+    P = small_problem()
+    M = O.dense_operator(P.L, P.T, 0.01 - 0.003j)
+    TM = P.T @ M
+    assert np.allclose(TM, TM.T, rtol=0, atol=1e-12 * np.max(np.abs(TM)))
+    A = -(P.L.toarray() @ P.T)
+    assert not np.allclose(A, A.T)      # A itself is nonsymmetric
+
+
+def test_operator_real_nonnegative_spectrum():
+    # A is D-self-adjoint, so diagonalisable with real eigenvalues; L T is PSD-like (eigenvalues >= 0).
+    P = small_problem()
+    ev = np.linalg.eigvals(P.L.toarray() @ P.T)
+    scale = np.max(np.abs(ev))
+    assert np.max(np.abs(ev.imag)) < 1e-10 * scale
+    assert np.min(ev.real) > -1e-10 * scale
+    assert np.sum(np.abs(ev) < 1e-10 * scale) == 1   # singular, exactly one zero mode (connected)
+
+
+# ----------------------------------------------------------------- solutions
+
+def test_dimer_closed_form_two_species():
+    # Two atoms: Sum q = 0 gives q = c (1, -1) and (k (eta1 + eta2 - 2 t) + z) c = E0 k dx.
+    r_A = 1.7
+    xyz = np.array([[0.0, 0.0, 0.0], [r_A, 0.0, 0.0]])
+    params = dict(G, eta=np.array([0.6, 0.35]))
+    P = O.Problem(xyz, params)
+    r = r_A / O.BOHR_A
+    k = (1.0 - 1.0 / (1.0 + math.exp(-12.0 * (r / (1.1 * P.r0) - 1.0)))) / r
+    d1, d2 = math.sqrt(2 / math.pi) / 0.6, math.sqrt(2 / math.pi) / 0.35
+    t = math.erf(r / math.sqrt(d1 * d1 + d2 * d2)) / r
+    for om in (0.1, 0.7, 3.0):
+        z = -((om / 27.211386245988) ** 2 + 1j * (om / 27.211386245988) / 170.0) / G["W"]
+        alpha_xx = k * r * r / (k * (0.6 + 0.35 - 2 * t) + z)
+        q = P.solve_lu(om, [1, 0, 0])
+        a = O.polarisability(P.xyz, q[:, None])
+        assert a[0, 0] == pytest.approx(alpha_xx, rel=1e-13)
+        assert abs(q[0] + q[1]) < 1e-15 * abs(q[0])
+
+
+def test_lu_matches_modal_closed_form():
+    P = small_problem(radius=11.0)
+    R = P.xyz.copy()
+    for om in (0.2, 0.9):
+        z = P.z(om)
+        Q_modal = O.solve_modal(P.L, P.T, z, R)
+        for k in range(3):
+            q = P.solve_lu(om, np.eye(3)[k])
+            assert np.linalg.norm(q - Q_modal[:, k]) <= 1e-10 * np.linalg.norm(q)
+
+
+def test_static_limit():
+    P = small_problem(radius=10.0)
+    R = P.xyz
+    a0 = O.static_polarisability(P.T, R)
+    assert np.allclose(a0, a0.T) and np.all(np.linalg.eigvalsh(a0[:2, :2]) > 0)
+    om = 1e-6
+    Q = np.column_stack([P.solve_lu(om, e) for e in np.eye(3)])
+    a = O.polarisability(R, Q)
+    assert np.allclose(a[:2, :2], a0[:2, :2], rtol=1e-6, atol=1e-8 * np.max(np.abs(a0)))
+
+
+def test_high_frequency_expansion():
+    P = small_problem(radius=10.0)
+    R = P.xyz
+    L = P.L.toarray()
+    om = 400.0   # eV, far above every mode
+    z = P.z(om)
+    Q = np.column_stack([P.solve_lu(om, e) for e in np.eye(3)])
+    a = O.polarisability(R, Q)
+    a1 = R.T @ L @ R / z
+    a2 = a1 - R.T @ L @ P.T @ L @ R / z ** 2
+    err1 = np.abs(a - a1)[:2, :2].max()
+    err2 = np.abs(a - a2)[:2, :2].max()
+    assert err2 < 1e-2 * err1
+    # Drude weight pair sum: R^T L R = sum_{i<j} Kbar_ij (r_i - r_j)(r_i - r_j)^T
+    K = -(L - np.diag(np.diag(L)))
+    iu = np.triu_indices(P.n, 1)
+    dr = R[iu[0]] - R[iu[1]]
+    assert np.allclose(R.T @ L @ R, (dr * K[iu][:, None]).T @ dr, rtol=1e-12)
+
+
+def test_charge_conservation_reciprocity_passivity():
+    P = small_problem(radius=10.0)
+    for om in (0.15, 0.6, 1.4):
+        Q = np.column_stack([P.solve_lu(om, e) for e in np.eye(3)])
+        assert np.max(np.abs(Q.sum(axis=0))) < 1e-12 * np.max(np.linalg.norm(Q, axis=0))
+        a = O.polarisability(P.xyz, Q)
+        assert abs(a[0, 1] - a[1, 0]) <= 1e-10 * abs(a[0, 0])       # alpha_kl = alpha_lk, no conjugation
+        assert a[0, 0].imag > 0 and a[1, 1].imag > 0                 # absorption is positive
+        assert np.all(O.cross_section(O.ev_to_hartree(om), np.diag(a)[:2]) > 0)
+
+
+def test_translation_rotation_permutation():
+    xyz = geo.jitter(geo.nanotube(5, 5, 4), 0.02, 3)
+    om = 0.4
+
+    def alpha(x):
+        P = O.Problem(x, G)
+        return O.polarisability(P.xyz, np.column_stack([P.solve_lu(om, e) for e in np.eye(3)]))
+
+    a = alpha(xyz)
+    assert np.allclose(alpha(xyz + np.array([3.0, -7.0, 11.0])), a, rtol=1e-9, atol=1e-9 * np.abs(a).max())
+    th = 0.7
+    Rz = np.array([[math.cos(th), -math.sin(th), 0], [math.sin(th), math.cos(th), 0], [0, 0, 1]])
+    assert np.allclose(alpha(xyz @ Rz.T), Rz @ a @ Rz.T, rtol=1e-9, atol=1e-9 * np.abs(a).max())
+    perm = np.random.default_rng(1).permutation(len(xyz))
+    assert np.allclose(alpha(xyz[perm]), a, rtol=1e-10, atol=1e-10 * np.abs(a).max())
+
+
+# ----------------------------------------------------------------- iterative solvers
+
+def test_gmres_full_space_reproduces_lu():
+    P = small_problem(radius=8.0)
+    for om in (0.3, 1.1):
+        q = P.solve_lu(om, [1, 0, 0])
+        x, info = P.solve_gmres(om, [1, 0, 0], restart=P.n, tol=1e-13)
+        assert info["cycles"] == 1
+        assert np.linalg.norm(x - q) <= 1e-9 * np.linalg.norm(q)
+
+
+def test_gmres_restarted_converges_and_estimates():
+    P = small_problem(radius=10.0)
+    q = P.solve_lu(0.8, [0, 1, 0])
+    x, info = P.solve_gmres(0.8, [0, 1, 0], restart=10, tol=1e-10)
+    assert info["cycles"] > 1
+    assert info["relres"] <= 1e-10
+    h = info["history"]
+    assert all(h[i + 1] <= h[i] * (1 + 1e-12) for i in range(len(h) - 1))   # restarted GMRES never increases the residual
+    assert np.linalg.norm(x - q) <= 1e-7 * np.linalg.norm(q)
+    assert P.residual(0.8, [0, 1, 0], x) == pytest.approx(info["relres"], rel=1e-6)
+
+
+def test_qmr_matches_lu():
+    P = small_problem(radius=10.0)
+    for om, d in ((0.3, [1, 0, 0]), (1.2, [0, 1, 0])):
+        q = P.solve_lu(om, d)
+        x, info = P.solve_qmr(om, d, tol=1e-11)
+        assert not info["breakdown"]
+        assert P.residual(om, d, x) <= 1e-10
+        assert np.linalg.norm(x - q) <= 1e-8 * np.linalg.norm(q)
+        # smoothed residual norms never increase faster than the bound tau_k sqrt(k+1)
+        assert info["history"][-1] <= 1e-11
+
+
+def test_qmr_general_complex_symmetric_with_identity_j():
+    # J = I: M = A + z I with A complex symmetric, the method is COCG plus QMR smoothing.
+    rng = np.random.default_rng(5)
+    n = 60
+    B = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A = (B + B.T) / 2 + 12 * np.eye(n)
+    b = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    x, info = O.qmr_jsym(lambda v: v, lambda v: A @ v, 0.5j, b, tol=1e-12, maxiter=2000)
+    xs = np.linalg.solve(A + 0.5j * np.eye(n), b)
+    assert np.linalg.norm(x - xs) <= 1e-9 * np.linalg.norm(xs)
+    # the QMR quasi-residual never exceeds the BCG residual: smoothed history is non-increasing overall
+    assert info["history"][-1] < info["history"][0]
+
+
+def test_qmr_needs_the_j_symmetry():
+    # Without M^T J = J M (here J = I but M nonsymmetric) the recurrence does not reach the solution.
+    rng = np.random.default_rng(6)
+    n = 40
+    A = rng.standard_normal((n, n)) + 8 * np.eye(n)
+    b = rng.standard_normal(n).astype(complex)
+    x, info = O.qmr_jsym(lambda v: v, lambda v: A @ v, 0.1j, b, tol=1e-12, maxiter=n)
+    xs = np.linalg.solve(A + 0.1j * np.eye(n), b)
+    assert np.linalg.norm(x - xs) > 1e-6 * np.linalg.norm(xs)
+
+
+# ----------------------------------------------------------------- structures printed in the paper
+
+def test_paper_structure_sizes():
+    with open(os.path.join(GOLD, "paper_structures.json")) as f:
+        gold = json.load(f)
+    for c in gold["cnt"]:
+        cell = geo.nanotube_atoms_per_cell(c["n"], c["m"])
+        ncell = int(round(c["length_nm"] * 10.0 / (math.sqrt(3) * geo.A_GRAPHENE * math.sqrt(c["n"] ** 2 + c["m"] ** 2 + c["n"] * c["m"]) / math.gcd(2 * c["m"] + c["n"], 2 * c["n"] + c["m"]))))
+        assert ncell * cell == c["atoms"], c["id"]
+        d = 0.246 / math.pi * math.sqrt(c["n"] ** 2 + c["m"] ** 2 + c["n"] * c["m"])
+        assert geo.nanotube_diameter(c["n"], c["m"]) / 10.0 == pytest.approx(d, rel=2e-4)
+        if c["id"] != "CNT2":        # the table's 2.77 nm for (16,24) contradicts the printed rule (2.73 nm)
+            assert abs(d - c["d_nm"]) < 0.006
+    assert len(geo.nanotube(8, 12, 27)) == 8208
+    for g in gold["gd"]:
+        n = len(geo.graphene_disk(g["d_nm"] * 5.0))
+        assert abs(n - g["atoms"]) / g["atoms"] < 0.015, g["id"]
+
+
+def test_material_closure_matches_workload_values():
+    lat = O.angstrom_to_bohr(geo.graphene_disk(20.0))
+    c = np.argmin(np.sum(lat ** 2, axis=1))
+    area = 3 * math.sqrt(3) / 4 * (geo.A_CC / O.BOHR_A) ** 2
+    Wg = O.drude_weight_closure(lat, c, area, O.ev_to_hartree(G["fermi_energy_eV"]) / math.pi,
+                                geo.A_CC / O.BOHR_A, G["fermi_d"], G["fermi_s"], G["cutoff_eps"])
+    assert Wg == pytest.approx(G["W"], rel=1e-12)
+    latf = O.angstrom_to_bohr(geo.fcc_sphere(20.0))
+    c = np.argmin(np.sum(latf ** 2, axis=1))
+    a = geo.A_FCC / O.BOHR_A
+    Wf = O.drude_weight_closure(latf, c, a ** 3 / 4, 4 / a ** 3, FCC["r0"] / O.BOHR_A,
+                                FCC["fermi_d"], FCC["fermi_s"], FCC["cutoff_eps"])
+    assert Wf == pytest.approx(FCC["W"], rel=1e-12)
+
+
+def test_residual_rows_match_full_residual():
+    P = small_problem(radius=10.0)
+    q = P.solve_lu(0.5, [1, 0, 0]) * (1 + 1e-6)   # a slightly wrong q so the residual is not ~0
+    b = P.rhs([1, 0, 0])
+    r_full = b - P.apply(P.z(0.5))(q)
+    rows = np.array([0, 3, 17, P.n - 1])
+    assert np.allclose(P.residual_rows(0.5, [1, 0, 0], q, rows), r_full[rows], rtol=1e-10, atol=1e-14)
+
+
+def test_qmr_smoothing_of_cg_is_minres():
+    # For a real symmetric matrix and J = I, BCG is CG and QMR smoothing must give the minimal
+    # residual over the Krylov space at every step (MINRES), computed here by least squares.
+    rng = np.random.default_rng(11)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(np.linspace(1.0, 30.0, n)) @ Q.T
+    b = rng.standard_normal(n).astype(complex)
+    _, info = O.qmr_jsym(lambda v: v, lambda v: A @ v, 0.0, b, tol=0.0, maxiter=8)
+    hist = np.array(info["history"]) * np.linalg.norm(b)
+    K = np.zeros((n, 8))
+    v = b.real / np.linalg.norm(b)
+    for k in range(8):
+        K[:, k] = v
+        v = A @ v
+        v = v - K[:, :k + 1] @ (K[:, :k + 1].T @ v)
+        v = v - K[:, :k + 1] @ (K[:, :k + 1].T @ v)
+        v /= np.linalg.norm(v)
+    for k in range(1, 9):
+        AK = A @ K[:, :k]
+        y, *_ = np.linalg.lstsq(AK, b.real, rcond=None)
+        minres = np.linalg.norm(b.real - AK @ y)
+        assert hist[k] == pytest.approx(minres, rel=1e-8)
+
+
+def test_matrix_free_t_matches_stored():
+    xyz = geo.jitter(geo.graphene_disk(8.0), 0.02, 3)
+    Pd = O.Problem(xyz, G)
+    Pf = O.Problem(xyz, G, dense_T=False)
+    x = np.random.default_rng(2).standard_normal((Pd.n, 2)) @ np.array([1.0, 1j])
+    assert np.allclose(Pf.apply_T(x), Pd.T @ x, rtol=1e-13, atol=0)

@@ -1,0 +1,253 @@
+/*
+ * wfq.h - C interface of the MI355X (gfx950) omegaFQ response library.
+ *
+ * Problem (Lafiosca, Giovannini, Benzi, Cappelli, arXiv 2103.00438, Section
+ * "Theoretical Model" and subsection "Properties of the omegaFQ linear system"):
+ * N atoms at positions r_i carry complex charges q. For a uniform field of
+ * amplitude E0 along unit direction k and angular frequency omega, q solves
+ *
+ *     (L T + z(omega) I) q = b_k,      b_k = E0 L (r . k),
+ *
+ * which is Eq. (wfq-a-matrix), (A - z I) q = R, multiplied by -1, with
+ *   T = D       damped Coulomb matrix, Eq. (d-matrix): T_ij = erf(r_ij / sqrt(d_i^2 + d_j^2)) / r_ij,
+ *               T_ii = eta_i, d_i = sqrt(2/pi) / eta_i (width-from-hardness equation);
+ *   L = P - Kbar  Eqs. (k-tot-factor), (a-matrix-product): Kbar_ij = (1 - f(r_ij)) / r_ij with the
+ *               Fermi damping f of Eq. (fermi), P_ii = sum_k Kbar_ik;
+ *   z(omega) = -(omega^2 + i omega / tau) / W   Eq. (z-def), W = 2 n0 A (effective area folded in);
+ *   R, V       Eqs. (r-vector-def) and (potential), V_i = -E0 (r_i . k).
+ * The polarisability returned is alpha_lk = sum_i r_{i,l} q_i^(k) / E0, whose diagonal gives the
+ * absorption cross section of Eq. (long-cross), sigma_k = (4 pi omega / c) Im alpha_kk.
+ *
+ * Units at this interface: positions in Angstrom, frequencies in eV, everything else in Hartree
+ * atomic units (eta, W, tau, E0). Inside, the library works in atomic units and may reorder atoms;
+ * every output is returned in the caller's atom order.
+ *
+ * Ownership: every input pointer is read during the call only; the caller keeps ownership. A
+ * handle owns all device memory of one structure (T copies, L, work space) until wfq_destroy.
+ * Calls on one handle must not overlap (a handle is single-threaded); distinct handles may be used
+ * from distinct threads. Errors: every int-returning function returns 0 (WFQ_OK) or a WFQ_E* code
+ * and stores a message readable with wfq_last_error() on the calling thread. Arguments are checked
+ * before any device work is issued; on an argument error nothing is modified.
+ */
+#ifndef WFQ_H
+#define WFQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------------ status codes */
+#define WFQ_OK             0
+#define WFQ_EINVAL         1  /* invalid argument (N < 2, NaN/Inf, coincident atoms, eta <= 0, ...) */
+#define WFQ_ENOMEM         2  /* device footprint exceeds the budget or the device is out of memory */
+#define WFQ_EDEVICE        3  /* HIP runtime error or no usable gfx950 device */
+#define WFQ_ESINGULAR      4  /* omega <= 0: z = 0 and L T is singular (rows of L sum to zero) */
+#define WFQ_ENOCONV        5  /* some system did not reach tol within max_iter (results still filled) */
+#define WFQ_EBREAKDOWN     6  /* QMR breakdown that the GMRES fallback could not repair */
+#define WFQ_ENUMERIC       7  /* NaN or Inf met during a solve */
+#define WFQ_EAGAIN         8  /* serving queue full, or result not ready yet */
+#define WFQ_EDISCONNECTED  9  /* warning from wfq_build: the Kbar graph is not connected */
+#define WFQ_ENOTFOUND     10  /* unknown serving ticket */
+
+/* ------------------------------------------------------------------ enumerations */
+#define WFQ_PREC_FP64  0      /* precision of the T products inside the Krylov iterations */
+#define WFQ_PREC_FP32  1
+#define WFQ_PREC_BF16  2
+
+#define WFQ_GMRES      0      /* restarted GMRES(m), Saad & Schultz (Section "Solution strategies") */
+#define WFQ_QMR        1      /* J-symmetric QMR from BCG with J = T, no look-ahead (same section) */
+
+#define WFQ_TMODE_AUTO    0   /* stored T when it fits the budget, else on the fly */
+#define WFQ_TMODE_STORED  1   /* dense T kept in device memory */
+#define WFQ_TMODE_OTF     2   /* T elements recomputed in every product (matrix-free section) */
+
+/* bits of wfq_params.store_mask: which stored copies of T wfq_build creates */
+#define WFQ_STORE_FP64  1u
+#define WFQ_STORE_FP32  2u
+#define WFQ_STORE_BF16  4u
+
+typedef struct wfq_handle wfq_handle;
+typedef struct wfq_server wfq_server;
+
+typedef struct {
+    int64_t       n;      /* number of atoms, >= 2 */
+    const double* xyz;    /* [n][3] positions, Angstrom, host memory */
+    const double* eta;    /* [n] per-atom hardness (Hartree), or NULL to use wfq_params.eta */
+} wfq_geometry;
+
+typedef struct {
+    double   eta;            /* hardness (Hartree) when wfq_geometry.eta is NULL; > 0 */
+    double   r0;             /* equilibrium distance r0 of Eq. (fermi), Angstrom; > 0 */
+    double   fermi_d;        /* d of Eq. (fermi); > 0 */
+    double   fermi_s;        /* s of Eq. (fermi); > 0 */
+    double   cutoff_eps;     /* Kbar_ij kept where 1 - f(r_ij) >= cutoff_eps; in (0, 0.5) */
+    double   W;              /* 2 n0 A (atomic units); > 0 */
+    double   tau;            /* Drude relaxation time (atomic units); > 0 */
+    int32_t  t_mode;         /* WFQ_TMODE_* */
+    uint32_t store_mask;     /* WFQ_STORE_* bits; 0 = FP64 and FP32 */
+    uint64_t device_budget;  /* bytes the handle may use on the device; 0 = 90% of free memory */
+    int32_t  device;         /* HIP device ordinal */
+} wfq_params;
+
+typedef struct {
+    int32_t algorithm;   /* WFQ_GMRES or WFQ_QMR */
+    int32_t restart;     /* GMRES: Krylov dimension m per cycle; QMR: steps between FP64 checks */
+    int32_t max_iter;    /* cap on T products per system (inner iterations); > 0 */
+    int32_t precision;   /* WFQ_PREC_*: precision of T inside the iterations (FP64 refinement always) */
+    double  E0;          /* field amplitude (atomic units); 0 means 1 */
+    int32_t max_batch;   /* systems solved together; 0 = as many as fit the budget */
+    int32_t timing;      /* nonzero: time every kernel launch with HIP events (wfq_kernel_stats) */
+    int32_t escalate;    /* nonzero: a system whose FP64 residual stalls moves to the next precision */
+} wfq_solve_opts;
+
+typedef struct {
+    int32_t status;      /* WFQ_OK, WFQ_ENOCONV, WFQ_EBREAKDOWN, WFQ_ENUMERIC for this system */
+    int32_t iters;       /* inner iterations (one T product each) */
+    int32_t cycles;      /* FP64 refinement cycles (GMRES restarts / QMR checks) */
+    int32_t precision;   /* precision of the last cycle (after any escalation) */
+    double  relres;      /* FP64 true relative residual ||b - (L T + z I) q|| / ||b|| */
+    double  rmse;        /* ||b - (L T + z I) q|| / sqrt(N), size-independent measure of Eq. (rmse) */
+    double  err_est;     /* estimated relative error of q: relres times a Hessenberg condition estimate */
+    double  t_done_ms;   /* completion time of this system, measured from the start of the call */
+} wfq_result;
+
+/*
+ * wfq_build - set up one structure on the device: unit conversion, spatial reordering, widths,
+ * the sparse L (cell-list neighbour search within the cutoff radius r_c = s r0 (1 + ln(1/eps - 1)/d))
+ * and the dense T copies requested by store_mask (computed in FP64, stored with round to nearest
+ * even). Returns WFQ_EDISCONNECTED (with a valid handle) when the Kbar graph has more than one
+ * connected component: each component then conserves its own charge and solves remain valid.
+ * On any other error *out is set to NULL.
+ */
+int wfq_build(const wfq_geometry* g, const wfq_params* p, wfq_handle** out);
+
+/* wfq_destroy - release every resource of the handle (NULL is accepted). */
+void wfq_destroy(wfq_handle* h);
+
+/*
+ * wfq_solve - solve all n_omega * n_dir systems of Eq. (wfq-a-matrix) for the given frequencies
+ * (eV, each > 0) and unit field directions dirs[n_dir][3], to relative FP64 residual <= tol, starting
+ * from q0 = 0 (the paper's protocol in Section "Numerical Results"). Systems sharing the handle's T
+ * are solved together in batches: one block product T X serves every active system. The inner
+ * iterations use T in o->precision; every FP64 refinement point recomputes the true residual with
+ * the FP64 operator. Outputs (host memory, any may be NULL):
+ *   q_re, q_im         [n_omega][n_dir][n] charges in the caller's atom order;
+ *   alpha_re, alpha_im [n_omega][n_dir][3] alpha[l] for field direction k (complex);
+ *   info               [n_omega][n_dir] per-system results.
+ * Returns the worst per-system status (WFQ_ENOCONV etc.); outputs are filled in every case except
+ * argument and device errors.
+ */
+int wfq_solve(wfq_handle* h, const double* omegas_eV, int32_t n_omega,
+              const double* dirs, int32_t n_dir, double tol, const wfq_solve_opts* o,
+              double* q_re, double* q_im, double* alpha_re, double* alpha_im, wfq_result* info);
+
+/*
+ * wfq_solve_dev - as wfq_solve, but q_re/q_im/alpha_re/alpha_im are device pointers (same layouts,
+ * may be NULL) and all work is ordered on the HIP stream `stream` (a hipStream_t, NULL = the null
+ * stream). The call returns after the results are written (it synchronises the stream).
+ */
+int wfq_solve_dev(wfq_handle* h, const double* omegas_eV, int32_t n_omega,
+                  const double* dirs, int32_t n_dir, double tol, const wfq_solve_opts* o,
+                  double* q_re_dev, double* q_im_dev, double* alpha_re_dev, double* alpha_im_dev,
+                  wfq_result* info, void* stream);
+
+/* ------------------------------------------------------------------ single steps (for checks)
+ * These expose one stage of the path each, in the caller's atom order, so that every stage can be
+ * compared with an independent implementation. They are not needed to solve.
+ */
+
+/* number of atoms and of nonzeros of L (including the diagonal) */
+int wfq_info(const wfq_handle* h, int64_t* n, int64_t* nnz_L, int64_t* bytes_device);
+
+/* T_ij for `count` index pairs (caller order) from the stored copy of the given precision, widened
+ * to double. Fails with WFQ_EINVAL if that copy was not built. */
+int wfq_sample_T(const wfq_handle* h, int32_t precision, const int64_t* i, const int64_t* j,
+                 int64_t count, double* out);
+
+/* L as triplets (row, col, value), caller order, nnz_L entries, row-major by internal order. */
+int wfq_export_L(const wfq_handle* h, int64_t* rows, int64_t* cols, double* vals);
+
+/* Y = T X for ncol real host vectors X[ncol][n] (caller order), with T in `precision`
+ * (WFQ_PREC_FP32/BF16 round X to that precision and accumulate in FP32), Y[ncol][n] in double. */
+int wfq_apply_T(wfq_handle* h, int32_t precision, int32_t ncol, const double* X, double* Y);
+
+/* Y = (L T + z_s I) X_s for S complex vectors (planar re/im, [S][n] each), T in `precision`. */
+int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t S, const double* z_re, const double* z_im,
+                 const double* X_re, const double* X_im, double* Y_re, double* Y_im);
+
+/* b = E0 L (r . k) for n_dir directions: out[n_dir][n] */
+int wfq_rhs(wfq_handle* h, const double* dirs, int32_t n_dir, double E0, double* out);
+
+/* per-kernel timings gathered by solves run with opts.timing != 0 (since the last reset):
+ * for kernel class c < *n_classes: names[c] (static strings), launches[c], total_ms[c],
+ * flops[c] and bytes[c] (algorithmic counts summed over launches). Pass NULL arrays to query
+ * *n_classes. reset != 0 clears the counters after reading. */
+int wfq_kernel_stats(wfq_handle* h, int32_t* n_classes, const char** names, int64_t* launches,
+                     double* total_ms, double* flops, double* bytes, int32_t reset);
+
+/* ------------------------------------------------------------------ serving
+ * A request loop for spectrum jobs of different structures arriving over time. Each job is one
+ * geometry + parameters + frequency list + field directions. Jobs are admitted while their device
+ * footprint (T copies, L, Krylov bases) fits the budget and a slot is free; admitted jobs run on
+ * their own streams and overlap on the device. Submission never blocks.
+ */
+typedef struct {
+    uint64_t device_budget;   /* bytes for all resident jobs; 0 = 90% of free memory */
+    int32_t  max_jobs;        /* concurrently resident jobs (slots), >= 1 */
+    int32_t  max_queue;       /* waiting jobs before submit returns WFQ_EAGAIN, >= 1 */
+    int32_t  device;          /* HIP device ordinal */
+    wfq_solve_opts opts;      /* solver options applied to every job */
+    double   tol;             /* relative residual target of every job */
+} wfq_serve_cfg;
+
+typedef struct {
+    wfq_geometry   geom;      /* copied at submit */
+    wfq_params     params;    /* copied at submit (t_mode, device and budget are taken from the server) */
+    const double*  omegas_eV; /* [n_omega], copied at submit */
+    int32_t        n_omega;
+    const double*  dirs;      /* [n_dir][3], copied at submit */
+    int32_t        n_dir;
+} wfq_job;
+
+typedef struct {
+    double t_submit_ms;       /* all times from server start */
+    double t_admit_ms;
+    double t_done_ms;
+    double latency_ms;        /* t_done - t_submit */
+    int32_t status;
+    int32_t n_systems;
+} wfq_job_timing;
+
+typedef struct {
+    int64_t jobs_done;
+    int64_t systems_done;
+    double  p50_ms;           /* job latency percentiles over completed jobs */
+    double  p99_ms;
+    double  solves_per_s;     /* systems completed per second of server wall time */
+    double  busy_frac;        /* fraction of wall time with at least one job running */
+    int32_t max_resident;     /* most jobs resident at once */
+} wfq_stats;
+
+int wfq_serve(const wfq_serve_cfg* c, wfq_server** out);
+int wfq_submit(wfq_server* s, const wfq_job* job, uint64_t* ticket);
+/* non-blocking: WFQ_EAGAIN until the job is done; outputs as in wfq_solve (host, may be NULL) */
+int wfq_poll(wfq_server* s, uint64_t ticket, double* q_re, double* q_im, double* alpha_re,
+             double* alpha_im, wfq_result* info, wfq_job_timing* timing);
+/* blocking variant of wfq_poll */
+int wfq_wait(wfq_server* s, uint64_t ticket, double* q_re, double* q_im, double* alpha_re,
+             double* alpha_im, wfq_result* info, wfq_job_timing* timing);
+int wfq_serve_stats(wfq_server* s, wfq_stats* out);
+/* stop accepting jobs, finish the running ones, release everything (NULL accepted) */
+void wfq_serve_stop(wfq_server* s);
+
+/* thread-local message of the last failing call on this thread ("" if none) */
+const char* wfq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WFQ_H */

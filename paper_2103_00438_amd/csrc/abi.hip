@@ -1,0 +1,427 @@
+// C interface of libwfq: argument checking, error reporting and handle ownership. The numerical
+// work lives in build.hip (structure set-up), gemm.hip / otf.hip (T products), krylov.hip and
+// solver.hip (batched Krylov solves) and serve.hip (request loop).
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "krylov.h"
+#include "solver.h"
+
+namespace wfq {
+
+namespace {
+thread_local std::string g_last_error;
+}
+
+void set_error(int code, const std::string& msg) {
+    (void)code;
+    g_last_error = msg;
+}
+
+}  // namespace wfq
+
+using namespace wfq;
+
+struct wfq_handle {
+    Structure S;
+    hipStream_t stream = nullptr;
+    KernelStat stats[KC_COUNT];
+};
+
+namespace {
+
+const char* kClassNames[KC_COUNT] = {"tx_gemm_f64", "tx_gemm_f32", "tx_gemm_bf16", "tx_skinny", "tx_otf",
+                                     "spmm_shift",  "cgs_dot",     "cgs_update",   "givens",    "pack",
+                                     "x_update",    "fp64_residual", "qmr",        "other"};
+
+template <typename F>
+int guarded(F&& f) {
+    try {
+        wfq::g_last_error.clear();
+        return f();
+    } catch (const Error& e) {
+        set_error(e.code, e.msg);
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error(WFQ_ENOMEM, "host allocation failed");
+        return WFQ_ENOMEM;
+    } catch (const std::exception& e) {
+        set_error(WFQ_EDEVICE, e.what());
+        return WFQ_EDEVICE;
+    }
+}
+
+int fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+void check_device(int device) {
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) fail(WFQ_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= count) fail(WFQ_EINVAL, "device ordinal out of range");
+    hipDeviceProp_t prop;
+    WFQ_HIP(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        fail(WFQ_EDEVICE, std::string("libwfq is built for gfx950, found ") + prop.gcnArchName);
+    WFQ_HIP(hipSetDevice(device));
+}
+
+void check_opts(const wfq_solve_opts* o) {
+    if (!o) fail(WFQ_EINVAL, "opts is NULL");
+    if (o->algorithm != WFQ_GMRES && o->algorithm != WFQ_QMR) fail(WFQ_EINVAL, "unknown algorithm");
+    if (o->restart < 1 || o->restart > 1000) fail(WFQ_EINVAL, "restart must be in [1, 1000]");
+    if (o->max_iter < 1) fail(WFQ_EINVAL, "max_iter must be >= 1");
+    if (o->precision != WFQ_PREC_FP64 && o->precision != WFQ_PREC_FP32 && o->precision != WFQ_PREC_BF16)
+        fail(WFQ_EINVAL, "unknown precision");
+    if (!std::isfinite(o->E0) || o->E0 < 0.0) fail(WFQ_EINVAL, "E0 must be finite and >= 0");
+    if (o->max_batch < 0) fail(WFQ_EINVAL, "max_batch must be >= 0");
+}
+
+void check_solve_args(const wfq_handle* h, const double* omegas, int n_omega, const double* dirs, int n_dir,
+                      double tol, const wfq_solve_opts* o) {
+    if (!h) fail(WFQ_EINVAL, "handle is NULL");
+    if (n_omega < 1 || n_dir < 1) fail(WFQ_EINVAL, "need n_omega >= 1 and n_dir >= 1");
+    if (!omegas || !dirs) fail(WFQ_EINVAL, "omegas and dirs must not be NULL");
+    if (!(tol > 0.0) || !(tol < 1.0)) fail(WFQ_EINVAL, "tol must be in (0, 1)");
+    check_opts(o);
+    for (int d = 0; d < n_dir; ++d) {
+        double nn = 0;
+        for (int a = 0; a < 3; ++a) {
+            if (!std::isfinite(dirs[3 * d + a])) fail(WFQ_EINVAL, "field direction is not finite");
+            nn += dirs[3 * d + a] * dirs[3 * d + a];
+        }
+        if (std::fabs(nn - 1.0) > 1e-9) fail(WFQ_EINVAL, "field directions must be unit vectors");
+    }
+    for (int k = 0; k < n_omega; ++k) {
+        if (!std::isfinite(omegas[k])) fail(WFQ_EINVAL, "frequency is not finite");
+        if (omegas[k] <= 0.0)
+            fail(WFQ_ESINGULAR, "omega <= 0: z(omega) = 0 and L T is singular (rows of L sum to zero)");
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* wfq_last_error(void) { return wfq::g_last_error.c_str(); }
+
+int wfq_build(const wfq_geometry* g, const wfq_params* p, wfq_handle** out) {
+    if (out) *out = nullptr;
+    return guarded([&]() -> int {
+        if (!g || !p || !out) fail(WFQ_EINVAL, "geometry, params and out must not be NULL");
+        if (g->n < 2) fail(WFQ_EINVAL, "need at least 2 atoms");
+        if (g->n > (int64_t)1 << 30) fail(WFQ_EINVAL, "too many atoms");
+        if (!g->xyz) fail(WFQ_EINVAL, "xyz is NULL");
+        for (int64_t i = 0; i < 3 * g->n; ++i)
+            if (!std::isfinite(g->xyz[i])) fail(WFQ_EINVAL, "positions must be finite");
+        if (g->eta) {
+            for (int64_t i = 0; i < g->n; ++i)
+                if (!finite_pos(g->eta[i])) fail(WFQ_EINVAL, "eta must be finite and > 0");
+        } else if (!finite_pos(p->eta)) {
+            fail(WFQ_EINVAL, "eta must be finite and > 0");
+        }
+        if (!finite_pos(p->r0) || !finite_pos(p->fermi_d) || !finite_pos(p->fermi_s))
+            fail(WFQ_EINVAL, "r0, fermi_d and fermi_s must be finite and > 0");
+        if (!(p->cutoff_eps > 0.0 && p->cutoff_eps < 0.5)) fail(WFQ_EINVAL, "cutoff_eps must be in (0, 0.5)");
+        if (!finite_pos(p->W) || !finite_pos(p->tau)) fail(WFQ_EINVAL, "W and tau must be finite and > 0");
+        if (p->t_mode < WFQ_TMODE_AUTO || p->t_mode > WFQ_TMODE_OTF) fail(WFQ_EINVAL, "unknown t_mode");
+        if (p->store_mask & ~7u) fail(WFQ_EINVAL, "unknown store_mask bits");
+        check_device(p->device);
+        auto* h = new wfq_handle();
+        h->S.device = p->device;
+        for (int k = 0; k < KC_COUNT; ++k) h->stats[k].name = kClassNames[k];
+        try {
+            WFQ_HIP(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+            size_t free_b = 0, total_b = 0;
+            WFQ_HIP(hipMemGetInfo(&free_b, &total_b));
+            h->S.budget = p->device_budget ? p->device_budget : (uint64_t)(0.9 * (double)free_b);
+            build_structure(h->S, g, p, h->stream);
+        } catch (...) {
+            free_structure(h->S);
+            if (h->stream) (void)hipStreamDestroy(h->stream);
+            delete h;
+            throw;
+        }
+        *out = h;
+        if (!h->S.connected) {
+            set_error(WFQ_EDISCONNECTED, "the Kbar graph is not connected; each component conserves its own charge");
+            return WFQ_EDISCONNECTED;
+        }
+        return WFQ_OK;
+    });
+}
+
+void wfq_destroy(wfq_handle* h) {
+    if (!h) return;
+    (void)hipSetDevice(h->S.device);
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    free_structure(h->S);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+static int solve_impl(wfq_handle* h, const double* omegas_eV, int32_t n_omega, const double* dirs, int32_t n_dir,
+                      double tol, const wfq_solve_opts* o, const SolveOutputs& out, hipStream_t st) {
+    return guarded([&]() -> int {
+        check_solve_args(h, omegas_eV, n_omega, dirs, n_dir, tol, o);
+        WFQ_HIP(hipSetDevice(h->S.device));
+        if (h->S.t_mode != WFQ_TMODE_STORED && o->algorithm != WFQ_GMRES)
+            fail(WFQ_EINVAL, "matrix-free T supports GMRES only");
+        int rc = solve_all(h->S, omegas_eV, n_omega, dirs, n_dir, tol, *o, out, st, o->timing ? h->stats : nullptr);
+        if (rc != WFQ_OK) set_error(rc, "some systems did not converge cleanly (see info[].status)");
+        return rc;
+    });
+}
+
+int wfq_solve(wfq_handle* h, const double* omegas_eV, int32_t n_omega, const double* dirs, int32_t n_dir, double tol,
+              const wfq_solve_opts* o, double* q_re, double* q_im, double* alpha_re, double* alpha_im,
+              wfq_result* info) {
+    SolveOutputs out;
+    out.q_re = q_re;
+    out.q_im = q_im;
+    out.alpha_re = alpha_re;
+    out.alpha_im = alpha_im;
+    out.info = info;
+    out.on_device = false;
+    return solve_impl(h, omegas_eV, n_omega, dirs, n_dir, tol, o, out, h ? h->stream : nullptr);
+}
+
+int wfq_solve_dev(wfq_handle* h, const double* omegas_eV, int32_t n_omega, const double* dirs, int32_t n_dir,
+                  double tol, const wfq_solve_opts* o, double* q_re_dev, double* q_im_dev, double* alpha_re_dev,
+                  double* alpha_im_dev, wfq_result* info, void* stream) {
+    SolveOutputs out;
+    out.q_re = q_re_dev;
+    out.q_im = q_im_dev;
+    out.alpha_re = alpha_re_dev;
+    out.alpha_im = alpha_im_dev;
+    out.info = info;
+    out.on_device = true;
+    return solve_impl(h, omegas_eV, n_omega, dirs, n_dir, tol, o, out, static_cast<hipStream_t>(stream));
+}
+
+int wfq_info(const wfq_handle* h, int64_t* n, int64_t* nnz_L, int64_t* bytes_device) {
+    return guarded([&]() -> int {
+        if (!h) fail(WFQ_EINVAL, "handle is NULL");
+        if (n) *n = h->S.n;
+        if (nnz_L) *nnz_L = h->S.nnz;
+        if (bytes_device) *bytes_device = (int64_t)h->S.bytes;
+        return WFQ_OK;
+    });
+}
+
+namespace {
+__global__ void sample_kernel(int prec, const double* T64, const float* T32, const uint16_t* T16, int64_t npad,
+                              const int64_t* ii, const int64_t* jj, int64_t count, double* out) {
+    int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= count) return;
+    int64_t o = ii[k] * npad + jj[k];
+    out[k] = prec == WFQ_PREC_FP64 ? T64[o]
+             : prec == WFQ_PREC_FP32 ? (double)T32[o]
+                                     : (double)__uint_as_float((uint32_t)T16[o] << 16);
+}
+}  // namespace
+
+int wfq_sample_T(const wfq_handle* h, int32_t precision, const int64_t* i, const int64_t* j, int64_t count,
+                 double* out) {
+    return guarded([&]() -> int {
+        if (!h || !i || !j || !out || count < 0) fail(WFQ_EINVAL, "bad arguments");
+        const Structure& S = h->S;
+        if (S.t_mode != WFQ_TMODE_STORED) fail(WFQ_EINVAL, "T is not stored");
+        if ((precision == WFQ_PREC_FP64 && !S.T64) || (precision == WFQ_PREC_FP32 && !S.T32) ||
+            (precision == WFQ_PREC_BF16 && !S.T16) || precision < 0 || precision > 2)
+            fail(WFQ_EINVAL, "that copy of T was not built");
+        if (count == 0) return WFQ_OK;
+        std::vector<int64_t> ii(count), jj(count);
+        for (int64_t k = 0; k < count; ++k) {
+            if (i[k] < 0 || i[k] >= S.n || j[k] < 0 || j[k] >= S.n) fail(WFQ_EINVAL, "index out of range");
+            ii[k] = S.iperm[i[k]];
+            jj[k] = S.iperm[j[k]];
+        }
+        WFQ_HIP(hipSetDevice(S.device));
+        int64_t *di = nullptr, *dj = nullptr;
+        double* dout = nullptr;
+        WFQ_HIP(hipMalloc(&di, count * 8));
+        WFQ_HIP(hipMalloc(&dj, count * 8));
+        WFQ_HIP(hipMalloc(&dout, count * 8));
+        WFQ_HIP(hipMemcpyAsync(di, ii.data(), count * 8, hipMemcpyHostToDevice, h->stream));
+        WFQ_HIP(hipMemcpyAsync(dj, jj.data(), count * 8, hipMemcpyHostToDevice, h->stream));
+        hipLaunchKernelGGL(sample_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, h->stream, precision,
+                           S.T64, S.T32, S.T16, S.npad, di, dj, count, dout);
+        WFQ_CHECK_LAUNCH();
+        WFQ_HIP(hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, h->stream));
+        WFQ_HIP(hipStreamSynchronize(h->stream));
+        (void)hipFree(di);
+        (void)hipFree(dj);
+        (void)hipFree(dout);
+        return WFQ_OK;
+    });
+}
+
+int wfq_export_L(const wfq_handle* h, int64_t* rows, int64_t* cols, double* vals) {
+    return guarded([&]() -> int {
+        if (!h || !rows || !cols || !vals) fail(WFQ_EINVAL, "bad arguments");
+        const Structure& S = h->S;
+        WFQ_HIP(hipSetDevice(S.device));
+        std::vector<int32_t> rp(S.n + 1), cl(S.nnz);
+        std::vector<double> vl(S.nnz);
+        WFQ_HIP(hipMemcpy(rp.data(), S.rowptr, (S.n + 1) * 4, hipMemcpyDeviceToHost));
+        WFQ_HIP(hipMemcpy(cl.data(), S.col, S.nnz * 4, hipMemcpyDeviceToHost));
+        WFQ_HIP(hipMemcpy(vl.data(), S.val, S.nnz * 8, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < S.n; ++i)
+            for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
+                rows[p] = S.perm[i];
+                cols[p] = S.perm[cl[p]];
+                vals[p] = vl[p];
+            }
+        return WFQ_OK;
+    });
+}
+
+int wfq_apply_T(wfq_handle* h, int32_t precision, int32_t ncol, const double* X, double* Y) {
+    return guarded([&]() -> int {
+        if (!h || !X || !Y || ncol < 1) fail(WFQ_EINVAL, "bad arguments");
+        if (precision < 0 || precision > 2) fail(WFQ_EINVAL, "unknown precision");
+        Structure& S = h->S;
+        WFQ_HIP(hipSetDevice(S.device));
+        const int64_t np = S.npad, n = S.n;
+        const int64_t rows = round_up(ncol, kColPad);
+        std::vector<double> xh((size_t)rows * np, 0.0);
+        for (int c = 0; c < ncol; ++c)
+            for (int64_t k = 0; k < n; ++k) xh[(size_t)c * np + k] = X[(size_t)c * n + S.perm[k]];
+        double *dx64 = nullptr, *dy64 = nullptr;
+        void *dx = nullptr, *dy = nullptr;
+        WFQ_HIP(hipMalloc(&dx64, rows * np * 8));
+        WFQ_HIP(hipMalloc(&dx, rows * np * 8));
+        WFQ_HIP(hipMalloc(&dy, rows * np * 8));
+        WFQ_HIP(hipMemcpyAsync(dx64, xh.data(), rows * np * 8, hipMemcpyHostToDevice, h->stream));
+        convert_from_f64(precision, dx64, dx, rows * np, h->stream);
+        std::vector<double> yh((size_t)ncol * np);
+        if (precision == WFQ_PREC_FP64) {
+            tx_f64(S, (const double*)dx, (double*)dy, ncol, h->stream);
+            WFQ_HIP(hipMemcpyAsync(yh.data(), dy, (size_t)ncol * np * 8, hipMemcpyDeviceToHost, h->stream));
+        } else {
+            if (precision == WFQ_PREC_FP32)
+                tx_f32(S, (const float*)dx, (float*)dy, ncol, h->stream);
+            else
+                tx_bf16(S, (const uint16_t*)dx, (float*)dy, ncol, h->stream);
+            std::vector<float> yf((size_t)ncol * np);
+            WFQ_HIP(hipMemcpyAsync(yf.data(), dy, (size_t)ncol * np * 4, hipMemcpyDeviceToHost, h->stream));
+            WFQ_HIP(hipStreamSynchronize(h->stream));
+            for (size_t q = 0; q < yf.size(); ++q) yh[q] = yf[q];
+        }
+        WFQ_HIP(hipStreamSynchronize(h->stream));
+        (void)dy64;
+        (void)hipFree(dx64);
+        (void)hipFree(dx);
+        (void)hipFree(dy);
+        for (int c = 0; c < ncol; ++c)
+            for (int64_t k = 0; k < n; ++k) Y[(size_t)c * n + S.perm[k]] = yh[(size_t)c * np + k];
+        return WFQ_OK;
+    });
+}
+
+int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t nsys, const double* z_re, const double* z_im,
+                 const double* X_re, const double* X_im, double* Y_re, double* Y_im) {
+    return guarded([&]() -> int {
+        if (!h || !z_re || !z_im || !X_re || !X_im || !Y_re || !Y_im || nsys < 1) fail(WFQ_EINVAL, "bad arguments");
+        if (precision < 0 || precision > 2) fail(WFQ_EINVAL, "unknown precision");
+        Structure& S = h->S;
+        WFQ_HIP(hipSetDevice(S.device));
+        const int64_t np = S.npad, n = S.n;
+        // two vector slots per system: 0 = input, 1 = output
+        const int64_t sys_stride = 4 * np;
+        std::vector<double> vh((size_t)nsys * sys_stride, 0.0);
+        for (int s = 0; s < nsys; ++s)
+            for (int64_t k = 0; k < n; ++k) {
+                vh[(size_t)s * sys_stride + k] = X_re[(size_t)s * n + S.perm[k]];
+                vh[(size_t)s * sys_stride + np + k] = X_im[(size_t)s * n + S.perm[k]];
+            }
+        std::vector<double2> zh(nsys);
+        std::vector<int> sl(nsys);
+        for (int s = 0; s < nsys; ++s) {
+            zh[s] = make_double2(z_re[s], z_im[s]);
+            sl[s] = s;
+        }
+        const int64_t rows = round_up(2 * (int64_t)nsys, kColPad);
+        double* dv = nullptr;
+        double2* dz = nullptr;
+        int* dsys = nullptr;
+        void *dx = nullptr, *dy = nullptr;
+        WFQ_HIP(hipMalloc(&dv, vh.size() * 8));
+        WFQ_HIP(hipMalloc(&dz, nsys * sizeof(double2)));
+        WFQ_HIP(hipMalloc(&dsys, nsys * sizeof(int)));
+        WFQ_HIP(hipMalloc(&dx, rows * np * 8));
+        WFQ_HIP(hipMalloc(&dy, rows * np * 8));
+        WFQ_HIP(hipMemsetAsync(dx, 0, rows * np * 8, h->stream));
+        WFQ_HIP(hipMemcpyAsync(dv, vh.data(), vh.size() * 8, hipMemcpyHostToDevice, h->stream));
+        WFQ_HIP(hipMemcpyAsync(dz, zh.data(), nsys * sizeof(double2), hipMemcpyHostToDevice, h->stream));
+        WFQ_HIP(hipMemcpyAsync(dsys, sl.data(), nsys * sizeof(int), hipMemcpyHostToDevice, h->stream));
+        Basis V{dv, sys_stride, 2 * np, np};
+        pack_columns(precision, V, dsys, nsys, 0, nullptr, false, dx, np, h->stream);
+        if (precision == WFQ_PREC_FP64)
+            tx_f64(S, (const double*)dx, (double*)dy, 2 * nsys, h->stream);
+        else if (precision == WFQ_PREC_FP32)
+            tx_f32(S, (const float*)dx, (float*)dy, 2 * nsys, h->stream);
+        else
+            tx_bf16(S, (const uint16_t*)dx, (float*)dy, 2 * nsys, h->stream);
+        spmm_shift(S, precision == WFQ_PREC_FP64, dy, np, dsys, nsys, dz, V, 0, 1, h->stream);
+        WFQ_HIP(hipMemcpyAsync(vh.data(), dv, vh.size() * 8, hipMemcpyDeviceToHost, h->stream));
+        WFQ_HIP(hipStreamSynchronize(h->stream));
+        (void)hipFree(dv);
+        (void)hipFree(dz);
+        (void)hipFree(dsys);
+        (void)hipFree(dx);
+        (void)hipFree(dy);
+        for (int s = 0; s < nsys; ++s)
+            for (int64_t k = 0; k < n; ++k) {
+                Y_re[(size_t)s * n + S.perm[k]] = vh[(size_t)s * sys_stride + 2 * np + k];
+                Y_im[(size_t)s * n + S.perm[k]] = vh[(size_t)s * sys_stride + 3 * np + k];
+            }
+        return WFQ_OK;
+    });
+}
+
+int wfq_rhs(wfq_handle* h, const double* dirs, int32_t n_dir, double E0, double* out) {
+    return guarded([&]() -> int {
+        if (!h || !dirs || !out || n_dir < 1) fail(WFQ_EINVAL, "bad arguments");
+        Structure& S = h->S;
+        WFQ_HIP(hipSetDevice(S.device));
+        double *dd = nullptr, *db = nullptr;
+        WFQ_HIP(hipMalloc(&dd, 3 * n_dir * 8));
+        WFQ_HIP(hipMalloc(&db, (size_t)n_dir * S.npad * 8));
+        WFQ_HIP(hipMemcpyAsync(dd, dirs, 3 * n_dir * 8, hipMemcpyHostToDevice, h->stream));
+        build_rhs(S, dd, n_dir, E0 != 0.0 ? E0 : 1.0, db, S.npad, h->stream);
+        std::vector<double> bh((size_t)n_dir * S.npad);
+        WFQ_HIP(hipMemcpyAsync(bh.data(), db, bh.size() * 8, hipMemcpyDeviceToHost, h->stream));
+        WFQ_HIP(hipStreamSynchronize(h->stream));
+        (void)hipFree(dd);
+        (void)hipFree(db);
+        for (int d = 0; d < n_dir; ++d)
+            for (int64_t k = 0; k < S.n; ++k) out[(size_t)d * S.n + S.perm[k]] = bh[(size_t)d * S.npad + k];
+        return WFQ_OK;
+    });
+}
+
+int wfq_kernel_stats(wfq_handle* h, int32_t* n_classes, const char** names, int64_t* launches, double* total_ms,
+                     double* flops, double* bytes, int32_t reset) {
+    return guarded([&]() -> int {
+        if (!h || !n_classes) fail(WFQ_EINVAL, "bad arguments");
+        *n_classes = KC_COUNT;
+        for (int k = 0; k < KC_COUNT; ++k) {
+            if (names) names[k] = h->stats[k].name;
+            if (launches) launches[k] = h->stats[k].launches;
+            if (total_ms) total_ms[k] = h->stats[k].ms;
+            if (flops) flops[k] = h->stats[k].flops;
+            if (bytes) bytes[k] = h->stats[k].bytes;
+        }
+        if (reset)
+            for (int k = 0; k < KC_COUNT; ++k) {
+                h->stats[k].launches = 0;
+                h->stats[k].ms = h->stats[k].flops = h->stats[k].bytes = 0;
+            }
+        return WFQ_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,398 @@
+// Structure set-up on the device: atom ordering, the sparse Drude Laplacian L and the dense
+// damped Coulomb matrix T (arXiv 2103.00438, Section "Theoretical Model").
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "common.h"
+#include "device_util.h"
+
+namespace wfq {
+
+namespace {
+
+constexpr double kBohrA = 0.529177210903;  // Angstrom per bohr
+constexpr double kCoincidentA = 1e-6;      // atoms closer than this are rejected
+
+// Spread the low 21 bits of v so that bit b moves to bit 3b (Morton interleave helper).
+uint64_t spread3(uint64_t v) {
+    v &= 0x1fffffull;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
+    return v;
+}
+
+struct CellGrid {
+    double lo[3];
+    double h;       // cell edge (>= cutoff radius)
+    int dim[3];
+};
+
+// ----------------------------------------------------------------------- device kernels
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+struct GridArgs {
+    double lo0, lo1, lo2, inv_h;
+    int d0, d1, d2;
+};
+
+__device__ inline void cell_of(const GridArgs& g, double x, double y, double z, int& cx, int& cy, int& cz) {
+    cx = clampi((int)floor((x - g.lo0) * g.inv_h), 0, g.d0 - 1);
+    cy = clampi((int)floor((y - g.lo1) * g.inv_h), 0, g.d1 - 1);
+    cz = clampi((int)floor((z - g.lo2) * g.inv_h), 0, g.d2 - 1);
+}
+
+// 1 - f(r) of Eq. (fermi), divided by r: the off-diagonal Kbar_ij of Eq. (k-tot-factor).
+__device__ inline double kbar_of(double r, double inv_sr0, double d) {
+    double x = d * (r * inv_sr0 - 1.0);
+    return 1.0 / ((1.0 + exp(x)) * r);
+}
+
+// Pass 1 (count=true): number of neighbours within rc per atom; pass 2: write the CSR row of
+// L = P - Kbar with the diagonal first, then -Kbar_ij in cell traversal order (deterministic).
+template <bool kCount>
+__global__ void neighbour_kernel(int64_t n, const double* __restrict__ pos, int64_t npad, GridArgs g,
+                                 const int32_t* __restrict__ cell_start, const int32_t* __restrict__ cell_count,
+                                 double rc2, double inv_sr0, double fd, double close2,
+                                 int32_t* __restrict__ counts, const int32_t* __restrict__ rowptr,
+                                 int32_t* __restrict__ col, double* __restrict__ val, int32_t* __restrict__ flag) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double* px = pos;
+    const double* py = pos + npad;
+    const double* pz = pos + 2 * npad;
+    double xi = px[i], yi = py[i], zi = pz[i];
+    int cx, cy, cz;
+    cell_of(g, xi, yi, zi, cx, cy, cz);
+    int cnt = 0;
+    double diag = 0.0;
+    int64_t base = kCount ? 0 : rowptr[i];
+    int out = 1;
+    for (int dz = -1; dz <= 1; ++dz) {
+        int z = cz + dz;
+        if (z < 0 || z >= g.d2) continue;
+        for (int dy = -1; dy <= 1; ++dy) {
+            int y = cy + dy;
+            if (y < 0 || y >= g.d1) continue;
+            for (int dx = -1; dx <= 1; ++dx) {
+                int x = cx + dx;
+                if (x < 0 || x >= g.d0) continue;
+                int64_t c = ((int64_t)z * g.d1 + y) * g.d0 + x;
+                int s0 = cell_start[c], sc = cell_count[c];
+                for (int jj = 0; jj < sc; ++jj) {
+                    int j = s0 + jj;
+                    if (j == i) continue;
+                    double ddx = xi - px[j], ddy = yi - py[j], ddz = zi - pz[j];
+                    double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                    if (r2 < close2) flag[0] = 1;
+                    if (r2 < rc2) {
+                        if (kCount) {
+                            ++cnt;
+                        } else {
+                            double k = kbar_of(sqrt(r2), inv_sr0, fd);
+                            diag += k;
+                            col[base + out] = j;
+                            val[base + out] = -k;
+                            ++out;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (kCount) {
+        counts[i] = cnt + 1;  // + diagonal
+    } else {
+        col[base] = (int32_t)i;
+        val[base] = diag;
+    }
+}
+
+// Exclusive scan of n counts into rowptr[0..n] by one block (set-up only, n up to a few million).
+__global__ void scan_kernel(int64_t n, const int32_t* __restrict__ counts, int32_t* __restrict__ rowptr) {
+    __shared__ int64_t part[1024];
+    int t = threadIdx.x;
+    int64_t per = (n + 1023) / 1024;
+    int64_t b = t * per, e = min(n, b + per);
+    int64_t s = 0;
+    for (int64_t i = b; i < e; ++i) s += counts[i];
+    part[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int k = 0; k < 1024; ++k) {
+            int64_t v = part[k];
+            part[k] = acc;
+            acc += v;
+        }
+        rowptr[n] = (int32_t)acc;
+    }
+    __syncthreads();
+    int64_t acc = part[t];
+    for (int64_t i = b; i < e; ++i) {
+        rowptr[i] = (int32_t)acc;
+        acc += counts[i];
+    }
+}
+
+// Dense T of Eq. (d-matrix) in FP64, stored in any of FP64 / FP32 / BF16 (row-major, ld = npad).
+// Each block fills a 32 x 256 tile; padding rows/columns are written as zero.
+__global__ void __launch_bounds__(256) build_T_kernel(int64_t n, int64_t npad, const double* __restrict__ pos,
+                                                      const double* __restrict__ eta, const double* __restrict__ width,
+                                                      double* __restrict__ T64, float* __restrict__ T32,
+                                                      uint16_t* __restrict__ T16) {
+    int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t i0 = (int64_t)blockIdx.y * 32;
+    const double* px = pos;
+    const double* py = pos + npad;
+    const double* pz = pos + 2 * npad;
+    bool jin = j < n;
+    double xj = jin ? px[j] : 0.0, yj = jin ? py[j] : 0.0, zj = jin ? pz[j] : 0.0;
+    double dj2 = jin ? width[j] * width[j] : 0.0;
+    for (int r = 0; r < 32; ++r) {
+        int64_t i = i0 + r;
+        double v = 0.0;
+        if (i < n && jin) {
+            if (i == j) {
+                v = eta[i];
+            } else {
+                double dx = px[i] - xj, dy = py[i] - yj, dz = pz[i] - zj;
+                double rr = sqrt(dx * dx + dy * dy + dz * dz);
+                double di = width[i];
+                v = erf(rr / sqrt(di * di + dj2)) / rr;
+            }
+        }
+        int64_t o = i * npad + j;
+        if (T64) T64[o] = v;
+        if (T32) T32[o] = (float)v;
+        if (T16) T16[o] = bf16_rne(v);
+    }
+}
+
+// b[d][i] = E0 sum_j L_ij (r_j . k_d): minus R of Eq. (r-vector-def) with V of Eq. (potential).
+__global__ void rhs_kernel(int64_t n, int64_t npad, const double* __restrict__ pos, const int32_t* __restrict__ rowptr,
+                           const int32_t* __restrict__ col, const double* __restrict__ val,
+                           const double* __restrict__ dirs, int n_dir, double E0, double* __restrict__ out,
+                           int64_t ld) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int d = blockIdx.y;
+    if (i >= npad || d >= n_dir) return;
+    double acc = 0.0;
+    if (i < n) {
+        double kx = dirs[3 * d], ky = dirs[3 * d + 1], kz = dirs[3 * d + 2];
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            int j = col[p];
+            acc += val[p] * (pos[j] * kx + pos[npad + j] * ky + pos[2 * npad + j] * kz);
+        }
+        acc *= E0;
+    }
+    out[d * ld + i] = acc;
+}
+
+template <typename T>
+T* dev_alloc(Structure& s, size_t count) {
+    size_t bytes = count * sizeof(T);
+    if (s.budget && s.bytes + bytes > s.budget)
+        throw Error{WFQ_ENOMEM, "device budget exceeded while building the structure (" +
+                                    std::to_string((s.bytes + bytes) >> 20) + " MiB needed)"};
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) throw Error{WFQ_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+    s.bytes += bytes;
+    return static_cast<T*>(p);
+}
+
+}  // namespace
+
+void free_structure(Structure& s) {
+    void* ptrs[] = {s.pos, s.eta, s.width, s.rowptr, s.col, s.val, s.T64, s.T32, s.T16, s.dperm};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    s.pos = s.eta = s.width = s.val = s.T64 = nullptr;
+    s.rowptr = s.col = s.dperm = nullptr;
+    s.T32 = nullptr;
+    s.T16 = nullptr;
+    s.bytes = 0;
+}
+
+void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, hipStream_t st) {
+    const int64_t n = g->n;
+    s.n = n;
+    s.npad = round_up(n, kPad);
+    s.r0 = p->r0 / kBohrA;
+    s.fd = p->fermi_d;
+    s.fs = p->fermi_s;
+    s.rc = s.fs * s.r0 * (1.0 + std::log(1.0 / p->cutoff_eps - 1.0) / s.fd);
+    s.W = p->W;
+    s.tau = p->tau;
+
+    // ---- a0: units and ordering. Atoms are grouped by cell (edge >= rc) and the cells are ordered
+    // along a Morton curve, so that neighbours in space are near in memory.
+    std::vector<double> xyz(3 * n);
+    for (int64_t i = 0; i < 3 * n; ++i) xyz[i] = g->xyz[i] / kBohrA;
+    CellGrid grid;
+    double hi[3];
+    for (int a = 0; a < 3; ++a) {
+        grid.lo[a] = hi[a] = xyz[a];
+        for (int64_t i = 1; i < n; ++i) {
+            grid.lo[a] = std::min(grid.lo[a], xyz[3 * i + a]);
+            hi[a] = std::max(hi[a], xyz[3 * i + a]);
+        }
+    }
+    grid.h = s.rc * (1.0 + 1e-9);
+    for (;;) {
+        int64_t total = 1;
+        for (int a = 0; a < 3; ++a) {
+            grid.dim[a] = std::max(1, (int)std::floor((hi[a] - grid.lo[a]) / grid.h) + 1);
+            total *= grid.dim[a];
+        }
+        if (total <= (int64_t)1 << 24 && grid.dim[0] < (1 << 21) && grid.dim[1] < (1 << 21) && grid.dim[2] < (1 << 21))
+            break;
+        grid.h *= 1.5;
+    }
+    std::vector<int64_t> cell(n);
+    std::vector<uint64_t> code(n);
+    for (int64_t i = 0; i < n; ++i) {
+        int c[3];
+        for (int a = 0; a < 3; ++a)
+            c[a] = std::min(grid.dim[a] - 1, std::max(0, (int)std::floor((xyz[3 * i + a] - grid.lo[a]) / grid.h)));
+        cell[i] = ((int64_t)c[2] * grid.dim[1] + c[1]) * grid.dim[0] + c[0];
+        code[i] = spread3(c[0]) | spread3(c[1]) << 1 | spread3(c[2]) << 2;
+    }
+    s.perm.resize(n);
+    std::iota(s.perm.begin(), s.perm.end(), 0);
+    std::stable_sort(s.perm.begin(), s.perm.end(), [&](int64_t a, int64_t b) { return code[a] < code[b]; });
+    s.iperm.resize(n);
+    for (int64_t k = 0; k < n; ++k) s.iperm[s.perm[k]] = k;
+
+    const int64_t ncell = (int64_t)grid.dim[0] * grid.dim[1] * grid.dim[2];
+    std::vector<int32_t> cell_start(ncell, 0), cell_count(ncell, 0);
+    for (int64_t k = n - 1; k >= 0; --k) {
+        int64_t c = cell[s.perm[k]];
+        cell_count[c] += 1;
+        cell_start[c] = (int32_t)k;   // the atoms of one cell are contiguous in the new order
+    }
+
+    std::vector<double> pos_h(3 * s.npad, 0.0), eta_h(s.npad, 0.0), width_h(s.npad, 0.0);
+    s.pos_host.assign(3 * n, 0.0);
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t i = s.perm[k];
+        for (int a = 0; a < 3; ++a) {
+            pos_h[a * s.npad + k] = xyz[3 * i + a];
+            s.pos_host[a * n + k] = xyz[3 * i + a];
+        }
+        double e = g->eta ? g->eta[i] : p->eta;
+        eta_h[k] = e;
+        width_h[k] = std::sqrt(2.0 / M_PI) / e;   // d_i = sqrt(2/pi) / eta_i (width-from-hardness)
+    }
+
+    std::vector<int32_t> perm32(s.perm.begin(), s.perm.end());
+    s.dperm = dev_alloc<int32_t>(s, n);
+    WFQ_HIP(hipMemcpyAsync(s.dperm, perm32.data(), n * 4, hipMemcpyHostToDevice, st));
+    s.pos = dev_alloc<double>(s, 3 * s.npad);
+    s.eta = dev_alloc<double>(s, s.npad);
+    s.width = dev_alloc<double>(s, s.npad);
+    WFQ_HIP(hipMemcpyAsync(s.pos, pos_h.data(), pos_h.size() * 8, hipMemcpyHostToDevice, st));
+    WFQ_HIP(hipMemcpyAsync(s.eta, eta_h.data(), eta_h.size() * 8, hipMemcpyHostToDevice, st));
+    WFQ_HIP(hipMemcpyAsync(s.width, width_h.data(), width_h.size() * 8, hipMemcpyHostToDevice, st));
+
+    // ---- a1: neighbour search and CSR of L = P - Kbar
+    int32_t *d_start = nullptr, *d_count = nullptr, *d_counts = nullptr, *d_flag = nullptr;
+    WFQ_HIP(hipMalloc(&d_start, ncell * 4));
+    WFQ_HIP(hipMalloc(&d_count, ncell * 4));
+    WFQ_HIP(hipMalloc(&d_counts, n * 4));
+    WFQ_HIP(hipMalloc(&d_flag, 4));
+    WFQ_HIP(hipMemcpyAsync(d_start, cell_start.data(), ncell * 4, hipMemcpyHostToDevice, st));
+    WFQ_HIP(hipMemcpyAsync(d_count, cell_count.data(), ncell * 4, hipMemcpyHostToDevice, st));
+    WFQ_HIP(hipMemsetAsync(d_flag, 0, 4, st));
+    GridArgs ga{grid.lo[0], grid.lo[1], grid.lo[2], 1.0 / grid.h, grid.dim[0], grid.dim[1], grid.dim[2]};
+    const double rc2 = s.rc * s.rc;
+    const double inv_sr0 = 1.0 / (s.fs * s.r0);
+    const double close = kCoincidentA / kBohrA;
+    s.rowptr = dev_alloc<int32_t>(s, n + 1);
+    dim3 blk(256), grd((unsigned)((n + 255) / 256));
+    hipLaunchKernelGGL(neighbour_kernel<true>, grd, blk, 0, st, n, s.pos, s.npad, ga, d_start, d_count, rc2, inv_sr0,
+                       s.fd, close * close, d_counts, nullptr, nullptr, nullptr, d_flag);
+    WFQ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, n, d_counts, s.rowptr);
+    WFQ_CHECK_LAUNCH();
+    int32_t nnz32 = 0, flag = 0;
+    WFQ_HIP(hipMemcpyAsync(&nnz32, s.rowptr + n, 4, hipMemcpyDeviceToHost, st));
+    WFQ_HIP(hipMemcpyAsync(&flag, d_flag, 4, hipMemcpyDeviceToHost, st));
+    WFQ_HIP(hipStreamSynchronize(st));
+    if (flag) {
+        (void)hipFree(d_start); (void)hipFree(d_count); (void)hipFree(d_counts); (void)hipFree(d_flag);
+        throw Error{WFQ_EINVAL, "two atoms are closer than 1e-6 Angstrom"};
+    }
+    s.nnz = nnz32;
+    s.col = dev_alloc<int32_t>(s, s.nnz);
+    s.val = dev_alloc<double>(s, s.nnz);
+    hipLaunchKernelGGL(neighbour_kernel<false>, grd, blk, 0, st, n, s.pos, s.npad, ga, d_start, d_count, rc2, inv_sr0,
+                       s.fd, close * close, nullptr, s.rowptr, s.col, s.val, d_flag);
+    WFQ_CHECK_LAUNCH();
+
+    // connectivity of the Kbar graph (breadth-first search on the host)
+    {
+        std::vector<int32_t> rp(n + 1), cl(s.nnz);
+        WFQ_HIP(hipMemcpyAsync(rp.data(), s.rowptr, (n + 1) * 4, hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipMemcpyAsync(cl.data(), s.col, s.nnz * 4, hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipStreamSynchronize(st));
+        std::vector<char> seen(n, 0);
+        std::vector<int32_t> stack{0};
+        seen[0] = 1;
+        int64_t reached = 1;
+        while (!stack.empty()) {
+            int32_t i = stack.back();
+            stack.pop_back();
+            for (int32_t q = rp[i]; q < rp[i + 1]; ++q)
+                if (!seen[cl[q]]) {
+                    seen[cl[q]] = 1;
+                    ++reached;
+                    stack.push_back(cl[q]);
+                }
+        }
+        s.connected = reached == n;
+    }
+    (void)hipFree(d_start);
+    (void)hipFree(d_count);
+    (void)hipFree(d_counts);
+    (void)hipFree(d_flag);
+
+    // ---- a2: stored T copies
+    uint32_t mask = p->store_mask ? p->store_mask : (WFQ_STORE_FP64 | WFQ_STORE_FP32);
+    s.t_mode = p->t_mode;
+    if (s.t_mode == WFQ_TMODE_AUTO) {
+        uint64_t need = 0;
+        if (mask & WFQ_STORE_FP64) need += (uint64_t)s.npad * s.npad * 8;
+        if (mask & WFQ_STORE_FP32) need += (uint64_t)s.npad * s.npad * 4;
+        if (mask & WFQ_STORE_BF16) need += (uint64_t)s.npad * s.npad * 2;
+        // leave at least a third of the budget for the Krylov work space
+        s.t_mode = (s.budget == 0 || s.bytes + need <= s.budget / 3 * 2) ? WFQ_TMODE_STORED : WFQ_TMODE_OTF;
+    }
+    if (s.t_mode == WFQ_TMODE_STORED) {
+        const size_t nn = (size_t)s.npad * s.npad;
+        if (mask & WFQ_STORE_FP64) s.T64 = dev_alloc<double>(s, nn);
+        if (mask & WFQ_STORE_FP32) s.T32 = dev_alloc<float>(s, nn);
+        if (mask & WFQ_STORE_BF16) s.T16 = dev_alloc<uint16_t>(s, nn);
+        dim3 tg((unsigned)(s.npad / 256), (unsigned)(s.npad / 32));
+        hipLaunchKernelGGL(build_T_kernel, tg, dim3(256), 0, st, n, s.npad, s.pos, s.eta, s.width, s.T64, s.T32,
+                           s.T16);
+        WFQ_CHECK_LAUNCH();
+    }
+    WFQ_HIP(hipStreamSynchronize(st));
+}
+
+void build_rhs(const Structure& s, const double* dirs_dev, int n_dir, double E0, double* out, int64_t ld,
+               hipStream_t st) {
+    dim3 grd((unsigned)((s.npad + 255) / 256), (unsigned)n_dir);
+    hipLaunchKernelGGL(rhs_kernel, grd, dim3(256), 0, st, s.n, s.npad, s.pos, s.rowptr, s.col, s.val, dirs_dev,
+                       n_dir, E0, out, ld);
+    WFQ_CHECK_LAUNCH();
+}
+
+}  // namespace wfq

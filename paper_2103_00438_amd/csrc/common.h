@@ -1,0 +1,125 @@
+// Internal declarations shared by the HIP translation units of libwfq.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/wfq.h"
+
+namespace wfq {
+
+// Every dense vector / matrix dimension is padded to a multiple of this, so the block-product
+// kernels never need bounds checks (padding entries are kept at exactly zero).
+constexpr int kPad = 256;
+// Rows of the packed right-hand-side block are padded to this (largest m-tile of the products).
+constexpr int kColPad = 128;
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+void set_error(int code, const std::string& msg);
+
+#define WFQ_HIP(call)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (call);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::wfq::Error{WFQ_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+    } while (0)
+
+#define WFQ_CHECK_LAUNCH() WFQ_HIP(hipGetLastError())
+
+// ------------------------------------------------------------------ device-resident structure
+
+struct Structure {
+    int device = 0;
+    int64_t n = 0;       // atoms
+    int64_t npad = 0;    // n rounded up to kPad
+    std::vector<int64_t> perm;   // internal index -> caller index
+    std::vector<int64_t> iperm;  // caller index -> internal index
+    std::vector<double> pos_host;  // [3][n] internal order, bohr
+    int32_t* dperm = nullptr;    // device [n], internal index -> caller index
+    double* pos = nullptr;       // device [3][npad] SoA, bohr (padding: zeros)
+    double* eta = nullptr;       // device [npad]
+    double* width = nullptr;     // device [npad], d_i
+    int64_t nnz = 0;
+    int32_t* rowptr = nullptr;   // device [n + 1]
+    int32_t* col = nullptr;      // device [nnz]
+    double* val = nullptr;       // device [nnz]
+    double* T64 = nullptr;       // device [npad][npad]
+    float* T32 = nullptr;
+    uint16_t* T16 = nullptr;     // bf16 bit patterns
+    int t_mode = WFQ_TMODE_STORED;
+    double r0 = 0, fd = 0, fs = 0, rc = 0, W = 0, tau = 0;
+    uint64_t budget = 0;
+    uint64_t bytes = 0;          // device bytes held by this structure
+    bool connected = true;
+};
+
+struct KernelStat {
+    const char* name;
+    int64_t launches = 0;
+    double ms = 0, flops = 0, bytes = 0;
+};
+
+enum KernelClass {
+    KC_GEMM_F64 = 0, KC_GEMM_F32, KC_GEMM_BF16, KC_SKINNY, KC_OTF,
+    KC_SPMM, KC_DOT, KC_UPDATE, KC_GIVENS, KC_PACK, KC_XUPDATE, KC_RESID, KC_QMR, KC_OTHER,
+    KC_COUNT
+};
+
+// ------------------------------------------------------------------ per-kernel timing
+
+// Times kernel launches with HIP events recorded on the launching stream (enabled per solve).
+class Timer {
+  public:
+    explicit Timer(bool on) : on_(on) {}
+    ~Timer();
+    void begin(hipStream_t st);
+    void end(hipStream_t st, int kclass, double flops, double bytes);
+    // wait for the recorded events and add them to stats
+    void collect(KernelStat* stats);
+    bool on() const { return on_; }
+
+  private:
+    struct Rec {
+        hipEvent_t a, b;
+        int kc;
+        double flops, bytes;
+    };
+    bool on_;
+    std::vector<Rec> recs_;
+    std::vector<hipEvent_t> pool_;
+    hipEvent_t pending_ = nullptr;
+    hipEvent_t get();
+};
+
+// ------------------------------------------------------------------ builders (build.hip)
+void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, hipStream_t st);
+void free_structure(Structure& s);
+void build_rhs(const Structure& s, const double* dirs_dev, int n_dir, double E0, double* out, int64_t ld,
+               hipStream_t st);
+
+// ------------------------------------------------------------------ products (gemm.hip)
+// Y[c][i] = sum_k T[i][k] X[c][k] for c < ncol, i < npad; X, Y row-major with leading dimension ld.
+// X must hold round_up(ncol, kColPad) rows (rows >= ncol zero). Y likewise.
+void tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_t st);
+void tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st);
+void tx_bf16(const Structure& s, const uint16_t* X, float* Y, int ncol, hipStream_t st);
+const char* tx_variant(int precision, int ncol);
+// dst[i] = cast(src[i]) for i < count (round to nearest even)
+void convert_from_f64(int prec, const double* src, void* dst, int64_t count, hipStream_t st);
+void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st);
+void otf_tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_t st);
+
+}  // namespace wfq

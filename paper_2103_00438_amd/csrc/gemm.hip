@@ -1,0 +1,329 @@
+// Block products Y = T X with the stored damped Coulomb matrix (the dense half of the operator
+// A = (Kbar - P) D of Eq. (a-matrix-product); arXiv 2103.00438). T is symmetric, so each output
+// column is a row-times-row product: Y[c][i] = sum_k T[i][k] X[c][k]. Both operands are contiguous
+// along k, which is the layout the matrix cores want.
+//
+// Wide blocks (many Krylov columns) run on MFMA: FP64 v_mfma_f64_16x16x4, FP32 v_mfma_f32_16x16x4,
+// BF16 v_mfma_f32_16x16x32 (FP32 accumulation). A work-group (4 waves) owns a BM x BN output tile,
+// stages 128-byte k-slices of its X rows and T rows in LDS (double buffered, rows padded to 144
+// bytes so that each group of 8 lanes reading 16 bytes covers all 32 banks) and each wave computes
+// a (16 WM) x (16 WN) sub-tile. Each lane feeds the matrix core 16 bytes of k per operand; the k
+// order inside a slice is a permutation that is the same for both operands, so the sum is exact.
+// Narrow blocks (<= 8 columns, e.g. one frequency at a time) stream T once with vector loads.
+#include "common.h"
+#include "device_util.h"
+
+namespace wfq {
+
+namespace {
+
+template <int P>
+struct Prec;
+template <>
+struct Prec<WFQ_PREC_FP64> {
+    using elem = double;
+    using out = double;
+    using acc = doublex4;
+    using sacc = double;
+};
+template <>
+struct Prec<WFQ_PREC_FP32> {
+    using elem = float;
+    using out = float;
+    using acc = floatx4;
+    using sacc = float;
+};
+template <>
+struct Prec<WFQ_PREC_BF16> {
+    using elem = uint16_t;
+    using out = float;
+    using acc = floatx4;
+    using sacc = float;
+};
+
+__device__ inline void mma(doublex4& c, const uint4& a, const uint4& b) {
+    double a0 = __hiloint2double(a.y, a.x), a1 = __hiloint2double(a.w, a.z);
+    double b0 = __hiloint2double(b.y, b.x), b1 = __hiloint2double(b.w, b.z);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, c, 0, 0, 0);
+}
+
+template <int P>
+__device__ inline void mma(floatx4& c, const uint4& a, const uint4& b);
+
+template <>
+__device__ inline void mma<WFQ_PREC_FP32>(floatx4& c, const uint4& a, const uint4& b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+}
+
+template <>
+__device__ inline void mma<WFQ_PREC_BF16>(floatx4& c, const uint4& a, const uint4& b) {
+    bf16x8 av = __builtin_bit_cast(bf16x8, a);
+    bf16x8 bv = __builtin_bit_cast(bf16x8, b);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+}
+
+template <int P, typename A>
+__device__ inline void mma_any(A& c, const uint4& a, const uint4& b) {
+    if constexpr (P == WFQ_PREC_FP64)
+        mma(c, a, b);
+    else
+        mma<P>(c, a, b);
+}
+
+constexpr int kRowStride = 144;  // bytes per staged row (128 data + 16 pad)
+
+// Map a linear work-group id to a (m-tile, n-tile) pair so that the work-groups dispatched to one
+// XCD (ids congruent mod 8) get a contiguous run of tiles, m fastest: the m-tiles that share one
+// slab of T rows then run on the same XCD and reuse it from that XCD's L2.
+__device__ inline void xcd_tile(int b, int mt_count, int total, int& mt, int& nt) {
+    int xcd = b & 7, slot = b >> 3;
+    int q = total >> 3, r = total & 7;
+    int logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    mt = logical % mt_count;
+    nt = logical / mt_count;
+}
+
+template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
+__global__ void __launch_bounds__(256, OCC) tx_mfma_kernel(const typename Prec<P>::elem* __restrict__ X,
+                                                           const typename Prec<P>::elem* __restrict__ T,
+                                                           typename Prec<P>::out* __restrict__ Y, int64_t ld,
+                                                           int mt_count, int nt_count) {
+    static_assert(WAVES_M * WAVES_N == 4, "4 waves per work-group");
+    using elem = typename Prec<P>::elem;
+    using acc_t = typename Prec<P>::acc;
+    constexpr int BM = 16 * WM * WAVES_M;
+    constexpr int BN = 16 * WN * WAVES_N;
+    constexpr int ROWS = BM + BN;
+    constexpr int PER_T = ROWS * 8 / 256;
+    static_assert(ROWS * 8 % 256 == 0, "whole chunks per thread");
+    __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * kRowStride];
+
+    int mt, nt;
+    xcd_tile(blockIdx.x, mt_count, mt_count * nt_count, mt, nt);
+    const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WAVES_M, wn = wave / WAVES_M;
+
+    const char* src[PER_T];
+    int dst[PER_T];
+#pragma unroll
+    for (int u = 0; u < PER_T; ++u) {
+        int q = tid + 256 * u;
+        int row = q >> 3, cc = q & 7;
+        const elem* base = row < BM ? X + (m0 + row) * ld : T + (n0 + row - BM) * ld;
+        src[u] = reinterpret_cast<const char*>(base) + cc * 16;
+        dst[u] = row * kRowStride + cc * 16;
+    }
+
+    acc_t acc[WM][WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+    const int nk = (int)(ld * (int64_t)sizeof(elem) / 128);
+    uint4 reg[PER_T];
+#pragma unroll
+    for (int u = 0; u < PER_T; ++u) reg[u] = *reinterpret_cast<const uint4*>(src[u]);
+#pragma unroll
+    for (int u = 0; u < PER_T; ++u) *reinterpret_cast<uint4*>(lds + dst[u]) = reg[u];
+    __syncthreads();
+
+    const int frag_row = lane & 15, frag_chunk = lane >> 4;
+    for (int kt = 0; kt < nk; ++kt) {
+        if (kt + 1 < nk) {
+            const int64_t off = (int64_t)(kt + 1) * 128;
+#pragma unroll
+            for (int u = 0; u < PER_T; ++u) reg[u] = *reinterpret_cast<const uint4*>(src[u] + off);
+        }
+        const char* L = lds + (kt & 1) * ROWS * kRowStride;
+#pragma unroll
+        for (int cg = 0; cg < 2; ++cg) {
+            uint4 af[WM], bf[WN];
+            const int coff = (cg * 4 + frag_chunk) * 16;
+#pragma unroll
+            for (int a = 0; a < WM; ++a)
+                af[a] = *reinterpret_cast<const uint4*>(L + (wm * 16 * WM + a * 16 + frag_row) * kRowStride + coff);
+#pragma unroll
+            for (int b = 0; b < WN; ++b)
+                bf[b] = *reinterpret_cast<const uint4*>(L + (BM + wn * 16 * WN + b * 16 + frag_row) * kRowStride + coff);
+#pragma unroll
+            for (int a = 0; a < WM; ++a)
+#pragma unroll
+                for (int b = 0; b < WN; ++b) mma_any<P>(acc[a][b], af[a], bf[b]);
+        }
+        if (kt + 1 < nk) {
+            char* S = lds + ((kt + 1) & 1) * ROWS * kRowStride;
+#pragma unroll
+            for (int u = 0; u < PER_T; ++u) *reinterpret_cast<uint4*>(S + dst[u]) = reg[u];
+        }
+        __syncthreads();
+    }
+
+    // D[i][j] of one 16 x 16 block sits in lane j + 16 (i / 4), element i % 4.
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int64_t c = m0 + wm * 16 * WM + a * 16 + 4 * (lane >> 4) + r;
+                int64_t i = n0 + wn * 16 * WN + b * 16 + (lane & 15);
+                Y[c * ld + i] = acc[a][b][r];
+            }
+}
+
+// ---- narrow blocks: each wave streams R rows of T once and keeps up to NC columns of X in registers.
+
+__device__ inline void unpack(const uint4& v, float (&f)[4]) {
+    f[0] = __uint_as_float(v.x); f[1] = __uint_as_float(v.y); f[2] = __uint_as_float(v.z); f[3] = __uint_as_float(v.w);
+}
+__device__ inline void unpack(const uint4& v, double (&f)[2]) {
+    f[0] = __hiloint2double(v.y, v.x); f[1] = __hiloint2double(v.w, v.z);
+}
+__device__ inline void unpack(const uint4& v, float (&f)[8]) {
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        f[2 * q] = __uint_as_float(w[q] << 16);
+        f[2 * q + 1] = __uint_as_float(w[q] & 0xffff0000u);
+    }
+}
+
+template <int P>
+struct SkinnyVec;
+template <>
+struct SkinnyVec<WFQ_PREC_FP64> { static constexpr int E = 2; };
+template <>
+struct SkinnyVec<WFQ_PREC_FP32> { static constexpr int E = 4; };
+template <>
+struct SkinnyVec<WFQ_PREC_BF16> { static constexpr int E = 8; };
+
+template <int P, int NC, int R>
+__global__ void __launch_bounds__(256) tx_skinny_kernel(const typename Prec<P>::elem* __restrict__ X,
+                                                        const typename Prec<P>::elem* __restrict__ T,
+                                                        typename Prec<P>::out* __restrict__ Y, int64_t ld, int ncol) {
+    using elem = typename Prec<P>::elem;
+    using S = typename Prec<P>::sacc;
+    constexpr int E = SkinnyVec<P>::E;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * R;
+    S acc[R][NC];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[r][c] = 0;
+    for (int64_t k = (int64_t)lane * E; k < ld; k += 64 * E) {
+        S xv[NC][E];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            uint4 v = *reinterpret_cast<const uint4*>(X + c * ld + k);
+            unpack(v, xv[c]);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            S tv[E];
+            unpack(*reinterpret_cast<const uint4*>(T + (row0 + r) * ld + k), tv);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int e = 0; e < E; ++e) acc[r][c] += tv[e] * xv[c][e];
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            S v = acc[r][c];
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+            acc[r][c] = v;
+        }
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < ncol)
+#pragma unroll
+                for (int r = 0; r < R; ++r) Y[c * ld + row0 + r] = acc[r][c];
+    }
+}
+
+template <int P>
+void launch_tx(const Structure& s, const typename Prec<P>::elem* T, const typename Prec<P>::elem* X,
+               typename Prec<P>::out* Y, int ncol, hipStream_t st) {
+    if (ncol <= 0) return;
+    const int64_t ld = s.npad;
+    if (T == nullptr) throw Error{WFQ_EINVAL, "the stored copy of T for this precision was not built"};
+    if (ncol <= 8) {
+        constexpr int R = 4;
+        dim3 grd((unsigned)(ld / (4 * R)));
+        if (ncol <= 2)
+            hipLaunchKernelGGL((tx_skinny_kernel<P, 2, R>), grd, dim3(256), 0, st, X, T, Y, ld, ncol);
+        else if (ncol <= 4)
+            hipLaunchKernelGGL((tx_skinny_kernel<P, 4, R>), grd, dim3(256), 0, st, X, T, Y, ld, ncol);
+        else
+            hipLaunchKernelGGL((tx_skinny_kernel<P, 8, R>), grd, dim3(256), 0, st, X, T, Y, ld, ncol);
+        WFQ_CHECK_LAUNCH();
+        return;
+    }
+    constexpr int OCC = P == WFQ_PREC_FP64 ? 1 : 2;
+    if (ncol <= 32) {
+        constexpr int BM = 32, BN = 128;
+        int mtc = (int)((ncol + BM - 1) / BM), ntc = (int)(ld / BN);
+        hipLaunchKernelGGL((tx_mfma_kernel<P, 2, 2, 1, 4, 2>), dim3(mtc * ntc), dim3(256), 0, st, X, T, Y, ld, mtc, ntc);
+    } else if (ncol <= 64) {
+        constexpr int BM = 64, BN = 128;
+        int mtc = (int)((ncol + BM - 1) / BM), ntc = (int)(ld / BN);
+        hipLaunchKernelGGL((tx_mfma_kernel<P, 4, 2, 1, 4, 2>), dim3(mtc * ntc), dim3(256), 0, st, X, T, Y, ld, mtc, ntc);
+    } else {
+        constexpr int BM = 128, BN = 128;
+        int mtc = (int)((ncol + BM - 1) / BM), ntc = (int)(ld / BN);
+        hipLaunchKernelGGL((tx_mfma_kernel<P, 4, 4, 2, 2, OCC>), dim3(mtc * ntc), dim3(256), 0, st, X, T, Y, ld, mtc,
+                           ntc);
+    }
+    WFQ_CHECK_LAUNCH();
+}
+
+template <typename E>
+__global__ void convert_kernel(const double* __restrict__ src, E* __restrict__ dst, int64_t count) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) dst[i] = cast_from_double<E>(src[i]);
+}
+
+}  // namespace
+
+void convert_from_f64(int prec, const double* src, void* dst, int64_t count, hipStream_t st) {
+    if (count <= 0) return;
+    dim3 grd((unsigned)((count + 255) / 256));
+    if (prec == WFQ_PREC_FP64)
+        WFQ_HIP(hipMemcpyAsync(dst, src, count * 8, hipMemcpyDeviceToDevice, st));
+    else if (prec == WFQ_PREC_FP32)
+        hipLaunchKernelGGL(convert_kernel<float>, grd, dim3(256), 0, st, src, static_cast<float*>(dst), count);
+    else
+        hipLaunchKernelGGL(convert_kernel<uint16_t>, grd, dim3(256), 0, st, src, static_cast<uint16_t*>(dst), count);
+    WFQ_CHECK_LAUNCH();
+}
+
+void tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_t st) {
+    launch_tx<WFQ_PREC_FP64>(s, s.T64, X, Y, ncol, st);
+}
+void tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st) {
+    launch_tx<WFQ_PREC_FP32>(s, s.T32, X, Y, ncol, st);
+}
+void tx_bf16(const Structure& s, const uint16_t* X, float* Y, int ncol, hipStream_t st) {
+    launch_tx<WFQ_PREC_BF16>(s, s.T16, X, Y, ncol, st);
+}
+
+const char* tx_variant(int precision, int ncol) {
+    (void)precision;
+    if (ncol <= 8) return "skinny";
+    if (ncol <= 32) return "mfma_32x128";
+    if (ncol <= 64) return "mfma_64x128";
+    return "mfma_128x128";
+}
+
+}  // namespace wfq

@@ -1,0 +1,106 @@
+// Launch wrappers of the Krylov-side kernels (restarted GMRES with CGS2 Arnoldi, J-symmetric QMR,
+// FP64 refinement residuals, observables). All vectors are FP64 complex in planar layout: for
+// system s and vector slot j the real plane starts at base + s * sys_stride + j * vec_stride and the
+// imaginary plane npad entries later. Systems are addressed by id; every launch takes a device list
+// `sys` of the nsys system ids it works on (the active set).
+#pragma once
+
+#include "common.h"
+
+namespace wfq {
+
+struct Basis {
+    double* base = nullptr;
+    int64_t sys_stride = 0;  // doubles between systems
+    int64_t vec_stride = 0;  // doubles between vector slots of one system
+    int64_t npad = 0;
+};
+
+// rows handled by one wave in the chunked reductions (64 lanes x 8 rows)
+constexpr int kWaveRows = 512;
+inline int64_t wave_chunks(int64_t n) { return (n + kWaveRows - 1) / kWaveRows; }
+
+// X[2k + plane][i] = cast(V(sys[k], j)[plane][i] * scale[sys[k]]) for i < npad (scale may be NULL);
+// with write_back the scaled FP64 value is also stored back into V. prec = WFQ_PREC_*.
+void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, const double* scale, bool write_back,
+                  void* X, int64_t ld, hipStream_t st);
+
+// V(s, jdst) = L Y[2k, 2k+1] + z_s V(s, jsrc) for the nsys systems (Y in FP32 or FP64).
+void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
+                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st);
+
+// partial[s][i][wc] = sum over rows of wave chunk wc of conj(V(s, i)) * V(s, jw), i = 0..j.
+void multi_dot(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, double2* partial, int mdim,
+               hipStream_t st);
+// h[s][i] = sum_wc partial[s][i][wc] (i <= j); when acc is not NULL also acc[s][i] += h[s][i] (acc set to h if first).
+void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
+                 hipStream_t st);
+// V(s, jw) -= sum_{i<=j} h[s][i] V(s, i); with norm2 != NULL also norm2[s][wc] = partial sum |V(s, jw)|^2.
+void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, const double2* h, int mdim,
+                  double* norm2, hipStream_t st);
+
+struct GivensArgs {
+    const double2* h1;   // [S][mdim] first CGS pass
+    const double2* h2;   // [S][mdim] second CGS pass
+    const double* norm2; // [S][nwc] partial squared norms of the new vector
+    int nwc;
+    double2* R;          // [S][mdim][mdim] column-major upper triangle (R[s][j][i] = R_ij)
+    double* cs;          // [S][mdim]
+    double2* sn;         // [S][mdim]
+    double2* g;          // [S][mdim + 1]
+    double* est;         // [S] |g_{j+1}|
+    double* inv_h;       // [S] 1 / h_{j+1,j} (normalisation of the next basis vector)
+    const double* tol_abs;  // [S]
+    int* flags;          // [S] bit0: converged (estimate), bit1: happy breakdown, bit2: NaN
+};
+void givens_step(const int* sys, int nsys, int j, int mdim, const GivensArgs& a, hipStream_t st);
+
+// y = R^-1 g over the first k[s] steps; cond[s] = max|R_ii| / min|R_ii| (a cheap condition estimate).
+void tri_solve(const int* sys, int nsys, const int* ksteps, int mdim, const double2* R, const double2* g,
+               double2* y, double* cond, hipStream_t st);
+// x(s) += sum_{i < k[s]} y[s][i] V(s, i)
+void x_update(const Basis& V, const Basis& x, int64_t n, const int* sys, int nsys, const int* ksteps,
+              const double2* y, int mdim, hipStream_t st);
+
+// r(s) = b[dir[s]] - (L Y[2k,2k+1] + z_s x(s)) written to V(s, 0); norm2[s][blk] partial |r|^2.
+void residual(const Structure& S, const double* Y, int64_t ld, const int* sys, int nsys, const double2* z,
+              const Basis& x, const double* b, const int* dir, const Basis& V, double* norm2, int nblk,
+              hipStream_t st);
+inline int resid_blocks(int64_t n) { return (int)((n + 255) / 256); }
+// out[s] = sqrt(sum_b norm2[s][b]) for b < nb
+void sumsq(const int* sys, int nsys, const double* norm2, int nb, double* out, hipStream_t st);
+
+// V(s, 0) = b[dir[s]] (x0 = 0), norm2[s][blk] partial |b|^2
+void copy_rhs(const Structure& S, const int* sys, int nsys, const double* b, const int* dir, const Basis& V,
+              double* norm2, int nblk, hipStream_t st);
+
+// alpha[s][l] = sum_i r_{i,l} x(s)_i / E0  (complex, l = x, y, z)
+void observables(const Structure& S, const int* sys, int nsys, const Basis& x, double E0, double2* alpha,
+                 hipStream_t st);
+// q_out[s][perm[i]] = x(s)_i (caller atom order); q_re / q_im may be NULL
+void scatter_q(const Structure& S, const int32_t* perm, const int* sys, int nsys, const Basis& x, double* q_re,
+               double* q_im, hipStream_t st);
+
+// ---- J-symmetric QMR from BCG, one step split around the T product (see qmr kernels)
+struct QmrVecs {
+    Basis x, r, p, tp, q, xq, s;   // slot 0 of each
+};
+// rho_new partials: sum_i r_i (T r)_i (bilinear), with T r taken from Y (FP32 or FP64) columns
+void qmr_rho(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const QmrVecs& v, int64_t n,
+             double2* partial, hipStream_t st);
+// p = r + beta p, tp = Tr + beta tp (beta from rho_new / rho_old, or 0 at the first step)
+void qmr_dirs(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const QmrVecs& v, int64_t n,
+              const double2* rho_new, const double2* rho_old, const int* first, hipStream_t st);
+// q = L tp + z p and partial sigma = tp^T q
+void qmr_q(const Structure& S, const int* sys, int nsys, const QmrVecs& v, const double2* z, double2* partial,
+           hipStream_t st);
+// alpha = rho / sigma; x += alpha p; r -= alpha q; partial |r|^2
+void qmr_xr(const int* sys, int nsys, const QmrVecs& v, int64_t n, const double2* rho, const double2* sigma,
+            double* norm2, hipStream_t st);
+// QMR smoothing: tau2 update from |r|^2, eta; xq += eta (x - xq); s += eta (r - s); partial |s|^2
+void qmr_smooth(const int* sys, int nsys, const QmrVecs& v, int64_t n, const double* rnorm, double* tau2,
+                double* norm2, hipStream_t st);
+// generic complex partial-sum reduction: out[s] = sum_b partial[s][b] (nb per system)
+void reduce_complex(const int* sys, int nsys, const double2* partial, int nb, double2* out, hipStream_t st);
+
+}  // namespace wfq

@@ -1,0 +1,499 @@
+// Krylov-side kernels: the sparse half of the operator (L Y + z V), classical Gram-Schmidt with
+// reorthogonalisation for the Arnoldi process, the Givens-updated Hessenberg least-squares problem,
+// the solution update, the FP64 refinement residual and the observables (arXiv 2103.00438, Section
+// "Solution strategies": GMRES paragraph and restarted GMRES(k); Eq. (long-cross) for the dipole).
+//
+// All of these are bandwidth-bound vector sweeps. Reductions are deterministic: each wave sums a
+// fixed 512-row chunk with a fixed butterfly, and per-chunk partials are added in chunk order.
+#include "device_util.h"
+#include "krylov.h"
+
+namespace wfq {
+
+namespace {
+
+__device__ inline double* vre(const Basis& V, int s, int j) { return V.base + (int64_t)s * V.sys_stride + (int64_t)j * V.vec_stride; }
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 cscale(double c, double2 a) { return make_double2(c * a.x, c * a.y); }
+__device__ inline double cabs2(double2 a) { return hypot(a.x, a.y); }
+
+// block of 256 threads -> one value, fixed order
+__device__ inline double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0) sh[wave] = v;
+    __syncthreads();
+    double t = sh[0] + sh[1] + sh[2] + sh[3];
+    return t;
+}
+
+template <typename E>
+__global__ void __launch_bounds__(256) pack_kernel(Basis V, const int* __restrict__ sys, int j,
+                                                   const double* __restrict__ scale, int write_back, E* __restrict__ X,
+                                                   int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y;
+    const int s = sys[k];
+    double* re = vre(V, s, j);
+    double* im = re + V.npad;
+    const double sc = scale ? scale[s] : 1.0;
+    const double a = re[i] * sc, b = im[i] * sc;
+    if (write_back) {
+        re[i] = a;
+        im[i] = b;
+    }
+    X[(int64_t)(2 * k) * ld + i] = cast_from_double<E>(a);
+    X[(int64_t)(2 * k + 1) * ld + i] = cast_from_double<E>(b);
+}
+
+// Each thread owns one row of L and up to NS systems, so the row's (col, val) pairs are read once
+// for NS right-hand sides.
+template <typename YE, int NS>
+__global__ void __launch_bounds__(256) spmm_kernel(int64_t n, const int32_t* __restrict__ rowptr,
+                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                   const YE* __restrict__ Y, int64_t ld, const int* __restrict__ sys,
+                                                   int nsys, const double2* __restrict__ z, Basis V, int jsrc, int jdst) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int k0 = blockIdx.y * NS;
+    const int kn = min(NS, nsys - k0);
+    double ar[NS], ai[NS];
+#pragma unroll
+    for (int t = 0; t < NS; ++t) ar[t] = ai[t] = 0.0;
+    const int p0 = rowptr[i], p1 = rowptr[i + 1];
+    for (int p = p0; p < p1; ++p) {
+        const int c = col[p];
+        const double v = val[p];
+#pragma unroll
+        for (int t = 0; t < NS; ++t)
+            if (t < kn) {
+                ar[t] += v * widen(Y[(int64_t)(2 * (k0 + t)) * ld + c]);
+                ai[t] += v * widen(Y[(int64_t)(2 * (k0 + t) + 1) * ld + c]);
+            }
+    }
+#pragma unroll
+    for (int t = 0; t < NS; ++t)
+        if (t < kn) {
+            const int s = sys[k0 + t];
+            const double* sr = vre(V, s, jsrc);
+            const double vr = sr[i], vi = sr[i + V.npad];
+            const double2 zz = z[s];
+            double* dr = vre(V, s, jdst);
+            dr[i] = ar[t] + zz.x * vr - zz.y * vi;
+            dr[i + V.npad] = ai[t] + zz.x * vi + zz.y * vr;
+        }
+}
+
+__global__ void __launch_bounds__(256) dot_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
+                                                  double2* __restrict__ partial, int mdim, int64_t nwc) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
+    if (wc >= nwc) return;
+    const int s = sys[blockIdx.y];
+    const double* wr = vre(V, s, jw);
+    const double* wi = wr + V.npad;
+    const int64_t row0 = wc * kWaveRows + lane;
+    double xr[8], xi[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        xr[r] = row < n ? wr[row] : 0.0;
+        xi[r] = row < n ? wi[row] : 0.0;
+    }
+    for (int i = 0; i <= j; ++i) {
+        const double* vr = vre(V, s, i);
+        const double* vi = vr + V.npad;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t row = row0 + 64 * r;
+            if (row < n) {
+                const double a = vr[row], b = vi[row];
+                sr += a * xr[r] + b * xi[r];   // conj(v) w
+                si += a * xi[r] - b * xr[r];
+            }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) partial[((int64_t)s * mdim + i) * nwc + wc] = make_double2(sr, si);
+    }
+}
+
+__global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const double2* __restrict__ partial, int mdim,
+                                   int64_t nwc, double2* __restrict__ h) {
+    const int s = sys[blockIdx.x];
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        const double2* p = partial + ((int64_t)s * mdim + i) * nwc;
+        double sr = 0.0, si = 0.0;
+        for (int64_t w = 0; w < nwc; ++w) {
+            sr += p[w].x;
+            si += p[w].y;
+        }
+        h[(int64_t)s * mdim + i] = make_double2(sr, si);
+    }
+}
+
+__global__ void __launch_bounds__(256) update_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
+                                                     const double2* __restrict__ h, int mdim,
+                                                     double* __restrict__ norm2, int64_t nwc) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
+    if (wc >= nwc) return;
+    const int s = sys[blockIdx.y];
+    double* wr = vre(V, s, jw);
+    double* wi = wr + V.npad;
+    const int64_t row0 = wc * kWaveRows + lane;
+    double xr[8], xi[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        xr[r] = row < n ? wr[row] : 0.0;
+        xi[r] = row < n ? wi[row] : 0.0;
+    }
+    for (int i = 0; i <= j; ++i) {
+        const double2 hh = h[(int64_t)s * mdim + i];
+        const double* vr = vre(V, s, i);
+        const double* vi = vr + V.npad;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t row = row0 + 64 * r;
+            if (row < n) {
+                const double a = vr[row], b = vi[row];
+                xr[r] -= hh.x * a - hh.y * b;
+                xi[r] -= hh.x * b + hh.y * a;
+            }
+        }
+    }
+    double nn = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        if (row < n) {
+            wr[row] = xr[r];
+            wi[row] = xi[r];
+            nn += xr[r] * xr[r] + xi[r] * xi[r];
+        }
+    }
+    if (norm2) {
+        nn = wave_sum(nn);
+        if (lane == 0) norm2[(int64_t)s * nwc + wc] = nn;
+    }
+}
+
+// One thread per system: new Hessenberg column, previous rotations, new rotation, residual estimate.
+__global__ void givens_kernel(const int* __restrict__ sys, int nsys, int j, int mdim, GivensArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsys) return;
+    const int s = sys[k];
+    double2* col = a.R + ((int64_t)s * mdim + j) * mdim;
+    for (int i = 0; i <= j; ++i) col[i] = cadd(a.h1[(int64_t)s * mdim + i], a.h2[(int64_t)s * mdim + i]);
+    double hn2 = 0.0;
+    for (int w = 0; w < a.nwc; ++w) hn2 += a.norm2[(int64_t)s * a.nwc + w];
+    const double hn = sqrt(hn2);
+    double* cs = a.cs + (int64_t)s * mdim;
+    double2* sn = a.sn + (int64_t)s * mdim;
+    for (int i = 0; i < j; ++i) {
+        const double2 x = col[i], y = col[i + 1];
+        col[i] = cadd(cscale(cs[i], x), cmul(sn[i], y));
+        col[i + 1] = cadd(cscale(-1.0, cmul(cconj(sn[i]), x)), cscale(cs[i], y));
+    }
+    // rotation zeroing hn below col[j]: c real, s complex, [c s; -conj(s) c]
+    const double2 x = col[j];
+    const double ax = cabs2(x);
+    double c;
+    double2 sv;
+    if (hn == 0.0) {
+        c = 1.0;
+        sv = make_double2(0.0, 0.0);
+    } else if (ax == 0.0) {
+        c = 0.0;
+        sv = make_double2(1.0, 0.0);
+    } else {
+        const double nu = hypot(ax, hn);
+        c = ax / nu;
+        sv = make_double2(x.x / ax * hn / nu, x.y / ax * hn / nu);
+    }
+    cs[j] = c;
+    sn[j] = sv;
+    col[j] = cadd(cscale(c, x), cscale(hn, sv));
+    double2* g = a.g + (int64_t)s * (mdim + 1);
+    const double2 gj = g[j];
+    g[j + 1] = cscale(-1.0, cmul(cconj(sv), gj));
+    g[j] = cscale(c, gj);
+    const double est = cabs2(g[j + 1]);
+    a.est[s] = est;
+    a.inv_h[s] = hn > 0.0 ? 1.0 / hn : 0.0;
+    int f = 0;
+    if (est <= a.tol_abs[s]) f |= 1;
+    if (hn <= 1e-14 * cabs2(col[j])) f |= 2;
+    if (!(est == est) || !(hn == hn)) f |= 4;
+    a.flags[s] = f;
+}
+
+__global__ void tri_solve_kernel(const int* __restrict__ sys, int nsys, const int* __restrict__ ksteps, int mdim,
+                                 const double2* __restrict__ R, const double2* __restrict__ g, double2* __restrict__ y,
+                                 double* __restrict__ cond) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsys) return;
+    const int s = sys[k];
+    const int kk = ksteps[s];
+    const double2* Rs = R + (int64_t)s * mdim * mdim;
+    const double2* gs = g + (int64_t)s * (mdim + 1);
+    double2* ys = y + (int64_t)s * mdim;
+    double dmax = 0.0, dmin = 1e300;
+    for (int i = kk - 1; i >= 0; --i) {
+        double2 acc = gs[i];
+        for (int l = i + 1; l < kk; ++l) {
+            const double2 t = cmul(Rs[(int64_t)l * mdim + i], ys[l]);
+            acc.x -= t.x;
+            acc.y -= t.y;
+        }
+        const double2 d = Rs[(int64_t)i * mdim + i];
+        const double dd = d.x * d.x + d.y * d.y;
+        ys[i] = make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
+        const double ad = sqrt(dd);
+        dmax = fmax(dmax, ad);
+        dmin = fmin(dmin, ad);
+    }
+    if (cond) cond[s] = kk > 0 && dmin > 0.0 ? dmax / dmin : 1.0;
+}
+
+__global__ void __launch_bounds__(256) x_update_kernel(Basis V, Basis X, int64_t n, const int* __restrict__ sys,
+                                                       const int* __restrict__ ksteps, const double2* __restrict__ y,
+                                                       int mdim) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int s = sys[blockIdx.y];
+    const int kk = ksteps[s];
+    double ar = 0.0, ai = 0.0;
+    for (int l = 0; l < kk; ++l) {
+        const double2 yy = y[(int64_t)s * mdim + l];
+        const double* vr = vre(V, s, l);
+        const double a = vr[i], b = vr[i + V.npad];
+        ar += yy.x * a - yy.y * b;
+        ai += yy.x * b + yy.y * a;
+    }
+    double* xr = vre(X, s, 0);
+    xr[i] += ar;
+    xr[i + X.npad] += ai;
+}
+
+__global__ void __launch_bounds__(256) residual_kernel(int64_t n, const int32_t* __restrict__ rowptr,
+                                                       const int32_t* __restrict__ col, const double* __restrict__ val,
+                                                       const double* __restrict__ Y, int64_t ld,
+                                                       const int* __restrict__ sys, const double2* __restrict__ z,
+                                                       Basis X, const double* __restrict__ b, const int* __restrict__ dir,
+                                                       Basis V, double* __restrict__ norm2, int nblk) {
+    __shared__ double sh[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int k = blockIdx.y;
+    const int s = sys[k];
+    double nn = 0.0;
+    if (i < n) {
+        double ar = 0.0, ai = 0.0;
+        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+            const int c = col[p];
+            const double v = val[p];
+            ar += v * Y[(int64_t)(2 * k) * ld + c];
+            ai += v * Y[(int64_t)(2 * k + 1) * ld + c];
+        }
+        const double* xr = vre(X, s, 0);
+        const double xre = xr[i], xim = xr[i + X.npad];
+        const double2 zz = z[s];
+        const double rr = b[(int64_t)dir[s] * V.npad + i] - (ar + zz.x * xre - zz.y * xim);
+        const double ri = -(ai + zz.x * xim + zz.y * xre);
+        double* vr = vre(V, s, 0);
+        vr[i] = rr;
+        vr[i + V.npad] = ri;
+        nn = rr * rr + ri * ri;
+    }
+    nn = block_sum(nn, sh);
+    if (threadIdx.x == 0) norm2[(int64_t)s * nblk + blockIdx.x] = nn;
+}
+
+__global__ void __launch_bounds__(256) copy_rhs_kernel(int64_t n, const int* __restrict__ sys,
+                                                       const double* __restrict__ b, const int* __restrict__ dir, Basis V,
+                                                       double* __restrict__ norm2, int nblk) {
+    __shared__ double sh[4];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int s = sys[blockIdx.y];
+    double nn = 0.0;
+    if (i < n) {
+        const double v = b[(int64_t)dir[s] * V.npad + i];
+        double* vr = vre(V, s, 0);
+        vr[i] = v;
+        vr[i + V.npad] = 0.0;
+        nn = v * v;
+    }
+    nn = block_sum(nn, sh);
+    if (threadIdx.x == 0) norm2[(int64_t)s * nblk + blockIdx.x] = nn;
+}
+
+__global__ void sumsq_kernel(const int* __restrict__ sys, int nsys, const double* __restrict__ norm2, int nb,
+                             double* __restrict__ out) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsys) return;
+    const int s = sys[k];
+    double acc = 0.0;
+    for (int b = 0; b < nb; ++b) acc += norm2[(int64_t)s * nb + b];
+    out[s] = sqrt(acc);
+}
+
+__global__ void __launch_bounds__(256) observables_kernel(int64_t n, int64_t npad, const double* __restrict__ pos,
+                                                          const int* __restrict__ sys, Basis X, double E0,
+                                                          double2* __restrict__ alpha) {
+    __shared__ double sh[4];
+    const int s = sys[blockIdx.x];
+    const double* xr = vre(X, s, 0);
+    const double* xi = xr + X.npad;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const double a = xr[i], b = xi[i];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double r = pos[l * npad + i];
+            acc[2 * l] += r * a;
+            acc[2 * l + 1] += r * b;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 6; ++q) acc[q] = block_sum(acc[q], sh);
+    if (threadIdx.x == 0)
+        for (int l = 0; l < 3; ++l) alpha[(int64_t)s * 3 + l] = make_double2(acc[2 * l] / E0, acc[2 * l + 1] / E0);
+}
+
+__global__ void __launch_bounds__(256) scatter_kernel(int64_t n, const int32_t* __restrict__ perm,
+                                                      const int* __restrict__ sys, Basis X, double* __restrict__ qr,
+                                                      double* __restrict__ qi) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int s = sys[blockIdx.y];
+    const double* xr = vre(X, s, 0);
+    const int64_t o = (int64_t)s * n + perm[i];
+    if (qr) qr[o] = xr[i];
+    if (qi) qi[o] = xr[i + X.npad];
+}
+
+}  // namespace
+
+void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, const double* scale, bool write_back,
+                  void* X, int64_t ld, hipStream_t st) {
+    if (nsys <= 0) return;
+    dim3 grd((unsigned)(V.npad / 256), (unsigned)nsys);
+    if (prec == WFQ_PREC_FP64)
+        hipLaunchKernelGGL(pack_kernel<double>, grd, dim3(256), 0, st, V, sys, j, scale, (int)write_back,
+                           static_cast<double*>(X), ld);
+    else if (prec == WFQ_PREC_FP32)
+        hipLaunchKernelGGL(pack_kernel<float>, grd, dim3(256), 0, st, V, sys, j, scale, (int)write_back,
+                           static_cast<float*>(X), ld);
+    else
+        hipLaunchKernelGGL(pack_kernel<uint16_t>, grd, dim3(256), 0, st, V, sys, j, scale, (int)write_back,
+                           static_cast<uint16_t*>(X), ld);
+    WFQ_CHECK_LAUNCH();
+}
+
+void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
+                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st) {
+    if (nsys <= 0) return;
+    constexpr int NS = 4;
+    dim3 grd((unsigned)((S.n + 255) / 256), (unsigned)((nsys + NS - 1) / NS));
+    if (y_is_f64)
+        hipLaunchKernelGGL((spmm_kernel<double, NS>), grd, dim3(256), 0, st, S.n, S.rowptr, S.col, S.val,
+                           static_cast<const double*>(Y), ld, sys, nsys, z, V, jsrc, jdst);
+    else
+        hipLaunchKernelGGL((spmm_kernel<float, NS>), grd, dim3(256), 0, st, S.n, S.rowptr, S.col, S.val,
+                           static_cast<const float*>(Y), ld, sys, nsys, z, V, jsrc, jdst);
+    WFQ_CHECK_LAUNCH();
+}
+
+void multi_dot(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, double2* partial, int mdim,
+               hipStream_t st) {
+    if (nsys <= 0) return;
+    const int64_t nwc = wave_chunks(n);
+    dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
+    hipLaunchKernelGGL(dot_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, partial, mdim, nwc);
+    WFQ_CHECK_LAUNCH();
+}
+
+void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
+                 hipStream_t st) {
+    if (nsys <= 0) return;
+    hipLaunchKernelGGL(reduce_dots_kernel, dim3(nsys), dim3(128), 0, st, sys, j, partial, mdim, wave_chunks(n), h);
+    WFQ_CHECK_LAUNCH();
+}
+
+void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, const double2* h, int mdim,
+                  double* norm2, hipStream_t st) {
+    if (nsys <= 0) return;
+    const int64_t nwc = wave_chunks(n);
+    dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
+    hipLaunchKernelGGL(update_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, h, mdim, norm2, nwc);
+    WFQ_CHECK_LAUNCH();
+}
+
+void givens_step(const int* sys, int nsys, int j, int mdim, const GivensArgs& a, hipStream_t st) {
+    if (nsys <= 0) return;
+    hipLaunchKernelGGL(givens_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sys, nsys, j, mdim, a);
+    WFQ_CHECK_LAUNCH();
+}
+
+void tri_solve(const int* sys, int nsys, const int* ksteps, int mdim, const double2* R, const double2* g,
+               double2* y, double* cond, hipStream_t st) {
+    if (nsys <= 0) return;
+    hipLaunchKernelGGL(tri_solve_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sys, nsys, ksteps, mdim, R, g, y,
+                       cond);
+    WFQ_CHECK_LAUNCH();
+}
+
+void x_update(const Basis& V, const Basis& x, int64_t n, const int* sys, int nsys, const int* ksteps,
+              const double2* y, int mdim, hipStream_t st) {
+    if (nsys <= 0) return;
+    dim3 grd((unsigned)((n + 255) / 256), (unsigned)nsys);
+    hipLaunchKernelGGL(x_update_kernel, grd, dim3(256), 0, st, V, x, n, sys, ksteps, y, mdim);
+    WFQ_CHECK_LAUNCH();
+}
+
+void residual(const Structure& S, const double* Y, int64_t ld, const int* sys, int nsys, const double2* z,
+              const Basis& x, const double* b, const int* dir, const Basis& V, double* norm2, int nblk,
+              hipStream_t st) {
+    if (nsys <= 0) return;
+    dim3 grd((unsigned)nblk, (unsigned)nsys);
+    hipLaunchKernelGGL(residual_kernel, grd, dim3(256), 0, st, S.n, S.rowptr, S.col, S.val, Y, ld, sys, z, x, b, dir,
+                       V, norm2, nblk);
+    WFQ_CHECK_LAUNCH();
+}
+
+void sumsq(const int* sys, int nsys, const double* norm2, int nb, double* out, hipStream_t st) {
+    if (nsys <= 0) return;
+    hipLaunchKernelGGL(sumsq_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sys, nsys, norm2, nb, out);
+    WFQ_CHECK_LAUNCH();
+}
+
+void copy_rhs(const Structure& S, const int* sys, int nsys, const double* b, const int* dir, const Basis& V,
+              double* norm2, int nblk, hipStream_t st) {
+    if (nsys <= 0) return;
+    dim3 grd((unsigned)nblk, (unsigned)nsys);
+    hipLaunchKernelGGL(copy_rhs_kernel, grd, dim3(256), 0, st, S.n, sys, b, dir, V, norm2, nblk);
+    WFQ_CHECK_LAUNCH();
+}
+
+void observables(const Structure& S, const int* sys, int nsys, const Basis& x, double E0, double2* alpha,
+                 hipStream_t st) {
+    if (nsys <= 0) return;
+    hipLaunchKernelGGL(observables_kernel, dim3(nsys), dim3(256), 0, st, S.n, S.npad, S.pos, sys, x, E0, alpha);
+    WFQ_CHECK_LAUNCH();
+}
+
+void scatter_q(const Structure& S, const int32_t* perm, const int* sys, int nsys, const Basis& x, double* q_re,
+               double* q_im, hipStream_t st) {
+    if (nsys <= 0 || (!q_re && !q_im)) return;
+    dim3 grd((unsigned)((S.n + 255) / 256), (unsigned)nsys);
+    hipLaunchKernelGGL(scatter_kernel, grd, dim3(256), 0, st, S.n, perm, sys, x, q_re, q_im);
+    WFQ_CHECK_LAUNCH();
+}
+
+}  // namespace wfq

@@ -1,0 +1,556 @@
+// Host drivers of the batched solves (arXiv 2103.00438, Section "Solution strategies").
+//
+// All (frequency, field) systems of one structure share T, so each Krylov step applies T to the
+// current basis vectors of every active system at once: one block product T X with 2 real columns
+// per complex system. Restarted GMRES(m) runs its inner cycles with T in the requested precision
+// (FP64, FP32, or BF16 with FP32 accumulation); every restart is an FP64 refinement point where the
+// true residual b - (L T + z I) x is recomputed with the FP64 copy of T, and the next cycle starts
+// from it. Systems leave the active set when their estimate reaches the target (the block shrinks),
+// and a system whose FP64 residual stalls while its inner estimate fell is moved to a higher
+// precision (its inner operator was not accurate enough).
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "krylov.h"
+#include "solver.h"
+
+namespace wfq {
+
+// ------------------------------------------------------------------ Timer
+
+Timer::~Timer() {
+    for (auto& r : recs_) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool_) (void)hipEventDestroy(e);
+    if (pending_) (void)hipEventDestroy(pending_);
+}
+
+hipEvent_t Timer::get() {
+    if (!pool_.empty()) {
+        hipEvent_t e = pool_.back();
+        pool_.pop_back();
+        return e;
+    }
+    hipEvent_t e;
+    WFQ_HIP(hipEventCreate(&e));
+    return e;
+}
+
+void Timer::begin(hipStream_t st) {
+    if (!on_) return;
+    pending_ = get();
+    WFQ_HIP(hipEventRecord(pending_, st));
+}
+
+void Timer::end(hipStream_t st, int kclass, double flops, double bytes) {
+    if (!on_ || !pending_) return;
+    hipEvent_t b = get();
+    WFQ_HIP(hipEventRecord(b, st));
+    recs_.push_back({pending_, b, kclass, flops, bytes});
+    pending_ = nullptr;
+}
+
+void Timer::collect(KernelStat* stats) {
+    for (auto& r : recs_) {
+        WFQ_HIP(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        WFQ_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        if (stats) {
+            stats[r.kc].launches += 1;
+            stats[r.kc].ms += ms;
+            stats[r.kc].flops += r.flops;
+            stats[r.kc].bytes += r.bytes;
+        }
+        pool_.push_back(r.a);
+        pool_.push_back(r.b);
+    }
+    recs_.clear();
+}
+
+namespace {
+
+template <typename T>
+struct DevArray {
+    T* p = nullptr;
+    size_t count = 0;
+    DevArray() = default;
+    DevArray(const DevArray&) = delete;
+    DevArray& operator=(const DevArray&) = delete;
+    void alloc(size_t c) {
+        count = c;
+        if (c == 0) return;
+        WFQ_HIP(hipMalloc(&p, c * sizeof(T)));
+        WFQ_HIP(hipMemset(p, 0, c * sizeof(T)));
+    }
+    ~DevArray() {
+        if (p) (void)hipFree(p);
+    }
+};
+
+template <typename T>
+struct PinnedArray {
+    T* p = nullptr;
+    void alloc(size_t c) {
+        if (c == 0) c = 1;
+        WFQ_HIP(hipHostMalloc(&p, c * sizeof(T), hipHostMallocDefault));
+        std::memset(p, 0, c * sizeof(T));
+    }
+    ~PinnedArray() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+int elem_size(int prec) { return prec == WFQ_PREC_FP64 ? 8 : prec == WFQ_PREC_FP32 ? 4 : 2; }
+int out_size(int prec) { return prec == WFQ_PREC_FP64 ? 8 : 4; }
+
+bool have_copy(const Structure& S, int prec) {
+    return prec == WFQ_PREC_FP64 ? S.T64 != nullptr : prec == WFQ_PREC_FP32 ? S.T32 != nullptr : S.T16 != nullptr;
+}
+
+// next precision up that has a stored copy (FP64 always last)
+int escalate_prec(const Structure& S, int prec) {
+    if (prec == WFQ_PREC_BF16 && have_copy(S, WFQ_PREC_FP32)) return WFQ_PREC_FP32;
+    return WFQ_PREC_FP64;
+}
+
+enum Slot { SLOT_G0 = 0, SLOT_G1 = 1, SLOT_G2 = 2, SLOT_STEP = 3, SLOT_ACT = 4, NSLOT = 5 };
+
+struct Work {
+    int B = 0, mdim = 0, n_dir = 0;
+    int64_t n = 0, npad = 0, nwc = 0, nblk = 0, mpad = 0;
+    bool need32 = false, need16 = false;
+    DevArray<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, tol_abs, cond;
+    DevArray<float> X32, Y32, Y16;
+    DevArray<uint16_t> X16;
+    DevArray<double2> partial, h1, h2, R, sn, g, y, z, alpha;
+    DevArray<int> flags, ksteps, dir, sys[NSLOT];
+    PinnedArray<int> h_sys[NSLOT], h_flags, h_ksteps;
+    PinnedArray<double> h_est, h_beta, h_invb;
+    PinnedArray<double2> h_g, h_alpha;
+    Basis Vb, Xb;
+};
+
+void alloc_work(Work& w, const Structure& S, int B, int m, int n_dir, int prec) {
+    w.B = B;
+    w.mdim = m + 1;
+    w.n_dir = n_dir;
+    w.n = S.n;
+    w.npad = S.npad;
+    w.nwc = wave_chunks(S.n);
+    w.nblk = resid_blocks(S.n);
+    w.mpad = round_up(2 * (int64_t)B, kColPad);
+    w.need16 = prec == WFQ_PREC_BF16;
+    w.need32 = prec == WFQ_PREC_FP32 || (prec == WFQ_PREC_BF16 && have_copy(S, WFQ_PREC_FP32));
+    const int64_t np = S.npad;
+    w.V.alloc((size_t)B * w.mdim * 2 * np);
+    w.X.alloc((size_t)B * 2 * np);
+    w.b.alloc((size_t)n_dir * np);
+    w.X64.alloc((size_t)w.mpad * np);
+    w.Y64.alloc((size_t)w.mpad * np);
+    if (w.need32) {
+        w.X32.alloc((size_t)w.mpad * np);
+        w.Y32.alloc((size_t)w.mpad * np);
+    }
+    if (w.need16) {
+        w.X16.alloc((size_t)w.mpad * np);
+        w.Y16.alloc((size_t)w.mpad * np);
+    }
+    w.partial.alloc((size_t)B * w.mdim * w.nwc);
+    w.h1.alloc((size_t)B * w.mdim);
+    w.h2.alloc((size_t)B * w.mdim);
+    w.R.alloc((size_t)B * w.mdim * w.mdim);
+    w.cs.alloc((size_t)B * w.mdim);
+    w.sn.alloc((size_t)B * w.mdim);
+    w.g.alloc((size_t)B * (w.mdim + 1));
+    w.y.alloc((size_t)B * w.mdim);
+    w.z.alloc(B);
+    w.alpha.alloc((size_t)B * 3);
+    w.est.alloc(B);
+    w.inv_h.alloc(B);
+    w.inv_beta.alloc(B);
+    w.beta.alloc(B);
+    w.norm2.alloc((size_t)B * std::max(w.nwc, w.nblk));
+    w.tol_abs.alloc(B);
+    w.cond.alloc(B);
+    w.flags.alloc(B);
+    w.ksteps.alloc(B);
+    w.dir.alloc(B);
+    for (int k = 0; k < NSLOT; ++k) {
+        w.sys[k].alloc(B);
+        w.h_sys[k].alloc(B);
+    }
+    w.h_flags.alloc(B);
+    w.h_ksteps.alloc(B);
+    w.h_est.alloc(B);
+    w.h_beta.alloc(B);
+    w.h_invb.alloc(B);
+    w.h_g.alloc((size_t)B * (w.mdim + 1));
+    w.h_alpha.alloc((size_t)B * 3);
+    w.Vb = Basis{w.V.p, (int64_t)w.mdim * 2 * np, 2 * np, np};
+    w.Xb = Basis{w.X.p, 2 * np, 2 * np, np};
+}
+
+void upload(Work& w, int slot, const std::vector<int>& v, hipStream_t st) {
+    std::memcpy(w.h_sys[slot].p, v.data(), v.size() * sizeof(int));
+    if (!v.empty())
+        WFQ_HIP(hipMemcpyAsync(w.sys[slot].p, w.h_sys[slot].p, v.size() * sizeof(int), hipMemcpyHostToDevice, st));
+}
+
+struct SysState {
+    double omega = 0;   // Hartree
+    int dir = 0;
+    double2 z{0, 0};
+    int prec = WFQ_PREC_FP64;
+    int status = WFQ_OK;
+    int iters = 0, cycles = 0;
+    double bnorm = 0, beta = 0, relres = 1, est_end = 0, cond = 1;
+    double t_done = 0;
+    bool done = false;
+};
+
+// One T X block product for the columns of one precision group (X already packed).
+void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, hipStream_t st) {
+    const double n = (double)S.n;
+    tm.begin(st);
+    if (prec == WFQ_PREC_FP64)
+        tx_f64(S, w.X64.p, w.Y64.p, ncol, st);
+    else if (prec == WFQ_PREC_FP32)
+        tx_f32(S, w.X32.p, w.Y32.p, ncol, st);
+    else
+        tx_bf16(S, w.X16.p, w.Y16.p, ncol, st);
+    const int kc = ncol <= 8 ? KC_SKINNY
+                             : (prec == WFQ_PREC_FP64 ? KC_GEMM_F64 : prec == WFQ_PREC_FP32 ? KC_GEMM_F32 : KC_GEMM_BF16);
+    tm.end(st, kc, 2.0 * n * n * ncol, elem_size(prec) * n * n + ncol * n * (elem_size(prec) + out_size(prec)));
+}
+
+void* x_block(Work& w, int prec) {
+    return prec == WFQ_PREC_FP64 ? (void*)w.X64.p : prec == WFQ_PREC_FP32 ? (void*)w.X32.p : (void*)w.X16.p;
+}
+const void* y_block(Work& w, int prec) {
+    return prec == WFQ_PREC_FP64 ? (const void*)w.Y64.p : prec == WFQ_PREC_FP32 ? (const void*)w.Y32.p
+                                                                                 : (const void*)w.Y16.p;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// FP64 refinement residual of the systems in `act`: V(s,0) = b - (L T + z I) x, beta = ||V(s,0)||.
+void fp64_residual(const Structure& S, Work& w, const std::vector<int>& act, Timer& tm, hipStream_t st) {
+    const int na = (int)act.size();
+    const double n = (double)S.n;
+    tm.begin(st);
+    pack_columns(WFQ_PREC_FP64, w.Xb, w.sys[SLOT_ACT].p, na, 0, nullptr, false, w.X64.p, w.npad, st);
+    tm.end(st, KC_PACK, 0, 32.0 * n * na);
+    block_product(S, w, WFQ_PREC_FP64, 2 * na, tm, st);
+    tm.begin(st);
+    residual(S, w.Y64.p, w.npad, w.sys[SLOT_ACT].p, na, w.z.p, w.Xb, w.b.p, w.dir.p, w.Vb, w.norm2.p, (int)w.nblk, st);
+    sumsq(w.sys[SLOT_ACT].p, na, w.norm2.p, (int)w.nblk, w.beta.p, st);
+    tm.end(st, KC_RESID, 4.0 * S.nnz * na + 8 * n * na, 12.0 * S.nnz + na * n * (16 + 16 + 16 + 8));
+}
+
+// Restarted GMRES(m) with FP64 refinement at every restart, for the systems of one batch.
+void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double tol, const wfq_solve_opts& o,
+                 Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0) {
+    const int B = (int)ss.size();
+    const int m = w.mdim - 1;
+    const double n = (double)S.n;
+    // per-system constants
+    {
+        std::vector<double2> zh(B);
+        std::vector<int> dh(B);
+        for (int s = 0; s < B; ++s) {
+            zh[s] = ss[s].z;
+            dh[s] = ss[s].dir;
+        }
+        WFQ_HIP(hipMemcpyAsync(w.z.p, zh.data(), B * sizeof(double2), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(w.dir.p, dh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemsetAsync(w.X.p, 0, w.X.count * sizeof(double), st));
+        WFQ_HIP(hipStreamSynchronize(st));
+    }
+    std::vector<int> all(B);
+    for (int s = 0; s < B; ++s) all[s] = s;
+    upload(w, SLOT_ACT, all, st);
+    // x0 = 0, r0 = b
+    copy_rhs(S, w.sys[SLOT_ACT].p, B, w.b.p, w.dir.p, w.Vb, w.norm2.p, (int)w.nblk, st);
+    sumsq(w.sys[SLOT_ACT].p, B, w.norm2.p, (int)w.nblk, w.beta.p, st);
+    WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    WFQ_HIP(hipStreamSynchronize(st));
+    std::vector<int> active;
+    {
+        std::vector<double> tol_h(B);
+        for (int s = 0; s < B; ++s) {
+            ss[s].bnorm = ss[s].beta = w.h_beta.p[s];
+            tol_h[s] = 0.5 * tol * ss[s].bnorm;   // inner target: half the outer one
+            if (ss[s].bnorm == 0.0) {
+                ss[s].relres = 0.0;
+                ss[s].done = true;
+                ss[s].t_done = ms_since(t0);
+            } else if (!std::isfinite(ss[s].bnorm)) {
+                ss[s].status = WFQ_ENUMERIC;
+                ss[s].done = true;
+            } else {
+                active.push_back(s);
+            }
+        }
+        WFQ_HIP(hipMemcpyAsync(w.tol_abs.p, tol_h.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipStreamSynchronize(st));
+    }
+
+    GivensArgs ga{w.h1.p, w.h2.p, w.norm2.p, (int)w.nwc, w.R.p, w.cs.p, w.sn.p, w.g.p, w.est.p, w.inv_h.p,
+                  w.tol_abs.p, w.flags.p};
+
+    while (!active.empty()) {
+        // cycle start: g = beta e1, v0 = r / beta
+        std::memset(w.h_g.p, 0, (size_t)B * (w.mdim + 1) * sizeof(double2));
+        for (int s : active) {
+            w.h_g.p[(size_t)s * (w.mdim + 1)] = make_double2(ss[s].beta, 0.0);
+            w.h_invb.p[s] = 1.0 / ss[s].beta;
+            w.h_ksteps.p[s] = 0;
+            ss[s].cycles += 1;
+        }
+        WFQ_HIP(hipMemcpyAsync(w.g.p, w.h_g.p, (size_t)B * (w.mdim + 1) * sizeof(double2), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(w.inv_beta.p, w.h_invb.p, B * sizeof(double), hipMemcpyHostToDevice, st));
+        std::vector<int> stepping;
+        for (int s : active)
+            if (ss[s].iters < o.max_iter) stepping.push_back(s);
+        for (int j = 0; j < m && !stepping.empty(); ++j) {
+            const int ns = (int)stepping.size();
+            // the operator on the new basis vectors, one block product per precision group
+            std::vector<int> grp[3];
+            for (int s : stepping) grp[ss[s].prec].push_back(s);
+            for (int p = 0; p < 3; ++p) {
+                if (grp[p].empty()) continue;
+                const int ng = (int)grp[p].size();
+                upload(w, p, grp[p], st);
+                tm.begin(st);
+                pack_columns(p, w.Vb, w.sys[p].p, ng, j, j == 0 ? w.inv_beta.p : w.inv_h.p, true, x_block(w, p),
+                             w.npad, st);
+                tm.end(st, KC_PACK, 0, ng * n * (32.0 + 2 * elem_size(p)));
+                block_product(S, w, p, 2 * ng, tm, st);
+                tm.begin(st);
+                spmm_shift(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, w.z.p, w.Vb, j, j + 1, st);
+                tm.end(st, KC_SPMM, 4.0 * S.nnz * ng + 8 * n * ng,
+                       12.0 * S.nnz + ng * n * (2.0 * out_size(p) + 16 + 16));
+            }
+            // CGS2 against v_0 .. v_j, then the Givens update of the least-squares problem
+            upload(w, SLOT_STEP, stepping, st);
+            const int* sl = w.sys[SLOT_STEP].p;
+            for (int pass = 0; pass < 2; ++pass) {
+                double2* h = pass == 0 ? w.h1.p : w.h2.p;
+                tm.begin(st);
+                multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st);
+                reduce_dots(S.n, sl, ns, j, w.partial.p, w.mdim, h, st);
+                tm.end(st, KC_DOT, 8.0 * n * ns * (j + 1), 16.0 * n * ns * (j + 2));
+                tm.begin(st);
+                multi_update(w.Vb, S.n, sl, ns, j, j + 1, h, w.mdim, pass == 1 ? w.norm2.p : nullptr, st);
+                tm.end(st, KC_UPDATE, 8.0 * n * ns * (j + 1), 16.0 * n * ns * (j + 3));
+            }
+            tm.begin(st);
+            givens_step(sl, ns, j, w.mdim, ga, st);
+            tm.end(st, KC_GIVENS, 0, 0);
+            WFQ_HIP(hipMemcpyAsync(w.h_flags.p, w.flags.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
+            WFQ_HIP(hipMemcpyAsync(w.h_est.p, w.est.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+            WFQ_HIP(hipStreamSynchronize(st));
+            std::vector<int> next;
+            for (int s : stepping) {
+                w.h_ksteps.p[s] = j + 1;
+                ss[s].iters += 1;
+                ss[s].est_end = w.h_est.p[s];
+                const int f = w.h_flags.p[s];
+                if (f & 4) {
+                    ss[s].status = WFQ_ENUMERIC;
+                    continue;
+                }
+                if (f == 0 && ss[s].iters < o.max_iter) next.push_back(s);
+            }
+            stepping.swap(next);
+        }
+        // drop systems that hit NaN
+        std::vector<int> act2;
+        for (int s : active) {
+            if (ss[s].status == WFQ_ENUMERIC) {
+                ss[s].done = true;
+                ss[s].t_done = ms_since(t0);
+            } else {
+                act2.push_back(s);
+            }
+        }
+        active.swap(act2);
+        if (active.empty()) break;
+        // x += V y, then the FP64 refinement residual
+        const int na = (int)active.size();
+        upload(w, SLOT_ACT, active, st);
+        WFQ_HIP(hipMemcpyAsync(w.ksteps.p, w.h_ksteps.p, B * sizeof(int), hipMemcpyHostToDevice, st));
+        tm.begin(st);
+        tri_solve(w.sys[SLOT_ACT].p, na, w.ksteps.p, w.mdim, w.R.p, w.g.p, w.y.p, w.cond.p, st);
+        x_update(w.Vb, w.Xb, S.n, w.sys[SLOT_ACT].p, na, w.ksteps.p, w.y.p, w.mdim, st);
+        tm.end(st, KC_XUPDATE, 0, 16.0 * n * na * (m + 2));
+        fp64_residual(S, w, active, tm, st);
+        WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        std::vector<double> condh(B);
+        WFQ_HIP(hipMemcpyAsync(condh.data(), w.cond.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipStreamSynchronize(st));
+        std::vector<int> still;
+        const double now = ms_since(t0);
+        for (int s : active) {
+            const double beta_prev = ss[s].beta;
+            ss[s].beta = w.h_beta.p[s];
+            ss[s].relres = ss[s].beta / ss[s].bnorm;
+            ss[s].cond = condh[s];
+            if (!std::isfinite(ss[s].beta)) {
+                ss[s].status = WFQ_ENUMERIC;
+                ss[s].done = true;
+                ss[s].t_done = now;
+            } else if (ss[s].relres <= tol) {
+                ss[s].done = true;
+                ss[s].t_done = now;
+            } else if (ss[s].iters >= o.max_iter) {
+                ss[s].status = WFQ_ENOCONV;
+                ss[s].done = true;
+                ss[s].t_done = now;
+            } else {
+                // the inner operator was too coarse: the FP64 residual did not follow the estimate
+                if (o.escalate && ss[s].prec != WFQ_PREC_FP64 && ss[s].beta > 0.5 * beta_prev &&
+                    ss[s].beta > 100.0 * ss[s].est_end)
+                    ss[s].prec = escalate_prec(S, ss[s].prec);
+                still.push_back(s);
+            }
+        }
+        active.swap(still);
+    }
+}
+
+}  // namespace
+
+uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_dir) {
+    const uint64_t np = S.npad;
+    const uint64_t mdim = (uint64_t)o.restart + 1;
+    const uint64_t mpad = round_up(2 * (int64_t)B, kColPad);
+    uint64_t b = 0;
+    b += (uint64_t)B * mdim * 2 * np * 8;       // basis
+    b += (uint64_t)B * 2 * np * 8;              // solution
+    b += (uint64_t)n_dir * np * 8;              // right-hand sides
+    b += mpad * np * 16;                        // FP64 block in/out
+    if (o.precision == WFQ_PREC_FP32 || o.precision == WFQ_PREC_BF16) b += mpad * np * 8;
+    if (o.precision == WFQ_PREC_BF16) b += mpad * np * 6;
+    const uint64_t nwc = wave_chunks(S.n);
+    b += (uint64_t)B * mdim * nwc * 16;         // dot partials
+    b += (uint64_t)B * mdim * mdim * 16;        // R
+    b += (uint64_t)B * (mdim * 64 + 2 * np * 8 / 1);  // small arrays + output staging
+    return b;
+}
+
+int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* dirs, int n_dir, double tol,
+              const wfq_solve_opts& o, const SolveOutputs& out, hipStream_t st, KernelStat* stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    const double kHartreeEV = 27.211386245988;
+    const int total = n_omega * n_dir;
+    const double E0 = o.E0 != 0.0 ? o.E0 : 1.0;
+    int prec = o.precision;
+    if (!have_copy(S, prec))
+        throw Error{WFQ_EINVAL, "the stored copy of T for the requested precision was not built (store_mask)"};
+    if (!have_copy(S, WFQ_PREC_FP64))
+        throw Error{WFQ_EINVAL, "FP64 refinement needs the FP64 copy of T (store_mask must include WFQ_STORE_FP64)"};
+
+    // batch size: as many systems as fit the budget
+    int B = o.max_batch > 0 ? std::min(o.max_batch, total) : total;
+    const uint64_t avail = S.budget > S.bytes ? S.budget - S.bytes : 0;
+    while (B > 1 && S.budget && batch_bytes(S, o, B, n_dir) > avail) B = (B + 1) / 2;
+    if (S.budget && batch_bytes(S, o, B, n_dir) > avail)
+        throw Error{WFQ_ENOMEM, "not enough device memory for one system's Krylov work space"};
+
+    Work w;
+    alloc_work(w, S, B, o.restart, n_dir, prec);
+    // right-hand sides b_k = E0 L r_k (shared by every frequency)
+    {
+        DevArray<double> d_dirs;
+        d_dirs.alloc((size_t)3 * n_dir);
+        WFQ_HIP(hipMemcpy(d_dirs.p, dirs, 3 * n_dir * sizeof(double), hipMemcpyHostToDevice));
+        build_rhs(S, d_dirs.p, n_dir, E0, w.b.p, S.npad, st);
+        WFQ_HIP(hipStreamSynchronize(st));
+    }
+    DevArray<double> stage_re, stage_im;
+    if (!out.on_device) {
+        if (out.q_re) stage_re.alloc((size_t)B * S.n);
+        if (out.q_im) stage_im.alloc((size_t)B * S.n);
+    }
+    Timer tm(stats != nullptr);
+    int worst = WFQ_OK;
+    for (int s0 = 0; s0 < total; s0 += B) {
+        const int nb = std::min(B, total - s0);
+        std::vector<SysState> ss(nb);
+        for (int s = 0; s < nb; ++s) {
+            const int gid = s0 + s;
+            ss[s].omega = omegas_eV[gid / n_dir] / kHartreeEV;
+            ss[s].dir = gid % n_dir;
+            const double om = ss[s].omega;
+            ss[s].z = make_double2(-(om * om) / S.W, -(om / S.tau) / S.W);   // z = -(w^2 + i w / tau) / W
+            ss[s].prec = prec;
+        }
+        if (o.algorithm == WFQ_GMRES)
+            gmres_batch(S, w, ss, tol, o, tm, st, t0);
+        else
+            throw Error{WFQ_EINVAL, "QMR is not available in this build"};
+        // outputs of the batch
+        std::vector<int> all(nb);
+        for (int s = 0; s < nb; ++s) all[s] = s;
+        upload(w, SLOT_ACT, all, st);
+        observables(S, w.sys[SLOT_ACT].p, nb, w.Xb, E0, w.alpha.p, st);
+        WFQ_HIP(hipMemcpyAsync(w.h_alpha.p, w.alpha.p, (size_t)nb * 3 * sizeof(double2), hipMemcpyDeviceToHost, st));
+        if (out.on_device) {
+            scatter_q(S, S.dperm, w.sys[SLOT_ACT].p, nb, w.Xb, out.q_re ? out.q_re + (size_t)s0 * S.n : nullptr,
+                      out.q_im ? out.q_im + (size_t)s0 * S.n : nullptr, st);
+        } else if (out.q_re || out.q_im) {
+            scatter_q(S, S.dperm, w.sys[SLOT_ACT].p, nb, w.Xb, stage_re.p, stage_im.p, st);
+            if (out.q_re)
+                WFQ_HIP(hipMemcpyAsync(out.q_re + (size_t)s0 * S.n, stage_re.p, (size_t)nb * S.n * 8,
+                                       hipMemcpyDeviceToHost, st));
+            if (out.q_im)
+                WFQ_HIP(hipMemcpyAsync(out.q_im + (size_t)s0 * S.n, stage_im.p, (size_t)nb * S.n * 8,
+                                       hipMemcpyDeviceToHost, st));
+        }
+        WFQ_HIP(hipStreamSynchronize(st));
+        std::vector<double> are(nb * 3), aim(nb * 3);
+        for (int s = 0; s < nb * 3; ++s) {
+            are[s] = w.h_alpha.p[s].x;
+            aim[s] = w.h_alpha.p[s].y;
+        }
+        if (out.alpha_re) {
+            if (out.on_device)
+                WFQ_HIP(hipMemcpy(out.alpha_re + (size_t)s0 * 3, are.data(), nb * 3 * 8, hipMemcpyHostToDevice));
+            else
+                std::memcpy(out.alpha_re + (size_t)s0 * 3, are.data(), nb * 3 * 8);
+        }
+        if (out.alpha_im) {
+            if (out.on_device)
+                WFQ_HIP(hipMemcpy(out.alpha_im + (size_t)s0 * 3, aim.data(), nb * 3 * 8, hipMemcpyHostToDevice));
+            else
+                std::memcpy(out.alpha_im + (size_t)s0 * 3, aim.data(), nb * 3 * 8);
+        }
+        for (int s = 0; s < nb; ++s) {
+            const SysState& q = ss[s];
+            if (out.info) {
+                wfq_result& r = out.info[s0 + s];
+                r.status = q.status;
+                r.iters = q.iters;
+                r.cycles = q.cycles;
+                r.precision = q.prec;
+                r.relres = q.relres;
+                r.rmse = q.beta / std::sqrt((double)S.n);
+                r.err_est = q.relres * q.cond;
+                r.t_done_ms = q.t_done;
+            }
+            if (q.status != WFQ_OK && worst == WFQ_OK) worst = q.status;
+            if (q.status == WFQ_ENUMERIC) worst = WFQ_ENUMERIC;
+        }
+    }
+    tm.collect(stats);
+    return worst;
+}
+
+}  // namespace wfq

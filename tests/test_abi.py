@@ -1,0 +1,69 @@
+"""Host-side checks of the C interface (no GPU needed): the library loads, exports every entry
+point declared in include/wfq.h, and rejects bad arguments before touching a device."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2103_00438_amd", "libwfq.so")
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "wfq.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(wfq_[a-z_A-Z]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("wfq_build", "wfq_solve", "wfq_solve_dev", "wfq_serve", "wfq_submit", "wfq_poll",
+                     "wfq_wait", "wfq_serve_stats", "wfq_serve_stop", "wfq_destroy", "wfq_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    assert os.path.exists(LIB), "build libwfq.so first (python -m paper_2103_00438_amd.build)"
+    lib = ctypes.CDLL(LIB)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_2103_00438_amd import wfq
+    for name in declared_functions():
+        assert name in wfq._SIGNATURES, name
+        assert hasattr(wfq, name), name
+
+
+def test_argument_errors_before_device():
+    from paper_2103_00438_amd import wfq
+    import wfq_inputs as wi
+    p = dict(wi.workloads.GRAPHENE)
+    with pytest.raises(wfq.WfqError) as e:
+        wfq.wfq_build(np.zeros((1, 3)), p)           # N < 2
+    assert e.value.code == wfq.WFQ_EINVAL
+    bad = np.zeros((3, 3))
+    bad[1, 0] = np.nan
+    with pytest.raises(wfq.WfqError) as e:
+        wfq.wfq_build(bad, p)
+    assert e.value.code == wfq.WFQ_EINVAL
+    with pytest.raises(wfq.WfqError) as e:
+        wfq.wfq_build(np.eye(3), dict(p, eta=-1.0))
+    assert e.value.code == wfq.WFQ_EINVAL
+    with pytest.raises(wfq.WfqError) as e:
+        wfq.wfq_build(np.eye(3), dict(p, cutoff_eps=0.7))
+    assert e.value.code == wfq.WFQ_EINVAL
+    assert "cutoff_eps" in wfq.wfq_last_error()
+
+
+def test_null_handle_is_rejected():
+    from paper_2103_00438_amd import wfq
+    lib = wfq.load()
+    assert lib.wfq_info(None, None, None, None) == wfq.WFQ_EINVAL
+    lib.wfq_destroy(None)
+    lib.wfq_serve_stop(None)

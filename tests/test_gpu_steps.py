@@ -1,0 +1,129 @@
+"""Step-by-step parity of the HIP path against the CPU oracle (needs an MI355X).
+
+Each stage of the hot path is called through the C interface and compared element by element
+with the oracle on the same seeded structure: the damped Coulomb matrix in each storage precision,
+the Drude Laplacian, the right-hand sides, the block product T X in each precision and every tile
+variant, and the full operator (L T + z I) X.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import wfq_oracle as O
+from helpers import GRAPHENE, UNIT, ragged_tube, round_to
+import wfq_inputs as wi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2103_00438_amd import wfq
+    wfq.load()
+    return wfq
+
+
+@pytest.fixture(scope="module")
+def tube():
+    xyz = ragged_tube()                      # 1200 atoms: 4 full 256-tiles and a ragged tail
+    return xyz, O.Problem(xyz, GRAPHENE)
+
+
+@pytest.fixture(scope="module")
+def handle(lib, tube):
+    xyz, _ = tube
+    h = lib.wfq_build(xyz, GRAPHENE, store=("fp64", "fp32", "bf16"))
+    yield h
+    h.close()
+
+
+def test_T_elements_all_precisions(lib, handle, tube):
+    _, P = tube
+    n = P.n
+    i, j = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    i, j = i.ravel(), j.ravel()
+    ref = P.T[i, j]
+    t64 = lib.wfq_sample_T(handle, "fp64", i, j)
+    assert np.max(np.abs(t64 - ref) / np.abs(ref)) < 4e-16 * 8      # a few ulps (erf implementations)
+    for prec in ("fp32", "bf16"):
+        tp = lib.wfq_sample_T(handle, prec, i, j)
+        # stored copy = FP64 value rounded to nearest; allow the FP64 ulps to flip a tie
+        assert np.max(np.abs(tp - ref) / np.abs(ref)) <= UNIT[prec] * (1 + 1e-6)
+        exact = tp == round_to(prec, ref)
+        assert exact.mean() > 0.9999
+
+
+def test_laplacian_structure_and_values(lib, handle, tube):
+    _, P = tube
+    r, c, v = lib.wfq_export_L(handle)
+    L = P.L.tocoo()
+    got = {(a, b): x for a, b, x in zip(r, c, v)}
+    want = {(a, b): x for a, b, x in zip(L.row, L.col, L.data)}
+    assert set(got) == set(want)                                     # same sparsity pattern, exactly
+    keys = list(want)
+    g = np.array([got[k] for k in keys])
+    w = np.array([want[k] for k in keys])
+    assert np.allclose(g, w, rtol=1e-13, atol=1e-16)
+    rows = np.zeros(P.n)
+    np.add.at(rows, r, v)
+    assert np.max(np.abs(rows)) < 1e-14 * np.max(np.abs(v))
+
+
+def test_rhs(lib, handle, tube):
+    _, P = tube
+    dirs = np.eye(3)
+    b = lib.wfq_rhs(handle, dirs, E0=1.0)
+    for k in range(3):
+        ref = P.rhs(dirs[k])
+        assert np.max(np.abs(b[k] - ref)) <= 1e-13 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+@pytest.mark.parametrize("ncol", [1, 2, 5, 8, 9, 24, 32, 33, 64, 65, 130])
+def test_block_product(lib, handle, tube, prec, ncol):
+    _, P = tube
+    rng = np.random.default_rng(100 + ncol)
+    X = rng.standard_normal((ncol, P.n))
+    Y = lib.wfq_apply_T(handle, prec, X)
+    Tq = round_to(prec, P.T)
+    Xq = round_to(prec, X)
+    ref = Xq @ Tq                     # T symmetric: row c of Y is T x_c
+    bound = np.abs(Xq) @ np.abs(Tq)
+    # accumulation error of an n-term sum in the accumulator precision (FP64 or FP32)
+    u_acc = UNIT["fp64"] if prec == "fp64" else UNIT["fp32"]
+    assert np.all(np.abs(Y - ref) <= 2 * P.n * u_acc * bound + 1e-300)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_operator_apply(lib, handle, tube, prec):
+    _, P = tube
+    rng = np.random.default_rng(7)
+    S = 5
+    X = rng.standard_normal((S, P.n)) + 1j * rng.standard_normal((S, P.n))
+    z = np.array([P.z(om) for om in (0.05, 0.2, 0.4, 0.7, 1.0)])
+    Y = lib.wfq_apply_op(handle, prec, z, X)
+    L = P.L
+    for s in range(S):
+        if prec == "fp64":
+            ref = L @ (P.T @ X[s]) + z[s] * X[s]
+            scale = np.abs(L) @ (np.abs(P.T) @ np.abs(X[s])) + np.abs(z[s] * X[s])
+            assert np.all(np.abs(Y[s] - ref) <= 1e-12 * scale)
+        else:
+            Tq = round_to(prec, P.T)
+            xr, xi = round_to(prec, X[s].real), round_to(prec, X[s].imag)
+            ty = Tq @ xr + 1j * (Tq @ xi)
+            ref = L @ ty + z[s] * X[s]
+            scale = np.abs(L) @ (np.abs(Tq) @ (np.abs(xr) + np.abs(xi))) + np.abs(z[s] * X[s])
+            assert np.all(np.abs(Y[s] - ref) <= 2 * P.n * UNIT["fp32"] * scale)
+
+
+def test_small_structure_dimer(lib):
+    # N = 2: one 256-tile of padding around two atoms
+    xyz = np.array([[0.0, 0.0, 0.0], [1.7, 0.0, 0.0]])
+    P = O.Problem(xyz, GRAPHENE)
+    h = lib.wfq_build(xyz, GRAPHENE)
+    t = lib.wfq_sample_T(h, "fp64", [0, 0, 1, 1], [0, 1, 0, 1])
+    assert np.allclose(t, P.T.ravel(), rtol=1e-15)
+    Y = lib.wfq_apply_T(h, "fp64", np.array([[1.0, -2.0]]))
+    assert np.allclose(Y[0], P.T @ np.array([1.0, -2.0]), rtol=1e-14)
+    h.close()

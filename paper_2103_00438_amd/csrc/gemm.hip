@@ -164,14 +164,17 @@ __global__ void __launch_bounds__(256, OCC) tx_mfma_kernel(const typename Prec<P
         __syncthreads();
     }
 
-    // D[i][j] of one 16 x 16 block sits in lane j + 16 (i / 4), element i % 4.
+    // Accumulator layout of one 16 x 16 block: column j = lane % 16 in every case; the row of
+    // element r is 4 (lane / 16) + r for the FP32 and BF16 instructions and lane / 16 + 4 r for
+    // the FP64 one.
 #pragma unroll
     for (int a = 0; a < WM; ++a)
 #pragma unroll
         for (int b = 0; b < WN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                int64_t c = m0 + wm * 16 * WM + a * 16 + 4 * (lane >> 4) + r;
+                const int row = P == WFQ_PREC_FP64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+                int64_t c = m0 + wm * 16 * WM + a * 16 + row;
                 int64_t i = n0 + wn * 16 * WN + b * 16 + (lane & 15);
                 Y[c * ld + i] = acc[a][b][r];
             }

@@ -75,7 +75,9 @@ def test_rhs(lib, handle, tube):
     b = lib.wfq_rhs(handle, dirs, E0=1.0)
     for k in range(3):
         ref = P.rhs(dirs[k])
-        assert np.max(np.abs(b[k] - ref)) <= 1e-13 * np.max(np.abs(ref))
+        # b is a short sum of large terms (positions times L): bound the rounding by |L| |r . k|
+        scale = np.abs(P.L) @ np.abs(P.xyz @ dirs[k])
+        assert np.all(np.abs(b[k] - ref) <= 64 * UNIT["fp64"] * scale)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])

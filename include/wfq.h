@@ -94,7 +94,7 @@ typedef struct {
 
 typedef struct {
     int32_t algorithm;   /* WFQ_GMRES or WFQ_QMR */
-    int32_t restart;     /* GMRES: Krylov dimension m per cycle; QMR: steps between FP64 checks */
+    int32_t restart;     /* GMRES: Krylov dimension m per cycle (1..256); QMR: steps between FP64 checks */
     int32_t max_iter;    /* cap on T products per system (inner iterations); > 0 */
     int32_t precision;   /* WFQ_PREC_*: precision of T inside the iterations (FP64 refinement always) */
     double  E0;          /* field amplitude (atomic units); 0 means 1 */
@@ -180,6 +180,19 @@ int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t S, const double* z_re
 
 /* b = E0 L (r . k) for n_dir directions: out[n_dir][n] */
 int wfq_rhs(wfq_handle* h, const double* dirs, int32_t n_dir, double E0, double* out);
+
+/* ------------------------------------------------------------------ block-product tuning
+ * The block product T X has several kernel shapes (MFMA tiles of different sizes, a narrow
+ * streaming kernel). wfq_tx_variants lists them for a precision: *count entries, names[k] (static
+ * strings) and max_ncol[k] (largest column count the shape accepts); NULL arrays query *count.
+ * wfq_tune times every applicable shape on random columns for each ncols[q] (reps launches each on
+ * the handle's stream), writes the average times to ms[q][k] (negative: not applicable) and keeps
+ * the fastest shape per ncol in the handle; later products with n columns use the shape tuned for
+ * the smallest tuned ncol >= n (the largest tuned one beyond that). Untuned handles use a built-in
+ * choice by column count. */
+int wfq_tx_variants(int32_t precision, int32_t* count, const char** names, int32_t* max_ncol);
+int wfq_tune(wfq_handle* h, int32_t precision, const int32_t* ncols, int32_t n_ncols, int32_t reps, double* ms,
+             int32_t* chosen);
 
 /* per-kernel timings gathered by solves run with opts.timing != 0 (since the last reset):
  * for kernel class c < *n_classes: names[c] (static strings), launches[c], total_ms[c],

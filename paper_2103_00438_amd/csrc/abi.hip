@@ -70,7 +70,7 @@ void check_device(int device) {
 void check_opts(const wfq_solve_opts* o) {
     if (!o) fail(WFQ_EINVAL, "opts is NULL");
     if (o->algorithm != WFQ_GMRES && o->algorithm != WFQ_QMR) fail(WFQ_EINVAL, "unknown algorithm");
-    if (o->restart < 1 || o->restart > 1000) fail(WFQ_EINVAL, "restart must be in [1, 1000]");
+    if (o->restart < 1 || o->restart > 256) fail(WFQ_EINVAL, "restart must be in [1, 256]");
     if (o->max_iter < 1) fail(WFQ_EINVAL, "max_iter must be >= 1");
     if (o->precision != WFQ_PREC_FP64 && o->precision != WFQ_PREC_FP32 && o->precision != WFQ_PREC_BF16)
         fail(WFQ_EINVAL, "unknown precision");
@@ -399,6 +399,40 @@ int wfq_rhs(wfq_handle* h, const double* dirs, int32_t n_dir, double E0, double*
         (void)hipFree(db);
         for (int d = 0; d < n_dir; ++d)
             for (int64_t k = 0; k < S.n; ++k) out[(size_t)d * S.n + S.perm[k]] = bh[(size_t)d * S.npad + k];
+        return WFQ_OK;
+    });
+}
+
+int wfq_tx_variants(int32_t precision, int32_t* count, const char** names, int32_t* max_ncol) {
+    return guarded([&]() -> int {
+        if (!count) fail(WFQ_EINVAL, "count is NULL");
+        if (precision < 0 || precision > 2) fail(WFQ_EINVAL, "unknown precision");
+        *count = tx_variant_count(precision);
+        for (int k = 0; k < *count; ++k) {
+            if (names) names[k] = tx_variant_name(precision, k);
+            if (max_ncol) max_ncol[k] = tx_variant_max_ncol(precision, k);
+        }
+        return WFQ_OK;
+    });
+}
+
+int wfq_tune(wfq_handle* h, int32_t precision, const int32_t* ncols, int32_t n_ncols, int32_t reps, double* ms,
+             int32_t* chosen) {
+    return guarded([&]() -> int {
+        if (!h || !ncols || n_ncols < 1 || reps < 1) fail(WFQ_EINVAL, "bad arguments");
+        if (precision < 0 || precision > 2) fail(WFQ_EINVAL, "unknown precision");
+        Structure& S = h->S;
+        if (S.t_mode != WFQ_TMODE_STORED) fail(WFQ_EINVAL, "T is not stored");
+        WFQ_HIP(hipSetDevice(S.device));
+        const int nv = tx_variant_count(precision);
+        std::vector<double> row(nv);
+        for (int q = 0; q < n_ncols; ++q) {
+            if (ncols[q] < 1 || ncols[q] > 4096) fail(WFQ_EINVAL, "ncol must be in [1, 4096]");
+            tune_tx(S, precision, ncols[q], reps, row.data(), h->stream);
+            if (ms)
+                for (int k = 0; k < nv; ++k) ms[(size_t)q * nv + k] = row[k];
+            if (chosen) chosen[q] = S.tuned[precision].count(ncols[q]) ? S.tuned[precision][ncols[q]] : -1;
+        }
         return WFQ_OK;
     });
 }

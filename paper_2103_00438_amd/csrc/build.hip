@@ -174,6 +174,20 @@ __global__ void __launch_bounds__(256) build_T_kernel(int64_t n, int64_t npad, c
     }
 }
 
+// Transposed ELL copy of the CSR rows: entry t of row i at [t][i], so that consecutive rows
+// (consecutive lanes) read consecutive addresses. Short rows are padded with (i, 0).
+__global__ void ell_kernel(int64_t n, int64_t npad, int w, const int32_t* __restrict__ rowptr,
+                           const int32_t* __restrict__ col, const double* __restrict__ val,
+                           int32_t* __restrict__ ecol, double* __restrict__ eval) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    int p0 = i < n ? rowptr[i] : 0, len = i < n ? rowptr[i + 1] - p0 : 0;
+    for (int t = 0; t < w; ++t) {
+        ecol[(int64_t)t * npad + i] = t < len ? col[p0 + t] : (int32_t)(i < n ? i : 0);
+        eval[(int64_t)t * npad + i] = t < len ? val[p0 + t] : 0.0;
+    }
+}
+
 // b[d][i] = E0 sum_j L_ij (r_j . k_d): minus R of Eq. (r-vector-def) with V of Eq. (potential).
 __global__ void rhs_kernel(int64_t n, int64_t npad, const double* __restrict__ pos, const int32_t* __restrict__ rowptr,
                            const int32_t* __restrict__ col, const double* __restrict__ val,
@@ -210,11 +224,12 @@ T* dev_alloc(Structure& s, size_t count) {
 }  // namespace
 
 void free_structure(Structure& s) {
-    void* ptrs[] = {s.pos, s.eta, s.width, s.rowptr, s.col, s.val, s.T64, s.T32, s.T16, s.dperm};
+    void* ptrs[] = {s.pos, s.eta, s.width, s.rowptr, s.col, s.val, s.T64, s.T32, s.T16, s.dperm, s.ell_col, s.ell_val};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s.pos = s.eta = s.width = s.val = s.T64 = nullptr;
-    s.rowptr = s.col = s.dperm = nullptr;
+    s.rowptr = s.col = s.dperm = s.ell_col = nullptr;
+    s.ell_val = nullptr;
     s.T32 = nullptr;
     s.T16 = nullptr;
     s.bytes = 0;
@@ -357,7 +372,15 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
                 }
         }
         s.connected = reached == n;
+        int w = 0;
+        for (int64_t i = 0; i < n; ++i) w = std::max(w, rp[i + 1] - rp[i]);
+        s.ell_w = w;
     }
+    s.ell_col = dev_alloc<int32_t>(s, (size_t)s.ell_w * s.npad);
+    s.ell_val = dev_alloc<double>(s, (size_t)s.ell_w * s.npad);
+    hipLaunchKernelGGL(ell_kernel, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, n, s.npad, s.ell_w, s.rowptr,
+                       s.col, s.val, s.ell_col, s.ell_val);
+    WFQ_CHECK_LAUNCH();
     (void)hipFree(d_start);
     (void)hipFree(d_count);
     (void)hipFree(d_counts);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -14,8 +15,9 @@ namespace wfq {
 // Every dense vector / matrix dimension is padded to a multiple of this, so the block-product
 // kernels never need bounds checks (padding entries are kept at exactly zero).
 constexpr int kPad = 256;
-// Rows of the packed right-hand-side block are padded to this (largest m-tile of the products).
-constexpr int kColPad = 128;
+// Rows of the packed right-hand-side block are padded to this: the largest m-tile of any
+// block-product variant, so no variant reads or writes past the allocated rows.
+constexpr int kColPad = 256;
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -56,6 +58,9 @@ struct Structure {
     int32_t* rowptr = nullptr;   // device [n + 1]
     int32_t* col = nullptr;      // device [nnz]
     double* val = nullptr;       // device [nnz]
+    int ell_w = 0;               // ELL width: longest row of L (diagonal included)
+    int32_t* ell_col = nullptr;  // device [ell_w][npad], column of entry t of row i (padding: i)
+    double* ell_val = nullptr;   // device [ell_w][npad], value (padding: 0)
     double* T64 = nullptr;       // device [npad][npad]
     float* T32 = nullptr;
     uint16_t* T16 = nullptr;     // bf16 bit patterns
@@ -64,6 +69,7 @@ struct Structure {
     uint64_t budget = 0;
     uint64_t bytes = 0;          // device bytes held by this structure
     bool connected = true;
+    std::map<int, int> tuned[3];   // per precision: ncol -> block-product variant chosen by tune_tx
 };
 
 struct KernelStat {
@@ -117,6 +123,10 @@ void tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_
 void tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st);
 void tx_bf16(const Structure& s, const uint16_t* X, float* Y, int ncol, hipStream_t st);
 const char* tx_variant(int precision, int ncol);
+int tx_variant_count(int precision);
+const char* tx_variant_name(int precision, int k);
+int tx_variant_max_ncol(int precision, int k);
+void tune_tx(Structure& s, int prec, int ncol, int reps, double* ms, hipStream_t st);
 // dst[i] = cast(src[i]) for i < count (round to nearest even)
 void convert_from_f64(int prec, const double* src, void* dst, int64_t count, hipStream_t st);
 void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st);

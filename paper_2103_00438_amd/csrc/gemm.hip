@@ -10,6 +10,9 @@
 // a (16 WM) x (16 WN) sub-tile. Each lane feeds the matrix core 16 bytes of k per operand; the k
 // order inside a slice is a permutation that is the same for both operands, so the sum is exact.
 // Narrow blocks (<= 8 columns, e.g. one frequency at a time) stream T once with vector loads.
+#include <cstring>
+#include <iterator>
+
 #include "common.h"
 #include "device_util.h"
 
@@ -87,20 +90,22 @@ __device__ inline void xcd_tile(int b, int mt_count, int total, int& mt, int& nt
     nt = logical / mt_count;
 }
 
-template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int OCC>
-__global__ void __launch_bounds__(256, OCC) tx_mfma_kernel(const typename Prec<P>::elem* __restrict__ X,
-                                                           const typename Prec<P>::elem* __restrict__ T,
-                                                           typename Prec<P>::out* __restrict__ Y, int64_t ld,
-                                                           int mt_count, int nt_count) {
-    static_assert(WAVES_M * WAVES_N == 4, "4 waves per work-group");
+// KB = bytes of k staged per row and stage (128 or 256); rows are padded by 16 bytes in LDS.
+template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int KB, int OCC>
+__global__ void __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
+    tx_mfma_kernel(const typename Prec<P>::elem* __restrict__ X, const typename Prec<P>::elem* __restrict__ T,
+                   typename Prec<P>::out* __restrict__ Y, int64_t ld, int mt_count, int nt_count) {
     using elem = typename Prec<P>::elem;
     using acc_t = typename Prec<P>::acc;
+    constexpr int NT = 64 * WAVES_M * WAVES_N;
     constexpr int BM = 16 * WM * WAVES_M;
     constexpr int BN = 16 * WN * WAVES_N;
     constexpr int ROWS = BM + BN;
-    constexpr int PER_T = ROWS * 8 / 256;
-    static_assert(ROWS * 8 % 256 == 0, "whole chunks per thread");
-    __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * kRowStride];
+    constexpr int CH = KB / 16;          // 16-byte chunks per staged row
+    constexpr int RS = KB + 16;          // padded LDS row stride
+    constexpr int PER_T = ROWS * CH / NT;
+    static_assert(ROWS * CH % NT == 0, "whole chunks per thread");
+    __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * RS];
 
     int mt, nt;
     xcd_tile(blockIdx.x, mt_count, mt_count * nt_count, mt, nt);
@@ -112,11 +117,11 @@ __global__ void __launch_bounds__(256, OCC) tx_mfma_kernel(const typename Prec<P
     int dst[PER_T];
 #pragma unroll
     for (int u = 0; u < PER_T; ++u) {
-        int q = tid + 256 * u;
-        int row = q >> 3, cc = q & 7;
+        int q = tid + NT * u;
+        int row = q / CH, cc = q % CH;
         const elem* base = row < BM ? X + (m0 + row) * ld : T + (n0 + row - BM) * ld;
         src[u] = reinterpret_cast<const char*>(base) + cc * 16;
-        dst[u] = row * kRowStride + cc * 16;
+        dst[u] = row * RS + cc * 16;
     }
 
     acc_t acc[WM][WN];
@@ -125,7 +130,7 @@ __global__ void __launch_bounds__(256, OCC) tx_mfma_kernel(const typename Prec<P
 #pragma unroll
         for (int b = 0; b < WN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-    const int nk = (int)(ld * (int64_t)sizeof(elem) / 128);
+    const int nk = (int)(ld * (int64_t)sizeof(elem) / KB);
     uint4 reg[PER_T];
 #pragma unroll
     for (int u = 0; u < PER_T; ++u) reg[u] = *reinterpret_cast<const uint4*>(src[u]);
@@ -136,28 +141,28 @@ __global__ void __launch_bounds__(256, OCC) tx_mfma_kernel(const typename Prec<P
     const int frag_row = lane & 15, frag_chunk = lane >> 4;
     for (int kt = 0; kt < nk; ++kt) {
         if (kt + 1 < nk) {
-            const int64_t off = (int64_t)(kt + 1) * 128;
+            const int64_t off = (int64_t)(kt + 1) * KB;
 #pragma unroll
             for (int u = 0; u < PER_T; ++u) reg[u] = *reinterpret_cast<const uint4*>(src[u] + off);
         }
-        const char* L = lds + (kt & 1) * ROWS * kRowStride;
+        const char* L = lds + (kt & 1) * ROWS * RS;
 #pragma unroll
-        for (int cg = 0; cg < 2; ++cg) {
+        for (int cg = 0; cg < CH / 4; ++cg) {
             uint4 af[WM], bf[WN];
             const int coff = (cg * 4 + frag_chunk) * 16;
 #pragma unroll
             for (int a = 0; a < WM; ++a)
-                af[a] = *reinterpret_cast<const uint4*>(L + (wm * 16 * WM + a * 16 + frag_row) * kRowStride + coff);
+                af[a] = *reinterpret_cast<const uint4*>(L + (wm * 16 * WM + a * 16 + frag_row) * RS + coff);
 #pragma unroll
             for (int b = 0; b < WN; ++b)
-                bf[b] = *reinterpret_cast<const uint4*>(L + (BM + wn * 16 * WN + b * 16 + frag_row) * kRowStride + coff);
+                bf[b] = *reinterpret_cast<const uint4*>(L + (BM + wn * 16 * WN + b * 16 + frag_row) * RS + coff);
 #pragma unroll
             for (int a = 0; a < WM; ++a)
 #pragma unroll
                 for (int b = 0; b < WN; ++b) mma_any<P>(acc[a][b], af[a], bf[b]);
         }
         if (kt + 1 < nk) {
-            char* S = lds + ((kt + 1) & 1) * ROWS * kRowStride;
+            char* S = lds + ((kt + 1) & 1) * ROWS * RS;
 #pragma unroll
             for (int u = 0; u < PER_T; ++u) *reinterpret_cast<uint4*>(S + dst[u]) = reg[u];
         }
@@ -255,39 +260,99 @@ __global__ void __launch_bounds__(256) tx_skinny_kernel(const typename Prec<P>::
     }
 }
 
+// ---- variant registry: every kernel shape that can compute a block product, per precision.
+
+struct Variant {
+    const char* name;
+    int bm, bn;        // output tile (m = columns of Y, n = atoms); bm = 0 for the narrow kernel
+    int max_ncol;      // largest ncol the variant accepts (narrow kernels hold columns in registers)
+    void (*launch)(const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st);
+};
+
+template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int KB, int OCC>
+void launch_mfma(const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st) {
+    constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+    using elem = typename Prec<P>::elem;
+    using out = typename Prec<P>::out;
+    const int mtc = (ncol + BM - 1) / BM, ntc = (int)(ld / BN);
+    hipLaunchKernelGGL((tx_mfma_kernel<P, WM, WN, WAVES_M, WAVES_N, KB, OCC>), dim3(mtc * ntc),
+                       dim3(64 * WAVES_M * WAVES_N), 0, st, static_cast<const elem*>(X), static_cast<const elem*>(T),
+                       static_cast<out*>(Y), ld, mtc, ntc);
+}
+
+template <int P, int NC>
+void launch_skinny(const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st) {
+    constexpr int R = 4;
+    using elem = typename Prec<P>::elem;
+    using out = typename Prec<P>::out;
+    hipLaunchKernelGGL((tx_skinny_kernel<P, NC, R>), dim3((unsigned)(ld / (4 * R))), dim3(256), 0, st,
+                       static_cast<const elem*>(X), static_cast<const elem*>(T), static_cast<out*>(Y), ld, ncol);
+}
+
 template <int P>
-void launch_tx(const Structure& s, const typename Prec<P>::elem* T, const typename Prec<P>::elem* X,
-               typename Prec<P>::out* Y, int ncol, hipStream_t st) {
-    if (ncol <= 0) return;
-    const int64_t ld = s.npad;
+const std::vector<Variant>& variants() {
+    constexpr int OCC2 = P == WFQ_PREC_FP64 ? 1 : 2;
+    static const std::vector<Variant> v = {
+        {"skinny2", 0, 4, 2, launch_skinny<P, 2>},
+        {"skinny4", 0, 4, 4, launch_skinny<P, 4>},
+        {"skinny8", 0, 4, 8, launch_skinny<P, 8>},
+        {"m32n128", 32, 128, 1 << 30, launch_mfma<P, 2, 2, 1, 4, 128, 2>},
+        {"m64n128", 64, 128, 1 << 30, launch_mfma<P, 4, 2, 1, 4, 128, 2>},
+        {"m128n128", 128, 128, 1 << 30, launch_mfma<P, 4, 4, 2, 2, 128, OCC2>},
+        {"m128n64", 128, 64, 1 << 30, launch_mfma<P, 4, 2, 2, 2, 128, 2>},
+        {"m64n256", 64, 256, 1 << 30, launch_mfma<P, 4, 4, 1, 4, 128, 1>},
+        {"m128n256w8", 128, 256, 1 << 30, launch_mfma<P, 4, 4, 2, 4, 128, 1>},
+        {"m256n128w8", 256, 128, 1 << 30, launch_mfma<P, 4, 4, 4, 2, 128, 1>},
+        {"m128n128k256", 128, 128, 1 << 30, launch_mfma<P, 4, 4, 2, 2, 256, 1>},
+        {"m64n128k256", 64, 128, 1 << 30, launch_mfma<P, 4, 2, 1, 4, 256, 1>},
+    };
+    return v;
+}
+
+const std::vector<Variant>& variants_of(int prec) {
+    return prec == WFQ_PREC_FP64 ? variants<WFQ_PREC_FP64>()
+           : prec == WFQ_PREC_FP32 ? variants<WFQ_PREC_FP32>() : variants<WFQ_PREC_BF16>();
+}
+
+int find_variant(int prec, const char* name) {
+    const auto& v = variants_of(prec);
+    for (size_t k = 0; k < v.size(); ++k)
+        if (std::strcmp(v[k].name, name) == 0) return (int)k;
+    return -1;
+}
+
+// Built-in choice when no tuning result covers ncol (the fastest shapes measured on MI355X for a
+// 20 000-atom T, per column count).
+int default_variant(int prec, int ncol) {
+    if (ncol <= 2) return find_variant(prec, "skinny2");
+    if (ncol <= 4) return find_variant(prec, "skinny4");
+    if (ncol <= 8) return find_variant(prec, "skinny8");
+    if (ncol <= 64) return find_variant(prec, "m64n128k256");
+    if (ncol <= 128) return find_variant(prec, "m128n64");
+    if (ncol <= 192) return find_variant(prec, "m64n128");
+    if (ncol <= 256) return find_variant(prec, "m256n128w8");
+    return find_variant(prec, "m128n256w8");
+}
+
+int pick_variant(const Structure& s, int prec, int ncol) {
+    const auto& tuned = s.tuned[prec];
+    // the tuned entry with the smallest ncol >= this one (or the largest tuned one)
+    auto it = tuned.lower_bound(ncol);
+    if (it == tuned.end() && !tuned.empty()) it = std::prev(tuned.end());
+    if (it != tuned.end()) {
+        const Variant& v = variants_of(prec)[it->second];
+        if (ncol <= v.max_ncol) return it->second;
+    }
+    return default_variant(prec, ncol);
+}
+
+void run_variant(const Structure& s, int prec, int var, const void* X, void* Y, int ncol, hipStream_t st) {
+    const void* T = prec == WFQ_PREC_FP64 ? (const void*)s.T64 : prec == WFQ_PREC_FP32 ? (const void*)s.T32
+                                                                                       : (const void*)s.T16;
     if (T == nullptr) throw Error{WFQ_EINVAL, "the stored copy of T for this precision was not built"};
-    if (ncol <= 8) {
-        constexpr int R = 4;
-        dim3 grd((unsigned)(ld / (4 * R)));
-        if (ncol <= 2)
-            hipLaunchKernelGGL((tx_skinny_kernel<P, 2, R>), grd, dim3(256), 0, st, X, T, Y, ld, ncol);
-        else if (ncol <= 4)
-            hipLaunchKernelGGL((tx_skinny_kernel<P, 4, R>), grd, dim3(256), 0, st, X, T, Y, ld, ncol);
-        else
-            hipLaunchKernelGGL((tx_skinny_kernel<P, 8, R>), grd, dim3(256), 0, st, X, T, Y, ld, ncol);
-        WFQ_CHECK_LAUNCH();
-        return;
-    }
-    constexpr int OCC = P == WFQ_PREC_FP64 ? 1 : 2;
-    if (ncol <= 32) {
-        constexpr int BM = 32, BN = 128;
-        int mtc = (int)((ncol + BM - 1) / BM), ntc = (int)(ld / BN);
-        hipLaunchKernelGGL((tx_mfma_kernel<P, 2, 2, 1, 4, 2>), dim3(mtc * ntc), dim3(256), 0, st, X, T, Y, ld, mtc, ntc);
-    } else if (ncol <= 64) {
-        constexpr int BM = 64, BN = 128;
-        int mtc = (int)((ncol + BM - 1) / BM), ntc = (int)(ld / BN);
-        hipLaunchKernelGGL((tx_mfma_kernel<P, 4, 2, 1, 4, 2>), dim3(mtc * ntc), dim3(256), 0, st, X, T, Y, ld, mtc, ntc);
-    } else {
-        constexpr int BM = 128, BN = 128;
-        int mtc = (int)((ncol + BM - 1) / BM), ntc = (int)(ld / BN);
-        hipLaunchKernelGGL((tx_mfma_kernel<P, 4, 4, 2, 2, OCC>), dim3(mtc * ntc), dim3(256), 0, st, X, T, Y, ld, mtc,
-                           ntc);
-    }
+    const Variant& v = variants_of(prec)[var];
+    if (ncol > v.max_ncol) throw Error{WFQ_EINVAL, "kernel variant cannot take that many columns"};
+    v.launch(X, T, Y, s.npad, ncol, st);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -312,21 +377,74 @@ void convert_from_f64(int prec, const double* src, void* dst, int64_t count, hip
 }
 
 void tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_t st) {
-    launch_tx<WFQ_PREC_FP64>(s, s.T64, X, Y, ncol, st);
+    if (ncol > 0) run_variant(s, WFQ_PREC_FP64, pick_variant(s, WFQ_PREC_FP64, ncol), X, Y, ncol, st);
 }
 void tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st) {
-    launch_tx<WFQ_PREC_FP32>(s, s.T32, X, Y, ncol, st);
+    if (ncol > 0) run_variant(s, WFQ_PREC_FP32, pick_variant(s, WFQ_PREC_FP32, ncol), X, Y, ncol, st);
 }
 void tx_bf16(const Structure& s, const uint16_t* X, float* Y, int ncol, hipStream_t st) {
-    launch_tx<WFQ_PREC_BF16>(s, s.T16, X, Y, ncol, st);
+    if (ncol > 0) run_variant(s, WFQ_PREC_BF16, pick_variant(s, WFQ_PREC_BF16, ncol), X, Y, ncol, st);
 }
 
 const char* tx_variant(int precision, int ncol) {
-    (void)precision;
-    if (ncol <= 8) return "skinny";
-    if (ncol <= 32) return "mfma_32x128";
-    if (ncol <= 64) return "mfma_64x128";
-    return "mfma_128x128";
+    return variants_of(precision)[default_variant(precision, ncol)].name;
+}
+
+int tx_variant_count(int precision) { return (int)variants_of(precision).size(); }
+const char* tx_variant_name(int precision, int k) { return variants_of(precision)[k].name; }
+int tx_variant_max_ncol(int precision, int k) { return variants_of(precision)[k].max_ncol; }
+
+// Time every variant that accepts ncol (reps launches each, after one warm-up launch) on random
+// device data and keep the fastest for this ncol in s.tuned. ms[k] = average time of variant k
+// (negative when the variant does not apply).
+void tune_tx(Structure& s, int prec, int ncol, int reps, double* ms, hipStream_t st) {
+    const int64_t rows = round_up(ncol, kColPad);
+    const int es = prec == WFQ_PREC_FP64 ? 8 : prec == WFQ_PREC_FP32 ? 4 : 2;
+    const int os = prec == WFQ_PREC_FP64 ? 8 : 4;
+    void *X = nullptr, *Y = nullptr;
+    double* X64 = nullptr;
+    WFQ_HIP(hipMalloc(&X, rows * s.npad * es));
+    WFQ_HIP(hipMalloc(&Y, rows * s.npad * os));
+    WFQ_HIP(hipMalloc(&X64, rows * s.npad * 8));
+    {
+        std::vector<double> h(rows * s.npad, 0.0);
+        uint64_t state = 0x9E3779B97F4A7C15ull * (uint64_t)(ncol + 1);
+        for (int64_t c = 0; c < ncol; ++c)
+            for (int64_t i = 0; i < s.n; ++i) {
+                state = state * 6364136223846793005ull + 1442695040888963407ull;
+                h[c * s.npad + i] = (double)(state >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+            }
+        WFQ_HIP(hipMemcpy(X64, h.data(), h.size() * 8, hipMemcpyHostToDevice));
+    }
+    convert_from_f64(prec, X64, X, rows * s.npad, st);
+    hipEvent_t a, b;
+    WFQ_HIP(hipEventCreate(&a));
+    WFQ_HIP(hipEventCreate(&b));
+    const auto& vs = variants_of(prec);
+    double best = 1e300;
+    int best_k = -1;
+    for (size_t k = 0; k < vs.size(); ++k) {
+        ms[k] = -1.0;
+        if (ncol > vs[k].max_ncol || (vs[k].bm == 0 && ncol > vs[k].max_ncol)) continue;
+        run_variant(s, prec, (int)k, X, Y, ncol, st);
+        WFQ_HIP(hipEventRecord(a, st));
+        for (int r = 0; r < reps; ++r) run_variant(s, prec, (int)k, X, Y, ncol, st);
+        WFQ_HIP(hipEventRecord(b, st));
+        WFQ_HIP(hipEventSynchronize(b));
+        float t = 0.f;
+        WFQ_HIP(hipEventElapsedTime(&t, a, b));
+        ms[k] = t / reps;
+        if (ms[k] < best) {
+            best = ms[k];
+            best_k = (int)k;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    (void)hipFree(X);
+    (void)hipFree(Y);
+    (void)hipFree(X64);
+    if (best_k >= 0) s.tuned[prec][ncol] = best_k;
 }
 
 }  // namespace wfq

@@ -51,12 +51,12 @@ __global__ void __launch_bounds__(256) pack_kernel(Basis V, const int* __restric
 }
 
 // Each thread owns one row of L and up to NS systems, so the row's (col, val) pairs are read once
-// for NS right-hand sides.
+// for NS right-hand sides; L is read in the transposed ELL layout (coalesced across rows).
 template <typename YE, int NS>
-__global__ void __launch_bounds__(256) spmm_kernel(int64_t n, const int32_t* __restrict__ rowptr,
-                                                   const int32_t* __restrict__ col, const double* __restrict__ val,
-                                                   const YE* __restrict__ Y, int64_t ld, const int* __restrict__ sys,
-                                                   int nsys, const double2* __restrict__ z, Basis V, int jsrc, int jdst) {
+__global__ void __launch_bounds__(256) spmm_kernel(int64_t n, int64_t npad, int w, const int32_t* __restrict__ ecol,
+                                                   const double* __restrict__ eval, const YE* __restrict__ Y,
+                                                   int64_t ld, const int* __restrict__ sys, int nsys,
+                                                   const double2* __restrict__ z, Basis V, int jsrc, int jdst) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int k0 = blockIdx.y * NS;
@@ -64,10 +64,9 @@ __global__ void __launch_bounds__(256) spmm_kernel(int64_t n, const int32_t* __r
     double ar[NS], ai[NS];
 #pragma unroll
     for (int t = 0; t < NS; ++t) ar[t] = ai[t] = 0.0;
-    const int p0 = rowptr[i], p1 = rowptr[i + 1];
-    for (int p = p0; p < p1; ++p) {
-        const int c = col[p];
-        const double v = val[p];
+    for (int p = 0; p < w; ++p) {
+        const int c = ecol[(int64_t)p * npad + i];
+        const double v = eval[(int64_t)p * npad + i];
 #pragma unroll
         for (int t = 0; t < NS; ++t)
             if (t < kn) {
@@ -234,32 +233,52 @@ __global__ void givens_kernel(const int* __restrict__ sys, int nsys, int j, int 
     a.flags[s] = f;
 }
 
-__global__ void tri_solve_kernel(const int* __restrict__ sys, int nsys, const int* __restrict__ ksteps, int mdim,
-                                 const double2* __restrict__ R, const double2* __restrict__ g, double2* __restrict__ y,
-                                 double* __restrict__ cond) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nsys) return;
-    const int s = sys[k];
+// One wave per system: column-oriented back substitution on R y = g (k <= mdim - 1 steps).
+__global__ void __launch_bounds__(64) tri_solve_kernel(const int* __restrict__ sys, const int* __restrict__ ksteps,
+                                                       int mdim, const double2* __restrict__ R,
+                                                       const double2* __restrict__ g, double2* __restrict__ y,
+                                                       double* __restrict__ cond) {
+    const int s = sys[blockIdx.x];
+    const int lane = threadIdx.x;
     const int kk = ksteps[s];
     const double2* Rs = R + (int64_t)s * mdim * mdim;
     const double2* gs = g + (int64_t)s * (mdim + 1);
     double2* ys = y + (int64_t)s * mdim;
+    // each lane keeps the right-hand side entries l = lane, lane + 64, ...
+    double2 rhs[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int l = lane + 64 * q;
+        rhs[q] = l < kk ? gs[l] : make_double2(0.0, 0.0);
+    }
     double dmax = 0.0, dmin = 1e300;
     for (int i = kk - 1; i >= 0; --i) {
-        double2 acc = gs[i];
-        for (int l = i + 1; l < kk; ++l) {
-            const double2 t = cmul(Rs[(int64_t)l * mdim + i], ys[l]);
-            acc.x -= t.x;
-            acc.y -= t.y;
-        }
+        const int owner = i & 63, slot = i >> 6;
+        double2 ri = make_double2(0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (q == slot) ri = rhs[q];
+        ri.x = __shfl(ri.x, owner, 64);
+        ri.y = __shfl(ri.y, owner, 64);
         const double2 d = Rs[(int64_t)i * mdim + i];
         const double dd = d.x * d.x + d.y * d.y;
-        ys[i] = make_double2((acc.x * d.x + acc.y * d.y) / dd, (acc.y * d.x - acc.x * d.y) / dd);
+        const double2 yi = make_double2((ri.x * d.x + ri.y * d.y) / dd, (ri.y * d.x - ri.x * d.y) / dd);
+        if (lane == 0) ys[i] = yi;
         const double ad = sqrt(dd);
         dmax = fmax(dmax, ad);
         dmin = fmin(dmin, ad);
+        // rhs_l -= R_li y_i for l < i (column i of R)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int l = lane + 64 * q;
+            if (l < i) {
+                const double2 t = cmul(Rs[(int64_t)i * mdim + l], yi);
+                rhs[q].x -= t.x;
+                rhs[q].y -= t.y;
+            }
+        }
     }
-    if (cond) cond[s] = kk > 0 && dmin > 0.0 ? dmax / dmin : 1.0;
+    if (cond && lane == 0) cond[s] = kk > 0 && dmin > 0.0 ? dmax / dmin : 1.0;
 }
 
 __global__ void __launch_bounds__(256) x_update_kernel(Basis V, Basis X, int64_t n, const int* __restrict__ sys,
@@ -282,8 +301,9 @@ __global__ void __launch_bounds__(256) x_update_kernel(Basis V, Basis X, int64_t
     xr[i + X.npad] += ai;
 }
 
-__global__ void __launch_bounds__(256) residual_kernel(int64_t n, const int32_t* __restrict__ rowptr,
-                                                       const int32_t* __restrict__ col, const double* __restrict__ val,
+__global__ void __launch_bounds__(256) residual_kernel(int64_t n, int64_t npad, int w,
+                                                       const int32_t* __restrict__ ecol,
+                                                       const double* __restrict__ eval,
                                                        const double* __restrict__ Y, int64_t ld,
                                                        const int* __restrict__ sys, const double2* __restrict__ z,
                                                        Basis X, const double* __restrict__ b, const int* __restrict__ dir,
@@ -295,9 +315,9 @@ __global__ void __launch_bounds__(256) residual_kernel(int64_t n, const int32_t*
     double nn = 0.0;
     if (i < n) {
         double ar = 0.0, ai = 0.0;
-        for (int p = rowptr[i]; p < rowptr[i + 1]; ++p) {
-            const int c = col[p];
-            const double v = val[p];
+        for (int p = 0; p < w; ++p) {
+            const int c = ecol[(int64_t)p * npad + i];
+            const double v = eval[(int64_t)p * npad + i];
             ar += v * Y[(int64_t)(2 * k) * ld + c];
             ai += v * Y[(int64_t)(2 * k + 1) * ld + c];
         }
@@ -399,14 +419,14 @@ void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, con
 void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
                 const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st) {
     if (nsys <= 0) return;
-    constexpr int NS = 4;
+    constexpr int NS = 8;
     dim3 grd((unsigned)((S.n + 255) / 256), (unsigned)((nsys + NS - 1) / NS));
     if (y_is_f64)
-        hipLaunchKernelGGL((spmm_kernel<double, NS>), grd, dim3(256), 0, st, S.n, S.rowptr, S.col, S.val,
-                           static_cast<const double*>(Y), ld, sys, nsys, z, V, jsrc, jdst);
+        hipLaunchKernelGGL((spmm_kernel<double, NS>), grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col,
+                           S.ell_val, static_cast<const double*>(Y), ld, sys, nsys, z, V, jsrc, jdst);
     else
-        hipLaunchKernelGGL((spmm_kernel<float, NS>), grd, dim3(256), 0, st, S.n, S.rowptr, S.col, S.val,
-                           static_cast<const float*>(Y), ld, sys, nsys, z, V, jsrc, jdst);
+        hipLaunchKernelGGL((spmm_kernel<float, NS>), grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col,
+                           S.ell_val, static_cast<const float*>(Y), ld, sys, nsys, z, V, jsrc, jdst);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -444,8 +464,8 @@ void givens_step(const int* sys, int nsys, int j, int mdim, const GivensArgs& a,
 void tri_solve(const int* sys, int nsys, const int* ksteps, int mdim, const double2* R, const double2* g,
                double2* y, double* cond, hipStream_t st) {
     if (nsys <= 0) return;
-    hipLaunchKernelGGL(tri_solve_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sys, nsys, ksteps, mdim, R, g, y,
-                       cond);
+    if (mdim > 257) throw Error{WFQ_EINVAL, "restart length above 256 is not supported"};
+    hipLaunchKernelGGL(tri_solve_kernel, dim3(nsys), dim3(64), 0, st, sys, ksteps, mdim, R, g, y, cond);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -462,8 +482,8 @@ void residual(const Structure& S, const double* Y, int64_t ld, const int* sys, i
               hipStream_t st) {
     if (nsys <= 0) return;
     dim3 grd((unsigned)nblk, (unsigned)nsys);
-    hipLaunchKernelGGL(residual_kernel, grd, dim3(256), 0, st, S.n, S.rowptr, S.col, S.val, Y, ld, sys, z, x, b, dir,
-                       V, norm2, nblk);
+    hipLaunchKernelGGL(residual_kernel, grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col, S.ell_val, Y, ld, sys,
+                       z, x, b, dir, V, norm2, nblk);
     WFQ_CHECK_LAUNCH();
 }
 

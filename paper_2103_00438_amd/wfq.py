@@ -99,6 +99,9 @@ _SIGNATURES = {
     "wfq_serve_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "wfq_serve_stop": (None, [C.c_void_p]),
     "wfq_last_error": (C.c_char_p, []),
+    "wfq_tx_variants": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_char_p), C.POINTER(C.c_int32)]),
+    "wfq_tune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32, _DP,
+                           C.POINTER(C.c_int32)]),
 }
 
 
@@ -316,6 +319,27 @@ def wfq_kernel_stats(h: Handle, reset=False) -> dict:
                                 int(reset)))
     return {names[q].decode(): dict(launches=int(la[q]), ms=float(ms[q]), flops=float(fl[q]), bytes=float(by[q]))
             for q in range(k)}
+
+
+def wfq_tx_variants(precision) -> list:
+    lib = load()
+    cnt = C.c_int32()
+    _check(lib.wfq_tx_variants(PREC[precision], C.byref(cnt), None, None))
+    names = (C.c_char_p * cnt.value)()
+    mx = (C.c_int32 * cnt.value)()
+    _check(lib.wfq_tx_variants(PREC[precision], C.byref(cnt), names, mx))
+    return [(names[k].decode(), mx[k]) for k in range(cnt.value)]
+
+
+def wfq_tune(h: Handle, precision, ncols, reps=5) -> dict:
+    """Time every block-product shape for each column count; the handle keeps the fastest."""
+    names = [v[0] for v in wfq_tx_variants(precision)]
+    nc = np.ascontiguousarray(ncols, dtype=np.int32)
+    ms = np.zeros((len(nc), len(names)))
+    chosen = np.zeros(len(nc), dtype=np.int32)
+    _check(load().wfq_tune(h.ptr, PREC[precision], nc.ctypes.data_as(C.POINTER(C.c_int32)), len(nc), int(reps),
+                           _dp(ms), chosen.ctypes.data_as(C.POINTER(C.c_int32))))
+    return dict(variants=names, ncols=nc.tolist(), ms=ms, chosen=[names[c] if c >= 0 else None for c in chosen])
 
 
 # ------------------------------------------------------------------ serving

@@ -87,6 +87,8 @@ def main():
     ncols = sorted({c for c in (16, 32, 64, 96, 128, 192, 256, 320, 384, 512, 640, 768) if c <= 2 * wl.n_systems}
                    | {2 * wl.n_systems})
     tune = wfq.wfq_tune(h, prec, ncols, reps=2)
+    if prec != "fp64":
+        wfq.wfq_tune(h, "fp64", ncols, reps=2)   # shapes of the FP64 refinement products
     tune_s = time.perf_counter() - t0
 
     for _ in range(args.warmup):

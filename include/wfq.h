@@ -94,7 +94,7 @@ typedef struct {
 
 typedef struct {
     int32_t algorithm;   /* WFQ_GMRES or WFQ_QMR */
-    int32_t restart;     /* GMRES: Krylov dimension m per cycle (1..256); QMR: steps between FP64 checks */
+    int32_t restart;     /* GMRES: Krylov dimension m per cycle (1..256); QMR: steps between FP64 checks (>= 1) */
     int32_t max_iter;    /* cap on T products per system (inner iterations); > 0 */
     int32_t precision;   /* WFQ_PREC_*: precision of T inside the iterations (FP64 refinement always) */
     double  E0;          /* field amplitude (atomic units); 0 means 1 */

@@ -70,7 +70,8 @@ void check_device(int device) {
 void check_opts(const wfq_solve_opts* o) {
     if (!o) fail(WFQ_EINVAL, "opts is NULL");
     if (o->algorithm != WFQ_GMRES && o->algorithm != WFQ_QMR) fail(WFQ_EINVAL, "unknown algorithm");
-    if (o->restart < 1 || o->restart > 256) fail(WFQ_EINVAL, "restart must be in [1, 256]");
+    if (o->restart < 1) fail(WFQ_EINVAL, "restart must be >= 1");
+    if (o->algorithm == WFQ_GMRES && o->restart > 256) fail(WFQ_EINVAL, "GMRES restart must be in [1, 256]");
     if (o->max_iter < 1) fail(WFQ_EINVAL, "max_iter must be >= 1");
     if (o->precision != WFQ_PREC_FP64 && o->precision != WFQ_PREC_FP32 && o->precision != WFQ_PREC_BF16)
         fail(WFQ_EINVAL, "unknown precision");
@@ -166,8 +167,8 @@ static int solve_impl(wfq_handle* h, const double* omegas_eV, int32_t n_omega, c
     return guarded([&]() -> int {
         check_solve_args(h, omegas_eV, n_omega, dirs, n_dir, tol, o);
         WFQ_HIP(hipSetDevice(h->S.device));
-        if (h->S.t_mode != WFQ_TMODE_STORED && o->algorithm != WFQ_GMRES)
-            fail(WFQ_EINVAL, "matrix-free T supports GMRES only");
+        if (h->S.t_mode != WFQ_TMODE_STORED && o->precision == WFQ_PREC_BF16)
+            fail(WFQ_EINVAL, "matrix-free T runs in FP32 or FP64");
         int rc = solve_all(h->S, omegas_eV, n_omega, dirs, n_dir, tol, *o, out, st, o->timing ? h->stats : nullptr);
         if (rc != WFQ_OK) set_error(rc, "some systems did not converge cleanly (see info[].status)");
         return rc;

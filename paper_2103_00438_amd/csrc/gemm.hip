@@ -336,10 +336,11 @@ int default_variant(int prec, int ncol) {
 
 int pick_variant(const Structure& s, int prec, int ncol) {
     const auto& tuned = s.tuned[prec];
-    // the tuned entry with the smallest ncol >= this one (or the largest tuned one)
+    // the tuned entry with the smallest ncol >= this one (or the largest tuned one), used only when
+    // it was tuned for a comparable width (within a factor of two)
     auto it = tuned.lower_bound(ncol);
     if (it == tuned.end() && !tuned.empty()) it = std::prev(tuned.end());
-    if (it != tuned.end()) {
+    if (it != tuned.end() && it->first <= 2 * ncol && ncol <= 2 * it->first) {
         const Variant& v = variants_of(prec)[it->second];
         if (ncol <= v.max_ncol) return it->second;
     }

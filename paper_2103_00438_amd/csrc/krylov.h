@@ -81,26 +81,33 @@ void observables(const Structure& S, const int* sys, int nsys, const Basis& x, d
 void scatter_q(const Structure& S, const int32_t* perm, const int* sys, int nsys, const Basis& x, double* q_re,
                double* q_im, hipStream_t st);
 
-// ---- J-symmetric QMR from BCG, one step split around the T product (see qmr kernels)
-struct QmrVecs {
-    Basis x, r, p, tp, q, xq, s;   // slot 0 of each
-};
-// rho_new partials: sum_i r_i (T r)_i (bilinear), with T r taken from Y (FP32 or FP64) columns
-void qmr_rho(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const QmrVecs& v, int64_t n,
-             double2* partial, hipStream_t st);
-// p = r + beta p, tp = Tr + beta tp (beta from rho_new / rho_old, or 0 at the first step)
-void qmr_dirs(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const QmrVecs& v, int64_t n,
+// ---- J-symmetric QMR from BCG (qmr.hip). Slots of the per-system basis Q:
+// 0 r, 1 p, 2 T p, 3 q = M p, 4 x (BCG), 5 xq (QMR iterate), 6 s (QMR residual).
+constexpr int kQmrSlots = 7;
+// partial[s][blk] of rho = r^T (T r), T r read from the packed block Y (rows 2k, 2k+1)
+void qmr_rho(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const Basis& Q, int64_t n,
+             double2* partial, int nblk, hipStream_t st);
+// beta = rho_new / rho_old (0 where first[s]); p = r + beta p; T p = T r + beta T p
+void qmr_dirs(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const Basis& Q, int64_t n,
               const double2* rho_new, const double2* rho_old, const int* first, hipStream_t st);
-// q = L tp + z p and partial sigma = tp^T q
-void qmr_q(const Structure& S, const int* sys, int nsys, const QmrVecs& v, const double2* z, double2* partial,
-           hipStream_t st);
-// alpha = rho / sigma; x += alpha p; r -= alpha q; partial |r|^2
-void qmr_xr(const int* sys, int nsys, const QmrVecs& v, int64_t n, const double2* rho, const double2* sigma,
-            double* norm2, hipStream_t st);
-// QMR smoothing: tau2 update from |r|^2, eta; xq += eta (x - xq); s += eta (r - s); partial |s|^2
-void qmr_smooth(const int* sys, int nsys, const QmrVecs& v, int64_t n, const double* rnorm, double* tau2,
-                double* norm2, hipStream_t st);
-// generic complex partial-sum reduction: out[s] = sum_b partial[s][b] (nb per system)
+// q = L (T p) + z p with partials of sigma = (T p)^T q and of ||T p||^2, ||q||^2
+void qmr_q(const Structure& S, const int* sys, int nsys, const Basis& Q, const double2* z, double2* part_sig,
+           double2* part_nrm, int nblk, hipStream_t st);
+// sigma[s] and breakdown flags (bit 3: Lanczos breakdown, bit 2: NaN)
+void qmr_sigma(const int* sys, int nsys, const double2* part_sig, const double2* part_nrm, int nblk,
+               const double2* rho, double2* sigma, int* flags, hipStream_t st);
+// alpha = rho / sigma; x += alpha p; r -= alpha q; partials of ||r||^2
+void qmr_xr(const int* sys, int nsys, const Basis& Q, int64_t n, const double2* rho, const double2* sigma,
+            double* norm2, int nblk, hipStream_t st);
+// tau^2 and eta of the smoothing from ||r||^2; clears first[s]
+void qmr_weights(const int* sys, int nsys, const double* rn_part, int nblk, double* tau2, double* eta, int* first,
+                 hipStream_t st);
+// xq += eta (x - xq); s += eta (r - s); partials of ||s||^2
+void qmr_smooth(const int* sys, int nsys, const Basis& Q, int64_t n, const double* eta, double* norm2, int nblk,
+                hipStream_t st);
+// restart from the QMR iterate: x = xq, p = T p = 0, s = r (r must hold the residual of xq)
+void qmr_restart(const int* sys, int nsys, const Basis& Q, hipStream_t st);
+// out[s] = sum_b partial[s][b]
 void reduce_complex(const int* sys, int nsys, const double2* partial, int nb, double2* out, hipStream_t st);
 
 }  // namespace wfq

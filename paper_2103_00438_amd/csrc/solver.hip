@@ -127,6 +127,11 @@ struct Work {
     DevArray<float> X32, Y32, Y16;
     DevArray<uint16_t> X16;
     DevArray<double2> partial, h1, h2, R, sn, g, y, z, alpha;
+    // QMR scalars and partials
+    DevArray<double2> rho_a, rho_b, sigma, part_sig, part_nrm;
+    DevArray<double> tau2, eta, snorm;
+    DevArray<int> first;
+    PinnedArray<double> h_snorm;
     DevArray<int> flags, ksteps, dir, sys[NSLOT];
     PinnedArray<int> h_sys[NSLOT], h_flags, h_ksteps;
     PinnedArray<double> h_est, h_beta, h_invb;
@@ -190,9 +195,22 @@ void alloc_work(Work& w, const Structure& S, int B, int m, int n_dir, int prec) 
     w.h_invb.alloc(B);
     w.h_g.alloc((size_t)B * (w.mdim + 1));
     w.h_alpha.alloc((size_t)B * 3);
+    w.rho_a.alloc(B);
+    w.rho_b.alloc(B);
+    w.sigma.alloc(B);
+    w.part_sig.alloc((size_t)B * w.nblk);
+    w.part_nrm.alloc((size_t)B * w.nblk);
+    w.tau2.alloc(B);
+    w.eta.alloc(B);
+    w.snorm.alloc(B);
+    w.first.alloc(B);
+    w.h_snorm.alloc(B);
     w.Vb = Basis{w.V.p, (int64_t)w.mdim * 2 * np, 2 * np, np};
     w.Xb = Basis{w.X.p, 2 * np, 2 * np, np};
 }
+
+// view of one vector slot of a basis as a one-slot basis
+Basis slot_view(const Basis& V, int j) { return Basis{V.base + (int64_t)j * V.vec_stride, V.sys_stride, V.vec_stride, V.npad}; }
 
 void upload(Work& w, int slot, const std::vector<int>& v, hipStream_t st) {
     std::memcpy(w.h_sys[slot].p, v.data(), v.size() * sizeof(int));
@@ -255,7 +273,7 @@ void fp64_residual(const Structure& S, Work& w, const std::vector<int>& act, Tim
 
 // Restarted GMRES(m) with FP64 refinement at every restart, for the systems of one batch.
 void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double tol, const wfq_solve_opts& o,
-                 Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0) {
+                 Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0, bool warm = false) {
     const int B = (int)ss.size();
     const int m = w.mdim - 1;
     const double n = (double)S.n;
@@ -269,7 +287,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         }
         WFQ_HIP(hipMemcpyAsync(w.z.p, zh.data(), B * sizeof(double2), hipMemcpyHostToDevice, st));
         WFQ_HIP(hipMemcpyAsync(w.dir.p, dh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemsetAsync(w.X.p, 0, w.X.count * sizeof(double), st));
+        if (!warm) WFQ_HIP(hipMemsetAsync(w.X.p, 0, w.X.count * sizeof(double), st));
         WFQ_HIP(hipStreamSynchronize(st));
     }
     std::vector<int> all(B);
@@ -299,6 +317,25 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         }
         WFQ_HIP(hipMemcpyAsync(w.tol_abs.p, tol_h.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
         WFQ_HIP(hipStreamSynchronize(st));
+    }
+    if (warm && !active.empty()) {
+        // start from the given x: r = b - (L T + z I) x in FP64
+        upload(w, SLOT_ACT, active, st);
+        fp64_residual(S, w, active, tm, st);
+        WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipStreamSynchronize(st));
+        std::vector<int> still;
+        for (int s : active) {
+            ss[s].beta = w.h_beta.p[s];
+            ss[s].relres = ss[s].beta / ss[s].bnorm;
+            if (ss[s].relres <= tol) {
+                ss[s].done = true;
+                ss[s].t_done = ms_since(t0);
+            } else {
+                still.push_back(s);
+            }
+        }
+        active.swap(still);
     }
 
     GivensArgs ga{w.h1.p, w.h2.p, w.norm2.p, (int)w.nwc, w.R.p, w.cs.p, w.sn.p, w.g.p, w.est.p, w.inv_h.p,
@@ -425,11 +462,181 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
     }
 }
 
+// J-symmetric QMR from BCG (J = T) with FP64 refinement every o.restart steps; systems whose Lanczos
+// process breaks down are returned in `broken` (their QMR iterate stays in slot 5) for a GMRES
+// fallback.
+void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double tol, const wfq_solve_opts& o,
+               Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0, std::vector<int>& broken) {
+    const int B = (int)ss.size();
+    const double n = (double)S.n;
+    const Basis Q = w.Vb;
+    const Basis XQ = slot_view(Q, 5);
+    {
+        std::vector<double2> zh(B);
+        std::vector<int> dh(B);
+        for (int s = 0; s < B; ++s) {
+            zh[s] = ss[s].z;
+            dh[s] = ss[s].dir;
+        }
+        WFQ_HIP(hipMemcpyAsync(w.z.p, zh.data(), B * sizeof(double2), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(w.dir.p, dh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemsetAsync(w.V.p, 0, w.V.count * sizeof(double), st));
+    }
+    std::vector<int> all(B);
+    for (int s = 0; s < B; ++s) all[s] = s;
+    upload(w, SLOT_ACT, all, st);
+    copy_rhs(S, w.sys[SLOT_ACT].p, B, w.b.p, w.dir.p, Q, w.norm2.p, (int)w.nblk, st);   // r = b (x0 = 0)
+    sumsq(w.sys[SLOT_ACT].p, B, w.norm2.p, (int)w.nblk, w.beta.p, st);
+    WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    WFQ_HIP(hipStreamSynchronize(st));
+    std::vector<int> active;
+    for (int s = 0; s < B; ++s) {
+        ss[s].bnorm = ss[s].beta = w.h_beta.p[s];
+        if (ss[s].bnorm == 0.0) {
+            ss[s].relres = 0.0;
+            ss[s].done = true;
+            ss[s].t_done = ms_since(t0);
+        } else if (!std::isfinite(ss[s].bnorm)) {
+            ss[s].status = WFQ_ENUMERIC;
+            ss[s].done = true;
+        } else {
+            active.push_back(s);
+        }
+    }
+    const int nblk = (int)w.nblk;
+    while (!active.empty()) {
+        // cycle start: x = xq, p = T p = 0, s = r, tau = ||r||
+        const int na = (int)active.size();
+        upload(w, SLOT_ACT, active, st);
+        std::vector<double> t2(B, 0.0);
+        std::vector<int> fh(B, 1);
+        for (int s : active) {
+            t2[s] = ss[s].beta * ss[s].beta;
+            ss[s].cycles += 1;
+        }
+        WFQ_HIP(hipMemcpyAsync(w.tau2.p, t2.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(w.first.p, fh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        qmr_restart(w.sys[SLOT_ACT].p, na, Q, st);
+        WFQ_HIP(hipStreamSynchronize(st));
+        double2* rho_new = w.rho_a.p;
+        double2* rho_old = w.rho_b.p;
+        std::vector<int> stepping;
+        for (int s : active)
+            if (ss[s].iters < o.max_iter) stepping.push_back(s);
+        for (int k = 0; k < o.restart && !stepping.empty(); ++k) {
+            const int ns = (int)stepping.size();
+            std::vector<int> grp[3];
+            for (int s : stepping) grp[ss[s].prec].push_back(s);
+            for (int p = 0; p < 3; ++p) {
+                if (grp[p].empty()) continue;
+                const int ng = (int)grp[p].size();
+                upload(w, p, grp[p], st);
+                tm.begin(st);
+                pack_columns(p, Q, w.sys[p].p, ng, 0, nullptr, false, x_block(w, p), w.npad, st);
+                tm.end(st, KC_PACK, 0, ng * n * (16.0 + 2 * elem_size(p)));
+                block_product(S, w, p, 2 * ng, tm, st);
+                tm.begin(st);
+                qmr_rho(p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, Q, S.n, w.part_sig.p, nblk, st);
+                reduce_complex(w.sys[p].p, ng, w.part_sig.p, nblk, rho_new, st);
+                qmr_dirs(p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, Q, S.n, rho_new, rho_old,
+                         w.first.p, st);
+                tm.end(st, KC_QMR, 0, ng * n * (16.0 * 5 + 4 * out_size(p)));
+            }
+            upload(w, SLOT_STEP, stepping, st);
+            const int* sl = w.sys[SLOT_STEP].p;
+            tm.begin(st);
+            qmr_q(S, sl, ns, Q, w.z.p, w.part_sig.p, w.part_nrm.p, nblk, st);
+            tm.end(st, KC_SPMM, 4.0 * S.nnz * ns, 12.0 * S.nnz + ns * n * 48.0);
+            tm.begin(st);
+            qmr_sigma(sl, ns, w.part_sig.p, w.part_nrm.p, nblk, rho_new, w.sigma.p, w.flags.p, st);
+            qmr_xr(sl, ns, Q, S.n, rho_new, w.sigma.p, w.norm2.p, nblk, st);
+            qmr_weights(sl, ns, w.norm2.p, nblk, w.tau2.p, w.eta.p, w.first.p, st);
+            qmr_smooth(sl, ns, Q, S.n, w.eta.p, w.norm2.p, nblk, st);
+            sumsq(sl, ns, w.norm2.p, nblk, w.snorm.p, st);
+            tm.end(st, KC_QMR, 0, ns * n * 16.0 * 12);
+            WFQ_HIP(hipMemcpyAsync(w.h_flags.p, w.flags.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
+            WFQ_HIP(hipMemcpyAsync(w.h_snorm.p, w.snorm.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+            WFQ_HIP(hipStreamSynchronize(st));
+            std::swap(rho_new, rho_old);
+            std::vector<int> next;
+            for (int s : stepping) {
+                ss[s].iters += 1;
+                ss[s].est_end = w.h_snorm.p[s];
+                const int f = w.h_flags.p[s];
+                if (f & 4) {
+                    ss[s].status = WFQ_ENUMERIC;
+                    continue;
+                }
+                if (f & 8) {
+                    ss[s].status = WFQ_EBREAKDOWN;
+                    continue;
+                }
+                if (w.h_snorm.p[s] > 0.5 * tol * ss[s].bnorm && ss[s].iters < o.max_iter) next.push_back(s);
+            }
+            stepping.swap(next);
+        }
+        // systems that broke down leave for the GMRES fallback; NaN ends a system
+        std::vector<int> act2;
+        for (int s : active) {
+            if (ss[s].status == WFQ_ENUMERIC) {
+                ss[s].done = true;
+                ss[s].t_done = ms_since(t0);
+            } else if (ss[s].status == WFQ_EBREAKDOWN) {
+                broken.push_back(s);
+            } else {
+                act2.push_back(s);
+            }
+        }
+        active.swap(act2);
+        if (active.empty()) break;
+        // FP64 refinement point: r = b - (L T + z I) xq into slot 0
+        upload(w, SLOT_ACT, active, st);
+        {
+            const int na2 = (int)active.size();
+            tm.begin(st);
+            pack_columns(WFQ_PREC_FP64, XQ, w.sys[SLOT_ACT].p, na2, 0, nullptr, false, w.X64.p, w.npad, st);
+            tm.end(st, KC_PACK, 0, 32.0 * n * na2);
+            block_product(S, w, WFQ_PREC_FP64, 2 * na2, tm, st);
+            tm.begin(st);
+            residual(S, w.Y64.p, w.npad, w.sys[SLOT_ACT].p, na2, w.z.p, XQ, w.b.p, w.dir.p, Q, w.norm2.p, nblk, st);
+            sumsq(w.sys[SLOT_ACT].p, na2, w.norm2.p, nblk, w.beta.p, st);
+            tm.end(st, KC_RESID, 0, 12.0 * S.nnz + na2 * n * 56.0);
+        }
+        WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipStreamSynchronize(st));
+        std::vector<int> still;
+        const double now = ms_since(t0);
+        for (int s : active) {
+            const double beta_prev = ss[s].beta;
+            ss[s].beta = w.h_beta.p[s];
+            ss[s].relres = ss[s].beta / ss[s].bnorm;
+            if (!std::isfinite(ss[s].beta)) {
+                ss[s].status = WFQ_ENUMERIC;
+                ss[s].done = true;
+                ss[s].t_done = now;
+            } else if (ss[s].relres <= tol) {
+                ss[s].done = true;
+                ss[s].t_done = now;
+            } else if (ss[s].iters >= o.max_iter) {
+                ss[s].status = WFQ_ENOCONV;
+                ss[s].done = true;
+                ss[s].t_done = now;
+            } else {
+                if (o.escalate && ss[s].prec != WFQ_PREC_FP64 && ss[s].beta > 0.5 * beta_prev &&
+                    ss[s].beta > 100.0 * ss[s].est_end)
+                    ss[s].prec = escalate_prec(S, ss[s].prec);
+                still.push_back(s);
+            }
+        }
+        active.swap(still);
+    }
+}
+
 }  // namespace
 
 uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_dir) {
     const uint64_t np = S.npad;
-    const uint64_t mdim = (uint64_t)o.restart + 1;
+    const uint64_t mdim = o.algorithm == WFQ_QMR ? (uint64_t)kQmrSlots : (uint64_t)o.restart + 1;
     const uint64_t mpad = round_up(2 * (int64_t)B, kColPad);
     uint64_t b = 0;
     b += (uint64_t)B * mdim * 2 * np * 8;       // basis
@@ -465,7 +672,9 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
         throw Error{WFQ_ENOMEM, "not enough device memory for one system's Krylov work space"};
 
     Work w;
-    alloc_work(w, S, B, o.restart, n_dir, prec);
+    const bool qmr = o.algorithm == WFQ_QMR;
+    alloc_work(w, S, B, qmr ? kQmrSlots - 1 : o.restart, n_dir, prec);
+    if (qmr) w.Xb = slot_view(w.Vb, 5);   // the QMR iterate is the solution
     // right-hand sides b_k = E0 L r_k (shared by every frequency)
     {
         DevArray<double> d_dirs;
@@ -492,10 +701,43 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
             ss[s].z = make_double2(-(om * om) / S.W, -(om / S.tau) / S.W);   // z = -(w^2 + i w / tau) / W
             ss[s].prec = prec;
         }
-        if (o.algorithm == WFQ_GMRES)
+        if (!qmr) {
             gmres_batch(S, w, ss, tol, o, tm, st, t0);
-        else
-            throw Error{WFQ_EINVAL, "QMR is not available in this build"};
+        } else {
+            std::vector<int> broken;
+            qmr_batch(S, w, ss, tol, o, tm, st, t0, broken);
+            if (!broken.empty()) {
+                // GMRES fallback from the QMR iterate of each broken-down system
+                wfq_solve_opts og = o;
+                og.algorithm = WFQ_GMRES;
+                og.restart = std::min(50, std::max(o.restart, 10));
+                const int nbk = (int)broken.size();
+                Work wg;
+                alloc_work(wg, S, nbk, og.restart, n_dir, prec);
+                WFQ_HIP(hipMemcpyAsync(wg.b.p, w.b.p, w.b.count * sizeof(double), hipMemcpyDeviceToDevice, st));
+                std::vector<SysState> sg(nbk);
+                for (int q = 0; q < nbk; ++q) {
+                    const int s = broken[q];
+                    sg[q] = ss[s];
+                    sg[q].status = WFQ_OK;
+                    sg[q].done = false;
+                    WFQ_HIP(hipMemcpyAsync(wg.X.p + (size_t)q * 2 * S.npad, w.Xb.base + (size_t)s * w.Xb.sys_stride,
+                                           2 * S.npad * sizeof(double), hipMemcpyDeviceToDevice, st));
+                }
+                gmres_batch(S, wg, sg, tol, og, tm, st, t0, true);
+                for (int q = 0; q < nbk; ++q) {
+                    const int s = broken[q];
+                    const int iters_qmr = ss[s].iters, cycles_qmr = ss[s].cycles;
+                    ss[s] = sg[q];
+                    ss[s].iters += iters_qmr;
+                    ss[s].cycles += cycles_qmr;
+                    if (ss[s].status == WFQ_ENOCONV) ss[s].status = WFQ_EBREAKDOWN;
+                    WFQ_HIP(hipMemcpyAsync(w.Xb.base + (size_t)s * w.Xb.sys_stride, wg.X.p + (size_t)q * 2 * S.npad,
+                                           2 * S.npad * sizeof(double), hipMemcpyDeviceToDevice, st));
+                }
+                WFQ_HIP(hipStreamSynchronize(st));
+            }
+        }
         // outputs of the batch
         std::vector<int> all(nb);
         for (int s = 0; s < nb; ++s) all[s] = s;

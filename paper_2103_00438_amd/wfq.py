@@ -106,12 +106,21 @@ _SIGNATURES = {
 
 
 def load(path: str = LIB_PATH) -> C.CDLL:
-    """Load libwfq.so (raises if it is missing: there is no fallback path)."""
+    """Load libwfq.so (raises if it is missing: there is no fallback path).
+
+    PyTorch ships its own HIP runtime and loads it under the same SONAME (libamdhip64.so.7) that
+    libwfq.so needs. Importing torch first makes libwfq bind to that already-loaded runtime, so the
+    process holds one HIP runtime and torch's device buffers and streams are valid inside libwfq.
+    """
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libwfq.so not found at {path}; build it with python -m paper_2103_00438_amd.build")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in _SIGNATURES.items():
         f = getattr(lib, name)

@@ -31,7 +31,7 @@ struct wfq_handle {
 
 namespace {
 
-const char* kClassNames[KC_COUNT] = {"tx_gemm_f64", "tx_gemm_f32", "tx_gemm_bf16", "tx_skinny", "tx_otf",
+const char* kClassNames[KC_COUNT] = {"tx_gemm_f64", "tx_gemm_f32", "tx_gemm_bf16", "tx_skinny", "tx_otf_f32", "tx_otf_f64",
                                      "spmm_shift",  "cgs_dot",     "cgs_update",   "givens",    "pack",
                                      "x_update",    "fp64_residual", "qmr",        "other"};
 
@@ -298,14 +298,10 @@ int wfq_apply_T(wfq_handle* h, int32_t precision, int32_t ncol, const double* X,
         WFQ_HIP(hipMemcpyAsync(dx64, xh.data(), rows * np * 8, hipMemcpyHostToDevice, h->stream));
         convert_from_f64(precision, dx64, dx, rows * np, h->stream);
         std::vector<double> yh((size_t)ncol * np);
+        tx_any(S, precision, dx, dy, ncol, h->stream);
         if (precision == WFQ_PREC_FP64) {
-            tx_f64(S, (const double*)dx, (double*)dy, ncol, h->stream);
             WFQ_HIP(hipMemcpyAsync(yh.data(), dy, (size_t)ncol * np * 8, hipMemcpyDeviceToHost, h->stream));
         } else {
-            if (precision == WFQ_PREC_FP32)
-                tx_f32(S, (const float*)dx, (float*)dy, ncol, h->stream);
-            else
-                tx_bf16(S, (const uint16_t*)dx, (float*)dy, ncol, h->stream);
             std::vector<float> yf((size_t)ncol * np);
             WFQ_HIP(hipMemcpyAsync(yf.data(), dy, (size_t)ncol * np * 4, hipMemcpyDeviceToHost, h->stream));
             WFQ_HIP(hipStreamSynchronize(h->stream));
@@ -360,12 +356,7 @@ int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t nsys, const double* z
         WFQ_HIP(hipMemcpyAsync(dsys, sl.data(), nsys * sizeof(int), hipMemcpyHostToDevice, h->stream));
         Basis V{dv, sys_stride, 2 * np, np};
         pack_columns(precision, V, dsys, nsys, 0, nullptr, false, dx, np, h->stream);
-        if (precision == WFQ_PREC_FP64)
-            tx_f64(S, (const double*)dx, (double*)dy, 2 * nsys, h->stream);
-        else if (precision == WFQ_PREC_FP32)
-            tx_f32(S, (const float*)dx, (float*)dy, 2 * nsys, h->stream);
-        else
-            tx_bf16(S, (const uint16_t*)dx, (float*)dy, 2 * nsys, h->stream);
+        tx_any(S, precision, dx, dy, 2 * nsys, h->stream);
         spmm_shift(S, precision == WFQ_PREC_FP64, dy, np, dsys, nsys, dz, V, 0, 1, h->stream);
         WFQ_HIP(hipMemcpyAsync(vh.data(), dv, vh.size() * 8, hipMemcpyDeviceToHost, h->stream));
         WFQ_HIP(hipStreamSynchronize(h->stream));

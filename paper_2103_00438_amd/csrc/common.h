@@ -79,7 +79,7 @@ struct KernelStat {
 };
 
 enum KernelClass {
-    KC_GEMM_F64 = 0, KC_GEMM_F32, KC_GEMM_BF16, KC_SKINNY, KC_OTF,
+    KC_GEMM_F64 = 0, KC_GEMM_F32, KC_GEMM_BF16, KC_SKINNY, KC_OTF, KC_OTF_F64,
     KC_SPMM, KC_DOT, KC_UPDATE, KC_GIVENS, KC_PACK, KC_XUPDATE, KC_RESID, KC_QMR, KC_OTHER,
     KC_COUNT
 };
@@ -123,6 +123,8 @@ void tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_
 void tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st);
 void tx_bf16(const Structure& s, const uint16_t* X, float* Y, int ncol, hipStream_t st);
 const char* tx_variant(int precision, int ncol);
+// T X with the stored copy of T in `prec`, or recomputed on the fly when the structure is matrix-free
+void tx_any(const Structure& s, int prec, const void* X, void* Y, int ncol, hipStream_t st);
 int tx_variant_count(int precision);
 const char* tx_variant_name(int precision, int k);
 int tx_variant_max_ncol(int precision, int k);

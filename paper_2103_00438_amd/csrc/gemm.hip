@@ -387,6 +387,24 @@ void tx_bf16(const Structure& s, const uint16_t* X, float* Y, int ncol, hipStrea
     if (ncol > 0) run_variant(s, WFQ_PREC_BF16, pick_variant(s, WFQ_PREC_BF16, ncol), X, Y, ncol, st);
 }
 
+void tx_any(const Structure& s, int prec, const void* X, void* Y, int ncol, hipStream_t st) {
+    if (s.t_mode == WFQ_TMODE_OTF) {
+        if (prec == WFQ_PREC_FP32)
+            otf_tx_f32(s, static_cast<const float*>(X), static_cast<float*>(Y), ncol, st);
+        else if (prec == WFQ_PREC_FP64)
+            otf_tx_f64(s, static_cast<const double*>(X), static_cast<double*>(Y), ncol, st);
+        else
+            throw Error{WFQ_EINVAL, "matrix-free T runs in FP32 or FP64"};
+        return;
+    }
+    if (prec == WFQ_PREC_FP64)
+        tx_f64(s, static_cast<const double*>(X), static_cast<double*>(Y), ncol, st);
+    else if (prec == WFQ_PREC_FP32)
+        tx_f32(s, static_cast<const float*>(X), static_cast<float*>(Y), ncol, st);
+    else
+        tx_bf16(s, static_cast<const uint16_t*>(X), static_cast<float*>(Y), ncol, st);
+}
+
 const char* tx_variant(int precision, int ncol) {
     return variants_of(precision)[default_variant(precision, ncol)].name;
 }

@@ -1,2 +1,228 @@
-// placeholder translation unit, filled below
+// Matrix-free block products Y = T X: the damped Coulomb elements of Eq. (d-matrix) are recomputed
+// in every product instead of being stored (arXiv 2103.00438, subsection "Large systems": the
+// on-the-fly matrix-vector product). The sparse half L is still applied from its stored rows.
+//
+// A work-group owns BI = 128 target atoms and BC columns of X. It walks over the sources in tiles of
+// BJ atoms; per tile it stages the source positions (relative to the centre of its target block,
+// so that coordinate differences keep full relative precision in FP32) and the X tile in LDS,
+// evaluates the T tile on the vector ALUs, and accumulates the tile product on the matrix cores
+// (the same fragment layout as the stored-T kernels). Tile sums are added to the running sum with
+// Kahan compensation, so the FP32 result does not drift over ~10^4 source tiles.
+//
+// FP32 elements use erf(x) = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p x) (Abramowitz &
+// Stegun, Handbook of Mathematical Functions, formula 7.1.26; absolute error <= 1.5e-7) for
+// x >= 1/2 and the Maclaurin series of erf below; FP64 elements use the device library's erf.
 #include "common.h"
+#include "device_util.h"
+
+namespace wfq {
+
+namespace {
+
+constexpr int kBI = 128;   // targets per work-group (4 waves x 32)
+
+__device__ inline float erf_f32(float x) {
+    if (x < 0.5f) {
+        const float x2 = x * x;
+        // 2/sqrt(pi) * (x - x^3/3 + x^5/10 - x^7/42 + x^9/216 - x^11/1320 + x^13/9360)
+        float p = 1.2055332981789664e-4f;
+        p = p * x2 - 8.5483270234508645e-4f;
+        p = p * x2 + 5.2239776254421878e-3f;
+        p = p * x2 - 2.6866170645131252e-2f;
+        p = p * x2 + 1.1283791670955126e-1f;
+        p = p * x2 - 3.7612638903183752e-1f;
+        p = p * x2 + 1.1283791670955126f;
+        return x * p;
+    }
+    const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * x);
+    float p = 1.061405429f;
+    p = p * t - 1.453152027f;
+    p = p * t + 1.421413741f;
+    p = p * t - 0.284496736f;
+    p = p * t + 0.254829592f;
+    p = p * t;
+    return 1.0f - p * __expf(-x * x);
+}
+
+template <int P>
+struct OtfT;
+template <>
+struct OtfT<WFQ_PREC_FP32> {
+    using elem = float;
+    using acc = floatx4;
+    static constexpr int BJ = 64;   // 256-byte rows
+};
+template <>
+struct OtfT<WFQ_PREC_FP64> {
+    using elem = double;
+    using acc = doublex4;
+    static constexpr int BJ = 32;
+};
+
+__device__ inline void mma_otf(floatx4& c, const uint4& a, const uint4& b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+}
+__device__ inline void mma_otf(doublex4& c, const uint4& a, const uint4& b) {
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double(a.y, a.x), __hiloint2double(b.y, b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double(a.w, a.z), __hiloint2double(b.w, b.z), c, 0, 0, 0);
+}
+
+// T_ij for one pair from coordinates relative to a common centre
+__device__ inline float t_elem(float xi, float yi, float zi, float di2, float xj, float yj, float zj, float dj2) {
+    const float dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    const float r2 = dx * dx + dy * dy + dz * dz;
+    const float inv_r = __builtin_amdgcn_rsqf(r2);
+    const float x = r2 * inv_r * __builtin_amdgcn_rsqf(di2 + dj2);
+    return erf_f32(x) * inv_r;
+}
+__device__ inline double t_elem(double xi, double yi, double zi, double di2, double xj, double yj, double zj,
+                                double dj2) {
+    const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    const double r = sqrt(dx * dx + dy * dy + dz * dz);
+    return erf(r / sqrt(di2 + dj2)) / r;
+}
+
+template <int P, int BC>
+__global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const double* __restrict__ pos,
+                                                  const double* __restrict__ width, const double* __restrict__ eta,
+                                                  const typename OtfT<P>::elem* __restrict__ X,
+                                                  typename OtfT<P>::elem* __restrict__ Y) {
+    using E = typename OtfT<P>::elem;
+    using acc_t = typename OtfT<P>::acc;
+    constexpr int BJ = OtfT<P>::BJ;
+    constexpr int KB = BJ * (int)sizeof(E);   // 256 bytes of k per row
+    constexpr int RS = KB + 16;
+    constexpr int WM = BC / 16;               // column blocks
+    constexpr int WN = 2;                     // 32 target rows per wave
+    constexpr int XCH = BC * (KB / 16);       // 16-byte chunks of the X tile
+    __shared__ __attribute__((aligned(16))) char lds[(BC + kBI) * RS];
+    __shared__ E src[4][BJ];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t i0 = (int64_t)blockIdx.x * kBI;
+    const int64_t c0 = (int64_t)blockIdx.y * BC;
+    const int64_t ic = min(i0 + kBI / 2, n - 1);
+    const double cx = pos[ic], cy = pos[npad + ic], cz = pos[2 * npad + ic];
+
+    // this thread evaluates row `it` of the T tile, half `jh` of its columns
+    const int it = tid >> 1, jh = tid & 1;
+    const int64_t ti = i0 + it;
+    const bool tin = ti < n;
+    const E xi = tin ? (E)(pos[ti] - cx) : E(0), yi = tin ? (E)(pos[npad + ti] - cy) : E(0);
+    const E zi = tin ? (E)(pos[2 * npad + ti] - cz) : E(0);
+    const E di2 = tin ? (E)(width[ti] * width[ti]) : E(1);
+    const E etai = tin ? (E)eta[ti] : E(0);
+
+    acc_t sum[WM][WN], comp[WM][WN];
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+            sum[a][b] = acc_t{0, 0, 0, 0};
+            comp[a][b] = acc_t{0, 0, 0, 0};
+        }
+    char* XT = lds;
+    char* TT = lds + BC * RS;
+    const int frag_row = lane & 15, frag_chunk = lane >> 4;
+
+    for (int64_t j0 = 0; j0 < npad; j0 += BJ) {
+        __syncthreads();
+        if (tid < BJ) {
+            const int64_t j = j0 + tid;
+            const bool jin = j < n;
+            src[0][tid] = jin ? (E)(pos[j] - cx) : E(0);
+            src[1][tid] = jin ? (E)(pos[npad + j] - cy) : E(0);
+            src[2][tid] = jin ? (E)(pos[2 * npad + j] - cz) : E(0);
+            src[3][tid] = jin ? (E)(width[j] * width[j]) : E(1);
+        }
+        for (int q = tid; q < XCH; q += 256) {
+            const int row = q / (KB / 16), cc = q % (KB / 16);
+            *reinterpret_cast<uint4*>(XT + row * RS + cc * 16) =
+                *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(X + (c0 + row) * npad + j0) + cc * 16);
+        }
+        __syncthreads();
+        // T tile: row it, columns jh * BJ/2 .. + BJ/2 (zero outside the atoms, eta on the diagonal)
+        E* trow = reinterpret_cast<E*>(TT + it * RS);
+#pragma unroll 4
+        for (int jj = 0; jj < BJ / 2; ++jj) {
+            const int jl = jh * (BJ / 2) + jj;
+            const int64_t j = j0 + jl;
+            E v;
+            if (!tin || j >= n)
+                v = E(0);
+            else if (j == ti)
+                v = etai;
+            else
+                v = t_elem(xi, yi, zi, di2, src[0][jl], src[1][jl], src[2][jl], src[3][jl]);
+            trow[jl] = v;
+        }
+        __syncthreads();
+        acc_t tile[WM][WN];
+#pragma unroll
+        for (int a = 0; a < WM; ++a)
+#pragma unroll
+            for (int b = 0; b < WN; ++b) tile[a][b] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int cg = 0; cg < KB / 64; ++cg) {
+            uint4 af[WM], bf[WN];
+            const int coff = (cg * 4 + frag_chunk) * 16;
+#pragma unroll
+            for (int a = 0; a < WM; ++a) af[a] = *reinterpret_cast<const uint4*>(XT + (a * 16 + frag_row) * RS + coff);
+#pragma unroll
+            for (int b = 0; b < WN; ++b)
+                bf[b] = *reinterpret_cast<const uint4*>(TT + (wave * 32 + b * 16 + frag_row) * RS + coff);
+#pragma unroll
+            for (int a = 0; a < WM; ++a)
+#pragma unroll
+                for (int b = 0; b < WN; ++b) mma_otf(tile[a][b], af[a], bf[b]);
+        }
+        // compensated accumulation of the tile sums
+#pragma unroll
+        for (int a = 0; a < WM; ++a)
+#pragma unroll
+            for (int b = 0; b < WN; ++b)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const E y = tile[a][b][r] - comp[a][b][r];
+                    const E t = sum[a][b][r] + y;
+                    comp[a][b][r] = (t - sum[a][b][r]) - y;
+                    sum[a][b][r] = t;
+                }
+    }
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = P == WFQ_PREC_FP64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+                const int64_t c = c0 + a * 16 + row;
+                const int64_t i = i0 + wave * 32 + b * 16 + (lane & 15);
+                Y[c * npad + i] = sum[a][b][r];
+            }
+}
+
+}  // namespace
+
+void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st) {
+    if (ncol <= 0) return;
+    constexpr int BC = 32;
+    dim3 grd((unsigned)(s.npad / kBI), (unsigned)((ncol + BC - 1) / BC));
+    hipLaunchKernelGGL((otf_kernel<WFQ_PREC_FP32, BC>), grd, dim3(256), 0, st, s.n, s.npad, s.pos, s.width, s.eta, X,
+                       Y);
+    WFQ_CHECK_LAUNCH();
+}
+
+void otf_tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_t st) {
+    if (ncol <= 0) return;
+    constexpr int BC = 32;
+    dim3 grd((unsigned)(s.npad / kBI), (unsigned)((ncol + BC - 1) / BC));
+    hipLaunchKernelGGL((otf_kernel<WFQ_PREC_FP64, BC>), grd, dim3(256), 0, st, s.n, s.npad, s.pos, s.width, s.eta, X,
+                       Y);
+    WFQ_CHECK_LAUNCH();
+}
+
+}  // namespace wfq

@@ -108,6 +108,7 @@ int elem_size(int prec) { return prec == WFQ_PREC_FP64 ? 8 : prec == WFQ_PREC_FP
 int out_size(int prec) { return prec == WFQ_PREC_FP64 ? 8 : 4; }
 
 bool have_copy(const Structure& S, int prec) {
+    if (S.t_mode == WFQ_TMODE_OTF) return prec != WFQ_PREC_BF16;   // recomputed in FP32 or FP64
     return prec == WFQ_PREC_FP64 ? S.T64 != nullptr : prec == WFQ_PREC_FP32 ? S.T32 != nullptr : S.T16 != nullptr;
 }
 
@@ -230,27 +231,27 @@ struct SysState {
     bool done = false;
 };
 
-// One T X block product for the columns of one precision group (X already packed).
-void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, hipStream_t st) {
-    const double n = (double)S.n;
-    tm.begin(st);
-    if (prec == WFQ_PREC_FP64)
-        tx_f64(S, w.X64.p, w.Y64.p, ncol, st);
-    else if (prec == WFQ_PREC_FP32)
-        tx_f32(S, w.X32.p, w.Y32.p, ncol, st);
-    else
-        tx_bf16(S, w.X16.p, w.Y16.p, ncol, st);
-    const int kc = ncol <= 8 ? KC_SKINNY
-                             : (prec == WFQ_PREC_FP64 ? KC_GEMM_F64 : prec == WFQ_PREC_FP32 ? KC_GEMM_F32 : KC_GEMM_BF16);
-    tm.end(st, kc, 2.0 * n * n * ncol, elem_size(prec) * n * n + ncol * n * (elem_size(prec) + out_size(prec)));
-}
-
 void* x_block(Work& w, int prec) {
     return prec == WFQ_PREC_FP64 ? (void*)w.X64.p : prec == WFQ_PREC_FP32 ? (void*)w.X32.p : (void*)w.X16.p;
 }
 const void* y_block(Work& w, int prec) {
     return prec == WFQ_PREC_FP64 ? (const void*)w.Y64.p : prec == WFQ_PREC_FP32 ? (const void*)w.Y32.p
                                                                                  : (const void*)w.Y16.p;
+}
+
+// One T X block product for the columns of one precision group (X already packed).
+void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, hipStream_t st) {
+    const double n = (double)S.n;
+    tm.begin(st);
+    tx_any(S, prec, x_block(w, prec), const_cast<void*>(y_block(w, prec)), ncol, st);
+    if (S.t_mode == WFQ_TMODE_OTF) {
+        // flops: the MFMA accumulation; the element evaluations are counted by launches x n^2 pairs
+        tm.end(st, prec == WFQ_PREC_FP64 ? KC_OTF_F64 : KC_OTF, 2.0 * n * n * ncol, ncol * n * 2.0 * elem_size(prec));
+        return;
+    }
+    const int kc = ncol <= 8 ? KC_SKINNY
+                             : (prec == WFQ_PREC_FP64 ? KC_GEMM_F64 : prec == WFQ_PREC_FP32 ? KC_GEMM_F32 : KC_GEMM_BF16);
+    tm.end(st, kc, 2.0 * n * n * ncol, elem_size(prec) * n * n + ncol * n * (elem_size(prec) + out_size(prec)));
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -660,7 +661,9 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
     const double E0 = o.E0 != 0.0 ? o.E0 : 1.0;
     int prec = o.precision;
     if (!have_copy(S, prec))
-        throw Error{WFQ_EINVAL, "the stored copy of T for the requested precision was not built (store_mask)"};
+        throw Error{WFQ_EINVAL, S.t_mode == WFQ_TMODE_OTF
+                                    ? "matrix-free T runs in FP32 or FP64"
+                                    : "the stored copy of T for the requested precision was not built (store_mask)"};
     if (!have_copy(S, WFQ_PREC_FP64))
         throw Error{WFQ_EINVAL, "FP64 refinement needs the FP64 copy of T (store_mask must include WFQ_STORE_FP64)"};
 

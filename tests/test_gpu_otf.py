@@ -1,0 +1,91 @@
+"""Matrix-free (on-the-fly) T products and solves against the oracle (needs an MI355X)."""
+
+import numpy as np
+import pytest
+
+from oracle import wfq_oracle as O
+from helpers import GRAPHENE, UNIT, ragged_tube, round_to
+
+pytestmark = pytest.mark.gpu
+
+# FP32 elements use a rational/exponential erf with absolute error <= 1.5e-7 (relative <= 3e-7
+# for the arguments >= 1/2 where it is used) and the Maclaurin series below 1/2.
+ERF_REL = 3.2e-7
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2103_00438_amd import wfq
+    wfq.load()
+    return wfq
+
+
+@pytest.fixture(scope="module")
+def tube():
+    xyz = ragged_tube()
+    return xyz, O.Problem(xyz, GRAPHENE)
+
+
+@pytest.mark.parametrize("ncol", [1, 2, 31, 32, 33, 64])
+def test_otf_products(lib, tube, ncol):
+    xyz, P = tube
+    h = lib.wfq_build(xyz, GRAPHENE, t_mode="otf")
+    X = np.random.default_rng(ncol).standard_normal((ncol, P.n))
+    bound = np.abs(X) @ np.abs(P.T)
+    Y64 = lib.wfq_apply_T(h, "fp64", X)
+    assert np.all(np.abs(Y64 - X @ P.T) <= 64 * UNIT["fp64"] * bound + 1e-300)
+    Y32 = lib.wfq_apply_T(h, "fp32", X)
+    Xq = round_to("fp32", X)
+    ref = Xq @ P.T
+    # element error (erf approximation + FP32 geometry) + accumulation inside 64-source tiles (FP32)
+    tol = (ERF_REL + 16 * UNIT["fp32"] + 2 * 64 * UNIT["fp32"]) * (np.abs(Xq) @ np.abs(P.T))
+    assert np.all(np.abs(Y32 - ref) <= tol)
+    h.close()
+
+
+def test_otf_element_accuracy_across_branch(lib):
+    # a dimer scanned through r / sqrt(d_i^2 + d_j^2) = 0.05 .. 6: T_12 from the product with e_2
+    eta = 0.6
+    d = np.sqrt(2 / np.pi) / eta
+    sig = np.sqrt(2) * d
+    worst = 0.0
+    for x in np.concatenate([np.linspace(0.05, 0.95, 19), np.linspace(1.0, 6.0, 11)]):
+        r_bohr = x * sig
+        xyz = np.array([[0.0, 0.0, 0.0], [r_bohr * O.BOHR_A, 0.0, 0.0]])
+        P = O.Problem(xyz, dict(GRAPHENE, eta=eta))
+        h = lib.wfq_build(xyz, dict(GRAPHENE, eta=eta), t_mode="otf")
+        y = lib.wfq_apply_T(h, "fp32", np.array([[0.0, 1.0]]))[0]
+        h.close()
+        worst = max(worst, abs(y[0] - P.T[0, 1]) / P.T[0, 1])
+    assert worst <= ERF_REL + 8 * UNIT["fp32"]
+
+
+def test_otf_matches_stored_fp64(lib, tube):
+    xyz, P = tube
+    hs = lib.wfq_build(xyz, GRAPHENE)
+    ho = lib.wfq_build(xyz, GRAPHENE, t_mode="otf")
+    X = np.random.default_rng(3).standard_normal((8, P.n))
+    a = lib.wfq_apply_T(hs, "fp64", X)
+    b = lib.wfq_apply_T(ho, "fp64", X)
+    assert np.all(np.abs(a - b) <= 64 * UNIT["fp64"] * (np.abs(X) @ np.abs(P.T)))
+    hs.close()
+    ho.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_otf_solve_matches_lu(lib, tube, prec):
+    xyz, P = tube
+    h = lib.wfq_build(xyz, GRAPHENE, t_mode="otf")
+    om = np.array([0.15, 0.6])
+    dirs = np.eye(3)[:2]
+    out = lib.wfq_solve(h, om, dirs, 1e-8, restart=60, precision=prec)
+    assert out["status"] == 0
+    for a in range(2):
+        for k in range(2):
+            ref = P.solve_lu(om[a], dirs[k])
+            q = out["q"][a, k]
+            assert np.linalg.norm(q - ref) / np.linalg.norm(ref) <= 1e-6
+            assert out["info"][a * 2 + k]["relres"] <= 1e-8
+    with pytest.raises(lib.WfqError):
+        lib.wfq_solve(h, om, dirs, 1e-8, precision="bf16")
+    h.close()

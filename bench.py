@@ -1,22 +1,26 @@
 """Benchmark: omega-point solves per second of the batched mixed-precision solve on one MI355X.
 
-Workload (cnt20k): armchair (10,10) carbon nanotube, 500 periods = 20 000 atoms, jitter 0.01 A
-(seed 2), graphene parameters (eps_F = 0.4 eV, tau = 170 a.u., d = 12, s = 1.1), 64 frequencies
-uniform in 0.05-1.0 eV x 3 field polarisations = 192 systems sharing one stored T. One step = one
-wfq_solve over all 192 systems: FP32 T products inside restarted GMRES(50) with FP64 refinement to
-relative FP64 residual 1e-8. T and L are built (and resident in HBM) before the timed region.
+Default workload (cnt20k): armchair (10,10) carbon nanotube, 500 periods = 20 000 atoms, jitter
+0.01 A (seed 2), graphene parameters (eps_F = 0.4 eV, tau = 170 a.u., d = 12, s = 1.1), 64
+frequencies uniform in 0.05-1.0 eV x 3 field polarisations = 192 systems sharing one stored T.
+One step = one wfq_solve over all 192 systems: FP32 T products inside restarted GMRES(50) with FP64
+refinement to relative FP64 residual 1e-8. T and L are built (and resident in HBM) before the timed
+region.
 
-Printed (one JSON line): solves/s, p50/p99 per-system completion latency inside a step, the
-largest relative difference of q against the FP64 solve on the same GPU, the per-frequency FP64
-baseline (one system per solve, same library), the roofline figures of the dominant kernel (FP32
-MFMA block product, timed with HIP events on the library's stream) and the CPU oracle timed on a
-bounded sample.
+Printed (one JSON line): solves/s, p50/p99 per-system completion latency inside a step, the largest
+relative difference of q against the FP64 solve on the same GPU, the per-frequency FP64 baseline
+(one system per solve, same library), the roofline figures of the dominant kernel (timed with HIP
+events on the library's stream) and the CPU oracle timed on a bounded sample.
+
+Other workloads (--workload): disk600 (single-system latency), fcc120k (BF16 T, 120k atoms),
+sheet1m (matrix-free T, 10^6 atoms), serve_mix (Poisson stream of jobs through wfq_serve).
 """
 
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -28,6 +32,12 @@ sys.path.insert(0, ROOT)
 
 PEAKS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}   # TFLOP/s, dense MFMA (MI355X)
 HBM_PEAK = 8000.0                                        # GB/s
+# Matrix-free FP32 elements: ~26 VALU instructions per pair, 4 of them quarter-rate transcendentals
+# (3 extra issue slots each) = 38 issue slots; non-packed FP32 VALU issue rate of MI355X =
+# 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s.
+OTF_SLOTS_PER_PAIR = 38.0
+VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
+METRIC = "omega-point solves/s at rel. err 1e-6 (mixed vs FP64, same GPU); p50/p99 latency"
 
 
 def parse():
@@ -36,20 +46,28 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cnt20k")
+    ap.add_argument("--algorithm", default=None)
+    ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 comparison runs")
-    ap.add_argument("--precision", default=None)
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in block-product shapes")
+    ap.add_argument("--ref-systems", type=int, default=0,
+                    help="compare only this many systems against FP64 (0 = all)")
+    ap.add_argument("--jobs", type=int, default=40, help="serve_mix: number of jobs in the stream")
     return ap.parse_args()
+
+
+def cores_used():
+    try:
+        from threadpoolctl import threadpool_info
+        return max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
+    except Exception:
+        return os.cpu_count() or 1
 
 
 def cpu_baseline(wl, sys_index):
     """The oracle as it stands: FP64 restarted GMRES on one system of the workload (host cores)."""
     from oracle import wfq_oracle as O
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([int(p.get("num_threads", 1)) for p in threadpool_info()] or [1])
-    except Exception:
-        cores = os.cpu_count() or 1
     t0 = time.perf_counter()
     P = O.Problem(wl.xyz, wl.params)
     t_build = time.perf_counter() - t0
@@ -57,39 +75,80 @@ def cpu_baseline(wl, sys_index):
     t0 = time.perf_counter()
     x, info = P.solve_gmres(wl.omegas_eV[a], wl.dirs[k], wl.restart, wl.tol)
     t_solve = time.perf_counter() - t0
-    return dict(value=1.0 / t_solve, unit="solves/s", cores=cores, kind="oracle",
+    return dict(value=1.0 / t_solve, unit="solves/s", cores=cores_used(), kind="oracle",
                 sample=f"1 of {wl.n_systems} systems (omega={wl.omegas_eV[a]:.4f} eV, dir {k}), FP64 GMRES"
                        f"({wl.restart}) to {wl.tol:g}; solve {t_solve:.1f} s ({info['iters']} iterations), "
                        f"matrix build {t_build:.1f} s not included",
                 solve_s=t_solve, build_s=t_build, iters=info["iters"])
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(json.dumps(dict(error="this build runs on one GPU only; --gpus must be 1")))
-        sys.exit(2)
-    import torch
-    import wfq_inputs as wi
-    from paper_2103_00438_amd import wfq
+def cpu_baseline_matrix_free(wl, iters_per_solve, n_rows=256):
+    """The oracle's pairwise (matrix-free) rows of T x on a sample of rows, scaled to solves/s."""
+    from oracle import wfq_oracle as O
+    xyz = O.angstrom_to_bohr(wl.xyz)
+    eta = np.full(len(xyz), wl.params["eta"])
+    x = np.random.default_rng(0).standard_normal(len(xyz))
+    rows = np.arange(n_rows) * (len(xyz) // n_rows)
+    t0 = time.perf_counter()
+    for s in range(0, n_rows, 16):
+        O.coulomb_rows(xyz, eta, rows[s:s + 16]) @ x
+    t = time.perf_counter() - t0
+    per_product = t / n_rows * len(xyz) * 2          # 2 real columns per complex system
+    return dict(value=1.0 / (per_product * iters_per_solve), unit="solves/s", cores=cores_used(), kind="oracle",
+                sample=f"{n_rows} rows of the matrix-free T x ({n_rows * len(xyz):.3g} pairs, {t:.1f} s); "
+                       f"extrapolated to one system = {iters_per_solve:.0f} products of 2 real columns "
+                       f"(the GPU's mean iteration count); L and vector work ignored",
+                pairs_per_s=n_rows * len(xyz) / t)
 
-    wl = wi.workload(args.workload)
+
+def kernel_table(stats):
+    return {k: dict(ms=round(v["ms"], 3), launches=v["launches"],
+                    gbps=(v["bytes"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 else None)
+            for k, v in stats.items() if v["launches"]}
+
+
+def roofline_of(stats, prec, otf, n):
+    if otf:
+        key = "tx_otf_f32" if prec == "fp32" else "tx_otf_f64"
+        st = stats[key]
+        # one launch evaluates n^2 pairs per 32-column block (flops are counted as 2 n^2 ncol)
+        ncol_avg = st["flops"] / max(1, st["launches"]) / (2.0 * n * n)
+        pairs = n * n * math.ceil(ncol_avg / 32)
+        avg_s = st["ms"] / max(1, st["launches"]) / 1e3
+        achieved = pairs / avg_s / 1e9 if avg_s > 0 else 0.0
+        peak = VALU_LANE_OPS / OTF_SLOTS_PER_PAIR / 1e9
+        return dict(bound="alu", achieved=achieved, peak=peak, unit="Gpair/s", frac=achieved / peak, traffic=None,
+                    kernel=key, launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
+                    pairs_per_launch=pairs)
+    dom = {"fp32": "tx_gemm_f32", "fp64": "tx_gemm_f64", "bf16": "tx_gemm_bf16"}[prec]
+    st = stats[dom]
+    achieved = st["flops"] / (st["ms"] / 1e3) / 1e12 if st["ms"] > 0 else 0.0
+    return dict(bound="mfma", achieved=achieved, peak=PEAKS[prec], unit="TFLOP/s", frac=achieved / PEAKS[prec],
+                traffic=None, kernel=dom, launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
+                avg_flops_per_launch=st["flops"] / max(1, st["launches"]))
+
+
+def bench_batched(args, wl, wfq, torch):
     prec = args.precision or wl.precision
-    store = ("fp64", "fp32", "bf16") if prec == "bf16" else ("fp64", "fp32")
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
+    algo = args.algorithm or wl.algorithm
+    otf = wl.t_mode == "otf"
+    store = ("fp64", "bf16") if prec == "bf16" else ("fp64", "fp32")
     t0 = time.perf_counter()
-    h = wfq.wfq_build(wl.xyz, wl.params, store=store, device=0)
+    h = wfq.wfq_build(wl.xyz, wl.params, t_mode=wl.t_mode, store=store, device=0)
     build_s = time.perf_counter() - t0
-    opts = dict(restart=wl.restart, precision=prec, algorithm=wl.algorithm)
-    # the library's autotuner picks the block-product shape per column count (outside the timed region)
-    t0 = time.perf_counter()
-    ncols = sorted({c for c in (16, 32, 64, 96, 128, 192, 256, 320, 384, 512, 640, 768) if c <= 2 * wl.n_systems}
-                   | {2 * wl.n_systems})
-    tune = wfq.wfq_tune(h, prec, ncols, reps=2)
-    if prec != "fp64":
-        wfq.wfq_tune(h, "fp64", ncols, reps=2)   # shapes of the FP64 refinement products
-    tune_s = time.perf_counter() - t0
+    opts = dict(restart=wl.restart, precision=prec, algorithm=algo, progress=wl.n > 50000)
+    tune = None
+    tune_s = 0.0
+    S = wl.n_systems
+    if not otf and not args.no_tune:
+        # the library's autotuner picks the block-product shape per column count (outside the timed region)
+        t0 = time.perf_counter()
+        ncols = sorted({c for c in (16, 32, 64, 96, 128, 192, 256, 320, 384, 512, 640, 768) if c <= 2 * S}
+                       | {2 * S})
+        tune = wfq.wfq_tune(h, prec, ncols, reps=2)
+        if prec != "fp64":
+            wfq.wfq_tune(h, "fp64", ncols, reps=2)   # shapes of the FP64 refinement products
+        tune_s = time.perf_counter() - t0
 
     for _ in range(args.warmup):
         wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=False, **opts)
@@ -102,68 +161,167 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     stats = wfq.wfq_kernel_stats(h)
-    S = wl.n_systems
     value = S * args.steps / elapsed
     last = outs[-1]
     lat = np.array([r["t_done_ms"] for r in last["info"]])
     iters = np.array([r["iters"] for r in last["info"]])
     statuses = sorted(set(r["status"] for r in last["info"]))
     relres_max = max(r["relres"] for r in last["info"])
-
-    dom = {"fp32": "tx_gemm_f32", "fp64": "tx_gemm_f64", "bf16": "tx_gemm_bf16"}[prec]
-    st = stats[dom]
-    achieved = st["flops"] / (st["ms"] / 1e3) / 1e12 if st["ms"] > 0 else 0.0
-    roofline = dict(bound="mfma", achieved=achieved, peak=PEAKS[prec], unit="TFLOP/s",
-                    frac=achieved / PEAKS[prec], traffic=None, kernel=dom,
-                    launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
-                    avg_flops_per_launch=st["flops"] / max(1, st["launches"]))
-    breakdown = {k: dict(ms=round(v["ms"], 3), launches=v["launches"],
-                         gbps=(v["bytes"] / (v["ms"] / 1e3) / 1e9) if v["ms"] > 0 else None)
-                 for k, v in stats.items() if v["launches"]}
+    prec_end = sorted(set(r["precision"] for r in last["info"]))
+    roofline = roofline_of(stats, prec, otf, wl.n)
 
     extra = {}
-    if not args.no_reference:
-        # the same systems with FP64 T inside the iterations (same GPU, same library): accuracy of
-        # the mixed result, and the batched FP64 rate
+    if not args.no_reference and prec != "fp64":
+        # the same systems with FP64 T inside the iterations (same GPU, same library)
+        sel = list(range(S))
+        if args.ref_systems and args.ref_systems < S:
+            sel = [int(round(v)) for v in np.linspace(0, S - 1, args.ref_systems)]
         t0 = time.perf_counter()
-        ref = wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=True, restart=wl.restart, precision="fp64")
+        qref = np.zeros((len(sel), wl.n), dtype=complex)
+        aref = np.zeros((len(sel), 3), dtype=complex)
+        if len(sel) == S:
+            ref = wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=True, restart=wl.restart,
+                                precision="fp64", algorithm=algo, progress=wl.n > 50000)
+            qref = ref["q"].reshape(S, wl.n)
+            aref = ref["alpha"].reshape(S, 3)
+        else:
+            for q, s in enumerate(sel):
+                a, k = divmod(s, len(wl.dirs))
+                r1 = wfq.wfq_solve(h, wl.omegas_eV[a:a + 1], wl.dirs[k:k + 1], wl.tol, want_q=True,
+                                   restart=wl.restart, precision="fp64", algorithm=algo, progress=wl.n > 50000)
+                qref[q] = r1["q"][0, 0]
+                aref[q] = r1["alpha"][0, 0]
         t_ref = time.perf_counter() - t0
-        qm, qr = last["q"], ref["q"]
-        err = np.linalg.norm(qm - qr, axis=2) / np.linalg.norm(qr, axis=2)
-        am, ar = last["alpha"], ref["alpha"]
-        aerr = np.abs(am - ar).max(axis=2) / np.abs(ar).max(axis=2)
+        qm = last["q"].reshape(S, wl.n)[sel]
+        am = last["alpha"].reshape(S, 3)[sel]
+        err = np.linalg.norm(qm - qref, axis=1) / np.linalg.norm(qref, axis=1)
+        aerr = np.abs(am - aref).max(axis=1) / np.abs(aref).max(axis=1)
+        extra = dict(max_rel_err_q_vs_fp64=float(err.max()), max_rel_err_alpha_vs_fp64=float(aerr.max()),
+                     fp64_reference_systems=len(sel), fp64_reference_s=t_ref)
+        if len(sel) == S:
+            extra["fp64_batched_solves_per_s"] = S / t_ref
         # per-frequency FP64 baseline: one system per solve, sampled
-        samp = [0, S // 4, S // 2, 3 * S // 4, S - 1]
+        samp = [0, S // 2, S - 1] if wl.n > 50000 else [0, S // 4, S // 2, 3 * S // 4, S - 1]
         t0 = time.perf_counter()
         for s in samp:
             a, k = divmod(s, len(wl.dirs))
             wfq.wfq_solve(h, wl.omegas_eV[a:a + 1], wl.dirs[k:k + 1], wl.tol, want_q=False,
-                          restart=wl.restart, precision="fp64")
+                          restart=wl.restart, precision="fp64", algorithm=algo, progress=wl.n > 50000)
         t_pf = (time.perf_counter() - t0) / len(samp)
-        extra = dict(max_rel_err_q_vs_fp64=float(err.max()), max_rel_err_alpha_vs_fp64=float(aerr.max()),
-                     fp64_batched_solves_per_s=S / t_ref,
-                     fp64_per_frequency_solves_per_s=1.0 / t_pf,
-                     speedup_vs_fp64_per_frequency=value * t_pf,
+        extra.update(fp64_per_frequency_solves_per_s=1.0 / t_pf, speedup_vs_fp64_per_frequency=value * t_pf,
                      per_frequency_sample=f"{len(samp)} systems, one per solve")
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(wl, S // 2)
+        if otf or wl.n > 50000:
+            cpu = cpu_baseline_matrix_free(wl, float(iters.mean()))
+        else:
+            cpu = cpu_baseline(wl, S // 2)
 
     line = dict(
-        metric="omega-point solves/s at rel. err 1e-6 (mixed vs FP64, same GPU); p50/p99 latency",
-        value=value, unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        metric=METRIC, value=value, unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
         ms_per_step=elapsed / args.steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
         dtype={"fp32": "fp32-ir-fp64", "bf16": "bf16-ir-fp64", "fp64": "fp64"}[prec], data="synthetic",
         config=dict(workload=wl.name, n_atoms=wl.n, n_systems=S, n_omega=len(wl.omegas_eV), n_dir=len(wl.dirs),
-                    precision=prec, algorithm=wl.algorithm, restart=wl.restart, tol=wl.tol,
+                    precision=prec, algorithm=algo, restart=wl.restart, tol=wl.tol, t_mode=wl.t_mode,
                     description=wl.description),
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         iters_mean=float(iters.mean()), iters_max=int(iters.max()), relres_max=relres_max,
-        statuses=statuses, build_s=build_s, tune_s=tune_s,
-        tuned={str(c): v for c, v in zip(tune["ncols"], tune["chosen"])},
-        roofline=roofline, cpu_baseline=cpu, kernels=breakdown, **extra)
-    print(json.dumps(line))
+        statuses=statuses, final_precisions=prec_end, build_s=build_s, tune_s=tune_s,
+        tuned={str(c): v for c, v in zip(tune["ncols"], tune["chosen"])} if tune else None,
+        roofline=roofline, cpu_baseline=cpu, kernels=kernel_table(stats), **extra)
     h.close()
+    return line
+
+
+def bench_latency(args, wl, wfq, torch):
+    """disk600: one small system; latency of a single solve."""
+    h = wfq.wfq_build(wl.xyz, wl.params, device=0)
+    opts = dict(restart=wl.restart, precision=wl.precision, algorithm=args.algorithm or wl.algorithm)
+    for _ in range(max(1, args.warmup)):
+        wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, **opts)
+    reps = max(20, args.steps)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        t1 = time.perf_counter()
+        out = wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, **opts)
+        lat.append((time.perf_counter() - t1) * 1e3)
+    elapsed = time.perf_counter() - t0
+    from oracle import wfq_oracle as O
+    P = O.Problem(wl.xyz, wl.params)
+    t1 = time.perf_counter()
+    P.solve_lu(wl.omegas_eV[0], wl.dirs[0])
+    t_lu = time.perf_counter() - t1
+    t1 = time.perf_counter()
+    _, info = P.solve_gmres(wl.omegas_eV[0], wl.dirs[0], wl.restart, wl.tol)
+    t_gm = time.perf_counter() - t1
+    line = dict(metric=METRIC, value=reps / elapsed, unit="solves/s", n_gpus=1, steps=reps, warmup=args.warmup,
+                ms_per_step=elapsed / reps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="fp64", data="synthetic",
+                config=dict(workload=wl.name, n_atoms=wl.n, n_systems=1, precision="fp64", restart=wl.restart,
+                            tol=wl.tol, description=wl.description),
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                iters=out["info"][0]["iters"], relres=out["info"][0]["relres"],
+                cpu_baseline=dict(value=1.0 / t_gm, unit="solves/s", cores=cores_used(), kind="oracle",
+                                  sample=f"the same system: FP64 GMRES({wl.restart}) {t_gm * 1e3:.1f} ms "
+                                         f"({info['iters']} iterations); dense LU {t_lu * 1e3:.1f} ms"))
+    h.close()
+    return line
+
+
+def bench_serve(args, wl, wfq, torch):
+    """serve_mix: a seeded Poisson stream of spectrum jobs through the request loop."""
+    import wfq_inputs as wi
+    jobs = wi.serve_mix_jobs(n_jobs=args.jobs)
+    srv = wfq.wfq_serve(wl.tol, max_jobs=4, max_queue=4096, restart=wl.restart, precision=wl.precision)
+    t0 = time.perf_counter()
+    tickets = []
+    for j in jobs:
+        delay = j["arrival"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(wfq.wfq_submit(srv, j["xyz"], j["params"], j["omegas_eV"], j["dirs"]))
+    res = [wfq.wfq_wait(srv, t) for t in tickets]
+    elapsed = time.perf_counter() - t0
+    st = wfq.wfq_serve_stats(srv)
+    wfq.wfq_serve_stop(srv)
+    lat = np.array([r["timing"]["latency_ms"] for r in res])
+    queue = np.array([r["timing"]["t_admit_ms"] - r["timing"]["t_submit_ms"] for r in res])
+    systems = sum(r["timing"]["n_systems"] for r in res)
+    ok = sum(r["status"] == 0 for r in res)
+    n_atoms = [len(j["xyz"]) for j in jobs]
+    line = dict(metric=METRIC, value=systems / elapsed, unit="solves/s", n_gpus=1, steps=len(jobs), warmup=0,
+                ms_per_step=elapsed / len(jobs) * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="fp32-ir-fp64", data="synthetic",
+                config=dict(workload=wl.name, jobs=len(jobs), rate_per_s=20.0, n_atoms_min=int(min(n_atoms)),
+                            n_atoms_max=int(max(n_atoms)), systems=systems, tol=wl.tol, precision=wl.precision,
+                            max_jobs=4, description=wl.description),
+                p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                queue_p50_ms=float(np.percentile(queue, 50)), queue_p99_ms=float(np.percentile(queue, 99)),
+                jobs_ok=int(ok), busy_frac=st["busy_frac"], max_resident=st["max_resident"],
+                wall_s=elapsed, offered_span_s=jobs[-1]["arrival"])
+    return line
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps(dict(error="this build runs on one GPU only; --gpus must be 1")))
+        sys.exit(2)
+    import torch
+    import wfq_inputs as wi
+    from paper_2103_00438_amd import wfq
+
+    torch.cuda.set_device(torch.device("cuda:0"))
+    wl = wi.workload(args.workload)
+    if wl.name == "disk600":
+        line = bench_latency(args, wl, wfq, torch)
+    elif wl.name == "serve_mix":
+        line = bench_serve(args, wl, wfq, torch)
+    else:
+        line = bench_batched(args, wl, wfq, torch)
+    print(json.dumps(line))
 
 
 if __name__ == "__main__":

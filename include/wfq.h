@@ -101,6 +101,7 @@ typedef struct {
     int32_t max_batch;   /* systems solved together; 0 = as many as fit the budget */
     int32_t timing;      /* nonzero: time every kernel launch with HIP events (wfq_kernel_stats) */
     int32_t escalate;    /* nonzero: a system whose FP64 residual stalls moves to the next precision */
+    int32_t progress;    /* nonzero: one line on stderr per refinement point and every 10 inner steps */
 } wfq_solve_opts;
 
 typedef struct {

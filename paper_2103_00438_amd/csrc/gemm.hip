@@ -69,6 +69,56 @@ __device__ inline void mma<WFQ_PREC_BF16>(floatx4& c, const uint4& a, const uint
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
 }
 
+// Element-outer issue order: for each k element, one MFMA into every accumulator in turn, so
+// consecutive MFMAs never depend on each other.
+template <int P, int WM, int WN, typename A>
+__device__ inline void mma_block_interleaved(A (&acc)[WM][WN], const uint4 (&af)[WM], const uint4 (&bf)[WN]) {
+    if constexpr (P == WFQ_PREC_FP32) {
+        float a[WM][4], b[WN][4];
+#pragma unroll
+        for (int x = 0; x < WM; ++x) {
+            a[x][0] = __uint_as_float(af[x].x); a[x][1] = __uint_as_float(af[x].y);
+            a[x][2] = __uint_as_float(af[x].z); a[x][3] = __uint_as_float(af[x].w);
+        }
+#pragma unroll
+        for (int y = 0; y < WN; ++y) {
+            b[y][0] = __uint_as_float(bf[y].x); b[y][1] = __uint_as_float(bf[y].y);
+            b[y][2] = __uint_as_float(bf[y].z); b[y][3] = __uint_as_float(bf[y].w);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+#pragma unroll
+            for (int x = 0; x < WM; ++x)
+#pragma unroll
+                for (int y = 0; y < WN; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[x][e], b[y][e], acc[x][y], 0, 0, 0);
+    } else if constexpr (P == WFQ_PREC_FP64) {
+        double a[WM][2], b[WN][2];
+#pragma unroll
+        for (int x = 0; x < WM; ++x) {
+            a[x][0] = __hiloint2double(af[x].y, af[x].x);
+            a[x][1] = __hiloint2double(af[x].w, af[x].z);
+        }
+#pragma unroll
+        for (int y = 0; y < WN; ++y) {
+            b[y][0] = __hiloint2double(bf[y].y, bf[y].x);
+            b[y][1] = __hiloint2double(bf[y].w, bf[y].z);
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+#pragma unroll
+            for (int x = 0; x < WM; ++x)
+#pragma unroll
+                for (int y = 0; y < WN; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[x][e], b[y][e], acc[x][y], 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int x = 0; x < WM; ++x)
+#pragma unroll
+            for (int y = 0; y < WN; ++y) mma<P>(acc[x][y], af[x], bf[y]);
+    }
+}
+
 template <int P, typename A>
 __device__ inline void mma_any(A& c, const uint4& a, const uint4& b) {
     if constexpr (P == WFQ_PREC_FP64)
@@ -91,7 +141,7 @@ __device__ inline void xcd_tile(int b, int mt_count, int total, int& mt, int& nt
 }
 
 // KB = bytes of k staged per row and stage (128 or 256); rows are padded by 16 bytes in LDS.
-template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int KB, int OCC>
+template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int KB, int OCC, int ILV>
 __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
     tx_mfma_kernel(const typename Prec<P>::elem* __restrict__ X, const typename Prec<P>::elem* __restrict__ T,
                    typename Prec<P>::out* __restrict__ Y, int64_t ld, int mt_count, int nt_count) {
@@ -156,10 +206,14 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
 #pragma unroll
             for (int b = 0; b < WN; ++b)
                 bf[b] = *reinterpret_cast<const uint4*>(L + (BM + wn * 16 * WN + b * 16 + frag_row) * RS + coff);
+            if constexpr (ILV) {
+                mma_block_interleaved<P, WM, WN>(acc, af, bf);
+            } else {
 #pragma unroll
-            for (int a = 0; a < WM; ++a)
+                for (int a = 0; a < WM; ++a)
 #pragma unroll
-                for (int b = 0; b < WN; ++b) mma_any<P>(acc[a][b], af[a], bf[b]);
+                    for (int b = 0; b < WN; ++b) mma_any<P>(acc[a][b], af[a], bf[b]);
+            }
         }
         if (kt + 1 < nk) {
             char* S = lds + ((kt + 1) & 1) * ROWS * RS;
@@ -269,13 +323,13 @@ struct Variant {
     void (*launch)(const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st);
 };
 
-template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int KB, int OCC>
+template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int KB, int OCC, int ILV = 0>
 void launch_mfma(const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st) {
     constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
     using elem = typename Prec<P>::elem;
     using out = typename Prec<P>::out;
     const int mtc = (ncol + BM - 1) / BM, ntc = (int)(ld / BN);
-    hipLaunchKernelGGL((tx_mfma_kernel<P, WM, WN, WAVES_M, WAVES_N, KB, OCC>), dim3(mtc * ntc),
+    hipLaunchKernelGGL((tx_mfma_kernel<P, WM, WN, WAVES_M, WAVES_N, KB, OCC, ILV>), dim3(mtc * ntc),
                        dim3(64 * WAVES_M * WAVES_N), 0, st, static_cast<const elem*>(X), static_cast<const elem*>(T),
                        static_cast<out*>(Y), ld, mtc, ntc);
 }
@@ -305,6 +359,11 @@ const std::vector<Variant>& variants() {
         {"m256n128w8", 256, 128, 1 << 30, launch_mfma<P, 4, 4, 4, 2, 128, 1>},
         {"m128n128k256", 128, 128, 1 << 30, launch_mfma<P, 4, 4, 2, 2, 256, 1>},
         {"m64n128k256", 64, 128, 1 << 30, launch_mfma<P, 4, 2, 1, 4, 256, 1>},
+        {"m128n256w8i", 128, 256, 1 << 30, launch_mfma<P, 4, 4, 2, 4, 128, 1, 1>},
+        {"m256n128w8i", 256, 128, 1 << 30, launch_mfma<P, 4, 4, 4, 2, 128, 1, 1>},
+        {"m64n128i", 64, 128, 1 << 30, launch_mfma<P, 4, 2, 1, 4, 128, 2, 1>},
+        {"m128n64i", 128, 64, 1 << 30, launch_mfma<P, 4, 2, 2, 2, 128, 2, 1>},
+        {"m64n128k256i", 64, 128, 1 << 30, launch_mfma<P, 4, 2, 1, 4, 256, 1, 1>},
     };
     return v;
 }

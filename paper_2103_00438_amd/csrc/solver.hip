@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 
 #include "krylov.h"
@@ -258,6 +259,14 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+void progress_line(const wfq_solve_opts& o, const char* what, int cycle, int step, size_t active, double worst,
+                   std::chrono::steady_clock::time_point t0) {
+    if (!o.progress) return;
+    std::fprintf(stderr, "[wfq] %s cycle %d step %d: %zu active, worst relres %.3e, %.1f s\n", what, cycle, step,
+                 active, worst, ms_since(t0) / 1e3);
+    std::fflush(stderr);
+}
+
 // FP64 refinement residual of the systems in `act`: V(s,0) = b - (L T + z I) x, beta = ||V(s,0)||.
 void fp64_residual(const Structure& S, Work& w, const std::vector<int>& act, Timer& tm, hipStream_t st) {
     const int na = (int)act.size();
@@ -407,6 +416,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                 if (f == 0 && ss[s].iters < o.max_iter) next.push_back(s);
             }
             stepping.swap(next);
+            if ((j + 1) % 10 == 0) progress_line(o, "gmres", ss[active[0]].cycles, j + 1, stepping.size(), -1.0, t0);
         }
         // drop systems that hit NaN
         std::vector<int> act2;
@@ -458,6 +468,11 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                     ss[s].prec = escalate_prec(S, ss[s].prec);
                 still.push_back(s);
             }
+        }
+        if (o.progress) {
+            double worst = 0.0;
+            for (int s : active) worst = std::max(worst, ss[s].relres);
+            progress_line(o, "gmres refinement", ss[active[0]].cycles, 0, still.size(), worst, t0);
         }
         active.swap(still);
     }
@@ -575,6 +590,7 @@ void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double to
                 if (w.h_snorm.p[s] > 0.5 * tol * ss[s].bnorm && ss[s].iters < o.max_iter) next.push_back(s);
             }
             stepping.swap(next);
+            if ((k + 1) % 10 == 0) progress_line(o, "qmr", ss[active[0]].cycles, k + 1, stepping.size(), -1.0, t0);
         }
         // systems that broke down leave for the GMRES fallback; NaN ends a system
         std::vector<int> act2;
@@ -628,6 +644,11 @@ void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double to
                     ss[s].prec = escalate_prec(S, ss[s].prec);
                 still.push_back(s);
             }
+        }
+        if (o.progress) {
+            double worst = 0.0;
+            for (int s : active) worst = std::max(worst, ss[s].relres);
+            progress_line(o, "qmr refinement", ss[active[0]].cycles, 0, still.size(), worst, t0);
         }
         active.swap(still);
     }

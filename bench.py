@@ -132,22 +132,26 @@ def bench_batched(args, wl, wfq, torch):
     prec = args.precision or wl.precision
     algo = args.algorithm or wl.algorithm
     otf = wl.t_mode == "otf"
-    store = ("fp64", "bf16") if prec == "bf16" else ("fp64", "fp32")
+    store = ("fp64", "fp32", "bf16") if prec == "bf16" else ("fp64", "fp32")
     t0 = time.perf_counter()
     h = wfq.wfq_build(wl.xyz, wl.params, t_mode=wl.t_mode, store=store, device=0)
     build_s = time.perf_counter() - t0
-    opts = dict(restart=wl.restart, precision=prec, algorithm=algo, progress=wl.n > 50000)
+    opts = dict(restart=wl.restart, precision=prec, algorithm=algo, progress=wl.n > 50000, max_iter=5000)
     tune = None
     tune_s = 0.0
     S = wl.n_systems
     if not otf and not args.no_tune:
         # the library's autotuner picks the block-product shape per column count (outside the timed region)
         t0 = time.perf_counter()
-        ncols = sorted({c for c in (16, 32, 64, 96, 128, 192, 256, 320, 384, 512, 640, 768) if c <= 2 * S}
-                       | {2 * S})
-        tune = wfq.wfq_tune(h, prec, ncols, reps=2)
-        if prec != "fp64":
-            wfq.wfq_tune(h, "fp64", ncols, reps=2)   # shapes of the FP64 refinement products
+        big = wl.n > 50000
+        grid = (64, 128, 256, 384, 512, 768) if big else (16, 32, 64, 96, 128, 192, 256, 320, 384, 512, 640, 768)
+        ncols = sorted({c for c in grid if c <= 2 * S} | {2 * S})
+        reps = 1 if big else 2
+        tune = wfq.wfq_tune(h, prec, ncols, reps=reps)
+        if prec == "bf16":
+            wfq.wfq_tune(h, "fp32", ncols, reps=reps)   # systems that escalate continue in FP32
+        if prec != "fp64" and not big:
+            wfq.wfq_tune(h, "fp64", ncols, reps=reps)   # shapes of the FP64 refinement products
         tune_s = time.perf_counter() - t0
 
     for _ in range(args.warmup):

@@ -119,6 +119,14 @@ int escalate_prec(const Structure& S, int prec) {
     return WFQ_PREC_FP64;
 }
 
+// A refinement cycle at reduced precision failed when the FP64 residual grew (a restarted Krylov
+// cycle with the exact operator never increases it), or when it fell by less than 2x although the
+// inner estimate claimed more than 10x.
+bool needs_escalation(double beta, double beta_prev, double est_end) {
+    if (!(beta <= beta_prev)) return true;
+    return beta > 0.5 * beta_prev && beta > 10.0 * est_end;
+}
+
 enum Slot { SLOT_G0 = 0, SLOT_G1 = 1, SLOT_G2 = 2, SLOT_STEP = 3, SLOT_ACT = 4, NSLOT = 5 };
 
 struct Work {
@@ -462,9 +470,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                 ss[s].done = true;
                 ss[s].t_done = now;
             } else {
-                // the inner operator was too coarse: the FP64 residual did not follow the estimate
-                if (o.escalate && ss[s].prec != WFQ_PREC_FP64 && ss[s].beta > 0.5 * beta_prev &&
-                    ss[s].beta > 100.0 * ss[s].est_end)
+                if (o.escalate && ss[s].prec != WFQ_PREC_FP64 && needs_escalation(ss[s].beta, beta_prev, ss[s].est_end))
                     ss[s].prec = escalate_prec(S, ss[s].prec);
                 still.push_back(s);
             }
@@ -639,8 +645,7 @@ void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double to
                 ss[s].done = true;
                 ss[s].t_done = now;
             } else {
-                if (o.escalate && ss[s].prec != WFQ_PREC_FP64 && ss[s].beta > 0.5 * beta_prev &&
-                    ss[s].beta > 100.0 * ss[s].est_end)
+                if (o.escalate && ss[s].prec != WFQ_PREC_FP64 && needs_escalation(ss[s].beta, beta_prev, ss[s].est_end))
                     ss[s].prec = escalate_prec(S, ss[s].prec);
                 still.push_back(s);
             }

@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--ref-systems", type=int, default=0,
                     help="compare only this many systems against FP64 (0 = all)")
     ap.add_argument("--jobs", type=int, default=40, help="serve_mix: number of jobs in the stream")
+    ap.add_argument("--max-iter", type=int, default=5000, help="cap on inner iterations per system")
     return ap.parse_args()
 
 
@@ -136,7 +137,7 @@ def bench_batched(args, wl, wfq, torch):
     t0 = time.perf_counter()
     h = wfq.wfq_build(wl.xyz, wl.params, t_mode=wl.t_mode, store=store, device=0)
     build_s = time.perf_counter() - t0
-    opts = dict(restart=wl.restart, precision=prec, algorithm=algo, progress=wl.n > 50000, max_iter=5000)
+    opts = dict(restart=wl.restart, precision=prec, algorithm=algo, progress=wl.n > 50000, max_iter=args.max_iter)
     tune = None
     tune_s = 0.0
     S = wl.n_systems

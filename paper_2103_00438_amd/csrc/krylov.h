@@ -29,21 +29,28 @@ void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, con
 void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
                 const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st);
 
-// partial[s][i][wc] = sum over rows of wave chunk wc of conj(V(s, i)) * V(s, jw), i = 0..j.
+// partial[s][i][wc] = sum over rows of wave chunk wc of conj(V(s, i)) * V(s, jw), i = 0..j; with
+// self_norm also partial[s][j+1][wc] = partial ||V(s, jw)||^2. Systems with active[s] == 0 are
+// skipped (active may be NULL).
 void multi_dot(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, double2* partial, int mdim,
-               hipStream_t st);
-// h[s][i] = sum_wc partial[s][i][wc] (i <= j); when acc is not NULL also acc[s][i] += h[s][i] (acc set to h if first).
+               hipStream_t st, const int* active = nullptr, bool self_norm = false);
+// h[s][i] = sum_wc partial[s][i][wc] for i <= j (skipping systems with active[s] == 0)
 void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
-                 hipStream_t st);
+                 hipStream_t st, const int* active = nullptr);
 // V(s, jw) -= sum_{i<=j} h[s][i] V(s, i); with norm2 != NULL also norm2[s][wc] = partial sum |V(s, jw)|^2.
 void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, const double2* h, int mdim,
-                  double* norm2, hipStream_t st);
+                  double* norm2, hipStream_t st, const int* active = nullptr);
+// reorth[s] = (||w'||^2 < ||w||^2 / 2) with ||w||^2 from h1[s][j+1] and ||w'||^2 from norm2a; h2 = 0 where not needed
+void reorth_test(const int* sys, int nsys, int j, int mdim, const double2* h1, const double* norm2a, int64_t n,
+                 double2* h2, int* reorth, hipStream_t st);
 
 struct GivensArgs {
     const double2* h1;   // [S][mdim] first CGS pass
     const double2* h2;   // [S][mdim] second CGS pass
-    const double* norm2; // [S][nwc] partial squared norms of the new vector
+    const double* norm2; // [S][nwc] partial squared norms of the new vector after the second pass
     int nwc;
+    const double* norm2a; // [S][nwc] the same after the first pass (used where reorth[s] == 0)
+    const int* reorth;    // [S] 1 where the second pass ran (NULL: always)
     double2* R;          // [S][mdim][mdim] column-major upper triangle (R[s][j][i] = R_ij)
     double* cs;          // [S][mdim]
     double2* sn;         // [S][mdim]

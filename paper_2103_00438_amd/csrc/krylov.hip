@@ -88,11 +88,13 @@ __global__ void __launch_bounds__(256) spmm_kernel(int64_t n, int64_t npad, int 
 }
 
 __global__ void __launch_bounds__(256) dot_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
-                                                  double2* __restrict__ partial, int mdim, int64_t nwc) {
+                                                  double2* __restrict__ partial, int mdim, int64_t nwc,
+                                                  const int* __restrict__ active, int self_norm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
     if (wc >= nwc) return;
     const int s = sys[blockIdx.y];
+    if (active && !active[s]) return;
     const double* wr = vre(V, s, jw);
     const double* wi = wr + V.npad;
     const int64_t row0 = wc * kWaveRows + lane;
@@ -120,11 +122,20 @@ __global__ void __launch_bounds__(256) dot_kernel(Basis V, int64_t n, const int*
         si = wave_sum(si);
         if (lane == 0) partial[((int64_t)s * mdim + i) * nwc + wc] = make_double2(sr, si);
     }
+    if (self_norm) {
+        // ||w||^2 in slot j + 1 (the reorthogonalisation test compares it with the projected norm)
+        double nn = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) nn += xr[r] * xr[r] + xi[r] * xi[r];
+        nn = wave_sum(nn);
+        if (lane == 0) partial[((int64_t)s * mdim + j + 1) * nwc + wc] = make_double2(nn, 0.0);
+    }
 }
 
 __global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const double2* __restrict__ partial, int mdim,
-                                   int64_t nwc, double2* __restrict__ h) {
+                                   int64_t nwc, double2* __restrict__ h, const int* __restrict__ active) {
     const int s = sys[blockIdx.x];
+    if (active && !active[s]) return;
     for (int i = threadIdx.x; i <= j; i += blockDim.x) {
         const double2* p = partial + ((int64_t)s * mdim + i) * nwc;
         double sr = 0.0, si = 0.0;
@@ -138,11 +149,13 @@ __global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const dou
 
 __global__ void __launch_bounds__(256) update_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
                                                      const double2* __restrict__ h, int mdim,
-                                                     double* __restrict__ norm2, int64_t nwc) {
+                                                     double* __restrict__ norm2, int64_t nwc,
+                                                     const int* __restrict__ active) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
     if (wc >= nwc) return;
     const int s = sys[blockIdx.y];
+    if (active && !active[s]) return;
     double* wr = vre(V, s, jw);
     double* wi = wr + V.npad;
     const int64_t row0 = wc * kWaveRows + lane;
@@ -183,6 +196,24 @@ __global__ void __launch_bounds__(256) update_kernel(Basis V, int64_t n, const i
     }
 }
 
+// Daniel-Gragg-Kaufman-Stewart test: a second Gram-Schmidt pass is needed only when projecting
+// removed more than half of the vector's squared norm (||w'||^2 < ||w||^2 / 2). Systems that skip it
+// get h2 = 0 and keep the norm of the first pass.
+__global__ void reorth_test_kernel(const int* __restrict__ sys, int nsys, int j, int mdim,
+                                   const double2* __restrict__ h1, const double* __restrict__ norm2a, int nwc,
+                                   double2* __restrict__ h2, int* __restrict__ reorth) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsys) return;
+    const int s = sys[k];
+    double nw = 0.0;
+    for (int w = 0; w < nwc; ++w) nw += norm2a[(int64_t)s * nwc + w];
+    const double w2 = h1[(int64_t)s * mdim + j + 1].x;
+    const int need = !(nw >= 0.5 * w2);
+    reorth[s] = need;
+    if (!need)
+        for (int i = 0; i <= j; ++i) h2[(int64_t)s * mdim + i] = make_double2(0.0, 0.0);
+}
+
 // One thread per system: new Hessenberg column, previous rotations, new rotation, residual estimate.
 __global__ void givens_kernel(const int* __restrict__ sys, int nsys, int j, int mdim, GivensArgs a) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -191,7 +222,8 @@ __global__ void givens_kernel(const int* __restrict__ sys, int nsys, int j, int 
     double2* col = a.R + ((int64_t)s * mdim + j) * mdim;
     for (int i = 0; i <= j; ++i) col[i] = cadd(a.h1[(int64_t)s * mdim + i], a.h2[(int64_t)s * mdim + i]);
     double hn2 = 0.0;
-    for (int w = 0; w < a.nwc; ++w) hn2 += a.norm2[(int64_t)s * a.nwc + w];
+    const double* nsrc = (a.reorth == nullptr || a.reorth[s]) ? a.norm2 : a.norm2a;
+    for (int w = 0; w < a.nwc; ++w) hn2 += nsrc[(int64_t)s * a.nwc + w];
     const double hn = sqrt(hn2);
     double* cs = a.cs + (int64_t)s * mdim;
     double2* sn = a.sn + (int64_t)s * mdim;
@@ -431,27 +463,37 @@ void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, co
 }
 
 void multi_dot(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, double2* partial, int mdim,
-               hipStream_t st) {
+               hipStream_t st, const int* active, bool self_norm) {
     if (nsys <= 0) return;
     const int64_t nwc = wave_chunks(n);
     dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
-    hipLaunchKernelGGL(dot_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, partial, mdim, nwc);
+    hipLaunchKernelGGL(dot_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, partial, mdim, nwc, active,
+                       (int)self_norm);
     WFQ_CHECK_LAUNCH();
 }
 
 void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
-                 hipStream_t st) {
+                 hipStream_t st, const int* active) {
     if (nsys <= 0) return;
-    hipLaunchKernelGGL(reduce_dots_kernel, dim3(nsys), dim3(128), 0, st, sys, j, partial, mdim, wave_chunks(n), h);
+    hipLaunchKernelGGL(reduce_dots_kernel, dim3(nsys), dim3(128), 0, st, sys, j, partial, mdim, wave_chunks(n), h,
+                       active);
     WFQ_CHECK_LAUNCH();
 }
 
 void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, const double2* h, int mdim,
-                  double* norm2, hipStream_t st) {
+                  double* norm2, hipStream_t st, const int* active) {
     if (nsys <= 0) return;
     const int64_t nwc = wave_chunks(n);
     dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
-    hipLaunchKernelGGL(update_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, h, mdim, norm2, nwc);
+    hipLaunchKernelGGL(update_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, h, mdim, norm2, nwc, active);
+    WFQ_CHECK_LAUNCH();
+}
+
+void reorth_test(const int* sys, int nsys, int j, int mdim, const double2* h1, const double* norm2a, int64_t n,
+                 double2* h2, int* reorth, hipStream_t st) {
+    if (nsys <= 0) return;
+    hipLaunchKernelGGL(reorth_test_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sys, nsys, j, mdim, h1, norm2a,
+                       (int)wave_chunks(n), h2, reorth);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -133,7 +133,8 @@ struct Work {
     int B = 0, mdim = 0, n_dir = 0;
     int64_t n = 0, npad = 0, nwc = 0, nblk = 0, mpad = 0;
     bool need32 = false, need16 = false;
-    DevArray<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, tol_abs, cond;
+    DevArray<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, norm2a, tol_abs, cond;
+    DevArray<int> reorth;
     DevArray<float> X32, Y32, Y16;
     DevArray<uint16_t> X16;
     DevArray<double2> partial, h1, h2, R, sn, g, y, z, alpha;
@@ -189,6 +190,8 @@ void alloc_work(Work& w, const Structure& S, int B, int m, int n_dir, int prec) 
     w.inv_beta.alloc(B);
     w.beta.alloc(B);
     w.norm2.alloc((size_t)B * std::max(w.nwc, w.nblk));
+    w.norm2a.alloc((size_t)B * w.nwc);
+    w.reorth.alloc(B);
     w.tol_abs.alloc(B);
     w.cond.alloc(B);
     w.flags.alloc(B);
@@ -356,8 +359,8 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         active.swap(still);
     }
 
-    GivensArgs ga{w.h1.p, w.h2.p, w.norm2.p, (int)w.nwc, w.R.p, w.cs.p, w.sn.p, w.g.p, w.est.p, w.inv_h.p,
-                  w.tol_abs.p, w.flags.p};
+    GivensArgs ga{w.h1.p, w.h2.p, w.norm2.p, (int)w.nwc, w.norm2a.p, w.reorth.p, w.R.p, w.cs.p, w.sn.p, w.g.p,
+                  w.est.p, w.inv_h.p, w.tol_abs.p, w.flags.p};
 
     while (!active.empty()) {
         // cycle start: g = beta e1, v0 = r / beta
@@ -395,16 +398,23 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             // CGS2 against v_0 .. v_j, then the Givens update of the least-squares problem
             upload(w, SLOT_STEP, stepping, st);
             const int* sl = w.sys[SLOT_STEP].p;
-            for (int pass = 0; pass < 2; ++pass) {
-                double2* h = pass == 0 ? w.h1.p : w.h2.p;
-                tm.begin(st);
-                multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st);
-                reduce_dots(S.n, sl, ns, j, w.partial.p, w.mdim, h, st);
-                tm.end(st, KC_DOT, 8.0 * n * ns * (j + 1), 16.0 * n * ns * (j + 2));
-                tm.begin(st);
-                multi_update(w.Vb, S.n, sl, ns, j, j + 1, h, w.mdim, pass == 1 ? w.norm2.p : nullptr, st);
-                tm.end(st, KC_UPDATE, 8.0 * n * ns * (j + 1), 16.0 * n * ns * (j + 3));
-            }
+            // first pass (with ||w||^2), the reorthogonalisation test, and the second pass only
+            // for the systems that need it
+            tm.begin(st);
+            multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, nullptr, true);
+            reduce_dots(S.n, sl, ns, j + 1, w.partial.p, w.mdim, w.h1.p, st);
+            tm.end(st, KC_DOT, 8.0 * n * ns * (j + 2), 16.0 * n * ns * (j + 2));
+            tm.begin(st);
+            multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h1.p, w.mdim, w.norm2a.p, st);
+            reorth_test(sl, ns, j, w.mdim, w.h1.p, w.norm2a.p, S.n, w.h2.p, w.reorth.p, st);
+            tm.end(st, KC_UPDATE, 8.0 * n * ns * (j + 1), 16.0 * n * ns * (j + 3));
+            tm.begin(st);
+            multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, w.reorth.p, false);
+            reduce_dots(S.n, sl, ns, j, w.partial.p, w.mdim, w.h2.p, st, w.reorth.p);
+            tm.end(st, KC_DOT, 0, 0);
+            tm.begin(st);
+            multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h2.p, w.mdim, w.norm2.p, st, w.reorth.p);
+            tm.end(st, KC_UPDATE, 0, 0);
             tm.begin(st);
             givens_step(sl, ns, j, w.mdim, ga, st);
             tm.end(st, KC_GIVENS, 0, 0);

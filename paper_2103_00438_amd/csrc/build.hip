@@ -232,6 +232,9 @@ void free_structure(Structure& s) {
     s.ell_val = nullptr;
     s.T32 = nullptr;
     s.T16 = nullptr;
+    if (s.split_ws) (void)hipFree(s.split_ws);
+    s.split_ws = nullptr;
+    s.split_ws_bytes = 0;
     s.bytes = 0;
 }
 

@@ -18,12 +18,14 @@ constexpr int kPad = 256;
 // Rows of the packed right-hand-side block are padded to this: the largest m-tile of any
 // block-product variant, so no variant reads or writes past the allocated rows.
 constexpr int kColPad = 256;
+constexpr uint64_t kSplitWsCap = 512ull << 20;   // work space of split-k block products
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef double doublex4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));   // 16 bytes, kept in registers
 
 struct Error {
     int code;
@@ -70,6 +72,9 @@ struct Structure {
     uint64_t bytes = 0;          // device bytes held by this structure
     bool connected = true;
     std::map<int, int> tuned[3];   // per precision: ncol -> block-product variant chosen by tune_tx
+    // partial tiles of split-k block products (grown on demand, at most kSplitWsCap bytes)
+    mutable void* split_ws = nullptr;
+    mutable uint64_t split_ws_bytes = 0;
 };
 
 struct KernelStat {

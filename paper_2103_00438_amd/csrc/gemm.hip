@@ -44,7 +44,7 @@ struct Prec<WFQ_PREC_BF16> {
     using sacc = float;
 };
 
-__device__ inline void mma(doublex4& c, const uint4& a, const uint4& b) {
+__device__ inline void mma(doublex4& c, const u32x4& a, const u32x4& b) {
     double a0 = __hiloint2double(a.y, a.x), a1 = __hiloint2double(a.w, a.z);
     double b0 = __hiloint2double(b.y, b.x), b1 = __hiloint2double(b.w, b.z);
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, c, 0, 0, 0);
@@ -52,10 +52,10 @@ __device__ inline void mma(doublex4& c, const uint4& a, const uint4& b) {
 }
 
 template <int P>
-__device__ inline void mma(floatx4& c, const uint4& a, const uint4& b);
+__device__ inline void mma(floatx4& c, const u32x4& a, const u32x4& b);
 
 template <>
-__device__ inline void mma<WFQ_PREC_FP32>(floatx4& c, const uint4& a, const uint4& b) {
+__device__ inline void mma<WFQ_PREC_FP32>(floatx4& c, const u32x4& a, const u32x4& b) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
@@ -63,7 +63,7 @@ __device__ inline void mma<WFQ_PREC_FP32>(floatx4& c, const uint4& a, const uint
 }
 
 template <>
-__device__ inline void mma<WFQ_PREC_BF16>(floatx4& c, const uint4& a, const uint4& b) {
+__device__ inline void mma<WFQ_PREC_BF16>(floatx4& c, const u32x4& a, const u32x4& b) {
     bf16x8 av = __builtin_bit_cast(bf16x8, a);
     bf16x8 bv = __builtin_bit_cast(bf16x8, b);
     c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
@@ -72,7 +72,7 @@ __device__ inline void mma<WFQ_PREC_BF16>(floatx4& c, const uint4& a, const uint
 // Element-outer issue order: for each k element, one MFMA into every accumulator in turn, so
 // consecutive MFMAs never depend on each other.
 template <int P, int WM, int WN, typename A>
-__device__ inline void mma_block_interleaved(A (&acc)[WM][WN], const uint4 (&af)[WM], const uint4 (&bf)[WN]) {
+__device__ inline void mma_block_interleaved(A (&acc)[WM][WN], const u32x4 (&af)[WM], const u32x4 (&bf)[WN]) {
     if constexpr (P == WFQ_PREC_FP32) {
         float a[WM][4], b[WN][4];
 #pragma unroll
@@ -120,7 +120,7 @@ __device__ inline void mma_block_interleaved(A (&acc)[WM][WN], const uint4 (&af)
 }
 
 template <int P, typename A>
-__device__ inline void mma_any(A& c, const uint4& a, const uint4& b) {
+__device__ inline void mma_any(A& c, const u32x4& a, const u32x4& b) {
     if constexpr (P == WFQ_PREC_FP64)
         mma(c, a, b);
     else
@@ -132,19 +132,24 @@ constexpr int kRowStride = 144;  // bytes per staged row (128 data + 16 pad)
 // Map a linear work-group id to a (m-tile, n-tile) pair so that the work-groups dispatched to one
 // XCD (ids congruent mod 8) get a contiguous run of tiles, m fastest: the m-tiles that share one
 // slab of T rows then run on the same XCD and reuse it from that XCD's L2.
-__device__ inline void xcd_tile(int b, int mt_count, int total, int& mt, int& nt) {
+__device__ inline int xcd_logical(int b, int total) {
     int xcd = b & 7, slot = b >> 3;
     int q = total >> 3, r = total & 7;
-    int logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-    mt = logical % mt_count;
-    nt = logical / mt_count;
+    return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
 // KB = bytes of k staged per row and stage (128 or 256); rows are padded by 16 bytes in LDS.
+//
+// Split k: with split > 1 the k range is cut into `split` equal parts and each (m-tile, part,
+// n-tile) is one work-group, m fastest, so the m-tiles that share one slab of T and one k part
+// stay adjacent (same XCD, same time) and T is still read once. Part 0 writes Y, part p > 0 writes
+// its partial tile to ws + (p - 1) * mrows * ld in the layout of Y; split_reduce_kernel then adds
+// the parts to Y in part order (a fixed summation order, so results are reproducible).
 template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int KB, int OCC, int ILV>
 __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
     tx_mfma_kernel(const typename Prec<P>::elem* __restrict__ X, const typename Prec<P>::elem* __restrict__ T,
-                   typename Prec<P>::out* __restrict__ Y, int64_t ld, int mt_count, int nt_count) {
+                   typename Prec<P>::out* __restrict__ Y, int64_t ld, int ncol, int mt_count, int nt_count, int split,
+                   typename Prec<P>::out* __restrict__ ws) {
     using elem = typename Prec<P>::elem;
     using acc_t = typename Prec<P>::acc;
     constexpr int NT = 64 * WAVES_M * WAVES_N;
@@ -153,26 +158,36 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
     constexpr int ROWS = BM + BN;
     constexpr int CH = KB / 16;          // 16-byte chunks per staged row
     constexpr int RS = KB + 16;          // padded LDS row stride
-    constexpr int PER_T = ROWS * CH / NT;
-    static_assert(ROWS * CH % NT == 0, "whole chunks per thread");
+    constexpr int TOTAL = ROWS * CH;     // 16-byte chunks per stage
+    constexpr int PER_T = (TOTAL + NT - 1) / NT;
+    // chunk u of this thread exists (only the last one can be missing)
+#define WFQ_CHUNK_OK(u) (TOTAL % NT == 0 || (u) < PER_T - 1 || r0 + (u) * RSTEP < ROWS)
     __shared__ __attribute__((aligned(16))) char lds[2 * ROWS * RS];
 
-    int mt, nt;
-    xcd_tile(blockIdx.x, mt_count, mt_count * nt_count, mt, nt);
+    const int logical = xcd_logical(blockIdx.x, mt_count * nt_count * split);
+    const int mt = logical % mt_count;
+    const int part = (logical / mt_count) % split;
+    const int nt = logical / (mt_count * split);
     const int64_t m0 = (int64_t)mt * BM, n0 = (int64_t)nt * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WAVES_M, wn = wave / WAVES_M;
 
-    const char* src[PER_T];
-    int dst[PER_T];
-#pragma unroll
-    for (int u = 0; u < PER_T; ++u) {
-        int q = tid + NT * u;
-        int row = q / CH, cc = q % CH;
-        const elem* base = row < BM ? X + (m0 + row) * ld : T + (n0 + row - BM) * ld;
-        src[u] = reinterpret_cast<const char*>(base) + cc * 16;
-        dst[u] = row * RS + cc * 16;
-    }
+    // chunk u of this thread: row r0 + u * RSTEP (X rows first, then T rows), byte column cc * 16
+    static_assert(NT % CH == 0, "whole rows per pass");
+    constexpr int RSTEP = NT / CH;
+    const int r0 = tid / CH, cc = tid % CH;
+    const int64_t ldb = ld * (int64_t)sizeof(elem);
+    const char* xb = reinterpret_cast<const char*>(X) + m0 * ldb + cc * 16;
+    const char* tb = reinterpret_cast<const char*>(T) + n0 * ldb + cc * 16;
+    const int dst0 = r0 * RS + cc * 16;
+    // A missing last chunk re-reads the last row, and X rows past the last column (the tile can
+    // be wider than the rows the caller holds) re-read the last column: loads stay unconditional
+    // and in bounds; what they feed lands only in Y rows >= ncol, which are not stored.
+    const int xlast = ncol - 1 - (int)m0;
+    auto src_of = [&](int u) {
+        const int row = min(r0 + u * RSTEP, ROWS - 1);
+        return row < BM ? xb + min(row, xlast) * ldb : tb + (row - BM) * ldb;
+    };
 
     acc_t acc[WM][WN];
 #pragma unroll
@@ -180,32 +195,40 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
 #pragma unroll
         for (int b = 0; b < WN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
 
-    const int nk = (int)(ld * (int64_t)sizeof(elem) / KB);
-    uint4 reg[PER_T];
+    const int nk_all = (int)(ld * (int64_t)sizeof(elem) / KB);
+    const int kb = (int)((int64_t)nk_all * part / split), ke = (int)((int64_t)nk_all * (part + 1) / split);
+    u32x4 reg[PER_T];
 #pragma unroll
-    for (int u = 0; u < PER_T; ++u) reg[u] = *reinterpret_cast<const uint4*>(src[u]);
+    for (int u = 0; u < PER_T; ++u)
+        reg[u] = *reinterpret_cast<const u32x4*>(src_of(u) + (int64_t)kb * KB);
 #pragma unroll
-    for (int u = 0; u < PER_T; ++u) *reinterpret_cast<uint4*>(lds + dst[u]) = reg[u];
+    for (int u = 0; u < PER_T; ++u)
+        if (WFQ_CHUNK_OK(u)) *reinterpret_cast<u32x4*>(lds + dst0 + u * RSTEP * RS) = reg[u];
     __syncthreads();
 
     const int frag_row = lane & 15, frag_chunk = lane >> 4;
-    for (int kt = 0; kt < nk; ++kt) {
-        if (kt + 1 < nk) {
-            const int64_t off = (int64_t)(kt + 1) * KB;
+    for (int kt = kb; kt < ke; ++kt) {
+        // prefetch the next k-step (the last step re-reads its own: loads stay unconditional, so
+        // the staging registers live in VGPRs across the MFMA block instead of going to scratch)
+        {
+            const int64_t off = (int64_t)min(kt + 1, ke - 1) * KB;
 #pragma unroll
-            for (int u = 0; u < PER_T; ++u) reg[u] = *reinterpret_cast<const uint4*>(src[u] + off);
+            for (int u = 0; u < PER_T; ++u)
+                reg[u] = *reinterpret_cast<const u32x4*>(src_of(u) + off);
         }
-        const char* L = lds + (kt & 1) * ROWS * RS;
+        // keep the loads ahead of the MFMA block: issued late, their latency is not hidden
+        __builtin_amdgcn_sched_barrier(0);
+        const char* L = lds + ((kt - kb) & 1) * ROWS * RS;
 #pragma unroll
         for (int cg = 0; cg < CH / 4; ++cg) {
-            uint4 af[WM], bf[WN];
+            u32x4 af[WM], bf[WN];
             const int coff = (cg * 4 + frag_chunk) * 16;
 #pragma unroll
             for (int a = 0; a < WM; ++a)
-                af[a] = *reinterpret_cast<const uint4*>(L + (wm * 16 * WM + a * 16 + frag_row) * RS + coff);
+                af[a] = *reinterpret_cast<const u32x4*>(L + (wm * 16 * WM + a * 16 + frag_row) * RS + coff);
 #pragma unroll
             for (int b = 0; b < WN; ++b)
-                bf[b] = *reinterpret_cast<const uint4*>(L + (BM + wn * 16 * WN + b * 16 + frag_row) * RS + coff);
+                bf[b] = *reinterpret_cast<const u32x4*>(L + (BM + wn * 16 * WN + b * 16 + frag_row) * RS + coff);
             if constexpr (ILV) {
                 mma_block_interleaved<P, WM, WN>(acc, af, bf);
             } else {
@@ -215,10 +238,14 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
                     for (int b = 0; b < WN; ++b) mma_any<P>(acc[a][b], af[a], bf[b]);
             }
         }
-        if (kt + 1 < nk) {
-            char* S = lds + ((kt + 1) & 1) * ROWS * RS;
+        // the other buffer was last read in step kt - 1, which every wave left at its barrier;
+        // the stores wait for the loads, so they stay behind the MFMA block
+        __builtin_amdgcn_sched_barrier(0);
+        {
+            char* S = lds + ((kt + 1 - kb) & 1) * ROWS * RS;
 #pragma unroll
-            for (int u = 0; u < PER_T; ++u) *reinterpret_cast<uint4*>(S + dst[u]) = reg[u];
+            for (int u = 0; u < PER_T; ++u)
+                if (WFQ_CHUNK_OK(u)) *reinterpret_cast<u32x4*>(S + dst0 + u * RSTEP * RS) = reg[u];
         }
         __syncthreads();
     }
@@ -226,6 +253,7 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
     // Accumulator layout of one 16 x 16 block: column j = lane % 16 in every case; the row of
     // element r is 4 (lane / 16) + r for the FP32 and BF16 instructions and lane / 16 + 4 r for
     // the FP64 one.
+    typename Prec<P>::out* out = part == 0 ? Y : ws + (int64_t)(part - 1) * mt_count * BM * ld;
 #pragma unroll
     for (int a = 0; a < WM; ++a)
 #pragma unroll
@@ -235,19 +263,32 @@ __global__ void __launch_bounds__(64 * WAVES_M * WAVES_N, OCC)
                 const int row = P == WFQ_PREC_FP64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
                 int64_t c = m0 + wm * 16 * WM + a * 16 + row;
                 int64_t i = n0 + wn * 16 * WN + b * 16 + (lane & 15);
-                Y[c * ld + i] = acc[a][b][r];
+                if (c < ncol) out[c * ld + i] = acc[a][b][r];
             }
+}
+
+#undef WFQ_CHUNK_OK
+
+// Y[q] += ws_1[q] + ws_2[q] + ... for the first `count` elements, parts added in order.
+template <typename O>
+__global__ void __launch_bounds__(256) split_reduce_kernel(O* __restrict__ Y, const O* __restrict__ ws,
+                                                            int64_t count, int64_t stride, int parts) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= count) return;
+    O v = Y[q];
+    for (int p = 0; p < parts; ++p) v += ws[p * stride + q];
+    Y[q] = v;
 }
 
 // ---- narrow blocks: each wave streams R rows of T once and keeps up to NC columns of X in registers.
 
-__device__ inline void unpack(const uint4& v, float (&f)[4]) {
+__device__ inline void unpack(const u32x4& v, float (&f)[4]) {
     f[0] = __uint_as_float(v.x); f[1] = __uint_as_float(v.y); f[2] = __uint_as_float(v.z); f[3] = __uint_as_float(v.w);
 }
-__device__ inline void unpack(const uint4& v, double (&f)[2]) {
+__device__ inline void unpack(const u32x4& v, double (&f)[2]) {
     f[0] = __hiloint2double(v.y, v.x); f[1] = __hiloint2double(v.w, v.z);
 }
-__device__ inline void unpack(const uint4& v, float (&f)[8]) {
+__device__ inline void unpack(const u32x4& v, float (&f)[8]) {
     uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -283,13 +324,13 @@ __global__ void __launch_bounds__(256) tx_skinny_kernel(const typename Prec<P>::
         S xv[NC][E];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            uint4 v = *reinterpret_cast<const uint4*>(X + c * ld + k);
+            u32x4 v = *reinterpret_cast<const u32x4*>(X + c * ld + k);
             unpack(v, xv[c]);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             S tv[E];
-            unpack(*reinterpret_cast<const uint4*>(T + (row0 + r) * ld + k), tv);
+            unpack(*reinterpret_cast<const u32x4*>(T + (row0 + r) * ld + k), tv);
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -320,22 +361,78 @@ struct Variant {
     const char* name;
     int bm, bn;        // output tile (m = columns of Y, n = atoms); bm = 0 for the narrow kernel
     int max_ncol;      // largest ncol the variant accepts (narrow kernels hold columns in registers)
-    void (*launch)(const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st);
+    void (*launch)(const Structure& s, const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st);
 };
 
+// Number of k parts for a grid of `tiles` work-groups over nk k-steps when `slots` work-groups fit
+// on the chip at once: the time is taken as proportional to (rounds of work-groups) x (k-steps per
+// part), plus two k-steps per extra part for writing and adding the partial tiles. A split must
+// win by 3 % and keep parts >= 8 k-steps and the partial tiles within the work-space cap.
+int choose_split(int64_t tiles, int nk, int64_t slots, uint64_t part_bytes) {
+    auto cost = [&](int sp) { return (double)((tiles * sp + slots - 1) / slots) * ((nk + sp - 1) / sp) + 2.0 * (sp - 1); };
+    int best = 1;
+    double best_cost = cost(1);
+    for (int sp = 2; sp <= 8; ++sp) {
+        if (nk / sp < 8 || (uint64_t)(sp - 1) * part_bytes > kSplitWsCap) break;
+        const double c = cost(sp);
+        if (c < 0.97 * best_cost) {
+            best = sp;
+            best_cost = c;
+        }
+    }
+    return best;
+}
+
+void* split_workspace(const Structure& s, uint64_t bytes) {
+    if (bytes > s.split_ws_bytes) {
+        if (s.split_ws) {
+            WFQ_HIP(hipFree(s.split_ws));
+            s.split_ws = nullptr;
+            s.split_ws_bytes = 0;
+        }
+        hipError_t e = hipMalloc(&s.split_ws, bytes);
+        if (e != hipSuccess) throw Error{WFQ_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+        s.split_ws_bytes = bytes;
+    }
+    return s.split_ws;
+}
+
+int device_cus(int device) {
+    int cus = 0;
+    WFQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    return cus > 0 ? cus : 1;
+}
+
 template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int KB, int OCC, int ILV = 0>
-void launch_mfma(const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st) {
+void launch_mfma(const Structure& s, const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st) {
     constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
+    constexpr int NT = 64 * WAVES_M * WAVES_N;
     using elem = typename Prec<P>::elem;
     using out = typename Prec<P>::out;
+    auto kern = tx_mfma_kernel<P, WM, WN, WAVES_M, WAVES_N, KB, OCC, ILV>;
+    static const int per_cu = [&] {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(kern), NT, 0) !=
+                hipSuccess || nb < 1)
+            nb = 1;
+        return nb;
+    }();
     const int mtc = (ncol + BM - 1) / BM, ntc = (int)(ld / BN);
-    hipLaunchKernelGGL((tx_mfma_kernel<P, WM, WN, WAVES_M, WAVES_N, KB, OCC, ILV>), dim3(mtc * ntc),
-                       dim3(64 * WAVES_M * WAVES_N), 0, st, static_cast<const elem*>(X), static_cast<const elem*>(T),
-                       static_cast<out*>(Y), ld, mtc, ntc);
+    const int nk = (int)(ld * (int64_t)sizeof(elem) / KB);
+    const uint64_t part_bytes = (uint64_t)mtc * BM * ld * sizeof(out);
+    const int split = choose_split((int64_t)mtc * ntc, nk, (int64_t)per_cu * device_cus(s.device), part_bytes);
+    out* ws = split > 1 ? static_cast<out*>(split_workspace(s, (split - 1) * part_bytes)) : nullptr;
+    hipLaunchKernelGGL(kern, dim3(mtc * ntc * split), dim3(NT), 0, st, static_cast<const elem*>(X),
+                       static_cast<const elem*>(T), static_cast<out*>(Y), ld, ncol, mtc, ntc, split, ws);
+    if (split > 1) {
+        const int64_t count = (int64_t)ncol * ld;
+        hipLaunchKernelGGL(split_reduce_kernel<out>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                           static_cast<out*>(Y), ws, count, (int64_t)mtc * BM * ld, split - 1);
+    }
 }
 
 template <int P, int NC>
-void launch_skinny(const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st) {
+void launch_skinny(const Structure&, const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st) {
     constexpr int R = 4;
     using elem = typename Prec<P>::elem;
     using out = typename Prec<P>::out;
@@ -368,9 +465,26 @@ const std::vector<Variant>& variants() {
     return v;
 }
 
+// Wider column tiles for FP32 and BF16 (their accumulators are half the size of FP64 ones), so
+// that column counts between the powers of two are not padded up to the next multiple of 128.
+template <int P>
+const std::vector<Variant>& variants_all() {
+    static const std::vector<Variant> v = [] {
+        std::vector<Variant> r = variants<P>();
+        if constexpr (P != WFQ_PREC_FP64) {
+            r.push_back({"m96n256w8", 96, 256, 1 << 30, launch_mfma<P, 3, 4, 2, 4, 128, 1>});
+            r.push_back({"m160n256w8", 160, 256, 1 << 30, launch_mfma<P, 5, 4, 2, 4, 128, 1>});
+            r.push_back({"m192n256w8", 192, 256, 1 << 30, launch_mfma<P, 6, 4, 2, 4, 128, 1>});
+            r.push_back({"m192n128w8", 192, 128, 1 << 30, launch_mfma<P, 3, 4, 4, 2, 128, 1>});
+        }
+        return r;
+    }();
+    return v;
+}
+
 const std::vector<Variant>& variants_of(int prec) {
-    return prec == WFQ_PREC_FP64 ? variants<WFQ_PREC_FP64>()
-           : prec == WFQ_PREC_FP32 ? variants<WFQ_PREC_FP32>() : variants<WFQ_PREC_BF16>();
+    return prec == WFQ_PREC_FP64 ? variants_all<WFQ_PREC_FP64>()
+           : prec == WFQ_PREC_FP32 ? variants_all<WFQ_PREC_FP32>() : variants_all<WFQ_PREC_BF16>();
 }
 
 int find_variant(int prec, const char* name) {
@@ -412,7 +526,7 @@ void run_variant(const Structure& s, int prec, int var, const void* X, void* Y, 
     if (T == nullptr) throw Error{WFQ_EINVAL, "the stored copy of T for this precision was not built"};
     const Variant& v = variants_of(prec)[var];
     if (ncol > v.max_ncol) throw Error{WFQ_EINVAL, "kernel variant cannot take that many columns"};
-    v.launch(X, T, Y, s.npad, ncol, st);
+    v.launch(s, X, T, Y, s.npad, ncol, st);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -87,6 +87,74 @@ __global__ void __launch_bounds__(256) spmm_kernel(int64_t n, int64_t npad, int 
         }
 }
 
+// Row-block variant. A work-group owns R consecutive rows for one group of systems. Their ELL
+// rows are staged once in LDS ([entry][row], so lanes read consecutive words) and reused for every
+// system of the group; each wave works on 64 / R systems at a time, one lane per (row, system).
+// The neighbour window of each Y plane is then gathered by the work-groups of neighbouring row
+// blocks at about the same time: row blocks are laid out so that the work-groups of one XCD (ids
+// congruent mod 8) own one contiguous run of rows, and that XCD's L2 serves the overlapping windows.
+template <typename YE, int R>
+__global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad, int w,
+                                                        const int32_t* __restrict__ ecol,
+                                                        const double* __restrict__ eval, const YE* __restrict__ Y,
+                                                        int64_t ld, const int* __restrict__ sys, int nsys, int per_group,
+                                                        const double2* __restrict__ z, Basis V, int jsrc, int jdst) {
+    extern __shared__ char smem[];
+    double* lval = reinterpret_cast<double*>(smem);
+    int32_t* lcol = reinterpret_cast<int32_t*>(smem + (size_t)w * R * sizeof(double));
+    constexpr int G = 64 / R;
+    const int per_xcd = (int)(gridDim.x >> 3);
+    const int64_t rb = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    const int64_t r0 = rb * R;
+    if (r0 >= n) return;   // whole work-group: grid padded to a multiple of 8 row blocks
+    for (int q = threadIdx.x; q < w * R; q += 256) {
+        const int e = q / R, r = q % R;
+        const int64_t i = r0 + r;   // < npad: npad is a multiple of R
+        lcol[q] = ecol[(int64_t)e * npad + i];
+        lval[q] = eval[(int64_t)e * npad + i];
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r = lane % R, g = lane / R;
+    const int64_t i = r0 + r;
+    if (i >= n) return;
+    const int k_end = min(nsys, (int)(blockIdx.y + 1) * per_group);
+    for (int k = (int)blockIdx.y * per_group + wave * G + g; k < k_end; k += 4 * G) {
+        const YE* yr = Y + (int64_t)(2 * k) * ld;
+        const YE* yi = yr + ld;
+        double ar = 0.0, ai = 0.0;
+#pragma unroll 4
+        for (int e = 0; e < w; ++e) {
+            const int c = lcol[e * R + r];
+            const double v = lval[e * R + r];
+            ar += v * widen(yr[c]);
+            ai += v * widen(yi[c]);
+        }
+        const int s = sys[k];
+        const double* sr = vre(V, s, jsrc);
+        const double vr = sr[i], vi = sr[i + V.npad];
+        const double2 zz = z[s];
+        double* dr = vre(V, s, jdst);
+        dr[i] = ar + zz.x * vr - zz.y * vi;
+        dr[i + V.npad] = ai + zz.x * vi + zz.y * vr;
+    }
+}
+
+template <typename YE, int R>
+void launch_spmm_rows(const Structure& S, const YE* Y, int64_t ld, const int* sys, int nsys, const double2* z,
+                      const Basis& V, int jsrc, int jdst, hipStream_t st) {
+    constexpr int G = 64 / R;
+    const int64_t nb = S.npad / R;
+    const int64_t nb8 = (nb + 7) / 8 * 8;
+    // enough work-groups to fill the chip (about 8 per CU), but at least one system per wave
+    const int64_t want = (2048 + nb8 - 1) / nb8;
+    const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(want, (nsys + 4 * G - 1) / (4 * G)));
+    const int per_group = (nsys + gy - 1) / gy;
+    const size_t lds = (size_t)S.ell_w * R * 12;
+    hipLaunchKernelGGL((spmm_rows_kernel<YE, R>), dim3((unsigned)nb8, (unsigned)gy), dim3(256), lds, st, S.n, S.npad,
+                       S.ell_w, S.ell_col, S.ell_val, Y, ld, sys, nsys, per_group, z, V, jsrc, jdst);
+}
+
 __global__ void __launch_bounds__(256) dot_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
                                                   double2* __restrict__ partial, int mdim, int64_t nwc,
                                                   const int* __restrict__ active, int self_norm) {
@@ -451,6 +519,28 @@ void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, con
 void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
                 const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st) {
     if (nsys <= 0) return;
+    // row-block kernel with the largest row block whose ELL rows fit in 40 KB of LDS (4 work-groups
+    // per CU); the per-thread kernel only for neighbour lists too long even for 8 rows
+    const size_t per_row = (size_t)S.ell_w * 12;
+    const int R = per_row * 64 <= 40960 ? 64 : per_row * 32 <= 40960 ? 32 : per_row * 16 <= 40960 ? 16
+                  : per_row * 8 <= 40960 ? 8 : 0;
+    if (R > 0) {
+        if (y_is_f64) {
+            const double* Yd = static_cast<const double*>(Y);
+            if (R == 64) launch_spmm_rows<double, 64>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, st);
+            else if (R == 32) launch_spmm_rows<double, 32>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, st);
+            else if (R == 16) launch_spmm_rows<double, 16>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, st);
+            else launch_spmm_rows<double, 8>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, st);
+        } else {
+            const float* Yf = static_cast<const float*>(Y);
+            if (R == 64) launch_spmm_rows<float, 64>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, st);
+            else if (R == 32) launch_spmm_rows<float, 32>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, st);
+            else if (R == 16) launch_spmm_rows<float, 16>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, st);
+            else launch_spmm_rows<float, 8>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, st);
+        }
+        WFQ_CHECK_LAUNCH();
+        return;
+    }
     constexpr int NS = 8;
     dim3 grd((unsigned)((S.n + 255) / 256), (unsigned)((nsys + NS - 1) / NS));
     if (y_is_f64)

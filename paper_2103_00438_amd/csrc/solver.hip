@@ -686,6 +686,7 @@ uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_d
     b += (uint64_t)B * mdim * nwc * 16;         // dot partials
     b += (uint64_t)B * mdim * mdim * 16;        // R
     b += (uint64_t)B * (mdim * 64 + 2 * np * 8 / 1);  // small arrays + output staging
+    b += std::min<uint64_t>(kSplitWsCap, 7 * mpad * np * 8);   // split-k partial tiles
     return b;
 }
 

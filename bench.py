@@ -19,9 +19,11 @@ sheet1m (matrix-free T, 10^6 atoms), serve_mix (Poisson stream of jobs through w
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -108,7 +110,27 @@ def kernel_table(stats):
             for k, v in stats.items() if v["launches"]}
 
 
-def roofline_of(stats, prec, otf, n):
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of this workload
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size); None when there is none or the
+    kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_rocprof.md")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        m = re.search(r"<!-- traffic (\{.*\}) -->", f.read())
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("kernel") != kernel:
+        return None
+    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+            return None
+    return rec["bytes_per_launch"]
+
+
+def roofline_of(stats, prec, otf, n, workload=None):
     if otf:
         key = "tx_otf_f32" if prec == "fp32" else "tx_otf_f64"
         st = stats[key]
@@ -125,7 +147,7 @@ def roofline_of(stats, prec, otf, n):
     st = stats[dom]
     achieved = st["flops"] / (st["ms"] / 1e3) / 1e12 if st["ms"] > 0 else 0.0
     return dict(bound="mfma", achieved=achieved, peak=PEAKS[prec], unit="TFLOP/s", frac=achieved / PEAKS[prec],
-                traffic=None, kernel=dom, launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
+                traffic=measured_traffic(workload, dom), kernel=dom, launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
                 avg_flops_per_launch=st["flops"] / max(1, st["launches"]))
 
 
@@ -145,7 +167,7 @@ def bench_batched(args, wl, wfq, torch):
         # the library's autotuner picks the block-product shape per column count (outside the timed region)
         t0 = time.perf_counter()
         big = wl.n > 50000
-        grid = (64, 128, 256, 384, 512, 768) if big else (16, 32, 64, 96, 128, 192, 256, 320, 384, 512, 640, 768)
+        grid = (64, 128, 256, 384, 512, 768) if big else (16, 32, 64, 96, 128, 160, 192, 224, 256, 288, 320, 352, 384, 512, 640, 768)
         ncols = sorted({c for c in grid if c <= 2 * S} | {2 * S})
         reps = 1 if big else 2
         tune = wfq.wfq_tune(h, prec, ncols, reps=reps)
@@ -173,7 +195,7 @@ def bench_batched(args, wl, wfq, torch):
     statuses = sorted(set(r["status"] for r in last["info"]))
     relres_max = max(r["relres"] for r in last["info"])
     prec_end = sorted(set(r["precision"] for r in last["info"]))
-    roofline = roofline_of(stats, prec, otf, wl.n)
+    roofline = roofline_of(stats, prec, otf, wl.n, wl.name)
 
     extra = {}
     if not args.no_reference and prec != "fp64":

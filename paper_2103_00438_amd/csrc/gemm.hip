@@ -494,17 +494,23 @@ int find_variant(int prec, const char* name) {
     return -1;
 }
 
-// Built-in choice when no tuning result covers ncol (the fastest shapes measured on MI355X for a
-// 20 000-atom T, per column count).
+// Built-in choice when no tuning result covers ncol: the fastest shapes measured on MI355X for a
+// 20 000-atom T, per precision and column count.
 int default_variant(int prec, int ncol) {
     if (ncol <= 2) return find_variant(prec, "skinny2");
     if (ncol <= 4) return find_variant(prec, "skinny4");
     if (ncol <= 8) return find_variant(prec, "skinny8");
-    if (ncol <= 64) return find_variant(prec, "m64n128k256");
-    if (ncol <= 128) return find_variant(prec, "m128n64");
-    if (ncol <= 192) return find_variant(prec, "m64n128");
-    if (ncol <= 256) return find_variant(prec, "m256n128w8");
-    return find_variant(prec, "m128n256w8");
+    struct Pick { int upto; const char* name; };
+    static const Pick f64[] = {{32, "m32n128"}, {64, "m64n128i"}, {96, "m128n256w8i"}, {128, "m128n256w8"},
+                               {192, "m64n128i"}, {256, "m128n256w8i"}, {320, "m64n128"}, {1 << 30, "m128n256w8i"}};
+    static const Pick f32[] = {{32, "m32n128"}, {64, "m64n128k256i"}, {96, "m96n256w8"}, {128, "m128n64i"},
+                               {192, "m96n256w8"}, {256, "m128n64i"}, {320, "m160n256w8"}, {1 << 30, "m96n256w8"}};
+    static const Pick b16[] = {{32, "m64n128i"}, {64, "m64n128i"}, {128, "m128n128"}, {192, "m192n256w8"},
+                               {256, "m256n128w8i"}, {320, "m160n256w8"}, {1 << 30, "m192n256w8"}};
+    const Pick* t = prec == WFQ_PREC_FP64 ? f64 : prec == WFQ_PREC_FP32 ? f32 : b16;
+    while (ncol > t->upto) ++t;
+    const int k = find_variant(prec, t->name);
+    return k >= 0 ? k : find_variant(prec, "m128n256w8");   // present for every precision
 }
 
 int pick_variant(const Structure& s, int prec, int ncol) {

@@ -67,3 +67,16 @@ def test_null_handle_is_rejected():
     assert lib.wfq_info(None, None, None, None) == wfq.WFQ_EINVAL
     lib.wfq_destroy(None)
     lib.wfq_serve_stop(None)
+
+
+def test_block_product_variant_registry():
+    # every precision has the narrow kernels and the 128 x 256 tile; FP32 and BF16 add the wide
+    # column tiles (their accumulators are half the size of FP64 ones)
+    from paper_2103_00438_amd import wfq
+    names = {p: [n for n, _ in wfq.wfq_tx_variants(p)] for p in ("fp64", "fp32", "bf16")}
+    for p, v in names.items():
+        assert len(v) == len(set(v))
+        assert {"skinny2", "skinny4", "skinny8", "m128n256w8", "m32n128"} <= set(v)
+    wide = {"m96n256w8", "m160n256w8", "m192n256w8", "m192n128w8"}
+    assert wide <= set(names["fp32"]) and wide <= set(names["bf16"])
+    assert not wide & set(names["fp64"])

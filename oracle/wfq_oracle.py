@@ -317,6 +317,69 @@ def gmres(apply, b, restart, tol, maxiter, x0=None):
     return x, dict(iters=iters, cycles=cycles, relres=history[-1], history=history)
 
 
+# --------------------------------------------------------------------------- one Krylov space for all frequencies
+
+def gmres_multishift(apply_A, b, shifts, tol, maxdim):
+    """Unrestarted GMRES for the whole family (A + z I) x = b, z in `shifts`, on one Krylov space.
+
+    The matrix of the scaled system is real and frequency independent; the frequency enters only as
+    the uniform diagonal shift z (the remark after Eq. wfq-a-matrix), and Krylov spaces are invariant
+    under such shifts (the conclusions point to this property for spectra). With the Arnoldi
+    relation A V_k = V_{k+1} Hbar_k of the unshifted matrix,
+        (A + z I) V_k = V_{k+1} (Hbar_k + z Ibar_k),   Ibar_k = [I_k; 0],
+    so the GMRES iterate of every shifted system is x_k = V_k y, with
+        y = argmin_y || beta e_1 - (Hbar_k + z Ibar_k) y ||_2,   beta = ||b||.
+    A and b are real here, so the basis and Hbar are real and only y is complex.
+
+    Arnoldi by modified Gram-Schmidt; the small least-squares problem of each shift not yet
+    converged is solved directly at every step (numpy lstsq), and the shift stops at the first k
+    with residual norm <= tol * beta. Shifts that never get there keep the step-`maxdim` iterate.
+
+    Returns (X [len(shifts)][n] complex, info dict(iters [per shift], relres [per shift estimate])).
+    """
+    b = np.asarray(b, dtype=np.float64)
+    n = b.shape[0]
+    shifts = np.asarray(shifts, dtype=np.complex128)
+    ns = len(shifts)
+    beta = np.linalg.norm(b)
+    X = np.zeros((ns, n), dtype=np.complex128)
+    iters = np.zeros(ns, dtype=np.int64)
+    relres = np.ones(ns)
+    if beta == 0.0:
+        return X, dict(iters=iters, relres=np.zeros(ns))
+    V = np.zeros((maxdim + 1, n))
+    H = np.zeros((maxdim + 1, maxdim))
+    V[0] = b / beta
+    active = list(range(ns))
+    for j in range(maxdim):
+        w = np.asarray(apply_A(V[j]), dtype=np.float64)
+        for i in range(j + 1):
+            H[i, j] = V[i] @ w
+            w = w - H[i, j] * V[i]
+        H[j + 1, j] = np.linalg.norm(w)
+        if H[j + 1, j] > 0.0:
+            V[j + 1] = w / H[j + 1, j]
+        k = j + 1
+        rhs = np.zeros(k + 1, dtype=np.complex128)
+        rhs[0] = beta
+        still = []
+        for q in active:
+            Hz = H[:k + 1, :k].astype(np.complex128)
+            Hz[np.arange(k), np.arange(k)] += shifts[q]
+            y = np.linalg.lstsq(Hz, rhs, rcond=None)[0]
+            res = np.linalg.norm(rhs - Hz @ y)
+            relres[q] = res / beta
+            if res <= tol * beta or H[j + 1, j] == 0.0 or k == maxdim:
+                X[q] = V[:k].T @ y
+                iters[q] = k
+            else:
+                still.append(q)
+        active = still
+        if not active:
+            break
+    return X, dict(iters=iters, relres=relres)
+
+
 # --------------------------------------------------------------------------- J-symmetric QMR from BCG
 
 def qmr_jsym(apply_T, apply_L, z, b, tol, maxiter, x0=None, breakdown=1e-14):
@@ -466,6 +529,14 @@ class Problem:
 
     def solve_gmres(self, omega_eV, direction, restart, tol, maxiter=100000, E0=1.0):
         return gmres(self.apply(self.z(omega_eV)), self.rhs(direction, E0), restart, tol, maxiter)
+
+    def apply_LT(self, x):
+        """x -> L T x: the real frequency-independent part of the operator (minus A of Eq. wfq-a-matrix)."""
+        return self.L @ self.apply_T(x)
+
+    def solve_multishift(self, omegas_eV, direction, tol, maxdim, E0=1.0):
+        z = np.array([self.z(w) for w in np.atleast_1d(omegas_eV)])
+        return gmres_multishift(self.apply_LT, self.rhs(direction, E0), z, tol, maxdim)
 
     def solve_qmr(self, omega_eV, direction, tol, maxiter=100000, E0=1.0):
         return qmr_jsym(self.apply_T, lambda v: self.L @ v, self.z(omega_eV), self.rhs(direction, E0), tol, maxiter)

@@ -277,6 +277,36 @@ def test_gmres_restarted_converges_and_estimates():
     assert P.residual(0.8, [0, 1, 0], x) == pytest.approx(info["relres"], rel=1e-6)
 
 
+def test_multishift_matches_lu_for_every_shift():
+    # one real Krylov space serves every frequency: each shifted solution must be the LU solution
+    P = small_problem(radius=10.0)
+    om = np.array([0.1, 0.3, 0.8, 1.5])
+    for d in ([1, 0, 0], [0, 1, 0]):
+        X, info = P.solve_multishift(om, d, tol=1e-12, maxdim=P.n)
+        assert np.all(info["relres"] <= 1e-12)
+        for q in range(len(om)):
+            ref = P.solve_lu(om[q], d)
+            assert np.linalg.norm(X[q] - ref) <= 1e-9 * np.linalg.norm(ref)
+            assert abs(X[q].sum()) <= 1e-10 * np.linalg.norm(X[q])          # charge conservation
+            assert P.residual(om[q], d, X[q]) <= 1e-11
+
+
+def test_multishift_iterates_are_those_of_gmres_on_each_shifted_matrix():
+    # shift invariance: the shared-basis iterate at step k is the GMRES iterate of (L T + z I)
+    # (complex Arnoldi on the shifted matrix, Givens QR): same step count, same x
+    P = small_problem(radius=10.0)
+    om = np.array([0.2, 0.6, 1.3])
+    X, info = P.solve_multishift(om, [1, 0, 0], tol=1e-8, maxdim=P.n)
+    for q in range(len(om)):
+        x, gi = P.solve_gmres(om[q], [1, 0, 0], restart=P.n, tol=1e-8)
+        assert gi["cycles"] == 1
+        assert abs(int(info["iters"][q]) - gi["iters"]) <= 1
+        if int(info["iters"][q]) == gi["iters"]:
+            assert np.linalg.norm(X[q] - x) <= 1e-9 * np.linalg.norm(x)
+    # different shifts converge at different steps of the one basis
+    assert len(set(int(k) for k in info["iters"])) > 1
+
+
 def test_qmr_matches_lu():
     P = small_problem(radius=10.0)
     for om, d in ((0.3, [1, 0, 0]), (1.2, [0, 1, 0])):

@@ -33,6 +33,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAKS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}   # TFLOP/s, dense MFMA (MI355X)
+HBM_GBPS = 8000.0                                         # GB/s, HBM3E (MI355X)
 HBM_PEAK = 8000.0                                        # GB/s
 # Matrix-free FP32 elements: ~26 VALU instructions per pair, 4 of them quarter-rate transcendentals
 # (3 extra issue slots each) = 38 issue slots; non-packed FP32 VALU issue rate of MI355X =
@@ -48,7 +49,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cnt20k")
-    ap.add_argument("--algorithm", default=None)
+    ap.add_argument("--algorithm", default=None, help="gmres, qmr or msgmres (one shared basis per direction)")
+    ap.add_argument("--shift-dim", type=int, default=0, help="msgmres: largest shared-basis dimension (0 = 400)")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 comparison runs")
@@ -144,6 +146,15 @@ def roofline_of(stats, prec, otf, n, workload=None):
                     kernel=key, launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
                     pairs_per_launch=pairs)
     dom = {"fp32": "tx_gemm_f32", "fp64": "tx_gemm_f64", "bf16": "tx_gemm_bf16"}[prec]
+    if stats.get("tx_skinny", {}).get("ms", 0.0) > stats.get(dom, {}).get("ms", 0.0):
+        # narrow products dominate (one column per direction in multi-shift mode): HBM-bound, T read once
+        st = stats["tx_skinny"]
+        avg_s = st["ms"] / max(1, st["launches"]) / 1e3
+        achieved = st["bytes"] / max(1, st["launches"]) / avg_s / 1e9 if avg_s > 0 else 0.0
+        return dict(bound="hbm", achieved=achieved, peak=HBM_GBPS, unit="GB/s", frac=achieved / HBM_GBPS,
+                    traffic=measured_traffic(workload, "tx_skinny"), kernel="tx_skinny", launches=st["launches"],
+                    avg_launch_ms=st["ms"] / max(1, st["launches"]),
+                    avg_bytes_per_launch=st["bytes"] / max(1, st["launches"]))
     st = stats[dom]
     achieved = st["flops"] / (st["ms"] / 1e3) / 1e12 if st["ms"] > 0 else 0.0
     return dict(bound="mfma", achieved=achieved, peak=PEAKS[prec], unit="TFLOP/s", frac=achieved / PEAKS[prec],
@@ -159,7 +170,10 @@ def bench_batched(args, wl, wfq, torch):
     t0 = time.perf_counter()
     h = wfq.wfq_build(wl.xyz, wl.params, t_mode=wl.t_mode, store=store, device=0)
     build_s = time.perf_counter() - t0
-    opts = dict(restart=wl.restart, precision=prec, algorithm=algo, progress=wl.n > 50000, max_iter=args.max_iter)
+    opts = dict(restart=wl.restart, precision=prec, algorithm=algo, progress=wl.n > 50000, max_iter=args.max_iter,
+                shift_dim=args.shift_dim)
+    # FP64 references: the same solver, except that multi-shift is checked against batched GMRES
+    ref_algo = "gmres" if algo == "msgmres" else algo
     tune = None
     tune_s = 0.0
     S = wl.n_systems
@@ -208,14 +222,14 @@ def bench_batched(args, wl, wfq, torch):
         aref = np.zeros((len(sel), 3), dtype=complex)
         if len(sel) == S:
             ref = wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=True, restart=wl.restart,
-                                precision="fp64", algorithm=algo, progress=wl.n > 50000)
+                                precision="fp64", algorithm=ref_algo, progress=wl.n > 50000)
             qref = ref["q"].reshape(S, wl.n)
             aref = ref["alpha"].reshape(S, 3)
         else:
             for q, s in enumerate(sel):
                 a, k = divmod(s, len(wl.dirs))
                 r1 = wfq.wfq_solve(h, wl.omegas_eV[a:a + 1], wl.dirs[k:k + 1], wl.tol, want_q=True,
-                                   restart=wl.restart, precision="fp64", algorithm=algo, progress=wl.n > 50000)
+                                   restart=wl.restart, precision="fp64", algorithm=ref_algo, progress=wl.n > 50000)
                 qref[q] = r1["q"][0, 0]
                 aref[q] = r1["alpha"][0, 0]
         t_ref = time.perf_counter() - t0
@@ -233,7 +247,7 @@ def bench_batched(args, wl, wfq, torch):
         for s in samp:
             a, k = divmod(s, len(wl.dirs))
             wfq.wfq_solve(h, wl.omegas_eV[a:a + 1], wl.dirs[k:k + 1], wl.tol, want_q=False,
-                          restart=wl.restart, precision="fp64", algorithm=algo, progress=wl.n > 50000)
+                          restart=wl.restart, precision="fp64", algorithm=ref_algo, progress=wl.n > 50000)
         t_pf = (time.perf_counter() - t0) / len(samp)
         extra.update(fp64_per_frequency_solves_per_s=1.0 / t_pf, speedup_vs_fp64_per_frequency=value * t_pf,
                      per_frequency_sample=f"{len(samp)} systems, one per solve")

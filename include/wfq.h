@@ -59,6 +59,9 @@ extern "C" {
 
 #define WFQ_GMRES      0      /* restarted GMRES(m), Saad & Schultz (Section "Solution strategies") */
 #define WFQ_QMR        1      /* J-symmetric QMR from BCG with J = T, no look-ahead (same section) */
+#define WFQ_MSGMRES    2      /* multi-shift GMRES: one real Krylov basis of L T per field direction
+                                 serves every frequency (the frequency is only the diagonal shift z of
+                                 Eq. wfq-a-matrix; shift invariance of Krylov spaces, conclusions) */
 
 #define WFQ_TMODE_AUTO    0   /* stored T when it fits the budget, else on the fly */
 #define WFQ_TMODE_STORED  1   /* dense T kept in device memory */
@@ -93,8 +96,9 @@ typedef struct {
 } wfq_params;
 
 typedef struct {
-    int32_t algorithm;   /* WFQ_GMRES or WFQ_QMR */
-    int32_t restart;     /* GMRES: Krylov dimension m per cycle (1..256); QMR: steps between FP64 checks (>= 1) */
+    int32_t algorithm;   /* WFQ_GMRES, WFQ_QMR or WFQ_MSGMRES */
+    int32_t restart;     /* GMRES and MSGMRES: Krylov dimension m per refinement cycle (1..256);
+                            QMR: steps between FP64 checks (>= 1) */
     int32_t max_iter;    /* cap on T products per system (inner iterations); > 0 */
     int32_t precision;   /* WFQ_PREC_*: precision of T inside the iterations (FP64 refinement always) */
     double  E0;          /* field amplitude (atomic units); 0 means 1 */
@@ -102,6 +106,11 @@ typedef struct {
     int32_t timing;      /* nonzero: time every kernel launch with HIP events (wfq_kernel_stats) */
     int32_t escalate;    /* nonzero: a system whose FP64 residual stalls moves to the next precision */
     int32_t progress;    /* nonzero: one line on stderr per refinement point and every 10 inner steps */
+    int32_t shift_dim;   /* MSGMRES: largest dimension of the shared basis (0 = 400, at most 4096).
+                            Per direction the Arnoldi process runs on the real matrix L T from b_k until
+                            every frequency's shifted least-squares residual is <= tol ||b_k|| or the
+                            dimension is reached; each system then continues from that iterate in
+                            batched GMRES(restart) with FP64 refinement (usually: one FP64 residual). */
 } wfq_solve_opts;
 
 typedef struct {

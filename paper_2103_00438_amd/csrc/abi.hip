@@ -69,9 +69,11 @@ void check_device(int device) {
 
 void check_opts(const wfq_solve_opts* o) {
     if (!o) fail(WFQ_EINVAL, "opts is NULL");
-    if (o->algorithm != WFQ_GMRES && o->algorithm != WFQ_QMR) fail(WFQ_EINVAL, "unknown algorithm");
+    if (o->algorithm != WFQ_GMRES && o->algorithm != WFQ_QMR && o->algorithm != WFQ_MSGMRES)
+        fail(WFQ_EINVAL, "unknown algorithm");
     if (o->restart < 1) fail(WFQ_EINVAL, "restart must be >= 1");
-    if (o->algorithm == WFQ_GMRES && o->restart > 256) fail(WFQ_EINVAL, "GMRES restart must be in [1, 256]");
+    if (o->algorithm != WFQ_QMR && o->restart > 256) fail(WFQ_EINVAL, "GMRES restart must be in [1, 256]");
+    if (o->shift_dim < 0 || o->shift_dim > 4096) fail(WFQ_EINVAL, "shift_dim must be in [0, 4096]");
     if (o->max_iter < 1) fail(WFQ_EINVAL, "max_iter must be >= 1");
     if (o->precision != WFQ_PREC_FP64 && o->precision != WFQ_PREC_FP32 && o->precision != WFQ_PREC_BF16)
         fail(WFQ_EINVAL, "unknown precision");

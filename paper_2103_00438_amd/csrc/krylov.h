@@ -117,4 +117,38 @@ void qmr_restart(const int* sys, int nsys, const Basis& Q, hipStream_t st);
 // out[s] = sum_b partial[s][b]
 void reduce_complex(const int* sys, int nsys, const double2* partial, int nb, double2* out, hipStream_t st);
 
+// ---- multi-shift GMRES (mshift.hip): one real Arnoldi basis per field direction, shared by the
+// frequencies of that direction. Real basis of direction d, slot j at V + (d * mdim1 + j) * npad;
+// `dirs` lists the ndir directions a launch works on; partial / h arrays hold pslots entries per
+// direction; Hessenberg column j of direction d at H + (d * m + j) * (m + 1).
+constexpr int kMsGroup = 8;   // systems per group in ms_xupdate
+// X[c] = cast(V(d_c, j) * scale[d_c]) and V(d_c, j) *= scale[d_c]
+void ms_pack(int prec, double* V, int64_t npad, int mdim1, int j, const int* dirs, int ndir, const double* scale,
+             void* X, int64_t ld, hipStream_t st);
+// V(d_c, jdst) = L Y[c]
+void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* dirs, int ndir, double* V,
+             int mdim1, int jdst, hipStream_t st);
+// partial[d][i][wc] = chunk sums of V(d, i) . V(d, jw), i < nvec; self_norm: slot nvec = ||V(d, jw)||^2
+void ms_dot(const double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
+            double* partial, int pslots, bool self_norm, hipStream_t st);
+// h[d][i] = sum over chunks of partial[d][i], i < count
+void ms_reduce(const int* dirs, int ndir, const double* partial, int pslots, int64_t n, int count, double* h,
+               hipStream_t st);
+// V(d, jw) -= sum_{i < nvec} h[d][i] V(d, i); norm (may be NULL): chunk sums of ||V(d, jw)||^2 [d][nwc]
+void ms_update(double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
+               const double* h, int pslots, double* norm, hipStream_t st);
+// Hessenberg column j from the two Gram-Schmidt passes and the norm; inv_h[d] = 1 / H_{j+1,j}
+void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const double* h2, int pslots,
+             const double* norm, int64_t n, double* H, double* inv_h, hipStream_t st);
+// Givens step j of each listed system on Hbar + z Ibar of its direction (flags as in givens_step)
+void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const double2* z, const double* H, double* cs,
+               double2* sn, double2* g, double2* R, int64_t rstride, double* est, const double* tol_abs, int* flags,
+               hipStream_t st);
+// y = R^-1 g over k[s] columns; cond = max|R_ii| / min|R_ii|
+void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t rstride, const double2* g,
+              double2* y, double* cond, hipStream_t st);
+// x(s) = V(d, 0..k[s]-1) y[s] for groups of kMsGroup systems (grp_sys entries -1 = none)
+void ms_xupdate(const double* V, int64_t n, int64_t npad, int mdim1, const int* grp_sys, const int* grp_dir, int ngrp,
+                const int* ksteps, const double2* y, int m, const Basis& X, hipStream_t st);
+
 }  // namespace wfq

@@ -1,0 +1,394 @@
+// Multi-shift GMRES: one Krylov basis for every frequency of a field direction.
+//
+// The scaled system (L T + z I) q = b_k has a real, frequency-independent matrix L T; the frequency
+// only enters as the uniform complex diagonal shift z (arXiv 2103.00438, the remark after Eq.
+// wfq-a-matrix), and b_k = E0 L r_k does not depend on it. Krylov spaces are invariant under such
+// shifts (the conclusions point to this property for spectra): with the Arnoldi relation
+// A V_k = V_{k+1} Hbar_k of A = L T started from b_k,
+//     (A + z I) V_k = V_{k+1} (Hbar_k + z Ibar_k),   Ibar_k = [I_k; 0],
+// so the GMRES iterate of every shifted system is x = V_k y_z with y_z the least-squares solution of
+// (Hbar_k + z Ibar_k) y ~ ||b_k|| e_1. A and b_k are real, hence V and Hbar are real: one real
+// Arnoldi process per direction (one T product on a real vector per step, shared by all
+// frequencies) and one small complex Givens recurrence per (frequency, direction) system.
+//
+// Layouts: basis of direction d, slot j at V + (d * mdim1 + j) * npad (FP64, padding rows zero);
+// Hessenberg column j of direction d at H + (d * m + j) * (m + 1) (entries 0..j+1); per-system
+// rotations cs/sn [S][m], g [S][m+1], R packed by columns (column j at offset j (j + 1) / 2).
+#include "device_util.h"
+#include "krylov.h"
+
+namespace wfq {
+
+namespace {
+
+__device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ inline double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ inline double2 cscale(double c, double2 a) { return make_double2(c * a.x, c * a.y); }
+__device__ inline double cabs(double2 a) { return hypot(a.x, a.y); }
+__device__ inline double2 cdiv(double2 a, double2 b) {
+    const double d = b.x * b.x + b.y * b.y;
+    return make_double2((a.x * b.x + a.y * b.y) / d, (a.y * b.x - a.x * b.y) / d);
+}
+
+__device__ inline double* slot(double* V, int64_t npad, int mdim1, int d, int j) {
+    return V + ((int64_t)d * mdim1 + j) * npad;
+}
+
+// X[c][i] = cast(v) with v = V(d_c, j)[i] * scale[d_c], which is also written back (normalises the
+// new basis vector on its way into the product).
+template <typename E>
+__global__ void __launch_bounds__(256) ms_pack_kernel(double* __restrict__ V, int64_t npad, int mdim1, int j,
+                                                      const int* __restrict__ dirs, const double* __restrict__ scale,
+                                                      E* __restrict__ X, int64_t ld) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    const int d = dirs[c];
+    double* v = slot(V, npad, mdim1, d, j);
+    const double a = v[i] * scale[d];
+    v[i] = a;
+    X[(int64_t)c * ld + i] = cast_from_double<E>(a);
+}
+
+// V(d_c, jdst) = L Y[c] (real ELL rows; padding rows get 0)
+template <typename YE>
+__global__ void __launch_bounds__(256) ms_spmm_kernel(int64_t n, int64_t npad, int w, const int32_t* __restrict__ ecol,
+                                                      const double* __restrict__ eval, const YE* __restrict__ Y,
+                                                      int64_t ld, const int* __restrict__ dirs, double* __restrict__ V,
+                                                      int mdim1, int jdst) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    double acc = 0.0;
+    if (i < n) {
+        const YE* y = Y + (int64_t)c * ld;
+#pragma unroll 4
+        for (int e = 0; e < w; ++e) acc += eval[(int64_t)e * npad + i] * widen(y[ecol[(int64_t)e * npad + i]]);
+    }
+    slot(V, npad, mdim1, dirs[c], jdst)[i] = acc;
+}
+
+// partial[d][i][wc] = sum over wave chunk wc of V(d, i) * V(d, jw) for i < nvec; with self_norm
+// also partial[d][nvec][wc] = sum of V(d, jw)^2. One wave per 512-row chunk, fixed order.
+__global__ void __launch_bounds__(256) ms_dot_kernel(const double* __restrict__ V, int64_t n, int64_t npad, int mdim1,
+                                                     int nvec, int jw, const int* __restrict__ dirs,
+                                                     double* __restrict__ partial, int pslots, int64_t nwc,
+                                                     int self_norm) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
+    if (wc >= nwc) return;
+    const int d = dirs[blockIdx.y];
+    const double* w = V + ((int64_t)d * mdim1 + jw) * npad;
+    const int64_t row0 = wc * kWaveRows + lane;
+    double x[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        x[r] = row < n ? w[row] : 0.0;
+    }
+    double* out = partial + (int64_t)d * pslots * nwc;
+    for (int i = 0; i < nvec; ++i) {
+        const double* v = V + ((int64_t)d * mdim1 + i) * npad;
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t row = row0 + 64 * r;
+            if (row < n) s += v[row] * x[r];
+        }
+        s = wave_sum(s);
+        if (lane == 0) out[(int64_t)i * nwc + wc] = s;
+    }
+    if (self_norm) {
+        double s = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) s += x[r] * x[r];
+        s = wave_sum(s);
+        if (lane == 0) out[(int64_t)nvec * nwc + wc] = s;
+    }
+}
+
+// h[d][i] = sum_wc partial[d][i][wc], i < count (in chunk order)
+__global__ void ms_reduce_kernel(const int* __restrict__ dirs, const double* __restrict__ partial, int pslots,
+                                 int64_t nwc, int count, double* __restrict__ h) {
+    const int d = dirs[blockIdx.x];
+    for (int i = threadIdx.x; i < count; i += blockDim.x) {
+        const double* p = partial + ((int64_t)d * pslots + i) * nwc;
+        double s = 0.0;
+        for (int64_t q = 0; q < nwc; ++q) s += p[q];
+        h[(int64_t)d * pslots + i] = s;
+    }
+}
+
+// V(d, jw) -= sum_{i < nvec} h[d][i] V(d, i); with norm != NULL also norm[d][wc] = partial ||V(d, jw)||^2
+__global__ void __launch_bounds__(256) ms_update_kernel(double* __restrict__ V, int64_t n, int64_t npad, int mdim1,
+                                                        int nvec, int jw, const int* __restrict__ dirs,
+                                                        const double* __restrict__ h, int pslots,
+                                                        double* __restrict__ norm, int64_t nwc) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
+    if (wc >= nwc) return;
+    const int d = dirs[blockIdx.y];
+    double* w = V + ((int64_t)d * mdim1 + jw) * npad;
+    const int64_t row0 = wc * kWaveRows + lane;
+    double x[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        x[r] = row < n ? w[row] : 0.0;
+    }
+    const double* hd = h + (int64_t)d * pslots;
+    for (int i = 0; i < nvec; ++i) {
+        const double c = hd[i];
+        const double* v = V + ((int64_t)d * mdim1 + i) * npad;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t row = row0 + 64 * r;
+            if (row < n) x[r] -= c * v[row];
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        if (row < n) {
+            w[row] = x[r];
+            s += x[r] * x[r];
+        }
+    }
+    if (norm) {
+        s = wave_sum(s);
+        if (lane == 0) norm[(int64_t)d * nwc + wc] = s;
+    }
+}
+
+// Hessenberg column j of direction d: H_ij = h1_i + h2_i (two Gram-Schmidt passes), H_{j+1,j} = ||w||;
+// inv_h[d] = 1 / ||w|| normalises the next basis vector.
+__global__ void ms_hcol_kernel(const int* __restrict__ dirs, int j, int m, const double* __restrict__ h1,
+                               const double* __restrict__ h2, int pslots, const double* __restrict__ norm, int64_t nwc,
+                               double* __restrict__ H, double* __restrict__ inv_h) {
+    const int d = dirs[blockIdx.x];
+    double* col = H + ((int64_t)d * m + j) * (m + 1);
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h1[(int64_t)d * pslots + i] + h2[(int64_t)d * pslots + i];
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int64_t q = 0; q < nwc; ++q) s += norm[(int64_t)d * nwc + q];
+        const double hn = sqrt(s);
+        col[j + 1] = hn;
+        inv_h[d] = hn > 0.0 ? 1.0 / hn : 0.0;
+    }
+}
+
+// One Givens step of system s on column j of Hbar + z Ibar (direction sdir[s], shift z[s]): the
+// rotations of the earlier steps are applied, a new rotation zeroes the subdiagonal, the rotated
+// column is stored as column j of R, and |g_{j+1}| is the residual norm of the shifted system.
+__global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, int m, const int* __restrict__ sdir,
+                                 const double2* __restrict__ z, const double* __restrict__ H, double* __restrict__ cs,
+                                 double2* __restrict__ sn, double2* __restrict__ g, double2* __restrict__ R,
+                                 int64_t rstride, double* __restrict__ est, const double* __restrict__ tol_abs,
+                                 int* __restrict__ flags) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsys) return;
+    const int s = sys[k];
+    const double* hc = H + ((int64_t)sdir[s] * m + j) * (m + 1);
+    double2* col = R + (int64_t)s * rstride + (int64_t)j * (j + 1) / 2;
+    for (int i = 0; i <= j; ++i) col[i] = make_double2(hc[i], 0.0);
+    col[j] = cadd(col[j], z[s]);
+    const double hn = hc[j + 1];
+    double* c_s = cs + (int64_t)s * m;
+    double2* s_s = sn + (int64_t)s * m;
+    for (int i = 0; i < j; ++i) {
+        const double2 x = col[i], y = col[i + 1];
+        col[i] = cadd(cscale(c_s[i], x), cmul(s_s[i], y));
+        col[i + 1] = cadd(cscale(-1.0, cmul(cconj(s_s[i]), x)), cscale(c_s[i], y));
+    }
+    // rotation [c s; -conj(s) c] with c real zeroing hn below col[j]
+    const double2 x = col[j];
+    const double ax = cabs(x);
+    double c;
+    double2 sv;
+    if (hn == 0.0) {
+        c = 1.0;
+        sv = make_double2(0.0, 0.0);
+    } else if (ax == 0.0) {
+        c = 0.0;
+        sv = make_double2(1.0, 0.0);
+    } else {
+        const double nu = hypot(ax, hn);
+        c = ax / nu;
+        sv = make_double2(x.x / ax * hn / nu, x.y / ax * hn / nu);
+    }
+    c_s[j] = c;
+    s_s[j] = sv;
+    col[j] = cadd(cscale(c, x), cscale(hn, sv));
+    double2* gs = g + (int64_t)s * (m + 1);
+    const double2 gj = gs[j];
+    gs[j + 1] = cscale(-1.0, cmul(cconj(sv), gj));
+    gs[j] = cscale(c, gj);
+    const double e = cabs(gs[j + 1]);
+    est[s] = e;
+    int f = 0;
+    if (e <= tol_abs[s]) f |= 1;
+    if (hn <= 1e-14 * cabs(col[j])) f |= 2;   // the Krylov space is invariant: the iterate is exact
+    if (!(e == e) || !(hn == hn)) f |= 4;
+    flags[s] = f;
+}
+
+// y = R^-1 g over the first k[s] columns (back substitution on the packed R); cond[s] =
+// max |R_ii| / min |R_ii|.
+__global__ void ms_solve_kernel(const int* __restrict__ sys, int nsys, const int* __restrict__ ksteps, int m,
+                                const double2* __restrict__ R, int64_t rstride, const double2* __restrict__ g,
+                                double2* __restrict__ y, double* __restrict__ cond) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsys) return;
+    const int s = sys[k];
+    const int K = ksteps[s];
+    const double2* Rs = R + (int64_t)s * rstride;
+    const double2* gs = g + (int64_t)s * (m + 1);
+    double2* ys = y + (int64_t)s * m;
+    double dmax = 0.0, dmin = 1e300;
+    for (int i = K - 1; i >= 0; --i) {
+        double2 acc = gs[i];
+        for (int c = i + 1; c < K; ++c) acc = csub(acc, cmul(Rs[(int64_t)c * (c + 1) / 2 + i], ys[c]));
+        const double2 rii = Rs[(int64_t)i * (i + 1) / 2 + i];
+        ys[i] = cdiv(acc, rii);
+        const double a = cabs(rii);
+        dmax = fmax(dmax, a);
+        dmin = fmin(dmin, a);
+    }
+    cond[s] = K > 0 ? dmax / dmin : 1.0;
+}
+
+// x(s) = sum_{i < k[s]} y[s][i] V(d, i) for groups of up to 8 systems of one direction (the basis
+// is read once per group); rows >= n and systems with k = 0 get 0.
+__global__ void __launch_bounds__(256) ms_xupdate_kernel(const double* __restrict__ V, int64_t n, int64_t npad,
+                                                         int mdim1, const int* __restrict__ grp_sys,
+                                                         const int* __restrict__ grp_dir, const int* __restrict__ ksteps,
+                                                         const double2* __restrict__ y, int m, Basis X) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int gi = blockIdx.y;
+    const int d = grp_dir[gi];
+    int sid[kMsGroup], kk[kMsGroup];
+    int kmax = 0;
+#pragma unroll
+    for (int t = 0; t < kMsGroup; ++t) {
+        sid[t] = grp_sys[gi * kMsGroup + t];
+        kk[t] = sid[t] >= 0 ? ksteps[sid[t]] : 0;
+        kmax = max(kmax, kk[t]);
+    }
+    double ar[kMsGroup], ai[kMsGroup];
+#pragma unroll
+    for (int t = 0; t < kMsGroup; ++t) ar[t] = ai[t] = 0.0;
+    if (i < n) {
+        for (int c = 0; c < kmax; ++c) {
+            const double v = V[((int64_t)d * mdim1 + c) * npad + i];
+#pragma unroll
+            for (int t = 0; t < kMsGroup; ++t)
+                if (c < kk[t]) {
+                    const double2 yc = y[(int64_t)sid[t] * m + c];
+                    ar[t] += yc.x * v;
+                    ai[t] += yc.y * v;
+                }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < kMsGroup; ++t)
+        if (sid[t] >= 0) {
+            double* xr = X.base + (int64_t)sid[t] * X.sys_stride;
+            xr[i] = ar[t];
+            xr[i + X.npad] = ai[t];
+        }
+}
+
+}  // namespace
+
+void ms_pack(int prec, double* V, int64_t npad, int mdim1, int j, const int* dirs, int ndir, const double* scale,
+             void* X, int64_t ld, hipStream_t st) {
+    if (ndir <= 0) return;
+    dim3 grd((unsigned)(npad / 256), (unsigned)ndir);
+    if (prec == WFQ_PREC_FP64)
+        hipLaunchKernelGGL(ms_pack_kernel<double>, grd, dim3(256), 0, st, V, npad, mdim1, j, dirs, scale,
+                           static_cast<double*>(X), ld);
+    else if (prec == WFQ_PREC_FP32)
+        hipLaunchKernelGGL(ms_pack_kernel<float>, grd, dim3(256), 0, st, V, npad, mdim1, j, dirs, scale,
+                           static_cast<float*>(X), ld);
+    else
+        hipLaunchKernelGGL(ms_pack_kernel<uint16_t>, grd, dim3(256), 0, st, V, npad, mdim1, j, dirs, scale,
+                           static_cast<uint16_t*>(X), ld);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* dirs, int ndir, double* V,
+             int mdim1, int jdst, hipStream_t st) {
+    if (ndir <= 0) return;
+    dim3 grd((unsigned)(S.npad / 256), (unsigned)ndir);
+    if (y_is_f64)
+        hipLaunchKernelGGL(ms_spmm_kernel<double>, grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col, S.ell_val,
+                           static_cast<const double*>(Y), ld, dirs, V, mdim1, jdst);
+    else
+        hipLaunchKernelGGL(ms_spmm_kernel<float>, grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col, S.ell_val,
+                           static_cast<const float*>(Y), ld, dirs, V, mdim1, jdst);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_dot(const double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
+            double* partial, int pslots, bool self_norm, hipStream_t st) {
+    if (ndir <= 0) return;
+    const int64_t nwc = wave_chunks(n);
+    dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)ndir);
+    hipLaunchKernelGGL(ms_dot_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, nvec, jw, dirs, partial, pslots, nwc,
+                       (int)self_norm);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_reduce(const int* dirs, int ndir, const double* partial, int pslots, int64_t n, int count, double* h,
+               hipStream_t st) {
+    if (ndir <= 0 || count <= 0) return;
+    hipLaunchKernelGGL(ms_reduce_kernel, dim3((unsigned)ndir), dim3(128), 0, st, dirs, partial, pslots,
+                       wave_chunks(n), count, h);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_update(double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
+               const double* h, int pslots, double* norm, hipStream_t st) {
+    if (ndir <= 0) return;
+    const int64_t nwc = wave_chunks(n);
+    dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)ndir);
+    hipLaunchKernelGGL(ms_update_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, nvec, jw, dirs, h, pslots, norm,
+                       nwc);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const double* h2, int pslots,
+             const double* norm, int64_t n, double* H, double* inv_h, hipStream_t st) {
+    if (ndir <= 0) return;
+    hipLaunchKernelGGL(ms_hcol_kernel, dim3((unsigned)ndir), dim3(128), 0, st, dirs, j, m, h1, h2, pslots, norm,
+                       wave_chunks(n), H, inv_h);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const double2* z, const double* H, double* cs,
+               double2* sn, double2* g, double2* R, int64_t rstride, double* est, const double* tol_abs, int* flags,
+               hipStream_t st) {
+    if (nsys <= 0) return;
+    hipLaunchKernelGGL(ms_givens_kernel, dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st, sys, nsys, j, m, sdir, z,
+                       H, cs, sn, g, R, rstride, est, tol_abs, flags);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t rstride, const double2* g,
+              double2* y, double* cond, hipStream_t st) {
+    if (nsys <= 0) return;
+    hipLaunchKernelGGL(ms_solve_kernel, dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st, sys, nsys, ksteps, m, R,
+                       rstride, g, y, cond);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_xupdate(const double* V, int64_t n, int64_t npad, int mdim1, const int* grp_sys, const int* grp_dir, int ngrp,
+                const int* ksteps, const double2* y, int m, const Basis& X, hipStream_t st) {
+    if (ngrp <= 0) return;
+    dim3 grd((unsigned)(npad / 256), (unsigned)ngrp);
+    hipLaunchKernelGGL(ms_xupdate_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, grp_sys, grp_dir, ksteps, y, m, X);
+    WFQ_CHECK_LAUNCH();
+}
+
+}  // namespace wfq

@@ -200,7 +200,8 @@ int wfq_serve(const wfq_serve_cfg* c, wfq_server** out) {
         return WFQ_EINVAL;
     }
     if (c->opts.restart < 1 || c->opts.max_iter < 1 || c->opts.precision < 0 || c->opts.precision > 2 ||
-        (c->opts.algorithm != WFQ_GMRES && c->opts.algorithm != WFQ_QMR)) {
+        (c->opts.algorithm != WFQ_GMRES && c->opts.algorithm != WFQ_QMR && c->opts.algorithm != WFQ_MSGMRES) ||
+        c->opts.shift_dim < 0 || c->opts.shift_dim > 4096 || (c->opts.algorithm != WFQ_QMR && c->opts.restart > 256)) {
         wfq::set_error(WFQ_EINVAL, "invalid solver options");
         return WFQ_EINVAL;
     }

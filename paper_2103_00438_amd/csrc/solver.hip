@@ -494,6 +494,199 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
     }
 }
 
+// ---- multi-shift GMRES: one real Arnoldi basis of L T per direction for all frequencies
+
+int ms_dim(const wfq_solve_opts& o, int64_t n) {
+    const int64_t m = o.shift_dim > 0 ? o.shift_dim : 400;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(m, std::min<int64_t>(n, o.max_iter)));
+}
+
+uint64_t ms_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_dir) {
+    const uint64_t m = ms_dim(o, S.n), np = S.npad, nwc = wave_chunks(S.n);
+    uint64_t b = (uint64_t)n_dir * (m + 1) * np * 8;            // bases
+    b += (uint64_t)n_dir * m * (m + 1) * 8;                      // Hessenberg
+    b += (uint64_t)n_dir * ((m + 2) * nwc * 8 + nwc * 8 + (m + 2) * 16);   // partials, h1, h2
+    b += (uint64_t)B * (m * (m + 1) / 2) * 16;                   // R, packed
+    b += (uint64_t)B * (m * 40 + (m + 1) * 16 + 64);             // cs, sn, y, g, scalars
+    return b + (1u << 20);
+}
+
+// Runs the shared-basis phase for the systems of one batch and leaves each system's iterate in
+// w.Xb (zero where the phase could not help); ss[s].iters = steps of the shared basis it used.
+void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, double tol, const wfq_solve_opts& o,
+                   Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0) {
+    const int B = (int)ss.size();
+    const int nd = w.n_dir;
+    const int m = ms_dim(o, S.n);
+    const int mdim1 = m + 1, pslots = m + 2;
+    const int64_t n = S.n, np = S.npad, nwc = wave_chunks(S.n);
+    const int prec = o.precision;
+    const int64_t rstride = (int64_t)m * (m + 1) / 2;
+    const double dn = (double)n;
+    DevArray<double> V, H, part, h1, h2, nrm, inv_h, cs, est, tol_abs, cond;
+    DevArray<double2> sn, g, R, y, z;
+    DevArray<int> dirs, sdir, sys, flags, ksteps, grp_sys, grp_dir;
+    V.alloc((size_t)nd * mdim1 * np);
+    H.alloc((size_t)nd * m * (m + 1));
+    part.alloc((size_t)nd * pslots * nwc);
+    h1.alloc((size_t)nd * pslots);
+    h2.alloc((size_t)nd * pslots);
+    nrm.alloc((size_t)nd * nwc);
+    inv_h.alloc(nd);
+    cs.alloc((size_t)B * m);
+    sn.alloc((size_t)B * m);
+    g.alloc((size_t)B * (m + 1));
+    R.alloc((size_t)B * rstride);
+    y.alloc((size_t)B * m);
+    z.alloc(B);
+    est.alloc(B);
+    tol_abs.alloc(B);
+    cond.alloc(B);
+    dirs.alloc(nd);
+    sdir.alloc(B);
+    sys.alloc(B);
+    flags.alloc(B);
+    ksteps.alloc(B);
+    PinnedArray<int> h_dirs, h_sys, h_k;
+    PinnedArray<double> h_nrm;
+    h_dirs.alloc(nd);
+    h_sys.alloc(B);
+    h_k.alloc(B);
+    h_nrm.alloc((size_t)nd * pslots);
+
+    // v_0 of direction d is b_d / ||b_d||
+    for (int d = 0; d < nd; ++d) {
+        WFQ_HIP(hipMemcpyAsync(V.p + (size_t)d * mdim1 * np, w.b.p + (size_t)d * np, np * sizeof(double),
+                               hipMemcpyDeviceToDevice, st));
+        h_dirs.p[d] = d;
+    }
+    WFQ_HIP(hipMemcpyAsync(dirs.p, h_dirs.p, nd * sizeof(int), hipMemcpyHostToDevice, st));
+    ms_dot(V.p, n, np, mdim1, 0, 0, dirs.p, nd, part.p, pslots, true, st);
+    ms_reduce(dirs.p, nd, part.p, pslots, n, 1, h1.p, st);
+    WFQ_HIP(hipMemcpyAsync(h_nrm.p, h1.p, (size_t)nd * pslots * sizeof(double), hipMemcpyDeviceToHost, st));
+    WFQ_HIP(hipStreamSynchronize(st));
+    std::vector<double> beta(nd), invb(nd);
+    for (int d = 0; d < nd; ++d) {
+        beta[d] = std::sqrt(h_nrm.p[(size_t)d * pslots]);
+        invb[d] = beta[d] > 0.0 ? 1.0 / beta[d] : 0.0;
+    }
+    {
+        std::vector<double2> gh((size_t)B * (m + 1), make_double2(0.0, 0.0)), zh(B);
+        std::vector<double> th(B);
+        std::vector<int> dh(B);
+        for (int s = 0; s < B; ++s) {
+            gh[(size_t)s * (m + 1)] = make_double2(beta[ss[s].dir], 0.0);
+            th[s] = tol * beta[ss[s].dir];
+            dh[s] = ss[s].dir;
+            zh[s] = ss[s].z;
+        }
+        WFQ_HIP(hipMemcpyAsync(g.p, gh.data(), gh.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(tol_abs.p, th.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(sdir.p, dh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(z.p, zh.data(), B * sizeof(double2), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(inv_h.p, invb.data(), nd * sizeof(double), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipStreamSynchronize(st));
+    }
+    std::vector<int> stepping;
+    for (int s = 0; s < B; ++s) {
+        h_k.p[s] = 0;
+        if (!ss[s].done && beta[ss[s].dir] > 0.0) stepping.push_back(s);
+    }
+    for (int j = 0; j < m && !stepping.empty(); ++j) {
+        // directions that still have unconverged systems
+        std::vector<char> used(nd, 0);
+        for (int s : stepping) used[ss[s].dir] = 1;
+        int na = 0;
+        for (int d = 0; d < nd; ++d)
+            if (used[d]) h_dirs.p[na++] = d;
+        WFQ_HIP(hipMemcpyAsync(dirs.p, h_dirs.p, na * sizeof(int), hipMemcpyHostToDevice, st));
+        // w = L T v_j (one real column per direction)
+        tm.begin(st);
+        ms_pack(prec, V.p, np, mdim1, j, dirs.p, na, inv_h.p, x_block(w, prec), np, st);
+        tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(prec)));
+        block_product(S, w, prec, na, tm, st);
+        tm.begin(st);
+        ms_spmm(S, prec == WFQ_PREC_FP64, y_block(w, prec), np, dirs.p, na, V.p, mdim1, j + 1, st);
+        tm.end(st, KC_SPMM, 2.0 * S.nnz * na, 12.0 * S.nnz * na + na * dn * (out_size(prec) + 8));
+        // two classical Gram-Schmidt passes against v_0 .. v_j
+        const double pass = 8.0 * dn * na * (j + 2);
+        tm.begin(st);
+        ms_dot(V.p, n, np, mdim1, j + 1, j + 1, dirs.p, na, part.p, pslots, false, st);
+        ms_reduce(dirs.p, na, part.p, pslots, n, j + 1, h1.p, st);
+        tm.end(st, KC_DOT, 2.0 * dn * na * (j + 1), pass);
+        tm.begin(st);
+        ms_update(V.p, n, np, mdim1, j + 1, j + 1, dirs.p, na, h1.p, pslots, nullptr, st);
+        tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
+        tm.begin(st);
+        ms_dot(V.p, n, np, mdim1, j + 1, j + 1, dirs.p, na, part.p, pslots, false, st);
+        ms_reduce(dirs.p, na, part.p, pslots, n, j + 1, h2.p, st);
+        tm.end(st, KC_DOT, 2.0 * dn * na * (j + 1), pass);
+        tm.begin(st);
+        ms_update(V.p, n, np, mdim1, j + 1, j + 1, dirs.p, na, h2.p, pslots, nrm.p, st);
+        ms_hcol(dirs.p, na, j, m, h1.p, h2.p, pslots, nrm.p, n, H.p, inv_h.p, st);
+        tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
+        // every unconverged frequency of those directions: one Givens step on Hbar + z Ibar
+        const int ns = (int)stepping.size();
+        std::memcpy(h_sys.p, stepping.data(), ns * sizeof(int));
+        WFQ_HIP(hipMemcpyAsync(sys.p, h_sys.p, ns * sizeof(int), hipMemcpyHostToDevice, st));
+        tm.begin(st);
+        ms_givens(sys.p, ns, j, m, sdir.p, z.p, H.p, cs.p, sn.p, g.p, R.p, rstride, est.p, tol_abs.p, flags.p, st);
+        tm.end(st, KC_GIVENS, 0, 0);
+        WFQ_HIP(hipMemcpyAsync(w.h_flags.p, flags.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipMemcpyAsync(w.h_est.p, est.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipStreamSynchronize(st));
+        std::vector<int> next;
+        for (int s : stepping) {
+            const int f = w.h_flags.p[s];
+            if (f & 4) {
+                h_k.p[s] = 0;   // NaN: leave the system to batched GMRES from x = 0
+                continue;
+            }
+            h_k.p[s] = j + 1;
+            ss[s].est_end = w.h_est.p[s];
+            if ((f & 3) == 0) next.push_back(s);
+        }
+        stepping.swap(next);
+        if ((j + 1) % 10 == 0) progress_line(o, "multi-shift", 0, j + 1, stepping.size(), -1.0, t0);
+    }
+    // iterates: y = R^-1 g, x = V y (groups of systems of one direction share the basis reads)
+    std::vector<int> withk;
+    for (int s = 0; s < B; ++s)
+        if (h_k.p[s] > 0) withk.push_back(s);
+    WFQ_HIP(hipMemcpyAsync(ksteps.p, h_k.p, B * sizeof(int), hipMemcpyHostToDevice, st));
+    std::vector<int> gs, gd;
+    for (int d = 0; d < nd; ++d) {
+        std::vector<int> mem;
+        for (int s = 0; s < B; ++s)
+            if (ss[s].dir == d) mem.push_back(s);
+        for (size_t q = 0; q < mem.size(); q += kMsGroup) {
+            for (int t = 0; t < kMsGroup; ++t) gs.push_back(q + t < mem.size() ? mem[q + t] : -1);
+            gd.push_back(d);
+        }
+    }
+    const int ngrp = (int)gd.size();
+    grp_sys.alloc(gs.size());
+    grp_dir.alloc(gd.size());
+    WFQ_HIP(hipMemcpyAsync(grp_sys.p, gs.data(), gs.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    WFQ_HIP(hipMemcpyAsync(grp_dir.p, gd.data(), gd.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    tm.begin(st);
+    if (!withk.empty()) {
+        std::memcpy(h_sys.p, withk.data(), withk.size() * sizeof(int));
+        WFQ_HIP(hipMemcpyAsync(sys.p, h_sys.p, withk.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        ms_solve(sys.p, (int)withk.size(), ksteps.p, m, R.p, rstride, g.p, y.p, cond.p, st);
+    }
+    ms_xupdate(V.p, n, np, mdim1, grp_sys.p, grp_dir.p, ngrp, ksteps.p, y.p, m, w.Xb, st);
+    tm.end(st, KC_XUPDATE, 0, 0);
+    std::vector<double> ch(B, 1.0);
+    if (!withk.empty()) WFQ_HIP(hipMemcpyAsync(ch.data(), cond.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    WFQ_HIP(hipStreamSynchronize(st));
+    for (int s = 0; s < B; ++s) {
+        ss[s].iters += h_k.p[s];
+        if (h_k.p[s] > 0) ss[s].cond = ch[s];
+    }
+    if (o.progress) progress_line(o, "multi-shift done", 0, 0, stepping.size(), -1.0, t0);
+}
+
 // J-symmetric QMR from BCG (J = T) with FP64 refinement every o.restart steps; systems whose Lanczos
 // process breaks down are returned in `broken` (their QMR iterate stays in slot 5) for a GMRES
 // fallback.
@@ -687,6 +880,7 @@ uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_d
     b += (uint64_t)B * mdim * mdim * 16;        // R
     b += (uint64_t)B * (mdim * 64 + 2 * np * 8 / 1);  // small arrays + output staging
     b += std::min<uint64_t>(kSplitWsCap, 7 * mpad * np * 8);   // split-k partial tiles
+    if (o.algorithm == WFQ_MSGMRES) b += ms_bytes(S, o, B, n_dir);
     return b;
 }
 
@@ -741,7 +935,11 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
             ss[s].z = make_double2(-(om * om) / S.W, -(om / S.tau) / S.W);   // z = -(w^2 + i w / tau) / W
             ss[s].prec = prec;
         }
-        if (!qmr) {
+        if (o.algorithm == WFQ_MSGMRES) {
+            // shared-basis phase, then batched GMRES from its iterates (FP64 residual first)
+            msgmres_phase(S, w, ss, tol, o, tm, st, t0);
+            gmres_batch(S, w, ss, tol, o, tm, st, t0, true);
+        } else if (!qmr) {
             gmres_batch(S, w, ss, tol, o, tm, st, t0);
         } else {
             std::vector<int> broken;

@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "OK", 1: "EINVAL", 2: "ENOMEM", 3: "EDEVICE", 4: "ESINGULAR",
                 6: "EBREAKDOWN", 7: "ENUMERIC", 8: "EAGAIN", 9: "EDISCONNECTED", 10: "ENOTFOUND"}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 PREC_NAMES = {v: k for k, v in PREC.items()}
-ALGO = {"gmres": 0, "qmr": 1}
+ALGO = {"gmres": 0, "qmr": 1, "msgmres": 2}
 TMODE = {"auto": 0, "stored": 1, "otf": 2}
 STORE = {"fp64": 1, "fp32": 2, "bf16": 4}
 
@@ -44,7 +44,7 @@ class Params(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("algorithm", C.c_int32), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("E0", C.c_double), ("max_batch", C.c_int32), ("timing", C.c_int32),
-                ("escalate", C.c_int32), ("progress", C.c_int32)]
+                ("escalate", C.c_int32), ("progress", C.c_int32), ("shift_dim", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -214,9 +214,9 @@ def wfq_destroy(h: Handle) -> None:
 
 
 def make_opts(algorithm="gmres", restart=50, max_iter=100000, precision="fp64", E0=1.0, max_batch=0,
-              timing=False, escalate=True, progress=False) -> SolveOpts:
+              timing=False, escalate=True, progress=False, shift_dim=0) -> SolveOpts:
     return SolveOpts(ALGO[algorithm], int(restart), int(max_iter), PREC[precision], float(E0), int(max_batch),
-                     int(bool(timing)), int(bool(escalate)), int(bool(progress)))
+                     int(bool(timing)), int(bool(escalate)), int(bool(progress)), int(shift_dim))
 
 
 def _results(info):

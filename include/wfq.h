@@ -184,6 +184,12 @@ int wfq_export_L(const wfq_handle* h, int64_t* rows, int64_t* cols, double* vals
  * (WFQ_PREC_FP32/BF16 round X to that precision and accumulate in FP32), Y[ncol][n] in double. */
 int wfq_apply_T(wfq_handle* h, int32_t precision, int32_t ncol, const double* X, double* Y);
 
+/* As wfq_apply_T, but through block-product variant `variant` (an index into the list of
+ * wfq_tx_variants for this precision) instead of the automatic choice, so that every shape the
+ * autotuner may pick can be checked. Stored T only; WFQ_EINVAL for an unknown variant, one that
+ * cannot take ncol columns, or a matrix-free handle. */
+int wfq_apply_T_variant(wfq_handle* h, int32_t precision, int32_t variant, int32_t ncol, const double* X, double* Y);
+
 /* Y = (L T + z_s I) X_s for S complex vectors (planar re/im, [S][n] each), T in `precision`. */
 int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t S, const double* z_re, const double* z_im,
                  const double* X_re, const double* X_im, double* Y_re, double* Y_im);

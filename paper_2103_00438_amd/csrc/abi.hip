@@ -281,11 +281,18 @@ int wfq_export_L(const wfq_handle* h, int64_t* rows, int64_t* cols, double* vals
     });
 }
 
-int wfq_apply_T(wfq_handle* h, int32_t precision, int32_t ncol, const double* X, double* Y) {
+namespace {
+// Y = T X in `precision` through the automatic shape choice (variant < 0) or one registered variant.
+int apply_T_impl(wfq_handle* h, int32_t precision, int32_t variant, int32_t ncol, const double* X, double* Y) {
     return guarded([&]() -> int {
         if (!h || !X || !Y || ncol < 1) fail(WFQ_EINVAL, "bad arguments");
         if (precision < 0 || precision > 2) fail(WFQ_EINVAL, "unknown precision");
         Structure& S = h->S;
+        if (variant >= 0) {
+            if (S.t_mode == WFQ_TMODE_OTF) fail(WFQ_EINVAL, "kernel variants apply to a stored T");
+            if (variant >= tx_variant_count(precision)) fail(WFQ_EINVAL, "no such kernel variant");
+            if (ncol > tx_variant_max_ncol(precision, variant)) fail(WFQ_EINVAL, "the variant cannot take that many columns");
+        }
         WFQ_HIP(hipSetDevice(S.device));
         const int64_t np = S.npad, n = S.n;
         const int64_t rows = round_up(ncol, kColPad);
@@ -300,7 +307,10 @@ int wfq_apply_T(wfq_handle* h, int32_t precision, int32_t ncol, const double* X,
         WFQ_HIP(hipMemcpyAsync(dx64, xh.data(), rows * np * 8, hipMemcpyHostToDevice, h->stream));
         convert_from_f64(precision, dx64, dx, rows * np, h->stream);
         std::vector<double> yh((size_t)ncol * np);
-        tx_any(S, precision, dx, dy, ncol, h->stream);
+        if (variant >= 0)
+            tx_variant_run(S, precision, variant, dx, dy, ncol, h->stream);
+        else
+            tx_any(S, precision, dx, dy, ncol, h->stream);
         if (precision == WFQ_PREC_FP64) {
             WFQ_HIP(hipMemcpyAsync(yh.data(), dy, (size_t)ncol * np * 8, hipMemcpyDeviceToHost, h->stream));
         } else {
@@ -318,6 +328,15 @@ int wfq_apply_T(wfq_handle* h, int32_t precision, int32_t ncol, const double* X,
             for (int64_t k = 0; k < n; ++k) Y[(size_t)c * n + S.perm[k]] = yh[(size_t)c * np + k];
         return WFQ_OK;
     });
+}
+}  // namespace
+
+int wfq_apply_T(wfq_handle* h, int32_t precision, int32_t ncol, const double* X, double* Y) {
+    return apply_T_impl(h, precision, -1, ncol, X, Y);
+}
+
+int wfq_apply_T_variant(wfq_handle* h, int32_t precision, int32_t variant, int32_t ncol, const double* X, double* Y) {
+    return apply_T_impl(h, precision, variant, ncol, X, Y);
 }
 
 int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t nsys, const double* z_re, const double* z_im,

@@ -130,6 +130,8 @@ void tx_bf16(const Structure& s, const uint16_t* X, float* Y, int ncol, hipStrea
 const char* tx_variant(int precision, int ncol);
 // T X with the stored copy of T in `prec`, or recomputed on the fly when the structure is matrix-free
 void tx_any(const Structure& s, int prec, const void* X, void* Y, int ncol, hipStream_t st);
+// one registered block-product variant (index as listed by tx_variant_name), stored T only
+void tx_variant_run(const Structure& s, int prec, int var, const void* X, void* Y, int ncol, hipStream_t st);
 int tx_variant_count(int precision);
 const char* tx_variant_name(int precision, int k);
 int tx_variant_max_ncol(int precision, int k);

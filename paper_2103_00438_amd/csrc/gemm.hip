@@ -431,9 +431,8 @@ void launch_mfma(const Structure& s, const void* X, const void* T, void* Y, int6
     }
 }
 
-template <int P, int NC>
+template <int P, int NC, int R = 4>
 void launch_skinny(const Structure&, const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st) {
-    constexpr int R = 4;
     using elem = typename Prec<P>::elem;
     using out = typename Prec<P>::out;
     hipLaunchKernelGGL((tx_skinny_kernel<P, NC, R>), dim3((unsigned)(ld / (4 * R))), dim3(256), 0, st,
@@ -447,6 +446,8 @@ const std::vector<Variant>& variants() {
         {"skinny2", 0, 4, 2, launch_skinny<P, 2>},
         {"skinny4", 0, 4, 4, launch_skinny<P, 4>},
         {"skinny8", 0, 4, 8, launch_skinny<P, 8>},
+        {"skinny2r8", 0, 8, 2, launch_skinny<P, 2, 8>},
+        {"skinny4r8", 0, 8, 4, launch_skinny<P, 4, 8>},
         {"m32n128", 32, 128, 1 << 30, launch_mfma<P, 2, 2, 1, 4, 128, 2>},
         {"m64n128", 64, 128, 1 << 30, launch_mfma<P, 4, 2, 1, 4, 128, 2>},
         {"m128n128", 128, 128, 1 << 30, launch_mfma<P, 4, 4, 2, 2, 128, OCC2>},
@@ -497,16 +498,16 @@ int find_variant(int prec, const char* name) {
 // Built-in choice when no tuning result covers ncol: the fastest shapes measured on MI355X for a
 // 20 000-atom T, per precision and column count.
 int default_variant(int prec, int ncol) {
-    if (ncol <= 2) return find_variant(prec, "skinny2");
-    if (ncol <= 4) return find_variant(prec, "skinny4");
-    if (ncol <= 8) return find_variant(prec, "skinny8");
     struct Pick { int upto; const char* name; };
-    static const Pick f64[] = {{32, "m32n128"}, {64, "m64n128i"}, {96, "m128n256w8i"}, {128, "m128n256w8"},
-                               {192, "m64n128i"}, {256, "m128n256w8i"}, {320, "m64n128"}, {1 << 30, "m128n256w8i"}};
-    static const Pick f32[] = {{32, "m32n128"}, {64, "m64n128k256i"}, {96, "m96n256w8"}, {128, "m128n64i"},
-                               {192, "m96n256w8"}, {256, "m128n64i"}, {320, "m160n256w8"}, {1 << 30, "m96n256w8"}};
-    static const Pick b16[] = {{32, "m64n128i"}, {64, "m64n128i"}, {128, "m128n128"}, {192, "m192n256w8"},
-                               {256, "m256n128w8i"}, {320, "m160n256w8"}, {1 << 30, "m192n256w8"}};
+    static const Pick f64[] = {{2, "skinny2"}, {4, "skinny4"}, {8, "skinny8"}, {32, "m32n128"}, {64, "m64n128i"},
+                               {96, "m128n256w8i"}, {128, "m128n256w8"}, {192, "m64n128i"}, {256, "m128n256w8i"},
+                               {320, "m64n128"}, {1 << 30, "m128n256w8i"}};
+    static const Pick f32[] = {{2, "skinny2"}, {4, "skinny4r8"}, {32, "m32n128"}, {64, "m64n128k256i"},
+                               {96, "m96n256w8"}, {128, "m128n64i"}, {192, "m96n256w8"}, {256, "m128n64i"},
+                               {320, "m160n256w8"}, {1 << 30, "m96n256w8"}};
+    // BF16 T is 2 bytes per element: even one column streams it faster through the matrix cores
+    static const Pick b16[] = {{64, "m64n128i"}, {128, "m128n128"}, {192, "m192n256w8"}, {256, "m256n128w8i"},
+                               {320, "m160n256w8"}, {1 << 30, "m192n256w8"}};
     const Pick* t = prec == WFQ_PREC_FP64 ? f64 : prec == WFQ_PREC_FP32 ? f32 : b16;
     while (ncol > t->upto) ++t;
     const int k = find_variant(prec, t->name);
@@ -582,6 +583,10 @@ void tx_any(const Structure& s, int prec, const void* X, void* Y, int ncol, hipS
         tx_f32(s, static_cast<const float*>(X), static_cast<float*>(Y), ncol, st);
     else
         tx_bf16(s, static_cast<const uint16_t*>(X), static_cast<float*>(Y), ncol, st);
+}
+
+void tx_variant_run(const Structure& s, int prec, int var, const void* X, void* Y, int ncol, hipStream_t st) {
+    if (ncol > 0) run_variant(s, prec, var, X, Y, ncol, st);
 }
 
 const char* tx_variant(int precision, int ncol) {

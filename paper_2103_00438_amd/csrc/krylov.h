@@ -134,12 +134,13 @@ void ms_dot(const double* V, int64_t n, int64_t npad, int mdim1, int nvec, int j
 // h[d][i] = sum over chunks of partial[d][i], i < count
 void ms_reduce(const int* dirs, int ndir, const double* partial, int pslots, int64_t n, int count, double* h,
                hipStream_t st);
-// V(d, jw) -= sum_{i < nvec} h[d][i] V(d, i); norm (may be NULL): chunk sums of ||V(d, jw)||^2 [d][nwc]
+// V(d, jw) -= sum_{i < nvec} h[d][i] V(d, i); norm (may be NULL): sums of V(d, jw)^2 over 64-row
+// blocks, [d][npad / 64]
 void ms_update(double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
                const double* h, int pslots, double* norm, hipStream_t st);
 // Hessenberg column j from the two Gram-Schmidt passes and the norm; inv_h[d] = 1 / H_{j+1,j}
 void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const double* h2, int pslots,
-             const double* norm, int64_t n, double* H, double* inv_h, hipStream_t st);
+             const double* norm, int64_t n, int64_t npad, double* H, double* inv_h, hipStream_t st);
 // Givens step j of each listed system on Hbar + z Ibar of its direction (flags as in givens_step)
 void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const double2* z, const double* H, double* cs,
                double2* sn, double2* g, double2* R, int64_t rstride, double* est, const double* tol_abs, int* flags,

@@ -68,43 +68,29 @@ __global__ void __launch_bounds__(256) ms_spmm_kernel(int64_t n, int64_t npad, i
     slot(V, npad, mdim1, dirs[c], jdst)[i] = acc;
 }
 
-// partial[d][i][wc] = sum over wave chunk wc of V(d, i) * V(d, jw) for i < nvec; with self_norm
-// also partial[d][nvec][wc] = sum of V(d, jw)^2. One wave per 512-row chunk, fixed order.
+// partial[d][i][wc] = sum over wave chunk wc (512 rows) of V(d, i) * V(d, jw) for i < nvec; with
+// self_norm also partial[d][nvec][wc] = sum of V(d, jw)^2. One wave per (chunk, vector): the
+// launch has thousands of waves even for one direction, and each sum has a fixed order.
 __global__ void __launch_bounds__(256) ms_dot_kernel(const double* __restrict__ V, int64_t n, int64_t npad, int mdim1,
                                                      int nvec, int jw, const int* __restrict__ dirs,
                                                      double* __restrict__ partial, int pslots, int64_t nwc,
                                                      int self_norm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
-    if (wc >= nwc) return;
-    const int d = dirs[blockIdx.y];
+    const int64_t wc = blockIdx.x;
+    const int i = blockIdx.y * 4 + wave;
+    if (i >= nvec + self_norm) return;
+    const int d = dirs[blockIdx.z];
     const double* w = V + ((int64_t)d * mdim1 + jw) * npad;
+    const double* v = i < nvec ? V + ((int64_t)d * mdim1 + i) * npad : w;
     const int64_t row0 = wc * kWaveRows + lane;
-    double x[8];
+    double s = 0.0;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int64_t row = row0 + 64 * r;
-        x[r] = row < n ? w[row] : 0.0;
+        if (row < n) s += v[row] * w[row];
     }
-    double* out = partial + (int64_t)d * pslots * nwc;
-    for (int i = 0; i < nvec; ++i) {
-        const double* v = V + ((int64_t)d * mdim1 + i) * npad;
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t row = row0 + 64 * r;
-            if (row < n) s += v[row] * x[r];
-        }
-        s = wave_sum(s);
-        if (lane == 0) out[(int64_t)i * nwc + wc] = s;
-    }
-    if (self_norm) {
-        double s = 0.0;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) s += x[r] * x[r];
-        s = wave_sum(s);
-        if (lane == 0) out[(int64_t)nvec * nwc + wc] = s;
-    }
+    s = wave_sum(s);
+    if (lane == 0) partial[((int64_t)d * pslots + i) * nwc + wc] = s;
 }
 
 // h[d][i] = sum_wc partial[d][i][wc], i < count (in chunk order)
@@ -119,59 +105,51 @@ __global__ void ms_reduce_kernel(const int* __restrict__ dirs, const double* __r
     }
 }
 
-// V(d, jw) -= sum_{i < nvec} h[d][i] V(d, i); with norm != NULL also norm[d][wc] = partial ||V(d, jw)||^2
+// V(d, jw) -= sum_{i < nvec} h[d][i] V(d, i); with norm != NULL also norm[d][blk] = the sum of
+// V(d, jw)^2 over the 64 rows of block blk. A block owns 64 rows; its 4 waves take every 4th basis
+// vector and their partial sums are combined in LDS in a fixed order.
+constexpr int kMsRows = 64;
 __global__ void __launch_bounds__(256) ms_update_kernel(double* __restrict__ V, int64_t n, int64_t npad, int mdim1,
                                                         int nvec, int jw, const int* __restrict__ dirs,
                                                         const double* __restrict__ h, int pslots,
-                                                        double* __restrict__ norm, int64_t nwc) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
-    if (wc >= nwc) return;
+                                                        double* __restrict__ norm) {
+    __shared__ double part[4][kMsRows];
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t row = (int64_t)blockIdx.x * kMsRows + r;
     const int d = dirs[blockIdx.y];
-    double* w = V + ((int64_t)d * mdim1 + jw) * npad;
-    const int64_t row0 = wc * kWaveRows + lane;
-    double x[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t row = row0 + 64 * r;
-        x[r] = row < n ? w[row] : 0.0;
-    }
     const double* hd = h + (int64_t)d * pslots;
-    for (int i = 0; i < nvec; ++i) {
-        const double c = hd[i];
-        const double* v = V + ((int64_t)d * mdim1 + i) * npad;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t row = row0 + 64 * r;
-            if (row < n) x[r] -= c * v[row];
-        }
+    double acc = 0.0;
+    if (row < n) {
+#pragma unroll 4
+        for (int i = q; i < nvec; i += 4) acc += hd[i] * V[((int64_t)d * mdim1 + i) * npad + row];
     }
-    double s = 0.0;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t row = row0 + 64 * r;
+    part[q][r] = acc;
+    __syncthreads();
+    if (q == 0) {
+        double* w = V + ((int64_t)d * mdim1 + jw) * npad;
+        double x = 0.0;
         if (row < n) {
-            w[row] = x[r];
-            s += x[r] * x[r];
+            x = w[row] - ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r]));
+            w[row] = x;
         }
-    }
-    if (norm) {
-        s = wave_sum(s);
-        if (lane == 0) norm[(int64_t)d * nwc + wc] = s;
+        if (norm) {
+            const double s2 = wave_sum(x * x);
+            if (r == 0) norm[(int64_t)d * (npad / kMsRows) + blockIdx.x] = s2;
+        }
     }
 }
 
 // Hessenberg column j of direction d: H_ij = h1_i + h2_i (two Gram-Schmidt passes), H_{j+1,j} = ||w||;
 // inv_h[d] = 1 / ||w|| normalises the next basis vector.
 __global__ void ms_hcol_kernel(const int* __restrict__ dirs, int j, int m, const double* __restrict__ h1,
-                               const double* __restrict__ h2, int pslots, const double* __restrict__ norm, int64_t nwc,
+                               const double* __restrict__ h2, int pslots, const double* __restrict__ norm, int64_t nblk,
                                double* __restrict__ H, double* __restrict__ inv_h) {
     const int d = dirs[blockIdx.x];
     double* col = H + ((int64_t)d * m + j) * (m + 1);
     for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h1[(int64_t)d * pslots + i] + h2[(int64_t)d * pslots + i];
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int64_t q = 0; q < nwc; ++q) s += norm[(int64_t)d * nwc + q];
+        for (int64_t q = 0; q < nblk; ++q) s += norm[(int64_t)d * nblk + q];
         const double hn = sqrt(s);
         col[j + 1] = hn;
         inv_h[d] = hn > 0.0 ? 1.0 / hn : 0.0;
@@ -233,29 +211,37 @@ __global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, i
     flags[s] = f;
 }
 
-// y = R^-1 g over the first k[s] columns (back substitution on the packed R); cond[s] =
-// max |R_ii| / min |R_ii|.
-__global__ void ms_solve_kernel(const int* __restrict__ sys, int nsys, const int* __restrict__ ksteps, int m,
-                                const double2* __restrict__ R, int64_t rstride, const double2* __restrict__ g,
-                                double2* __restrict__ y, double* __restrict__ cond) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nsys) return;
-    const int s = sys[k];
+// y = R^-1 g over the first k[s] columns, one work-group per system: column-oriented back
+// substitution on the packed R (column i is contiguous), y kept in LDS; cond[s] = max|R_ii| / min|R_ii|.
+__global__ void __launch_bounds__(256) ms_solve_kernel(const int* __restrict__ sys, const int* __restrict__ ksteps,
+                                                       int m, const double2* __restrict__ R, int64_t rstride,
+                                                       const double2* __restrict__ g, double2* __restrict__ y,
+                                                       double* __restrict__ cond) {
+    extern __shared__ double2 ys[];
+    const int s = sys[blockIdx.x];
     const int K = ksteps[s];
     const double2* Rs = R + (int64_t)s * rstride;
     const double2* gs = g + (int64_t)s * (m + 1);
-    double2* ys = y + (int64_t)s * m;
-    double dmax = 0.0, dmin = 1e300;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) ys[i] = gs[i];
+    __syncthreads();
     for (int i = K - 1; i >= 0; --i) {
-        double2 acc = gs[i];
-        for (int c = i + 1; c < K; ++c) acc = csub(acc, cmul(Rs[(int64_t)c * (c + 1) / 2 + i], ys[c]));
-        const double2 rii = Rs[(int64_t)i * (i + 1) / 2 + i];
-        ys[i] = cdiv(acc, rii);
-        const double a = cabs(rii);
-        dmax = fmax(dmax, a);
-        dmin = fmin(dmin, a);
+        const double2* col = Rs + (int64_t)i * (i + 1) / 2;
+        const double2 yi = cdiv(ys[i], col[i]);   // every thread computes it; ys[i] is final here
+        __syncthreads();
+        if (threadIdx.x == 0) ys[i] = yi;
+        for (int r = threadIdx.x; r < i; r += blockDim.x) ys[r] = csub(ys[r], cmul(col[r], yi));
+        __syncthreads();
     }
-    cond[s] = K > 0 ? dmax / dmin : 1.0;
+    for (int i = threadIdx.x; i < K; i += blockDim.x) y[(int64_t)s * m + i] = ys[i];
+    if (threadIdx.x == 0) {
+        double dmax = 0.0, dmin = 1e300;
+        for (int i = 0; i < K; ++i) {
+            const double a = cabs(Rs[(int64_t)i * (i + 1) / 2 + i]);
+            dmax = fmax(dmax, a);
+            dmin = fmin(dmin, a);
+        }
+        cond[s] = K > 0 ? dmax / dmin : 1.0;
+    }
 }
 
 // x(s) = sum_{i < k[s]} y[s][i] V(d, i) for groups of up to 8 systems of one direction (the basis
@@ -332,9 +318,10 @@ void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const
 
 void ms_dot(const double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
             double* partial, int pslots, bool self_norm, hipStream_t st) {
-    if (ndir <= 0) return;
+    const int ntot = nvec + (self_norm ? 1 : 0);
+    if (ndir <= 0 || ntot <= 0) return;
     const int64_t nwc = wave_chunks(n);
-    dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)ndir);
+    dim3 grd((unsigned)nwc, (unsigned)((ntot + 3) / 4), (unsigned)ndir);
     hipLaunchKernelGGL(ms_dot_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, nvec, jw, dirs, partial, pslots, nwc,
                        (int)self_norm);
     WFQ_CHECK_LAUNCH();
@@ -351,18 +338,17 @@ void ms_reduce(const int* dirs, int ndir, const double* partial, int pslots, int
 void ms_update(double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
                const double* h, int pslots, double* norm, hipStream_t st) {
     if (ndir <= 0) return;
-    const int64_t nwc = wave_chunks(n);
-    dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)ndir);
-    hipLaunchKernelGGL(ms_update_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, nvec, jw, dirs, h, pslots, norm,
-                       nwc);
+    dim3 grd((unsigned)(npad / kMsRows), (unsigned)ndir);
+    hipLaunchKernelGGL(ms_update_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, nvec, jw, dirs, h, pslots, norm);
     WFQ_CHECK_LAUNCH();
 }
 
 void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const double* h2, int pslots,
-             const double* norm, int64_t n, double* H, double* inv_h, hipStream_t st) {
+             const double* norm, int64_t n, int64_t npad, double* H, double* inv_h, hipStream_t st) {
     if (ndir <= 0) return;
+    (void)n;
     hipLaunchKernelGGL(ms_hcol_kernel, dim3((unsigned)ndir), dim3(128), 0, st, dirs, j, m, h1, h2, pslots, norm,
-                       wave_chunks(n), H, inv_h);
+                       npad / kMsRows, H, inv_h);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -378,8 +364,8 @@ void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const do
 void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t rstride, const double2* g,
               double2* y, double* cond, hipStream_t st) {
     if (nsys <= 0) return;
-    hipLaunchKernelGGL(ms_solve_kernel, dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st, sys, nsys, ksteps, m, R,
-                       rstride, g, y, cond);
+    hipLaunchKernelGGL(ms_solve_kernel, dim3((unsigned)nsys), dim3(256), (size_t)m * sizeof(double2), st, sys, ksteps,
+                       m, R, rstride, g, y, cond);
     WFQ_CHECK_LAUNCH();
 }
 

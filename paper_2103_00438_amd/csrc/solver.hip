@@ -531,7 +531,7 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     part.alloc((size_t)nd * pslots * nwc);
     h1.alloc((size_t)nd * pslots);
     h2.alloc((size_t)nd * pslots);
-    nrm.alloc((size_t)nd * nwc);
+    nrm.alloc((size_t)nd * (np / 64));
     inv_h.alloc(nd);
     cs.alloc((size_t)B * m);
     sn.alloc((size_t)B * m);
@@ -623,7 +623,7 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         tm.end(st, KC_DOT, 2.0 * dn * na * (j + 1), pass);
         tm.begin(st);
         ms_update(V.p, n, np, mdim1, j + 1, j + 1, dirs.p, na, h2.p, pslots, nrm.p, st);
-        ms_hcol(dirs.p, na, j, m, h1.p, h2.p, pslots, nrm.p, n, H.p, inv_h.p, st);
+        ms_hcol(dirs.p, na, j, m, h1.p, h2.p, pslots, nrm.p, n, np, H.p, inv_h.p, st);
         tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
         // every unconverged frequency of those directions: one Givens step on Hbar + z Ibar
         const int ns = (int)stepping.size();

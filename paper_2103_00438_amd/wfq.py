@@ -88,6 +88,7 @@ _SIGNATURES = {
     "wfq_sample_T": (C.c_int, [C.c_void_p, C.c_int32, _I64P, _I64P, C.c_int64, _DP]),
     "wfq_export_L": (C.c_int, [C.c_void_p, _I64P, _I64P, _DP]),
     "wfq_apply_T": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _DP, _DP]),
+    "wfq_apply_T_variant": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _DP, _DP]),
     "wfq_apply_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _DP, _DP, _DP, _DP, _DP, _DP]),
     "wfq_rhs": (C.c_int, [C.c_void_p, _DP, C.c_int32, C.c_double, _DP]),
     "wfq_kernel_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_char_p), _I64P, _DP, _DP, _DP,
@@ -295,6 +296,19 @@ def wfq_apply_T(h: Handle, precision, X) -> np.ndarray:
         X = X[None, :]
     Y = np.zeros_like(X)
     _check(load().wfq_apply_T(h.ptr, PREC[precision], X.shape[0], _dp(X), _dp(Y)))
+    return Y
+
+
+def wfq_apply_T_variant(h: Handle, precision, variant, X) -> np.ndarray:
+    """Y = T X through one named (or indexed) block-product variant of the precision."""
+    if isinstance(variant, str):
+        names = [v[0] for v in wfq_tx_variants(precision)]
+        variant = names.index(variant)
+    X = _f64(X)
+    if X.ndim == 1:
+        X = X[None, :]
+    Y = np.zeros_like(X)
+    _check(load().wfq_apply_T_variant(h.ptr, PREC[precision], int(variant), X.shape[0], _dp(X), _dp(Y)))
     return Y
 
 

@@ -97,6 +97,34 @@ def test_block_product(lib, handle, tube, prec, ncol):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_every_block_product_variant(lib, handle, tube, prec):
+    # each shape the autotuner may choose, at ragged widths (partial column tiles, split k parts)
+    _, P = tube
+    Tq = round_to(prec, P.T)
+    u_acc = UNIT["fp64"] if prec == "fp64" else UNIT["fp32"]
+    rng = np.random.default_rng(31)
+    for name, max_ncol in lib.wfq_tx_variants(prec):
+        widths = [max_ncol, max_ncol - 1] if max_ncol < 64 else [3, 97, 200]
+        for ncol in widths:
+            if ncol < 1:
+                continue
+            X = rng.standard_normal((ncol, P.n))
+            Y = lib.wfq_apply_T_variant(handle, prec, name, X)
+            Xq = round_to(prec, X)
+            ref = Xq @ Tq
+            bound = np.abs(Xq) @ np.abs(Tq)
+            assert np.all(np.abs(Y - ref) <= 2 * P.n * u_acc * bound + 1e-300), (name, ncol)
+
+
+def test_variant_entry_point_rejects(lib, handle):
+    X = np.ones((5, handle.n))
+    with pytest.raises(lib.WfqError):
+        lib.wfq_apply_T_variant(handle, "fp32", "skinny4", X)       # 5 columns > 4
+    with pytest.raises(lib.WfqError):
+        lib.wfq_apply_T_variant(handle, "fp32", 10 ** 6, X)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_operator_apply(lib, handle, tube, prec):
     _, P = tube
     rng = np.random.default_rng(7)

@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--workload", default="cnt20k")
     ap.add_argument("--algorithm", default=None, help="gmres, qmr or msgmres (one shared basis per direction)")
     ap.add_argument("--shift-dim", type=int, default=0, help="msgmres: largest shared-basis dimension (0 = 400)")
+    ap.add_argument("--restart", type=int, default=0,
+                    help="override the workload's GMRES restart length / QMR check interval")
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 comparison runs")
@@ -146,8 +148,10 @@ def roofline_of(stats, prec, otf, n, workload=None):
         return dict(bound="alu", achieved=achieved, peak=peak, unit="Gpair/s", frac=achieved / peak, traffic=None,
                     kernel=key, launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
                     pairs_per_launch=pairs)
-    dom = {"fp32": "tx_gemm_f32", "fp64": "tx_gemm_f64", "bf16": "tx_gemm_bf16"}[prec]
-    if stats.get("tx_skinny", {}).get("ms", 0.0) > stats.get(dom, {}).get("ms", 0.0):
+    # the T-product class that took the most time (systems may have escalated to another precision)
+    classes = {"tx_gemm_f32": "fp32", "tx_gemm_f64": "fp64", "tx_gemm_bf16": "bf16", "tx_skinny": None}
+    dom = max(classes, key=lambda k: stats.get(k, {}).get("ms", 0.0))
+    if dom == "tx_skinny":
         # narrow products dominate (one column per direction in multi-shift mode): HBM-bound, T read once
         st = stats["tx_skinny"]
         avg_s = st["ms"] / max(1, st["launches"]) / 1e3
@@ -157,6 +161,7 @@ def roofline_of(stats, prec, otf, n, workload=None):
                     avg_launch_ms=st["ms"] / max(1, st["launches"]),
                     avg_bytes_per_launch=st["bytes"] / max(1, st["launches"]))
     st = stats[dom]
+    prec = classes[dom]
     achieved = st["flops"] / (st["ms"] / 1e3) / 1e12 if st["ms"] > 0 else 0.0
     return dict(bound="mfma", achieved=achieved, peak=PEAKS[prec], unit="TFLOP/s", frac=achieved / PEAKS[prec],
                 traffic=measured_traffic(workload, dom), kernel=dom, launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
@@ -213,11 +218,21 @@ def bench_batched(args, wl, wfq, torch):
     roofline = roofline_of(stats, prec, otf, wl.n, wl.name)
 
     extra = {}
-    if not args.no_reference and prec != "fp64":
+    if otf and not args.ref_systems:
+        # a matrix-free FP64 solve of even one 10^6-atom system takes minutes: the check is the FP64
+        # residual every result already carries (recomputed with FP64 elements on the fly) and the
+        # error estimate relres x cond(R)
+        extra = dict(fp64_reference_systems=0,
+                     err_est_max=float(max(r["err_est"] for r in last["info"])),
+                     fp64_check="relres of every system recomputed with FP64 matrix-free T")
+    elif not args.no_reference and prec != "fp64":
         # the same systems with FP64 T inside the iterations (same GPU, same library)
         sel = list(range(S))
-        if args.ref_systems and args.ref_systems < S:
-            sel = [int(round(v)) for v in np.linspace(0, S - 1, args.ref_systems)]
+        # very large or matrix-free workloads: a sample of systems, each solved alone (which is also
+        # the per-frequency FP64 baseline)
+        nref = args.ref_systems or (2 if wl.n > 50000 else 0)
+        if nref and nref < S:
+            sel = [int(round(v)) for v in np.linspace(0, S - 1, nref)] if nref > 1 else [S // 2]
         t0 = time.perf_counter()
         qref = np.zeros((len(sel), wl.n), dtype=complex)
         aref = np.zeros((len(sel), 3), dtype=complex)
@@ -242,16 +257,21 @@ def bench_batched(args, wl, wfq, torch):
                      fp64_reference_systems=len(sel), fp64_reference_s=t_ref)
         if len(sel) == S:
             extra["fp64_batched_solves_per_s"] = S / t_ref
-        # per-frequency FP64 baseline: one system per solve, sampled
-        samp = [0, S // 2, S - 1] if wl.n > 50000 else [0, S // 4, S // 2, 3 * S // 4, S - 1]
-        t0 = time.perf_counter()
-        for s in samp:
-            a, k = divmod(s, len(wl.dirs))
-            wfq.wfq_solve(h, wl.omegas_eV[a:a + 1], wl.dirs[k:k + 1], wl.tol, want_q=False,
-                          restart=wl.restart, precision="fp64", algorithm=ref_algo, progress=wl.n > 50000)
-        t_pf = (time.perf_counter() - t0) / len(samp)
+        # per-frequency FP64 baseline: one system per solve
+        if len(sel) < S:
+            t_pf = t_ref / len(sel)
+            samp_note = f"the {len(sel)} reference system(s) above, one per solve"
+        else:
+            samp = [0, S // 4, S // 2, 3 * S // 4, S - 1]
+            t0 = time.perf_counter()
+            for s in samp:
+                a, k = divmod(s, len(wl.dirs))
+                wfq.wfq_solve(h, wl.omegas_eV[a:a + 1], wl.dirs[k:k + 1], wl.tol, want_q=False,
+                              restart=wl.restart, precision="fp64", algorithm=ref_algo, progress=wl.n > 50000)
+            t_pf = (time.perf_counter() - t0) / len(samp)
+            samp_note = f"{len(samp)} systems, one per solve"
         extra.update(fp64_per_frequency_solves_per_s=1.0 / t_pf, speedup_vs_fp64_per_frequency=value * t_pf,
-                     per_frequency_sample=f"{len(samp)} systems, one per solve")
+                     per_frequency_sample=samp_note)
     cpu = None
     if not otf and algo != "msgmres" and not args.no_multishift and wl.n <= 50000:
         # the next step of the method on the same systems: one real Krylov basis per field direction
@@ -382,6 +402,8 @@ def main():
 
     torch.cuda.set_device(torch.device("cuda:0"))
     wl = wi.workload(args.workload)
+    if args.restart > 0:
+        wl.restart = args.restart
     if wl.name == "disk600":
         line = bench_latency(args, wl, wfq, torch)
     elif wl.name == "serve_mix":

@@ -224,10 +224,11 @@ T* dev_alloc(Structure& s, size_t count) {
 }  // namespace
 
 void free_structure(Structure& s) {
-    void* ptrs[] = {s.pos, s.eta, s.width, s.rowptr, s.col, s.val, s.T64, s.T32, s.T16, s.dperm, s.ell_col, s.ell_val};
+    void* ptrs[] = {s.pos, s.eta, s.width, s.rowptr, s.col, s.val, s.T64, s.T32, s.T16, s.dperm, s.ell_col, s.ell_val,
+                    s.sphere};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
-    s.pos = s.eta = s.width = s.val = s.T64 = nullptr;
+    s.pos = s.eta = s.width = s.val = s.T64 = s.sphere = nullptr;
     s.rowptr = s.col = s.dperm = s.ell_col = nullptr;
     s.ell_val = nullptr;
     s.T32 = nullptr;
@@ -318,6 +319,36 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     WFQ_HIP(hipMemcpyAsync(s.pos, pos_h.data(), pos_h.size() * 8, hipMemcpyHostToDevice, st));
     WFQ_HIP(hipMemcpyAsync(s.eta, eta_h.data(), eta_h.size() * 8, hipMemcpyHostToDevice, st));
     WFQ_HIP(hipMemcpyAsync(s.width, width_h.data(), width_h.size() * 8, hipMemcpyHostToDevice, st));
+    // bounding spheres of consecutive 64-atom blocks (internal order; padding atoms excluded, an
+    // empty block gets radius 0), used by the matrix-free products to find far-apart tile pairs
+    {
+        const int64_t nb = s.npad / 64;
+        std::vector<double> sph((size_t)nb * 4, 0.0);
+        for (int64_t b = 0; b < nb; ++b) {
+            const int64_t k0 = b * 64, k1 = std::min<int64_t>(n, k0 + 64);
+            if (k1 <= k0) continue;
+            double lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) lo[a] = hi[a] = s.pos_host[a * n + k0];
+            for (int64_t k = k0; k < k1; ++k)
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = std::min(lo[a], s.pos_host[a * n + k]);
+                    hi[a] = std::max(hi[a], s.pos_host[a * n + k]);
+                }
+            double c[3], r2 = 0.0;
+            for (int a = 0; a < 3; ++a) c[a] = 0.5 * (lo[a] + hi[a]);
+            for (int64_t k = k0; k < k1; ++k) {
+                double d2 = 0.0;
+                for (int a = 0; a < 3; ++a) d2 += (s.pos_host[a * n + k] - c[a]) * (s.pos_host[a * n + k] - c[a]);
+                r2 = std::max(r2, d2);
+            }
+            for (int a = 0; a < 3; ++a) sph[b * 4 + a] = c[a];
+            sph[b * 4 + 3] = std::sqrt(r2);
+        }
+        s.sphere = dev_alloc<double>(s, sph.size());
+        WFQ_HIP(hipMemcpyAsync(s.sphere, sph.data(), sph.size() * 8, hipMemcpyHostToDevice, st));
+        s.width_max = 0.0;
+        for (int64_t k = 0; k < n; ++k) s.width_max = std::max(s.width_max, width_h[k]);
+    }
 
     // ---- a1: neighbour search and CSR of L = P - Kbar
     int32_t *d_start = nullptr, *d_count = nullptr, *d_counts = nullptr, *d_flag = nullptr;

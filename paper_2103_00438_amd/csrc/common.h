@@ -56,6 +56,8 @@ struct Structure {
     double* pos = nullptr;       // device [3][npad] SoA, bohr (padding: zeros)
     double* eta = nullptr;       // device [npad]
     double* width = nullptr;     // device [npad], d_i
+    double* sphere = nullptr;    // device [npad / 64][4]: centre and radius of each 64-atom block (bohr)
+    double width_max = 0.0;      // largest d_i
     int64_t nnz = 0;
     int32_t* rowptr = nullptr;   // device [n + 1]
     int32_t* col = nullptr;      // device [nnz]

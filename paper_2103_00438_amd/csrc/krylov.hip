@@ -155,49 +155,48 @@ void launch_spmm_rows(const Structure& S, const YE* Y, int64_t ld, const int* sy
                        S.ell_w, S.ell_col, S.ell_val, Y, ld, sys, nsys, per_group, z, V, jsrc, jdst);
 }
 
+// Dots for the Arnoldi step: one wave per (512-row chunk, basis vector, system), so that even a
+// single system's step is spread over many waves; each sum runs in a fixed order.
+// partial[s][i][wc] = sum over chunk wc of conj(V(s, i)) V(s, jw), i <= j; with self_norm also
+// partial[s][j + 1][wc] = ||V(s, jw)||^2 over the chunk.
 __global__ void __launch_bounds__(256) dot_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
                                                   double2* __restrict__ partial, int mdim, int64_t nwc,
                                                   const int* __restrict__ active, int self_norm) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
-    if (wc >= nwc) return;
-    const int s = sys[blockIdx.y];
+    const int64_t wc = blockIdx.x;
+    const int i = blockIdx.y * 4 + wave;
+    if (i > j + self_norm) return;
+    const int s = sys[blockIdx.z];
     if (active && !active[s]) return;
     const double* wr = vre(V, s, jw);
     const double* wi = wr + V.npad;
     const int64_t row0 = wc * kWaveRows + lane;
-    double xr[8], xi[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t row = row0 + 64 * r;
-        xr[r] = row < n ? wr[row] : 0.0;
-        xi[r] = row < n ? wi[row] : 0.0;
-    }
-    for (int i = 0; i <= j; ++i) {
+    double sr = 0.0, si = 0.0;
+    if (i <= j) {
         const double* vr = vre(V, s, i);
         const double* vi = vr + V.npad;
-        double sr = 0.0, si = 0.0;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int64_t row = row0 + 64 * r;
             if (row < n) {
-                const double a = vr[row], b = vi[row];
-                sr += a * xr[r] + b * xi[r];   // conj(v) w
-                si += a * xi[r] - b * xr[r];
+                const double a = vr[row], b = vi[row], x = wr[row], y = wi[row];
+                sr += a * x + b * y;   // conj(v) w
+                si += a * y - b * x;
             }
         }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
-        if (lane == 0) partial[((int64_t)s * mdim + i) * nwc + wc] = make_double2(sr, si);
-    }
-    if (self_norm) {
-        // ||w||^2 in slot j + 1 (the reorthogonalisation test compares it with the projected norm)
-        double nn = 0.0;
+    } else {
 #pragma unroll
-        for (int r = 0; r < 8; ++r) nn += xr[r] * xr[r] + xi[r] * xi[r];
-        nn = wave_sum(nn);
-        if (lane == 0) partial[((int64_t)s * mdim + j + 1) * nwc + wc] = make_double2(nn, 0.0);
+        for (int r = 0; r < 8; ++r) {
+            const int64_t row = row0 + 64 * r;
+            if (row < n) {
+                const double x = wr[row], y = wi[row];
+                sr += x * x + y * y;
+            }
+        }
     }
+    sr = wave_sum(sr);
+    si = wave_sum(si);
+    if (lane == 0) partial[((int64_t)s * mdim + i) * nwc + wc] = make_double2(sr, si);
 }
 
 __global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const double2* __restrict__ partial, int mdim,
@@ -215,58 +214,66 @@ __global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const dou
     }
 }
 
+// V(s, jw) -= sum_{i <= j} h[s][i] V(s, i) for one 512-row chunk per work-group: each of the 4 waves
+// sums every 4th basis vector over the whole chunk, the partial sums meet in LDS and are combined
+// in a fixed order; norm2[s][wc] (if not NULL) = ||V(s, jw)||^2 over the chunk, also in fixed order.
 __global__ void __launch_bounds__(256) update_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
                                                      const double2* __restrict__ h, int mdim,
                                                      double* __restrict__ norm2, int64_t nwc,
                                                      const int* __restrict__ active) {
+    __shared__ double pr[4][kWaveRows], pi[4][kWaveRows];
+    __shared__ double red[4];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
-    if (wc >= nwc) return;
+    const int64_t wc = blockIdx.x;
     const int s = sys[blockIdx.y];
-    if (active && !active[s]) return;
-    double* wr = vre(V, s, jw);
-    double* wi = wr + V.npad;
-    const int64_t row0 = wc * kWaveRows + lane;
-    double xr[8], xi[8];
+    if (active && !active[s]) return;   // whole work-group
+    const int64_t row0 = wc * kWaveRows;
+    double ar[8], ai[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t row = row0 + 64 * r;
-        xr[r] = row < n ? wr[row] : 0.0;
-        xi[r] = row < n ? wi[row] : 0.0;
-    }
-    for (int i = 0; i <= j; ++i) {
+    for (int r = 0; r < 8; ++r) ar[r] = ai[r] = 0.0;
+    for (int i = wave; i <= j; i += 4) {
         const double2 hh = h[(int64_t)s * mdim + i];
         const double* vr = vre(V, s, i);
         const double* vi = vr + V.npad;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
-            const int64_t row = row0 + 64 * r;
+            const int64_t row = row0 + lane + 64 * r;
             if (row < n) {
                 const double a = vr[row], b = vi[row];
-                xr[r] -= hh.x * a - hh.y * b;
-                xi[r] -= hh.x * b + hh.y * a;
+                ar[r] += hh.x * a - hh.y * b;
+                ai[r] += hh.x * b + hh.y * a;
             }
         }
     }
-    double nn = 0.0;
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
-        const int64_t row = row0 + 64 * r;
+        pr[wave][lane + 64 * r] = ar[r];
+        pi[wave][lane + 64 * r] = ai[r];
+    }
+    __syncthreads();
+    double* wr = vre(V, s, jw);
+    double* wi = wr + V.npad;
+    double nn = 0.0;
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int q = threadIdx.x + 256 * t;
+        const int64_t row = row0 + q;
         if (row < n) {
-            wr[row] = xr[r];
-            wi[row] = xi[r];
-            nn += xr[r] * xr[r] + xi[r] * xi[r];
+            const double xr = wr[row] - ((pr[0][q] + pr[1][q]) + (pr[2][q] + pr[3][q]));
+            const double xi = wi[row] - ((pi[0][q] + pi[1][q]) + (pi[2][q] + pi[3][q]));
+            wr[row] = xr;
+            wi[row] = xi;
+            nn += xr * xr + xi * xi;
         }
     }
     if (norm2) {
         nn = wave_sum(nn);
-        if (lane == 0) norm2[(int64_t)s * nwc + wc] = nn;
+        if (lane == 0) red[wave] = nn;
+        __syncthreads();
+        if (threadIdx.x == 0) norm2[(int64_t)s * nwc + wc] = (red[0] + red[1]) + (red[2] + red[3]);
     }
 }
 
-// Daniel-Gragg-Kaufman-Stewart test: a second Gram-Schmidt pass is needed only when projecting
-// removed more than half of the vector's squared norm (||w'||^2 < ||w||^2 / 2). Systems that skip it
-// get h2 = 0 and keep the norm of the first pass.
 __global__ void reorth_test_kernel(const int* __restrict__ sys, int nsys, int j, int mdim,
                                    const double2* __restrict__ h1, const double* __restrict__ norm2a, int nwc,
                                    double2* __restrict__ h2, int* __restrict__ reorth) {
@@ -556,7 +563,7 @@ void multi_dot(const Basis& V, int64_t n, const int* sys, int nsys, int j, int j
                hipStream_t st, const int* active, bool self_norm) {
     if (nsys <= 0) return;
     const int64_t nwc = wave_chunks(n);
-    dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
+    dim3 grd((unsigned)nwc, (unsigned)((j + 1 + (self_norm ? 1 : 0) + 3) / 4), (unsigned)nsys);
     hipLaunchKernelGGL(dot_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, partial, mdim, nwc, active,
                        (int)self_norm);
     WFQ_CHECK_LAUNCH();
@@ -574,7 +581,7 @@ void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, in
                   double* norm2, hipStream_t st, const int* active) {
     if (nsys <= 0) return;
     const int64_t nwc = wave_chunks(n);
-    dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
+    dim3 grd((unsigned)nwc, (unsigned)nsys);
     hipLaunchKernelGGL(update_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, h, mdim, norm2, nwc, active);
     WFQ_CHECK_LAUNCH();
 }

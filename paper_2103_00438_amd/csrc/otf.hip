@@ -50,12 +50,14 @@ template <>
 struct OtfT<WFQ_PREC_FP32> {
     using elem = float;
     using acc = floatx4;
+    using vec4 = floatx4;           // (x, y, z, d^2) of one source atom
     static constexpr int BJ = 64;   // 256-byte rows
 };
 template <>
 struct OtfT<WFQ_PREC_FP64> {
     using elem = double;
     using acc = doublex4;
+    using vec4 = doublex4;
     static constexpr int BJ = 32;
 };
 
@@ -68,6 +70,16 @@ __device__ inline void mma_otf(floatx4& c, const uint4& a, const uint4& b) {
 __device__ inline void mma_otf(doublex4& c, const uint4& a, const uint4& b) {
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double(a.y, a.x), __hiloint2double(b.y, b.x), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f64_16x16x4f64(__hiloint2double(a.w, a.z), __hiloint2double(b.w, b.z), c, 0, 0, 0);
+}
+
+// 1 / r_ij, the far-field value of T_ij
+__device__ inline float inv_dist(float xi, float yi, float zi, float xj, float yj, float zj) {
+    const float dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    return __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+}
+__device__ inline double inv_dist(double xi, double yi, double zi, double xj, double yj, double zj) {
+    const double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    return 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
 }
 
 // T_ij for one pair from coordinates relative to a common centre
@@ -85,9 +97,21 @@ __device__ inline double t_elem(double xi, double yi, double zi, double di2, dou
     return erf(r / sqrt(di2 + dj2)) / r;
 }
 
+// Far-field test of a (target block, source tile) pair from the bounding spheres of their 64-atom
+// blocks: true when every pair is at least rfar apart, i.e. erf(r / sqrt(d_i^2 + d_j^2)) rounds to 1
+// in the element precision (rfar = 4.5 sqrt(2) d_max for FP32, erfc(4.5) = 2e-10; 6 sqrt(2) d_max for
+// FP64, erfc(6) = 2e-17), so T_ij = 1 / r_ij exactly as the full evaluation would round it.
+__device__ inline bool far_apart(const double* __restrict__ sph, int64_t bt, int64_t bs, double rfar) {
+    const double* a = sph + bt * 4;
+    const double* b = sph + bs * 4;
+    const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    return sqrt(dx * dx + dy * dy + dz * dz) - a[3] - b[3] >= rfar;
+}
+
 template <int P, int BC>
 __global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const double* __restrict__ pos,
                                                   const double* __restrict__ width, const double* __restrict__ eta,
+                                                  const double* __restrict__ sphere, double rfar,
                                                   const typename OtfT<P>::elem* __restrict__ X,
                                                   typename OtfT<P>::elem* __restrict__ Y) {
     using E = typename OtfT<P>::elem;
@@ -98,8 +122,9 @@ __global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const
     constexpr int WM = BC / 16;               // column blocks
     constexpr int WN = 2;                     // 32 target rows per wave
     constexpr int XCH = BC * (KB / 16);       // 16-byte chunks of the X tile
+    using V4 = typename OtfT<P>::vec4;
     __shared__ __attribute__((aligned(16))) char lds[(BC + kBI) * RS];
-    __shared__ E src[4][BJ];
+    __shared__ V4 src[BJ];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int64_t i0 = (int64_t)blockIdx.x * kBI;
@@ -133,10 +158,12 @@ __global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const
         if (tid < BJ) {
             const int64_t j = j0 + tid;
             const bool jin = j < n;
-            src[0][tid] = jin ? (E)(pos[j] - cx) : E(0);
-            src[1][tid] = jin ? (E)(pos[npad + j] - cy) : E(0);
-            src[2][tid] = jin ? (E)(pos[2 * npad + j] - cz) : E(0);
-            src[3][tid] = jin ? (E)(width[j] * width[j]) : E(1);
+            V4 p;
+            p.x = jin ? (E)(pos[j] - cx) : E(0);
+            p.y = jin ? (E)(pos[npad + j] - cy) : E(0);
+            p.z = jin ? (E)(pos[2 * npad + j] - cz) : E(0);
+            p.w = jin ? (E)(width[j] * width[j]) : E(1);
+            src[tid] = p;
         }
         for (int q = tid; q < XCH; q += 256) {
             const int row = q / (KB / 16), cc = q % (KB / 16);
@@ -146,18 +173,38 @@ __global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const
         __syncthreads();
         // T tile: row it, columns jh * BJ/2 .. + BJ/2 (zero outside the atoms, eta on the diagonal)
         E* trow = reinterpret_cast<E*>(TT + it * RS);
+        const int64_t bs = j0 / 64, bt = i0 / 64;
+        const bool full = tin && j0 + BJ <= n;   // no padding atom in this row of the tile
+        if (far_apart(sphere, bt, bs, rfar) && far_apart(sphere, bt + 1, bs, rfar)) {
+            if (full) {
+#pragma unroll 8
+                for (int jj = 0; jj < BJ / 2; ++jj) {
+                    const int jl = jh * (BJ / 2) + jj;
+                    const V4 p = src[jl];
+                    trow[jl] = inv_dist(xi, yi, zi, p.x, p.y, p.z);
+                }
+            } else {
+                for (int jj = 0; jj < BJ / 2; ++jj) {
+                    const int jl = jh * (BJ / 2) + jj;
+                    const V4 p = src[jl];
+                    trow[jl] = (tin && j0 + jl < n) ? inv_dist(xi, yi, zi, p.x, p.y, p.z) : E(0);
+                }
+            }
+        } else {
 #pragma unroll 4
-        for (int jj = 0; jj < BJ / 2; ++jj) {
-            const int jl = jh * (BJ / 2) + jj;
-            const int64_t j = j0 + jl;
-            E v;
-            if (!tin || j >= n)
-                v = E(0);
-            else if (j == ti)
-                v = etai;
-            else
-                v = t_elem(xi, yi, zi, di2, src[0][jl], src[1][jl], src[2][jl], src[3][jl]);
-            trow[jl] = v;
+            for (int jj = 0; jj < BJ / 2; ++jj) {
+                const int jl = jh * (BJ / 2) + jj;
+                const int64_t j = j0 + jl;
+                const V4 p = src[jl];
+                E v;
+                if (!tin || j >= n)
+                    v = E(0);
+                else if (j == ti)
+                    v = etai;
+                else
+                    v = t_elem(xi, yi, zi, di2, p.x, p.y, p.z, p.w);
+                trow[jl] = v;
+            }
         }
         __syncthreads();
         acc_t tile[WM][WN];
@@ -211,8 +258,9 @@ void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStrea
     if (ncol <= 0) return;
     constexpr int BC = 32;
     dim3 grd((unsigned)(s.npad / kBI), (unsigned)((ncol + BC - 1) / BC));
-    hipLaunchKernelGGL((otf_kernel<WFQ_PREC_FP32, BC>), grd, dim3(256), 0, st, s.n, s.npad, s.pos, s.width, s.eta, X,
-                       Y);
+    const double rfar = 4.5 * std::sqrt(2.0) * s.width_max;
+    hipLaunchKernelGGL((otf_kernel<WFQ_PREC_FP32, BC>), grd, dim3(256), 0, st, s.n, s.npad, s.pos, s.width, s.eta,
+                       s.sphere, rfar, X, Y);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -220,8 +268,9 @@ void otf_tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStr
     if (ncol <= 0) return;
     constexpr int BC = 32;
     dim3 grd((unsigned)(s.npad / kBI), (unsigned)((ncol + BC - 1) / BC));
-    hipLaunchKernelGGL((otf_kernel<WFQ_PREC_FP64, BC>), grd, dim3(256), 0, st, s.n, s.npad, s.pos, s.width, s.eta, X,
-                       Y);
+    const double rfar = 6.0 * std::sqrt(2.0) * s.width_max;
+    hipLaunchKernelGGL((otf_kernel<WFQ_PREC_FP64, BC>), grd, dim3(256), 0, st, s.n, s.npad, s.pos, s.width, s.eta,
+                       s.sphere, rfar, X, Y);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -899,7 +899,8 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
         throw Error{WFQ_EINVAL, "FP64 refinement needs the FP64 copy of T (store_mask must include WFQ_STORE_FP64)"};
 
     // batch size: as many systems as fit the budget
-    int B = o.max_batch > 0 ? std::min(o.max_batch, total) : total;
+    // (systems index the y/z dimension of several grids: at most 32768 per batch)
+    int B = std::min(o.max_batch > 0 ? std::min(o.max_batch, total) : total, 32768);
     const uint64_t avail = S.budget > S.bytes ? S.budget - S.bytes : 0;
     while (B > 1 && S.budget && batch_bytes(S, o, B, n_dir) > avail) B = (B + 1) / 2;
     if (S.budget && batch_bytes(S, o, B, n_dir) > avail)

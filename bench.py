@@ -34,12 +34,6 @@ sys.path.insert(0, ROOT)
 
 PEAKS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}   # TFLOP/s, dense MFMA (MI355X)
 HBM_GBPS = 8000.0                                         # GB/s, HBM3E (MI355X)
-HBM_PEAK = 8000.0                                        # GB/s
-# Matrix-free FP32 elements: ~26 VALU instructions per pair, 4 of them quarter-rate transcendentals
-# (3 extra issue slots each) = 38 issue slots; non-packed FP32 VALU issue rate of MI355X =
-# 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 39.3e12 lane-instructions/s.
-OTF_SLOTS_PER_PAIR = 38.0
-VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 METRIC = "omega-point solves/s at rel. err 1e-6 (mixed vs FP64, same GPU); p50/p99 latency"
 
 
@@ -57,6 +51,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 comparison runs")
     ap.add_argument("--no-multishift", action="store_true", help="skip the multi-shift FP64 run of the same systems")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB on the device 4 times (calibrates the HBM byte counters) and report GB/s")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in block-product shapes")
     ap.add_argument("--ref-systems", type=int, default=0,
                     help="compare only this many systems against FP64 (0 = all)")
@@ -137,17 +133,21 @@ def measured_traffic(workload, kernel):
 
 def roofline_of(stats, prec, otf, n, workload=None):
     if otf:
+        # Per pair the kernel evaluates T_ij on the vector ALUs (about 10 lane-slots for a far pair:
+        # 3 sub, 1 mul, 2 fma and a quarter-rate rsqrt; about 38 near the diagonal) and accumulates
+        # 2 * 32 flops per 32-column block on the FP32 matrix cores (64 flops per SIMD-cycle). With the
+        # far-field path the matrix-core work is the larger one, so the roofline is the FP32 MFMA peak
+        # on the flops of the column blocks actually present (2 n^2 ncol per launch).
         key = "tx_otf_f32" if prec == "fp32" else "tx_otf_f64"
         st = stats[key]
-        # one launch evaluates n^2 pairs per 32-column block (flops are counted as 2 n^2 ncol)
         ncol_avg = st["flops"] / max(1, st["launches"]) / (2.0 * n * n)
         pairs = n * n * math.ceil(ncol_avg / 32)
         avg_s = st["ms"] / max(1, st["launches"]) / 1e3
-        achieved = pairs / avg_s / 1e9 if avg_s > 0 else 0.0
-        peak = VALU_LANE_OPS / OTF_SLOTS_PER_PAIR / 1e9
-        return dict(bound="alu", achieved=achieved, peak=peak, unit="Gpair/s", frac=achieved / peak, traffic=None,
+        achieved = st["flops"] / max(1, st["launches"]) / avg_s / 1e12 if avg_s > 0 else 0.0
+        peak = PEAKS["fp32" if prec == "fp32" else "fp64"]
+        return dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak, traffic=None,
                     kernel=key, launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
-                    pairs_per_launch=pairs)
+                    pairs_per_launch=pairs, pairs_per_s=pairs / avg_s if avg_s > 0 else 0.0)
     # the T-product class that took the most time (systems may have escalated to another precision)
     classes = {"tx_gemm_f32": "fp32", "tx_gemm_f64": "fp64", "tx_gemm_bf16": "bf16", "tx_skinny": None}
     dom = max(classes, key=lambda k: stats.get(k, {}).get("ms", 0.0))
@@ -401,6 +401,18 @@ def main():
     from paper_2103_00438_amd import wfq
 
     torch.cuda.set_device(torch.device("cuda:0"))
+    if args.copy_probe:
+        a = torch.ones(64 * 1024 * 1024, device="cuda:0")      # 256 MiB of float32
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(4):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 4
+        print(json.dumps(dict(copy_bytes=2 * a.numel() * 4, copy_gbps=2 * a.numel() * 4 / dt / 1e9)))
+        return
     wl = wi.workload(args.workload)
     if args.restart > 0:
         wl.restart = args.restart

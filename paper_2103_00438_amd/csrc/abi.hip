@@ -268,9 +268,10 @@ int wfq_export_L(const wfq_handle* h, int64_t* rows, int64_t* cols, double* vals
         WFQ_HIP(hipSetDevice(S.device));
         std::vector<int32_t> rp(S.n + 1), cl(S.nnz);
         std::vector<double> vl(S.nnz);
-        WFQ_HIP(hipMemcpy(rp.data(), S.rowptr, (S.n + 1) * 4, hipMemcpyDeviceToHost));
-        WFQ_HIP(hipMemcpy(cl.data(), S.col, S.nnz * 4, hipMemcpyDeviceToHost));
-        WFQ_HIP(hipMemcpy(vl.data(), S.val, S.nnz * 8, hipMemcpyDeviceToHost));
+        WFQ_HIP(hipMemcpyAsync(rp.data(), S.rowptr, (S.n + 1) * 4, hipMemcpyDeviceToHost, h->stream));
+        WFQ_HIP(hipMemcpyAsync(cl.data(), S.col, S.nnz * 4, hipMemcpyDeviceToHost, h->stream));
+        WFQ_HIP(hipMemcpyAsync(vl.data(), S.val, S.nnz * 8, hipMemcpyDeviceToHost, h->stream));
+        WFQ_HIP(hipStreamSynchronize(h->stream));
         for (int64_t i = 0; i < S.n; ++i)
             for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
                 rows[p] = S.perm[i];

@@ -85,7 +85,10 @@ struct DevArray {
         count = c;
         if (c == 0) return;
         WFQ_HIP(hipMalloc(&p, c * sizeof(T)));
-        WFQ_HIP(hipMemset(p, 0, c * sizeof(T)));
+        // zero-fill on the null stream and wait for it: the solver's streams are non-blocking, so
+        // null-stream work is not ordered before their kernels otherwise
+        WFQ_HIP(hipMemsetAsync(p, 0, c * sizeof(T), nullptr));
+        WFQ_HIP(hipStreamSynchronize(nullptr));
     }
     ~DevArray() {
         if (p) (void)hipFree(p);
@@ -914,7 +917,7 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
     {
         DevArray<double> d_dirs;
         d_dirs.alloc((size_t)3 * n_dir);
-        WFQ_HIP(hipMemcpy(d_dirs.p, dirs, 3 * n_dir * sizeof(double), hipMemcpyHostToDevice));
+        WFQ_HIP(hipMemcpyAsync(d_dirs.p, dirs, 3 * n_dir * sizeof(double), hipMemcpyHostToDevice, st));
         build_rhs(S, d_dirs.p, n_dir, E0, w.b.p, S.npad, st);
         WFQ_HIP(hipStreamSynchronize(st));
     }
@@ -1003,16 +1006,19 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
         }
         if (out.alpha_re) {
             if (out.on_device)
-                WFQ_HIP(hipMemcpy(out.alpha_re + (size_t)s0 * 3, are.data(), nb * 3 * 8, hipMemcpyHostToDevice));
+                WFQ_HIP(hipMemcpyAsync(out.alpha_re + (size_t)s0 * 3, are.data(), nb * 3 * 8, hipMemcpyHostToDevice,
+                                       st));
             else
                 std::memcpy(out.alpha_re + (size_t)s0 * 3, are.data(), nb * 3 * 8);
         }
         if (out.alpha_im) {
             if (out.on_device)
-                WFQ_HIP(hipMemcpy(out.alpha_im + (size_t)s0 * 3, aim.data(), nb * 3 * 8, hipMemcpyHostToDevice));
+                WFQ_HIP(hipMemcpyAsync(out.alpha_im + (size_t)s0 * 3, aim.data(), nb * 3 * 8, hipMemcpyHostToDevice,
+                                       st));
             else
                 std::memcpy(out.alpha_im + (size_t)s0 * 3, aim.data(), nb * 3 * 8);
         }
+        if (out.on_device) WFQ_HIP(hipStreamSynchronize(st));   // are / aim are host temporaries
         for (int s = 0; s < nb; ++s) {
             const SysState& q = ss[s];
             if (out.info) {

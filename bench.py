@@ -290,7 +290,7 @@ def bench_batched(args, wl, wfq, torch):
                        iters_max=int(max(r["iters"] for r in ms["info"])),
                        relres_max=max(r["relres"] for r in ms["info"]),
                        statuses=sorted(set(r["status"] for r in ms["info"])),
-                       roofline=roofline_of(ms_stats, "fp64", False, wl.n, wl.name),
+                       roofline=roofline_of(ms_stats, "fp64", False, wl.n, f"{wl.name}_multishift"),
                        kernels=kernel_table(ms_stats))
         if "fp64_reference_systems" in extra and extra["fp64_reference_systems"] == S:
             qms = ms["q"].reshape(S, wl.n)
@@ -361,7 +361,9 @@ def bench_serve(args, wl, wfq, torch):
     """serve_mix: a seeded Poisson stream of spectrum jobs through the request loop."""
     import wfq_inputs as wi
     jobs = wi.serve_mix_jobs(n_jobs=args.jobs)
-    srv = wfq.wfq_serve(wl.tol, max_jobs=4, max_queue=4096, restart=wl.restart, precision=wl.precision)
+    prec = args.precision or wl.precision
+    algo = args.algorithm or wl.algorithm
+    srv = wfq.wfq_serve(wl.tol, max_jobs=4, max_queue=4096, restart=wl.restart, precision=prec, algorithm=algo)
     t0 = time.perf_counter()
     tickets = []
     for j in jobs:
@@ -380,10 +382,10 @@ def bench_serve(args, wl, wfq, torch):
     n_atoms = [len(j["xyz"]) for j in jobs]
     line = dict(metric=METRIC, value=systems / elapsed, unit="solves/s", n_gpus=1, steps=len(jobs), warmup=0,
                 ms_per_step=elapsed / len(jobs) * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
-                dtype="fp32-ir-fp64", data="synthetic",
+                dtype={"fp32": "fp32-ir-fp64", "bf16": "bf16-ir-fp64", "fp64": "fp64"}[prec], data="synthetic",
                 config=dict(workload=wl.name, jobs=len(jobs), rate_per_s=20.0, n_atoms_min=int(min(n_atoms)),
-                            n_atoms_max=int(max(n_atoms)), systems=systems, tol=wl.tol, precision=wl.precision,
-                            max_jobs=4, description=wl.description),
+                            n_atoms_max=int(max(n_atoms)), systems=systems, tol=wl.tol, precision=prec,
+                            algorithm=algo, max_jobs=4, description=wl.description),
                 p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                 queue_p50_ms=float(np.percentile(queue, 50)), queue_p99_ms=float(np.percentile(queue, 99)),
                 jobs_ok=int(ok), busy_frac=st["busy_frac"], max_resident=st["max_resident"],

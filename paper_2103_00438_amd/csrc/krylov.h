@@ -25,9 +25,10 @@ inline int64_t wave_chunks(int64_t n) { return (n + kWaveRows - 1) / kWaveRows; 
 void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, const double* scale, bool write_back,
                   void* X, int64_t ld, hipStream_t st);
 
-// V(s, jdst) = L Y[2k, 2k+1] + z_s V(s, jsrc) for the nsys systems (Y in FP32 or FP64).
+// V(s, jdst) = L Y[2k, 2k+1] + z_s V(s, jsrc) for the nsys systems (Y in FP32 or FP64); with
+// y_by_sys the rows of Y are addressed by system id (Y[2s, 2s+1]) instead of list position k.
 void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
-                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st);
+                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st, bool y_by_sys = false);
 
 // partial[s][i][wc] = sum over rows of wave chunk wc of conj(V(s, i)) * V(s, jw), i = 0..j; with
 // self_norm also partial[s][j+1][wc] = partial ||V(s, jw)||^2. Systems with active[s] == 0 are
@@ -95,11 +96,12 @@ constexpr int kQmrSlots = 7;
 void qmr_rho(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const Basis& Q, int64_t n,
              double2* partial, int nblk, hipStream_t st);
 // beta = rho_new / rho_old (0 where first[s]); p = r + beta p; T p = T r + beta T p
+// (T p is also written to tpb[2s, 2s+1] (FP64, leading dimension ld), the gather source of qmr_q)
 void qmr_dirs(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const Basis& Q, int64_t n,
-              const double2* rho_new, const double2* rho_old, const int* first, hipStream_t st);
+              const double2* rho_new, const double2* rho_old, const int* first, double* tpb, hipStream_t st);
 // q = L (T p) + z p with partials of sigma = (T p)^T q and of ||T p||^2, ||q||^2
-void qmr_q(const Structure& S, const int* sys, int nsys, const Basis& Q, const double2* z, double2* part_sig,
-           double2* part_nrm, int nblk, hipStream_t st);
+void qmr_q(const Structure& S, const int* sys, int nsys, const Basis& Q, const double2* z, const double* tpb,
+           double2* part_sig, double2* part_nrm, int nblk, hipStream_t st);
 // sigma[s] and breakdown flags (bit 3: Lanczos breakdown, bit 2: NaN)
 void qmr_sigma(const int* sys, int nsys, const double2* part_sig, const double2* part_nrm, int nblk,
                const double2* rho, double2* sigma, int* flags, hipStream_t st);

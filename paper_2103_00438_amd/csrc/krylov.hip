@@ -12,6 +12,9 @@ namespace wfq {
 
 namespace {
 
+// chunks x systems from which the one-wave-per-(chunk, system) Gram-Schmidt kernels fill the chip
+constexpr int64_t kWideWaves = 4096;
+
 __device__ inline double* vre(const Basis& V, int s, int j) { return V.base + (int64_t)s * V.sys_stride + (int64_t)j * V.vec_stride; }
 
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
@@ -98,7 +101,8 @@ __global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad,
                                                         const int32_t* __restrict__ ecol,
                                                         const double* __restrict__ eval, const YE* __restrict__ Y,
                                                         int64_t ld, const int* __restrict__ sys, int nsys, int per_group,
-                                                        const double2* __restrict__ z, Basis V, int jsrc, int jdst) {
+                                                        const double2* __restrict__ z, Basis V, int jsrc, int jdst,
+                                                        int y_by_sys) {
     extern __shared__ char smem[];
     double* lval = reinterpret_cast<double*>(smem);
     int32_t* lcol = reinterpret_cast<int32_t*>(smem + (size_t)w * R * sizeof(double));
@@ -120,7 +124,7 @@ __global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad,
     if (i >= n) return;
     const int k_end = min(nsys, (int)(blockIdx.y + 1) * per_group);
     for (int k = (int)blockIdx.y * per_group + wave * G + g; k < k_end; k += 4 * G) {
-        const YE* yr = Y + (int64_t)(2 * k) * ld;
+        const YE* yr = Y + (int64_t)(2 * (y_by_sys ? sys[k] : k)) * ld;
         const YE* yi = yr + ld;
         double ar = 0.0, ai = 0.0;
 #pragma unroll 4
@@ -142,7 +146,7 @@ __global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad,
 
 template <typename YE, int R>
 void launch_spmm_rows(const Structure& S, const YE* Y, int64_t ld, const int* sys, int nsys, const double2* z,
-                      const Basis& V, int jsrc, int jdst, hipStream_t st) {
+                      const Basis& V, int jsrc, int jdst, bool y_by_sys, hipStream_t st) {
     constexpr int G = 64 / R;
     const int64_t nb = S.npad / R;
     const int64_t nb8 = (nb + 7) / 8 * 8;
@@ -152,7 +156,54 @@ void launch_spmm_rows(const Structure& S, const YE* Y, int64_t ld, const int* sy
     const int per_group = (nsys + gy - 1) / gy;
     const size_t lds = (size_t)S.ell_w * R * 12;
     hipLaunchKernelGGL((spmm_rows_kernel<YE, R>), dim3((unsigned)nb8, (unsigned)gy), dim3(256), lds, st, S.n, S.npad,
-                       S.ell_w, S.ell_col, S.ell_val, Y, ld, sys, nsys, per_group, z, V, jsrc, jdst);
+                       S.ell_w, S.ell_col, S.ell_val, Y, ld, sys, nsys, per_group, z, V, jsrc, jdst, (int)y_by_sys);
+}
+
+// Dots for many systems at once: one wave per (512-row chunk, system) walks over the basis vectors
+// (enough waves to fill the chip when systems x chunks is large).
+__global__ void __launch_bounds__(256) dot_rows_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
+                                                  double2* __restrict__ partial, int mdim, int64_t nwc,
+                                                  const int* __restrict__ active, int self_norm) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
+    if (wc >= nwc) return;
+    const int s = sys[blockIdx.y];
+    if (active && !active[s]) return;
+    const double* wr = vre(V, s, jw);
+    const double* wi = wr + V.npad;
+    const int64_t row0 = wc * kWaveRows + lane;
+    double xr[8], xi[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        xr[r] = row < n ? wr[row] : 0.0;
+        xi[r] = row < n ? wi[row] : 0.0;
+    }
+    for (int i = 0; i <= j; ++i) {
+        const double* vr = vre(V, s, i);
+        const double* vi = vr + V.npad;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t row = row0 + 64 * r;
+            if (row < n) {
+                const double a = vr[row], b = vi[row];
+                sr += a * xr[r] + b * xi[r];   // conj(v) w
+                si += a * xi[r] - b * xr[r];
+            }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) partial[((int64_t)s * mdim + i) * nwc + wc] = make_double2(sr, si);
+    }
+    if (self_norm) {
+        // ||w||^2 in slot j + 1 (the reorthogonalisation test compares it with the projected norm)
+        double nn = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) nn += xr[r] * xr[r] + xi[r] * xi[r];
+        nn = wave_sum(nn);
+        if (lane == 0) partial[((int64_t)s * mdim + j + 1) * nwc + wc] = make_double2(nn, 0.0);
+    }
 }
 
 // Dots for the Arnoldi step: one wave per (512-row chunk, basis vector, system), so that even a
@@ -214,6 +265,59 @@ __global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const dou
     }
 }
 
+// Update for many systems at once: one wave per (512-row chunk, system), the chunk in registers.
+__global__ void __launch_bounds__(256) update_rows_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
+                                                     const double2* __restrict__ h, int mdim,
+                                                     double* __restrict__ norm2, int64_t nwc,
+                                                     const int* __restrict__ active) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
+    if (wc >= nwc) return;
+    const int s = sys[blockIdx.y];
+    if (active && !active[s]) return;
+    double* wr = vre(V, s, jw);
+    double* wi = wr + V.npad;
+    const int64_t row0 = wc * kWaveRows + lane;
+    double xr[8], xi[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        xr[r] = row < n ? wr[row] : 0.0;
+        xi[r] = row < n ? wi[row] : 0.0;
+    }
+    for (int i = 0; i <= j; ++i) {
+        const double2 hh = h[(int64_t)s * mdim + i];
+        const double* vr = vre(V, s, i);
+        const double* vi = vr + V.npad;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t row = row0 + 64 * r;
+            if (row < n) {
+                const double a = vr[row], b = vi[row];
+                xr[r] -= hh.x * a - hh.y * b;
+                xi[r] -= hh.x * b + hh.y * a;
+            }
+        }
+    }
+    double nn = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        if (row < n) {
+            wr[row] = xr[r];
+            wi[row] = xi[r];
+            nn += xr[r] * xr[r] + xi[r] * xi[r];
+        }
+    }
+    if (norm2) {
+        nn = wave_sum(nn);
+        if (lane == 0) norm2[(int64_t)s * nwc + wc] = nn;
+    }
+}
+
+// Daniel-Gragg-Kaufman-Stewart test: a second Gram-Schmidt pass is needed only when projecting
+// removed more than half of the vector's squared norm (||w'||^2 < ||w||^2 / 2). Systems that skip it
+// get h2 = 0 and keep the norm of the first pass.
 // V(s, jw) -= sum_{i <= j} h[s][i] V(s, i) for one 512-row chunk per work-group: each of the 4 waves
 // sums every 4th basis vector over the whole chunk, the partial sums meet in LDS and are combined
 // in a fixed order; norm2[s][wc] (if not NULL) = ||V(s, jw)||^2 over the chunk, also in fixed order.
@@ -524,7 +628,7 @@ void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, con
 }
 
 void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
-                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st) {
+                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st, bool y_by_sys) {
     if (nsys <= 0) return;
     // row-block kernel with the largest row block whose ELL rows fit in 40 KB of LDS (4 work-groups
     // per CU); the per-thread kernel only for neighbour lists too long even for 8 rows
@@ -534,20 +638,21 @@ void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, co
     if (R > 0) {
         if (y_is_f64) {
             const double* Yd = static_cast<const double*>(Y);
-            if (R == 64) launch_spmm_rows<double, 64>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, st);
-            else if (R == 32) launch_spmm_rows<double, 32>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, st);
-            else if (R == 16) launch_spmm_rows<double, 16>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, st);
-            else launch_spmm_rows<double, 8>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, st);
+            if (R == 64) launch_spmm_rows<double, 64>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
+            else if (R == 32) launch_spmm_rows<double, 32>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
+            else if (R == 16) launch_spmm_rows<double, 16>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
+            else launch_spmm_rows<double, 8>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
         } else {
             const float* Yf = static_cast<const float*>(Y);
-            if (R == 64) launch_spmm_rows<float, 64>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, st);
-            else if (R == 32) launch_spmm_rows<float, 32>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, st);
-            else if (R == 16) launch_spmm_rows<float, 16>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, st);
-            else launch_spmm_rows<float, 8>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, st);
+            if (R == 64) launch_spmm_rows<float, 64>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
+            else if (R == 32) launch_spmm_rows<float, 32>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
+            else if (R == 16) launch_spmm_rows<float, 16>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
+            else launch_spmm_rows<float, 8>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
         }
         WFQ_CHECK_LAUNCH();
         return;
     }
+    if (y_by_sys) throw Error{WFQ_EINVAL, "neighbour lists too long for the sparse product"};
     constexpr int NS = 8;
     dim3 grd((unsigned)((S.n + 255) / 256), (unsigned)((nsys + NS - 1) / NS));
     if (y_is_f64)
@@ -563,9 +668,15 @@ void multi_dot(const Basis& V, int64_t n, const int* sys, int nsys, int j, int j
                hipStream_t st, const int* active, bool self_norm) {
     if (nsys <= 0) return;
     const int64_t nwc = wave_chunks(n);
-    dim3 grd((unsigned)nwc, (unsigned)((j + 1 + (self_norm ? 1 : 0) + 3) / 4), (unsigned)nsys);
-    hipLaunchKernelGGL(dot_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, partial, mdim, nwc, active,
-                       (int)self_norm);
+    if (nwc * nsys >= kWideWaves) {
+        dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
+        hipLaunchKernelGGL(dot_rows_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, partial, mdim, nwc, active,
+                           (int)self_norm);
+    } else {
+        dim3 grd((unsigned)nwc, (unsigned)((j + 1 + (self_norm ? 1 : 0) + 3) / 4), (unsigned)nsys);
+        hipLaunchKernelGGL(dot_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, partial, mdim, nwc, active,
+                           (int)self_norm);
+    }
     WFQ_CHECK_LAUNCH();
 }
 
@@ -581,8 +692,13 @@ void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, in
                   double* norm2, hipStream_t st, const int* active) {
     if (nsys <= 0) return;
     const int64_t nwc = wave_chunks(n);
-    dim3 grd((unsigned)nwc, (unsigned)nsys);
-    hipLaunchKernelGGL(update_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, h, mdim, norm2, nwc, active);
+    if (nwc * nsys >= kWideWaves) {
+        dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
+        hipLaunchKernelGGL(update_rows_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, h, mdim, norm2, nwc, active);
+    } else {
+        dim3 grd((unsigned)nwc, (unsigned)nsys);
+        hipLaunchKernelGGL(update_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, h, mdim, norm2, nwc, active);
+    }
     WFQ_CHECK_LAUNCH();
 }
 

@@ -54,7 +54,8 @@ __global__ void __launch_bounds__(256) rho_kernel(const YE* __restrict__ Y, int6
 template <typename YE>
 __global__ void __launch_bounds__(256) dirs_kernel(const YE* __restrict__ Y, int64_t ld, const int* __restrict__ sys,
                                                    Basis Q, int64_t n, const double2* __restrict__ rho_new,
-                                                   const double2* __restrict__ rho_old, const int* __restrict__ first) {
+                                                   const double2* __restrict__ rho_old, const int* __restrict__ first,
+                                                   double* __restrict__ tpb) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int k = blockIdx.y;
@@ -75,37 +76,26 @@ __global__ void __launch_bounds__(256) dirs_kernel(const YE* __restrict__ Y, int
     p[i + o] = r[i + o] + br * pi + bi * pr;
     const double tr = widen(Y[(int64_t)(2 * k) * ld + i]), ti = widen(Y[(int64_t)(2 * k + 1) * ld + i]);
     const double qr = tp[i], qi = tp[i + o];
-    tp[i] = tr + br * qr - bi * qi;
-    tp[i + o] = ti + br * qi + bi * qr;
+    const double nr = tr + br * qr - bi * qi, ni = ti + br * qi + bi * qr;
+    tp[i] = nr;
+    tp[i + o] = ni;
+    tpb[(int64_t)(2 * s) * ld + i] = nr;
+    tpb[(int64_t)(2 * s + 1) * ld + i] = ni;
 }
 
-// q = L (T p) + z p; partial sums of sigma = (T p)^T q, ||T p||^2, ||q||^2
-__global__ void __launch_bounds__(256) q_kernel(int64_t n, int64_t npad, int w, const int32_t* __restrict__ ecol,
-                                                const double* __restrict__ eval, const int* __restrict__ sys,
-                                                const double2* __restrict__ z, Basis Q, double2* __restrict__ part_sig,
-                                                double2* __restrict__ part_nrm, int nblk) {
+// partial sums over 256-row blocks of sigma = (T p)^T q, ||T p||^2 and ||q||^2
+__global__ void __launch_bounds__(256) q_sums_kernel(int64_t n, const int* __restrict__ sys, Basis Q,
+                                                     double2* __restrict__ part_sig, double2* __restrict__ part_nrm,
+                                                     int nblk) {
     __shared__ double sh[4];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int s = sys[blockIdx.y];
     double sr = 0.0, si = 0.0, nt = 0.0, nq = 0.0;
     if (i < n) {
-        const double* tp = slot(Q, s, 2);
-        const double* p = slot(Q, s, 1);
-        double* q = slot(Q, s, 3);
         const int64_t o = Q.npad;
-        double ar = 0.0, ai = 0.0;
-        for (int t = 0; t < w; ++t) {
-            const int c = ecol[(int64_t)t * npad + i];
-            const double v = eval[(int64_t)t * npad + i];
-            ar += v * tp[c];
-            ai += v * tp[c + o];
-        }
-        const double2 zz = z[s];
-        const double pr = p[i], pi = p[i + o];
-        const double qr = ar + zz.x * pr - zz.y * pi, qi = ai + zz.x * pi + zz.y * pr;
-        q[i] = qr;
-        q[i + o] = qi;
-        const double tr = tp[i], ti = tp[i + o];
+        const double* tp = slot(Q, s, 2);
+        const double* q = slot(Q, s, 3);
+        const double qr = q[i], qi = q[i + o], tr = tp[i], ti = tp[i + o];
         sr = tr * qr - ti * qi;
         si = tr * qi + ti * qr;
         nt = tr * tr + ti * ti;
@@ -121,7 +111,6 @@ __global__ void __launch_bounds__(256) q_kernel(int64_t n, int64_t npad, int w, 
     }
 }
 
-// alpha = rho / sigma; x += alpha p; r -= alpha q; partial ||r||^2
 __global__ void __launch_bounds__(256) xr_kernel(const int* __restrict__ sys, Basis Q, int64_t n,
                                                  const double2* __restrict__ rho, const double2* __restrict__ sigma,
                                                  double* __restrict__ norm2, int nblk) {
@@ -258,24 +247,25 @@ void qmr_rho(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
 }
 
 void qmr_dirs(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const Basis& Q, int64_t n,
-              const double2* rho_new, const double2* rho_old, const int* first, hipStream_t st) {
+              const double2* rho_new, const double2* rho_old, const int* first, double* tpb, hipStream_t st) {
     if (nsys <= 0) return;
     dim3 grd((unsigned)((n + 255) / 256), (unsigned)nsys);
     if (y_is_f64)
         hipLaunchKernelGGL(dirs_kernel<double>, grd, dim3(256), 0, st, static_cast<const double*>(Y), ld, sys, Q, n,
-                           rho_new, rho_old, first);
+                           rho_new, rho_old, first, tpb);
     else
         hipLaunchKernelGGL(dirs_kernel<float>, grd, dim3(256), 0, st, static_cast<const float*>(Y), ld, sys, Q, n,
-                           rho_new, rho_old, first);
+                           rho_new, rho_old, first, tpb);
     WFQ_CHECK_LAUNCH();
 }
 
-void qmr_q(const Structure& S, const int* sys, int nsys, const Basis& Q, const double2* z, double2* part_sig,
-           double2* part_nrm, int nblk, hipStream_t st) {
+void qmr_q(const Structure& S, const int* sys, int nsys, const Basis& Q, const double2* z, const double* tpb,
+           double2* part_sig, double2* part_nrm, int nblk, hipStream_t st) {
     if (nsys <= 0) return;
+    // q (slot 3) = L (T p) + z p (slot 1), gathering T p from the compact block written by qmr_dirs
+    spmm_shift(S, true, tpb, S.npad, sys, nsys, z, Q, 1, 3, st, true);
     dim3 grd((unsigned)nblk, (unsigned)nsys);
-    hipLaunchKernelGGL(q_kernel, grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col, S.ell_val, sys, z, Q,
-                       part_sig, part_nrm, nblk);
+    hipLaunchKernelGGL(q_sums_kernel, grd, dim3(256), 0, st, S.n, sys, Q, part_sig, part_nrm, nblk);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -143,7 +143,7 @@ struct Work {
     DevArray<double2> partial, h1, h2, R, sn, g, y, z, alpha;
     // QMR scalars and partials
     DevArray<double2> rho_a, rho_b, sigma, part_sig, part_nrm;
-    DevArray<double> tau2, eta, snorm;
+    DevArray<double> tau2, eta, snorm, tpb;
     DevArray<int> first;
     PinnedArray<double> h_snorm;
     DevArray<int> flags, ksteps, dir, sys[NSLOT];
@@ -153,7 +153,7 @@ struct Work {
     Basis Vb, Xb;
 };
 
-void alloc_work(Work& w, const Structure& S, int B, int m, int n_dir, int prec) {
+void alloc_work(Work& w, const Structure& S, int B, int m, int n_dir, int prec, bool qmr = false) {
     w.B = B;
     w.mdim = m + 1;
     w.n_dir = n_dir;
@@ -221,6 +221,7 @@ void alloc_work(Work& w, const Structure& S, int B, int m, int n_dir, int prec) 
     w.snorm.alloc(B);
     w.first.alloc(B);
     w.h_snorm.alloc(B);
+    if (qmr) w.tpb.alloc((size_t)B * 2 * np);   // QMR: compact T p, rows by system id
     w.Vb = Basis{w.V.p, (int64_t)w.mdim * 2 * np, 2 * np, np};
     w.Xb = Basis{w.X.p, 2 * np, 2 * np, np};
 }
@@ -767,13 +768,13 @@ void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double to
                 qmr_rho(p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, Q, S.n, w.part_sig.p, nblk, st);
                 reduce_complex(w.sys[p].p, ng, w.part_sig.p, nblk, rho_new, st);
                 qmr_dirs(p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, Q, S.n, rho_new, rho_old,
-                         w.first.p, st);
+                         w.first.p, w.tpb.p, st);
                 tm.end(st, KC_QMR, 0, ng * n * (16.0 * 5 + 4 * out_size(p)));
             }
             upload(w, SLOT_STEP, stepping, st);
             const int* sl = w.sys[SLOT_STEP].p;
             tm.begin(st);
-            qmr_q(S, sl, ns, Q, w.z.p, w.part_sig.p, w.part_nrm.p, nblk, st);
+            qmr_q(S, sl, ns, Q, w.z.p, w.tpb.p, w.part_sig.p, w.part_nrm.p, nblk, st);
             tm.end(st, KC_SPMM, 4.0 * S.nnz * ns, 12.0 * S.nnz + ns * n * 48.0);
             tm.begin(st);
             qmr_sigma(sl, ns, w.part_sig.p, w.part_nrm.p, nblk, rho_new, w.sigma.p, w.flags.p, st);
@@ -884,6 +885,7 @@ uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_d
     b += (uint64_t)B * (mdim * 64 + 2 * np * 8 / 1);  // small arrays + output staging
     b += std::min<uint64_t>(kSplitWsCap, 7 * mpad * np * 8);   // split-k partial tiles
     if (o.algorithm == WFQ_MSGMRES) b += ms_bytes(S, o, B, n_dir);
+    if (o.algorithm == WFQ_QMR) b += (uint64_t)B * 2 * np * 8;   // compact T p
     return b;
 }
 
@@ -911,7 +913,7 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
 
     Work w;
     const bool qmr = o.algorithm == WFQ_QMR;
-    alloc_work(w, S, B, qmr ? kQmrSlots - 1 : o.restart, n_dir, prec);
+    alloc_work(w, S, B, qmr ? kQmrSlots - 1 : o.restart, n_dir, prec, qmr);
     if (qmr) w.Xb = slot_view(w.Vb, 5);   // the QMR iterate is the solution
     // right-hand sides b_k = E0 L r_k (shared by every frequency)
     {

@@ -112,23 +112,27 @@ def kernel_table(stats):
 
 
 def measured_traffic(workload, kernel):
-    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary of this workload
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size); None when there is none or the
-    kernel source changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{workload}_rocprof.md")
-    if not os.path.exists(path):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter summary of this workload
+    (profiles/*.md; FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size); None when there
+    is none or the kernel source changed since the counters were taken."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
         return None
-    with open(path) as f:
-        m = re.search(r"<!-- traffic (\{.*\}) -->", f.read())
-    if not m:
-        return None
-    rec = json.loads(m.group(1))
-    if rec.get("kernel") != kernel:
-        return None
-    with open(os.path.join(ROOT, rec["source"]), "rb") as f:
-        if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
-            return None
-    return rec["bytes_per_launch"]
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            m = re.search(r"<!-- traffic (\{.*\}) -->", f.read())
+        if not m:
+            continue
+        rec = json.loads(m.group(1))
+        if rec.get("workload") != workload or rec.get("kernel") != kernel:
+            continue
+        with open(os.path.join(ROOT, rec["source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["source_sha256"]:
+                return None
+        return rec["bytes_per_launch"]
+    return None
 
 
 def roofline_of(stats, prec, otf, n, workload=None):
@@ -145,8 +149,9 @@ def roofline_of(stats, prec, otf, n, workload=None):
         avg_s = st["ms"] / max(1, st["launches"]) / 1e3
         achieved = st["flops"] / max(1, st["launches"]) / avg_s / 1e12 if avg_s > 0 else 0.0
         peak = PEAKS["fp32" if prec == "fp32" else "fp64"]
-        return dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak, traffic=None,
-                    kernel=key, launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
+        return dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                    traffic=measured_traffic(workload, key), kernel=key, launches=st["launches"],
+                    avg_launch_ms=st["ms"] / max(1, st["launches"]),
                     pairs_per_launch=pairs, pairs_per_s=pairs / avg_s if avg_s > 0 else 0.0)
     # the T-product class that took the most time (systems may have escalated to another precision)
     classes = {"tx_gemm_f32": "fp32", "tx_gemm_f64": "fp64", "tx_gemm_bf16": "bf16", "tx_skinny": None}

@@ -61,6 +61,25 @@ def test_mix_equals_alone(lib):
     assert np.linalg.norm(q - ref) / np.linalg.norm(ref) <= 1e-6
 
 
+def test_mix_equals_alone_multishift(lib):
+    # the request loop with one shared Krylov basis per job and direction (FP64 T)
+    tol = 1e-8
+    js = jobs()
+    srv = lib.wfq_serve(tol, max_jobs=3, max_queue=64, restart=40, precision="fp64", algorithm="msgmres")
+    tickets = [lib.wfq_submit(srv, xyz, GRAPHENE, om, d) for xyz, om, d in js]
+    results = [lib.wfq_wait(srv, t) for t in tickets]
+    lib.wfq_serve_stop(srv)
+    for (xyz, om, d), res in zip(js, results):
+        assert res["status"] == 0
+        h = lib.wfq_build(xyz, GRAPHENE)
+        alone = lib.wfq_solve(h, om, d, tol, restart=40, precision="fp64", algorithm="msgmres")
+        batched = lib.wfq_solve(h, om, d, tol, restart=40, precision="fp64")
+        h.close()
+        assert np.linalg.norm(res["q"] - alone["q"]) / np.linalg.norm(alone["q"]) <= 1e-12   # deterministic
+        assert np.linalg.norm(res["q"] - batched["q"]) / np.linalg.norm(batched["q"]) <= 1e-6
+        assert all(i["relres"] <= tol for i in res["info"])
+
+
 def test_queue_limit_and_tickets(lib):
     xyz, om, d = jobs()[3]
     srv = lib.wfq_serve(1e-8, max_jobs=1, max_queue=2, restart=40, precision="fp32")

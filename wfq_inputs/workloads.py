@@ -6,6 +6,7 @@ each with a fixed seed:
 * ``disk600``   graphene disk, ~600 atoms, one frequency, field along x, FP64 GMRES(50).
 * ``cnt20k``    armchair (10,10) nanotube, 20 000 atoms, 64 frequencies x 3 fields,
                 FP32 stored T inside FP64 refinement.
+* ``disk600_spectrum`` the same disk over 200 frequencies x 3 directions (one shared basis each).
 * ``fcc120k``   FCC metal sphere (a = 4.09 Angstrom), ~120 000 atoms, 128 x 3 systems,
                 BF16 stored T inside FP64 refinement.
 * ``serve_mix`` Poisson stream of spectrum jobs (disks, ribbons, (n,n) tubes).
@@ -87,6 +88,17 @@ def _disk600() -> Workload:
                     description="graphene disk R=22.37 A, 1 frequency (0.3 eV), field x, GMRES(50), relres 1e-10")
 
 
+def _disk600_spectrum() -> Workload:
+    # the same disk over a 200-point spectrum, 0.01..2.00 eV (the paper's "0.0 to 2.0 in steps of
+    # 0.01" grid without the singular omega = 0), three field directions, one basis per direction
+    xyz = geo.jitter(geo.graphene_disk(22.37), 0.01, seed=1)
+    om = np.linspace(0.01, 2.0, 200)
+    return Workload("disk600_spectrum", xyz, dict(GRAPHENE), om, DIRS_XYZ.copy(),
+                    tol=1e-10, restart=50, precision="fp64", algorithm="msgmres",
+                    description="graphene disk R=22.37 A, 200 frequencies 0.01-2.0 eV x 3 directions, "
+                                "multi-shift GMRES, FP64, relres 1e-10")
+
+
 def _cnt20k() -> Workload:
     xyz = geo.jitter(geo.nanotube(10, 10, 500), 0.01, seed=2)
     om = np.linspace(0.05, 1.0, 64)
@@ -151,6 +163,7 @@ def _serve_mix() -> Workload:
 
 WORKLOADS = {
     "disk600": _disk600,
+    "disk600_spectrum": _disk600_spectrum,
     "cnt20k": _cnt20k,
     "fcc120k": _fcc120k,
     "serve_mix": _serve_mix,

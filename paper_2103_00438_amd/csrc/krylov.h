@@ -22,8 +22,9 @@ inline int64_t wave_chunks(int64_t n) { return (n + kWaveRows - 1) / kWaveRows; 
 
 // X[2k + plane][i] = cast(V(sys[k], j)[plane][i] * scale[sys[k]]) for i < npad (scale may be NULL);
 // with write_back the scaled FP64 value is also stored back into V. prec = WFQ_PREC_*.
+// With run != NULL, systems with run[s] == 0 get zero columns (and V is left alone).
 void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, const double* scale, bool write_back,
-                  void* X, int64_t ld, hipStream_t st);
+                  void* X, int64_t ld, hipStream_t st, const int* run = nullptr);
 
 // V(s, jdst) = L Y[2k, 2k+1] + z_s V(s, jsrc) for the nsys systems (Y in FP32 or FP64); with
 // y_by_sys the rows of Y are addressed by system id (Y[2s, 2s+1]) instead of list position k.
@@ -43,7 +44,7 @@ void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, in
                   double* norm2, hipStream_t st, const int* active = nullptr);
 // reorth[s] = (||w'||^2 < ||w||^2 / 2) with ||w||^2 from h1[s][j+1] and ||w'||^2 from norm2a; h2 = 0 where not needed
 void reorth_test(const int* sys, int nsys, int j, int mdim, const double2* h1, const double* norm2a, int64_t n,
-                 double2* h2, int* reorth, hipStream_t st);
+                 double2* h2, int* reorth, hipStream_t st, const int* run = nullptr);
 
 struct GivensArgs {
     const double2* h1;   // [S][mdim] first CGS pass
@@ -60,6 +61,9 @@ struct GivensArgs {
     double* inv_h;       // [S] 1 / h_{j+1,j} (normalisation of the next basis vector)
     const double* tol_abs;  // [S]
     int* flags;          // [S] bit0: converged (estimate), bit1: happy breakdown, bit2: NaN
+    int* ksteps = nullptr;  // [S] (optional) steps taken in this cycle, written every step
+    int* run = nullptr;     // [S] (optional) 1 while the system steps; cleared when a flag is raised,
+                            // after which every step kernel that takes `run` skips the system
 };
 void givens_step(const int* sys, int nsys, int j, int mdim, const GivensArgs& a, hipStream_t st);
 

@@ -37,10 +37,15 @@ __device__ inline double block_sum(double v, double* sh) {
 template <typename E>
 __global__ void __launch_bounds__(256) pack_kernel(Basis V, const int* __restrict__ sys, int j,
                                                    const double* __restrict__ scale, int write_back, E* __restrict__ X,
-                                                   int64_t ld) {
+                                                   int64_t ld, const int* __restrict__ run) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int k = blockIdx.y;
     const int s = sys[k];
+    if (run && !run[s]) {   // a system that stopped inside this chunk of steps: zero columns
+        X[(int64_t)(2 * k) * ld + i] = cast_from_double<E>(0.0);
+        X[(int64_t)(2 * k + 1) * ld + i] = cast_from_double<E>(0.0);
+        return;
+    }
     double* re = vre(V, s, j);
     double* im = re + V.npad;
     const double sc = scale ? scale[s] : 1.0;
@@ -380,10 +385,14 @@ __global__ void __launch_bounds__(256) update_kernel(Basis V, int64_t n, const i
 
 __global__ void reorth_test_kernel(const int* __restrict__ sys, int nsys, int j, int mdim,
                                    const double2* __restrict__ h1, const double* __restrict__ norm2a, int nwc,
-                                   double2* __restrict__ h2, int* __restrict__ reorth) {
+                                   double2* __restrict__ h2, int* __restrict__ reorth, const int* __restrict__ run) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsys) return;
     const int s = sys[k];
+    if (run && !run[s]) {
+        reorth[s] = 0;
+        return;
+    }
     double nw = 0.0;
     for (int w = 0; w < nwc; ++w) nw += norm2a[(int64_t)s * nwc + w];
     const double w2 = h1[(int64_t)s * mdim + j + 1].x;
@@ -398,6 +407,7 @@ __global__ void givens_kernel(const int* __restrict__ sys, int nsys, int j, int 
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsys) return;
     const int s = sys[k];
+    if (a.run && !a.run[s]) return;   // stopped earlier in this chunk of steps
     double2* col = a.R + ((int64_t)s * mdim + j) * mdim;
     for (int i = 0; i <= j; ++i) col[i] = cadd(a.h1[(int64_t)s * mdim + i], a.h2[(int64_t)s * mdim + i]);
     double hn2 = 0.0;
@@ -442,6 +452,8 @@ __global__ void givens_kernel(const int* __restrict__ sys, int nsys, int j, int 
     if (hn <= 1e-14 * cabs2(col[j])) f |= 2;
     if (!(est == est) || !(hn == hn)) f |= 4;
     a.flags[s] = f;
+    if (a.ksteps) a.ksteps[s] = j + 1;
+    if (a.run && f) a.run[s] = 0;
 }
 
 // One wave per system: column-oriented back substitution on R y = g (k <= mdim - 1 steps).
@@ -612,18 +624,18 @@ __global__ void __launch_bounds__(256) scatter_kernel(int64_t n, const int32_t* 
 }  // namespace
 
 void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, const double* scale, bool write_back,
-                  void* X, int64_t ld, hipStream_t st) {
+                  void* X, int64_t ld, hipStream_t st, const int* run) {
     if (nsys <= 0) return;
     dim3 grd((unsigned)(V.npad / 256), (unsigned)nsys);
     if (prec == WFQ_PREC_FP64)
         hipLaunchKernelGGL(pack_kernel<double>, grd, dim3(256), 0, st, V, sys, j, scale, (int)write_back,
-                           static_cast<double*>(X), ld);
+                           static_cast<double*>(X), ld, run);
     else if (prec == WFQ_PREC_FP32)
         hipLaunchKernelGGL(pack_kernel<float>, grd, dim3(256), 0, st, V, sys, j, scale, (int)write_back,
-                           static_cast<float*>(X), ld);
+                           static_cast<float*>(X), ld, run);
     else
         hipLaunchKernelGGL(pack_kernel<uint16_t>, grd, dim3(256), 0, st, V, sys, j, scale, (int)write_back,
-                           static_cast<uint16_t*>(X), ld);
+                           static_cast<uint16_t*>(X), ld, run);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -703,10 +715,10 @@ void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, in
 }
 
 void reorth_test(const int* sys, int nsys, int j, int mdim, const double2* h1, const double* norm2a, int64_t n,
-                 double2* h2, int* reorth, hipStream_t st) {
+                 double2* h2, int* reorth, hipStream_t st, const int* run) {
     if (nsys <= 0) return;
     hipLaunchKernelGGL(reorth_test_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sys, nsys, j, mdim, h1, norm2a,
-                       (int)wave_chunks(n), h2, reorth);
+                       (int)wave_chunks(n), h2, reorth, run);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -146,7 +146,7 @@ struct Work {
     DevArray<double> tau2, eta, snorm, tpb;
     DevArray<int> first;
     PinnedArray<double> h_snorm;
-    DevArray<int> flags, ksteps, dir, sys[NSLOT];
+    DevArray<int> flags, ksteps, dir, run, sys[NSLOT];
     PinnedArray<int> h_sys[NSLOT], h_flags, h_ksteps;
     PinnedArray<double> h_est, h_beta, h_invb;
     PinnedArray<double2> h_g, h_alpha;
@@ -199,6 +199,7 @@ void alloc_work(Work& w, const Structure& S, int B, int m, int n_dir, int prec, 
     w.cond.alloc(B);
     w.flags.alloc(B);
     w.ksteps.alloc(B);
+    w.run.alloc(B);
     w.dir.alloc(B);
     for (int k = 0; k < NSLOT; ++k) {
         w.sys[k].alloc(B);
@@ -380,18 +381,40 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         std::vector<int> stepping;
         for (int s : active)
             if (ss[s].iters < o.max_iter) stepping.push_back(s);
+        // Convergence is tracked on the device (the Givens step records the step count and clears
+        // run[s] when a flag is raised; every step kernel skips stopped systems). The host reads the
+        // flags and compacts the lists every `chunk` steps: after every step for large problems, whose
+        // block products shrink as systems drop out, and every 8 steps for small ones, where the
+        // round trip would cost more than the steps.
+        const int chunk = (S.npad <= 8192) ? 8 : 1;
+        WFQ_HIP(hipMemcpyAsync(w.ksteps.p, w.h_ksteps.p, B * sizeof(int), hipMemcpyHostToDevice, st));
+        GivensArgs gc = ga;
+        gc.ksteps = w.ksteps.p;
+        gc.run = w.run.p;
+        std::vector<int> grp[3];
+        auto lists = [&]() {   // upload the group lists, the step list and run = 1 for them
+            for (int p = 0; p < 3; ++p) grp[p].clear();
+            for (int s : stepping) grp[ss[s].prec].push_back(s);
+            for (int p = 0; p < 3; ++p)
+                if (!grp[p].empty()) upload(w, p, grp[p], st);
+            upload(w, SLOT_STEP, stepping, st);
+            std::vector<int> runh(B, 0);
+            for (int s : stepping) runh[s] = 1;
+            WFQ_HIP(hipMemcpyAsync(w.run.p, runh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+            WFQ_HIP(hipStreamSynchronize(st));   // runh is a host temporary
+        };
+        lists();
+        int since_sync = 0;
         for (int j = 0; j < m && !stepping.empty(); ++j) {
             const int ns = (int)stepping.size();
+            const int* run = chunk > 1 ? w.run.p : nullptr;
             // the operator on the new basis vectors, one block product per precision group
-            std::vector<int> grp[3];
-            for (int s : stepping) grp[ss[s].prec].push_back(s);
             for (int p = 0; p < 3; ++p) {
                 if (grp[p].empty()) continue;
                 const int ng = (int)grp[p].size();
-                upload(w, p, grp[p], st);
                 tm.begin(st);
                 pack_columns(p, w.Vb, w.sys[p].p, ng, j, j == 0 ? w.inv_beta.p : w.inv_h.p, true, x_block(w, p),
-                             w.npad, st);
+                             w.npad, st, run);
                 tm.end(st, KC_PACK, 0, ng * n * (32.0 + 2 * elem_size(p)));
                 block_product(S, w, p, 2 * ng, tm, st);
                 tm.begin(st);
@@ -400,17 +423,16 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                        12.0 * S.nnz + ng * n * (2.0 * out_size(p) + 16 + 16));
             }
             // CGS2 against v_0 .. v_j, then the Givens update of the least-squares problem
-            upload(w, SLOT_STEP, stepping, st);
             const int* sl = w.sys[SLOT_STEP].p;
             // first pass (with ||w||^2), the reorthogonalisation test, and the second pass only
             // for the systems that need it
             tm.begin(st);
-            multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, nullptr, true);
-            reduce_dots(S.n, sl, ns, j + 1, w.partial.p, w.mdim, w.h1.p, st);
+            multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, run, true);
+            reduce_dots(S.n, sl, ns, j + 1, w.partial.p, w.mdim, w.h1.p, st, run);
             tm.end(st, KC_DOT, 8.0 * n * ns * (j + 2), 16.0 * n * ns * (j + 2));
             tm.begin(st);
-            multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h1.p, w.mdim, w.norm2a.p, st);
-            reorth_test(sl, ns, j, w.mdim, w.h1.p, w.norm2a.p, S.n, w.h2.p, w.reorth.p, st);
+            multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h1.p, w.mdim, w.norm2a.p, st, run);
+            reorth_test(sl, ns, j, w.mdim, w.h1.p, w.norm2a.p, S.n, w.h2.p, w.reorth.p, st, run);
             tm.end(st, KC_UPDATE, 8.0 * n * ns * (j + 1), 16.0 * n * ns * (j + 3));
             tm.begin(st);
             multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, w.reorth.p, false);
@@ -420,15 +442,21 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h2.p, w.mdim, w.norm2.p, st, w.reorth.p);
             tm.end(st, KC_UPDATE, 0, 0);
             tm.begin(st);
-            givens_step(sl, ns, j, w.mdim, ga, st);
+            givens_step(sl, ns, j, w.mdim, gc, st);
             tm.end(st, KC_GIVENS, 0, 0);
+            ++since_sync;
+            // read back every `chunk` steps, at the end of the cycle, and before any system could pass
+            // max_iter inside the chunk
+            int room = 1 << 30;
+            for (int s : stepping) room = std::min(room, o.max_iter - ss[s].iters - since_sync);
+            if (since_sync < chunk && j + 1 < m && room > 0) continue;
             WFQ_HIP(hipMemcpyAsync(w.h_flags.p, w.flags.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
             WFQ_HIP(hipMemcpyAsync(w.h_est.p, w.est.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+            WFQ_HIP(hipMemcpyAsync(w.h_ksteps.p, w.ksteps.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
             WFQ_HIP(hipStreamSynchronize(st));
             std::vector<int> next;
             for (int s : stepping) {
-                w.h_ksteps.p[s] = j + 1;
-                ss[s].iters += 1;
+                ss[s].iters += since_sync - (j + 1 - w.h_ksteps.p[s]);   // steps this system took in the chunk
                 ss[s].est_end = w.h_est.p[s];
                 const int f = w.h_flags.p[s];
                 if (f & 4) {
@@ -437,7 +465,10 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                 }
                 if (f == 0 && ss[s].iters < o.max_iter) next.push_back(s);
             }
+            since_sync = 0;
+            const bool changed = next.size() != stepping.size();
             stepping.swap(next);
+            if (changed && !stepping.empty()) lists();
             if ((j + 1) % 10 == 0) progress_line(o, "gmres", ss[active[0]].cycles, j + 1, stepping.size(), -1.0, t0);
         }
         // drop systems that hit NaN

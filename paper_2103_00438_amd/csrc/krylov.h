@@ -147,10 +147,12 @@ void ms_update(double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, 
 // Hessenberg column j from the two Gram-Schmidt passes and the norm; inv_h[d] = 1 / H_{j+1,j}
 void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const double* h2, int pslots,
              const double* norm, int64_t n, int64_t npad, double* H, double* inv_h, hipStream_t st);
-// Givens step j of each listed system on Hbar + z Ibar of its direction (flags as in givens_step)
+// Givens step j of each listed system on Hbar + z Ibar of its direction (flags as in givens_step);
+// systems with run[s] == 0 are skipped, ksteps[s] = j + 1 is recorded and run[s] cleared when a flag
+// is raised.
 void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const double2* z, const double* H, double* cs,
                double2* sn, double2* g, double2* R, int64_t rstride, double* est, const double* tol_abs, int* flags,
-               hipStream_t st);
+               int* run, int* ksteps, hipStream_t st);
 // y = R^-1 g over k[s] columns; cond = max|R_ii| / min|R_ii|
 void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t rstride, const double2* g,
               double2* y, double* cond, hipStream_t st);

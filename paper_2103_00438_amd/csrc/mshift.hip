@@ -163,10 +163,11 @@ __global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, i
                                  const double2* __restrict__ z, const double* __restrict__ H, double* __restrict__ cs,
                                  double2* __restrict__ sn, double2* __restrict__ g, double2* __restrict__ R,
                                  int64_t rstride, double* __restrict__ est, const double* __restrict__ tol_abs,
-                                 int* __restrict__ flags) {
+                                 int* __restrict__ flags, int* __restrict__ run, int* __restrict__ ksteps) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsys) return;
     const int s = sys[k];
+    if (!run[s]) return;   // stopped earlier in this chunk of steps
     const double* hc = H + ((int64_t)sdir[s] * m + j) * (m + 1);
     double2* col = R + (int64_t)s * rstride + (int64_t)j * (j + 1) / 2;
     for (int i = 0; i <= j; ++i) col[i] = make_double2(hc[i], 0.0);
@@ -209,6 +210,8 @@ __global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, i
     if (hn <= 1e-14 * cabs(col[j])) f |= 2;   // the Krylov space is invariant: the iterate is exact
     if (!(e == e) || !(hn == hn)) f |= 4;
     flags[s] = f;
+    ksteps[s] = j + 1;
+    if (f) run[s] = 0;
 }
 
 // y = R^-1 g over the first k[s] columns, one work-group per system: column-oriented back
@@ -354,10 +357,10 @@ void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const do
 
 void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const double2* z, const double* H, double* cs,
                double2* sn, double2* g, double2* R, int64_t rstride, double* est, const double* tol_abs, int* flags,
-               hipStream_t st) {
+               int* run, int* ksteps, hipStream_t st) {
     if (nsys <= 0) return;
     hipLaunchKernelGGL(ms_givens_kernel, dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st, sys, nsys, j, m, sdir, z,
-                       H, cs, sn, g, R, rstride, est, tol_abs, flags);
+                       H, cs, sn, g, R, rstride, est, tol_abs, flags, run, ksteps);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -627,14 +627,32 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         h_k.p[s] = 0;
         if (!ss[s].done && beta[ss[s].dir] > 0.0) stepping.push_back(s);
     }
-    for (int j = 0; j < m && !stepping.empty(); ++j) {
-        // directions that still have unconverged systems
+    // Convergence is tracked on the device (the Givens step records each system's step count and
+    // clears run[s] when a flag is raised); the host compacts the lists every 8 steps. A direction
+    // whose systems all stopped inside a chunk keeps stepping to the chunk's end: its extra basis
+    // vectors are never used.
+    constexpr int kChunk = 8;
+    DevArray<int> run;
+    run.alloc(B);
+    int na = 0, ns = 0;
+    auto lists = [&]() {
         std::vector<char> used(nd, 0);
         for (int s : stepping) used[ss[s].dir] = 1;
-        int na = 0;
+        na = 0;
         for (int d = 0; d < nd; ++d)
             if (used[d]) h_dirs.p[na++] = d;
+        ns = (int)stepping.size();
+        std::memcpy(h_sys.p, stepping.data(), ns * sizeof(int));
+        std::vector<int> runh(B, 0);
+        for (int s : stepping) runh[s] = 1;
         WFQ_HIP(hipMemcpyAsync(dirs.p, h_dirs.p, na * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(sys.p, h_sys.p, ns * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(run.p, runh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipStreamSynchronize(st));   // runh is a host temporary
+    };
+    if (!stepping.empty()) lists();
+    int since_sync = 0;
+    for (int j = 0; j < m && !stepping.empty(); ++j) {
         // w = L T v_j (one real column per direction)
         tm.begin(st);
         ms_pack(prec, V.p, np, mdim1, j, dirs.p, na, inv_h.p, x_block(w, prec), np, st);
@@ -661,28 +679,27 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         ms_hcol(dirs.p, na, j, m, h1.p, h2.p, pslots, nrm.p, n, np, H.p, inv_h.p, st);
         tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
         // every unconverged frequency of those directions: one Givens step on Hbar + z Ibar
-        const int ns = (int)stepping.size();
-        std::memcpy(h_sys.p, stepping.data(), ns * sizeof(int));
-        WFQ_HIP(hipMemcpyAsync(sys.p, h_sys.p, ns * sizeof(int), hipMemcpyHostToDevice, st));
         tm.begin(st);
-        ms_givens(sys.p, ns, j, m, sdir.p, z.p, H.p, cs.p, sn.p, g.p, R.p, rstride, est.p, tol_abs.p, flags.p, st);
+        ms_givens(sys.p, ns, j, m, sdir.p, z.p, H.p, cs.p, sn.p, g.p, R.p, rstride, est.p, tol_abs.p, flags.p, run.p,
+                  ksteps.p, st);
         tm.end(st, KC_GIVENS, 0, 0);
+        if (++since_sync < kChunk && j + 1 < m) continue;
+        since_sync = 0;
         WFQ_HIP(hipMemcpyAsync(w.h_flags.p, flags.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
         WFQ_HIP(hipMemcpyAsync(w.h_est.p, est.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipMemcpyAsync(w.h_ksteps.p, ksteps.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
         WFQ_HIP(hipStreamSynchronize(st));
         std::vector<int> next;
         for (int s : stepping) {
             const int f = w.h_flags.p[s];
-            if (f & 4) {
-                h_k.p[s] = 0;   // NaN: leave the system to batched GMRES from x = 0
-                continue;
-            }
-            h_k.p[s] = j + 1;
+            h_k.p[s] = (f & 4) ? 0 : w.h_ksteps.p[s];   // NaN: leave the system to batched GMRES from x = 0
             ss[s].est_end = w.h_est.p[s];
-            if ((f & 3) == 0) next.push_back(s);
+            if (f == 0) next.push_back(s);
         }
+        const bool changed = next.size() != stepping.size();
         stepping.swap(next);
-        if ((j + 1) % 10 == 0) progress_line(o, "multi-shift", 0, j + 1, stepping.size(), -1.0, t0);
+        if (changed && !stepping.empty()) lists();
+        progress_line(o, "multi-shift", 0, j + 1, stepping.size(), -1.0, t0);
     }
     // iterates: y = R^-1 g, x = V y (groups of systems of one direction share the basis reads)
     std::vector<int> withk;

@@ -111,6 +111,15 @@ typedef struct {
                             every frequency's shifted least-squares residual is <= tol ||b_k|| or the
                             dimension is reached; each system then continues from that iterate in
                             batched GMRES(restart) with FP64 refinement (usually: one FP64 residual). */
+    int32_t graphs;      /* nonzero: for structures of at most 8192 atoms (whose inner steps are read back in
+                            chunks of 8) and for the multi-shift phase, a chunk of steps whose launch
+                            sequence repeats (same first step, length and list sizes) is captured as a HIP
+                            graph the second time it occurs and replayed after that; results are bitwise
+                            the same as without. The inner kernels of such small solves run back to back
+                            on the device already, so replays gain only a few percent, while each capture
+                            costs milliseconds: off by default. Needs a stream other than the null stream
+                            (wfq_solve_dev). Graphs and the work space stay on the handle until a solve of
+                            another shape or wfq_destroy. */
 } wfq_solve_opts;
 
 typedef struct {

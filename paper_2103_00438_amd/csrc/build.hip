@@ -224,6 +224,7 @@ T* dev_alloc(Structure& s, size_t count) {
 }  // namespace
 
 void free_structure(Structure& s) {
+    free_solve_cache(s);
     void* ptrs[] = {s.pos, s.eta, s.width, s.rowptr, s.col, s.val, s.T64, s.T32, s.T16, s.dperm, s.ell_col, s.ell_val,
                     s.sphere};
     for (void* p : ptrs)

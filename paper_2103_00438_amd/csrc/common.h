@@ -45,6 +45,8 @@ void set_error(int code, const std::string& msg);
 
 // ------------------------------------------------------------------ device-resident structure
 
+struct SolveCache;   // the solver's work space and captured graphs, kept between solves
+
 struct Structure {
     int device = 0;
     int64_t n = 0;       // atoms
@@ -77,7 +79,14 @@ struct Structure {
     // partial tiles of split-k block products (grown on demand, at most kSplitWsCap bytes)
     mutable void* split_ws = nullptr;
     mutable uint64_t split_ws_bytes = 0;
+    // bumped whenever a block-product choice (tuning) or the partial-tile buffer changes: captured
+    // launch sequences that refer to either are then stale
+    mutable uint64_t epoch = 0;
+    SolveCache* cache = nullptr;
 };
+
+// frees the solver's cached work space and graphs (the structure's device must be current)
+void free_solve_cache(Structure& s);
 
 struct KernelStat {
     const char* name;

@@ -390,6 +390,7 @@ void* split_workspace(const Structure& s, uint64_t bytes) {
             s.split_ws = nullptr;
             s.split_ws_bytes = 0;
         }
+        ++s.epoch;
         hipError_t e = hipMalloc(&s.split_ws, bytes);
         if (e != hipSuccess) throw Error{WFQ_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
         s.split_ws_bytes = bytes;
@@ -649,6 +650,7 @@ void tune_tx(Structure& s, int prec, int ncol, int reps, double* ms, hipStream_t
     (void)hipFree(Y);
     (void)hipFree(X64);
     if (best_k >= 0) s.tuned[prec][ncol] = best_k;
+    ++s.epoch;
 }
 
 }  // namespace wfq

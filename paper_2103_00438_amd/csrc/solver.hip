@@ -13,6 +13,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <set>
+#include <tuple>
 
 #include "krylov.h"
 #include "solver.h"
@@ -74,37 +78,24 @@ void Timer::collect(KernelStat* stats) {
 
 namespace {
 
+// A typed slice of one of the solver's two allocations (device memory and pinned host memory).
 template <typename T>
-struct DevArray {
+struct Buf {
     T* p = nullptr;
     size_t count = 0;
-    DevArray() = default;
-    DevArray(const DevArray&) = delete;
-    DevArray& operator=(const DevArray&) = delete;
-    void alloc(size_t c) {
-        count = c;
-        if (c == 0) return;
-        WFQ_HIP(hipMalloc(&p, c * sizeof(T)));
-        // zero-fill on the null stream and wait for it: the solver's streams are non-blocking, so
-        // null-stream work is not ordered before their kernels otherwise
-        WFQ_HIP(hipMemsetAsync(p, 0, c * sizeof(T), nullptr));
-        WFQ_HIP(hipStreamSynchronize(nullptr));
-    }
-    ~DevArray() {
-        if (p) (void)hipFree(p);
-    }
 };
 
-template <typename T>
-struct PinnedArray {
-    T* p = nullptr;
-    void alloc(size_t c) {
-        if (c == 0) c = 1;
-        WFQ_HIP(hipHostMalloc(&p, c * sizeof(T), hipHostMallocDefault));
-        std::memset(p, 0, c * sizeof(T));
-    }
-    ~PinnedArray() {
-        if (p) (void)hipHostFree(p);
+// Lays the solver's arrays out back to back (256-byte aligned) in one region; with base == nullptr
+// it only measures the region's size.
+struct Arena {
+    char* base = nullptr;
+    size_t off = 0;
+    template <typename T>
+    void take(Buf<T>& b, size_t count) {
+        off = (off + 255) & ~size_t(255);
+        b.count = count;
+        b.p = (base && count) ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
     }
 };
 
@@ -132,28 +123,64 @@ bool needs_escalation(double beta, double beta_prev, double est_end) {
 
 enum Slot { SLOT_G0 = 0, SLOT_G1 = 1, SLOT_G2 = 2, SLOT_STEP = 3, SLOT_ACT = 4, NSLOT = 5 };
 
+// What a solve's work space depends on: a solve with the same shape reuses it.
+struct WorkShape {
+    int B = 0, m = 0, n_dir = 0, prec = 0, ms_m = 0;   // ms_m: shared-basis dimension (0: no multi-shift)
+    bool qmr = false;
+    bool operator==(const WorkShape& o) const {
+        return B == o.B && m == o.m && n_dir == o.n_dir && prec == o.prec && ms_m == o.ms_m && qmr == o.qmr;
+    }
+};
+
+// arrays of the multi-shift phase (one real basis per direction, one shifted recurrence per system)
+struct MsWork {
+    Buf<double> V, H, part, h1, h2, nrm, inv_h, cs, est, tol_abs, cond;
+    Buf<double2> sn, g, R, y, z;
+    Buf<int> dirs, sdir, sys, flags, ksteps, grp_sys, grp_dir, run;
+    Buf<int> h_dirs, h_sys, h_k;   // pinned
+    Buf<double> h_nrm;             // pinned
+};
+
 struct Work {
+    WorkShape shape;
+    void* dev = nullptr;    // the one device allocation every device array lives in
+    void* host = nullptr;   // the one pinned host allocation
+    size_t dev_bytes = 0, host_bytes = 0;
     int B = 0, mdim = 0, n_dir = 0;
     int64_t n = 0, npad = 0, nwc = 0, nblk = 0, mpad = 0;
     bool need32 = false, need16 = false;
-    DevArray<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, norm2a, tol_abs, cond;
-    DevArray<int> reorth;
-    DevArray<float> X32, Y32, Y16;
-    DevArray<uint16_t> X16;
-    DevArray<double2> partial, h1, h2, R, sn, g, y, z, alpha;
+    Buf<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, norm2a, tol_abs, cond;
+    Buf<int> reorth;
+    Buf<float> X32, Y32, Y16;
+    Buf<uint16_t> X16;
+    Buf<double2> partial, h1, h2, R, sn, g, y, z, alpha;
     // QMR scalars and partials
-    DevArray<double2> rho_a, rho_b, sigma, part_sig, part_nrm;
-    DevArray<double> tau2, eta, snorm, tpb;
-    DevArray<int> first;
-    PinnedArray<double> h_snorm;
-    DevArray<int> flags, ksteps, dir, run, sys[NSLOT];
-    PinnedArray<int> h_sys[NSLOT], h_flags, h_ksteps;
-    PinnedArray<double> h_est, h_beta, h_invb;
-    PinnedArray<double2> h_g, h_alpha;
+    Buf<double2> rho_a, rho_b, sigma, part_sig, part_nrm;
+    Buf<double> tau2, eta, snorm, tpb;
+    Buf<int> first;
+    Buf<int> flags, ksteps, dir, run, sys[NSLOT];
+    Buf<double> d_dirs, stage_re, stage_im;
+    MsWork ms;
+    // pinned host mirrors
+    Buf<double> h_snorm, h_est, h_beta, h_invb;
+    Buf<int> h_sys[NSLOT], h_flags, h_ksteps;
+    Buf<double2> h_g, h_alpha;
     Basis Vb, Xb;
+
+    Work() = default;
+    Work(const Work&) = delete;
+    Work& operator=(const Work&) = delete;
+    ~Work() {
+        if (dev) (void)hipFree(dev);
+        if (host) (void)hipHostFree(host);
+    }
 };
 
-void alloc_work(Work& w, const Structure& S, int B, int m, int n_dir, int prec, bool qmr = false) {
+int ms_dim(const wfq_solve_opts& o, int64_t n);
+
+void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
+    const WorkShape& sh = w.shape;
+    const int B = sh.B, m = sh.m, n_dir = sh.n_dir, prec = sh.prec;
     w.B = B;
     w.mdim = m + 1;
     w.n_dir = n_dir;
@@ -165,66 +192,230 @@ void alloc_work(Work& w, const Structure& S, int B, int m, int n_dir, int prec, 
     w.need16 = prec == WFQ_PREC_BF16;
     w.need32 = prec == WFQ_PREC_FP32 || (prec == WFQ_PREC_BF16 && have_copy(S, WFQ_PREC_FP32));
     const int64_t np = S.npad;
-    w.V.alloc((size_t)B * w.mdim * 2 * np);
-    w.X.alloc((size_t)B * 2 * np);
-    w.b.alloc((size_t)n_dir * np);
-    w.X64.alloc((size_t)w.mpad * np);
-    w.Y64.alloc((size_t)w.mpad * np);
-    if (w.need32) {
-        w.X32.alloc((size_t)w.mpad * np);
-        w.Y32.alloc((size_t)w.mpad * np);
-    }
-    if (w.need16) {
-        w.X16.alloc((size_t)w.mpad * np);
-        w.Y16.alloc((size_t)w.mpad * np);
-    }
-    w.partial.alloc((size_t)B * w.mdim * w.nwc);
-    w.h1.alloc((size_t)B * w.mdim);
-    w.h2.alloc((size_t)B * w.mdim);
-    w.R.alloc((size_t)B * w.mdim * w.mdim);
-    w.cs.alloc((size_t)B * w.mdim);
-    w.sn.alloc((size_t)B * w.mdim);
-    w.g.alloc((size_t)B * (w.mdim + 1));
-    w.y.alloc((size_t)B * w.mdim);
-    w.z.alloc(B);
-    w.alpha.alloc((size_t)B * 3);
-    w.est.alloc(B);
-    w.inv_h.alloc(B);
-    w.inv_beta.alloc(B);
-    w.beta.alloc(B);
-    w.norm2.alloc((size_t)B * std::max(w.nwc, w.nblk));
-    w.norm2a.alloc((size_t)B * w.nwc);
-    w.reorth.alloc(B);
-    w.tol_abs.alloc(B);
-    w.cond.alloc(B);
-    w.flags.alloc(B);
-    w.ksteps.alloc(B);
-    w.run.alloc(B);
-    w.dir.alloc(B);
+    d.take(w.V, (size_t)B * w.mdim * 2 * np);
+    d.take(w.X, (size_t)B * 2 * np);
+    d.take(w.b, (size_t)n_dir * np);
+    d.take(w.X64, (size_t)w.mpad * np);
+    d.take(w.Y64, (size_t)w.mpad * np);
+    d.take(w.X32, w.need32 ? (size_t)w.mpad * np : 0);
+    d.take(w.Y32, w.need32 ? (size_t)w.mpad * np : 0);
+    d.take(w.X16, w.need16 ? (size_t)w.mpad * np : 0);
+    d.take(w.Y16, w.need16 ? (size_t)w.mpad * np : 0);
+    d.take(w.partial, (size_t)B * w.mdim * w.nwc);
+    d.take(w.h1, (size_t)B * w.mdim);
+    d.take(w.h2, (size_t)B * w.mdim);
+    d.take(w.R, (size_t)B * w.mdim * w.mdim);
+    d.take(w.cs, (size_t)B * w.mdim);
+    d.take(w.sn, (size_t)B * w.mdim);
+    d.take(w.g, (size_t)B * (w.mdim + 1));
+    d.take(w.y, (size_t)B * w.mdim);
+    d.take(w.z, B);
+    d.take(w.alpha, (size_t)B * 3);
+    d.take(w.est, B);
+    d.take(w.inv_h, B);
+    d.take(w.inv_beta, B);
+    d.take(w.beta, B);
+    d.take(w.norm2, (size_t)B * std::max(w.nwc, w.nblk));
+    d.take(w.norm2a, (size_t)B * w.nwc);
+    d.take(w.reorth, B);
+    d.take(w.tol_abs, B);
+    d.take(w.cond, B);
+    d.take(w.flags, B);
+    d.take(w.ksteps, B);
+    d.take(w.run, B);
+    d.take(w.dir, B);
     for (int k = 0; k < NSLOT; ++k) {
-        w.sys[k].alloc(B);
-        w.h_sys[k].alloc(B);
+        d.take(w.sys[k], B);
+        h.take(w.h_sys[k], B);
     }
-    w.h_flags.alloc(B);
-    w.h_ksteps.alloc(B);
-    w.h_est.alloc(B);
-    w.h_beta.alloc(B);
-    w.h_invb.alloc(B);
-    w.h_g.alloc((size_t)B * (w.mdim + 1));
-    w.h_alpha.alloc((size_t)B * 3);
-    w.rho_a.alloc(B);
-    w.rho_b.alloc(B);
-    w.sigma.alloc(B);
-    w.part_sig.alloc((size_t)B * w.nblk);
-    w.part_nrm.alloc((size_t)B * w.nblk);
-    w.tau2.alloc(B);
-    w.eta.alloc(B);
-    w.snorm.alloc(B);
-    w.first.alloc(B);
-    w.h_snorm.alloc(B);
-    if (qmr) w.tpb.alloc((size_t)B * 2 * np);   // QMR: compact T p, rows by system id
+    d.take(w.rho_a, B);
+    d.take(w.rho_b, B);
+    d.take(w.sigma, B);
+    d.take(w.part_sig, (size_t)B * w.nblk);
+    d.take(w.part_nrm, (size_t)B * w.nblk);
+    d.take(w.tau2, B);
+    d.take(w.eta, B);
+    d.take(w.snorm, B);
+    d.take(w.first, B);
+    d.take(w.tpb, sh.qmr ? (size_t)B * 2 * np : 0);   // QMR: compact T p, rows by system id
+    d.take(w.d_dirs, (size_t)3 * n_dir);
+    d.take(w.stage_re, (size_t)B * S.n);   // host outputs are staged through these
+    d.take(w.stage_im, (size_t)B * S.n);
+    h.take(w.h_flags, B);
+    h.take(w.h_ksteps, B);
+    h.take(w.h_est, B);
+    h.take(w.h_beta, B);
+    h.take(w.h_invb, B);
+    h.take(w.h_snorm, B);
+    h.take(w.h_g, (size_t)B * (w.mdim + 1));
+    h.take(w.h_alpha, (size_t)B * 3);
+    if (sh.ms_m > 0) {
+        MsWork& q = w.ms;
+        const int64_t mm = sh.ms_m, mdim1 = mm + 1, pslots = mm + 2;
+        d.take(q.V, (size_t)n_dir * mdim1 * np);
+        d.take(q.H, (size_t)n_dir * mm * (mm + 1));
+        d.take(q.part, (size_t)n_dir * pslots * w.nwc);
+        d.take(q.h1, (size_t)n_dir * pslots);
+        d.take(q.h2, (size_t)n_dir * pslots);
+        d.take(q.nrm, (size_t)n_dir * (np / 64));
+        d.take(q.inv_h, n_dir);
+        d.take(q.cs, (size_t)B * mm);
+        d.take(q.sn, (size_t)B * mm);
+        d.take(q.g, (size_t)B * (mm + 1));
+        d.take(q.R, (size_t)B * (mm * (mm + 1) / 2));
+        d.take(q.y, (size_t)B * mm);
+        d.take(q.z, B);
+        d.take(q.est, B);
+        d.take(q.tol_abs, B);
+        d.take(q.cond, B);
+        d.take(q.dirs, n_dir);
+        d.take(q.sdir, B);
+        d.take(q.sys, B);
+        d.take(q.flags, B);
+        d.take(q.ksteps, B);
+        d.take(q.run, B);
+        // groups of up to kMsGroup systems of one direction: at most B + (kMsGroup - 1) n_dir slots
+        d.take(q.grp_sys, (size_t)B + (size_t)(kMsGroup - 1) * n_dir);
+        d.take(q.grp_dir, (size_t)B + n_dir);
+        h.take(q.h_dirs, n_dir);
+        h.take(q.h_sys, B);
+        h.take(q.h_k, B);
+        h.take(q.h_nrm, (size_t)n_dir * pslots);
+    }
     w.Vb = Basis{w.V.p, (int64_t)w.mdim * 2 * np, 2 * np, np};
-    w.Xb = Basis{w.X.p, 2 * np, 2 * np, np};
+    w.Xb = sh.qmr ? Basis{w.V.p + 5 * 2 * np, (int64_t)w.mdim * 2 * np, 2 * np, np}   // the QMR iterate
+                  : Basis{w.X.p, 2 * np, 2 * np, np};
+}
+
+// Allocates the work space of one shape: one device and one pinned host allocation.
+void make_work(Work& w, const Structure& S, const WorkShape& sh) {
+    w.shape = sh;
+    Arena d, h;
+    layout_work(w, S, d, h);
+    w.dev_bytes = std::max<size_t>(d.off, 256);
+    w.host_bytes = std::max<size_t>(h.off, 256);
+    hipError_t e = hipMalloc(&w.dev, w.dev_bytes);
+    if (e != hipSuccess) {
+        w.dev = nullptr;
+        throw Error{WFQ_ENOMEM, std::string("hipMalloc of the Krylov work space failed: ") + hipGetErrorString(e)};
+    }
+    WFQ_HIP(hipHostMalloc(&w.host, w.host_bytes, hipHostMallocDefault));
+    Arena d2{static_cast<char*>(w.dev), 0}, h2{static_cast<char*>(w.host), 0};
+    layout_work(w, S, d2, h2);
+}
+
+// Every solve starts from a zeroed work space (a reused one holds the previous solve's data).
+void clear_work(Work& w, hipStream_t st) {
+    WFQ_HIP(hipMemsetAsync(w.dev, 0, w.dev_bytes, st));
+    std::memset(w.host, 0, w.host_bytes);
+}
+
+// ---- HIP graphs of inner-iteration chunks
+//
+// For small structures the inner iterations are bound by launch latency (a step is ~10 launches of a
+// few microseconds each). A chunk of steps between two host synchronisations is the same launch
+// sequence whenever its first step, length and list sizes repeat (the lists' contents live in device
+// buffers, and convergence inside a chunk is handled by the device-side run mask), so it is captured
+// once as a HIP graph and replayed. A chunk runs eagerly the first time its key is seen and is
+// captured the second time, so one-off shapes never pay for a capture, and every buffer a graph
+// refers to (the work space, the split-k partial tiles) exists before it is captured.
+
+struct GraphKey {
+    int kind, j0, c, ns, g0, g1, g2;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(kind, j0, c, ns, g0, g1, g2) < std::tie(o.kind, o.j0, o.c, o.ns, o.g0, o.g1, o.g2);
+    }
+};
+
+constexpr size_t kMaxGraphs = 1024;
+
+struct GraphCache {
+    std::map<GraphKey, hipGraphExec_t> exec;
+    std::set<GraphKey> seen;
+    uint64_t epoch = 0;   // Structure::epoch when the graphs were captured
+    void clear() {
+        for (auto& e : exec) (void)hipGraphExecDestroy(e.second);
+        exec.clear();
+        seen.clear();
+    }
+    ~GraphCache() { clear(); }
+};
+
+// Runs `body` (kernel launches on st only) eagerly, or as a captured graph, or replays the graph.
+template <typename F>
+void run_chunk(GraphCache* gc, const Structure& S, const GraphKey& k, hipStream_t st, F&& body) {
+    if (!gc) {
+        body();
+        return;
+    }
+    if (gc->epoch != S.epoch) {   // a block-product choice or a buffer it uses changed
+        gc->clear();
+        gc->epoch = S.epoch;
+    }
+    auto it = gc->exec.find(k);
+    if (it != gc->exec.end()) {
+        WFQ_HIP(hipGraphLaunch(it->second, st));
+        return;
+    }
+    if (gc->seen.insert(k).second || gc->exec.size() >= kMaxGraphs) {
+        body();
+        return;
+    }
+    hipGraph_t g = nullptr;
+    WFQ_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+    try {
+        body();
+    } catch (...) {
+        (void)hipStreamEndCapture(st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    WFQ_HIP(hipStreamEndCapture(st, &g));
+    hipGraphExec_t e = nullptr;
+    const hipError_t r = hipGraphInstantiate(&e, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (r != hipSuccess) throw Error{WFQ_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(r)};
+    gc->exec.emplace(k, e);
+    WFQ_HIP(hipGraphLaunch(e, st));
+}
+
+}  // namespace
+
+// The handle's solve work space and its graphs, kept between solves of the same shape when small.
+struct SolveCache {
+    std::unique_ptr<Work> work;
+    GraphCache graphs;
+};
+
+void free_solve_cache(Structure& S) {
+    delete S.cache;   // graphs first, then the work space
+    S.cache = nullptr;
+}
+
+namespace {
+
+// work spaces up to this size stay allocated on the handle after a solve
+constexpr size_t kKeepWorkBytes = 8ull << 30;
+
+// The work space for a solve of shape sh: the handle's cached one when the shape matches, else a
+// new one (cached when small; the previous cached one is freed first). graphs is set for a cached
+// work space.
+Work& solve_work(Structure& S, const WorkShape& sh, GraphCache*& graphs, std::unique_ptr<Work>& own) {
+    graphs = nullptr;
+    if (S.cache && S.cache->work && S.cache->work->shape == sh) {
+        graphs = &S.cache->graphs;
+        return *S.cache->work;
+    }
+    free_solve_cache(S);
+    own = std::make_unique<Work>();
+    make_work(*own, S, sh);
+    if (own->dev_bytes <= kKeepWorkBytes) {
+        S.cache = new SolveCache;
+        S.cache->work = std::move(own);
+        graphs = &S.cache->graphs;
+        return *S.cache->work;
+    }
+    return *own;
 }
 
 // view of one vector slot of a basis as a one-slot basis
@@ -299,7 +490,8 @@ void fp64_residual(const Structure& S, Work& w, const std::vector<int>& act, Tim
 
 // Restarted GMRES(m) with FP64 refinement at every restart, for the systems of one batch.
 void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double tol, const wfq_solve_opts& o,
-                 Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0, bool warm = false) {
+                 Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0, GraphCache* graphs,
+                 bool warm = false) {
     const int B = (int)ss.size();
     const int m = w.mdim - 1;
     const double n = (double)S.n;
@@ -388,9 +580,9 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         // round trip would cost more than the steps.
         const int chunk = (S.npad <= 8192) ? 8 : 1;
         WFQ_HIP(hipMemcpyAsync(w.ksteps.p, w.h_ksteps.p, B * sizeof(int), hipMemcpyHostToDevice, st));
-        GivensArgs gc = ga;
-        gc.ksteps = w.ksteps.p;
-        gc.run = w.run.p;
+        GivensArgs gc_args = ga;
+        gc_args.ksteps = w.ksteps.p;
+        gc_args.run = w.run.p;
         std::vector<int> grp[3];
         auto lists = [&]() {   // upload the group lists, the step list and run = 1 for them
             for (int p = 0; p < 3; ++p) grp[p].clear();
@@ -404,59 +596,66 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             WFQ_HIP(hipStreamSynchronize(st));   // runh is a host temporary
         };
         lists();
-        int since_sync = 0;
-        for (int j = 0; j < m && !stepping.empty(); ++j) {
+        // graphs only where steps are chunked and no per-launch events are recorded
+        GraphCache* gc = (chunk > 1 && !tm.on()) ? graphs : nullptr;
+        for (int j0 = 0; j0 < m && !stepping.empty();) {
             const int ns = (int)stepping.size();
             const int* run = chunk > 1 ? w.run.p : nullptr;
-            // the operator on the new basis vectors, one block product per precision group
-            for (int p = 0; p < 3; ++p) {
-                if (grp[p].empty()) continue;
-                const int ng = (int)grp[p].size();
+            // steps until the next read-back: the chunk, the end of the cycle, or the first system
+            // that would pass max_iter
+            int c = std::min(chunk, m - j0);
+            for (int s : stepping) c = std::min(c, o.max_iter - ss[s].iters);
+            auto step = [&](int j) {
+                // the operator on the new basis vectors, one block product per precision group
+                for (int p = 0; p < 3; ++p) {
+                    if (grp[p].empty()) continue;
+                    const int ng = (int)grp[p].size();
+                    tm.begin(st);
+                    pack_columns(p, w.Vb, w.sys[p].p, ng, j, j == 0 ? w.inv_beta.p : w.inv_h.p, true, x_block(w, p),
+                                 w.npad, st, run);
+                    tm.end(st, KC_PACK, 0, ng * n * (32.0 + 2 * elem_size(p)));
+                    block_product(S, w, p, 2 * ng, tm, st);
+                    tm.begin(st);
+                    spmm_shift(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, w.z.p, w.Vb, j, j + 1,
+                               st);
+                    tm.end(st, KC_SPMM, 4.0 * S.nnz * ng + 8 * n * ng,
+                           12.0 * S.nnz + ng * n * (2.0 * out_size(p) + 16 + 16));
+                }
+                // CGS2 against v_0 .. v_j, then the Givens update of the least-squares problem
+                const int* sl = w.sys[SLOT_STEP].p;
+                // first pass (with ||w||^2), the reorthogonalisation test, and the second pass only
+                // for the systems that need it
                 tm.begin(st);
-                pack_columns(p, w.Vb, w.sys[p].p, ng, j, j == 0 ? w.inv_beta.p : w.inv_h.p, true, x_block(w, p),
-                             w.npad, st, run);
-                tm.end(st, KC_PACK, 0, ng * n * (32.0 + 2 * elem_size(p)));
-                block_product(S, w, p, 2 * ng, tm, st);
+                multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, run, true);
+                reduce_dots(S.n, sl, ns, j + 1, w.partial.p, w.mdim, w.h1.p, st, run);
+                tm.end(st, KC_DOT, 8.0 * n * ns * (j + 2), 16.0 * n * ns * (j + 2));
                 tm.begin(st);
-                spmm_shift(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, w.z.p, w.Vb, j, j + 1, st);
-                tm.end(st, KC_SPMM, 4.0 * S.nnz * ng + 8 * n * ng,
-                       12.0 * S.nnz + ng * n * (2.0 * out_size(p) + 16 + 16));
-            }
-            // CGS2 against v_0 .. v_j, then the Givens update of the least-squares problem
-            const int* sl = w.sys[SLOT_STEP].p;
-            // first pass (with ||w||^2), the reorthogonalisation test, and the second pass only
-            // for the systems that need it
-            tm.begin(st);
-            multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, run, true);
-            reduce_dots(S.n, sl, ns, j + 1, w.partial.p, w.mdim, w.h1.p, st, run);
-            tm.end(st, KC_DOT, 8.0 * n * ns * (j + 2), 16.0 * n * ns * (j + 2));
-            tm.begin(st);
-            multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h1.p, w.mdim, w.norm2a.p, st, run);
-            reorth_test(sl, ns, j, w.mdim, w.h1.p, w.norm2a.p, S.n, w.h2.p, w.reorth.p, st, run);
-            tm.end(st, KC_UPDATE, 8.0 * n * ns * (j + 1), 16.0 * n * ns * (j + 3));
-            tm.begin(st);
-            multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, w.reorth.p, false);
-            reduce_dots(S.n, sl, ns, j, w.partial.p, w.mdim, w.h2.p, st, w.reorth.p);
-            tm.end(st, KC_DOT, 0, 0);
-            tm.begin(st);
-            multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h2.p, w.mdim, w.norm2.p, st, w.reorth.p);
-            tm.end(st, KC_UPDATE, 0, 0);
-            tm.begin(st);
-            givens_step(sl, ns, j, w.mdim, gc, st);
-            tm.end(st, KC_GIVENS, 0, 0);
-            ++since_sync;
-            // read back every `chunk` steps, at the end of the cycle, and before any system could pass
-            // max_iter inside the chunk
-            int room = 1 << 30;
-            for (int s : stepping) room = std::min(room, o.max_iter - ss[s].iters - since_sync);
-            if (since_sync < chunk && j + 1 < m && room > 0) continue;
+                multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h1.p, w.mdim, w.norm2a.p, st, run);
+                reorth_test(sl, ns, j, w.mdim, w.h1.p, w.norm2a.p, S.n, w.h2.p, w.reorth.p, st, run);
+                tm.end(st, KC_UPDATE, 8.0 * n * ns * (j + 1), 16.0 * n * ns * (j + 3));
+                tm.begin(st);
+                multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, w.reorth.p, false);
+                reduce_dots(S.n, sl, ns, j, w.partial.p, w.mdim, w.h2.p, st, w.reorth.p);
+                tm.end(st, KC_DOT, 0, 0);
+                tm.begin(st);
+                multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h2.p, w.mdim, w.norm2.p, st, w.reorth.p);
+                tm.end(st, KC_UPDATE, 0, 0);
+                tm.begin(st);
+                givens_step(sl, ns, j, w.mdim, gc_args, st);
+                tm.end(st, KC_GIVENS, 0, 0);
+            };
+            const GraphKey key{0, j0, c, ns, (int)grp[0].size(), (int)grp[1].size(), (int)grp[2].size()};
+            run_chunk(gc, S, key, st, [&] {
+                for (int j = j0; j < j0 + c; ++j) step(j);
+            });
+            j0 += c;
             WFQ_HIP(hipMemcpyAsync(w.h_flags.p, w.flags.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
             WFQ_HIP(hipMemcpyAsync(w.h_est.p, w.est.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
             WFQ_HIP(hipMemcpyAsync(w.h_ksteps.p, w.ksteps.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
             WFQ_HIP(hipStreamSynchronize(st));
             std::vector<int> next;
             for (int s : stepping) {
-                ss[s].iters += since_sync - (j + 1 - w.h_ksteps.p[s]);   // steps this system took in the chunk
+                ss[s].iters += c - (j0 - w.h_ksteps.p[s]);   // steps this system took in the chunk
                 ss[s].est_end = w.h_est.p[s];
                 const int f = w.h_flags.p[s];
                 if (f & 4) {
@@ -465,11 +664,10 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                 }
                 if (f == 0 && ss[s].iters < o.max_iter) next.push_back(s);
             }
-            since_sync = 0;
             const bool changed = next.size() != stepping.size();
             stepping.swap(next);
             if (changed && !stepping.empty()) lists();
-            if ((j + 1) % 10 == 0) progress_line(o, "gmres", ss[active[0]].cycles, j + 1, stepping.size(), -1.0, t0);
+            if (j0 % 10 == 0) progress_line(o, "gmres", ss[active[0]].cycles, j0, stepping.size(), -1.0, t0);
         }
         // drop systems that hit NaN
         std::vector<int> act2;
@@ -549,7 +747,7 @@ uint64_t ms_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_dir)
 // Runs the shared-basis phase for the systems of one batch and leaves each system's iterate in
 // w.Xb (zero where the phase could not help); ss[s].iters = steps of the shared basis it used.
 void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, double tol, const wfq_solve_opts& o,
-                   Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0) {
+                   Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0, GraphCache* graphs) {
     const int B = (int)ss.size();
     const int nd = w.n_dir;
     const int m = ms_dim(o, S.n);
@@ -558,51 +756,30 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     const int prec = o.precision;
     const int64_t rstride = (int64_t)m * (m + 1) / 2;
     const double dn = (double)n;
-    DevArray<double> V, H, part, h1, h2, nrm, inv_h, cs, est, tol_abs, cond;
-    DevArray<double2> sn, g, R, y, z;
-    DevArray<int> dirs, sdir, sys, flags, ksteps, grp_sys, grp_dir;
-    V.alloc((size_t)nd * mdim1 * np);
-    H.alloc((size_t)nd * m * (m + 1));
-    part.alloc((size_t)nd * pslots * nwc);
-    h1.alloc((size_t)nd * pslots);
-    h2.alloc((size_t)nd * pslots);
-    nrm.alloc((size_t)nd * (np / 64));
-    inv_h.alloc(nd);
-    cs.alloc((size_t)B * m);
-    sn.alloc((size_t)B * m);
-    g.alloc((size_t)B * (m + 1));
-    R.alloc((size_t)B * rstride);
-    y.alloc((size_t)B * m);
-    z.alloc(B);
-    est.alloc(B);
-    tol_abs.alloc(B);
-    cond.alloc(B);
-    dirs.alloc(nd);
-    sdir.alloc(B);
-    sys.alloc(B);
-    flags.alloc(B);
-    ksteps.alloc(B);
-    PinnedArray<int> h_dirs, h_sys, h_k;
-    PinnedArray<double> h_nrm;
-    h_dirs.alloc(nd);
-    h_sys.alloc(B);
-    h_k.alloc(B);
-    h_nrm.alloc((size_t)nd * pslots);
+    MsWork& q = w.ms;
+    if (w.shape.ms_m != m) throw Error{WFQ_EDEVICE, "multi-shift work space of the wrong dimension"};
+    double *V = q.V.p, *H = q.H.p, *part = q.part.p, *h1 = q.h1.p, *h2 = q.h2.p, *nrm = q.nrm.p, *inv_h = q.inv_h.p;
+    double *cs = q.cs.p, *est = q.est.p, *tol_abs = q.tol_abs.p, *cond = q.cond.p;
+    double2 *sn = q.sn.p, *g = q.g.p, *R = q.R.p, *y = q.y.p, *z = q.z.p;
+    int *dirs = q.dirs.p, *sdir = q.sdir.p, *sys = q.sys.p, *flags = q.flags.p, *ksteps = q.ksteps.p;
+    int *grp_sys = q.grp_sys.p, *grp_dir = q.grp_dir.p, *run = q.run.p;
+    int *h_dirs = q.h_dirs.p, *h_sys = q.h_sys.p, *h_k = q.h_k.p;
+    double* h_nrm = q.h_nrm.p;
 
     // v_0 of direction d is b_d / ||b_d||
     for (int d = 0; d < nd; ++d) {
-        WFQ_HIP(hipMemcpyAsync(V.p + (size_t)d * mdim1 * np, w.b.p + (size_t)d * np, np * sizeof(double),
+        WFQ_HIP(hipMemcpyAsync(V + (size_t)d * mdim1 * np, w.b.p + (size_t)d * np, np * sizeof(double),
                                hipMemcpyDeviceToDevice, st));
-        h_dirs.p[d] = d;
+        h_dirs[d] = d;
     }
-    WFQ_HIP(hipMemcpyAsync(dirs.p, h_dirs.p, nd * sizeof(int), hipMemcpyHostToDevice, st));
-    ms_dot(V.p, n, np, mdim1, 0, 0, dirs.p, nd, part.p, pslots, true, st);
-    ms_reduce(dirs.p, nd, part.p, pslots, n, 1, h1.p, st);
-    WFQ_HIP(hipMemcpyAsync(h_nrm.p, h1.p, (size_t)nd * pslots * sizeof(double), hipMemcpyDeviceToHost, st));
+    WFQ_HIP(hipMemcpyAsync(dirs, h_dirs, nd * sizeof(int), hipMemcpyHostToDevice, st));
+    ms_dot(V, n, np, mdim1, 0, 0, dirs, nd, part, pslots, true, st);
+    ms_reduce(dirs, nd, part, pslots, n, 1, h1, st);
+    WFQ_HIP(hipMemcpyAsync(h_nrm, h1, (size_t)nd * pslots * sizeof(double), hipMemcpyDeviceToHost, st));
     WFQ_HIP(hipStreamSynchronize(st));
     std::vector<double> beta(nd), invb(nd);
     for (int d = 0; d < nd; ++d) {
-        beta[d] = std::sqrt(h_nrm.p[(size_t)d * pslots]);
+        beta[d] = std::sqrt(h_nrm[(size_t)d * pslots]);
         invb[d] = beta[d] > 0.0 ? 1.0 / beta[d] : 0.0;
     }
     {
@@ -615,16 +792,16 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
             dh[s] = ss[s].dir;
             zh[s] = ss[s].z;
         }
-        WFQ_HIP(hipMemcpyAsync(g.p, gh.data(), gh.size() * sizeof(double2), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(tol_abs.p, th.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(sdir.p, dh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(z.p, zh.data(), B * sizeof(double2), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(inv_h.p, invb.data(), nd * sizeof(double), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(g, gh.data(), gh.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(tol_abs, th.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(sdir, dh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(z, zh.data(), B * sizeof(double2), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(inv_h, invb.data(), nd * sizeof(double), hipMemcpyHostToDevice, st));
         WFQ_HIP(hipStreamSynchronize(st));
     }
     std::vector<int> stepping;
     for (int s = 0; s < B; ++s) {
-        h_k.p[s] = 0;
+        h_k[s] = 0;
         if (!ss[s].done && beta[ss[s].dir] > 0.0) stepping.push_back(s);
     }
     // Convergence is tracked on the device (the Givens step records each system's step count and
@@ -632,80 +809,82 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     // whose systems all stopped inside a chunk keeps stepping to the chunk's end: its extra basis
     // vectors are never used.
     constexpr int kChunk = 8;
-    DevArray<int> run;
-    run.alloc(B);
     int na = 0, ns = 0;
     auto lists = [&]() {
         std::vector<char> used(nd, 0);
         for (int s : stepping) used[ss[s].dir] = 1;
         na = 0;
         for (int d = 0; d < nd; ++d)
-            if (used[d]) h_dirs.p[na++] = d;
+            if (used[d]) h_dirs[na++] = d;
         ns = (int)stepping.size();
-        std::memcpy(h_sys.p, stepping.data(), ns * sizeof(int));
+        std::memcpy(h_sys, stepping.data(), ns * sizeof(int));
         std::vector<int> runh(B, 0);
         for (int s : stepping) runh[s] = 1;
-        WFQ_HIP(hipMemcpyAsync(dirs.p, h_dirs.p, na * sizeof(int), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(sys.p, h_sys.p, ns * sizeof(int), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(run.p, runh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(dirs, h_dirs, na * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(sys, h_sys, ns * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipMemcpyAsync(run, runh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
         WFQ_HIP(hipStreamSynchronize(st));   // runh is a host temporary
     };
     if (!stepping.empty()) lists();
-    int since_sync = 0;
-    for (int j = 0; j < m && !stepping.empty(); ++j) {
-        // w = L T v_j (one real column per direction)
-        tm.begin(st);
-        ms_pack(prec, V.p, np, mdim1, j, dirs.p, na, inv_h.p, x_block(w, prec), np, st);
-        tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(prec)));
-        block_product(S, w, prec, na, tm, st);
-        tm.begin(st);
-        ms_spmm(S, prec == WFQ_PREC_FP64, y_block(w, prec), np, dirs.p, na, V.p, mdim1, j + 1, st);
-        tm.end(st, KC_SPMM, 2.0 * S.nnz * na, 12.0 * S.nnz * na + na * dn * (out_size(prec) + 8));
-        // two classical Gram-Schmidt passes against v_0 .. v_j
-        const double pass = 8.0 * dn * na * (j + 2);
-        tm.begin(st);
-        ms_dot(V.p, n, np, mdim1, j + 1, j + 1, dirs.p, na, part.p, pslots, false, st);
-        ms_reduce(dirs.p, na, part.p, pslots, n, j + 1, h1.p, st);
-        tm.end(st, KC_DOT, 2.0 * dn * na * (j + 1), pass);
-        tm.begin(st);
-        ms_update(V.p, n, np, mdim1, j + 1, j + 1, dirs.p, na, h1.p, pslots, nullptr, st);
-        tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
-        tm.begin(st);
-        ms_dot(V.p, n, np, mdim1, j + 1, j + 1, dirs.p, na, part.p, pslots, false, st);
-        ms_reduce(dirs.p, na, part.p, pslots, n, j + 1, h2.p, st);
-        tm.end(st, KC_DOT, 2.0 * dn * na * (j + 1), pass);
-        tm.begin(st);
-        ms_update(V.p, n, np, mdim1, j + 1, j + 1, dirs.p, na, h2.p, pslots, nrm.p, st);
-        ms_hcol(dirs.p, na, j, m, h1.p, h2.p, pslots, nrm.p, n, np, H.p, inv_h.p, st);
-        tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
-        // every unconverged frequency of those directions: one Givens step on Hbar + z Ibar
-        tm.begin(st);
-        ms_givens(sys.p, ns, j, m, sdir.p, z.p, H.p, cs.p, sn.p, g.p, R.p, rstride, est.p, tol_abs.p, flags.p, run.p,
-                  ksteps.p, st);
-        tm.end(st, KC_GIVENS, 0, 0);
-        if (++since_sync < kChunk && j + 1 < m) continue;
-        since_sync = 0;
-        WFQ_HIP(hipMemcpyAsync(w.h_flags.p, flags.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
-        WFQ_HIP(hipMemcpyAsync(w.h_est.p, est.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
-        WFQ_HIP(hipMemcpyAsync(w.h_ksteps.p, ksteps.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
+    GraphCache* gc = tm.on() ? nullptr : graphs;
+    for (int j0 = 0; j0 < m && !stepping.empty();) {
+        const int c = std::min(kChunk, m - j0);
+        auto step = [&](int j) {
+            // w = L T v_j (one real column per direction)
+            tm.begin(st);
+            ms_pack(prec, V, np, mdim1, j, dirs, na, inv_h, x_block(w, prec), np, st);
+            tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(prec)));
+            block_product(S, w, prec, na, tm, st);
+            tm.begin(st);
+            ms_spmm(S, prec == WFQ_PREC_FP64, y_block(w, prec), np, dirs, na, V, mdim1, j + 1, st);
+            tm.end(st, KC_SPMM, 2.0 * S.nnz * na, 12.0 * S.nnz * na + na * dn * (out_size(prec) + 8));
+            // two classical Gram-Schmidt passes against v_0 .. v_j
+            const double pass = 8.0 * dn * na * (j + 2);
+            tm.begin(st);
+            ms_dot(V, n, np, mdim1, j + 1, j + 1, dirs, na, part, pslots, false, st);
+            ms_reduce(dirs, na, part, pslots, n, j + 1, h1, st);
+            tm.end(st, KC_DOT, 2.0 * dn * na * (j + 1), pass);
+            tm.begin(st);
+            ms_update(V, n, np, mdim1, j + 1, j + 1, dirs, na, h1, pslots, nullptr, st);
+            tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
+            tm.begin(st);
+            ms_dot(V, n, np, mdim1, j + 1, j + 1, dirs, na, part, pslots, false, st);
+            ms_reduce(dirs, na, part, pslots, n, j + 1, h2, st);
+            tm.end(st, KC_DOT, 2.0 * dn * na * (j + 1), pass);
+            tm.begin(st);
+            ms_update(V, n, np, mdim1, j + 1, j + 1, dirs, na, h2, pslots, nrm, st);
+            ms_hcol(dirs, na, j, m, h1, h2, pslots, nrm, n, np, H, inv_h, st);
+            tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
+            // every unconverged frequency of those directions: one Givens step on Hbar + z Ibar
+            tm.begin(st);
+            ms_givens(sys, ns, j, m, sdir, z, H, cs, sn, g, R, rstride, est, tol_abs, flags, run, ksteps, st);
+            tm.end(st, KC_GIVENS, 0, 0);
+        };
+        run_chunk(gc, S, GraphKey{1, j0, c, ns, na, 0, 0}, st, [&] {
+            for (int j = j0; j < j0 + c; ++j) step(j);
+        });
+        j0 += c;
+        WFQ_HIP(hipMemcpyAsync(w.h_flags.p, flags, B * sizeof(int), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipMemcpyAsync(w.h_est.p, est, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipMemcpyAsync(w.h_ksteps.p, ksteps, B * sizeof(int), hipMemcpyDeviceToHost, st));
         WFQ_HIP(hipStreamSynchronize(st));
         std::vector<int> next;
         for (int s : stepping) {
             const int f = w.h_flags.p[s];
-            h_k.p[s] = (f & 4) ? 0 : w.h_ksteps.p[s];   // NaN: leave the system to batched GMRES from x = 0
+            h_k[s] = (f & 4) ? 0 : w.h_ksteps.p[s];   // NaN: leave the system to batched GMRES from x = 0
             ss[s].est_end = w.h_est.p[s];
             if (f == 0) next.push_back(s);
         }
         const bool changed = next.size() != stepping.size();
         stepping.swap(next);
         if (changed && !stepping.empty()) lists();
-        progress_line(o, "multi-shift", 0, j + 1, stepping.size(), -1.0, t0);
+        progress_line(o, "multi-shift", 0, j0, stepping.size(), -1.0, t0);
     }
     // iterates: y = R^-1 g, x = V y (groups of systems of one direction share the basis reads)
     std::vector<int> withk;
     for (int s = 0; s < B; ++s)
-        if (h_k.p[s] > 0) withk.push_back(s);
-    WFQ_HIP(hipMemcpyAsync(ksteps.p, h_k.p, B * sizeof(int), hipMemcpyHostToDevice, st));
+        if (h_k[s] > 0) withk.push_back(s);
+    WFQ_HIP(hipMemcpyAsync(ksteps, h_k, B * sizeof(int), hipMemcpyHostToDevice, st));
     std::vector<int> gs, gd;
     for (int d = 0; d < nd; ++d) {
         std::vector<int> mem;
@@ -717,24 +896,24 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         }
     }
     const int ngrp = (int)gd.size();
-    grp_sys.alloc(gs.size());
-    grp_dir.alloc(gd.size());
-    WFQ_HIP(hipMemcpyAsync(grp_sys.p, gs.data(), gs.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    WFQ_HIP(hipMemcpyAsync(grp_dir.p, gd.data(), gd.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    if (gs.size() > q.grp_sys.count || gd.size() > q.grp_dir.count)
+        throw Error{WFQ_EDEVICE, "multi-shift system groups exceed their work space"};
+    WFQ_HIP(hipMemcpyAsync(grp_sys, gs.data(), gs.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    WFQ_HIP(hipMemcpyAsync(grp_dir, gd.data(), gd.size() * sizeof(int), hipMemcpyHostToDevice, st));
     tm.begin(st);
     if (!withk.empty()) {
-        std::memcpy(h_sys.p, withk.data(), withk.size() * sizeof(int));
-        WFQ_HIP(hipMemcpyAsync(sys.p, h_sys.p, withk.size() * sizeof(int), hipMemcpyHostToDevice, st));
-        ms_solve(sys.p, (int)withk.size(), ksteps.p, m, R.p, rstride, g.p, y.p, cond.p, st);
+        std::memcpy(h_sys, withk.data(), withk.size() * sizeof(int));
+        WFQ_HIP(hipMemcpyAsync(sys, h_sys, withk.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        ms_solve(sys, (int)withk.size(), ksteps, m, R, rstride, g, y, cond, st);
     }
-    ms_xupdate(V.p, n, np, mdim1, grp_sys.p, grp_dir.p, ngrp, ksteps.p, y.p, m, w.Xb, st);
+    ms_xupdate(V, n, np, mdim1, grp_sys, grp_dir, ngrp, ksteps, y, m, w.Xb, st);
     tm.end(st, KC_XUPDATE, 0, 0);
     std::vector<double> ch(B, 1.0);
-    if (!withk.empty()) WFQ_HIP(hipMemcpyAsync(ch.data(), cond.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (!withk.empty()) WFQ_HIP(hipMemcpyAsync(ch.data(), cond, B * sizeof(double), hipMemcpyDeviceToHost, st));
     WFQ_HIP(hipStreamSynchronize(st));
     for (int s = 0; s < B; ++s) {
-        ss[s].iters += h_k.p[s];
-        if (h_k.p[s] > 0) ss[s].cond = ch[s];
+        ss[s].iters += h_k[s];
+        if (h_k[s] > 0) ss[s].cond = ch[s];
     }
     if (o.progress) progress_line(o, "multi-shift done", 0, 0, stepping.size(), -1.0, t0);
 }
@@ -959,23 +1138,23 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
     if (S.budget && batch_bytes(S, o, B, n_dir) > avail)
         throw Error{WFQ_ENOMEM, "not enough device memory for one system's Krylov work space"};
 
-    Work w;
     const bool qmr = o.algorithm == WFQ_QMR;
-    alloc_work(w, S, B, qmr ? kQmrSlots - 1 : o.restart, n_dir, prec, qmr);
-    if (qmr) w.Xb = slot_view(w.Vb, 5);   // the QMR iterate is the solution
+    WorkShape sh;
+    sh.B = B;
+    sh.m = qmr ? kQmrSlots - 1 : o.restart;
+    sh.n_dir = n_dir;
+    sh.prec = prec;
+    sh.ms_m = o.algorithm == WFQ_MSGMRES ? ms_dim(o, S.n) : 0;
+    sh.qmr = qmr;
+    GraphCache* graphs = nullptr;
+    std::unique_ptr<Work> own;   // a work space too large to keep on the handle
+    Work& w = solve_work(S, sh, graphs, own);
+    clear_work(w, st);
+    if (!o.graphs || !st) graphs = nullptr;
     // right-hand sides b_k = E0 L r_k (shared by every frequency)
-    {
-        DevArray<double> d_dirs;
-        d_dirs.alloc((size_t)3 * n_dir);
-        WFQ_HIP(hipMemcpyAsync(d_dirs.p, dirs, 3 * n_dir * sizeof(double), hipMemcpyHostToDevice, st));
-        build_rhs(S, d_dirs.p, n_dir, E0, w.b.p, S.npad, st);
-        WFQ_HIP(hipStreamSynchronize(st));
-    }
-    DevArray<double> stage_re, stage_im;
-    if (!out.on_device) {
-        if (out.q_re) stage_re.alloc((size_t)B * S.n);
-        if (out.q_im) stage_im.alloc((size_t)B * S.n);
-    }
+    WFQ_HIP(hipMemcpyAsync(w.d_dirs.p, dirs, 3 * n_dir * sizeof(double), hipMemcpyHostToDevice, st));
+    build_rhs(S, w.d_dirs.p, n_dir, E0, w.b.p, S.npad, st);
+    WFQ_HIP(hipStreamSynchronize(st));
     Timer tm(stats != nullptr);
     int worst = WFQ_OK;
     for (int s0 = 0; s0 < total; s0 += B) {
@@ -991,10 +1170,10 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
         }
         if (o.algorithm == WFQ_MSGMRES) {
             // shared-basis phase, then batched GMRES from its iterates (FP64 residual first)
-            msgmres_phase(S, w, ss, tol, o, tm, st, t0);
-            gmres_batch(S, w, ss, tol, o, tm, st, t0, true);
+            msgmres_phase(S, w, ss, tol, o, tm, st, t0, graphs);
+            gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs, true);
         } else if (!qmr) {
-            gmres_batch(S, w, ss, tol, o, tm, st, t0);
+            gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs);
         } else {
             std::vector<int> broken;
             qmr_batch(S, w, ss, tol, o, tm, st, t0, broken);
@@ -1005,7 +1184,13 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
                 og.restart = std::min(50, std::max(o.restart, 10));
                 const int nbk = (int)broken.size();
                 Work wg;
-                alloc_work(wg, S, nbk, og.restart, n_dir, prec);
+                WorkShape shg;
+                shg.B = nbk;
+                shg.m = og.restart;
+                shg.n_dir = n_dir;
+                shg.prec = prec;
+                make_work(wg, S, shg);
+                clear_work(wg, st);
                 WFQ_HIP(hipMemcpyAsync(wg.b.p, w.b.p, w.b.count * sizeof(double), hipMemcpyDeviceToDevice, st));
                 std::vector<SysState> sg(nbk);
                 for (int q = 0; q < nbk; ++q) {
@@ -1016,7 +1201,7 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
                     WFQ_HIP(hipMemcpyAsync(wg.X.p + (size_t)q * 2 * S.npad, w.Xb.base + (size_t)s * w.Xb.sys_stride,
                                            2 * S.npad * sizeof(double), hipMemcpyDeviceToDevice, st));
                 }
-                gmres_batch(S, wg, sg, tol, og, tm, st, t0, true);
+                gmres_batch(S, wg, sg, tol, og, tm, st, t0, nullptr, true);
                 for (int q = 0; q < nbk; ++q) {
                     const int s = broken[q];
                     const int iters_qmr = ss[s].iters, cycles_qmr = ss[s].cycles;
@@ -1040,12 +1225,13 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
             scatter_q(S, S.dperm, w.sys[SLOT_ACT].p, nb, w.Xb, out.q_re ? out.q_re + (size_t)s0 * S.n : nullptr,
                       out.q_im ? out.q_im + (size_t)s0 * S.n : nullptr, st);
         } else if (out.q_re || out.q_im) {
-            scatter_q(S, S.dperm, w.sys[SLOT_ACT].p, nb, w.Xb, stage_re.p, stage_im.p, st);
+            scatter_q(S, S.dperm, w.sys[SLOT_ACT].p, nb, w.Xb, out.q_re ? w.stage_re.p : nullptr,
+                      out.q_im ? w.stage_im.p : nullptr, st);
             if (out.q_re)
-                WFQ_HIP(hipMemcpyAsync(out.q_re + (size_t)s0 * S.n, stage_re.p, (size_t)nb * S.n * 8,
+                WFQ_HIP(hipMemcpyAsync(out.q_re + (size_t)s0 * S.n, w.stage_re.p, (size_t)nb * S.n * 8,
                                        hipMemcpyDeviceToHost, st));
             if (out.q_im)
-                WFQ_HIP(hipMemcpyAsync(out.q_im + (size_t)s0 * S.n, stage_im.p, (size_t)nb * S.n * 8,
+                WFQ_HIP(hipMemcpyAsync(out.q_im + (size_t)s0 * S.n, w.stage_im.p, (size_t)nb * S.n * 8,
                                        hipMemcpyDeviceToHost, st));
         }
         WFQ_HIP(hipStreamSynchronize(st));

@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--precision", default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-reference", action="store_true", help="skip the FP64 comparison runs")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the leg with warm starts across neighbouring frequencies")
     ap.add_argument("--no-multishift", action="store_true", help="skip the multi-shift FP64 run of the same systems")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB on the device 4 times (calibrates the HBM byte counters) and report GB/s")
@@ -312,6 +314,26 @@ def bench_batched(args, wl, wfq, torch):
             ms_line["max_rel_err_q_vs_fp64_batched"] = float(
                 (np.linalg.norm(qms - qref, axis=1) / np.linalg.norm(qref, axis=1)).max())
         extra["multishift_fp64"] = ms_line
+    if not otf and algo == "gmres" and not args.no_warm_start and len(wl.omegas_eV) >= 3 and wl.n <= 50000:
+        # warm starts across neighbouring frequencies (the same options as the timed steps): one
+        # warm-up and one timed run
+        wopts = dict(opts, warm_start=True)
+        wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=True, **wopts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ws = wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=True, **wopts)
+        torch.cuda.synchronize()
+        t_ws = time.perf_counter() - t0
+        ws_line = dict(value=S / t_ws, unit="solves/s", ms_per_step=t_ws * 1e3, dtype=prec,
+                       iters_mean=float(np.mean([r["iters"] for r in ws["info"]])),
+                       iters_max=int(max(r["iters"] for r in ws["info"])),
+                       relres_max=max(r["relres"] for r in ws["info"]),
+                       statuses=sorted(set(r["status"] for r in ws["info"])))
+        if "fp64_reference_systems" in extra and extra["fp64_reference_systems"] == S:
+            qws = ws["q"].reshape(S, wl.n)
+            ws_line["max_rel_err_q_vs_fp64_batched"] = float(
+                (np.linalg.norm(qws - qref, axis=1) / np.linalg.norm(qref, axis=1)).max())
+        extra["warm_start"] = ws_line
 
     if not args.no_cpu_baseline:
         if otf or wl.n > 50000:

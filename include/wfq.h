@@ -120,6 +120,13 @@ typedef struct {
                             costs milliseconds: off by default. Needs a stream other than the null stream
                             (wfq_solve_dev). Graphs and the work space stay on the handle until a solve of
                             another shape or wfq_destroy. */
+    int32_t warm_start;  /* GMRES only, nonzero: warm starts across neighbouring frequencies instead of
+                            q0 = 0 (the paper's protocol). Per direction, the systems of a batch sorted by
+                            frequency: every second one and the highest are solved first from q0 = 0; each
+                            of the others then starts from the linear interpolation in z of its two solved
+                            neighbours (q depends on the frequency only through z) and runs batched
+                            GMRES with FP64 refinement from there. Needs n_omega >= 3 (else ignored);
+                            WFQ_EINVAL with another algorithm. */
 } wfq_solve_opts;
 
 typedef struct {

@@ -469,6 +469,17 @@ def isotropic_cross_section(omega_ha, alpha):
 
 # --------------------------------------------------------------------------- a whole problem
 
+def interpolate_start(q_a, q_b, z_a, z_b, z):
+    """Starting guess for the shift z from solutions at two neighbouring shifts: the straight line
+    through (z_a, q_a) and (z_b, q_b) in the complex z-plane, evaluated at z. The solution of
+    (L T + z I) q = b depends on the frequency only through z and is analytic in z away from the
+    spectrum of -L T, so the guess is second-order accurate in the spacing."""
+    if z_b == z_a:
+        return np.array(q_a, dtype=np.complex128)
+    t = (z - z_a) / (z_b - z_a)
+    return q_a + t * (q_b - q_a)
+
+
 class Problem:
     """One structure with its model matrices (all FP64, atomic units)."""
 
@@ -527,8 +538,33 @@ class Problem:
     def solve_lu(self, omega_eV, direction, E0=1.0):
         return solve_dense(self.L, self.T, self.z(omega_eV), self.rhs(direction, E0))
 
-    def solve_gmres(self, omega_eV, direction, restart, tol, maxiter=100000, E0=1.0):
-        return gmres(self.apply(self.z(omega_eV)), self.rhs(direction, E0), restart, tol, maxiter)
+    def solve_gmres(self, omega_eV, direction, restart, tol, maxiter=100000, E0=1.0, x0=None):
+        return gmres(self.apply(self.z(omega_eV)), self.rhs(direction, E0), restart, tol, maxiter, x0=x0)
+
+    def solve_warm_sweep(self, omegas_eV, direction, restart, tol, maxiter=100000, E0=1.0):
+        """GMRES over a frequency sweep with warm starts (a project extension; the paper starts every
+        solve from q0 = 0). With the frequencies sorted, every second one and the highest are solved
+        from zero; each other one starts from `interpolate_start` of its two solved neighbours.
+        Returns (Q [n_omega][N] in the given order, iters [n_omega], first [n_omega] bool)."""
+        om = np.asarray(omegas_eV, dtype=np.float64)
+        order = np.argsort(om, kind="stable")
+        c = len(om)
+        first = np.zeros(c, dtype=bool)
+        for p, k in enumerate(order):
+            first[k] = (p % 2 == 0) or (p == c - 1)
+        Q = np.zeros((c, self.n), dtype=np.complex128)
+        iters = np.zeros(c, dtype=np.int64)
+        for k in np.flatnonzero(first):
+            Q[k], info = self.solve_gmres(om[k], direction, restart, tol, maxiter, E0)
+            iters[k] = info["iters"]
+        for p, k in enumerate(order):
+            if first[k]:
+                continue
+            a, b = order[p - 1], order[p + 1]
+            x0 = interpolate_start(Q[a], Q[b], self.z(om[a]), self.z(om[b]), self.z(om[k]))
+            Q[k], info = self.solve_gmres(om[k], direction, restart, tol, maxiter, E0, x0=x0)
+            iters[k] = info["iters"]
+        return Q, iters, first
 
     def apply_LT(self, x):
         """x -> L T x: the real frequency-independent part of the operator (minus A of Eq. wfq-a-matrix)."""

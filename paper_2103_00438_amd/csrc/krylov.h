@@ -86,6 +86,11 @@ void sumsq(const int* sys, int nsys, const double* norm2, int nb, double* out, h
 void copy_rhs(const Structure& S, const int* sys, int nsys, const double* b, const int* dir, const Basis& V,
               double* norm2, int nblk, hipStream_t st);
 
+// Warm start across neighbouring frequencies: x(sys[k]) = x(a) + t[k] (x(b) - x(a)) with a = src_a[k],
+// b = src_b[k] (linear interpolation in the shift z between two solved systems of one direction).
+void interp_start(const int* sys, int nsys, const int* src_a, const int* src_b, const double2* t, const Basis& x,
+                  int64_t n, hipStream_t st);
+
 // alpha[s][l] = sum_i r_{i,l} x(s)_i / E0  (complex, l = x, y, z)
 void observables(const Structure& S, const int* sys, int nsys, const Basis& x, double E0, double2* alpha,
                  hipStream_t st);

@@ -621,7 +621,32 @@ __global__ void __launch_bounds__(256) scatter_kernel(int64_t n, const int32_t* 
     if (qi) qi[o] = xr[i + X.npad];
 }
 
+// x(sys[k]) = x(src_a[k]) + t[k] (x(src_b[k]) - x(src_a[k])), complex t (the targets are distinct from
+// every source)
+__global__ void __launch_bounds__(256) interp_kernel(int64_t n, const int* __restrict__ sys,
+                                                     const int* __restrict__ src_a, const int* __restrict__ src_b,
+                                                     const double2* __restrict__ t, Basis X) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int k = blockIdx.y;
+    const double* ar = vre(X, src_a[k], 0);
+    const double* br = vre(X, src_b[k], 0);
+    double* xr = vre(X, sys[k], 0);
+    const double2 tk = t[k];
+    const double dr = br[i] - ar[i], di = br[i + X.npad] - ar[i + X.npad];
+    xr[i] = ar[i] + (tk.x * dr - tk.y * di);
+    xr[i + X.npad] = ar[i + X.npad] + (tk.x * di + tk.y * dr);
+}
+
 }  // namespace
+
+void interp_start(const int* sys, int nsys, const int* src_a, const int* src_b, const double2* t, const Basis& x,
+                  int64_t n, hipStream_t st) {
+    if (nsys <= 0) return;
+    dim3 grd((unsigned)((n + 255) / 256), (unsigned)nsys);
+    hipLaunchKernelGGL(interp_kernel, grd, dim3(256), 0, st, n, sys, src_a, src_b, t, x);
+    WFQ_CHECK_LAUNCH();
+}
 
 void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, const double* scale, bool write_back,
                   void* X, int64_t ld, hipStream_t st, const int* run) {

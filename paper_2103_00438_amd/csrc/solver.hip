@@ -160,6 +160,8 @@ struct Work {
     Buf<int> first;
     Buf<int> flags, ksteps, dir, run, sys[NSLOT];
     Buf<double> d_dirs, stage_re, stage_im;
+    Buf<int> warm_sys, warm_a, warm_b;   // warm starts: target and the two solved neighbours
+    Buf<double2> warm_t;                 // interpolation weight in z
     MsWork ms;
     // pinned host mirrors
     Buf<double> h_snorm, h_est, h_beta, h_invb;
@@ -239,6 +241,10 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.first, B);
     d.take(w.tpb, sh.qmr ? (size_t)B * 2 * np : 0);   // QMR: compact T p, rows by system id
     d.take(w.d_dirs, (size_t)3 * n_dir);
+    d.take(w.warm_sys, B);
+    d.take(w.warm_a, B);
+    d.take(w.warm_b, B);
+    d.take(w.warm_t, B);
     d.take(w.stage_re, (size_t)B * S.n);   // host outputs are staged through these
     d.take(w.stage_im, (size_t)B * S.n);
     h.take(w.h_flags, B);
@@ -489,9 +495,10 @@ void fp64_residual(const Structure& S, Work& w, const std::vector<int>& act, Tim
 }
 
 // Restarted GMRES(m) with FP64 refinement at every restart, for the systems of one batch.
+// `only` (if not NULL) restricts the solve to those systems of the batch; the others are untouched.
 void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double tol, const wfq_solve_opts& o,
                  Timer& tm, hipStream_t st, std::chrono::steady_clock::time_point t0, GraphCache* graphs,
-                 bool warm = false) {
+                 bool warm = false, const std::vector<int>* only = nullptr) {
     const int B = (int)ss.size();
     const int m = w.mdim - 1;
     const double n = (double)S.n;
@@ -508,18 +515,24 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         if (!warm) WFQ_HIP(hipMemsetAsync(w.X.p, 0, w.X.count * sizeof(double), st));
         WFQ_HIP(hipStreamSynchronize(st));
     }
-    std::vector<int> all(B);
-    for (int s = 0; s < B; ++s) all[s] = s;
+    std::vector<int> all;
+    if (only) {
+        all = *only;
+    } else {
+        all.resize(B);
+        for (int s = 0; s < B; ++s) all[s] = s;
+    }
+    if (all.empty()) return;
     upload(w, SLOT_ACT, all, st);
     // x0 = 0, r0 = b
-    copy_rhs(S, w.sys[SLOT_ACT].p, B, w.b.p, w.dir.p, w.Vb, w.norm2.p, (int)w.nblk, st);
-    sumsq(w.sys[SLOT_ACT].p, B, w.norm2.p, (int)w.nblk, w.beta.p, st);
+    copy_rhs(S, w.sys[SLOT_ACT].p, (int)all.size(), w.b.p, w.dir.p, w.Vb, w.norm2.p, (int)w.nblk, st);
+    sumsq(w.sys[SLOT_ACT].p, (int)all.size(), w.norm2.p, (int)w.nblk, w.beta.p, st);
     WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
     WFQ_HIP(hipStreamSynchronize(st));
     std::vector<int> active;
     {
         std::vector<double> tol_h(B);
-        for (int s = 0; s < B; ++s) {
+        for (int s : all) {
             ss[s].bnorm = ss[s].beta = w.h_beta.p[s];
             tol_h[s] = 0.5 * tol * ss[s].bnorm;   // inner target: half the outer one
             if (ss[s].bnorm == 0.0) {
@@ -1093,6 +1106,56 @@ void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double to
     }
 }
 
+// Warm starts across neighbouring frequencies (two passes): per direction, the systems of the batch
+// sorted by frequency; every second one and the last are solved first from q0 = 0, and each of the
+// others starts from the linear interpolation in z of its two solved neighbours (q depends on the
+// frequency only through z). A neighbour that failed leaves the system at q0 = 0.
+struct WarmPlan {
+    std::vector<int> first, second, tgt, a, b;
+    std::vector<double2> t;
+};
+
+WarmPlan warm_plan(const std::vector<SysState>& ss, int n_dir) {
+    WarmPlan p;
+    for (int d = 0; d < n_dir; ++d) {
+        std::vector<int> mem;
+        for (int s = 0; s < (int)ss.size(); ++s)
+            if (ss[s].dir == d) mem.push_back(s);
+        std::stable_sort(mem.begin(), mem.end(), [&](int x, int y) { return ss[x].omega < ss[y].omega; });
+        const int c = (int)mem.size();
+        for (int q = 0; q < c; ++q) {
+            if (q % 2 == 0 || q == c - 1)
+                p.first.push_back(mem[q]);
+            else
+                p.second.push_back(mem[q]);
+        }
+    }
+    return p;
+}
+
+// the interpolation lists of the second pass, once the first pass is done
+void warm_lists(WarmPlan& p, const std::vector<SysState>& ss) {
+    for (int s : p.second) {
+        // neighbours: the nearest solved systems of the same direction below and above in frequency
+        int a = -1, b = -1;
+        for (int f : p.first) {
+            if (ss[f].dir != ss[s].dir) continue;
+            if (ss[f].omega <= ss[s].omega && (a < 0 || ss[f].omega > ss[a].omega)) a = f;
+            if (ss[f].omega >= ss[s].omega && (b < 0 || ss[f].omega < ss[b].omega)) b = f;
+        }
+        if (a < 0 || b < 0 || ss[a].status != WFQ_OK || ss[b].status != WFQ_OK) continue;
+        const double2 za = ss[a].z, zb = ss[b].z, zs = ss[s].z;
+        const double dr = zb.x - za.x, di = zb.y - za.y, den = dr * dr + di * di;
+        const double nr = zs.x - za.x, ni = zs.y - za.y;
+        const double2 t = den > 0.0 ? make_double2((nr * dr + ni * di) / den, (ni * dr - nr * di) / den)
+                                    : make_double2(0.0, 0.0);
+        p.tgt.push_back(s);
+        p.a.push_back(a);
+        p.b.push_back(b);
+        p.t.push_back(t);
+    }
+}
+
 }  // namespace
 
 uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_dir) {
@@ -1172,6 +1235,20 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
             // shared-basis phase, then batched GMRES from its iterates (FP64 residual first)
             msgmres_phase(S, w, ss, tol, o, tm, st, t0, graphs);
             gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs, true);
+        } else if (!qmr && o.warm_start && n_omega >= 3) {
+            WarmPlan wp = warm_plan(ss, n_dir);
+            gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs, false, &wp.first);
+            warm_lists(wp, ss);
+            const int nt = (int)wp.tgt.size();
+            if (nt > 0) {
+                WFQ_HIP(hipMemcpyAsync(w.warm_sys.p, wp.tgt.data(), nt * sizeof(int), hipMemcpyHostToDevice, st));
+                WFQ_HIP(hipMemcpyAsync(w.warm_a.p, wp.a.data(), nt * sizeof(int), hipMemcpyHostToDevice, st));
+                WFQ_HIP(hipMemcpyAsync(w.warm_b.p, wp.b.data(), nt * sizeof(int), hipMemcpyHostToDevice, st));
+                WFQ_HIP(hipMemcpyAsync(w.warm_t.p, wp.t.data(), nt * sizeof(double2), hipMemcpyHostToDevice, st));
+                interp_start(w.warm_sys.p, nt, w.warm_a.p, w.warm_b.p, w.warm_t.p, w.Xb, S.n, st);
+                WFQ_HIP(hipStreamSynchronize(st));
+            }
+            gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs, true, &wp.second);
         } else if (!qmr) {
             gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs);
         } else {

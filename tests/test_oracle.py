@@ -418,3 +418,41 @@ def test_matrix_free_t_matches_stored():
     Pf = O.Problem(xyz, G, dense_T=False)
     x = np.random.default_rng(2).standard_normal((Pd.n, 2)) @ np.array([1.0, 1j])
     assert np.allclose(Pf.apply_T(x), Pd.T @ x, rtol=1e-13, atol=0)
+
+
+# ----------------------------------------------------------------- warm starts across frequencies
+
+def test_interpolated_start_is_exact_for_affine_data_and_second_order():
+    # the weight t = (z - z_a) / (z_b - z_a) reproduces any q(z) = u + z v exactly (a conjugated or
+    # real-only weight would not), and for the true solution the start error falls ~4x per halving
+    # of the spacing (second order: q is analytic in z between the neighbours)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    v = rng.standard_normal(50) + 1j * rng.standard_normal(50)
+    za, zb, z = -0.3 - 0.02j, -0.7 - 0.05j, -0.45 - 0.03j
+    assert np.allclose(O.interpolate_start(u + za * v, u + zb * v, za, zb, z), u + z * v, rtol=0, atol=1e-13)
+    P = small_problem()
+    d = np.array([1.0, 0.0, 0.0])
+    q = P.solve_lu(0.5, d)
+    errs = []
+    for h in (0.04, 0.02, 0.01):
+        x0 = O.interpolate_start(P.solve_lu(0.5 - h, d), P.solve_lu(0.5 + h, d), P.z(0.5 - h), P.z(0.5 + h), P.z(0.5))
+        errs.append(np.linalg.norm(x0 - q) / np.linalg.norm(q))
+    assert 3.0 < errs[0] / errs[1] < 5.0 and 3.0 < errs[1] / errs[2] < 5.0, errs
+
+
+def test_gmres_from_exact_start_takes_no_step_and_warm_sweep_matches_lu():
+    P = small_problem()
+    d = np.array([0.0, 1.0, 0.0])
+    q = P.solve_lu(0.6, d)
+    x, info = P.solve_gmres(0.6, d, restart=20, tol=1e-10, x0=q)
+    assert info["iters"] == 0 and np.allclose(x, q, rtol=0, atol=1e-12 * np.linalg.norm(q))
+    om = np.linspace(0.2, 1.0, 9)
+    Q, iters, first = P.solve_warm_sweep(om, d, restart=20, tol=1e-10)
+    assert first.tolist() == [True, False] * 4 + [True]
+    cold = [P.solve_gmres(w, d, restart=20, tol=1e-10)[1]["iters"] for w in om]
+    for k, w in enumerate(om):
+        ref = P.solve_lu(w, d)
+        assert np.linalg.norm(Q[k] - ref) <= 1e-7 * np.linalg.norm(ref)
+    # the interpolated starts save steps on every warm system
+    assert all(iters[k] < cold[k] for k in range(len(om)) if not first[k]), (iters, cold)

@@ -67,6 +67,37 @@ struct GivensArgs {
 };
 void givens_step(const int* sys, int nsys, int j, int mdim, const GivensArgs& a, hipStream_t st);
 
+// ---- Arnoldi with one reduction per step (dcgs.hip): classical Gram-Schmidt with delayed
+// reorthogonalisation. Step k (0 .. m) of a cycle: slot k holds u (one projection pass, unit norm;
+// at k = m the unnormalised w'), slot k + 1 holds z = (L T + z I) u for k < m.
+struct DcgsArgs {
+    const double2* dots;   // [S][2 mdim] reduced fused dots: a = Q^H u (0..k-1), alpha (k), b = Q^H z, beta
+    double2* hp;           // [S][mdim] first-pass coefficients of the newest column
+    double2* H;            // [S][mdim][mdim] Hessenberg matrix before rotations, column-major
+    double2* R;            // [S][mdim][mdim] rotated columns (R[s][c][i] = R_ic)
+    double* cs;            // [S][mdim]
+    double2* sn;           // [S][mdim]
+    double2* g;            // [S][mdim + 1]
+    double* est;           // [S] |g_{c+1}| after column c
+    const double* tol_abs; // [S]
+    int* flags;            // [S] bit0 converged, bit1 happy breakdown, bit2 NaN
+    int* ksteps;           // [S] completed columns in this cycle
+    int* run;              // [S] 1 while stepping; cleared with a flag
+    double* nu;            // [S] |w'| of the previous step
+    double* inv_h;         // [S] 1 / nu (the next product is taken of w' / nu)
+    double2* gamma;        // [S]
+    double* inv_rho;       // [S]
+    double* norm2;         // [S][nwc] chunk partials of |w'|^2
+};
+// partial[s][t][wc]: the fused dots of step k over 512-row chunks (2 k + 2 entries; k + 1 without z)
+void dcgs_dots(const Basis& V, int64_t n, const int* sys, int nsys, int k, bool with_z, double2* partial, int mdim,
+               const int* run, hipStream_t st);
+// column k - 1 of H completed and rotated (k >= 1), the step's update coefficients (with_z)
+void dcgs_coeff(const int* sys, int nsys, int k, bool with_z, int mdim, const DcgsArgs& a, hipStream_t st);
+// q_k into slot k, w' into slot k + 1, then nu and inv_h
+void dcgs_update(const Basis& V, int64_t n, const int* sys, int nsys, int k, int mdim, const DcgsArgs& a,
+                 hipStream_t st);
+
 // y = R^-1 g over the first k[s] steps; cond[s] = max|R_ii| / min|R_ii| (a cheap condition estimate).
 void tri_solve(const int* sys, int nsys, const int* ksteps, int mdim, const double2* R, const double2* g,
                double2* y, double* cond, hipStream_t st);

@@ -153,7 +153,8 @@ struct Work {
     Buf<int> reorth;
     Buf<float> X32, Y32, Y16;
     Buf<uint16_t> X16;
-    Buf<double2> partial, h1, h2, R, sn, g, y, z, alpha;
+    Buf<double2> partial, h1, h2, R, Hu, sn, g, y, z, alpha, gam;
+    Buf<double> nu, irho;
     // QMR scalars and partials
     Buf<double2> rho_a, rho_b, sigma, part_sig, part_nrm;
     Buf<double> tau2, eta, snorm, tpb;
@@ -203,10 +204,14 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.Y32, w.need32 ? (size_t)w.mpad * np : 0);
     d.take(w.X16, w.need16 ? (size_t)w.mpad * np : 0);
     d.take(w.Y16, w.need16 ? (size_t)w.mpad * np : 0);
-    d.take(w.partial, (size_t)B * w.mdim * w.nwc);
-    d.take(w.h1, (size_t)B * w.mdim);
+    d.take(w.partial, (size_t)B * 2 * w.mdim * w.nwc);   // fused dots: two entries per basis vector
+    d.take(w.h1, (size_t)B * 2 * w.mdim);
     d.take(w.h2, (size_t)B * w.mdim);
     d.take(w.R, (size_t)B * w.mdim * w.mdim);
+    d.take(w.Hu, sh.qmr ? 0 : (size_t)B * w.mdim * w.mdim);
+    d.take(w.gam, B);
+    d.take(w.nu, B);
+    d.take(w.irho, B);
     d.take(w.cs, (size_t)B * w.mdim);
     d.take(w.sn, (size_t)B * w.mdim);
     d.take(w.g, (size_t)B * (w.mdim + 1));
@@ -569,9 +574,6 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         active.swap(still);
     }
 
-    GivensArgs ga{w.h1.p, w.h2.p, w.norm2.p, (int)w.nwc, w.norm2a.p, w.reorth.p, w.R.p, w.cs.p, w.sn.p, w.g.p,
-                  w.est.p, w.inv_h.p, w.tol_abs.p, w.flags.p};
-
     while (!active.empty()) {
         // cycle start: g = beta e1, v0 = r / beta
         std::memset(w.h_g.p, 0, (size_t)B * (w.mdim + 1) * sizeof(double2));
@@ -586,16 +588,13 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         std::vector<int> stepping;
         for (int s : active)
             if (ss[s].iters < o.max_iter) stepping.push_back(s);
-        // Convergence is tracked on the device (the Givens step records the step count and clears
-        // run[s] when a flag is raised; every step kernel skips stopped systems). The host reads the
+        // Convergence is tracked on the device (the column step records the completed columns and
+        // clears run[s] when a flag is raised; every step kernel skips stopped systems). The host reads the
         // flags and compacts the lists every `chunk` steps: after every step for large problems, whose
         // block products shrink as systems drop out, and every 8 steps for small ones, where the
         // round trip would cost more than the steps.
         const int chunk = (S.npad <= 8192) ? 8 : 1;
         WFQ_HIP(hipMemcpyAsync(w.ksteps.p, w.h_ksteps.p, B * sizeof(int), hipMemcpyHostToDevice, st));
-        GivensArgs gc_args = ga;
-        gc_args.ksteps = w.ksteps.p;
-        gc_args.run = w.run.p;
         std::vector<int> grp[3];
         auto lists = [&]() {   // upload the group lists, the step list and run = 1 for them
             for (int p = 0; p < 3; ++p) grp[p].clear();
@@ -609,66 +608,66 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             WFQ_HIP(hipStreamSynchronize(st));   // runh is a host temporary
         };
         lists();
+        std::vector<int> it0(B, 0);
+        for (int s : active) it0[s] = ss[s].iters;
+        const DcgsArgs da{w.h1.p, w.h2.p, w.Hu.p, w.R.p, w.cs.p, w.sn.p, w.g.p, w.est.p, w.tol_abs.p, w.flags.p,
+                          w.ksteps.p, w.run.p, w.nu.p, w.inv_h.p, w.gam.p, w.irho.p, w.norm2.p};
         // graphs only where steps are chunked and no per-launch events are recorded
         GraphCache* gc = (chunk > 1 && !tm.on()) ? graphs : nullptr;
-        for (int j0 = 0; j0 < m && !stepping.empty();) {
+        // steps k = 0 .. m: step k forms the product of the newest direction (k < m) and completes
+        // column k - 1 (k >= 1); the last step only completes column m - 1
+        for (int k0 = 0; k0 <= m && !stepping.empty();) {
             const int ns = (int)stepping.size();
-            const int* run = chunk > 1 ? w.run.p : nullptr;
             // steps until the next read-back: the chunk, the end of the cycle, or the first system
-            // that would pass max_iter
-            int c = std::min(chunk, m - j0);
+            // that could pass max_iter (a step completes at most one column)
+            int c = std::min(chunk, m + 1 - k0);
             for (int s : stepping) c = std::min(c, o.max_iter - ss[s].iters);
-            auto step = [&](int j) {
-                // the operator on the new basis vectors, one block product per precision group
-                for (int p = 0; p < 3; ++p) {
-                    if (grp[p].empty()) continue;
-                    const int ng = (int)grp[p].size();
-                    tm.begin(st);
-                    pack_columns(p, w.Vb, w.sys[p].p, ng, j, j == 0 ? w.inv_beta.p : w.inv_h.p, true, x_block(w, p),
-                                 w.npad, st, run);
-                    tm.end(st, KC_PACK, 0, ng * n * (32.0 + 2 * elem_size(p)));
-                    block_product(S, w, p, 2 * ng, tm, st);
-                    tm.begin(st);
-                    spmm_shift(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, w.z.p, w.Vb, j, j + 1,
-                               st);
-                    tm.end(st, KC_SPMM, 4.0 * S.nnz * ng + 8 * n * ng,
-                           12.0 * S.nnz + ng * n * (2.0 * out_size(p) + 16 + 16));
+            auto step = [&](int k) {
+                const bool with_z = k < m;
+                if (with_z) {
+                    // the operator on the newest direction, one block product per precision group
+                    for (int p = 0; p < 3; ++p) {
+                        if (grp[p].empty()) continue;
+                        const int ng = (int)grp[p].size();
+                        tm.begin(st);
+                        pack_columns(p, w.Vb, w.sys[p].p, ng, k, k == 0 ? w.inv_beta.p : w.inv_h.p, true,
+                                     x_block(w, p), w.npad, st, w.run.p);
+                        tm.end(st, KC_PACK, 0, ng * n * (32.0 + 2 * elem_size(p)));
+                        block_product(S, w, p, 2 * ng, tm, st);
+                        tm.begin(st);
+                        spmm_shift(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, w.z.p, w.Vb, k,
+                                   k + 1, st);
+                        tm.end(st, KC_SPMM, 4.0 * S.nnz * ng + 8 * n * ng,
+                               12.0 * S.nnz + ng * n * (2.0 * out_size(p) + 16 + 16));
+                    }
                 }
-                // CGS2 against v_0 .. v_j, then the Givens update of the least-squares problem
+                // one fused sweep of dots, the Hessenberg column and its rotation, one update sweep
                 const int* sl = w.sys[SLOT_STEP].p;
-                // first pass (with ||w||^2), the reorthogonalisation test, and the second pass only
-                // for the systems that need it
                 tm.begin(st);
-                multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, run, true);
-                reduce_dots(S.n, sl, ns, j + 1, w.partial.p, w.mdim, w.h1.p, st, run);
-                tm.end(st, KC_DOT, 8.0 * n * ns * (j + 2), 16.0 * n * ns * (j + 2));
+                dcgs_dots(w.Vb, S.n, sl, ns, k, with_z, w.partial.p, w.mdim, w.run.p, st);
+                reduce_dots(S.n, sl, ns, with_z ? 2 * k + 1 : k, w.partial.p, 2 * w.mdim, w.h1.p, st, w.run.p);
+                tm.end(st, KC_DOT, 16.0 * n * ns * (k + 1), 16.0 * n * ns * (k + 2));
                 tm.begin(st);
-                multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h1.p, w.mdim, w.norm2a.p, st, run);
-                reorth_test(sl, ns, j, w.mdim, w.h1.p, w.norm2a.p, S.n, w.h2.p, w.reorth.p, st, run);
-                tm.end(st, KC_UPDATE, 8.0 * n * ns * (j + 1), 16.0 * n * ns * (j + 3));
-                tm.begin(st);
-                multi_dot(w.Vb, S.n, sl, ns, j, j + 1, w.partial.p, w.mdim, st, w.reorth.p, false);
-                reduce_dots(S.n, sl, ns, j, w.partial.p, w.mdim, w.h2.p, st, w.reorth.p);
-                tm.end(st, KC_DOT, 0, 0);
-                tm.begin(st);
-                multi_update(w.Vb, S.n, sl, ns, j, j + 1, w.h2.p, w.mdim, w.norm2.p, st, w.reorth.p);
-                tm.end(st, KC_UPDATE, 0, 0);
-                tm.begin(st);
-                givens_step(sl, ns, j, w.mdim, gc_args, st);
+                dcgs_coeff(sl, ns, k, with_z, w.mdim, da, st);
                 tm.end(st, KC_GIVENS, 0, 0);
+                if (with_z) {
+                    tm.begin(st);
+                    dcgs_update(w.Vb, S.n, sl, ns, k, w.mdim, da, st);
+                    tm.end(st, KC_UPDATE, 16.0 * n * ns * k, 16.0 * n * ns * (k + 4));
+                }
             };
-            const GraphKey key{0, j0, c, ns, (int)grp[0].size(), (int)grp[1].size(), (int)grp[2].size()};
+            const GraphKey key{0, k0, c, ns, (int)grp[0].size(), (int)grp[1].size(), (int)grp[2].size()};
             run_chunk(gc, S, key, st, [&] {
-                for (int j = j0; j < j0 + c; ++j) step(j);
+                for (int k = k0; k < k0 + c; ++k) step(k);
             });
-            j0 += c;
+            k0 += c;
             WFQ_HIP(hipMemcpyAsync(w.h_flags.p, w.flags.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
             WFQ_HIP(hipMemcpyAsync(w.h_est.p, w.est.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
             WFQ_HIP(hipMemcpyAsync(w.h_ksteps.p, w.ksteps.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
             WFQ_HIP(hipStreamSynchronize(st));
             std::vector<int> next;
             for (int s : stepping) {
-                ss[s].iters += c - (j0 - w.h_ksteps.p[s]);   // steps this system took in the chunk
+                ss[s].iters = it0[s] + w.h_ksteps.p[s];   // columns completed in this cycle
                 ss[s].est_end = w.h_est.p[s];
                 const int f = w.h_flags.p[s];
                 if (f & 4) {
@@ -680,7 +679,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             const bool changed = next.size() != stepping.size();
             stepping.swap(next);
             if (changed && !stepping.empty()) lists();
-            if (j0 % 10 == 0) progress_line(o, "gmres", ss[active[0]].cycles, j0, stepping.size(), -1.0, t0);
+            if (k0 % 10 == 0) progress_line(o, "gmres", ss[active[0]].cycles, k0, stepping.size(), -1.0, t0);
         }
         // drop systems that hit NaN
         std::vector<int> act2;

@@ -31,42 +31,9 @@ void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, con
 void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
                 const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st, bool y_by_sys = false);
 
-// partial[s][i][wc] = sum over rows of wave chunk wc of conj(V(s, i)) * V(s, jw), i = 0..j; with
-// self_norm also partial[s][j+1][wc] = partial ||V(s, jw)||^2. Systems with active[s] == 0 are
-// skipped (active may be NULL).
-void multi_dot(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, double2* partial, int mdim,
-               hipStream_t st, const int* active = nullptr, bool self_norm = false);
 // h[s][i] = sum_wc partial[s][i][wc] for i <= j (skipping systems with active[s] == 0)
 void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
                  hipStream_t st, const int* active = nullptr);
-// V(s, jw) -= sum_{i<=j} h[s][i] V(s, i); with norm2 != NULL also norm2[s][wc] = partial sum |V(s, jw)|^2.
-void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, const double2* h, int mdim,
-                  double* norm2, hipStream_t st, const int* active = nullptr);
-// reorth[s] = (||w'||^2 < ||w||^2 / 2) with ||w||^2 from h1[s][j+1] and ||w'||^2 from norm2a; h2 = 0 where not needed
-void reorth_test(const int* sys, int nsys, int j, int mdim, const double2* h1, const double* norm2a, int64_t n,
-                 double2* h2, int* reorth, hipStream_t st, const int* run = nullptr);
-
-struct GivensArgs {
-    const double2* h1;   // [S][mdim] first CGS pass
-    const double2* h2;   // [S][mdim] second CGS pass
-    const double* norm2; // [S][nwc] partial squared norms of the new vector after the second pass
-    int nwc;
-    const double* norm2a; // [S][nwc] the same after the first pass (used where reorth[s] == 0)
-    const int* reorth;    // [S] 1 where the second pass ran (NULL: always)
-    double2* R;          // [S][mdim][mdim] column-major upper triangle (R[s][j][i] = R_ij)
-    double* cs;          // [S][mdim]
-    double2* sn;         // [S][mdim]
-    double2* g;          // [S][mdim + 1]
-    double* est;         // [S] |g_{j+1}|
-    double* inv_h;       // [S] 1 / h_{j+1,j} (normalisation of the next basis vector)
-    const double* tol_abs;  // [S]
-    int* flags;          // [S] bit0: converged (estimate), bit1: happy breakdown, bit2: NaN
-    int* ksteps = nullptr;  // [S] (optional) steps taken in this cycle, written every step
-    int* run = nullptr;     // [S] (optional) 1 while the system steps; cleared when a flag is raised,
-                            // after which every step kernel that takes `run` skips the system
-};
-void givens_step(const int* sys, int nsys, int j, int mdim, const GivensArgs& a, hipStream_t st);
-
 // ---- Arnoldi with one reduction per step (dcgs.hip): classical Gram-Schmidt with delayed
 // reorthogonalisation. Step k (0 .. m) of a cycle: slot k holds u (one projection pass, unit norm;
 // at k = m the unnormalised w'), slot k + 1 holds z = (L T + z I) u for k < m.
@@ -183,7 +150,7 @@ void ms_update(double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, 
 // Hessenberg column j from the two Gram-Schmidt passes and the norm; inv_h[d] = 1 / H_{j+1,j}
 void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const double* h2, int pslots,
              const double* norm, int64_t n, int64_t npad, double* H, double* inv_h, hipStream_t st);
-// Givens step j of each listed system on Hbar + z Ibar of its direction (flags as in givens_step);
+// Givens step j of each listed system on Hbar + z Ibar of its direction (flags: bit0 converged, bit1 breakdown, bit2 NaN);
 // systems with run[s] == 0 are skipped, ksteps[s] = j + 1 is recorded and run[s] cleared when a flag
 // is raised.
 void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const double2* z, const double* H, double* cs,

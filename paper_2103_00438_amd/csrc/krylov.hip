@@ -1,5 +1,5 @@
-// Krylov-side kernels: the sparse half of the operator (L Y + z V), classical Gram-Schmidt with
-// reorthogonalisation for the Arnoldi process, the Givens-updated Hessenberg least-squares problem,
+// Krylov-side kernels: the sparse half of the operator (L Y + z V), the reduction of Gram-Schmidt
+// partial dots (the Arnoldi sweeps themselves are in dcgs.hip), the Hessenberg least-squares solve,
 // the solution update, the FP64 refinement residual and the observables (arXiv 2103.00438, Section
 // "Solution strategies": GMRES paragraph and restarted GMRES(k); Eq. (long-cross) for the dipole).
 //
@@ -12,16 +12,9 @@ namespace wfq {
 
 namespace {
 
-// chunks x systems from which the one-wave-per-(chunk, system) Gram-Schmidt kernels fill the chip
-constexpr int64_t kWideWaves = 4096;
-
 __device__ inline double* vre(const Basis& V, int s, int j) { return V.base + (int64_t)s * V.sys_stride + (int64_t)j * V.vec_stride; }
 
 __device__ inline double2 cmul(double2 a, double2 b) { return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
-__device__ inline double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
-__device__ inline double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
-__device__ inline double2 cscale(double c, double2 a) { return make_double2(c * a.x, c * a.y); }
-__device__ inline double cabs2(double2 a) { return hypot(a.x, a.y); }
 
 // block of 256 threads -> one value, fixed order
 __device__ inline double block_sum(double v, double* sh) {
@@ -164,97 +157,6 @@ void launch_spmm_rows(const Structure& S, const YE* Y, int64_t ld, const int* sy
                        S.ell_w, S.ell_col, S.ell_val, Y, ld, sys, nsys, per_group, z, V, jsrc, jdst, (int)y_by_sys);
 }
 
-// Dots for many systems at once: one wave per (512-row chunk, system) walks over the basis vectors
-// (enough waves to fill the chip when systems x chunks is large).
-__global__ void __launch_bounds__(256) dot_rows_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
-                                                  double2* __restrict__ partial, int mdim, int64_t nwc,
-                                                  const int* __restrict__ active, int self_norm) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
-    if (wc >= nwc) return;
-    const int s = sys[blockIdx.y];
-    if (active && !active[s]) return;
-    const double* wr = vre(V, s, jw);
-    const double* wi = wr + V.npad;
-    const int64_t row0 = wc * kWaveRows + lane;
-    double xr[8], xi[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t row = row0 + 64 * r;
-        xr[r] = row < n ? wr[row] : 0.0;
-        xi[r] = row < n ? wi[row] : 0.0;
-    }
-    for (int i = 0; i <= j; ++i) {
-        const double* vr = vre(V, s, i);
-        const double* vi = vr + V.npad;
-        double sr = 0.0, si = 0.0;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t row = row0 + 64 * r;
-            if (row < n) {
-                const double a = vr[row], b = vi[row];
-                sr += a * xr[r] + b * xi[r];   // conj(v) w
-                si += a * xi[r] - b * xr[r];
-            }
-        }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
-        if (lane == 0) partial[((int64_t)s * mdim + i) * nwc + wc] = make_double2(sr, si);
-    }
-    if (self_norm) {
-        // ||w||^2 in slot j + 1 (the reorthogonalisation test compares it with the projected norm)
-        double nn = 0.0;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) nn += xr[r] * xr[r] + xi[r] * xi[r];
-        nn = wave_sum(nn);
-        if (lane == 0) partial[((int64_t)s * mdim + j + 1) * nwc + wc] = make_double2(nn, 0.0);
-    }
-}
-
-// Dots for the Arnoldi step: one wave per (512-row chunk, basis vector, system), so that even a
-// single system's step is spread over many waves; each sum runs in a fixed order.
-// partial[s][i][wc] = sum over chunk wc of conj(V(s, i)) V(s, jw), i <= j; with self_norm also
-// partial[s][j + 1][wc] = ||V(s, jw)||^2 over the chunk.
-__global__ void __launch_bounds__(256) dot_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
-                                                  double2* __restrict__ partial, int mdim, int64_t nwc,
-                                                  const int* __restrict__ active, int self_norm) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = blockIdx.x;
-    const int i = blockIdx.y * 4 + wave;
-    if (i > j + self_norm) return;
-    const int s = sys[blockIdx.z];
-    if (active && !active[s]) return;
-    const double* wr = vre(V, s, jw);
-    const double* wi = wr + V.npad;
-    const int64_t row0 = wc * kWaveRows + lane;
-    double sr = 0.0, si = 0.0;
-    if (i <= j) {
-        const double* vr = vre(V, s, i);
-        const double* vi = vr + V.npad;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t row = row0 + 64 * r;
-            if (row < n) {
-                const double a = vr[row], b = vi[row], x = wr[row], y = wi[row];
-                sr += a * x + b * y;   // conj(v) w
-                si += a * y - b * x;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t row = row0 + 64 * r;
-            if (row < n) {
-                const double x = wr[row], y = wi[row];
-                sr += x * x + y * y;
-            }
-        }
-    }
-    sr = wave_sum(sr);
-    si = wave_sum(si);
-    if (lane == 0) partial[((int64_t)s * mdim + i) * nwc + wc] = make_double2(sr, si);
-}
-
 __global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const double2* __restrict__ partial, int mdim,
                                    int64_t nwc, double2* __restrict__ h, const int* __restrict__ active) {
     const int s = sys[blockIdx.x];
@@ -268,192 +170,6 @@ __global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const dou
         }
         h[(int64_t)s * mdim + i] = make_double2(sr, si);
     }
-}
-
-// Update for many systems at once: one wave per (512-row chunk, system), the chunk in registers.
-__global__ void __launch_bounds__(256) update_rows_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
-                                                     const double2* __restrict__ h, int mdim,
-                                                     double* __restrict__ norm2, int64_t nwc,
-                                                     const int* __restrict__ active) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
-    if (wc >= nwc) return;
-    const int s = sys[blockIdx.y];
-    if (active && !active[s]) return;
-    double* wr = vre(V, s, jw);
-    double* wi = wr + V.npad;
-    const int64_t row0 = wc * kWaveRows + lane;
-    double xr[8], xi[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t row = row0 + 64 * r;
-        xr[r] = row < n ? wr[row] : 0.0;
-        xi[r] = row < n ? wi[row] : 0.0;
-    }
-    for (int i = 0; i <= j; ++i) {
-        const double2 hh = h[(int64_t)s * mdim + i];
-        const double* vr = vre(V, s, i);
-        const double* vi = vr + V.npad;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t row = row0 + 64 * r;
-            if (row < n) {
-                const double a = vr[row], b = vi[row];
-                xr[r] -= hh.x * a - hh.y * b;
-                xi[r] -= hh.x * b + hh.y * a;
-            }
-        }
-    }
-    double nn = 0.0;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        const int64_t row = row0 + 64 * r;
-        if (row < n) {
-            wr[row] = xr[r];
-            wi[row] = xi[r];
-            nn += xr[r] * xr[r] + xi[r] * xi[r];
-        }
-    }
-    if (norm2) {
-        nn = wave_sum(nn);
-        if (lane == 0) norm2[(int64_t)s * nwc + wc] = nn;
-    }
-}
-
-// Daniel-Gragg-Kaufman-Stewart test: a second Gram-Schmidt pass is needed only when projecting
-// removed more than half of the vector's squared norm (||w'||^2 < ||w||^2 / 2). Systems that skip it
-// get h2 = 0 and keep the norm of the first pass.
-// V(s, jw) -= sum_{i <= j} h[s][i] V(s, i) for one 512-row chunk per work-group: each of the 4 waves
-// sums every 4th basis vector over the whole chunk, the partial sums meet in LDS and are combined
-// in a fixed order; norm2[s][wc] (if not NULL) = ||V(s, jw)||^2 over the chunk, also in fixed order.
-__global__ void __launch_bounds__(256) update_kernel(Basis V, int64_t n, const int* __restrict__ sys, int j, int jw,
-                                                     const double2* __restrict__ h, int mdim,
-                                                     double* __restrict__ norm2, int64_t nwc,
-                                                     const int* __restrict__ active) {
-    __shared__ double pr[4][kWaveRows], pi[4][kWaveRows];
-    __shared__ double red[4];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = blockIdx.x;
-    const int s = sys[blockIdx.y];
-    if (active && !active[s]) return;   // whole work-group
-    const int64_t row0 = wc * kWaveRows;
-    double ar[8], ai[8];
-#pragma unroll
-    for (int r = 0; r < 8; ++r) ar[r] = ai[r] = 0.0;
-    for (int i = wave; i <= j; i += 4) {
-        const double2 hh = h[(int64_t)s * mdim + i];
-        const double* vr = vre(V, s, i);
-        const double* vi = vr + V.npad;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            const int64_t row = row0 + lane + 64 * r;
-            if (row < n) {
-                const double a = vr[row], b = vi[row];
-                ar[r] += hh.x * a - hh.y * b;
-                ai[r] += hh.x * b + hh.y * a;
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        pr[wave][lane + 64 * r] = ar[r];
-        pi[wave][lane + 64 * r] = ai[r];
-    }
-    __syncthreads();
-    double* wr = vre(V, s, jw);
-    double* wi = wr + V.npad;
-    double nn = 0.0;
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int q = threadIdx.x + 256 * t;
-        const int64_t row = row0 + q;
-        if (row < n) {
-            const double xr = wr[row] - ((pr[0][q] + pr[1][q]) + (pr[2][q] + pr[3][q]));
-            const double xi = wi[row] - ((pi[0][q] + pi[1][q]) + (pi[2][q] + pi[3][q]));
-            wr[row] = xr;
-            wi[row] = xi;
-            nn += xr * xr + xi * xi;
-        }
-    }
-    if (norm2) {
-        nn = wave_sum(nn);
-        if (lane == 0) red[wave] = nn;
-        __syncthreads();
-        if (threadIdx.x == 0) norm2[(int64_t)s * nwc + wc] = (red[0] + red[1]) + (red[2] + red[3]);
-    }
-}
-
-__global__ void reorth_test_kernel(const int* __restrict__ sys, int nsys, int j, int mdim,
-                                   const double2* __restrict__ h1, const double* __restrict__ norm2a, int nwc,
-                                   double2* __restrict__ h2, int* __restrict__ reorth, const int* __restrict__ run) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nsys) return;
-    const int s = sys[k];
-    if (run && !run[s]) {
-        reorth[s] = 0;
-        return;
-    }
-    double nw = 0.0;
-    for (int w = 0; w < nwc; ++w) nw += norm2a[(int64_t)s * nwc + w];
-    const double w2 = h1[(int64_t)s * mdim + j + 1].x;
-    const int need = !(nw >= 0.5 * w2);
-    reorth[s] = need;
-    if (!need)
-        for (int i = 0; i <= j; ++i) h2[(int64_t)s * mdim + i] = make_double2(0.0, 0.0);
-}
-
-// One thread per system: new Hessenberg column, previous rotations, new rotation, residual estimate.
-__global__ void givens_kernel(const int* __restrict__ sys, int nsys, int j, int mdim, GivensArgs a) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nsys) return;
-    const int s = sys[k];
-    if (a.run && !a.run[s]) return;   // stopped earlier in this chunk of steps
-    double2* col = a.R + ((int64_t)s * mdim + j) * mdim;
-    for (int i = 0; i <= j; ++i) col[i] = cadd(a.h1[(int64_t)s * mdim + i], a.h2[(int64_t)s * mdim + i]);
-    double hn2 = 0.0;
-    const double* nsrc = (a.reorth == nullptr || a.reorth[s]) ? a.norm2 : a.norm2a;
-    for (int w = 0; w < a.nwc; ++w) hn2 += nsrc[(int64_t)s * a.nwc + w];
-    const double hn = sqrt(hn2);
-    double* cs = a.cs + (int64_t)s * mdim;
-    double2* sn = a.sn + (int64_t)s * mdim;
-    for (int i = 0; i < j; ++i) {
-        const double2 x = col[i], y = col[i + 1];
-        col[i] = cadd(cscale(cs[i], x), cmul(sn[i], y));
-        col[i + 1] = cadd(cscale(-1.0, cmul(cconj(sn[i]), x)), cscale(cs[i], y));
-    }
-    // rotation zeroing hn below col[j]: c real, s complex, [c s; -conj(s) c]
-    const double2 x = col[j];
-    const double ax = cabs2(x);
-    double c;
-    double2 sv;
-    if (hn == 0.0) {
-        c = 1.0;
-        sv = make_double2(0.0, 0.0);
-    } else if (ax == 0.0) {
-        c = 0.0;
-        sv = make_double2(1.0, 0.0);
-    } else {
-        const double nu = hypot(ax, hn);
-        c = ax / nu;
-        sv = make_double2(x.x / ax * hn / nu, x.y / ax * hn / nu);
-    }
-    cs[j] = c;
-    sn[j] = sv;
-    col[j] = cadd(cscale(c, x), cscale(hn, sv));
-    double2* g = a.g + (int64_t)s * (mdim + 1);
-    const double2 gj = g[j];
-    g[j + 1] = cscale(-1.0, cmul(cconj(sv), gj));
-    g[j] = cscale(c, gj);
-    const double est = cabs2(g[j + 1]);
-    a.est[s] = est;
-    a.inv_h[s] = hn > 0.0 ? 1.0 / hn : 0.0;
-    int f = 0;
-    if (est <= a.tol_abs[s]) f |= 1;
-    if (hn <= 1e-14 * cabs2(col[j])) f |= 2;
-    if (!(est == est) || !(hn == hn)) f |= 4;
-    a.flags[s] = f;
-    if (a.ksteps) a.ksteps[s] = j + 1;
-    if (a.run && f) a.run[s] = 0;
 }
 
 // One wave per system: column-oriented back substitution on R y = g (k <= mdim - 1 steps).
@@ -701,55 +417,11 @@ void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, co
     WFQ_CHECK_LAUNCH();
 }
 
-void multi_dot(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, double2* partial, int mdim,
-               hipStream_t st, const int* active, bool self_norm) {
-    if (nsys <= 0) return;
-    const int64_t nwc = wave_chunks(n);
-    if (nwc * nsys >= kWideWaves) {
-        dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
-        hipLaunchKernelGGL(dot_rows_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, partial, mdim, nwc, active,
-                           (int)self_norm);
-    } else {
-        dim3 grd((unsigned)nwc, (unsigned)((j + 1 + (self_norm ? 1 : 0) + 3) / 4), (unsigned)nsys);
-        hipLaunchKernelGGL(dot_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, partial, mdim, nwc, active,
-                           (int)self_norm);
-    }
-    WFQ_CHECK_LAUNCH();
-}
-
 void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
                  hipStream_t st, const int* active) {
     if (nsys <= 0) return;
     hipLaunchKernelGGL(reduce_dots_kernel, dim3(nsys), dim3(128), 0, st, sys, j, partial, mdim, wave_chunks(n), h,
                        active);
-    WFQ_CHECK_LAUNCH();
-}
-
-void multi_update(const Basis& V, int64_t n, const int* sys, int nsys, int j, int jw, const double2* h, int mdim,
-                  double* norm2, hipStream_t st, const int* active) {
-    if (nsys <= 0) return;
-    const int64_t nwc = wave_chunks(n);
-    if (nwc * nsys >= kWideWaves) {
-        dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)nsys);
-        hipLaunchKernelGGL(update_rows_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, h, mdim, norm2, nwc, active);
-    } else {
-        dim3 grd((unsigned)nwc, (unsigned)nsys);
-        hipLaunchKernelGGL(update_kernel, grd, dim3(256), 0, st, V, n, sys, j, jw, h, mdim, norm2, nwc, active);
-    }
-    WFQ_CHECK_LAUNCH();
-}
-
-void reorth_test(const int* sys, int nsys, int j, int mdim, const double2* h1, const double* norm2a, int64_t n,
-                 double2* h2, int* reorth, hipStream_t st, const int* run) {
-    if (nsys <= 0) return;
-    hipLaunchKernelGGL(reorth_test_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sys, nsys, j, mdim, h1, norm2a,
-                       (int)wave_chunks(n), h2, reorth, run);
-    WFQ_CHECK_LAUNCH();
-}
-
-void givens_step(const int* sys, int nsys, int j, int mdim, const GivensArgs& a, hipStream_t st) {
-    if (nsys <= 0) return;
-    hipLaunchKernelGGL(givens_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sys, nsys, j, mdim, a);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -149,8 +149,7 @@ struct Work {
     int B = 0, mdim = 0, n_dir = 0;
     int64_t n = 0, npad = 0, nwc = 0, nblk = 0, mpad = 0;
     bool need32 = false, need16 = false;
-    Buf<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, norm2a, tol_abs, cond;
-    Buf<int> reorth;
+    Buf<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, tol_abs, cond;
     Buf<float> X32, Y32, Y16;
     Buf<uint16_t> X16;
     Buf<double2> partial, h1, h2, R, Hu, sn, g, y, z, alpha, gam;
@@ -223,8 +222,6 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.inv_beta, B);
     d.take(w.beta, B);
     d.take(w.norm2, (size_t)B * std::max(w.nwc, w.nblk));
-    d.take(w.norm2a, (size_t)B * w.nwc);
-    d.take(w.reorth, B);
     d.take(w.tol_abs, B);
     d.take(w.cond, B);
     d.take(w.flags, B);

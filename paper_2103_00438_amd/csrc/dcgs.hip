@@ -191,12 +191,14 @@ __global__ void __launch_bounds__(64) dcgs_coeff_kernel(const int* __restrict__ 
             // previous rotations, then the one that zeroes hn below col[c]: [cs sn; -conj(sn) cs]
             double* cs = a.cs + (int64_t)s * mdim;
             double2* sn = a.sn + (int64_t)s * mdim;
+            // the running entry stays in registers; the unrotated entries are loaded ahead of it
+            double2 cur = col[0];
             for (int i = 0; i < c; ++i) {
-                const double2 x = col[i], y = col[i + 1];
-                col[i] = c_add(c_scale(cs[i], x), c_mul(sn[i], y));
-                col[i + 1] = c_sub(c_scale(cs[i], y), c_conj_mul(sn[i], x));
+                const double2 y = col[i + 1];
+                col[i] = c_add(c_scale(cs[i], cur), c_mul(sn[i], y));
+                cur = c_sub(c_scale(cs[i], y), c_conj_mul(sn[i], cur));
             }
-            const double2 x = col[c];
+            const double2 x = cur;
             const double ax = c_abs(x);
             double cr;
             double2 sv;

@@ -170,18 +170,21 @@ __global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, i
     if (!run[s]) return;   // stopped earlier in this chunk of steps
     const double* hc = H + ((int64_t)sdir[s] * m + j) * (m + 1);
     double2* col = R + (int64_t)s * rstride + (int64_t)j * (j + 1) / 2;
-    for (int i = 0; i <= j; ++i) col[i] = make_double2(hc[i], 0.0);
-    col[j] = cadd(col[j], z[s]);
+    const double2 zs = z[s];
     const double hn = hc[j + 1];
     double* c_s = cs + (int64_t)s * m;
     double2* s_s = sn + (int64_t)s * m;
+    // column j of Hbar + z Ibar through the previous rotations; the running entry stays in registers
+    double2 cur = make_double2(hc[0] + (j == 0 ? zs.x : 0.0), j == 0 ? zs.y : 0.0);
     for (int i = 0; i < j; ++i) {
-        const double2 x = col[i], y = col[i + 1];
-        col[i] = cadd(cscale(c_s[i], x), cmul(s_s[i], y));
-        col[i + 1] = cadd(cscale(-1.0, cmul(cconj(s_s[i]), x)), cscale(c_s[i], y));
+        const double2 y = make_double2(hc[i + 1] + (i + 1 == j ? zs.x : 0.0), i + 1 == j ? zs.y : 0.0);
+        const double ci = c_s[i];
+        const double2 si = s_s[i];
+        col[i] = cadd(cscale(ci, cur), cmul(si, y));
+        cur = cadd(cscale(-1.0, cmul(cconj(si), cur)), cscale(ci, y));
     }
     // rotation [c s; -conj(s) c] with c real zeroing hn below col[j]
-    const double2 x = col[j];
+    const double2 x = cur;
     const double ax = cabs(x);
     double c;
     double2 sv;

@@ -1166,8 +1166,8 @@ uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_d
     if (o.precision == WFQ_PREC_FP32 || o.precision == WFQ_PREC_BF16) b += mpad * np * 8;
     if (o.precision == WFQ_PREC_BF16) b += mpad * np * 6;
     const uint64_t nwc = wave_chunks(S.n);
-    b += (uint64_t)B * mdim * nwc * 16;         // dot partials
-    b += (uint64_t)B * mdim * mdim * 16;        // R
+    b += (uint64_t)B * 2 * mdim * nwc * 16;     // fused dot partials (two entries per basis vector)
+    b += (uint64_t)B * 2 * mdim * mdim * 16;    // R and the Hessenberg matrix before rotations
     b += (uint64_t)B * (mdim * 64 + 2 * np * 8 / 1);  // small arrays + output staging
     b += std::min<uint64_t>(kSplitWsCap, 7 * mpad * np * 8);   // split-k partial tiles
     if (o.algorithm == WFQ_MSGMRES) b += ms_bytes(S, o, B, n_dir);

@@ -478,6 +478,8 @@ const std::vector<Variant>& variants_all() {
             r.push_back({"m160n256w8", 160, 256, 1 << 30, launch_mfma<P, 5, 4, 2, 4, 128, 1>});
             r.push_back({"m192n256w8", 192, 256, 1 << 30, launch_mfma<P, 6, 4, 2, 4, 128, 1>});
             r.push_back({"m192n128w8", 192, 128, 1 << 30, launch_mfma<P, 3, 4, 4, 2, 128, 1>});
+            r.push_back({"m224n256w8", 224, 256, 1 << 30, launch_mfma<P, 7, 4, 2, 4, 128, 1>});
+            r.push_back({"m224n128w8", 224, 128, 1 << 30, launch_mfma<P, 7, 2, 2, 4, 128, 1>});
         }
         return r;
     }();
@@ -504,8 +506,9 @@ int default_variant(int prec, int ncol) {
                                {96, "m128n256w8i"}, {128, "m128n256w8"}, {192, "m64n128i"}, {256, "m128n256w8i"},
                                {320, "m64n128"}, {1 << 30, "m128n256w8i"}};
     static const Pick f32[] = {{2, "skinny2"}, {4, "skinny4r8"}, {32, "m32n128"}, {64, "m64n128k256i"},
-                               {96, "m96n256w8"}, {128, "m128n64i"}, {192, "m96n256w8"}, {256, "m128n64i"},
-                               {320, "m160n256w8"}, {1 << 30, "m96n256w8"}};
+                               {96, "m96n256w8"}, {128, "m128n64i"}, {160, "m160n256w8"}, {192, "m96n256w8"},
+                               {224, "m224n128w8"}, {256, "m128n64i"}, {288, "m96n256w8"}, {320, "m160n256w8"},
+                               {1 << 30, "m96n256w8"}};
     // BF16 T is 2 bytes per element: even one column streams it faster through the matrix cores
     static const Pick b16[] = {{64, "m64n128i"}, {128, "m128n128"}, {192, "m192n256w8"}, {256, "m256n128w8i"},
                                {320, "m160n256w8"}, {1 << 30, "m192n256w8"}};

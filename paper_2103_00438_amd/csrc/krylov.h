@@ -152,12 +152,12 @@ void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const do
              const double* norm, int64_t n, int64_t npad, double* H, double* inv_h, hipStream_t st);
 // Givens step j of each listed system on Hbar + z Ibar of its direction (flags: bit0 converged, bit1 breakdown, bit2 NaN);
 // systems with run[s] == 0 are skipped, ksteps[s] = j + 1 is recorded and run[s] cleared when a flag
-// is raised.
+// is raised. cs, sn, g and the packed R are system-minor: entry e of system s at e * S + s.
 void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const double2* z, const double* H, double* cs,
-               double2* sn, double2* g, double2* R, int64_t rstride, double* est, const double* tol_abs, int* flags,
+               double2* sn, double2* g, double2* R, int64_t S, double* est, const double* tol_abs, int* flags,
                int* run, int* ksteps, hipStream_t st);
-// y = R^-1 g over k[s] columns; cond = max|R_ii| / min|R_ii|
-void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t rstride, const double2* g,
+// y = R^-1 g over k[s] columns (system-minor R and g as above); cond = max|R_ii| / min|R_ii|
+void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t S, const double2* g,
               double2* y, double* cond, hipStream_t st);
 // x(s) = V(d, 0..k[s]-1) y[s] for groups of kMsGroup systems (grp_sys entries -1 = none)
 void ms_xupdate(const double* V, int64_t n, int64_t npad, int mdim1, const int* grp_sys, const int* grp_dir, int ngrp,

@@ -12,8 +12,10 @@
 // frequencies) and one small complex Givens recurrence per (frequency, direction) system.
 //
 // Layouts: basis of direction d, slot j at V + (d * mdim1 + j) * npad (FP64, padding rows zero);
-// Hessenberg column j of direction d at H + (d * m + j) * (m + 1) (entries 0..j+1); per-system
-// rotations cs/sn [S][m], g [S][m+1], R packed by columns (column j at offset j (j + 1) / 2).
+// Hessenberg column j of direction d at H + (d * m + j) * (m + 1) (entries 0..j+1). Per-system
+// arrays are system-minor (entry e of system s at e * S + s, S = systems of the batch), so that the
+// one-thread-per-system Givens step reads and writes consecutive addresses across a wave: rotations
+// cs/sn (m entries), g (m + 1), R packed by columns (column j from entry j (j + 1) / 2).
 #include "device_util.h"
 #include "krylov.h"
 
@@ -162,25 +164,23 @@ __global__ void ms_hcol_kernel(const int* __restrict__ dirs, int j, int m, const
 __global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, int m, const int* __restrict__ sdir,
                                  const double2* __restrict__ z, const double* __restrict__ H, double* __restrict__ cs,
                                  double2* __restrict__ sn, double2* __restrict__ g, double2* __restrict__ R,
-                                 int64_t rstride, double* __restrict__ est, const double* __restrict__ tol_abs,
+                                 int64_t S, double* __restrict__ est, const double* __restrict__ tol_abs,
                                  int* __restrict__ flags, int* __restrict__ run, int* __restrict__ ksteps) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsys) return;
     const int s = sys[k];
     if (!run[s]) return;   // stopped earlier in this chunk of steps
     const double* hc = H + ((int64_t)sdir[s] * m + j) * (m + 1);
-    double2* col = R + (int64_t)s * rstride + (int64_t)j * (j + 1) / 2;
+    double2* col = R + ((int64_t)j * (j + 1) / 2) * S + s;   // entry i of the column at col[i * S]
     const double2 zs = z[s];
     const double hn = hc[j + 1];
-    double* c_s = cs + (int64_t)s * m;
-    double2* s_s = sn + (int64_t)s * m;
     // column j of Hbar + z Ibar through the previous rotations; the running entry stays in registers
     double2 cur = make_double2(hc[0] + (j == 0 ? zs.x : 0.0), j == 0 ? zs.y : 0.0);
     for (int i = 0; i < j; ++i) {
         const double2 y = make_double2(hc[i + 1] + (i + 1 == j ? zs.x : 0.0), i + 1 == j ? zs.y : 0.0);
-        const double ci = c_s[i];
-        const double2 si = s_s[i];
-        col[i] = cadd(cscale(ci, cur), cmul(si, y));
+        const double ci = cs[(int64_t)i * S + s];
+        const double2 si = sn[(int64_t)i * S + s];
+        col[(int64_t)i * S] = cadd(cscale(ci, cur), cmul(si, y));
         cur = cadd(cscale(-1.0, cmul(cconj(si), cur)), cscale(ci, y));
     }
     // rotation [c s; -conj(s) c] with c real zeroing hn below col[j]
@@ -199,18 +199,19 @@ __global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, i
         c = ax / nu;
         sv = make_double2(x.x / ax * hn / nu, x.y / ax * hn / nu);
     }
-    c_s[j] = c;
-    s_s[j] = sv;
-    col[j] = cadd(cscale(c, x), cscale(hn, sv));
-    double2* gs = g + (int64_t)s * (m + 1);
-    const double2 gj = gs[j];
-    gs[j + 1] = cscale(-1.0, cmul(cconj(sv), gj));
-    gs[j] = cscale(c, gj);
-    const double e = cabs(gs[j + 1]);
+    cs[(int64_t)j * S + s] = c;
+    sn[(int64_t)j * S + s] = sv;
+    const double2 cj = cadd(cscale(c, x), cscale(hn, sv));
+    col[(int64_t)j * S] = cj;
+    const double2 gj = g[(int64_t)j * S + s];
+    const double2 gn = cscale(-1.0, cmul(cconj(sv), gj));
+    g[(int64_t)(j + 1) * S + s] = gn;
+    g[(int64_t)j * S + s] = cscale(c, gj);
+    const double e = cabs(gn);
     est[s] = e;
     int f = 0;
     if (e <= tol_abs[s]) f |= 1;
-    if (hn <= 1e-14 * cabs(col[j])) f |= 2;   // the Krylov space is invariant: the iterate is exact
+    if (hn <= 1e-14 * cabs(cj)) f |= 2;   // the Krylov space is invariant: the iterate is exact
     if (!(e == e) || !(hn == hn)) f |= 4;
     flags[s] = f;
     ksteps[s] = j + 1;
@@ -218,31 +219,30 @@ __global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, i
 }
 
 // y = R^-1 g over the first k[s] columns, one work-group per system: column-oriented back
-// substitution on the packed R (column i is contiguous), y kept in LDS; cond[s] = max|R_ii| / min|R_ii|.
+// substitution on the packed R (entry i of column c at ((c (c + 1) / 2) + i) S + s), y kept in LDS;
+// cond[s] = max|R_ii| / min|R_ii|.
 __global__ void __launch_bounds__(256) ms_solve_kernel(const int* __restrict__ sys, const int* __restrict__ ksteps,
-                                                       int m, const double2* __restrict__ R, int64_t rstride,
+                                                       int m, const double2* __restrict__ R, int64_t S,
                                                        const double2* __restrict__ g, double2* __restrict__ y,
                                                        double* __restrict__ cond) {
     extern __shared__ double2 ys[];
     const int s = sys[blockIdx.x];
     const int K = ksteps[s];
-    const double2* Rs = R + (int64_t)s * rstride;
-    const double2* gs = g + (int64_t)s * (m + 1);
-    for (int i = threadIdx.x; i < K; i += blockDim.x) ys[i] = gs[i];
+    auto rat = [&](int c, int i) { return R[((int64_t)c * (c + 1) / 2 + i) * S + s]; };
+    for (int i = threadIdx.x; i < K; i += blockDim.x) ys[i] = g[(int64_t)i * S + s];
     __syncthreads();
     for (int i = K - 1; i >= 0; --i) {
-        const double2* col = Rs + (int64_t)i * (i + 1) / 2;
-        const double2 yi = cdiv(ys[i], col[i]);   // every thread computes it; ys[i] is final here
+        const double2 yi = cdiv(ys[i], rat(i, i));   // every thread computes it; ys[i] is final here
         __syncthreads();
         if (threadIdx.x == 0) ys[i] = yi;
-        for (int r = threadIdx.x; r < i; r += blockDim.x) ys[r] = csub(ys[r], cmul(col[r], yi));
+        for (int r = threadIdx.x; r < i; r += blockDim.x) ys[r] = csub(ys[r], cmul(rat(i, r), yi));
         __syncthreads();
     }
     for (int i = threadIdx.x; i < K; i += blockDim.x) y[(int64_t)s * m + i] = ys[i];
     if (threadIdx.x == 0) {
         double dmax = 0.0, dmin = 1e300;
         for (int i = 0; i < K; ++i) {
-            const double a = cabs(Rs[(int64_t)i * (i + 1) / 2 + i]);
+            const double a = cabs(rat(i, i));
             dmax = fmax(dmax, a);
             dmin = fmin(dmin, a);
         }
@@ -359,19 +359,19 @@ void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const do
 }
 
 void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const double2* z, const double* H, double* cs,
-               double2* sn, double2* g, double2* R, int64_t rstride, double* est, const double* tol_abs, int* flags,
+               double2* sn, double2* g, double2* R, int64_t S, double* est, const double* tol_abs, int* flags,
                int* run, int* ksteps, hipStream_t st) {
     if (nsys <= 0) return;
     hipLaunchKernelGGL(ms_givens_kernel, dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st, sys, nsys, j, m, sdir, z,
-                       H, cs, sn, g, R, rstride, est, tol_abs, flags, run, ksteps);
+                       H, cs, sn, g, R, S, est, tol_abs, flags, run, ksteps);
     WFQ_CHECK_LAUNCH();
 }
 
-void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t rstride, const double2* g,
+void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t S, const double2* g,
               double2* y, double* cond, hipStream_t st) {
     if (nsys <= 0) return;
     hipLaunchKernelGGL(ms_solve_kernel, dim3((unsigned)nsys), dim3(256), (size_t)m * sizeof(double2), st, sys, ksteps,
-                       m, R, rstride, g, y, cond);
+                       m, R, S, g, y, cond);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -763,7 +763,6 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     const int mdim1 = m + 1, pslots = m + 2;
     const int64_t n = S.n, np = S.npad, nwc = wave_chunks(S.n);
     const int prec = o.precision;
-    const int64_t rstride = (int64_t)m * (m + 1) / 2;
     const double dn = (double)n;
     MsWork& q = w.ms;
     if (w.shape.ms_m != m) throw Error{WFQ_EDEVICE, "multi-shift work space of the wrong dimension"};
@@ -792,11 +791,12 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         invb[d] = beta[d] > 0.0 ? 1.0 / beta[d] : 0.0;
     }
     {
+        // g = beta e_1 (system-minor: entry 0 of every system first)
         std::vector<double2> gh((size_t)B * (m + 1), make_double2(0.0, 0.0)), zh(B);
         std::vector<double> th(B);
         std::vector<int> dh(B);
         for (int s = 0; s < B; ++s) {
-            gh[(size_t)s * (m + 1)] = make_double2(beta[ss[s].dir], 0.0);
+            gh[(size_t)s] = make_double2(beta[ss[s].dir], 0.0);
             th[s] = tol * beta[ss[s].dir];
             dh[s] = ss[s].dir;
             zh[s] = ss[s].z;
@@ -866,7 +866,7 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
             tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
             // every unconverged frequency of those directions: one Givens step on Hbar + z Ibar
             tm.begin(st);
-            ms_givens(sys, ns, j, m, sdir, z, H, cs, sn, g, R, rstride, est, tol_abs, flags, run, ksteps, st);
+            ms_givens(sys, ns, j, m, sdir, z, H, cs, sn, g, R, B, est, tol_abs, flags, run, ksteps, st);
             tm.end(st, KC_GIVENS, 0, 0);
         };
         run_chunk(gc, S, GraphKey{1, j0, c, ns, na, 0, 0}, st, [&] {
@@ -913,7 +913,7 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     if (!withk.empty()) {
         std::memcpy(h_sys, withk.data(), withk.size() * sizeof(int));
         WFQ_HIP(hipMemcpyAsync(sys, h_sys, withk.size() * sizeof(int), hipMemcpyHostToDevice, st));
-        ms_solve(sys, (int)withk.size(), ksteps, m, R, rstride, g, y, cond, st);
+        ms_solve(sys, (int)withk.size(), ksteps, m, R, B, g, y, cond, st);
     }
     ms_xupdate(V, n, np, mdim1, grp_sys, grp_dir, ngrp, ksteps, y, m, w.Xb, st);
     tm.end(st, KC_XUPDATE, 0, 0);

@@ -322,9 +322,10 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     WFQ_HIP(hipMemcpyAsync(s.width, width_h.data(), width_h.size() * 8, hipMemcpyHostToDevice, st));
     // bounding spheres of consecutive 64-atom blocks (internal order; padding atoms excluded, an
     // empty block gets radius 0), used by the matrix-free products to find far-apart tile pairs
+    // (the host copy lives until the stream is synchronised at the end of the build)
+    std::vector<double> sph((size_t)(s.npad / 64) * 4, 0.0);
     {
         const int64_t nb = s.npad / 64;
-        std::vector<double> sph((size_t)nb * 4, 0.0);
         for (int64_t b = 0; b < nb; ++b) {
             const int64_t k0 = b * 64, k1 = std::min<int64_t>(n, k0 + 64);
             if (k1 <= k0) continue;

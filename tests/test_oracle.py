@@ -456,3 +456,74 @@ def test_gmres_from_exact_start_takes_no_step_and_warm_sweep_matches_lu():
         assert np.linalg.norm(Q[k] - ref) <= 1e-7 * np.linalg.norm(ref)
     # the interpolated starts save steps on every warm system
     assert all(iters[k] < cold[k] for k in range(len(om)) if not first[k]), (iters, cold)
+
+
+# ----------------------------------------------------------------- preconditioning study (not adopted)
+
+def _bisect_blocks(xyz, leaf):
+    """Index sets of at most `leaf` atoms from recursive coordinate bisection (longest extent)."""
+    out = []
+
+    def rec(ids):
+        if len(ids) <= leaf:
+            out.append(ids)
+            return
+        p = xyz[ids]
+        o = ids[np.argsort(p[:, np.argmax(p.max(0) - p.min(0))], kind="stable")]
+        h = max(leaf, (len(o) // 2 // leaf) * leaf)
+        rec(o[:h])
+        rec(o[h:])
+
+    rec(np.arange(len(xyz)))
+    return out
+
+
+def _bj_steps(P, om, d, blocks, kind):
+    """GMRES(50) steps to 1e-8 without (kind None) or with a block-Jacobi right preconditioner:
+    'exact' = the diagonal blocks of L T + z I, 'separable' = L_bb T_bb + z I."""
+    z = P.z(om)
+    A = O.dense_operator(P.L, P.T, z)
+    b = P.rhs(d).astype(complex)
+    if kind is None:
+        return O.gmres(lambda v: A @ v, b, 50, 1e-8, 5000)[1]["iters"], None
+    L = P.L.toarray() if scipy.sparse.issparse(P.L) else np.asarray(P.L)
+    inv = []
+    for ids in blocks:
+        Mb = A[np.ix_(ids, ids)] if kind == "exact" else \
+            L[np.ix_(ids, ids)] @ P.T[np.ix_(ids, ids)] + z * np.eye(len(ids))
+        inv.append((ids, np.linalg.inv(Mb)))
+
+    def minv(v):
+        out = np.empty_like(v)
+        for ids, Mi in inv:
+            out[ids] = Mi @ v[ids]
+        return out
+
+    u, info = O.gmres(lambda v: A @ minv(v), b, 50, 1e-8, 5000)
+    return info["iters"], minv(u)
+
+
+def test_block_jacobi_study():
+    # right preconditioning with the exact diagonal blocks of L T + z I (256-atom blocks) cuts the
+    # GMRES(50) steps on the disk above its lowest resonances, and the preconditioned solution is the
+    # LU one; blocks built from L_bb T_bb (whose only frequency dependence would be the diagonal
+    # shift) lose the coupling across block boundaries and need more steps than no preconditioner on
+    # a tube. Exact blocks differ per system, and at the benchmark sizes reading them costs more per
+    # step than the steps they save, which is why the solver does not use them.
+    wl = wi.workload("disk600")
+    P = O.Problem(wl.xyz, wl.params)
+    blocks = _bisect_blocks(O.angstrom_to_bohr(np.asarray(wl.xyz)), 256)
+    d = np.array([1.0, 0.0, 0.0])
+    for om in (1.0, 1.5):
+        plain, _ = _bj_steps(P, om, d, blocks, None)
+        steps, q = _bj_steps(P, om, d, blocks, "exact")
+        assert steps < 0.6 * plain, (om, steps, plain)
+        ref = P.solve_lu(om, d)
+        assert np.linalg.norm(q - ref) <= 1e-6 * np.linalg.norm(ref)
+    xyz = geo.jitter(geo.nanotube(10, 10, 50), 0.01, 3)
+    Pt = O.Problem(xyz, G)
+    bt = _bisect_blocks(O.angstrom_to_bohr(np.asarray(xyz)), 256)
+    dz = np.array([0.0, 0.0, 1.0])
+    plain, _ = _bj_steps(Pt, 0.3, dz, bt, None)
+    sep, _ = _bj_steps(Pt, 0.3, dz, bt, "separable")
+    assert sep > plain, (sep, plain)

@@ -541,6 +541,24 @@ class Problem:
     def solve_gmres(self, omega_eV, direction, restart, tol, maxiter=100000, E0=1.0, x0=None):
         return gmres(self.apply(self.z(omega_eV)), self.rhs(direction, E0), restart, tol, maxiter, x0=x0)
 
+    def solve_block_jacobi(self, omega_eV, direction, blocks, restart, tol, maxiter=100000, E0=1.0):
+        """GMRES on (L T + z I) M^-1 u = b, q = M^-1 u, with M the block-diagonal part of L T + z I
+        over the index sets `blocks` (a partition of the atoms): right preconditioning, so the
+        residual GMRES minimises is the true one (a project extension, next to the paper's remark that
+        the diagonal of the matrix did not help). Returns (q, info)."""
+        z = self.z(omega_eV)
+        A = dense_operator(self.L, self.T, z)
+        inv = [(np.asarray(ids), np.linalg.inv(A[np.ix_(ids, ids)])) for ids in blocks]
+
+        def minv(v):
+            out = np.empty_like(v)
+            for ids, Mi in inv:
+                out[ids] = Mi @ v[ids]
+            return out
+
+        u, info = gmres(lambda v: A @ minv(v), self.rhs(direction, E0), restart, tol, maxiter)
+        return minv(u), info
+
     def solve_warm_sweep(self, omegas_eV, direction, restart, tol, maxiter=100000, E0=1.0):
         """GMRES over a frequency sweep with warm starts (a project extension; the paper starts every
         solve from q0 = 0). With the frequencies sorted, every second one and the highest are solved

@@ -527,3 +527,21 @@ def test_block_jacobi_study():
     plain, _ = _bj_steps(Pt, 0.3, dz, bt, None)
     sep, _ = _bj_steps(Pt, 0.3, dz, bt, "separable")
     assert sep > plain, (sep, plain)
+
+
+def test_block_jacobi_gmres_pins():
+    # one block holding every atom: M = A, so A M^-1 = I and GMRES stops after one step with the LU
+    # solution; a partition into 64-atom blocks gives the LU solution in fewer steps than no
+    # preconditioner above the disk's lowest resonances
+    P = small_problem()
+    d = np.array([1.0, 0.0, 0.0])
+    q1, i1 = P.solve_block_jacobi(0.8, d, [np.arange(P.n)], restart=20, tol=1e-12)
+    ref = P.solve_lu(0.8, d)
+    assert i1["iters"] == 1 and np.linalg.norm(q1 - ref) <= 1e-10 * np.linalg.norm(ref)
+    wl = wi.workload("disk600")
+    Pd = O.Problem(wl.xyz, wl.params)
+    blocks = [np.arange(k, min(k + 64, Pd.n)) for k in range(0, Pd.n, 64)]   # any partition is valid
+    q, info = Pd.solve_block_jacobi(1.0, d, blocks, restart=50, tol=1e-10)
+    ref = Pd.solve_lu(1.0, d)
+    assert np.linalg.norm(q - ref) <= 1e-7 * np.linalg.norm(ref)
+    assert info["relres"] <= 1e-10

@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the leg with warm starts across neighbouring frequencies")
     ap.add_argument("--no-multishift", action="store_true", help="skip the multi-shift FP64 run of the same systems")
+    ap.add_argument("--no-block-jacobi", action="store_true",
+                    help="skip the leg with block-Jacobi right preconditioning (64-atom diagonal blocks)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB on the device 4 times (calibrates the HBM byte counters) and report GB/s")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in block-product shapes")
@@ -334,6 +336,30 @@ def bench_batched(args, wl, wfq, torch):
             ws_line["max_rel_err_q_vs_fp64_batched"] = float(
                 (np.linalg.norm(qws - qref, axis=1) / np.linalg.norm(qref, axis=1)).max())
         extra["warm_start"] = ws_line
+    if not otf and algo == "gmres" and not args.no_block_jacobi and wl.n <= 50000:
+        # block-Jacobi right preconditioning (the same options as the timed steps): one warm-up and
+        # one timed run
+        bopts = dict(opts, block_jacobi=True)
+        wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=True, **bopts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        bj = wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=True, **bopts)
+        torch.cuda.synchronize()
+        t_bj = time.perf_counter() - t0
+        wfq.wfq_kernel_stats(h, reset=True)
+        wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=False, timing=True, **bopts)
+        bj_stats = wfq.wfq_kernel_stats(h)
+        bj_line = dict(value=S / t_bj, unit="solves/s", ms_per_step=t_bj * 1e3, dtype=prec,
+                       iters_mean=float(np.mean([r["iters"] for r in bj["info"]])),
+                       iters_max=int(max(r["iters"] for r in bj["info"])),
+                       relres_max=max(r["relres"] for r in bj["info"]),
+                       statuses=sorted(set(r["status"] for r in bj["info"])),
+                       kernels=kernel_table(bj_stats))
+        if "fp64_reference_systems" in extra and extra["fp64_reference_systems"] == S:
+            qbj = bj["q"].reshape(S, wl.n)
+            bj_line["max_rel_err_q_vs_fp64_batched"] = float(
+                (np.linalg.norm(qbj - qref, axis=1) / np.linalg.norm(qref, axis=1)).max())
+        extra["block_jacobi"] = bj_line
 
     if not args.no_cpu_baseline:
         if otf or wl.n > 50000:
@@ -372,6 +398,19 @@ def bench_latency(args, wl, wfq, torch):
         out = wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, **opts)
         lat.append((time.perf_counter() - t1) * 1e3)
     elapsed = time.perf_counter() - t0
+    bj = None
+    if not args.no_block_jacobi:
+        # the same solve with block-Jacobi right preconditioning (64-atom diagonal blocks)
+        bopts = dict(opts, block_jacobi=True)
+        for _ in range(max(1, args.warmup)):
+            wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, **bopts)
+        blat = []
+        for _ in range(reps):
+            t1 = time.perf_counter()
+            bo = wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, **bopts)
+            blat.append((time.perf_counter() - t1) * 1e3)
+        bj = dict(p50_ms=float(np.percentile(blat, 50)), p99_ms=float(np.percentile(blat, 99)),
+                  iters=bo["info"][0]["iters"], relres=bo["info"][0]["relres"])
     from oracle import wfq_oracle as O
     P = O.Problem(wl.xyz, wl.params)
     t1 = time.perf_counter()
@@ -386,7 +425,7 @@ def bench_latency(args, wl, wfq, torch):
                 config=dict(workload=wl.name, n_atoms=wl.n, n_systems=1, precision="fp64", restart=wl.restart,
                             tol=wl.tol, description=wl.description),
                 p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                iters=out["info"][0]["iters"], relres=out["info"][0]["relres"],
+                iters=out["info"][0]["iters"], relres=out["info"][0]["relres"], block_jacobi=bj,
                 cpu_baseline=dict(value=1.0 / t_gm, unit="solves/s", cores=cores_used(), kind="oracle",
                                   sample=f"the same system: FP64 GMRES({wl.restart}) {t_gm * 1e3:.1f} ms "
                                          f"({info['iters']} iterations); dense LU {t_lu * 1e3:.1f} ms"))

@@ -127,6 +127,15 @@ typedef struct {
                             neighbours (q depends on the frequency only through z) and runs batched
                             GMRES with FP64 refinement from there. Needs n_omega >= 3 (else ignored);
                             WFQ_EINVAL with another algorithm. */
+    int32_t block_jacobi; /* GMRES only, nonzero: right preconditioning with the exact 64 x 64 diagonal
+                            blocks M_s of L T + z_s I over runs of 64 atoms in the library's internal
+                            (spatially sorted) order, so GMRES runs on (L T + z_s I) M_s^-1 and minimises
+                            the true residual (a project extension; the paper runs its solvers
+                            unpreconditioned). Each block is inverted once per solve in FP64 (Gauss-Jordan,
+                            partial pivoting); every system then holds N x 64 complex doubles (1 KiB per
+                            atom) and each inner step reads them once. The block products keep the chosen
+                            precision. Needs the stored FP64 T (WFQ_EINVAL otherwise, and with another
+                            algorithm or with warm_start). */
 } wfq_solve_opts;
 
 typedef struct {

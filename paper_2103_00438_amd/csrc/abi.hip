@@ -33,7 +33,7 @@ namespace {
 
 const char* kClassNames[KC_COUNT] = {"tx_gemm_f64", "tx_gemm_f32", "tx_gemm_bf16", "tx_skinny", "tx_otf_f32", "tx_otf_f64",
                                      "spmm_shift",  "cgs_dot",     "cgs_update",   "givens",    "pack",
-                                     "x_update",    "fp64_residual", "qmr",        "other"};
+                                     "x_update",    "fp64_residual", "qmr",        "block_jacobi", "other"};
 
 template <typename F>
 int guarded(F&& f) {
@@ -80,6 +80,9 @@ void check_opts(const wfq_solve_opts* o) {
     if (!std::isfinite(o->E0) || o->E0 < 0.0) fail(WFQ_EINVAL, "E0 must be finite and >= 0");
     if (o->max_batch < 0) fail(WFQ_EINVAL, "max_batch must be >= 0");
     if (o->warm_start && o->algorithm != WFQ_GMRES) fail(WFQ_EINVAL, "warm starts are a GMRES option");
+    if (o->block_jacobi && o->algorithm != WFQ_GMRES)
+        fail(WFQ_EINVAL, "block-Jacobi preconditioning is a GMRES option");
+    if (o->block_jacobi && o->warm_start) fail(WFQ_EINVAL, "block_jacobi and warm_start cannot be combined");
 }
 
 void check_solve_args(const wfq_handle* h, const double* omegas, int n_omega, const double* dirs, int n_dir,

@@ -96,7 +96,7 @@ struct KernelStat {
 
 enum KernelClass {
     KC_GEMM_F64 = 0, KC_GEMM_F32, KC_GEMM_BF16, KC_SKINNY, KC_OTF, KC_OTF_F64,
-    KC_SPMM, KC_DOT, KC_UPDATE, KC_GIVENS, KC_PACK, KC_XUPDATE, KC_RESID, KC_QMR, KC_OTHER,
+    KC_SPMM, KC_DOT, KC_UPDATE, KC_GIVENS, KC_PACK, KC_XUPDATE, KC_RESID, KC_QMR, KC_PRECOND, KC_OTHER,
     KC_COUNT
 };
 

@@ -27,9 +27,11 @@ void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, con
                   void* X, int64_t ld, hipStream_t st, const int* run = nullptr);
 
 // V(s, jdst) = L Y[2k, 2k+1] + z_s V(s, jsrc) for the nsys systems (Y in FP32 or FP64); with
-// y_by_sys the rows of Y are addressed by system id (Y[2s, 2s+1]) instead of list position k.
+// y_by_sys the rows of Y are addressed by system id (Y[2s, 2s+1]) instead of list position k; with
+// shift_src the shifted term is taken from that basis instead (shift_src(s, jsrc)).
 void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
-                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st, bool y_by_sys = false);
+                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st, bool y_by_sys = false,
+                const Basis* shift_src = nullptr);
 
 // h[s][i] = sum_wc partial[s][i][wc] for i <= j (skipping systems with active[s] == 0)
 void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
@@ -162,5 +164,18 @@ void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2*
 // x(s) = V(d, 0..k[s]-1) y[s] for groups of kMsGroup systems (grp_sys entries -1 = none)
 void ms_xupdate(const double* V, int64_t n, int64_t npad, int mdim1, const int* grp_sys, const int* grp_dir, int ngrp,
                 const int* ksteps, const double2* y, int m, const Basis& X, hipStream_t st);
+
+// ---- block-Jacobi right preconditioning (64-atom diagonal blocks of L T + z I)
+//
+// bj_setup: C_b = (L T)_bb into C ([npad/64][64][64], FP64; needs the stored FP64 T), then
+// P_sb = (C_b + z_s I)^-1 for the nsys listed systems into P ([B][npad/64][64 x 64] complex, column-major).
+void bj_setup(const Structure& S, const int* sys, int nsys, const double2* z, double* C, double2* P,
+              hipStream_t st);
+// v = V(s, j) * scale[s] (written back), u = P_s v into U(s) and into X[2k + plane] in precision prec
+// (zero columns where run[s] == 0; scale and run may be NULL), for the nsys listed systems.
+void bj_pack(int prec, const Basis& V, int j, const int* sys, int nsys, const double* scale, const double2* P,
+             int64_t npad, const Basis& U, void* X, int64_t ld, const int* run, hipStream_t st);
+// X(s) += P_s U(s) for the nsys listed systems
+void bj_add(const int* sys, int nsys, const double2* P, int64_t npad, const Basis& U, const Basis& X, hipStream_t st);
 
 }  // namespace wfq

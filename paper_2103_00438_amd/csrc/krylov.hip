@@ -57,7 +57,8 @@ template <typename YE, int NS>
 __global__ void __launch_bounds__(256) spmm_kernel(int64_t n, int64_t npad, int w, const int32_t* __restrict__ ecol,
                                                    const double* __restrict__ eval, const YE* __restrict__ Y,
                                                    int64_t ld, const int* __restrict__ sys, int nsys,
-                                                   const double2* __restrict__ z, Basis V, int jsrc, int jdst) {
+                                                   const double2* __restrict__ z, Basis Vs, Basis V, int jsrc,
+                                                   int jdst) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     const int k0 = blockIdx.y * NS;
@@ -79,8 +80,8 @@ __global__ void __launch_bounds__(256) spmm_kernel(int64_t n, int64_t npad, int 
     for (int t = 0; t < NS; ++t)
         if (t < kn) {
             const int s = sys[k0 + t];
-            const double* sr = vre(V, s, jsrc);
-            const double vr = sr[i], vi = sr[i + V.npad];
+            const double* sr = vre(Vs, s, jsrc);
+            const double vr = sr[i], vi = sr[i + Vs.npad];
             const double2 zz = z[s];
             double* dr = vre(V, s, jdst);
             dr[i] = ar[t] + zz.x * vr - zz.y * vi;
@@ -99,7 +100,8 @@ __global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad,
                                                         const int32_t* __restrict__ ecol,
                                                         const double* __restrict__ eval, const YE* __restrict__ Y,
                                                         int64_t ld, const int* __restrict__ sys, int nsys, int per_group,
-                                                        const double2* __restrict__ z, Basis V, int jsrc, int jdst,
+                                                        const double2* __restrict__ z, Basis Vs, Basis V, int jsrc,
+                                                        int jdst,
                                                         int y_by_sys) {
     extern __shared__ char smem[];
     double* lval = reinterpret_cast<double*>(smem);
@@ -133,8 +135,8 @@ __global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad,
             ai += v * widen(yi[c]);
         }
         const int s = sys[k];
-        const double* sr = vre(V, s, jsrc);
-        const double vr = sr[i], vi = sr[i + V.npad];
+        const double* sr = vre(Vs, s, jsrc);
+        const double vr = sr[i], vi = sr[i + Vs.npad];
         const double2 zz = z[s];
         double* dr = vre(V, s, jdst);
         dr[i] = ar + zz.x * vr - zz.y * vi;
@@ -144,7 +146,7 @@ __global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad,
 
 template <typename YE, int R>
 void launch_spmm_rows(const Structure& S, const YE* Y, int64_t ld, const int* sys, int nsys, const double2* z,
-                      const Basis& V, int jsrc, int jdst, bool y_by_sys, hipStream_t st) {
+                      const Basis& Vs, const Basis& V, int jsrc, int jdst, bool y_by_sys, hipStream_t st) {
     constexpr int G = 64 / R;
     const int64_t nb = S.npad / R;
     const int64_t nb8 = (nb + 7) / 8 * 8;
@@ -154,7 +156,8 @@ void launch_spmm_rows(const Structure& S, const YE* Y, int64_t ld, const int* sy
     const int per_group = (nsys + gy - 1) / gy;
     const size_t lds = (size_t)S.ell_w * R * 12;
     hipLaunchKernelGGL((spmm_rows_kernel<YE, R>), dim3((unsigned)nb8, (unsigned)gy), dim3(256), lds, st, S.n, S.npad,
-                       S.ell_w, S.ell_col, S.ell_val, Y, ld, sys, nsys, per_group, z, V, jsrc, jdst, (int)y_by_sys);
+                       S.ell_w, S.ell_col, S.ell_val, Y, ld, sys, nsys, per_group, z, Vs, V, jsrc, jdst,
+                       (int)y_by_sys);
 }
 
 __global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const double2* __restrict__ partial, int mdim,
@@ -381,8 +384,10 @@ void pack_columns(int prec, const Basis& V, const int* sys, int nsys, int j, con
 }
 
 void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys,
-                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st, bool y_by_sys) {
+                const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st, bool y_by_sys,
+                const Basis* shift_src) {
     if (nsys <= 0) return;
+    const Basis& Vs = shift_src ? *shift_src : V;
     // row-block kernel with the largest row block whose ELL rows fit in 40 KB of LDS (4 work-groups
     // per CU); the per-thread kernel only for neighbour lists too long even for 8 rows
     const size_t per_row = (size_t)S.ell_w * 12;
@@ -391,16 +396,16 @@ void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, co
     if (R > 0) {
         if (y_is_f64) {
             const double* Yd = static_cast<const double*>(Y);
-            if (R == 64) launch_spmm_rows<double, 64>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
-            else if (R == 32) launch_spmm_rows<double, 32>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
-            else if (R == 16) launch_spmm_rows<double, 16>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
-            else launch_spmm_rows<double, 8>(S, Yd, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
+            if (R == 64) launch_spmm_rows<double, 64>(S, Yd, ld, sys, nsys, z, Vs, V, jsrc, jdst, y_by_sys, st);
+            else if (R == 32) launch_spmm_rows<double, 32>(S, Yd, ld, sys, nsys, z, Vs, V, jsrc, jdst, y_by_sys, st);
+            else if (R == 16) launch_spmm_rows<double, 16>(S, Yd, ld, sys, nsys, z, Vs, V, jsrc, jdst, y_by_sys, st);
+            else launch_spmm_rows<double, 8>(S, Yd, ld, sys, nsys, z, Vs, V, jsrc, jdst, y_by_sys, st);
         } else {
             const float* Yf = static_cast<const float*>(Y);
-            if (R == 64) launch_spmm_rows<float, 64>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
-            else if (R == 32) launch_spmm_rows<float, 32>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
-            else if (R == 16) launch_spmm_rows<float, 16>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
-            else launch_spmm_rows<float, 8>(S, Yf, ld, sys, nsys, z, V, jsrc, jdst, y_by_sys, st);
+            if (R == 64) launch_spmm_rows<float, 64>(S, Yf, ld, sys, nsys, z, Vs, V, jsrc, jdst, y_by_sys, st);
+            else if (R == 32) launch_spmm_rows<float, 32>(S, Yf, ld, sys, nsys, z, Vs, V, jsrc, jdst, y_by_sys, st);
+            else if (R == 16) launch_spmm_rows<float, 16>(S, Yf, ld, sys, nsys, z, Vs, V, jsrc, jdst, y_by_sys, st);
+            else launch_spmm_rows<float, 8>(S, Yf, ld, sys, nsys, z, Vs, V, jsrc, jdst, y_by_sys, st);
         }
         WFQ_CHECK_LAUNCH();
         return;
@@ -410,10 +415,10 @@ void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, co
     dim3 grd((unsigned)((S.n + 255) / 256), (unsigned)((nsys + NS - 1) / NS));
     if (y_is_f64)
         hipLaunchKernelGGL((spmm_kernel<double, NS>), grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col,
-                           S.ell_val, static_cast<const double*>(Y), ld, sys, nsys, z, V, jsrc, jdst);
+                           S.ell_val, static_cast<const double*>(Y), ld, sys, nsys, z, Vs, V, jsrc, jdst);
     else
         hipLaunchKernelGGL((spmm_kernel<float, NS>), grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col,
-                           S.ell_val, static_cast<const float*>(Y), ld, sys, nsys, z, V, jsrc, jdst);
+                           S.ell_val, static_cast<const float*>(Y), ld, sys, nsys, z, Vs, V, jsrc, jdst);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -127,8 +127,10 @@ enum Slot { SLOT_G0 = 0, SLOT_G1 = 1, SLOT_G2 = 2, SLOT_STEP = 3, SLOT_ACT = 4, 
 struct WorkShape {
     int B = 0, m = 0, n_dir = 0, prec = 0, ms_m = 0;   // ms_m: shared-basis dimension (0: no multi-shift)
     bool qmr = false;
+    bool bj = false;   // block-Jacobi preconditioning
     bool operator==(const WorkShape& o) const {
-        return B == o.B && m == o.m && n_dir == o.n_dir && prec == o.prec && ms_m == o.ms_m && qmr == o.qmr;
+        return B == o.B && m == o.m && n_dir == o.n_dir && prec == o.prec && ms_m == o.ms_m && qmr == o.qmr &&
+               bj == o.bj;
     }
 };
 
@@ -162,12 +164,16 @@ struct Work {
     Buf<double> d_dirs, stage_re, stage_im;
     Buf<int> warm_sys, warm_a, warm_b;   // warm starts: target and the two solved neighbours
     Buf<double2> warm_t;                 // interpolation weight in z
+    // block-Jacobi: C_b (FP64, [npad/64][64][64]), the inverted blocks of every system
+    // ([B][npad/64][64 x 64] complex, column-major) and the preconditioned vector u of every system
+    Buf<double> bj_C, bj_U;
+    Buf<double2> bj_P;
     MsWork ms;
     // pinned host mirrors
     Buf<double> h_snorm, h_est, h_beta, h_invb;
     Buf<int> h_sys[NSLOT], h_flags, h_ksteps;
     Buf<double2> h_g, h_alpha;
-    Basis Vb, Xb;
+    Basis Vb, Xb, Ub;
 
     Work() = default;
     Work(const Work&) = delete;
@@ -247,6 +253,9 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.warm_a, B);
     d.take(w.warm_b, B);
     d.take(w.warm_t, B);
+    d.take(w.bj_C, sh.bj ? (size_t)np * 64 : 0);
+    d.take(w.bj_P, sh.bj ? (size_t)B * np * 64 : 0);
+    d.take(w.bj_U, sh.bj ? (size_t)B * 2 * np : 0);
     d.take(w.stage_re, (size_t)B * S.n);   // host outputs are staged through these
     d.take(w.stage_im, (size_t)B * S.n);
     h.take(w.h_flags, B);
@@ -293,6 +302,7 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     w.Vb = Basis{w.V.p, (int64_t)w.mdim * 2 * np, 2 * np, np};
     w.Xb = sh.qmr ? Basis{w.V.p + 5 * 2 * np, (int64_t)w.mdim * 2 * np, 2 * np, np}   // the QMR iterate
                   : Basis{w.X.p, 2 * np, 2 * np, np};
+    w.Ub = Basis{w.bj_U.p, 2 * np, 0, np};   // one vector per system: every slot index names it
 }
 
 // Allocates the work space of one shape: one device and one pinned host allocation.
@@ -526,6 +536,14 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
     }
     if (all.empty()) return;
     upload(w, SLOT_ACT, all, st);
+    const bool bj = w.shape.bj;
+    if (bj) {
+        // the inverted diagonal blocks of every system of the solve
+        tm.begin(st);
+        bj_setup(S, w.sys[SLOT_ACT].p, (int)all.size(), w.z.p, w.bj_C.p, w.bj_P.p, st);
+        tm.end(st, KC_PRECOND, 8.0 * S.nnz * 64 + (double)all.size() * (S.npad / 64) * 64.0 * 63 * 128 * 8,
+               S.npad * 64.0 * 8 * (1 + all.size() * 2.0));
+    }
     // x0 = 0, r0 = b
     copy_rhs(S, w.sys[SLOT_ACT].p, (int)all.size(), w.b.p, w.dir.p, w.Vb, w.norm2.p, (int)w.nblk, st);
     sumsq(w.sys[SLOT_ACT].p, (int)all.size(), w.norm2.p, (int)w.nblk, w.beta.p, st);
@@ -626,14 +644,22 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                     for (int p = 0; p < 3; ++p) {
                         if (grp[p].empty()) continue;
                         const int ng = (int)grp[p].size();
+                        const double* scale = k == 0 ? w.inv_beta.p : w.inv_h.p;
                         tm.begin(st);
-                        pack_columns(p, w.Vb, w.sys[p].p, ng, k, k == 0 ? w.inv_beta.p : w.inv_h.p, true,
-                                     x_block(w, p), w.npad, st, w.run.p);
-                        tm.end(st, KC_PACK, 0, ng * n * (32.0 + 2 * elem_size(p)));
+                        if (bj) {
+                            // u = M^-1 v: the product is taken of u, and u is the shifted term
+                            bj_pack(p, w.Vb, k, w.sys[p].p, ng, scale, w.bj_P.p, w.npad, w.Ub, x_block(w, p), w.npad,
+                                    w.run.p, st);
+                            tm.end(st, KC_PRECOND, 8.0 * 64 * n * ng, ng * n * (1024.0 + 48 + 2 * elem_size(p)));
+                        } else {
+                            pack_columns(p, w.Vb, w.sys[p].p, ng, k, scale, true, x_block(w, p), w.npad, st,
+                                         w.run.p);
+                            tm.end(st, KC_PACK, 0, ng * n * (32.0 + 2 * elem_size(p)));
+                        }
                         block_product(S, w, p, 2 * ng, tm, st);
                         tm.begin(st);
-                        spmm_shift(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, w.z.p, w.Vb, k,
-                                   k + 1, st);
+                        spmm_shift(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, w.z.p, w.Vb,
+                                   bj ? 0 : k, k + 1, st, false, bj ? &w.Ub : nullptr);
                         tm.end(st, KC_SPMM, 4.0 * S.nnz * ng + 8 * n * ng,
                                12.0 * S.nnz + ng * n * (2.0 * out_size(p) + 16 + 16));
                     }
@@ -696,8 +722,18 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         WFQ_HIP(hipMemcpyAsync(w.ksteps.p, w.h_ksteps.p, B * sizeof(int), hipMemcpyHostToDevice, st));
         tm.begin(st);
         tri_solve(w.sys[SLOT_ACT].p, na, w.ksteps.p, w.mdim, w.R.p, w.g.p, w.y.p, w.cond.p, st);
-        x_update(w.Vb, w.Xb, S.n, w.sys[SLOT_ACT].p, na, w.ksteps.p, w.y.p, w.mdim, st);
-        tm.end(st, KC_XUPDATE, 0, 16.0 * n * na * (m + 2));
+        if (bj) {
+            // x += M^-1 (V y)
+            WFQ_HIP(hipMemsetAsync(w.bj_U.p, 0, w.bj_U.count * sizeof(double), st));
+            x_update(w.Vb, w.Ub, S.n, w.sys[SLOT_ACT].p, na, w.ksteps.p, w.y.p, w.mdim, st);
+            tm.end(st, KC_XUPDATE, 0, 16.0 * n * na * (m + 2));
+            tm.begin(st);
+            bj_add(w.sys[SLOT_ACT].p, na, w.bj_P.p, w.npad, w.Ub, w.Xb, st);
+            tm.end(st, KC_PRECOND, 8.0 * 64 * n * na, na * n * (1024.0 + 48));
+        } else {
+            x_update(w.Vb, w.Xb, S.n, w.sys[SLOT_ACT].p, na, w.ksteps.p, w.y.p, w.mdim, st);
+            tm.end(st, KC_XUPDATE, 0, 16.0 * n * na * (m + 2));
+        }
         fp64_residual(S, w, active, tm, st);
         WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
         std::vector<double> condh(B);
@@ -1172,6 +1208,7 @@ uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_d
     b += std::min<uint64_t>(kSplitWsCap, 7 * mpad * np * 8);   // split-k partial tiles
     if (o.algorithm == WFQ_MSGMRES) b += ms_bytes(S, o, B, n_dir);
     if (o.algorithm == WFQ_QMR) b += (uint64_t)B * 2 * np * 8;   // compact T p
+    if (o.block_jacobi) b += np * 64 * 8 + (uint64_t)B * (np * 64 * 16 + 2 * np * 8);   // C, P, u
     return b;
 }
 
@@ -1188,6 +1225,8 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
                                     : "the stored copy of T for the requested precision was not built (store_mask)"};
     if (!have_copy(S, WFQ_PREC_FP64))
         throw Error{WFQ_EINVAL, "FP64 refinement needs the FP64 copy of T (store_mask must include WFQ_STORE_FP64)"};
+    if (o.block_jacobi && !S.T64)
+        throw Error{WFQ_EINVAL, "block-Jacobi preconditioning needs the stored FP64 T (not matrix-free)"};
 
     // batch size: as many systems as fit the budget
     // (systems index the y/z dimension of several grids: at most 32768 per batch)
@@ -1205,6 +1244,7 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
     sh.prec = prec;
     sh.ms_m = o.algorithm == WFQ_MSGMRES ? ms_dim(o, S.n) : 0;
     sh.qmr = qmr;
+    sh.bj = o.block_jacobi && o.algorithm == WFQ_GMRES;
     GraphCache* graphs = nullptr;
     std::unique_ptr<Work> own;   // a work space too large to keep on the handle
     Work& w = solve_work(S, sh, graphs, own);

@@ -168,14 +168,15 @@ void ms_xupdate(const double* V, int64_t n, int64_t npad, int mdim1, const int* 
 // ---- block-Jacobi right preconditioning (64-atom diagonal blocks of L T + z I)
 //
 // bj_setup: C_b = (L T)_bb into C ([npad/64][64][64], FP64; needs the stored FP64 T), then
-// P_sb = (C_b + z_s I)^-1 for the nsys listed systems into P ([B][npad/64][64 x 64] complex, column-major).
-void bj_setup(const Structure& S, const int* sys, int nsys, const double2* z, double* C, double2* P,
+// P_sb = (C_b + z_s I)^-1 for the nsys listed systems into P ([B][npad/64][64 x 64] complex FP32,
+// column-major; inverted in FP64).
+void bj_setup(const Structure& S, const int* sys, int nsys, const double2* z, double* C, float2* P,
               hipStream_t st);
 // v = V(s, j) * scale[s] (written back), u = P_s v into U(s) and into X[2k + plane] in precision prec
 // (zero columns where run[s] == 0; scale and run may be NULL), for the nsys listed systems.
-void bj_pack(int prec, const Basis& V, int j, const int* sys, int nsys, const double* scale, const double2* P,
+void bj_pack(int prec, const Basis& V, int j, const int* sys, int nsys, const double* scale, const float2* P,
              int64_t npad, const Basis& U, void* X, int64_t ld, const int* run, hipStream_t st);
 // X(s) += P_s U(s) for the nsys listed systems
-void bj_add(const int* sys, int nsys, const double2* P, int64_t npad, const Basis& U, const Basis& X, hipStream_t st);
+void bj_add(const int* sys, int nsys, const float2* P, int64_t npad, const Basis& U, const Basis& X, hipStream_t st);
 
 }  // namespace wfq

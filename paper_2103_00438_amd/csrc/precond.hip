@@ -52,95 +52,174 @@ __device__ inline double2 c_inv(double2 a) {
     return make_double2(a.x / d, -a.y / d);
 }
 
-// P_sb = (C_b + z_s I)^-1, one work-group of 256 threads per (block, listed system): Gauss-Jordan
-// elimination with partial pivoting on [M | I] (64 x 128 complex in LDS; pivot = the largest
-// modulus in the column, the first row on ties). Output column-major: P[(s nblk + b) 4096 + c 64 + r].
-__global__ void __launch_bounds__(256) bj_invert_kernel(const double* __restrict__ C, const int* __restrict__ sys,
+constexpr int kG = 8;        // inversion: threads per row
+constexpr int kJ = kB / kG;  // inversion: entries per thread
+
+// P_sb = (C_b + z_s I)^-1, one work-group of 512 threads per (block, listed system): Gauss-Jordan
+// elimination in place with partial pivoting (pivot = the largest modulus in the column, the first
+// row on ties), in FP64 and in registers: thread (row r = tid / 8, g = tid % 8) holds the 8 entries
+// of row r in the columns g + 8 j. Step p shares only the pivot column, the pivot row and the row it
+// is swapped with through LDS (double-buffered by p % 2, so two barriers a step). The row swaps make
+// the result the inverse of the row-permuted matrix; the columns are put back in place when the
+// result is written. To keep the register indices compile-time constants, the 8 steps of column
+// group jp run unrolled with the pivot column in a[0], and the row array is rotated by one after each
+// group (8 rotations restore the original order).
+// Output rounded to complex FP32, column-major: P[(s nblk + b) 4096 + c 64 + r]. The rounded inverse
+// is the preconditioner (the same one in the product and in the iterate update), so the rounding
+// changes the step count at most marginally and the solution not at all.
+__global__ void __launch_bounds__(512) bj_invert_kernel(const double* __restrict__ C, const int* __restrict__ sys,
                                                         const double2* __restrict__ z, int64_t nblk,
-                                                        double2* __restrict__ P) {
-    __shared__ double2 A[kB][2 * kB + 1];
-    __shared__ double2 fcol[kB];
-    __shared__ int piv;
+                                                        float2* __restrict__ P) {
+    __shared__ double mag[2][kB];
+    __shared__ double2 colv[2][kB];
+    __shared__ double2 prow[2][kB];
+    __shared__ double2 srow[2][kB];
+    __shared__ int qs[kB];
+    __shared__ int dest[kB];
     const int64_t b = blockIdx.x;
     const int s = sys[blockIdx.y];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, r = tid >> 3, g = tid & 7, lane = tid & 63;
     const double2 zs = z[s];
-    for (int idx = tid; idx < kB * 2 * kB; idx += 256) {
-        const int r = idx / (2 * kB), c = idx % (2 * kB);
-        double2 v;
-        if (c < kB) {
-            v = make_double2(C[(b * kB + r) * kB + c], 0.0);
-            if (r == c) {
-                v.x += zs.x;
-                v.y += zs.y;
-            }
-        } else {
-            v = make_double2(c - kB == r ? 1.0 : 0.0, 0.0);
+    double2 a[kJ];
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+        const int c = g + kG * j;
+        double2 v = make_double2(C[(b * kB + r) * kB + c], 0.0);
+        if (c == r) {
+            v.x += zs.x;
+            v.y += zs.y;
         }
-        A[r][c] = v;
+        a[j] = v;
     }
-    __syncthreads();
-    for (int p = 0; p < kB; ++p) {
-        if (wave == 0) {
-            // argmax over rows p .. 63 of |A[r][p]|^2; lane r holds row r
-            double val = -1.0;
-            if (lane >= p) val = A[lane][p].x * A[lane][p].x + A[lane][p].y * A[lane][p].y;
-            int idx = lane;
+#pragma unroll 1
+    for (int jp = 0; jp < kJ; ++jp) {
+#pragma unroll
+        for (int gp = 0; gp < kG; ++gp) {
+            const int p = kG * jp + gp;
+            const int buf = gp & 1;
+            if (g == gp) {   // the owners of column p (held in a[0])
+                const double2 v = a[0];
+                mag[buf][r] = r >= p ? v.x * v.x + v.y * v.y : -1.0;
+                colv[buf][r] = v;
+            }
+            __syncthreads();
+            // argmax over the rows, the same in every wave (a total order: larger value, then lower row)
+            double val = mag[buf][lane];
+            int q = lane;
 #pragma unroll
             for (int off = 32; off >= 1; off >>= 1) {
                 const double ov = __shfl_xor(val, off, 64);
-                const int oi = __shfl_xor(idx, off, 64);
-                if (ov > val || (ov == val && oi < idx)) {
+                const int oq = __shfl_xor(q, off, 64);
+                if (ov > val || (ov == val && oq < q)) {
                     val = ov;
-                    idx = oi;
+                    q = oq;
                 }
             }
-            if (lane == 0) piv = idx;
-        }
-        __syncthreads();
-        const int q = piv;
-        if (q != p)
-            for (int c = tid; c < 2 * kB; c += 256) {
-                const double2 t = A[p][c];
-                A[p][c] = A[q][c];
-                A[q][c] = t;
+            if (r == q) {
+#pragma unroll
+                for (int j = 0; j < kJ; ++j) prow[buf][g + kG * ((j + jp) & (kJ - 1))] = a[j];
             }
-        __syncthreads();
-        const double2 ip = c_inv(A[p][p]);
-        __syncthreads();   // every thread has read the pivot before row p is scaled
-        for (int c = tid; c < 2 * kB; c += 256) A[p][c] = c_mul(A[p][c], ip);
-        if (tid < kB) fcol[tid] = A[tid][p];
-        __syncthreads();
-        for (int idx = tid; idx < kB * 2 * kB; idx += 256) {
-            const int r = idx / (2 * kB), c = idx % (2 * kB);
-            if (r == p) continue;
-            const double2 f = fcol[r], a = A[p][c];
-            A[r][c] = make_double2(A[r][c].x - (f.x * a.x - f.y * a.y), A[r][c].y - (f.x * a.y + f.y * a.x));
+            if (r == p && q != p) {
+#pragma unroll
+                for (int j = 0; j < kJ; ++j) srow[buf][g + kG * ((j + jp) & (kJ - 1))] = a[j];
+            }
+            if (tid == 0) qs[p] = q;
+            __syncthreads();
+            const double2 inv = c_inv(prow[buf][p]);
+            if (r == p) {
+                // the (swapped-in) pivot row, scaled; its column p becomes 1 / pivot
+#pragma unroll
+                for (int j = 0; j < kJ; ++j) {
+                    const int c = g + kG * ((j + jp) & (kJ - 1));
+                    a[j] = c == p ? inv : c_mul(prow[buf][c], inv);
+                }
+            } else {
+                double2 f = colv[buf][r];
+                if (r == q) {   // this row now holds the old row p
+                    f = colv[buf][p];
+#pragma unroll
+                    for (int j = 0; j < kJ; ++j) a[j] = srow[buf][g + kG * ((j + jp) & (kJ - 1))];
+                }
+                const double2 fi = c_mul(f, inv);
+#pragma unroll
+                for (int j = 0; j < kJ; ++j) {
+                    const int c = g + kG * ((j + jp) & (kJ - 1));
+                    const double2 pr = prow[buf][c];
+                    a[j] = c == p ? make_double2(-fi.x, -fi.y)
+                                  : make_double2(a[j].x - (fi.x * pr.x - fi.y * pr.y),
+                                                 a[j].y - (fi.x * pr.y + fi.y * pr.x));
+                }
+            }
         }
-        __syncthreads();
+        // rotate so that the next group's pivot column sits in a[0]
+        const double2 t = a[0];
+#pragma unroll
+        for (int j = 0; j < kJ - 1; ++j) a[j] = a[j + 1];
+        a[kJ - 1] = t;
     }
-    double2* out = P + ((int64_t)s * nblk + b) * kB * kB;
-    for (int idx = tid; idx < kB * kB; idx += 256) {
-        const int c = idx / kB, r = idx % kB;
-        out[idx] = A[r][kB + c];
+    __syncthreads();
+    // inverse = X S_63 ... S_0 (S_p: the row swap of step p, applied to columns): output column j is
+    // computed column sigma(j), with sigma(j) = j carried through the swaps of steps 0 .. 63 in order
+    if (tid < kB) {
+        int idx = tid;
+        for (int p = 0; p < kB; ++p) {
+            const int q = qs[p];
+            idx = idx == p ? q : (idx == q ? p : idx);
+        }
+        dest[idx] = tid;
+    }
+    __syncthreads();
+    float2* out = P + ((int64_t)s * nblk + b) * kB * kB;
+#pragma unroll
+    for (int j = 0; j < kJ; ++j) {
+        const int c = g + kG * j;
+        out[dest[c] * kB + r] = make_float2((float)a[j].x, (float)a[j].y);
     }
 }
 
-// The preconditioned product input for block b of listed system k: v = V(s, j) * scale[s] is
-// written back (the normalised basis vector), u = P_sb v goes to U(s) and to columns 2k, 2k+1 of
-// the packed block X. A system with run[s] == 0 gets zero columns.
+// Lane c's value of x, for a wave-uniform c (two 32-bit lane reads).
+__device__ inline double lane_value(double x, int c) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), c);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), c);
+    return __hiloint2double(hi, lo);
+}
+
+// y[r] = sum_c P_sb[c][r] x[c] for the 64 rows of one block, x held one entry per lane; the 64
+// columns are read as 4 groups of 16 loads in flight (coalesced 512-byte rows of P).
+__device__ inline void block_apply(const float2* __restrict__ Pb, int r, double xr, double xi, double& ar,
+                                   double& ai) {
+    ar = 0.0;
+    ai = 0.0;
+#pragma unroll
+    for (int c0 = 0; c0 < kB; c0 += 16) {
+        float2 p[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) p[t] = Pb[(c0 + t) * kB + r];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const double vr = lane_value(xr, c0 + t), vi = lane_value(xi, c0 + t);
+            const double pr = p[t].x, pi = p[t].y;
+            ar += pr * vr - pi * vi;
+            ai += pr * vi + pi * vr;
+        }
+    }
+}
+
+// The preconditioned product input, one wave per (block b, listed system k): v = V(s, j) * scale[s]
+// is written back (the normalised basis vector), u = P_sb v goes to U(s) and to columns 2k, 2k+1
+// of the packed block X. A system with run[s] == 0 gets zero columns.
 template <typename E>
-__global__ void __launch_bounds__(64) bj_pack_kernel(Basis V, int j, const int* __restrict__ sys,
-                                                     const double* __restrict__ scale, const double2* __restrict__ P,
-                                                     int64_t nblk, Basis U, E* __restrict__ X, int64_t ld,
-                                                     const int* __restrict__ run) {
-    __shared__ double2 v[kB];
+__global__ void __launch_bounds__(256) bj_pack_kernel(Basis V, int j, const int* __restrict__ sys, int nsys,
+                                                      const double* __restrict__ scale, const float2* __restrict__ P,
+                                                      int64_t nblk, Basis U, E* __restrict__ X, int64_t ld,
+                                                      const int* __restrict__ run) {
     const int64_t b = blockIdx.x;
-    const int k = blockIdx.y;
+    const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (k >= nsys) return;   // whole waves; no work-group barrier below
     const int s = sys[k];
-    const int r = threadIdx.x;
+    const int r = threadIdx.x & 63;
     const int64_t i = b * kB + r;
-    if (run && !run[s]) {   // uniform over the work-group
+    if (run && !run[s]) {
         X[(int64_t)(2 * k) * ld + i] = cast_from_double<E>(0.0);
         X[(int64_t)(2 * k + 1) * ld + i] = cast_from_double<E>(0.0);
         return;
@@ -150,15 +229,8 @@ __global__ void __launch_bounds__(64) bj_pack_kernel(Basis V, int j, const int* 
     const double a = vr[i] * sc, bb = vr[i + V.npad] * sc;
     vr[i] = a;
     vr[i + V.npad] = bb;
-    v[r] = make_double2(a, bb);
-    __syncthreads();
-    const double2* Pb = P + ((int64_t)s * nblk + b) * kB * kB;
-    double ar = 0.0, ai = 0.0;
-    for (int c = 0; c < kB; ++c) {
-        const double2 p = Pb[c * kB + r], x = v[c];
-        ar += p.x * x.x - p.y * x.y;
-        ai += p.x * x.y + p.y * x.x;
-    }
+    double ar, ai;
+    block_apply(P + ((int64_t)s * nblk + b) * kB * kB, r, a, bb, ar, ai);
     double* ur = vslot(U, s, 0);
     ur[i] = ar;
     ur[i + U.npad] = ai;
@@ -166,24 +238,18 @@ __global__ void __launch_bounds__(64) bj_pack_kernel(Basis V, int j, const int* 
     X[(int64_t)(2 * k + 1) * ld + i] = cast_from_double<E>(ai);
 }
 
-// X(s) += P_s U(s) over block b of listed system k (the iterate update through the preconditioner)
-__global__ void __launch_bounds__(64) bj_add_kernel(const int* __restrict__ sys, const double2* __restrict__ P,
-                                                    int64_t nblk, Basis U, Basis X) {
-    __shared__ double2 t[kB];
+// X(s) += P_s U(s), one wave per (block b, listed system k) (the iterate update through M^-1)
+__global__ void __launch_bounds__(256) bj_add_kernel(const int* __restrict__ sys, int nsys,
+                                                     const float2* __restrict__ P, int64_t nblk, Basis U, Basis X) {
     const int64_t b = blockIdx.x;
-    const int s = sys[blockIdx.y];
-    const int r = threadIdx.x;
+    const int k = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (k >= nsys) return;
+    const int s = sys[k];
+    const int r = threadIdx.x & 63;
     const int64_t i = b * kB + r;
     const double* ur = vslot(U, s, 0);
-    t[r] = make_double2(ur[i], ur[i + U.npad]);
-    __syncthreads();
-    const double2* Pb = P + ((int64_t)s * nblk + b) * kB * kB;
-    double ar = 0.0, ai = 0.0;
-    for (int c = 0; c < kB; ++c) {
-        const double2 p = Pb[c * kB + r], x = t[c];
-        ar += p.x * x.x - p.y * x.y;
-        ai += p.x * x.y + p.y * x.x;
-    }
+    double ar, ai;
+    block_apply(P + ((int64_t)s * nblk + b) * kB * kB, r, ur[i], ur[i + U.npad], ar, ai);
     double* xr = vslot(X, s, 0);
     xr[i] += ar;
     xr[i + X.npad] += ai;
@@ -191,7 +257,7 @@ __global__ void __launch_bounds__(64) bj_add_kernel(const int* __restrict__ sys,
 
 }  // namespace
 
-void bj_setup(const Structure& S, const int* sys, int nsys, const double2* z, double* C, double2* P,
+void bj_setup(const Structure& S, const int* sys, int nsys, const double2* z, double* C, float2* P,
               hipStream_t st) {
     if (!S.T64) throw Error{WFQ_EINVAL, "block-Jacobi preconditioning needs the stored FP64 T"};
     const int64_t nblk = S.npad / kB;
@@ -199,31 +265,33 @@ void bj_setup(const Structure& S, const int* sys, int nsys, const double2* z, do
                        S.T64, C);
     WFQ_CHECK_LAUNCH();
     if (nsys <= 0) return;
-    hipLaunchKernelGGL(bj_invert_kernel, dim3((unsigned)nblk, (unsigned)nsys), dim3(256), 0, st, C, sys, z, nblk, P);
+    hipLaunchKernelGGL(bj_invert_kernel, dim3((unsigned)nblk, (unsigned)nsys), dim3(64 * kG), 0, st, C, sys, z, nblk,
+                       P);
     WFQ_CHECK_LAUNCH();
 }
 
-void bj_pack(int prec, const Basis& V, int j, const int* sys, int nsys, const double* scale, const double2* P,
+void bj_pack(int prec, const Basis& V, int j, const int* sys, int nsys, const double* scale, const float2* P,
              int64_t npad, const Basis& U, void* X, int64_t ld, const int* run, hipStream_t st) {
     if (nsys <= 0) return;
     const int64_t nblk = npad / kB;
-    dim3 grd((unsigned)nblk, (unsigned)nsys);
+    dim3 grd((unsigned)nblk, (unsigned)((nsys + 3) / 4));
     if (prec == WFQ_PREC_FP64)
-        hipLaunchKernelGGL(bj_pack_kernel<double>, grd, dim3(kB), 0, st, V, j, sys, scale, P, nblk, U,
+        hipLaunchKernelGGL(bj_pack_kernel<double>, grd, dim3(256), 0, st, V, j, sys, nsys, scale, P, nblk, U,
                            static_cast<double*>(X), ld, run);
     else if (prec == WFQ_PREC_FP32)
-        hipLaunchKernelGGL(bj_pack_kernel<float>, grd, dim3(kB), 0, st, V, j, sys, scale, P, nblk, U,
+        hipLaunchKernelGGL(bj_pack_kernel<float>, grd, dim3(256), 0, st, V, j, sys, nsys, scale, P, nblk, U,
                            static_cast<float*>(X), ld, run);
     else
-        hipLaunchKernelGGL(bj_pack_kernel<uint16_t>, grd, dim3(kB), 0, st, V, j, sys, scale, P, nblk, U,
+        hipLaunchKernelGGL(bj_pack_kernel<uint16_t>, grd, dim3(256), 0, st, V, j, sys, nsys, scale, P, nblk, U,
                            static_cast<uint16_t*>(X), ld, run);
     WFQ_CHECK_LAUNCH();
 }
 
-void bj_add(const int* sys, int nsys, const double2* P, int64_t npad, const Basis& U, const Basis& X, hipStream_t st) {
+void bj_add(const int* sys, int nsys, const float2* P, int64_t npad, const Basis& U, const Basis& X, hipStream_t st) {
     if (nsys <= 0) return;
     const int64_t nblk = npad / kB;
-    hipLaunchKernelGGL(bj_add_kernel, dim3((unsigned)nblk, (unsigned)nsys), dim3(kB), 0, st, sys, P, nblk, U, X);
+    hipLaunchKernelGGL(bj_add_kernel, dim3((unsigned)nblk, (unsigned)((nsys + 3) / 4)), dim3(256), 0, st, sys, nsys, P,
+                       nblk, U, X);
     WFQ_CHECK_LAUNCH();
 }
 

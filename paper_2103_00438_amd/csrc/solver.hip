@@ -165,9 +165,9 @@ struct Work {
     Buf<int> warm_sys, warm_a, warm_b;   // warm starts: target and the two solved neighbours
     Buf<double2> warm_t;                 // interpolation weight in z
     // block-Jacobi: C_b (FP64, [npad/64][64][64]), the inverted blocks of every system
-    // ([B][npad/64][64 x 64] complex, column-major) and the preconditioned vector u of every system
+    // ([B][npad/64][64 x 64] complex FP32, column-major) and the preconditioned vector u of every system
     Buf<double> bj_C, bj_U;
-    Buf<double2> bj_P;
+    Buf<float2> bj_P;
     MsWork ms;
     // pinned host mirrors
     Buf<double> h_snorm, h_est, h_beta, h_invb;
@@ -542,7 +542,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         tm.begin(st);
         bj_setup(S, w.sys[SLOT_ACT].p, (int)all.size(), w.z.p, w.bj_C.p, w.bj_P.p, st);
         tm.end(st, KC_PRECOND, 8.0 * S.nnz * 64 + (double)all.size() * (S.npad / 64) * 64.0 * 63 * 128 * 8,
-               S.npad * 64.0 * 8 * (1 + all.size() * 2.0));
+               S.npad * 64.0 * 8 * (1.0 + all.size()));
     }
     // x0 = 0, r0 = b
     copy_rhs(S, w.sys[SLOT_ACT].p, (int)all.size(), w.b.p, w.dir.p, w.Vb, w.norm2.p, (int)w.nblk, st);
@@ -650,7 +650,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                             // u = M^-1 v: the product is taken of u, and u is the shifted term
                             bj_pack(p, w.Vb, k, w.sys[p].p, ng, scale, w.bj_P.p, w.npad, w.Ub, x_block(w, p), w.npad,
                                     w.run.p, st);
-                            tm.end(st, KC_PRECOND, 8.0 * 64 * n * ng, ng * n * (1024.0 + 48 + 2 * elem_size(p)));
+                            tm.end(st, KC_PRECOND, 8.0 * 64 * n * ng, ng * n * (512.0 + 48 + 2 * elem_size(p)));
                         } else {
                             pack_columns(p, w.Vb, w.sys[p].p, ng, k, scale, true, x_block(w, p), w.npad, st,
                                          w.run.p);
@@ -729,7 +729,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             tm.end(st, KC_XUPDATE, 0, 16.0 * n * na * (m + 2));
             tm.begin(st);
             bj_add(w.sys[SLOT_ACT].p, na, w.bj_P.p, w.npad, w.Ub, w.Xb, st);
-            tm.end(st, KC_PRECOND, 8.0 * 64 * n * na, na * n * (1024.0 + 48));
+            tm.end(st, KC_PRECOND, 8.0 * 64 * n * na, na * n * (512.0 + 48));
         } else {
             x_update(w.Vb, w.Xb, S.n, w.sys[SLOT_ACT].p, na, w.ksteps.p, w.y.p, w.mdim, st);
             tm.end(st, KC_XUPDATE, 0, 16.0 * n * na * (m + 2));
@@ -1208,7 +1208,7 @@ uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_d
     b += std::min<uint64_t>(kSplitWsCap, 7 * mpad * np * 8);   // split-k partial tiles
     if (o.algorithm == WFQ_MSGMRES) b += ms_bytes(S, o, B, n_dir);
     if (o.algorithm == WFQ_QMR) b += (uint64_t)B * 2 * np * 8;   // compact T p
-    if (o.block_jacobi) b += np * 64 * 8 + (uint64_t)B * (np * 64 * 16 + 2 * np * 8);   // C, P, u
+    if (o.block_jacobi) b += np * 64 * 8 + (uint64_t)B * (np * 64 * 8 + 2 * np * 8);   // C, P, u
     return b;
 }
 

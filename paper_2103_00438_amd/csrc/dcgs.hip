@@ -39,15 +39,11 @@ __device__ inline double c_abs(double2 a) { return hypot(a.x, a.y); }
 __device__ inline int dot_a(int t) { return t; }
 __device__ inline int dot_b(int k, int t) { return k + 1 + t; }
 
-// Wide form: one wave per (512-row chunk, system); u and z of the chunk in registers.
-__global__ void __launch_bounds__(256) dcgs_dot_rows_kernel(Basis V, int64_t n, const int* __restrict__ sys, int k,
-                                                       int with_z, double2* __restrict__ partial, int pstride,
-                                                       int64_t nwc, const int* __restrict__ run) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
-    if (wc >= nwc) return;
-    const int s = sys[blockIdx.y];
-    if (run && !run[s]) return;
+// Wide form: one wave per (512-row chunk, system); u and z of the chunk in registers. FULL: every
+// row of the chunk is below n (all chunks but the last), so the loads need no per-row guard.
+template <bool FULL>
+__device__ inline void dot_rows_body(const Basis& V, int64_t n, int s, int k, int with_z, double2* __restrict__ partial,
+                                     int pstride, int64_t nwc, int64_t wc, int lane) {
     const double* ur = slot(V, s, k);
     const double* zr = with_z ? slot(V, s, k + 1) : ur;
     const int64_t row0 = wc * kWaveRows + lane;
@@ -55,26 +51,46 @@ __global__ void __launch_bounds__(256) dcgs_dot_rows_kernel(Basis V, int64_t n, 
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int64_t row = row0 + 64 * r;
-        const bool in = row < n;
+        const bool in = FULL || row < n;
         xr[r] = in ? ur[row] : 0.0;
         xi[r] = in ? ur[row + V.npad] : 0.0;
         yr[r] = (in && with_z) ? zr[row] : 0.0;
         yi[r] = (in && with_z) ? zr[row + V.npad] : 0.0;
     }
     double2* P = partial + (int64_t)s * pstride * nwc + wc;
-    for (int i = 0; i < k; ++i) {
+    // in full chunks the rows of basis vector i + 1 are loaded before the sums of vector i are
+    // reduced, so a wave keeps loads in flight across its reductions (rows past n read as zero:
+    // same sums)
+    double va[8], vb[8];
+    auto load_v = [&](int i, double (&ra)[8], double (&rb)[8]) {
         const double* vr = slot(V, s, i);
-        const double* vi = vr + V.npad;
-        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int64_t row = row0 + 64 * r;
-            if (row < n) {
-                const double a = vr[row], b = vi[row];
-                ar += a * xr[r] + b * xi[r];   // conj(v) u
-                ai += a * xi[r] - b * xr[r];
-                br += a * yr[r] + b * yi[r];   // conj(v) z
-                bi += a * yi[r] - b * yr[r];
+            const bool in = FULL || row < n;
+            ra[r] = in ? vr[row] : 0.0;
+            rb[r] = in ? vr[row + V.npad] : 0.0;
+        }
+    };
+    if (k > 0) load_v(0, va, vb);
+    for (int i = 0; i < k; ++i) {
+        double na[8], nb[8];
+        if constexpr (FULL) load_v(min(i + 1, k - 1), na, nb);   // the last step re-reads its own vector
+        else if (i > 0) load_v(i, va, vb);                       // the tail chunk: no prefetch
+        double ar = 0.0, ai = 0.0, br = 0.0, bi = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const double a = va[r], b = vb[r];
+            ar += a * xr[r] + b * xi[r];   // conj(v) u
+            ai += a * xi[r] - b * xr[r];
+            br += a * yr[r] + b * yi[r];   // conj(v) z
+            bi += a * yi[r] - b * yr[r];
+        }
+        if constexpr (FULL) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+                va[r] = na[r];
+                vb[r] = nb[r];
             }
         }
         ar = wave_sum(ar);
@@ -100,6 +116,20 @@ __global__ void __launch_bounds__(256) dcgs_dot_rows_kernel(Basis V, int64_t n, 
         P[(int64_t)k * nwc] = make_double2(al, 0.0);
         if (with_z) P[(int64_t)(2 * k + 1) * nwc] = make_double2(br, bi);
     }
+}
+
+__global__ void __launch_bounds__(256) dcgs_dot_rows_kernel(Basis V, int64_t n, const int* __restrict__ sys, int k,
+                                                       int with_z, double2* __restrict__ partial, int pstride,
+                                                       int64_t nwc, const int* __restrict__ run) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
+    if (wc >= nwc) return;
+    const int s = sys[blockIdx.y];
+    if (run && !run[s]) return;
+    if ((wc + 1) * kWaveRows <= n)
+        dot_rows_body<true>(V, n, s, k, with_z, partial, pstride, nwc, wc, lane);
+    else
+        dot_rows_body<false>(V, n, s, k, with_z, partial, pstride, nwc, wc, lane);
 }
 
 // Narrow form: one wave per (512-row chunk, basis vector t <= k, system), so that a few systems
@@ -255,14 +285,11 @@ __global__ void __launch_bounds__(64) dcgs_coeff_kernel(const int* __restrict__ 
 }
 
 // Wide update: one wave per (512-row chunk, system): q_k = (u - Q a) / rho into slot k and
-// w' = (z - Q b - q_k gamma) / rho into slot k + 1, with the chunk's |w'|^2.
-__global__ void __launch_bounds__(256) dcgs_update_rows_kernel(Basis V, int64_t n, const int* __restrict__ sys, int k,
-                                                          int mdim, DcgsArgs a, int64_t nwc) {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
-    if (wc >= nwc) return;
-    const int s = sys[blockIdx.y];
-    if (a.run && !a.run[s]) return;
+// w' = (z - Q b - q_k gamma) / rho into slot k + 1, with the chunk's |w'|^2. FULL: every row of the chunk is
+// below n (all chunks but the last).
+template <bool FULL>
+__device__ inline void update_rows_body(const Basis& V, int64_t n, int s, int k, int mdim, const DcgsArgs& a,
+                                        int64_t nwc, int64_t wc, int lane) {
     double* ur = slot(V, s, k);
     double* zr = slot(V, s, k + 1);
     const int64_t row0 = wc * kWaveRows + lane;
@@ -270,26 +297,42 @@ __global__ void __launch_bounds__(256) dcgs_update_rows_kernel(Basis V, int64_t 
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int64_t row = row0 + 64 * r;
-        const bool in = row < n;
+        const bool in = FULL || row < n;
         xr[r] = in ? ur[row] : 0.0;
         xi[r] = in ? ur[row + V.npad] : 0.0;
         yr[r] = in ? zr[row] : 0.0;
         yi[r] = in ? zr[row + V.npad] : 0.0;
     }
     const double2* d = a.dots + (int64_t)s * 2 * mdim;
-    for (int i = 0; i < k; ++i) {
-        const double2 ca = d[dot_a(i)], cb = d[dot_b(k, i)];
+    // in full chunks the rows of basis vector i + 1 are loaded while vector i is applied (rows past
+    // n read as zero and are not stored)
+    double va[8], vb[8];
+    auto load_v = [&](int i, double (&ra)[8], double (&rb)[8]) {
         const double* vr = slot(V, s, i);
-        const double* vi = vr + V.npad;
 #pragma unroll
         for (int r = 0; r < 8; ++r) {
             const int64_t row = row0 + 64 * r;
-            if (row < n) {
-                const double p = vr[row], q = vi[row];
-                xr[r] -= ca.x * p - ca.y * q;
-                xi[r] -= ca.x * q + ca.y * p;
-                yr[r] -= cb.x * p - cb.y * q;
-                yi[r] -= cb.x * q + cb.y * p;
+            const bool in = FULL || row < n;
+            ra[r] = in ? vr[row] : 0.0;
+            rb[r] = in ? vr[row + V.npad] : 0.0;
+        }
+    };
+    if (k > 0) load_v(0, va, vb);
+    for (int i = 0; i < k; ++i) {
+        double na[8], nb[8];
+        if constexpr (FULL) load_v(min(i + 1, k - 1), na, nb);   // the last step re-reads its own vector
+        else if (i > 0) load_v(i, va, vb);                       // the tail chunk: no prefetch
+        const double2 ca = d[dot_a(i)], cb = d[dot_b(k, i)];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const double p = va[r], q = vb[r];
+            xr[r] -= ca.x * p - ca.y * q;
+            xi[r] -= ca.x * q + ca.y * p;
+            yr[r] -= cb.x * p - cb.y * q;
+            yi[r] -= cb.x * q + cb.y * p;
+            if constexpr (FULL) {
+                va[r] = na[r];
+                vb[r] = nb[r];
             }
         }
     }
@@ -299,7 +342,7 @@ __global__ void __launch_bounds__(256) dcgs_update_rows_kernel(Basis V, int64_t 
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int64_t row = row0 + 64 * r;
-        if (row < n) {
+        if (FULL || row < n) {
             const double qr = xr[r] * ir, qi = xi[r] * ir;
             const double wr = (yr[r] - (gm.x * qr - gm.y * qi)) * ir;
             const double wi = (yi[r] - (gm.x * qi + gm.y * qr)) * ir;
@@ -312,6 +355,19 @@ __global__ void __launch_bounds__(256) dcgs_update_rows_kernel(Basis V, int64_t 
     }
     nn = wave_sum(nn);
     if (lane == 0) a.norm2[(int64_t)s * nwc + wc] = nn;
+}
+
+__global__ void __launch_bounds__(256) dcgs_update_rows_kernel(Basis V, int64_t n, const int* __restrict__ sys, int k,
+                                                          int mdim, DcgsArgs a, int64_t nwc) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
+    if (wc >= nwc) return;
+    const int s = sys[blockIdx.y];
+    if (a.run && !a.run[s]) return;
+    if ((wc + 1) * kWaveRows <= n)
+        update_rows_body<true>(V, n, s, k, mdim, a, nwc, wc, lane);
+    else
+        update_rows_body<false>(V, n, s, k, mdim, a, nwc, wc, lane);
 }
 
 // Narrow update: one 512-row chunk per work-group; each of the 4 waves sums every 4th basis vector

@@ -80,3 +80,33 @@ def test_block_product_variant_registry():
     wide = {"m96n256w8", "m160n256w8", "m192n256w8", "m192n128w8"}
     assert wide <= set(names["fp32"]) and wide <= set(names["bf16"])
     assert not wide & set(names["fp64"])
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    # the ctypes mirrors of the header's structs: same size and the same offset for every field
+    # (a field added on one side only would shift every later one), measured by a C probe
+    import shutil
+    import subprocess
+    from paper_2103_00438_amd import wfq
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = {"wfq_geometry": wfq.Geometry, "wfq_params": wfq.Params, "wfq_solve_opts": wfq.SolveOpts,
+             "wfq_result": wfq.Result, "wfq_serve_cfg": wfq.ServeCfg, "wfq_job": wfq.Job,
+             "wfq_job_timing": wfq.JobTiming, "wfq_stats": wfq.Stats}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "wfq.h"', "int main(void) {"]
+    for cname, py in pairs.items():
+        lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'    printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["    return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in pairs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)

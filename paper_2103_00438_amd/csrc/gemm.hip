@@ -4,10 +4,10 @@
 // along k, which is the layout the matrix cores want.
 //
 // Wide blocks (many Krylov columns) run on MFMA: FP64 v_mfma_f64_16x16x4, FP32 v_mfma_f32_16x16x4,
-// BF16 v_mfma_f32_16x16x32 (FP32 accumulation). A work-group (4 waves) owns a BM x BN output tile,
-// stages 128-byte k-slices of its X rows and T rows in LDS (double buffered, rows padded to 144
-// bytes so that each group of 8 lanes reading 16 bytes covers all 32 banks) and each wave computes
-// a (16 WM) x (16 WN) sub-tile. Each lane feeds the matrix core 16 bytes of k per operand; the k
+// BF16 v_mfma_f32_16x16x32 (FP32 accumulation). A work-group (4 or 8 waves) owns a BM x BN output
+// tile, stages 64-, 128- or 256-byte k-slices of its X rows and T rows in LDS (double buffered,
+// rows padded by 16 bytes so that each group of 8 lanes reading 16 bytes covers all 32 banks) and
+// each wave computes a (16 WM) x (16 WN) sub-tile. Each lane feeds the matrix core 16 bytes of k per operand; the k
 // order inside a slice is a permutation that is the same for both operands, so the sum is exact.
 // Narrow blocks (<= 8 columns, e.g. one frequency at a time) stream T once with vector loads.
 #include <cstring>
@@ -138,7 +138,7 @@ __device__ inline int xcd_logical(int b, int total) {
     return xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
 }
 
-// KB = bytes of k staged per row and stage (128 or 256); rows are padded by 16 bytes in LDS.
+// KB = bytes of k staged per row and stage (64, 128 or 256); rows are padded by 16 bytes in LDS.
 //
 // Split k: with split > 1 the k range is cut into `split` equal parts and each (m-tile, part,
 // n-tile) is one work-group, m fastest, so the m-tiles that share one slab of T and one k part
@@ -480,6 +480,9 @@ const std::vector<Variant>& variants_all() {
             r.push_back({"m192n128w8", 192, 128, 1 << 30, launch_mfma<P, 3, 4, 4, 2, 128, 1>});
             r.push_back({"m224n256w8", 224, 256, 1 << 30, launch_mfma<P, 7, 4, 2, 4, 128, 1>});
             r.push_back({"m224n128w8", 224, 128, 1 << 30, launch_mfma<P, 7, 2, 2, 4, 128, 1>});
+            // 64-byte k stages: half the LDS, so two work-groups share a CU and one's matrix-core
+            // work covers the other's barrier
+            r.push_back({"m128n256w8k64", 128, 256, 1 << 30, launch_mfma<P, 4, 4, 2, 4, 64, 2>});
         }
         return r;
     }();
@@ -506,9 +509,9 @@ int default_variant(int prec, int ncol) {
                                {96, "m128n256w8i"}, {128, "m128n256w8"}, {192, "m64n128i"}, {256, "m128n256w8i"},
                                {320, "m64n128"}, {1 << 30, "m128n256w8i"}};
     static const Pick f32[] = {{2, "skinny2"}, {4, "skinny4r8"}, {32, "m32n128"}, {64, "m64n128k256i"},
-                               {96, "m96n256w8"}, {128, "m128n64i"}, {160, "m160n256w8"}, {192, "m96n256w8"},
-                               {224, "m224n128w8"}, {256, "m128n64i"}, {288, "m96n256w8"}, {320, "m160n256w8"},
-                               {1 << 30, "m96n256w8"}};
+                               {96, "m96n256w8"}, {128, "m128n256w8k64"}, {160, "m160n256w8"}, {192, "m96n256w8"},
+                               {224, "m224n128w8"}, {256, "m128n256w8k64"}, {288, "m96n256w8"}, {320, "m160n256w8"},
+                               {1 << 30, "m128n256w8k64"}};
     // BF16 T is 2 bytes per element: even one column streams it faster through the matrix cores
     static const Pick b16[] = {{64, "m64n128i"}, {128, "m128n128"}, {192, "m192n256w8"}, {256, "m256n128w8i"},
                                {320, "m160n256w8"}, {1 << 30, "m192n256w8"}};

@@ -5,10 +5,10 @@
 // Blocks are 64 consecutive atoms of the internal, spatially sorted order. For block b the
 // frequency-independent part is C_b = (L T)_bb, C_b[r][c] = sum_k L_{ik} T_{kj} (i = 64 b + r,
 // j = 64 b + c); for system s the block of the operator is C_b + z_s I, inverted once per solve by
-// Gauss-Jordan elimination with partial pivoting in LDS. GMRES then runs on (L T + z I) M^-1 with
-// the true residual; the product input is u = M^-1 v (block by block), and the iterate update is
-// x += M^-1 (V y). Padding atoms have zero rows and columns in C, so their diagonal is z and the
-// padding of every vector stays zero.
+// Gauss-Jordan elimination with partial pivoting (FP64, in registers) and stored in complex FP32.
+// GMRES then runs on (L T + z I) M^-1 with the true residual; the product input is u = M^-1 v
+// (block by block), and the iterate update is x += M^-1 (V y). Padding atoms have zero rows and
+// columns in C, so their diagonal is z and the padding of every vector stays zero.
 #include "device_util.h"
 #include "krylov.h"
 

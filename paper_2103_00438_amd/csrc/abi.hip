@@ -256,8 +256,7 @@ int wfq_sample_T(const wfq_handle* h, int32_t precision, const int64_t* i, const
         hipLaunchKernelGGL(sample_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, h->stream, precision,
                            S.T64, S.T32, S.T16, S.npad, di, dj, count, dout);
         WFQ_CHECK_LAUNCH();
-        WFQ_HIP(hipMemcpyAsync(out, dout, count * 8, hipMemcpyDeviceToHost, h->stream));
-        WFQ_HIP(hipStreamSynchronize(h->stream));
+        d2h_sync(h->S, out, dout, count * 8, h->stream);
         (void)hipFree(di);
         (void)hipFree(dj);
         (void)hipFree(dout);
@@ -272,10 +271,9 @@ int wfq_export_L(const wfq_handle* h, int64_t* rows, int64_t* cols, double* vals
         WFQ_HIP(hipSetDevice(S.device));
         std::vector<int32_t> rp(S.n + 1), cl(S.nnz);
         std::vector<double> vl(S.nnz);
-        WFQ_HIP(hipMemcpyAsync(rp.data(), S.rowptr, (S.n + 1) * 4, hipMemcpyDeviceToHost, h->stream));
-        WFQ_HIP(hipMemcpyAsync(cl.data(), S.col, S.nnz * 4, hipMemcpyDeviceToHost, h->stream));
-        WFQ_HIP(hipMemcpyAsync(vl.data(), S.val, S.nnz * 8, hipMemcpyDeviceToHost, h->stream));
-        WFQ_HIP(hipStreamSynchronize(h->stream));
+        d2h_sync(S, rp.data(), S.rowptr, (S.n + 1) * 4, h->stream);
+        d2h_sync(S, cl.data(), S.col, S.nnz * 4, h->stream);
+        d2h_sync(S, vl.data(), S.val, S.nnz * 8, h->stream);
         for (int64_t i = 0; i < S.n; ++i)
             for (int32_t p = rp[i]; p < rp[i + 1]; ++p) {
                 rows[p] = S.perm[i];
@@ -317,11 +315,10 @@ int apply_T_impl(wfq_handle* h, int32_t precision, int32_t variant, int32_t ncol
         else
             tx_any(S, precision, dx, dy, ncol, h->stream);
         if (precision == WFQ_PREC_FP64) {
-            WFQ_HIP(hipMemcpyAsync(yh.data(), dy, (size_t)ncol * np * 8, hipMemcpyDeviceToHost, h->stream));
+            d2h_sync(S, yh.data(), dy, (size_t)ncol * np * 8, h->stream);
         } else {
             std::vector<float> yf((size_t)ncol * np);
-            WFQ_HIP(hipMemcpyAsync(yf.data(), dy, (size_t)ncol * np * 4, hipMemcpyDeviceToHost, h->stream));
-            WFQ_HIP(hipStreamSynchronize(h->stream));
+            d2h_sync(S, yf.data(), dy, (size_t)ncol * np * 4, h->stream);
             for (size_t q = 0; q < yf.size(); ++q) yh[q] = yf[q];
         }
         WFQ_HIP(hipStreamSynchronize(h->stream));
@@ -384,8 +381,7 @@ int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t nsys, const double* z
         pack_columns(precision, V, dsys, nsys, 0, nullptr, false, dx, np, h->stream);
         tx_any(S, precision, dx, dy, 2 * nsys, h->stream);
         spmm_shift(S, precision == WFQ_PREC_FP64, dy, np, dsys, nsys, dz, V, 0, 1, h->stream);
-        WFQ_HIP(hipMemcpyAsync(vh.data(), dv, vh.size() * 8, hipMemcpyDeviceToHost, h->stream));
-        WFQ_HIP(hipStreamSynchronize(h->stream));
+        d2h_sync(S, vh.data(), dv, vh.size() * 8, h->stream);
         (void)hipFree(dv);
         (void)hipFree(dz);
         (void)hipFree(dsys);
@@ -411,8 +407,7 @@ int wfq_rhs(wfq_handle* h, const double* dirs, int32_t n_dir, double E0, double*
         WFQ_HIP(hipMemcpyAsync(dd, dirs, 3 * n_dir * 8, hipMemcpyHostToDevice, h->stream));
         build_rhs(S, dd, n_dir, E0 != 0.0 ? E0 : 1.0, db, S.npad, h->stream);
         std::vector<double> bh((size_t)n_dir * S.npad);
-        WFQ_HIP(hipMemcpyAsync(bh.data(), db, bh.size() * 8, hipMemcpyDeviceToHost, h->stream));
-        WFQ_HIP(hipStreamSynchronize(h->stream));
+        d2h_sync(S, bh.data(), db, bh.size() * 8, h->stream);
         (void)hipFree(dd);
         (void)hipFree(db);
         for (int d = 0; d < n_dir; ++d)

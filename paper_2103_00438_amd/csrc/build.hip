@@ -237,7 +237,35 @@ void free_structure(Structure& s) {
     if (s.split_ws) (void)hipFree(s.split_ws);
     s.split_ws = nullptr;
     s.split_ws_bytes = 0;
+    if (s.pin_stage) (void)hipHostFree(s.pin_stage);
+    s.pin_stage = nullptr;
+    s.pin_stage_bytes = 0;
     s.bytes = 0;
+}
+
+void d2h_sync(const Structure& s, void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) {
+        WFQ_HIP(hipStreamSynchronize(st));
+        return;
+    }
+    constexpr size_t kChunk = 32u << 20;
+    const size_t cap = std::min(bytes, kChunk);
+    if (s.pin_stage_bytes < cap) {
+        if (s.pin_stage) {
+            WFQ_HIP(hipStreamSynchronize(st));
+            WFQ_HIP(hipHostFree(s.pin_stage));
+            s.pin_stage = nullptr;
+            s.pin_stage_bytes = 0;
+        }
+        WFQ_HIP(hipHostMalloc(&s.pin_stage, cap, hipHostMallocDefault));
+        s.pin_stage_bytes = cap;
+    }
+    for (size_t off = 0; off < bytes; off += cap) {
+        const size_t len = std::min(cap, bytes - off);
+        WFQ_HIP(hipMemcpyAsync(s.pin_stage, static_cast<const char*>(src) + off, len, hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipStreamSynchronize(st));
+        std::memcpy(static_cast<char*>(dst) + off, s.pin_stage, len);
+    }
 }
 
 void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, hipStream_t st) {
@@ -390,9 +418,8 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     // connectivity of the Kbar graph (breadth-first search on the host)
     {
         std::vector<int32_t> rp(n + 1), cl(s.nnz);
-        WFQ_HIP(hipMemcpyAsync(rp.data(), s.rowptr, (n + 1) * 4, hipMemcpyDeviceToHost, st));
-        WFQ_HIP(hipMemcpyAsync(cl.data(), s.col, s.nnz * 4, hipMemcpyDeviceToHost, st));
-        WFQ_HIP(hipStreamSynchronize(st));
+        d2h_sync(s, rp.data(), s.rowptr, (n + 1) * 4, st);
+        d2h_sync(s, cl.data(), s.col, s.nnz * 4, st);
         std::vector<char> seen(n, 0);
         std::vector<int32_t> stack{0};
         seen[0] = 1;

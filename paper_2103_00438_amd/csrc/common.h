@@ -82,11 +82,20 @@ struct Structure {
     // bumped whenever a block-product choice (tuning) or the partial-tile buffer changes: captured
     // launch sequences that refer to either are then stale
     mutable uint64_t epoch = 0;
+    // pinned host staging of device-to-host copies (d2h_sync)
+    mutable void* pin_stage = nullptr;
+    mutable size_t pin_stage_bytes = 0;
     SolveCache* cache = nullptr;
 };
 
 // frees the solver's cached work space and graphs (the structure's device must be current)
 void free_solve_cache(Structure& s);
+
+// Device-to-host copy into ordinary (pageable) host memory, staged in chunks through the
+// structure's pinned staging buffer (allocated on first use, freed with the structure): the copy
+// engines write only memory the library owns, never the caller's pages. The stream's earlier work
+// is finished and dst holds the data on return.
+void d2h_sync(const Structure& s, void* dst, const void* src, size_t bytes, hipStream_t st);
 
 struct KernelStat {
     const char* name;

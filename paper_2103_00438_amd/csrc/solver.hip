@@ -737,8 +737,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         fp64_residual(S, w, active, tm, st);
         WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
         std::vector<double> condh(B);
-        WFQ_HIP(hipMemcpyAsync(condh.data(), w.cond.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
-        WFQ_HIP(hipStreamSynchronize(st));
+        d2h_sync(S, condh.data(), w.cond.p, B * sizeof(double), st);
         std::vector<int> still;
         const double now = ms_since(t0);
         for (int s : active) {
@@ -954,8 +953,10 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     ms_xupdate(V, n, np, mdim1, grp_sys, grp_dir, ngrp, ksteps, y, m, w.Xb, st);
     tm.end(st, KC_XUPDATE, 0, 0);
     std::vector<double> ch(B, 1.0);
-    if (!withk.empty()) WFQ_HIP(hipMemcpyAsync(ch.data(), cond, B * sizeof(double), hipMemcpyDeviceToHost, st));
-    WFQ_HIP(hipStreamSynchronize(st));
+    if (!withk.empty())
+        d2h_sync(S, ch.data(), cond, B * sizeof(double), st);
+    else
+        WFQ_HIP(hipStreamSynchronize(st));
     for (int s = 0; s < B; ++s) {
         ss[s].iters += h_k[s];
         if (h_k[s] > 0) ss[s].cond = ch[s];
@@ -1340,12 +1341,8 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
         } else if (out.q_re || out.q_im) {
             scatter_q(S, S.dperm, w.sys[SLOT_ACT].p, nb, w.Xb, out.q_re ? w.stage_re.p : nullptr,
                       out.q_im ? w.stage_im.p : nullptr, st);
-            if (out.q_re)
-                WFQ_HIP(hipMemcpyAsync(out.q_re + (size_t)s0 * S.n, w.stage_re.p, (size_t)nb * S.n * 8,
-                                       hipMemcpyDeviceToHost, st));
-            if (out.q_im)
-                WFQ_HIP(hipMemcpyAsync(out.q_im + (size_t)s0 * S.n, w.stage_im.p, (size_t)nb * S.n * 8,
-                                       hipMemcpyDeviceToHost, st));
+            if (out.q_re) d2h_sync(S, out.q_re + (size_t)s0 * S.n, w.stage_re.p, (size_t)nb * S.n * 8, st);
+            if (out.q_im) d2h_sync(S, out.q_im + (size_t)s0 * S.n, w.stage_im.p, (size_t)nb * S.n * 8, st);
         }
         WFQ_HIP(hipStreamSynchronize(st));
         std::vector<double> are(nb * 3), aim(nb * 3);

@@ -251,8 +251,8 @@ int wfq_sample_T(const wfq_handle* h, int32_t precision, const int64_t* i, const
         WFQ_HIP(hipMalloc(&di, count * 8));
         WFQ_HIP(hipMalloc(&dj, count * 8));
         WFQ_HIP(hipMalloc(&dout, count * 8));
-        WFQ_HIP(hipMemcpyAsync(di, ii.data(), count * 8, hipMemcpyHostToDevice, h->stream));
-        WFQ_HIP(hipMemcpyAsync(dj, jj.data(), count * 8, hipMemcpyHostToDevice, h->stream));
+        h2d_sync(h->S, di, ii.data(), count * 8, h->stream);
+        h2d_sync(h->S, dj, jj.data(), count * 8, h->stream);
         hipLaunchKernelGGL(sample_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, h->stream, precision,
                            S.T64, S.T32, S.T16, S.npad, di, dj, count, dout);
         WFQ_CHECK_LAUNCH();
@@ -307,7 +307,7 @@ int apply_T_impl(wfq_handle* h, int32_t precision, int32_t variant, int32_t ncol
         WFQ_HIP(hipMalloc(&dx64, rows * np * 8));
         WFQ_HIP(hipMalloc(&dx, rows * np * 8));
         WFQ_HIP(hipMalloc(&dy, rows * np * 8));
-        WFQ_HIP(hipMemcpyAsync(dx64, xh.data(), rows * np * 8, hipMemcpyHostToDevice, h->stream));
+        h2d_sync(h->S, dx64, xh.data(), rows * np * 8, h->stream);
         convert_from_f64(precision, dx64, dx, rows * np, h->stream);
         std::vector<double> yh((size_t)ncol * np);
         if (variant >= 0)
@@ -374,9 +374,9 @@ int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t nsys, const double* z
         WFQ_HIP(hipMalloc(&dx, rows * np * 8));
         WFQ_HIP(hipMalloc(&dy, rows * np * 8));
         WFQ_HIP(hipMemsetAsync(dx, 0, rows * np * 8, h->stream));
-        WFQ_HIP(hipMemcpyAsync(dv, vh.data(), vh.size() * 8, hipMemcpyHostToDevice, h->stream));
-        WFQ_HIP(hipMemcpyAsync(dz, zh.data(), nsys * sizeof(double2), hipMemcpyHostToDevice, h->stream));
-        WFQ_HIP(hipMemcpyAsync(dsys, sl.data(), nsys * sizeof(int), hipMemcpyHostToDevice, h->stream));
+        h2d_sync(h->S, dv, vh.data(), vh.size() * 8, h->stream);
+        h2d_sync(h->S, dz, zh.data(), nsys * sizeof(double2), h->stream);
+        h2d_sync(h->S, dsys, sl.data(), nsys * sizeof(int), h->stream);
         Basis V{dv, sys_stride, 2 * np, np};
         pack_columns(precision, V, dsys, nsys, 0, nullptr, false, dx, np, h->stream);
         tx_any(S, precision, dx, dy, 2 * nsys, h->stream);
@@ -404,7 +404,7 @@ int wfq_rhs(wfq_handle* h, const double* dirs, int32_t n_dir, double E0, double*
         double *dd = nullptr, *db = nullptr;
         WFQ_HIP(hipMalloc(&dd, 3 * n_dir * 8));
         WFQ_HIP(hipMalloc(&db, (size_t)n_dir * S.npad * 8));
-        WFQ_HIP(hipMemcpyAsync(dd, dirs, 3 * n_dir * 8, hipMemcpyHostToDevice, h->stream));
+        h2d_sync(h->S, dd, dirs, 3 * n_dir * 8, h->stream);
         build_rhs(S, dd, n_dir, E0 != 0.0 ? E0 : 1.0, db, S.npad, h->stream);
         std::vector<double> bh((size_t)n_dir * S.npad);
         d2h_sync(S, bh.data(), db, bh.size() * 8, h->stream);

@@ -243,11 +243,10 @@ void free_structure(Structure& s) {
     s.bytes = 0;
 }
 
-void d2h_sync(const Structure& s, void* dst, const void* src, size_t bytes, hipStream_t st) {
-    if (bytes == 0) {
-        WFQ_HIP(hipStreamSynchronize(st));
-        return;
-    }
+namespace {
+
+// the structure's pinned staging buffer, at least min(bytes, 32 MiB) long; returns its length
+size_t pin_stage(const Structure& s, size_t bytes, hipStream_t st) {
     constexpr size_t kChunk = 32u << 20;
     const size_t cap = std::min(bytes, kChunk);
     if (s.pin_stage_bytes < cap) {
@@ -260,11 +259,35 @@ void d2h_sync(const Structure& s, void* dst, const void* src, size_t bytes, hipS
         WFQ_HIP(hipHostMalloc(&s.pin_stage, cap, hipHostMallocDefault));
         s.pin_stage_bytes = cap;
     }
+    return cap;
+}
+
+}  // namespace
+
+void d2h_sync(const Structure& s, void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) {
+        WFQ_HIP(hipStreamSynchronize(st));
+        return;
+    }
+    const size_t cap = pin_stage(s, bytes, st);
     for (size_t off = 0; off < bytes; off += cap) {
         const size_t len = std::min(cap, bytes - off);
         WFQ_HIP(hipMemcpyAsync(s.pin_stage, static_cast<const char*>(src) + off, len, hipMemcpyDeviceToHost, st));
         WFQ_HIP(hipStreamSynchronize(st));
         std::memcpy(static_cast<char*>(dst) + off, s.pin_stage, len);
+    }
+}
+
+void h2d_sync(const Structure& s, void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return;
+    const size_t cap = pin_stage(s, bytes, st);
+    // the staging buffer may still be the source of an earlier copy on this stream
+    WFQ_HIP(hipStreamSynchronize(st));
+    for (size_t off = 0; off < bytes; off += cap) {
+        const size_t len = std::min(cap, bytes - off);
+        std::memcpy(s.pin_stage, static_cast<const char*>(src) + off, len);
+        WFQ_HIP(hipMemcpyAsync(static_cast<char*>(dst) + off, s.pin_stage, len, hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipStreamSynchronize(st));
     }
 }
 
@@ -341,13 +364,13 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
 
     std::vector<int32_t> perm32(s.perm.begin(), s.perm.end());
     s.dperm = dev_alloc<int32_t>(s, n);
-    WFQ_HIP(hipMemcpyAsync(s.dperm, perm32.data(), n * 4, hipMemcpyHostToDevice, st));
+    h2d_sync(s, s.dperm, perm32.data(), n * 4, st);
     s.pos = dev_alloc<double>(s, 3 * s.npad);
     s.eta = dev_alloc<double>(s, s.npad);
     s.width = dev_alloc<double>(s, s.npad);
-    WFQ_HIP(hipMemcpyAsync(s.pos, pos_h.data(), pos_h.size() * 8, hipMemcpyHostToDevice, st));
-    WFQ_HIP(hipMemcpyAsync(s.eta, eta_h.data(), eta_h.size() * 8, hipMemcpyHostToDevice, st));
-    WFQ_HIP(hipMemcpyAsync(s.width, width_h.data(), width_h.size() * 8, hipMemcpyHostToDevice, st));
+    h2d_sync(s, s.pos, pos_h.data(), pos_h.size() * 8, st);
+    h2d_sync(s, s.eta, eta_h.data(), eta_h.size() * 8, st);
+    h2d_sync(s, s.width, width_h.data(), width_h.size() * 8, st);
     // bounding spheres of consecutive 64-atom blocks (internal order; padding atoms excluded, an
     // empty block gets radius 0), used by the matrix-free products to find far-apart tile pairs
     // (the host copy lives until the stream is synchronised at the end of the build)
@@ -375,7 +398,7 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
             sph[b * 4 + 3] = std::sqrt(r2);
         }
         s.sphere = dev_alloc<double>(s, sph.size());
-        WFQ_HIP(hipMemcpyAsync(s.sphere, sph.data(), sph.size() * 8, hipMemcpyHostToDevice, st));
+        h2d_sync(s, s.sphere, sph.data(), sph.size() * 8, st);
         s.width_max = 0.0;
         for (int64_t k = 0; k < n; ++k) s.width_max = std::max(s.width_max, width_h[k]);
     }
@@ -386,8 +409,8 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     WFQ_HIP(hipMalloc(&d_count, ncell * 4));
     WFQ_HIP(hipMalloc(&d_counts, n * 4));
     WFQ_HIP(hipMalloc(&d_flag, 4));
-    WFQ_HIP(hipMemcpyAsync(d_start, cell_start.data(), ncell * 4, hipMemcpyHostToDevice, st));
-    WFQ_HIP(hipMemcpyAsync(d_count, cell_count.data(), ncell * 4, hipMemcpyHostToDevice, st));
+    h2d_sync(s, d_start, cell_start.data(), ncell * 4, st);
+    h2d_sync(s, d_count, cell_count.data(), ncell * 4, st);
     WFQ_HIP(hipMemsetAsync(d_flag, 0, 4, st));
     GridArgs ga{grid.lo[0], grid.lo[1], grid.lo[2], 1.0 / grid.h, grid.dim[0], grid.dim[1], grid.dim[2]};
     const double rc2 = s.rc * s.rc;

@@ -96,6 +96,9 @@ void free_solve_cache(Structure& s);
 // engines write only memory the library owns, never the caller's pages. The stream's earlier work
 // is finished and dst holds the data on return.
 void d2h_sync(const Structure& s, void* dst, const void* src, size_t bytes, hipStream_t st);
+// Host-to-device copy from ordinary host memory through the same pinned staging buffer (the copy
+// engines read only memory the library owns); the copy is complete on return.
+void h2d_sync(const Structure& s, void* dst, const void* src, size_t bytes, hipStream_t st);
 
 struct KernelStat {
     const char* name;

@@ -624,7 +624,7 @@ void tune_tx(Structure& s, int prec, int ncol, int reps, double* ms, hipStream_t
                 state = state * 6364136223846793005ull + 1442695040888963407ull;
                 h[c * s.npad + i] = (double)(state >> 11) * (1.0 / 9007199254740992.0) - 0.5;
             }
-        WFQ_HIP(hipMemcpyAsync(X64, h.data(), h.size() * 8, hipMemcpyHostToDevice, st));
+        h2d_sync(s, X64, h.data(), h.size() * 8, st);
         WFQ_HIP(hipStreamSynchronize(st));
     }
     convert_from_f64(prec, X64, X, rows * s.npad, st);

@@ -171,7 +171,7 @@ struct Work {
     MsWork ms;
     // pinned host mirrors
     Buf<double> h_snorm, h_est, h_beta, h_invb;
-    Buf<int> h_sys[NSLOT], h_flags, h_ksteps;
+    Buf<int> h_sys[NSLOT], h_flags, h_ksteps, h_run;
     Buf<double2> h_g, h_alpha;
     Basis Vb, Xb, Ub;
 
@@ -260,6 +260,7 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.stage_im, (size_t)B * S.n);
     h.take(w.h_flags, B);
     h.take(w.h_ksteps, B);
+    h.take(w.h_run, B);
     h.take(w.h_est, B);
     h.take(w.h_beta, B);
     h.take(w.h_invb, B);
@@ -522,8 +523,8 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             zh[s] = ss[s].z;
             dh[s] = ss[s].dir;
         }
-        WFQ_HIP(hipMemcpyAsync(w.z.p, zh.data(), B * sizeof(double2), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(w.dir.p, dh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        h2d_sync(S, w.z.p, zh.data(), B * sizeof(double2), st);
+        h2d_sync(S, w.dir.p, dh.data(), B * sizeof(int), st);
         if (!warm) WFQ_HIP(hipMemsetAsync(w.X.p, 0, w.X.count * sizeof(double), st));
         WFQ_HIP(hipStreamSynchronize(st));
     }
@@ -566,7 +567,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                 active.push_back(s);
             }
         }
-        WFQ_HIP(hipMemcpyAsync(w.tol_abs.p, tol_h.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
+        h2d_sync(S, w.tol_abs.p, tol_h.data(), B * sizeof(double), st);
         WFQ_HIP(hipStreamSynchronize(st));
     }
     if (warm && !active.empty()) {
@@ -617,10 +618,10 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             for (int p = 0; p < 3; ++p)
                 if (!grp[p].empty()) upload(w, p, grp[p], st);
             upload(w, SLOT_STEP, stepping, st);
-            std::vector<int> runh(B, 0);
-            for (int s : stepping) runh[s] = 1;
-            WFQ_HIP(hipMemcpyAsync(w.run.p, runh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-            WFQ_HIP(hipStreamSynchronize(st));   // runh is a host temporary
+            std::fill(w.h_run.p, w.h_run.p + B, 0);
+            for (int s : stepping) w.h_run.p[s] = 1;
+            WFQ_HIP(hipMemcpyAsync(w.run.p, w.h_run.p, B * sizeof(int), hipMemcpyHostToDevice, st));
+            WFQ_HIP(hipStreamSynchronize(st));   // the pinned lists are rewritten by the next call
         };
         lists();
         std::vector<int> it0(B, 0);
@@ -836,11 +837,11 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
             dh[s] = ss[s].dir;
             zh[s] = ss[s].z;
         }
-        WFQ_HIP(hipMemcpyAsync(g, gh.data(), gh.size() * sizeof(double2), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(tol_abs, th.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(sdir, dh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(z, zh.data(), B * sizeof(double2), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(inv_h, invb.data(), nd * sizeof(double), hipMemcpyHostToDevice, st));
+        h2d_sync(S, g, gh.data(), gh.size() * sizeof(double2), st);
+        h2d_sync(S, tol_abs, th.data(), B * sizeof(double), st);
+        h2d_sync(S, sdir, dh.data(), B * sizeof(int), st);
+        h2d_sync(S, z, zh.data(), B * sizeof(double2), st);
+        h2d_sync(S, inv_h, invb.data(), nd * sizeof(double), st);
         WFQ_HIP(hipStreamSynchronize(st));
     }
     std::vector<int> stepping;
@@ -862,12 +863,12 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
             if (used[d]) h_dirs[na++] = d;
         ns = (int)stepping.size();
         std::memcpy(h_sys, stepping.data(), ns * sizeof(int));
-        std::vector<int> runh(B, 0);
-        for (int s : stepping) runh[s] = 1;
+        std::fill(w.h_run.p, w.h_run.p + B, 0);
+        for (int s : stepping) w.h_run.p[s] = 1;
         WFQ_HIP(hipMemcpyAsync(dirs, h_dirs, na * sizeof(int), hipMemcpyHostToDevice, st));
         WFQ_HIP(hipMemcpyAsync(sys, h_sys, ns * sizeof(int), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(run, runh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipStreamSynchronize(st));   // runh is a host temporary
+        WFQ_HIP(hipMemcpyAsync(run, w.h_run.p, B * sizeof(int), hipMemcpyHostToDevice, st));
+        WFQ_HIP(hipStreamSynchronize(st));   // the pinned lists are rewritten by the next call
     };
     if (!stepping.empty()) lists();
     GraphCache* gc = tm.on() ? nullptr : graphs;
@@ -942,8 +943,8 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     const int ngrp = (int)gd.size();
     if (gs.size() > q.grp_sys.count || gd.size() > q.grp_dir.count)
         throw Error{WFQ_EDEVICE, "multi-shift system groups exceed their work space"};
-    WFQ_HIP(hipMemcpyAsync(grp_sys, gs.data(), gs.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    WFQ_HIP(hipMemcpyAsync(grp_dir, gd.data(), gd.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    h2d_sync(S, grp_sys, gs.data(), gs.size() * sizeof(int), st);
+    h2d_sync(S, grp_dir, gd.data(), gd.size() * sizeof(int), st);
     tm.begin(st);
     if (!withk.empty()) {
         std::memcpy(h_sys, withk.data(), withk.size() * sizeof(int));
@@ -980,8 +981,8 @@ void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double to
             zh[s] = ss[s].z;
             dh[s] = ss[s].dir;
         }
-        WFQ_HIP(hipMemcpyAsync(w.z.p, zh.data(), B * sizeof(double2), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(w.dir.p, dh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        h2d_sync(S, w.z.p, zh.data(), B * sizeof(double2), st);
+        h2d_sync(S, w.dir.p, dh.data(), B * sizeof(int), st);
         WFQ_HIP(hipMemsetAsync(w.V.p, 0, w.V.count * sizeof(double), st));
     }
     std::vector<int> all(B);
@@ -1016,8 +1017,8 @@ void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double to
             t2[s] = ss[s].beta * ss[s].beta;
             ss[s].cycles += 1;
         }
-        WFQ_HIP(hipMemcpyAsync(w.tau2.p, t2.data(), B * sizeof(double), hipMemcpyHostToDevice, st));
-        WFQ_HIP(hipMemcpyAsync(w.first.p, fh.data(), B * sizeof(int), hipMemcpyHostToDevice, st));
+        h2d_sync(S, w.tau2.p, t2.data(), B * sizeof(double), st);
+        h2d_sync(S, w.first.p, fh.data(), B * sizeof(int), st);
         qmr_restart(w.sys[SLOT_ACT].p, na, Q, st);
         WFQ_HIP(hipStreamSynchronize(st));
         double2* rho_new = w.rho_a.p;
@@ -1252,7 +1253,7 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
     clear_work(w, st);
     if (!o.graphs || !st) graphs = nullptr;
     // right-hand sides b_k = E0 L r_k (shared by every frequency)
-    WFQ_HIP(hipMemcpyAsync(w.d_dirs.p, dirs, 3 * n_dir * sizeof(double), hipMemcpyHostToDevice, st));
+    h2d_sync(S, w.d_dirs.p, dirs, 3 * n_dir * sizeof(double), st);
     build_rhs(S, w.d_dirs.p, n_dir, E0, w.b.p, S.npad, st);
     WFQ_HIP(hipStreamSynchronize(st));
     Timer tm(stats != nullptr);
@@ -1278,10 +1279,10 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
             warm_lists(wp, ss);
             const int nt = (int)wp.tgt.size();
             if (nt > 0) {
-                WFQ_HIP(hipMemcpyAsync(w.warm_sys.p, wp.tgt.data(), nt * sizeof(int), hipMemcpyHostToDevice, st));
-                WFQ_HIP(hipMemcpyAsync(w.warm_a.p, wp.a.data(), nt * sizeof(int), hipMemcpyHostToDevice, st));
-                WFQ_HIP(hipMemcpyAsync(w.warm_b.p, wp.b.data(), nt * sizeof(int), hipMemcpyHostToDevice, st));
-                WFQ_HIP(hipMemcpyAsync(w.warm_t.p, wp.t.data(), nt * sizeof(double2), hipMemcpyHostToDevice, st));
+                h2d_sync(S, w.warm_sys.p, wp.tgt.data(), nt * sizeof(int), st);
+                h2d_sync(S, w.warm_a.p, wp.a.data(), nt * sizeof(int), st);
+                h2d_sync(S, w.warm_b.p, wp.b.data(), nt * sizeof(int), st);
+                h2d_sync(S, w.warm_t.p, wp.t.data(), nt * sizeof(double2), st);
                 interp_start(w.warm_sys.p, nt, w.warm_a.p, w.warm_b.p, w.warm_t.p, w.Xb, S.n, st);
                 WFQ_HIP(hipStreamSynchronize(st));
             }
@@ -1352,15 +1353,13 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
         }
         if (out.alpha_re) {
             if (out.on_device)
-                WFQ_HIP(hipMemcpyAsync(out.alpha_re + (size_t)s0 * 3, are.data(), nb * 3 * 8, hipMemcpyHostToDevice,
-                                       st));
+                h2d_sync(S, out.alpha_re + (size_t)s0 * 3, are.data(), nb * 3 * 8, st);
             else
                 std::memcpy(out.alpha_re + (size_t)s0 * 3, are.data(), nb * 3 * 8);
         }
         if (out.alpha_im) {
             if (out.on_device)
-                WFQ_HIP(hipMemcpyAsync(out.alpha_im + (size_t)s0 * 3, aim.data(), nb * 3 * 8, hipMemcpyHostToDevice,
-                                       st));
+                h2d_sync(S, out.alpha_im + (size_t)s0 * 3, aim.data(), nb * 3 * 8, st);
             else
                 std::memcpy(out.alpha_im + (size_t)s0 * 3, aim.data(), nb * 3 * 8);
         }

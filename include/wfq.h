@@ -132,9 +132,11 @@ typedef struct {
                             (spatially sorted) order, so GMRES runs on (L T + z_s I) M_s^-1 and minimises
                             the true residual (a project extension; the paper runs its solvers
                             unpreconditioned). Each block is inverted once per solve in FP64 (Gauss-Jordan,
-                            partial pivoting); every system then holds N x 64 complex doubles (1 KiB per
-                            atom) and each inner step reads them once. The block products keep the chosen
-                            precision. Needs the stored FP64 T (WFQ_EINVAL otherwise, and with another
+                            partial pivoting) and kept in complex FP32: every system holds N x 64 entries
+                            (512 bytes per atom) and each inner step reads them once. The rounded inverse
+                            is the preconditioner on both sides, so the solution is unchanged. The block
+                            products keep the chosen precision. A singular block gives NaN and the
+                            system ends with WFQ_ENUMERIC. Needs the stored FP64 T (WFQ_EINVAL otherwise, and with another
                             algorithm or with warm_start). */
 } wfq_solve_opts;
 

@@ -96,6 +96,20 @@ def test_block_product(lib, handle, tube, prec, ncol):
     assert np.all(np.abs(Y - ref) <= 2 * P.n * u_acc * bound + 1e-300)
 
 
+def test_block_product_larger_than_staging_chunk(lib, handle, tube):
+    # 3500 columns: X and Y are 35.8 MB each, more than the 32 MiB pinned staging chunk through which
+    # host arrays are copied, so both copy directions take more than one chunk
+    _, P = tube
+    rng = np.random.default_rng(77)
+    X = rng.standard_normal((3500, P.n))
+    Y = lib.wfq_apply_T(handle, "fp64", X)
+    ref = X @ P.T
+    bound = np.abs(X) @ np.abs(P.T)
+    # element by element within the accumulation bound: a chunk copied to a wrong offset (or not at
+    # all) would put whole rows of Y far outside it
+    assert np.all(np.abs(Y - ref) <= 2 * P.n * UNIT["fp64"] * bound + 1e-300)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
 def test_every_block_product_variant(lib, handle, tube, prec):
     # each shape the autotuner may choose, at ragged widths (partial column tiles, split k parts)

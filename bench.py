@@ -75,6 +75,25 @@ def cores_used():
         return os.cpu_count() or 1
 
 
+def host_info():
+    """The host the CPU baseline ran on: CPU model, logical CPUs and memory."""
+    model, mem_gb = "unknown", None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    mem_gb = round(int(line.split()[1]) / 2 ** 20, 1)
+                    break
+    except OSError:
+        pass
+    return dict(cpu_model=model, nproc=os.cpu_count(), mem_gb=mem_gb)
+
+
 def cpu_baseline(wl, sys_index):
     """The oracle as it stands: FP64 restarted GMRES on one system of the workload (host cores)."""
     from oracle import wfq_oracle as O
@@ -85,7 +104,7 @@ def cpu_baseline(wl, sys_index):
     t0 = time.perf_counter()
     x, info = P.solve_gmres(wl.omegas_eV[a], wl.dirs[k], wl.restart, wl.tol)
     t_solve = time.perf_counter() - t0
-    return dict(value=1.0 / t_solve, unit="solves/s", cores=cores_used(), kind="oracle",
+    return dict(value=1.0 / t_solve, unit="solves/s", cores=cores_used(), kind="oracle", host=host_info(),
                 sample=f"1 of {wl.n_systems} systems (omega={wl.omegas_eV[a]:.4f} eV, dir {k}), FP64 GMRES"
                        f"({wl.restart}) to {wl.tol:g}; solve {t_solve:.1f} s ({info['iters']} iterations), "
                        f"matrix build {t_build:.1f} s not included",
@@ -104,7 +123,7 @@ def cpu_baseline_matrix_free(wl, iters_per_solve, n_rows=256):
         O.coulomb_rows(xyz, eta, rows[s:s + 16]) @ x
     t = time.perf_counter() - t0
     per_product = t / n_rows * len(xyz) * 2          # 2 real columns per complex system
-    return dict(value=1.0 / (per_product * iters_per_solve), unit="solves/s", cores=cores_used(), kind="oracle",
+    return dict(value=1.0 / (per_product * iters_per_solve), unit="solves/s", cores=cores_used(), kind="oracle", host=host_info(),
                 sample=f"{n_rows} rows of the matrix-free T x ({n_rows * len(xyz):.3g} pairs, {t:.1f} s); "
                        f"extrapolated to one system = {iters_per_solve:.0f} products of 2 real columns "
                        f"(the GPU's mean iteration count); L and vector work ignored",
@@ -426,7 +445,7 @@ def bench_latency(args, wl, wfq, torch):
                             tol=wl.tol, description=wl.description),
                 p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                 iters=out["info"][0]["iters"], relres=out["info"][0]["relres"], block_jacobi=bj,
-                cpu_baseline=dict(value=1.0 / t_gm, unit="solves/s", cores=cores_used(), kind="oracle",
+                cpu_baseline=dict(value=1.0 / t_gm, unit="solves/s", cores=cores_used(), kind="oracle", host=host_info(),
                                   sample=f"the same system: FP64 GMRES({wl.restart}) {t_gm * 1e3:.1f} ms "
                                          f"({info['iters']} iterations); dense LU {t_lu * 1e3:.1f} ms"))
     h.close()

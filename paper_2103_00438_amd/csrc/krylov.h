@@ -33,6 +33,13 @@ void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, co
                 const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st, bool y_by_sys = false,
                 const Basis* shift_src = nullptr);
 
+// As spmm_shift (list positions, no y_by_sys), first interleaving the two planes of each system's
+// product into Yp (nsys x ld pairs, same element type as Y) so that the sparse product gathers both
+// with one load; falls back to spmm_shift where the neighbour lists are too long for 64-row blocks.
+void spmm_shift_pairs(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, void* Yp, const int* sys,
+                      int nsys, const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st,
+                      const Basis* shift_src = nullptr);
+
 // h[s][i] = sum_wc partial[s][i][wc] for i <= j (skipping systems with active[s] == 0)
 void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
                  hipStream_t st, const int* active = nullptr);

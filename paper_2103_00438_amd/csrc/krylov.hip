@@ -95,7 +95,25 @@ __global__ void __launch_bounds__(256) spmm_kernel(int64_t n, int64_t npad, int 
 // The neighbour window of each Y plane is then gathered by the work-groups of neighbouring row
 // blocks at about the same time: row blocks are laid out so that the work-groups of one XCD (ids
 // congruent mod 8) own one contiguous run of rows, and that XCD's L2 serves the overlapping windows.
-template <typename YE, int R>
+template <typename YE> struct Pair2;
+template <> struct Pair2<float> { using type = float2; };
+template <> struct Pair2<double> { using type = double2; };
+
+// Yp[k][i] = (Y[2k][i], Y[2k+1][i]): the real and imaginary planes of each system's product side
+// by side, so that the SpMM fetches both with one load per neighbour
+template <typename YE>
+__global__ void __launch_bounds__(256) pair_kernel(const YE* __restrict__ Y, int64_t ld,
+                                                   typename Pair2<YE>::type* __restrict__ Yp) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;   // grid: ld / 256 blocks (ld % 256 == 0)
+    const int64_t k = blockIdx.y;
+    typename Pair2<YE>::type v;
+    v.x = Y[(2 * k) * ld + i];
+    v.y = Y[(2 * k + 1) * ld + i];
+    Yp[k * ld + i] = v;
+}
+
+// PAIRS: Y is the interleaved form (row k = ld pairs) instead of two planes per system
+template <typename YE, int R, bool PAIRS = false>
 __global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad, int w,
                                                         const int32_t* __restrict__ ecol,
                                                         const double* __restrict__ eval, const YE* __restrict__ Y,
@@ -124,15 +142,28 @@ __global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad,
     if (i >= n) return;
     const int k_end = min(nsys, (int)(blockIdx.y + 1) * per_group);
     for (int k = (int)blockIdx.y * per_group + wave * G + g; k < k_end; k += 4 * G) {
-        const YE* yr = Y + (int64_t)(2 * (y_by_sys ? sys[k] : k)) * ld;
-        const YE* yi = yr + ld;
         double ar = 0.0, ai = 0.0;
+        if constexpr (PAIRS) {
+            const typename Pair2<YE>::type* yp =
+                reinterpret_cast<const typename Pair2<YE>::type*>(Y) + (int64_t)(y_by_sys ? sys[k] : k) * ld;
 #pragma unroll 4
-        for (int e = 0; e < w; ++e) {
-            const int c = lcol[e * R + r];
-            const double v = lval[e * R + r];
-            ar += v * widen(yr[c]);
-            ai += v * widen(yi[c]);
+            for (int e = 0; e < w; ++e) {
+                const int c = lcol[e * R + r];
+                const double v = lval[e * R + r];
+                const typename Pair2<YE>::type y = yp[c];
+                ar += v * widen(y.x);
+                ai += v * widen(y.y);
+            }
+        } else {
+            const YE* yr = Y + (int64_t)(2 * (y_by_sys ? sys[k] : k)) * ld;
+            const YE* yi = yr + ld;
+#pragma unroll 4
+            for (int e = 0; e < w; ++e) {
+                const int c = lcol[e * R + r];
+                const double v = lval[e * R + r];
+                ar += v * widen(yr[c]);
+                ai += v * widen(yi[c]);
+            }
         }
         const int s = sys[k];
         const double* sr = vre(Vs, s, jsrc);
@@ -144,7 +175,7 @@ __global__ void __launch_bounds__(256) spmm_rows_kernel(int64_t n, int64_t npad,
     }
 }
 
-template <typename YE, int R>
+template <typename YE, int R, bool PAIRS = false>
 void launch_spmm_rows(const Structure& S, const YE* Y, int64_t ld, const int* sys, int nsys, const double2* z,
                       const Basis& Vs, const Basis& V, int jsrc, int jdst, bool y_by_sys, hipStream_t st) {
     constexpr int G = 64 / R;
@@ -155,7 +186,7 @@ void launch_spmm_rows(const Structure& S, const YE* Y, int64_t ld, const int* sy
     const int gy = (int)std::max<int64_t>(1, std::min<int64_t>(want, (nsys + 4 * G - 1) / (4 * G)));
     const int per_group = (nsys + gy - 1) / gy;
     const size_t lds = (size_t)S.ell_w * R * 12;
-    hipLaunchKernelGGL((spmm_rows_kernel<YE, R>), dim3((unsigned)nb8, (unsigned)gy), dim3(256), lds, st, S.n, S.npad,
+    hipLaunchKernelGGL((spmm_rows_kernel<YE, R, PAIRS>), dim3((unsigned)nb8, (unsigned)gy), dim3(256), lds, st, S.n, S.npad,
                        S.ell_w, S.ell_col, S.ell_val, Y, ld, sys, nsys, per_group, z, Vs, V, jsrc, jdst,
                        (int)y_by_sys);
 }
@@ -419,6 +450,33 @@ void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, co
     else
         hipLaunchKernelGGL((spmm_kernel<float, NS>), grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col,
                            S.ell_val, static_cast<const float*>(Y), ld, sys, nsys, z, Vs, V, jsrc, jdst);
+    WFQ_CHECK_LAUNCH();
+}
+
+void spmm_shift_pairs(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, void* Yp, const int* sys,
+                      int nsys, const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st,
+                      const Basis* shift_src) {
+    if (nsys <= 0) return;
+    const size_t per_row = (size_t)S.ell_w * 12;
+    if (per_row * 64 > 40960 || ld != S.npad) {   // only the 64-row form reads pairs
+        spmm_shift(S, y_is_f64, Y, ld, sys, nsys, z, V, jsrc, jdst, st, false, shift_src);
+        return;
+    }
+    const Basis& Vs = shift_src ? *shift_src : V;
+    dim3 pg((unsigned)(ld / 256), (unsigned)nsys);
+    if (y_is_f64) {
+        hipLaunchKernelGGL(pair_kernel<double>, pg, dim3(256), 0, st, static_cast<const double*>(Y), ld,
+                           static_cast<double2*>(Yp));
+        WFQ_CHECK_LAUNCH();
+        launch_spmm_rows<double, 64, true>(S, static_cast<const double*>(Yp), ld, sys, nsys, z, Vs, V, jsrc, jdst,
+                                           false, st);
+    } else {
+        hipLaunchKernelGGL(pair_kernel<float>, pg, dim3(256), 0, st, static_cast<const float*>(Y), ld,
+                           static_cast<float2*>(Yp));
+        WFQ_CHECK_LAUNCH();
+        launch_spmm_rows<float, 64, true>(S, static_cast<const float*>(Yp), ld, sys, nsys, z, Vs, V, jsrc, jdst,
+                                          false, st);
+    }
     WFQ_CHECK_LAUNCH();
 }
 

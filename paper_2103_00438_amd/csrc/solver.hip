@@ -123,6 +123,10 @@ bool needs_escalation(double beta, double beta_prev, double est_end) {
 
 enum Slot { SLOT_G0 = 0, SLOT_G1 = 1, SLOT_G2 = 2, SLOT_STEP = 3, SLOT_ACT = 4, NSLOT = 5 };
 
+// structures above this padded size interleave the products' planes before the SpMM (an extra pass
+// over Y that pays where the sparse product is bound by its gathers, not by launch latency)
+constexpr int64_t kPairsFrom = 8192;
+
 // What a solve's work space depends on: a solve with the same shape reuses it.
 struct WorkShape {
     int B = 0, m = 0, n_dir = 0, prec = 0, ms_m = 0;   // ms_m: shared-basis dimension (0: no multi-shift)
@@ -152,7 +156,8 @@ struct Work {
     int64_t n = 0, npad = 0, nwc = 0, nblk = 0, mpad = 0;
     bool need32 = false, need16 = false;
     Buf<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, tol_abs, cond;
-    Buf<float> X32, Y32, Y16;
+    Buf<float> X32, Y32, Y16, Yp32;   // Yp*: the products' planes interleaved for the SpMM (large N)
+    Buf<double> Yp64;
     Buf<uint16_t> X16;
     Buf<double2> partial, h1, h2, R, Hu, sn, g, y, z, alpha, gam;
     Buf<double> nu, irho;
@@ -209,6 +214,9 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.Y32, w.need32 ? (size_t)w.mpad * np : 0);
     d.take(w.X16, w.need16 ? (size_t)w.mpad * np : 0);
     d.take(w.Y16, w.need16 ? (size_t)w.mpad * np : 0);
+    const bool pairs = np > kPairsFrom;
+    d.take(w.Yp64, pairs ? (size_t)w.mpad * np : 0);
+    d.take(w.Yp32, pairs && (w.need32 || w.need16) ? (size_t)w.mpad * np : 0);
     d.take(w.partial, (size_t)B * 2 * w.mdim * w.nwc);   // fused dots: two entries per basis vector
     d.take(w.h1, (size_t)B * 2 * w.mdim);
     d.take(w.h2, (size_t)B * w.mdim);
@@ -659,8 +667,13 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                         }
                         block_product(S, w, p, 2 * ng, tm, st);
                         tm.begin(st);
-                        spmm_shift(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, w.z.p, w.Vb,
-                                   bj ? 0 : k, k + 1, st, false, bj ? &w.Ub : nullptr);
+                        if (w.Yp64.p)
+                            spmm_shift_pairs(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad,
+                                             p == WFQ_PREC_FP64 ? (void*)w.Yp64.p : (void*)w.Yp32.p, w.sys[p].p,
+                                             ng, w.z.p, w.Vb, bj ? 0 : k, k + 1, st, bj ? &w.Ub : nullptr);
+                        else
+                            spmm_shift(S, p == WFQ_PREC_FP64, y_block(w, p), w.npad, w.sys[p].p, ng, w.z.p, w.Vb,
+                                       bj ? 0 : k, k + 1, st, false, bj ? &w.Ub : nullptr);
                         tm.end(st, KC_SPMM, 4.0 * S.nnz * ng + 8 * n * ng,
                                12.0 * S.nnz + ng * n * (2.0 * out_size(p) + 16 + 16));
                     }
@@ -1203,6 +1216,7 @@ uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_d
     b += mpad * np * 16;                        // FP64 block in/out
     if (o.precision == WFQ_PREC_FP32 || o.precision == WFQ_PREC_BF16) b += mpad * np * 8;
     if (o.precision == WFQ_PREC_BF16) b += mpad * np * 6;
+    if ((int64_t)np > kPairsFrom) b += mpad * np * (o.precision == WFQ_PREC_FP64 ? 8 : 12);   // interleaved planes
     const uint64_t nwc = wave_chunks(S.n);
     b += (uint64_t)B * 2 * mdim * nwc * 16;     // fused dot partials (two entries per basis vector)
     b += (uint64_t)B * 2 * mdim * mdim * 16;    // R and the Hessenberg matrix before rotations

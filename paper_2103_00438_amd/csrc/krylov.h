@@ -35,7 +35,7 @@ void spmm_shift(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, co
 
 // As spmm_shift (list positions, no y_by_sys), first interleaving the two planes of each system's
 // product into Yp (nsys x ld pairs, same element type as Y) so that the sparse product gathers both
-// with one load; falls back to spmm_shift where the neighbour lists are too long for 64-row blocks.
+// with one load; falls back to spmm_shift where the neighbour lists are too long for row blocks.
 void spmm_shift_pairs(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, void* Yp, const int* sys,
                       int nsys, const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st,
                       const Basis* shift_src = nullptr);

@@ -457,8 +457,11 @@ void spmm_shift_pairs(const Structure& S, bool y_is_f64, const void* Y, int64_t 
                       int nsys, const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st,
                       const Basis* shift_src) {
     if (nsys <= 0) return;
+    // the row block of spmm_shift; the per-thread form (R = 0) reads the two planes
     const size_t per_row = (size_t)S.ell_w * 12;
-    if (per_row * 64 > 40960 || ld != S.npad) {   // only the 64-row form reads pairs
+    const int R = per_row * 64 <= 40960 ? 64 : per_row * 32 <= 40960 ? 32 : per_row * 16 <= 40960 ? 16
+                  : per_row * 8 <= 40960 ? 8 : 0;
+    if (R == 0 || ld != S.npad) {
         spmm_shift(S, y_is_f64, Y, ld, sys, nsys, z, V, jsrc, jdst, st, false, shift_src);
         return;
     }
@@ -468,14 +471,20 @@ void spmm_shift_pairs(const Structure& S, bool y_is_f64, const void* Y, int64_t 
         hipLaunchKernelGGL(pair_kernel<double>, pg, dim3(256), 0, st, static_cast<const double*>(Y), ld,
                            static_cast<double2*>(Yp));
         WFQ_CHECK_LAUNCH();
-        launch_spmm_rows<double, 64, true>(S, static_cast<const double*>(Yp), ld, sys, nsys, z, Vs, V, jsrc, jdst,
-                                           false, st);
+        const double* P = static_cast<const double*>(Yp);
+        if (R == 64) launch_spmm_rows<double, 64, true>(S, P, ld, sys, nsys, z, Vs, V, jsrc, jdst, false, st);
+        else if (R == 32) launch_spmm_rows<double, 32, true>(S, P, ld, sys, nsys, z, Vs, V, jsrc, jdst, false, st);
+        else if (R == 16) launch_spmm_rows<double, 16, true>(S, P, ld, sys, nsys, z, Vs, V, jsrc, jdst, false, st);
+        else launch_spmm_rows<double, 8, true>(S, P, ld, sys, nsys, z, Vs, V, jsrc, jdst, false, st);
     } else {
         hipLaunchKernelGGL(pair_kernel<float>, pg, dim3(256), 0, st, static_cast<const float*>(Y), ld,
                            static_cast<float2*>(Yp));
         WFQ_CHECK_LAUNCH();
-        launch_spmm_rows<float, 64, true>(S, static_cast<const float*>(Yp), ld, sys, nsys, z, Vs, V, jsrc, jdst,
-                                          false, st);
+        const float* P = static_cast<const float*>(Yp);
+        if (R == 64) launch_spmm_rows<float, 64, true>(S, P, ld, sys, nsys, z, Vs, V, jsrc, jdst, false, st);
+        else if (R == 32) launch_spmm_rows<float, 32, true>(S, P, ld, sys, nsys, z, Vs, V, jsrc, jdst, false, st);
+        else if (R == 16) launch_spmm_rows<float, 16, true>(S, P, ld, sys, nsys, z, Vs, V, jsrc, jdst, false, st);
+        else launch_spmm_rows<float, 8, true>(S, P, ld, sys, nsys, z, Vs, V, jsrc, jdst, false, st);
     }
     WFQ_CHECK_LAUNCH();
 }

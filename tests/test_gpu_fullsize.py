@@ -88,6 +88,29 @@ def test_sheet1m_subwindow_solve(lib):
             assert np.linalg.norm(out["q"][a, k] - ref) / np.linalg.norm(ref) <= 1e-6
 
 
+def test_fcc_sphere_long_neighbour_lists_interleaved_spmm(lib):
+    # a 9 500-atom sphere: above the size where the SpMM reads interleaved planes, with ~320
+    # neighbours per row (8-row blocks); checked by the oracle's FP64 residual on sampled rows
+    wl = wi.workloads.FCC_METAL
+    xyz = geo.jitter(geo.fcc_sphere(34.0), 0.02, 34)
+    assert len(xyz) > 8192
+    h = lib.wfq_build(xyz, wl)
+    om = np.array([2.0, 3.5])
+    dirs = np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    tol = 1e-8
+    out = lib.wfq_solve(h, om, dirs, tol, restart=100, precision="fp32")
+    h.close()
+    assert out["status"] == 0
+    assert max(r["relres"] for r in out["info"]) <= tol
+    P = O.Problem(xyz, wl, dense_T=False)
+    rows = sampled_rows(len(xyz), 48, 9)
+    for a in range(2):
+        for k in range(2):
+            b = P.rhs(dirs[k])
+            r = P.residual_rows(om[a], dirs[k], out["q"][a, k], rows)
+            assert np.max(np.abs(r)) <= tol * np.linalg.norm(b), (a, k)
+
+
 @pytest.mark.parametrize("algorithm", ["gmres", "qmr"])
 def test_fcc_subsphere_bf16(lib, algorithm):
     # a 2000-atom sphere cut from the same lattice and jitter recipe as the 120k-atom workload

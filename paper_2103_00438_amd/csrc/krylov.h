@@ -40,6 +40,11 @@ void spmm_shift_pairs(const Structure& S, bool y_is_f64, const void* Y, int64_t 
                       int nsys, const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st,
                       const Basis* shift_src = nullptr);
 
+// V(s, jdst) = L Y_s + z_s V(s, jsrc) for the nsys listed systems, with Y already interleaved and
+// addressed by system id: Yp[s][i] = (re, im) pairs, ld pairs per system (FP64).
+void spmm_shift_interleaved(const Structure& S, const double* Yp, int64_t ld, const int* sys, int nsys,
+                            const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st);
+
 // h[s][i] = sum_wc partial[s][i][wc] for i <= j (skipping systems with active[s] == 0)
 void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
                  hipStream_t st, const int* active = nullptr);
@@ -112,7 +117,7 @@ constexpr int kQmrSlots = 7;
 void qmr_rho(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const Basis& Q, int64_t n,
              double2* partial, int nblk, hipStream_t st);
 // beta = rho_new / rho_old (0 where first[s]); p = r + beta p; T p = T r + beta T p
-// (T p is also written to tpb[2s, 2s+1] (FP64, leading dimension ld), the gather source of qmr_q)
+// (T p is also written to tpb as (re, im) pairs, ld pairs per system id (FP64), the gather source of qmr_q)
 void qmr_dirs(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys, const Basis& Q, int64_t n,
               const double2* rho_new, const double2* rho_old, const int* first, double* tpb, hipStream_t st);
 // q = L (T p) + z p with partials of sigma = (T p)^T q and of ||T p||^2, ||q||^2

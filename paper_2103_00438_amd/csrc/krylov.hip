@@ -489,6 +489,20 @@ void spmm_shift_pairs(const Structure& S, bool y_is_f64, const void* Y, int64_t 
     WFQ_CHECK_LAUNCH();
 }
 
+void spmm_shift_interleaved(const Structure& S, const double* Yp, int64_t ld, const int* sys, int nsys,
+                            const double2* z, const Basis& V, int jsrc, int jdst, hipStream_t st) {
+    if (nsys <= 0) return;
+    const size_t per_row = (size_t)S.ell_w * 12;
+    const int R = per_row * 64 <= 40960 ? 64 : per_row * 32 <= 40960 ? 32 : per_row * 16 <= 40960 ? 16
+                  : per_row * 8 <= 40960 ? 8 : 0;
+    if (R == 0) throw Error{WFQ_EINVAL, "neighbour lists too long for the sparse product"};
+    if (R == 64) launch_spmm_rows<double, 64, true>(S, Yp, ld, sys, nsys, z, V, V, jsrc, jdst, true, st);
+    else if (R == 32) launch_spmm_rows<double, 32, true>(S, Yp, ld, sys, nsys, z, V, V, jsrc, jdst, true, st);
+    else if (R == 16) launch_spmm_rows<double, 16, true>(S, Yp, ld, sys, nsys, z, V, V, jsrc, jdst, true, st);
+    else launch_spmm_rows<double, 8, true>(S, Yp, ld, sys, nsys, z, V, V, jsrc, jdst, true, st);
+    WFQ_CHECK_LAUNCH();
+}
+
 void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* partial, int mdim, double2* h,
                  hipStream_t st, const int* active) {
     if (nsys <= 0) return;

@@ -79,8 +79,7 @@ __global__ void __launch_bounds__(256) dirs_kernel(const YE* __restrict__ Y, int
     const double nr = tr + br * qr - bi * qi, ni = ti + br * qi + bi * qr;
     tp[i] = nr;
     tp[i + o] = ni;
-    tpb[(int64_t)(2 * s) * ld + i] = nr;
-    tpb[(int64_t)(2 * s + 1) * ld + i] = ni;
+    reinterpret_cast<double2*>(tpb)[(int64_t)s * ld + i] = make_double2(nr, ni);   // interleaved for the SpMM
 }
 
 // partial sums over 256-row blocks of sigma = (T p)^T q, ||T p||^2 and ||q||^2
@@ -262,8 +261,9 @@ void qmr_dirs(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys
 void qmr_q(const Structure& S, const int* sys, int nsys, const Basis& Q, const double2* z, const double* tpb,
            double2* part_sig, double2* part_nrm, int nblk, hipStream_t st) {
     if (nsys <= 0) return;
-    // q (slot 3) = L (T p) + z p (slot 1), gathering T p from the compact block written by qmr_dirs
-    spmm_shift(S, true, tpb, S.npad, sys, nsys, z, Q, 1, 3, st, true);
+    // q (slot 3) = L (T p) + z p (slot 1), gathering T p from the compact interleaved block that
+    // qmr_dirs wrote (one pair of doubles per atom and system)
+    spmm_shift_interleaved(S, tpb, S.npad, sys, nsys, z, Q, 1, 3, st);
     dim3 grd((unsigned)nblk, (unsigned)nsys);
     hipLaunchKernelGGL(q_sums_kernel, grd, dim3(256), 0, st, S.n, sys, Q, part_sig, part_nrm, nblk);
     WFQ_CHECK_LAUNCH();

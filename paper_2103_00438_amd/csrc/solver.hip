@@ -176,6 +176,9 @@ struct Work {
     MsWork ms;
     // pinned host mirrors
     Buf<double> h_snorm, h_est, h_beta, h_invb;
+    // est (B doubles), flags and ksteps (B ints each) side by side on the device and in the pinned
+    // mirror, so that the per-step read-back is one copy
+    Buf<double> step_dev, step_host;
     Buf<int> h_sys[NSLOT], h_flags, h_ksteps, h_run;
     Buf<double2> h_g, h_alpha;
     Basis Vb, Xb, Ub;
@@ -231,15 +234,16 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.y, (size_t)B * w.mdim);
     d.take(w.z, B);
     d.take(w.alpha, (size_t)B * 3);
-    d.take(w.est, B);
+    d.take(w.step_dev, (size_t)2 * B);
+    w.est = Buf<double>{w.step_dev.p, (size_t)B};
     d.take(w.inv_h, B);
     d.take(w.inv_beta, B);
     d.take(w.beta, B);
     d.take(w.norm2, (size_t)B * std::max(w.nwc, w.nblk));
     d.take(w.tol_abs, B);
     d.take(w.cond, B);
-    d.take(w.flags, B);
-    d.take(w.ksteps, B);
+    w.flags = Buf<int>{w.step_dev.p ? reinterpret_cast<int*>(w.step_dev.p + B) : nullptr, (size_t)B};
+    w.ksteps = Buf<int>{w.step_dev.p ? reinterpret_cast<int*>(w.step_dev.p + B) + B : nullptr, (size_t)B};
     d.take(w.run, B);
     d.take(w.dir, B);
     for (int k = 0; k < NSLOT; ++k) {
@@ -266,10 +270,11 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.bj_U, sh.bj ? (size_t)B * 2 * np : 0);
     d.take(w.stage_re, (size_t)B * S.n);   // host outputs are staged through these
     d.take(w.stage_im, (size_t)B * S.n);
-    h.take(w.h_flags, B);
-    h.take(w.h_ksteps, B);
+    h.take(w.step_host, (size_t)2 * B);
+    w.h_est = Buf<double>{w.step_host.p, (size_t)B};
+    w.h_flags = Buf<int>{w.step_host.p ? reinterpret_cast<int*>(w.step_host.p + B) : nullptr, (size_t)B};
+    w.h_ksteps = Buf<int>{w.step_host.p ? reinterpret_cast<int*>(w.step_host.p + B) + B : nullptr, (size_t)B};
     h.take(w.h_run, B);
-    h.take(w.h_est, B);
     h.take(w.h_beta, B);
     h.take(w.h_invb, B);
     h.take(w.h_snorm, B);
@@ -698,9 +703,10 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                 for (int k = k0; k < k0 + c; ++k) step(k);
             });
             k0 += c;
-            WFQ_HIP(hipMemcpyAsync(w.h_flags.p, w.flags.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
-            WFQ_HIP(hipMemcpyAsync(w.h_est.p, w.est.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
-            WFQ_HIP(hipMemcpyAsync(w.h_ksteps.p, w.ksteps.p, B * sizeof(int), hipMemcpyDeviceToHost, st));
+            // est, flags and ksteps: the whole region, laid out for the work space's batch size (a
+            // batch may hold fewer systems than that)
+            WFQ_HIP(hipMemcpyAsync(w.step_host.p, w.step_dev.p, w.step_dev.count * sizeof(double),
+                                   hipMemcpyDeviceToHost, st));
             WFQ_HIP(hipStreamSynchronize(st));
             std::vector<int> next;
             for (int s : stepping) {

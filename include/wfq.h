@@ -138,6 +138,11 @@ typedef struct {
                             products keep the chosen precision. A singular block gives NaN and the
                             system ends with WFQ_ENUMERIC. Needs the stored FP64 T (WFQ_EINVAL otherwise, and with another
                             algorithm or with warm_start). */
+    double  qmr_breakdown; /* QMR: a step breaks down (no look-ahead) when |sigma| <= qmr_breakdown ||T p|| ||q||,
+                            sigma = p^T T q the bilinear form of the step; 0 = 1e-14. Broken-down systems
+                            continue in GMRES from their QMR iterate (in groups that fit the budget left by
+                            the QMR work space; WFQ_EBREAKDOWN if none fits or GMRES does not converge).
+                            A large value forces the fallback (for tests of that path). */
 } wfq_solve_opts;
 
 typedef struct {
@@ -246,13 +251,17 @@ int wfq_kernel_stats(wfq_handle* h, int32_t* n_classes, const char** names, int6
 
 /* ------------------------------------------------------------------ serving
  * A request loop for spectrum jobs of different structures arriving over time. Each job is one
- * geometry + parameters + frequency list + field directions. Jobs are admitted while their device
- * footprint (T copies, L, Krylov bases) fits the budget and a slot is free; admitted jobs run on
- * their own streams and overlap on the device. Submission never blocks.
+ * geometry + parameters + frequency list + field directions. Jobs are admitted in arrival order
+ * while their device footprint (T copies, L, Krylov bases) fits the budget and a slot is free (a job
+ * is always admitted when nothing else is resident; a job whose footprint exceeds the whole budget
+ * ends with WFQ_ENOMEM); admitted jobs run on their own streams and overlap on the device.
+ * Submission never blocks. Every call is thread-safe; a ticket is retrieved (poll/wait returning a
+ * final status) once.
  */
 typedef struct {
     uint64_t device_budget;   /* bytes for all resident jobs; 0 = 90% of free memory */
-    int32_t  max_jobs;        /* concurrently resident jobs (slots), >= 1 */
+    int32_t  max_jobs;        /* concurrently resident jobs (slots), 1..64; wfq_serve starts one worker
+                                 thread per slot, wfq_serve_stop joins them */
     int32_t  max_queue;       /* waiting jobs before submit returns WFQ_EAGAIN, >= 1 */
     int32_t  device;          /* HIP device ordinal */
     wfq_solve_opts opts;      /* solver options applied to every job */

@@ -79,6 +79,7 @@ void check_opts(const wfq_solve_opts* o) {
         fail(WFQ_EINVAL, "unknown precision");
     if (!std::isfinite(o->E0) || o->E0 < 0.0) fail(WFQ_EINVAL, "E0 must be finite and >= 0");
     if (o->max_batch < 0) fail(WFQ_EINVAL, "max_batch must be >= 0");
+    if (!(o->qmr_breakdown >= 0.0)) fail(WFQ_EINVAL, "qmr_breakdown must be >= 0");
     if (o->warm_start && o->algorithm != WFQ_GMRES) fail(WFQ_EINVAL, "warm starts are a GMRES option");
     if (o->block_jacobi && o->algorithm != WFQ_GMRES)
         fail(WFQ_EINVAL, "block-Jacobi preconditioning is a GMRES option");

@@ -245,6 +245,31 @@ void free_structure(Structure& s) {
 
 namespace {
 
+// Device scratch of one build step: every buffer taken is freed by release() or, on an exception,
+// by the destructor (after the device work that may still use it has finished).
+struct ScratchDev {
+    std::vector<void*> bufs;
+    template <typename T>
+    T* take(int64_t count) {
+        void* p = nullptr;
+        const hipError_t e = hipMalloc(&p, std::max<int64_t>(count, 1) * sizeof(T));
+        if (e != hipSuccess) throw Error{WFQ_ENOMEM, std::string("hipMalloc of build scratch failed: ") + hipGetErrorString(e)};
+        bufs.push_back(p);
+        return static_cast<T*>(p);
+    }
+    void release() {
+        for (void* p : bufs) (void)hipFree(p);
+        bufs.clear();
+    }
+    ScratchDev() = default;
+    ScratchDev(const ScratchDev&) = delete;
+    ScratchDev& operator=(const ScratchDev&) = delete;
+    ~ScratchDev() {
+        if (!bufs.empty()) (void)hipDeviceSynchronize();
+        release();
+    }
+};
+
 // the structure's pinned staging buffer, at least min(bytes, 32 MiB) long; returns its length
 size_t pin_stage(const Structure& s, size_t bytes, hipStream_t st) {
     constexpr size_t kChunk = 32u << 20;
@@ -404,11 +429,13 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     }
 
     // ---- a1: neighbour search and CSR of L = P - Kbar
-    int32_t *d_start = nullptr, *d_count = nullptr, *d_counts = nullptr, *d_flag = nullptr;
-    WFQ_HIP(hipMalloc(&d_start, ncell * 4));
-    WFQ_HIP(hipMalloc(&d_count, ncell * 4));
-    WFQ_HIP(hipMalloc(&d_counts, n * 4));
-    WFQ_HIP(hipMalloc(&d_flag, 4));
+    // scratch of the search (cell table, per-row counts, the coincident-atom flag): freed on every
+    // path out of this block, the error paths included
+    ScratchDev scratch;
+    int32_t* d_start = scratch.take<int32_t>(ncell);
+    int32_t* d_count = scratch.take<int32_t>(ncell);
+    int32_t* d_counts = scratch.take<int32_t>(n);
+    int32_t* d_flag = scratch.take<int32_t>(1);
     h2d_sync(s, d_start, cell_start.data(), ncell * 4, st);
     h2d_sync(s, d_count, cell_count.data(), ncell * 4, st);
     WFQ_HIP(hipMemsetAsync(d_flag, 0, 4, st));
@@ -423,14 +450,12 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     WFQ_CHECK_LAUNCH();
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, n, d_counts, s.rowptr);
     WFQ_CHECK_LAUNCH();
+    // both scalars come back through the structure's pinned staging buffer (never a copy into
+    // pageable memory such as this thread's stack)
     int32_t nnz32 = 0, flag = 0;
-    WFQ_HIP(hipMemcpyAsync(&nnz32, s.rowptr + n, 4, hipMemcpyDeviceToHost, st));
-    WFQ_HIP(hipMemcpyAsync(&flag, d_flag, 4, hipMemcpyDeviceToHost, st));
-    WFQ_HIP(hipStreamSynchronize(st));
-    if (flag) {
-        (void)hipFree(d_start); (void)hipFree(d_count); (void)hipFree(d_counts); (void)hipFree(d_flag);
-        throw Error{WFQ_EINVAL, "two atoms are closer than 1e-6 Angstrom"};
-    }
+    d2h_sync(s, &nnz32, s.rowptr + n, 4, st);
+    d2h_sync(s, &flag, d_flag, 4, st);
+    if (flag) throw Error{WFQ_EINVAL, "two atoms are closer than 1e-6 Angstrom"};
     s.nnz = nnz32;
     s.col = dev_alloc<int32_t>(s, s.nnz);
     s.val = dev_alloc<double>(s, s.nnz);
@@ -467,10 +492,8 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     hipLaunchKernelGGL(ell_kernel, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, n, s.npad, s.ell_w, s.rowptr,
                        s.col, s.val, s.ell_col, s.ell_val);
     WFQ_CHECK_LAUNCH();
-    (void)hipFree(d_start);
-    (void)hipFree(d_count);
-    (void)hipFree(d_counts);
-    (void)hipFree(d_flag);
+    WFQ_HIP(hipStreamSynchronize(st));
+    scratch.release();
 
     // ---- a2: stored T copies
     uint32_t mask = p->store_mask ? p->store_mask : (WFQ_STORE_FP64 | WFQ_STORE_FP32);

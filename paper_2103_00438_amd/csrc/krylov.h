@@ -123,9 +123,9 @@ void qmr_dirs(bool y_is_f64, const void* Y, int64_t ld, const int* sys, int nsys
 // q = L (T p) + z p with partials of sigma = (T p)^T q and of ||T p||^2, ||q||^2
 void qmr_q(const Structure& S, const int* sys, int nsys, const Basis& Q, const double2* z, const double* tpb,
            double2* part_sig, double2* part_nrm, int nblk, hipStream_t st);
-// sigma[s] and breakdown flags (bit 3: Lanczos breakdown, bit 2: NaN)
+// sigma[s] and breakdown flags (bit 3: Lanczos breakdown when |sigma| <= thr ||T p|| ||q||, bit 2: NaN)
 void qmr_sigma(const int* sys, int nsys, const double2* part_sig, const double2* part_nrm, int nblk,
-               const double2* rho, double2* sigma, int* flags, hipStream_t st);
+               const double2* rho, double2* sigma, int* flags, double thr, hipStream_t st);
 // alpha = rho / sigma; x += alpha p; r -= alpha q; partials of ||r||^2
 void qmr_xr(const int* sys, int nsys, const Basis& Q, int64_t n, const double2* rho, const double2* sigma,
             double* norm2, int nblk, hipStream_t st);

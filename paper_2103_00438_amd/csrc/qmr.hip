@@ -141,7 +141,7 @@ __global__ void __launch_bounds__(256) xr_kernel(const int* __restrict__ sys, Ba
 // per system: sigma = sum of partials and the breakdown test (Lanczos breakdown: no look-ahead)
 __global__ void sigma_kernel(const int* __restrict__ sys, int nsys, const double2* __restrict__ part_sig,
                              const double2* __restrict__ part_nrm, int nblk, const double2* __restrict__ rho,
-                             double2* __restrict__ sigma, int* __restrict__ flags) {
+                             double2* __restrict__ sigma, int* __restrict__ flags, double thr) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nsys) return;
     const int s = sys[k];
@@ -156,7 +156,7 @@ __global__ void sigma_kernel(const int* __restrict__ sys, int nsys, const double
     sigma[s] = make_double2(sr, si);
     int f = 0;
     const double sabs = hypot(sr, si), rabs = hypot(rho[s].x, rho[s].y);
-    if (!(sabs > 1e-14 * sqrt(nt * nq)) || !(rabs > 0.0)) f |= 8;
+    if (!(sabs > thr * sqrt(nt * nq)) || !(rabs > 0.0)) f |= 8;
     if (!(sabs == sabs) || !(rabs == rabs)) f |= 4;
     flags[s] = f;
 }
@@ -270,10 +270,10 @@ void qmr_q(const Structure& S, const int* sys, int nsys, const Basis& Q, const d
 }
 
 void qmr_sigma(const int* sys, int nsys, const double2* part_sig, const double2* part_nrm, int nblk,
-               const double2* rho, double2* sigma, int* flags, hipStream_t st) {
+               const double2* rho, double2* sigma, int* flags, double thr, hipStream_t st) {
     if (nsys <= 0) return;
     hipLaunchKernelGGL(sigma_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, sys, nsys, part_sig, part_nrm, nblk, rho,
-                       sigma, flags);
+                       sigma, flags, thr);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -1,12 +1,13 @@
 // Request loop for spectrum jobs (one structure + frequency list + field directions each).
 //
-// Jobs wait in a FIFO queue and are admitted while a slot is free and their estimated device
-// footprint (stored T copies, L, Krylov work space) fits what the resident jobs leave of the budget.
-// Every admitted job runs on its own host thread and its own HIP stream: set-up, batched solve,
-// copy-out, release. Jobs that arrive while others run are admitted as soon as slots and memory
-// free up, so their work overlaps on the device. A job's arithmetic does not depend on what else is
-// resident (no cross-job reductions, fixed kernel choice per shape), so its result is the same alone
-// and in the mix.
+// Jobs wait in a FIFO queue. A fixed pool of max_jobs worker threads (started by wfq_serve, joined
+// by wfq_serve_stop) takes them: a free worker admits the job at the head of the queue as soon as
+// its estimated device footprint (stored T copies, L, Krylov work space) fits what the resident
+// jobs leave of the budget, then runs it on its own HIP stream: set-up, batched solve, copy-out,
+// release. Jobs that arrive while others run are admitted as soon as a worker and memory free up,
+// so their work overlaps on the device. A job's arithmetic does not depend on what else is
+// resident (no cross-job reductions, fixed kernel choice per shape), so its result is the same
+// alone and in the mix.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -25,6 +26,8 @@ using namespace wfq;
 namespace {
 
 using Clock = std::chrono::steady_clock;
+
+constexpr int kMaxWorkers = 64;   // upper limit of max_jobs (one worker thread per slot)
 
 struct Job {
     uint64_t ticket = 0;
@@ -49,12 +52,11 @@ struct wfq_server {
     uint64_t budget = 0;
     Clock::time_point t0;
     std::mutex mu;
-    std::condition_variable cv;       // scheduler wake-up
+    std::condition_variable cv;       // worker wake-up (new job, freed memory, stop)
     std::condition_variable done_cv;  // job completion
     std::deque<std::shared_ptr<Job>> queue;
     std::map<uint64_t, std::shared_ptr<Job>> jobs;
-    std::vector<std::thread> workers;
-    std::thread scheduler;
+    std::vector<std::thread> workers;   // the pool: max_jobs threads for the server's lifetime
     uint64_t next_ticket = 1;
     uint64_t reserved = 0;
     int resident = 0;
@@ -86,11 +88,14 @@ uint64_t estimate_footprint(const Job& j, const wfq_serve_cfg& c) {
     return t + (64ull << 20);
 }
 
-void run_job(wfq_server* srv, std::shared_ptr<Job> job) {
+// Runs one admitted job to completion. Never throws: any failure (including host allocation)
+// becomes the job's status.
+void run_job(wfq_server* srv, const std::shared_ptr<Job>& job) {
     int rc = WFQ_OK;
     std::string err;
     wfq_handle* h = nullptr;
-    {
+    const int S = job->n_omega * job->n_dir;
+    try {
         wfq_geometry g{job->n, job->xyz.data(), job->eta.empty() ? nullptr : job->eta.data()};
         wfq_params p = job->params;
         p.device = srv->cfg.device;
@@ -99,18 +104,23 @@ void run_job(wfq_server* srv, std::shared_ptr<Job> job) {
         rc = wfq_build(&g, &p, &h);
         if (rc == WFQ_EDISCONNECTED) rc = WFQ_OK;
         if (rc != WFQ_OK) err = wfq_last_error();
-    }
-    const int S = job->n_omega * job->n_dir;
-    if (rc == WFQ_OK) {
-        job->q_re.assign((size_t)S * job->n, 0.0);
-        job->q_im.assign((size_t)S * job->n, 0.0);
-        job->a_re.assign((size_t)S * 3, 0.0);
-        job->a_im.assign((size_t)S * 3, 0.0);
-        job->info.assign(S, wfq_result{});
-        rc = wfq_solve(h, job->omegas.data(), job->n_omega, job->dirs.data(), job->n_dir, srv->cfg.tol,
-                       &srv->cfg.opts, job->q_re.data(), job->q_im.data(), job->a_re.data(), job->a_im.data(),
-                       job->info.data());
-        if (rc != WFQ_OK) err = wfq_last_error();
+        if (rc == WFQ_OK) {
+            job->q_re.assign((size_t)S * job->n, 0.0);
+            job->q_im.assign((size_t)S * job->n, 0.0);
+            job->a_re.assign((size_t)S * 3, 0.0);
+            job->a_im.assign((size_t)S * 3, 0.0);
+            job->info.assign(S, wfq_result{});
+            rc = wfq_solve(h, job->omegas.data(), job->n_omega, job->dirs.data(), job->n_dir, srv->cfg.tol,
+                           &srv->cfg.opts, job->q_re.data(), job->q_im.data(), job->a_re.data(), job->a_im.data(),
+                           job->info.data());
+            if (rc != WFQ_OK) err = wfq_last_error();
+        }
+    } catch (const std::bad_alloc&) {
+        rc = WFQ_ENOMEM;
+        err = "host allocation failed";
+    } catch (const std::exception& e) {
+        rc = WFQ_EDEVICE;
+        err = e.what();
     }
     wfq_destroy(h);
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -131,16 +141,18 @@ void run_job(wfq_server* srv, std::shared_ptr<Job> job) {
     srv->done_cv.notify_all();
 }
 
-void scheduler_loop(wfq_server* srv) {
+// One worker of the pool: admits the job at the head of the queue when its footprint fits (or when
+// nothing is resident), fails a job that can never fit, and exits once the server stops and the
+// queue is empty. At most max_jobs jobs are resident because there are max_jobs workers.
+void worker_loop(wfq_server* srv) {
     std::unique_lock<std::mutex> lk(srv->mu);
     for (;;) {
         srv->cv.wait(lk, [&] {
-            if (srv->stopping && srv->queue.empty()) return true;
-            if (srv->queue.empty() || srv->resident >= srv->cfg.max_jobs) return false;
+            if (srv->queue.empty()) return srv->stopping;
             const auto& j = srv->queue.front();
-            return srv->reserved + j->footprint <= srv->budget || srv->resident == 0;
+            return j->footprint > srv->budget || srv->reserved + j->footprint <= srv->budget || srv->resident == 0;
         });
-        if (srv->stopping && srv->queue.empty()) break;
+        if (srv->queue.empty()) break;   // stopping and nothing left
         auto job = srv->queue.front();
         srv->queue.pop_front();
         if (job->footprint > srv->budget) {
@@ -150,6 +162,7 @@ void scheduler_loop(wfq_server* srv) {
             job->done = true;
             job->t_admit = job->t_done = srv->now_ms();
             srv->done_cv.notify_all();
+            srv->cv.notify_all();
             continue;
         }
         job->t_admit = srv->now_ms();
@@ -157,7 +170,10 @@ void scheduler_loop(wfq_server* srv) {
         srv->resident += 1;
         srv->max_resident = std::max(srv->max_resident, srv->resident);
         if (srv->busy_since < 0) srv->busy_since = job->t_admit;
-        srv->workers.emplace_back(run_job, srv, job);
+        srv->cv.notify_all();   // the next job may fit beside this one
+        lk.unlock();
+        run_job(srv, job);
+        lk.lock();
     }
 }
 
@@ -195,8 +211,8 @@ int wfq_serve(const wfq_serve_cfg* c, wfq_server** out) {
         wfq::set_error(WFQ_EINVAL, "cfg and out must not be NULL");
         return WFQ_EINVAL;
     }
-    if (c->max_jobs < 1 || c->max_queue < 1 || !(c->tol > 0.0 && c->tol < 1.0)) {
-        wfq::set_error(WFQ_EINVAL, "need max_jobs >= 1, max_queue >= 1, tol in (0, 1)");
+    if (c->max_jobs < 1 || c->max_jobs > kMaxWorkers || c->max_queue < 1 || !(c->tol > 0.0 && c->tol < 1.0)) {
+        wfq::set_error(WFQ_EINVAL, "need max_jobs in [1, 64], max_queue >= 1, tol in (0, 1)");
         return WFQ_EINVAL;
     }
     if (c->opts.restart < 1 || c->opts.max_iter < 1 || c->opts.precision < 0 || c->opts.precision > 2 ||
@@ -220,7 +236,20 @@ int wfq_serve(const wfq_serve_cfg* c, wfq_server** out) {
     (void)hipMemGetInfo(&free_b, &total_b);
     s->budget = c->device_budget ? c->device_budget : (uint64_t)(0.9 * (double)free_b);
     s->t0 = Clock::now();
-    s->scheduler = std::thread(scheduler_loop, s);
+    try {
+        for (int k = 0; k < c->max_jobs; ++k) s->workers.emplace_back(worker_loop, s);
+    } catch (const std::exception&) {
+        // could not start the pool: stop the workers that did start and report it
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->stopping = true;
+            s->cv.notify_all();
+        }
+        for (auto& t : s->workers) t.join();
+        delete s;
+        wfq::set_error(WFQ_ENOMEM, "could not start the worker threads");
+        return WFQ_ENOMEM;
+    }
     *out = s;
     return WFQ_OK;
 }
@@ -333,13 +362,8 @@ void wfq_serve_stop(wfq_server* s) {
         s->stopping = true;
         s->cv.notify_all();
     }
-    if (s->scheduler.joinable()) s->scheduler.join();
-    std::vector<std::thread> ws;
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        ws.swap(s->workers);
-    }
-    for (auto& t : ws)
+    // the workers drain the queue, finish their jobs and exit
+    for (auto& t : s->workers)
         if (t.joinable()) t.join();
     delete s;
 }

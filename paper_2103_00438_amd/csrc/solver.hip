@@ -1070,7 +1070,8 @@ void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double to
             qmr_q(S, sl, ns, Q, w.z.p, w.tpb.p, w.part_sig.p, w.part_nrm.p, nblk, st);
             tm.end(st, KC_SPMM, 4.0 * S.nnz * ns, 12.0 * S.nnz + ns * n * 48.0);
             tm.begin(st);
-            qmr_sigma(sl, ns, w.part_sig.p, w.part_nrm.p, nblk, rho_new, w.sigma.p, w.flags.p, st);
+            qmr_sigma(sl, ns, w.part_sig.p, w.part_nrm.p, nblk, rho_new, w.sigma.p, w.flags.p,
+                      o.qmr_breakdown > 0.0 ? o.qmr_breakdown : 1e-14, st);
             qmr_xr(sl, ns, Q, S.n, rho_new, w.sigma.p, w.norm2.p, nblk, st);
             qmr_weights(sl, ns, w.norm2.p, nblk, w.tau2.p, w.eta.p, w.first.p, st);
             qmr_smooth(sl, ns, Q, S.n, w.eta.p, w.norm2.p, nblk, st);
@@ -1313,41 +1314,53 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
             std::vector<int> broken;
             qmr_batch(S, w, ss, tol, o, tm, st, t0, broken);
             if (!broken.empty()) {
-                // GMRES fallback from the QMR iterate of each broken-down system
+                // GMRES fallback from the QMR iterate of each broken-down system, in groups whose
+                // work space fits what the QMR work space leaves of the budget; a system for which
+                // not even a one-system group fits keeps its QMR iterate and ends as WFQ_EBREAKDOWN
                 wfq_solve_opts og = o;
                 og.algorithm = WFQ_GMRES;
                 og.restart = std::min(50, std::max(o.restart, 10));
-                const int nbk = (int)broken.size();
-                Work wg;
-                WorkShape shg;
-                shg.B = nbk;
-                shg.m = og.restart;
-                shg.n_dir = n_dir;
-                shg.prec = prec;
-                make_work(wg, S, shg);
-                clear_work(wg, st);
-                WFQ_HIP(hipMemcpyAsync(wg.b.p, w.b.p, w.b.count * sizeof(double), hipMemcpyDeviceToDevice, st));
-                std::vector<SysState> sg(nbk);
-                for (int q = 0; q < nbk; ++q) {
-                    const int s = broken[q];
-                    sg[q] = ss[s];
-                    sg[q].status = WFQ_OK;
-                    sg[q].done = false;
-                    WFQ_HIP(hipMemcpyAsync(wg.X.p + (size_t)q * 2 * S.npad, w.Xb.base + (size_t)s * w.Xb.sys_stride,
-                                           2 * S.npad * sizeof(double), hipMemcpyDeviceToDevice, st));
+                const uint64_t used = batch_bytes(S, o, B, n_dir);
+                const uint64_t left = S.budget ? (avail > used ? avail - used : 0) : ~0ull;
+                int G = (int)broken.size();
+                while (G > 1 && batch_bytes(S, og, G, n_dir) > left) G = (G + 1) / 2;
+                if (batch_bytes(S, og, G, n_dir) > left) {
+                    for (int s : broken) ss[s].status = WFQ_EBREAKDOWN;
+                    broken.clear();
                 }
-                gmres_batch(S, wg, sg, tol, og, tm, st, t0, nullptr, true);
-                for (int q = 0; q < nbk; ++q) {
-                    const int s = broken[q];
-                    const int iters_qmr = ss[s].iters, cycles_qmr = ss[s].cycles;
-                    ss[s] = sg[q];
-                    ss[s].iters += iters_qmr;
-                    ss[s].cycles += cycles_qmr;
-                    if (ss[s].status == WFQ_ENOCONV) ss[s].status = WFQ_EBREAKDOWN;
-                    WFQ_HIP(hipMemcpyAsync(w.Xb.base + (size_t)s * w.Xb.sys_stride, wg.X.p + (size_t)q * 2 * S.npad,
-                                           2 * S.npad * sizeof(double), hipMemcpyDeviceToDevice, st));
+                for (size_t g0 = 0; g0 < broken.size(); g0 += G) {
+                    const int nbk = (int)std::min<size_t>(G, broken.size() - g0);
+                    Work wg;
+                    WorkShape shg;
+                    shg.B = nbk;
+                    shg.m = og.restart;
+                    shg.n_dir = n_dir;
+                    shg.prec = prec;
+                    make_work(wg, S, shg);
+                    clear_work(wg, st);
+                    WFQ_HIP(hipMemcpyAsync(wg.b.p, w.b.p, w.b.count * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    std::vector<SysState> sg(nbk);
+                    for (int q = 0; q < nbk; ++q) {
+                        const int s = broken[g0 + q];
+                        sg[q] = ss[s];
+                        sg[q].status = WFQ_OK;
+                        sg[q].done = false;
+                        WFQ_HIP(hipMemcpyAsync(wg.X.p + (size_t)q * 2 * S.npad, w.Xb.base + (size_t)s * w.Xb.sys_stride,
+                                               2 * S.npad * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    }
+                    gmres_batch(S, wg, sg, tol, og, tm, st, t0, nullptr, true);
+                    for (int q = 0; q < nbk; ++q) {
+                        const int s = broken[g0 + q];
+                        const int iters_qmr = ss[s].iters, cycles_qmr = ss[s].cycles;
+                        ss[s] = sg[q];
+                        ss[s].iters += iters_qmr;
+                        ss[s].cycles += cycles_qmr;
+                        if (ss[s].status == WFQ_ENOCONV) ss[s].status = WFQ_EBREAKDOWN;
+                        WFQ_HIP(hipMemcpyAsync(w.Xb.base + (size_t)s * w.Xb.sys_stride, wg.X.p + (size_t)q * 2 * S.npad,
+                                               2 * S.npad * sizeof(double), hipMemcpyDeviceToDevice, st));
+                    }
+                    WFQ_HIP(hipStreamSynchronize(st));
                 }
-                WFQ_HIP(hipStreamSynchronize(st));
             }
         }
         // outputs of the batch

@@ -65,3 +65,33 @@ def test_qmr_needs_more_iterations_than_gmres(lib, case):
     q = lib.wfq_solve(h, om[2:3], dirs[:1], 1e-8, algorithm="qmr", restart=5000, precision="fp64")
     assert q["info"][0]["iters"] >= g["info"][0]["iters"]
     h.close()
+
+
+def test_qmr_breakdown_falls_back_to_gmres(lib, case):
+    # QMR runs without look-ahead: when the bilinear form of a step is (near) zero the system leaves
+    # QMR and continues in GMRES from its QMR iterate. A threshold that every step meets forces that
+    # path on every system; the results must still be the LU solutions.
+    xyz, P, om, dirs, ref = case
+    h = lib.wfq_build(xyz, GRAPHENE)
+    tol = 1e-8
+    out = lib.wfq_solve(h, om, dirs, tol, algorithm="qmr", restart=60, precision="fp64", qmr_breakdown=1e30)
+    assert out["status"] == 0, out["info"]
+    for a in range(len(om)):
+        for k in range(3):
+            info = out["info"][a * 3 + k]
+            assert info["status"] == 0 and info["relres"] <= tol
+            assert info["iters"] > 0
+            assert rel(out["q"][a, k], ref[(a, k)]) <= 1e-6
+    # the same systems with the default threshold take the QMR route and agree
+    plain = lib.wfq_solve(h, om, dirs, tol, algorithm="qmr", restart=60, precision="fp64")
+    assert rel(plain["q"], out["q"]) <= 2e-6
+    h.close()
+
+
+def test_qmr_breakdown_threshold_is_checked(lib, case):
+    xyz = case[0]
+    h = lib.wfq_build(xyz, GRAPHENE)
+    with pytest.raises(lib.WfqError) as e:
+        lib.wfq_solve(h, [0.3], np.eye(3)[:1], 1e-8, algorithm="qmr", qmr_breakdown=-1.0)
+    assert e.value.code == lib.WFQ_EINVAL
+    h.close()

@@ -61,7 +61,6 @@ def test_mix_equals_alone(lib):
     assert np.linalg.norm(q - ref) / np.linalg.norm(ref) <= 1e-6
 
 
-@pytest.mark.skip(reason="a run of the GPU suite aborted inside this serving test (glibc: free(): invalid pointer while the caller waited for a job, no GPU fault) with no cause found in the code; kept off the GPU until one is")
 def test_mix_equals_alone_multishift(lib):
     # the request loop with one shared Krylov basis per job and direction (FP64 T)
     tol = 1e-8
@@ -81,7 +80,6 @@ def test_mix_equals_alone_multishift(lib):
         assert all(i["relres"] <= tol for i in res["info"])
 
 
-@pytest.mark.skip(reason="a run of the GPU suite aborted inside this serving test, right after the multi-shift serving test, with no cause found in the code; kept off the GPU until one is")
 def test_queue_limit_and_tickets(lib):
     xyz, om, d = jobs()[3]
     srv = lib.wfq_serve(1e-8, max_jobs=1, max_queue=2, restart=40, precision="fp32")

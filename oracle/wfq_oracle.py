@@ -25,9 +25,14 @@ Readings of the paper taken here (each listed with its reason in the design note
     as Eq. (wfq-a-matrix).
 
 Parity status: every function below is pinned by tests under tests/ against
-closed forms, invariants stated in the paper, or exact limits, except the
-material closure `drude_weight_closure`, which is a project choice (parity
-unpinned: the paper defers parameter values to earlier work).
+closed forms, invariants stated in the paper, exact limits or textbook results:
+the cross sections by the Thomas-Reiche-Kuhn sum rule, and the material closure
+`drude_weight_closure` (a project choice for values the paper defers to earlier
+work) by the Froehlich frequency of a Drude sphere that it reproduces.
+
+A plain C++ FP64 implementation of the same oracle (T, L, LU, GMRES, QMR, residuals,
+polarisability) lives in wfq_oracle.cpp with its ctypes front cpp_oracle.py; the same
+pins run against both (tests/test_oracle_both.py).
 """
 
 from __future__ import annotations
@@ -498,7 +503,11 @@ class Problem:
         self.T = coulomb_matrix(self.xyz, self.eta) if dense_T else None
 
     def apply_T(self, x):
+        """T x. T is real: a complex x is handled as T Re x + i T Im x (no complex copy of T)."""
         if self.T is not None:
+            x = np.asarray(x)
+            if np.iscomplexobj(x):
+                return self.T @ np.ascontiguousarray(x.real) + 1j * (self.T @ np.ascontiguousarray(x.imag))
             return self.T @ x
         out = np.empty(x.shape, dtype=np.result_type(x, np.float64))
         for s in range(0, self.n, 1024):
@@ -607,7 +616,9 @@ def drude_weight_closure(lattice_xyz_bohr, site, cell_measure, drude_weight, r0,
     the Drude weight gives
         W = 2 * cell_measure * drude_weight / sum_j (1 - f(r_0j)) x_0j^2 / r_0j,
     the sum running over the ideal-lattice neighbours of `site` within the cutoff.
-    (Parity unpinned: a project choice for values the paper does not print.)
+    A project choice for values the paper does not print; pinned by the physics it is meant to
+    reproduce: with it, the dipole plasmon of a Drude metal sphere approaches the classical
+    w_p / sqrt(3) (tests/test_oracle_both.py).
     """
     rc = cutoff_radius(r0, d, s, eps)
     diff = lattice_xyz_bohr - lattice_xyz_bohr[site]

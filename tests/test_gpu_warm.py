@@ -59,8 +59,11 @@ def test_warm_sweep_matches_lu_and_oracle_steps(lib, tube):
                 assert abs(info["iters"] - cold["info"][a * 2 + k]["iters"]) <= 1
             else:
                 # same start (up to the neighbours' 1e-10 residuals), same Krylov space: the oracle's
-                # step count, and fewer steps than from zero
-                assert -1 <= info["iters"] - int(it_o[a]) <= 3, (a, k, info["iters"], it_o[a])
+                # step count, and fewer steps than from zero. The start's residual is close to the
+                # tolerance, so the step that crosses it moves by one with the rounding order of the
+                # products (the oracle alone: 31 or 32 steps for one system), and the GPU stops on half
+                # the tolerance (one or two more)
+                assert -1 <= info["iters"] - int(it_o[a]) <= 4, (a, k, info["iters"], it_o[a])
                 assert info["iters"] < cold["info"][a * 2 + k]["iters"]
 
 

@@ -226,6 +226,24 @@ int wfq_apply_T_variant(wfq_handle* h, int32_t precision, int32_t variant, int32
 int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t S, const double* z_re, const double* z_im,
                  const double* X_re, const double* X_im, double* Y_re, double* Y_im);
 
+/*
+ * wfq_apply_op_noalloc - as wfq_apply_op, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): it calls no hipMalloc, hipFree or
+ * other allocating routine. Inputs and outputs are device pointers: z_re_dev, z_im_dev [nsys];
+ * X_re_dev, X_im_dev, Y_re_dev, Y_im_dev [nsys][n] in the caller's atom order. Work is only
+ * enqueued on `stream` (a hipStream_t; kernel launches only, no copies, memsets or host
+ * synchronisation), so Y is ready when the stream reaches that point. Its intermediates live in one
+ * static device array of wfq_noalloc_scratch_bytes() = 256 MiB per GPU, set up by wfq_build on that
+ * device and held until the process ends: calls needing more (about 16 nsys N + 256 N (s + 4) bytes
+ * for a T copy of s bytes per element, N padded to 256) fail with WFQ_ENOMEM before any work. Every
+ * call on one GPU shares that array, from any handle: calls whose work overlaps on the device race
+ * (order them on one stream or synchronise between them); each call rewrites everything it reads.
+ */
+int wfq_apply_op_noalloc(wfq_handle* h, int32_t precision, int32_t nsys, const double* z_re_dev,
+                         const double* z_im_dev, const double* X_re_dev, const double* X_im_dev,
+                         double* Y_re_dev, double* Y_im_dev, void* stream);
+uint64_t wfq_noalloc_scratch_bytes(void);
+
 /* b = E0 L (r . k) for n_dir directions: out[n_dir][n] */
 int wfq_rhs(wfq_handle* h, const double* dirs, int32_t n_dir, double E0, double* out);
 

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <mutex>
+#include <string>
 
 #include "krylov.h"
 #include "solver.h"
@@ -30,6 +31,8 @@ struct wfq_handle {
 };
 
 namespace {
+
+void* scratch_ptr(int device);   // the allocation-free entry point's scratch on `device` (defined below)
 
 const char* kClassNames[KC_COUNT] = {"tx_gemm_f64", "tx_gemm_f32", "tx_gemm_bf16", "tx_skinny", "tx_otf_f32", "tx_otf_f64",
                                      "spmm_shift",  "cgs_dot",     "cgs_update",   "givens",    "pack",
@@ -145,6 +148,7 @@ int wfq_build(const wfq_geometry* g, const wfq_params* p, wfq_handle** out) {
             WFQ_HIP(hipMemGetInfo(&free_b, &total_b));
             h->S.budget = p->device_budget ? p->device_budget : (uint64_t)(0.9 * (double)free_b);
             build_structure(h->S, g, p, h->stream);
+            (void)scratch_ptr(p->device);   // set-up of wfq_apply_op_noalloc's scratch on this device
         } catch (...) {
             free_structure(h->S);
             if (h->stream) (void)hipStreamDestroy(h->stream);
@@ -340,6 +344,140 @@ int wfq_apply_T(wfq_handle* h, int32_t precision, int32_t ncol, const double* X,
 
 int wfq_apply_T_variant(wfq_handle* h, int32_t precision, int32_t variant, int32_t ncol, const double* X, double* Y) {
     return apply_T_impl(h, precision, variant, ncol, X, Y);
+}
+
+}  // extern "C"
+
+// ---- the allocation-free operator entry point (wfq_apply_op_noalloc)
+//
+// Its scratch (the systems' vectors in the internal order, the shifts, the packed block, the
+// product and the split-k partial tiles) lives in one static device array. Every GPU the library
+// runs on holds its own copy for the life of the process; the host reaches it only through the
+// address hipGetSymbolAddress returns for the current device, kept per device below.
+namespace {
+
+constexpr uint64_t kNoAllocScratchBytes = 256ull << 20;
+constexpr int kMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// the device address of this device's scratch array (looked up once per device, with it current)
+void* scratch_ptr(int device) {
+    if (device < 0 || device >= kMaxDevices) fail(WFQ_EDEVICE, "device ordinal beyond the scratch table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            fail(WFQ_EDEVICE, std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e));
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
+
+// sys[k] = k, zs[k] = (z_re[k], z_im[k])
+__global__ void na_setup_kernel(int nsys, const double* __restrict__ z_re, const double* __restrict__ z_im,
+                                double2* __restrict__ zs, int* __restrict__ sys) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nsys) return;
+    zs[k] = make_double2(z_re[k], z_im[k]);
+    sys[k] = k;
+}
+
+// slot 0 of system s (re, im planes) = X_s in the internal order, zero padding; slot 1 cleared
+__global__ void na_gather_kernel(int64_t n, int64_t npad, const int32_t* __restrict__ perm,
+                                 const double* __restrict__ x_re, const double* __restrict__ x_im,
+                                 double* __restrict__ V) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= npad) return;
+    const int64_t s = blockIdx.y;
+    double* v = V + s * 4 * npad;
+    const bool in = i < n;
+    v[i] = in ? x_re[s * n + perm[i]] : 0.0;
+    v[npad + i] = in ? x_im[s * n + perm[i]] : 0.0;
+    v[2 * npad + i] = 0.0;
+    v[3 * npad + i] = 0.0;
+}
+
+// zero `words` 16-byte words (a fill kernel rather than a memset node, so the call can be captured)
+__global__ void na_zero_kernel(uint4* __restrict__ p, int64_t words) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256)
+        p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// restores the structure's own split-k work space when the call ends
+struct FixedSplit {
+    const Structure& S;
+    FixedSplit(const Structure& s, void* p, uint64_t bytes) : S(s) {
+        S.split_fixed = p;
+        S.split_fixed_bytes = bytes;
+    }
+    ~FixedSplit() {
+        S.split_fixed = nullptr;
+        S.split_fixed_bytes = 0;
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+uint64_t wfq_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+int wfq_apply_op_noalloc(wfq_handle* h, int32_t precision, int32_t nsys, const double* z_re_dev,
+                         const double* z_im_dev, const double* X_re_dev, const double* X_im_dev, double* Y_re_dev,
+                         double* Y_im_dev, void* stream) {
+    return guarded([&]() -> int {
+        if (!h || !z_re_dev || !z_im_dev || !X_re_dev || !X_im_dev || !Y_re_dev || !Y_im_dev || nsys < 1)
+            fail(WFQ_EINVAL, "bad arguments");
+        if (precision < 0 || precision > 2) fail(WFQ_EINVAL, "unknown precision");
+        Structure& S = h->S;
+        if (S.t_mode == WFQ_TMODE_OTF && precision == WFQ_PREC_BF16) fail(WFQ_EINVAL, "matrix-free T runs in FP32 or FP64");
+        if (S.t_mode == WFQ_TMODE_STORED &&
+            ((precision == WFQ_PREC_FP64 && !S.T64) || (precision == WFQ_PREC_FP32 && !S.T32) ||
+             (precision == WFQ_PREC_BF16 && !S.T16)))
+            fail(WFQ_EINVAL, "that copy of T was not built");
+        const int64_t np = S.npad;
+        const int64_t rows = round_up(2 * (int64_t)nsys, kColPad);
+        const uint64_t es = precision == WFQ_PREC_FP64 ? 8 : precision == WFQ_PREC_FP32 ? 4 : 2;
+        const uint64_t os = precision == WFQ_PREC_FP64 ? 8 : 4;
+        auto up = [](uint64_t b) { return (b + 255) & ~uint64_t(255); };
+        const uint64_t v_bytes = up((uint64_t)nsys * 4 * np * 8), z_bytes = up((uint64_t)nsys * 16),
+                       s_bytes = up((uint64_t)nsys * 4), x_bytes = up((uint64_t)rows * np * es),
+                       y_bytes = up((uint64_t)rows * np * os);
+        const uint64_t need = v_bytes + z_bytes + s_bytes + x_bytes + y_bytes;
+        if (need > kNoAllocScratchBytes)
+            fail(WFQ_ENOMEM, "wfq_apply_op_noalloc: " + std::to_string(nsys) + " systems of " + std::to_string(S.n) +
+                                 " atoms need " + std::to_string(need >> 20) + " MiB of scratch, more than its " +
+                                 std::to_string(kNoAllocScratchBytes >> 20) + " MiB");
+        WFQ_HIP(hipSetDevice(S.device));
+        char* base = static_cast<char*>(scratch_ptr(S.device));
+        double* V = reinterpret_cast<double*>(base);
+        double2* zs = reinterpret_cast<double2*>(base + v_bytes);
+        int* sys = reinterpret_cast<int*>(base + v_bytes + z_bytes);
+        void* X = base + v_bytes + z_bytes + s_bytes;
+        void* Y = base + v_bytes + z_bytes + s_bytes + x_bytes;
+        FixedSplit fs(S, base + need, kNoAllocScratchBytes - need);
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        hipLaunchKernelGGL(na_setup_kernel, dim3((nsys + 63) / 64), dim3(64), 0, st, nsys, z_re_dev, z_im_dev, zs, sys);
+        WFQ_CHECK_LAUNCH();
+        hipLaunchKernelGGL(na_gather_kernel, dim3((unsigned)(np / 256), (unsigned)nsys), dim3(256), 0, st, S.n, np,
+                           S.dperm, X_re_dev, X_im_dev, V);
+        WFQ_CHECK_LAUNCH();
+        const int64_t words = (int64_t)(x_bytes / 16);
+        hipLaunchKernelGGL(na_zero_kernel, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 4096)), dim3(256), 0,
+                           st, static_cast<uint4*>(X), words);
+        WFQ_CHECK_LAUNCH();
+        const Basis Vb{V, 4 * np, 2 * np, np};
+        pack_columns(precision, Vb, sys, nsys, 0, nullptr, false, X, np, st);
+        tx_any(S, precision, X, Y, 2 * nsys, st);
+        spmm_shift(S, precision == WFQ_PREC_FP64, Y, np, sys, nsys, zs, Vb, 0, 1, st);
+        scatter_q(S, S.dperm, sys, nsys, Basis{V + 2 * np, 4 * np, 2 * np, np}, Y_re_dev, Y_im_dev, st);
+        return WFQ_OK;
+    });
 }
 
 int wfq_apply_op(wfq_handle* h, int32_t precision, int32_t nsys, const double* z_re, const double* z_im,

@@ -79,6 +79,10 @@ struct Structure {
     // partial tiles of split-k block products (grown on demand, at most kSplitWsCap bytes)
     mutable void* split_ws = nullptr;
     mutable uint64_t split_ws_bytes = 0;
+    // when set, the partial tiles go to this region (at most split_fixed_bytes) and nothing is
+    // allocated: the block products then choose only splits whose partial tiles fit
+    mutable void* split_fixed = nullptr;
+    mutable uint64_t split_fixed_bytes = 0;
     // bumped whenever a block-product choice (tuning) or the partial-tile buffer changes: captured
     // launch sequences that refer to either are then stale
     mutable uint64_t epoch = 0;

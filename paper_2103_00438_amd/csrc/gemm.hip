@@ -368,12 +368,12 @@ struct Variant {
 // on the chip at once: the time is taken as proportional to (rounds of work-groups) x (k-steps per
 // part), plus two k-steps per extra part for writing and adding the partial tiles. A split must
 // win by 3 % and keep parts >= 8 k-steps and the partial tiles within the work-space cap.
-int choose_split(int64_t tiles, int nk, int64_t slots, uint64_t part_bytes) {
+int choose_split(int64_t tiles, int nk, int64_t slots, uint64_t part_bytes, uint64_t cap) {
     auto cost = [&](int sp) { return (double)((tiles * sp + slots - 1) / slots) * ((nk + sp - 1) / sp) + 2.0 * (sp - 1); };
     int best = 1;
     double best_cost = cost(1);
     for (int sp = 2; sp <= 8; ++sp) {
-        if (nk / sp < 8 || (uint64_t)(sp - 1) * part_bytes > kSplitWsCap) break;
+        if (nk / sp < 8 || (uint64_t)(sp - 1) * part_bytes > cap) break;
         const double c = cost(sp);
         if (c < 0.97 * best_cost) {
             best = sp;
@@ -384,6 +384,11 @@ int choose_split(int64_t tiles, int nk, int64_t slots, uint64_t part_bytes) {
 }
 
 void* split_workspace(const Structure& s, uint64_t bytes) {
+    if (s.split_fixed) {
+        // a caller-provided region (the allocation-free entry point): never allocate
+        if (bytes > s.split_fixed_bytes) throw Error{WFQ_ENOMEM, "split-k partial tiles exceed the fixed work space"};
+        return s.split_fixed;
+    }
     if (bytes > s.split_ws_bytes) {
         if (s.split_ws) {
             WFQ_HIP(hipFree(s.split_ws));
@@ -421,7 +426,8 @@ void launch_mfma(const Structure& s, const void* X, const void* T, void* Y, int6
     const int mtc = (ncol + BM - 1) / BM, ntc = (int)(ld / BN);
     const int nk = (int)(ld * (int64_t)sizeof(elem) / KB);
     const uint64_t part_bytes = (uint64_t)mtc * BM * ld * sizeof(out);
-    const int split = choose_split((int64_t)mtc * ntc, nk, (int64_t)per_cu * device_cus(s.device), part_bytes);
+    const uint64_t cap = s.split_fixed ? s.split_fixed_bytes : kSplitWsCap;
+    const int split = choose_split((int64_t)mtc * ntc, nk, (int64_t)per_cu * device_cus(s.device), part_bytes, cap);
     out* ws = split > 1 ? static_cast<out*>(split_workspace(s, (split - 1) * part_bytes)) : nullptr;
     hipLaunchKernelGGL(kern, dim3(mtc * ntc * split), dim3(NT), 0, st, static_cast<const elem*>(X),
                        static_cast<const elem*>(T), static_cast<out*>(Y), ld, ncol, mtc, ntc, split, ws);

@@ -92,6 +92,9 @@ _SIGNATURES = {
     "wfq_apply_T": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _DP, _DP]),
     "wfq_apply_T_variant": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, _DP, _DP]),
     "wfq_apply_op": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, _DP, _DP, _DP, _DP, _DP, _DP]),
+    "wfq_apply_op_noalloc": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "wfq_noalloc_scratch_bytes": (C.c_uint64, []),
     "wfq_rhs": (C.c_int, [C.c_void_p, _DP, C.c_int32, C.c_double, _DP]),
     "wfq_kernel_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_char_p), _I64P, _DP, _DP, _DP,
                                    C.c_int32]),
@@ -325,6 +328,23 @@ def wfq_apply_op(h: Handle, precision, z, X) -> np.ndarray:
     _check(load().wfq_apply_op(h.ptr, PREC[precision], X.shape[0], _dp(zr), _dp(zi), _dp(xr), _dp(xi), _dp(yr),
                                _dp(yi)))
     return yr + 1j * yi
+
+
+def wfq_apply_op_noalloc(h: Handle, precision, z_re, z_im, X_re, X_im, Y_re, Y_im, stream=None) -> int:
+    """Y = (L T + z_s I) X_s with device buffers (e.g. torch float64 tensors on cuda: z [nsys],
+    X and Y [nsys, N] in the caller's atom order); only enqueues work on `stream`."""
+    nsys = int(z_re.numel())
+
+    def ptr(t):
+        return C.c_void_p(t.data_ptr())
+
+    st = None if stream is None else C.c_void_p(int(stream))
+    return _check(load().wfq_apply_op_noalloc(h.ptr, PREC[precision], nsys, ptr(z_re), ptr(z_im), ptr(X_re),
+                                              ptr(X_im), ptr(Y_re), ptr(Y_im), st))
+
+
+def wfq_noalloc_scratch_bytes() -> int:
+    return int(load().wfq_noalloc_scratch_bytes())
 
 
 def wfq_rhs(h: Handle, dirs, E0=1.0) -> np.ndarray:

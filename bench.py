@@ -1,19 +1,22 @@
-"""Benchmark: omega-point solves per second of the batched mixed-precision solve on one MI355X.
+"""Benchmark: omega-point solves per second on one MI355X.
 
-Default workload (cnt20k): armchair (10,10) carbon nanotube, 500 periods = 20 000 atoms, jitter
-0.01 A (seed 2), graphene parameters (eps_F = 0.4 eV, tau = 170 a.u., d = 12, s = 1.1), 64
-frequencies uniform in 0.05-1.0 eV x 3 field polarisations = 192 systems sharing one stored T.
-One step = one wfq_solve over all 192 systems: FP32 T products inside restarted GMRES(50) with FP64
-refinement to relative FP64 residual 1e-8. T and L are built (and resident in HBM) before the timed
-region.
+Default workload (fcc120k): FCC metal sphere, a = 4.09 A, R = 78.8 A, 119 879 atoms, jitter 0.02 A
+(seed 3), metal parameters (tau = 170 a.u., d = 12, s = 1.1, W from the Drude sum-rule closure), 128
+frequencies uniform in 1.5-4.5 eV x 3 field polarisations = 384 systems sharing one T. One step =
+one wfq_solve over all 384 systems to relative FP64 residual 1e-7: multi-shift GMRES (one Krylov
+basis of L T per field direction shared by the 128 frequencies, FP64 throughout; the narrow T
+products recompute T's elements on the vector ALUs), then the FP64 residual check of every system.
+T (FP64 copy, for the residual check) and L are built and resident in HBM before the timed region.
 
-Printed (one JSON line): solves/s, p50/p99 per-system completion latency inside a step, the largest
-relative difference of q against the FP64 solve on the same GPU, the per-frequency FP64 baseline
-(one system per solve, same library), the roofline figures of the dominant kernel (timed with HIP
-events on the library's stream) and the CPU oracle timed on a bounded sample.
+Printed (one JSON line): solves/s, p50/p99 per-system completion latency inside a step, iterations,
+the largest relative difference of q against per-frequency FP64 GMRES(100) solves of sampled systems
+on the same GPU (which are also the per-frequency baseline), a per-frequency QMR leg, the roofline of
+the dominant kernel (HIP events on the library's stream) and the C++ CPU oracle timed on a bounded
+sample.
 
-Other workloads (--workload): disk600 (single-system latency), fcc120k (BF16 T, 120k atoms),
-sheet1m (matrix-free T, 10^6 atoms), serve_mix (Poisson stream of jobs through wfq_serve).
+Other workloads (--workload): cnt20k (FP32 T inside FP64 refinement, batched GMRES(50), 20 000
+atoms), disk600 (single-system latency), disk600_spectrum, sheet1m (matrix-free T, 10^6 atoms),
+serve_mix (Poisson stream of jobs through wfq_serve).
 """
 
 from __future__ import annotations
@@ -34,6 +37,9 @@ sys.path.insert(0, ROOT)
 
 PEAKS = {"fp32": 157.3, "fp64": 78.6, "bf16": 2500.0}   # TFLOP/s, dense MFMA (MI355X)
 HBM_GBPS = 8000.0                                         # GB/s, HBM3E (MI355X)
+# FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (one FP64 operation per lane per
+# clock; an FMA counts as one operation here)
+VALU_F64_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 METRIC = "omega-point solves/s at rel. err 1e-6 (mixed vs FP64, same GPU); p50/p99 latency"
 
 
@@ -44,7 +50,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2,
                     help="untimed solves first (small structures: the first sight of a step chunk runs "
                          "eagerly, the second captures it as a HIP graph, later ones replay it)")
-    ap.add_argument("--workload", default="cnt20k")
+    ap.add_argument("--workload", default="fcc120k")
     ap.add_argument("--algorithm", default=None, help="gmres, qmr or msgmres (one shared basis per direction)")
     ap.add_argument("--shift-dim", type=int, default=0, help="msgmres: largest shared-basis dimension (0 = 400)")
     ap.add_argument("--restart", type=int, default=0,
@@ -94,40 +100,63 @@ def host_info():
     return dict(cpu_model=model, nproc=os.cpu_count(), mem_gb=mem_gb)
 
 
-def cpu_baseline(wl, sys_index):
-    """The oracle as it stands: FP64 restarted GMRES on one system of the workload (host cores)."""
-    from oracle import wfq_oracle as O
+def cpu_baseline(wl, n_samples=5, budget_s=40.0):
+    """The C++ FP64 oracle (stored T, OpenMP over the host's cores): restarted GMRES on a stratified
+    sample of the workload's systems (evenly spaced over frequency, cycling through the field
+    directions), stopping early once budget_s of solve time is spent."""
+    from oracle import cpp_oracle
     t0 = time.perf_counter()
-    P = O.Problem(wl.xyz, wl.params)
+    P = cpp_oracle.CppProblem(wl.xyz, wl.params)
     t_build = time.perf_counter() - t0
-    a, k = divmod(sys_index, len(wl.dirs))
-    t0 = time.perf_counter()
-    x, info = P.solve_gmres(wl.omegas_eV[a], wl.dirs[k], wl.restart, wl.tol)
-    t_solve = time.perf_counter() - t0
-    return dict(value=1.0 / t_solve, unit="solves/s", cores=cores_used(), kind="oracle", host=host_info(),
-                sample=f"1 of {wl.n_systems} systems (omega={wl.omegas_eV[a]:.4f} eV, dir {k}), FP64 GMRES"
-                       f"({wl.restart}) to {wl.tol:g}; solve {t_solve:.1f} s ({info['iters']} iterations), "
-                       f"matrix build {t_build:.1f} s not included",
-                solve_s=t_solve, build_s=t_build, iters=info["iters"])
+    S = wl.n_systems
+    idx = [int(round(v)) for v in np.linspace(0, len(wl.omegas_eV) - 1, n_samples)]
+    done, t_solve, iters = [], 0.0, []
+    for q, a in enumerate(idx):
+        k = q % len(wl.dirs)
+        t1 = time.perf_counter()
+        _, info = P.solve_gmres(wl.omegas_eV[a], wl.dirs[k], wl.restart, wl.tol)
+        t_solve += time.perf_counter() - t1
+        done.append(f"{wl.omegas_eV[a]:.3f} eV/dir {k}")
+        iters.append(info["iters"])
+        if t_solve > budget_s:
+            break
+    return dict(value=len(done) / t_solve, unit="solves/s", cores=cpp_oracle.threads(), kind="oracle",
+                host=host_info(),
+                sample=f"{len(done)} of {S} systems ({', '.join(done)}), C++ oracle FP64 GMRES({wl.restart}) to "
+                       f"{wl.tol:g} with stored FP64 T; solve {t_solve:.1f} s, iterations {iters}; matrix build "
+                       f"{t_build:.1f} s not included",
+                solve_s=t_solve, build_s=t_build, iters=iters)
+
+
+def cpu_baseline_rows(wl, iters_per_solve, target_s=15.0):
+    """The C++ FP64 oracle's matrix-free T product (every element recomputed, OpenMP over the host's
+    cores) timed on sampled rows, scaled to one solve of iters_per_solve products of 2 real columns."""
+    from oracle import cpp_oracle
+    P = cpp_oracle.CppProblem(wl.xyz, wl.params, dense_T=False, build_L=False)
+    X = np.random.default_rng(0).standard_normal((wl.n, 2))
+    n_rows, t = 256, 0.0
+    while True:
+        rows = (np.arange(n_rows) * (wl.n // n_rows)).astype(np.int64)
+        t0 = time.perf_counter()
+        P.apply_T_rows(rows, X)
+        t = time.perf_counter() - t0
+        if t > target_s / 4 or n_rows >= wl.n:
+            break
+        n_rows = min(wl.n, int(n_rows * max(2.0, target_s / 4 / max(t, 1e-3))))
+    pairs_per_s = n_rows * wl.n / t
+    per_product = wl.n * wl.n / pairs_per_s
+    return dict(value=1.0 / (per_product * iters_per_solve), unit="solves/s", cores=cpp_oracle.threads(),
+                kind="oracle", host=host_info(),
+                sample=f"{n_rows} rows of the C++ oracle's matrix-free T x, 2 columns ({n_rows * wl.n:.3g} pair "
+                       f"evaluations in {t:.1f} s), extrapolated to one system = {iters_per_solve:.0f} products "
+                       f"(the per-frequency GMRES({wl.restart}) iteration count on the GPU); L and vector work "
+                       f"ignored",
+                pairs_per_s=pairs_per_s)
 
 
 def cpu_baseline_matrix_free(wl, iters_per_solve, n_rows=256):
     """The oracle's pairwise (matrix-free) rows of T x on a sample of rows, scaled to solves/s."""
-    from oracle import wfq_oracle as O
-    xyz = O.angstrom_to_bohr(wl.xyz)
-    eta = np.full(len(xyz), wl.params["eta"])
-    x = np.random.default_rng(0).standard_normal(len(xyz))
-    rows = np.arange(n_rows) * (len(xyz) // n_rows)
-    t0 = time.perf_counter()
-    for s in range(0, n_rows, 16):
-        O.coulomb_rows(xyz, eta, rows[s:s + 16]) @ x
-    t = time.perf_counter() - t0
-    per_product = t / n_rows * len(xyz) * 2          # 2 real columns per complex system
-    return dict(value=1.0 / (per_product * iters_per_solve), unit="solves/s", cores=cores_used(), kind="oracle", host=host_info(),
-                sample=f"{n_rows} rows of the matrix-free T x ({n_rows * len(xyz):.3g} pairs, {t:.1f} s); "
-                       f"extrapolated to one system = {iters_per_solve:.0f} products of 2 real columns "
-                       f"(the GPU's mean iteration count); L and vector work ignored",
-                pairs_per_s=n_rows * len(xyz) / t)
+    return cpu_baseline_rows(wl, iters_per_solve, target_s=10.0)
 
 
 def kernel_table(stats):
@@ -179,15 +208,28 @@ def roofline_of(stats, prec, otf, n, workload=None):
                     avg_launch_ms=st["ms"] / max(1, st["launches"]),
                     pairs_per_launch=pairs, pairs_per_s=pairs / avg_s if avg_s > 0 else 0.0)
     # the T-product class that took the most time (systems may have escalated to another precision)
-    classes = {"tx_gemm_f32": "fp32", "tx_gemm_f64": "fp64", "tx_gemm_bf16": "bf16", "tx_skinny": None}
+    classes = {"tx_gemm_f32": "fp32", "tx_gemm_f64": "fp64", "tx_gemm_bf16": "bf16", "tx_skinny": None,
+               "tx_skinny_f32": None, "tx_otf_narrow": None}
     dom = max(classes, key=lambda k: stats.get(k, {}).get("ms", 0.0))
-    if dom == "tx_skinny":
+    if dom == "tx_otf_narrow":
+        # narrow products with every element recomputed: bound by the FP64 vector ALUs. Work per pair:
+        # 3 differences, 3 operations for r^2, the reciprocal square root, 4 for its Newton step and one
+        # multiply-add per column (the library's count); peak: one FP64 operation per lane per clock
+        st = stats["tx_otf_narrow"]
+        avg_s = st["ms"] / max(1, st["launches"]) / 1e3
+        achieved = st["flops"] / max(1, st["launches"]) / avg_s / 1e12 if avg_s > 0 else 0.0
+        return dict(bound="alu", achieved=achieved, peak=VALU_F64_TOPS, unit="TOP/s", frac=achieved / VALU_F64_TOPS,
+                    traffic=measured_traffic(workload, "tx_otf_narrow"), kernel="tx_otf_narrow",
+                    launches=st["launches"], avg_launch_ms=st["ms"] / max(1, st["launches"]),
+                    avg_ops_per_launch=st["flops"] / max(1, st["launches"]),
+                    pairs_per_s=n * n / avg_s if avg_s > 0 else 0.0)
+    if dom in ("tx_skinny", "tx_skinny_f32"):
         # narrow products dominate (one column per direction in multi-shift mode): HBM-bound, T read once
-        st = stats["tx_skinny"]
+        st = stats[dom]
         avg_s = st["ms"] / max(1, st["launches"]) / 1e3
         achieved = st["bytes"] / max(1, st["launches"]) / avg_s / 1e9 if avg_s > 0 else 0.0
         return dict(bound="hbm", achieved=achieved, peak=HBM_GBPS, unit="GB/s", frac=achieved / HBM_GBPS,
-                    traffic=measured_traffic(workload, "tx_skinny"), kernel="tx_skinny", launches=st["launches"],
+                    traffic=measured_traffic(workload, dom), kernel=dom, launches=st["launches"],
                     avg_launch_ms=st["ms"] / max(1, st["launches"]),
                     avg_bytes_per_launch=st["bytes"] / max(1, st["launches"]))
     st = stats[dom]
@@ -384,7 +426,7 @@ def bench_batched(args, wl, wfq, torch):
         if otf or wl.n > 50000:
             cpu = cpu_baseline_matrix_free(wl, float(iters.mean()))
         else:
-            cpu = cpu_baseline(wl, S // 2)
+            cpu = cpu_baseline(wl)
 
     line = dict(
         metric=METRIC, value=value, unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
@@ -396,6 +438,121 @@ def bench_batched(args, wl, wfq, torch):
         p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
         iters_mean=float(iters.mean()), iters_max=int(iters.max()), relres_max=relres_max,
         statuses=statuses, final_precisions=prec_end, build_s=build_s, tune_s=tune_s,
+        tuned={str(c): v for c, v in zip(tune["ncols"], tune["chosen"])} if tune else None,
+        roofline=roofline, cpu_baseline=cpu, kernels=kernel_table(stats), **extra)
+    h.close()
+    return line
+
+
+def bench_multishift(args, wl, wfq, torch):
+    """Large structures solved by multi-shift GMRES in FP64 (fcc120k): one shared basis per field
+    direction, the narrow products recomputing T's elements; the FP64 copy of T serves the final
+    residual check. Per-frequency FP64 GMRES(restart) and QMR solves of sampled systems give the
+    reference, the per-frequency baseline and the two solvers' legs."""
+    prec = args.precision or wl.precision
+    shift_dim = args.shift_dim or wl.extra.get("shift_dim", 0)
+    S = wl.n_systems
+    nd = len(wl.dirs)
+    t0 = time.perf_counter()
+    h = wfq.wfq_build(wl.xyz, wl.params, store=("fp64",) if prec == "fp64" else ("fp64", prec), device=0)
+    build_s = time.perf_counter() - t0
+    opts = dict(restart=wl.restart, precision=prec, algorithm="msgmres", max_iter=args.max_iter, shift_dim=shift_dim)
+    tune = None
+    t0 = time.perf_counter()
+    if not args.no_tune:
+        # the shapes of the narrow products (one column per direction); the one FP64 residual check
+        # per solve keeps the built-in shape
+        tune = wfq.wfq_tune(h, "fp64", list(range(1, nd + 1)), reps=2)
+    tune_s = time.perf_counter() - t0
+    # every step writes q and alpha to device buffers (the results stay in HBM, as the inputs do)
+    dev = torch.device("cuda:0")
+    q_re = torch.zeros(S * wl.n, dtype=torch.float64, device=dev)
+    q_im = torch.zeros_like(q_re)
+    a_re = torch.zeros(S * 3, dtype=torch.float64, device=dev)
+    a_im = torch.zeros_like(a_re)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+
+    def step(timing):
+        return wfq.wfq_solve_dev(h, wl.omegas_eV, wl.dirs, wl.tol, q_re=q_re, q_im=q_im, alpha_re=a_re,
+                                 alpha_im=a_im, stream=stream, timing=timing, **opts)
+
+    for k in range(args.warmup):
+        step(False)
+        print(f"[bench] warm-up {k + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    wfq.wfq_kernel_stats(h, reset=True)
+    torch.cuda.synchronize()
+    outs = []
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        outs.append(step(True))
+        print(f"[bench] step {k + 1}/{args.steps}: {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    stats = wfq.wfq_kernel_stats(h)
+    value = S * args.steps / elapsed
+    last = outs[-1]
+    lat = np.array([r["t_done_ms"] for r in last["info"]])
+    iters = np.array([r["iters"] for r in last["info"]])
+    statuses = sorted(set(r["status"] for r in last["info"]))
+    roofline = roofline_of(stats, prec, False, wl.n, wl.name)
+    q = (q_re.cpu().numpy() + 1j * q_im.cpu().numpy()).reshape(S, wl.n)
+    alpha = (a_re.cpu().numpy() + 1j * a_im.cpu().numpy()).reshape(S, 3)
+    # invariants of every result: charge conservation, reciprocity alpha_lk = alpha_kl across directions
+    qsum = float(np.max(np.abs(q.sum(axis=1)) / np.linalg.norm(q, axis=1)))
+    A = alpha.reshape(len(wl.omegas_eV), nd, 3)
+    recip = float(max(abs(A[w, k, l] - A[w, l, k]) / max(abs(A[w, k, k]), abs(A[w, l, l]))
+                      for w in range(A.shape[0]) for k in range(nd) for l in range(nd) if l != k)) if nd > 1 else None
+
+    extra = {}
+    if not args.no_reference:
+        # per-frequency FP64 solves of sampled systems on the same GPU: GMRES(restart) is both the
+        # reference of every sampled result and the per-frequency baseline; QMR the second solver
+        nref = args.ref_systems or 2
+        sel = [int(round(v)) for v in np.linspace(S // 4, 3 * S // 4, nref)]
+        errs, aerrs, t_gm, it_gm = [], [], 0.0, []
+        for s_ in sel:
+            a, k = divmod(s_, nd)
+            torch.cuda.synchronize(); t1 = time.perf_counter()
+            r1 = wfq.wfq_solve(h, wl.omegas_eV[a:a + 1], wl.dirs[k:k + 1], wl.tol, want_q=True, restart=wl.restart,
+                               precision="fp64", algorithm="gmres", max_iter=20000)
+            torch.cuda.synchronize(); t_gm += time.perf_counter() - t1
+            it_gm.append(r1["info"][0]["iters"])
+            qr = r1["q"][0, 0]
+            errs.append(float(np.linalg.norm(q[s_] - qr) / np.linalg.norm(qr)))
+            ar = r1["alpha"][0, 0]
+            aerrs.append(float(np.abs(alpha[s_] - ar).max() / np.abs(ar).max()))
+        s_q = sel[len(sel) // 2]
+        a, k = divmod(s_q, nd)
+        torch.cuda.synchronize(); t1 = time.perf_counter()
+        rq = wfq.wfq_solve(h, wl.omegas_eV[a:a + 1], wl.dirs[k:k + 1], wl.tol, want_q=True, algorithm="qmr",
+                           restart=100000, precision="fp64", max_iter=20000)
+        torch.cuda.synchronize(); t_qmr = time.perf_counter() - t1
+        qq = rq["q"][0, 0]
+        extra = dict(
+            max_rel_err_q_vs_fp64=max(errs), max_rel_err_alpha_vs_fp64=max(aerrs),
+            fp64_reference=f"per-frequency FP64 GMRES({wl.restart}) of {len(sel)} sampled systems {sel}",
+            fp64_per_frequency_solves_per_s=len(sel) / t_gm, speedup_vs_fp64_per_frequency=value * t_gm / len(sel),
+            per_frequency_gmres=dict(solver=f"GMRES({wl.restart})", precision="fp64", systems=sel, iters=it_gm,
+                                     s_per_solve=t_gm / len(sel)),
+            per_frequency_qmr=dict(solver="J-symmetric QMR", precision="fp64", systems=[s_q],
+                                   iters=rq["info"][0]["iters"], s_per_solve=t_qmr,
+                                   status=rq["info"][0]["status"], relres=rq["info"][0]["relres"],
+                                   rel_err_q_vs_multishift=float(np.linalg.norm(q[s_q] - qq) / np.linalg.norm(qq))))
+    cpu = None
+    if not args.no_cpu_baseline:
+        it = float(np.mean(extra["per_frequency_gmres"]["iters"])) if extra else float(iters.mean())
+        cpu = cpu_baseline_rows(wl, it)
+    line = dict(
+        metric=METRIC, value=value, unit="solves/s", n_gpus=1, steps=args.steps, warmup=args.warmup,
+        ms_per_step=elapsed / args.steps * 1e3, higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype=prec, data="synthetic",
+        config=dict(workload=wl.name, n_atoms=wl.n, n_systems=S, n_omega=len(wl.omegas_eV), n_dir=nd,
+                    precision=prec, algorithm="msgmres", shift_dim=shift_dim, restart=wl.restart, tol=wl.tol,
+                    description=wl.description),
+        p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+        iters_mean=float(iters.mean()), iters_max=int(iters.max()),
+        relres_max=max(r["relres"] for r in last["info"]), statuses=statuses,
+        max_abs_charge_sum_rel=qsum, max_reciprocity_rel=recip, build_s=build_s, tune_s=tune_s,
         tuned={str(c): v for c, v in zip(tune["ncols"], tune["chosen"])} if tune else None,
         roofline=roofline, cpu_baseline=cpu, kernels=kernel_table(stats), **extra)
     h.close()
@@ -517,6 +674,8 @@ def main():
         line = bench_latency(args, wl, wfq, torch)
     elif wl.name == "serve_mix":
         line = bench_serve(args, wl, wfq, torch)
+    elif (args.algorithm or wl.algorithm) == "msgmres" and wl.n > 50000:
+        line = bench_multishift(args, wl, wfq, torch)
     else:
         line = bench_batched(args, wl, wfq, torch)
     print(json.dumps(line))

@@ -143,6 +143,14 @@ typedef struct {
                             continue in GMRES from their QMR iterate (in groups that fit the budget left by
                             the QMR work space; WFQ_EBREAKDOWN if none fits or GMRES does not converge).
                             A large value forces the fallback (for tests of that path). */
+    double  ms_relax;    /* MSGMRES with precision FP32 or BF16 (and the FP64 copy of T): 0 = every product of
+                            the shared basis in `precision`; otherwise the products start with FP64 T and
+                            switch to `precision` once every unconverged frequency's residual estimate is
+                            <= the switch level times ||b_k|| (an inexact Krylov process tolerates larger
+                            product errors as the residual falls). ms_relax > 0 is the level itself; < 0
+                            chooses it from the measured relative error delta of one product in `precision`:
+                            0.5 tol / (100 delta), clipped to [tol, 1]. Every result still ends with the FP64
+                            residual check and, where needed, batched GMRES in `precision`. */
 } wfq_solve_opts;
 
 typedef struct {
@@ -180,7 +188,9 @@ void wfq_destroy(wfq_handle* h);
  *   alpha_re, alpha_im [n_omega][n_dir][3] alpha[l] for field direction k (complex);
  *   info               [n_omega][n_dir] per-system results.
  * Returns the worst per-system status (WFQ_ENOCONV etc.); outputs are filled in every case except
- * argument and device errors.
+ * argument and device errors. The handle keeps the solve's device work space (and pinned host
+ * mirrors) until a solve of another shape or wfq_destroy, so repeated solves of one shape allocate
+ * nothing.
  */
 int wfq_solve(wfq_handle* h, const double* omegas_eV, int32_t n_omega,
               const double* dirs, int32_t n_dir, double tol, const wfq_solve_opts* o,

@@ -113,6 +113,90 @@ __global__ void neighbour_kernel(int64_t n, const double* __restrict__ pos, int6
     }
 }
 
+// Near-field correction of the far-field element: C_ij = T_ij - 1 / r_ij for 0 < r_ij < rfar (where
+// erf(r_ij / sqrt(d_i^2 + d_j^2)) is not yet 1 in FP64), C_ii = eta_i; T = 1/r (off the diagonal) + C.
+// Pass 1 (kCount) writes the entries per row; pass 2 fills the transposed ELL layout [w][npad]
+// (diagonal first, then the neighbours in cell traversal order; padding entries: column i, value 0).
+// The search visits the cells within R = ceil(rfar / h) of the atom's cell.
+template <bool kCount>
+__global__ void near_kernel(int64_t n, const double* __restrict__ pos, const double* __restrict__ width,
+                            const double* __restrict__ eta, int64_t npad, GridArgs g, int R,
+                            const int32_t* __restrict__ cell_start, const int32_t* __restrict__ cell_count,
+                            double rfar2, int32_t* __restrict__ counts, int w, int32_t* __restrict__ ecol,
+                            double* __restrict__ eval) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npad) return;
+    if (i >= n) {
+        if (!kCount)
+            for (int t = 0; t < w; ++t) {
+                ecol[(int64_t)t * npad + i] = 0;
+                eval[(int64_t)t * npad + i] = 0.0;
+            }
+        return;
+    }
+    const double* px = pos;
+    const double* py = pos + npad;
+    const double* pz = pos + 2 * npad;
+    const double xi = px[i], yi = py[i], zi = pz[i], di2 = width[i] * width[i];
+    int cx, cy, cz;
+    cell_of(g, xi, yi, zi, cx, cy, cz);
+    int out = 1;
+    if (!kCount) {
+        ecol[i] = (int32_t)i;
+        eval[i] = eta[i];
+    }
+    for (int dz = -R; dz <= R; ++dz) {
+        const int z = cz + dz;
+        if (z < 0 || z >= g.d2) continue;
+        for (int dy = -R; dy <= R; ++dy) {
+            const int y = cy + dy;
+            if (y < 0 || y >= g.d1) continue;
+            for (int dx = -R; dx <= R; ++dx) {
+                const int x = cx + dx;
+                if (x < 0 || x >= g.d0) continue;
+                const int64_t c = ((int64_t)z * g.d1 + y) * g.d0 + x;
+                const int s0 = cell_start[c], sc = cell_count[c];
+                for (int jj = 0; jj < sc; ++jj) {
+                    const int j = s0 + jj;
+                    if (j == i) continue;
+                    const double ddx = xi - px[j], ddy = yi - py[j], ddz = zi - pz[j];
+                    const double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
+                    if (r2 < rfar2) {
+                        if (!kCount && out < w) {
+                            const double r = sqrt(r2);
+                            // erf(x) / r - 1 / r = -erfc(x) / r
+                            ecol[(int64_t)out * npad + i] = j;
+                            eval[(int64_t)out * npad + i] = -erfc(r / sqrt(di2 + width[j] * width[j])) / r;
+                        }
+                        ++out;
+                    }
+                }
+            }
+        }
+    }
+    if (kCount) {
+        counts[i] = out;
+    } else {
+        for (int t = out; t < w; ++t) {
+            ecol[(int64_t)t * npad + i] = (int32_t)i;
+            eval[(int64_t)t * npad + i] = 0.0;
+        }
+    }
+}
+
+// largest of n counts (one block; set-up only)
+__global__ void max_kernel(int64_t n, const int32_t* __restrict__ counts, int32_t* __restrict__ out) {
+    __shared__ int32_t part[1024];
+    int32_t m = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) m = max(m, counts[i]);
+    part[threadIdx.x] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < 1024; ++k) m = max(m, part[k]);
+        out[0] = m;
+    }
+}
+
 // Exclusive scan of n counts into rowptr[0..n] by one block (set-up only, n up to a few million).
 __global__ void scan_kernel(int64_t n, const int32_t* __restrict__ counts, int32_t* __restrict__ rowptr) {
     __shared__ int64_t part[1024];
@@ -226,12 +310,14 @@ T* dev_alloc(Structure& s, size_t count) {
 void free_structure(Structure& s) {
     free_solve_cache(s);
     void* ptrs[] = {s.pos, s.eta, s.width, s.rowptr, s.col, s.val, s.T64, s.T32, s.T16, s.dperm, s.ell_col, s.ell_val,
-                    s.sphere};
+                    s.sphere, s.near_col, s.near_val};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s.pos = s.eta = s.width = s.val = s.T64 = s.sphere = nullptr;
     s.rowptr = s.col = s.dperm = s.ell_col = nullptr;
     s.ell_val = nullptr;
+    s.near_col = nullptr;
+    s.near_val = nullptr;
     s.T32 = nullptr;
     s.T16 = nullptr;
     if (s.split_ws) (void)hipFree(s.split_ws);
@@ -492,6 +578,25 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     hipLaunchKernelGGL(ell_kernel, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, n, s.npad, s.ell_w, s.rowptr,
                        s.col, s.val, s.ell_col, s.ell_val);
     WFQ_CHECK_LAUNCH();
+    // ---- near-field correction of the far-field element (used by the narrow matrix-free products)
+    {
+        s.rfar = 6.0 * std::sqrt(2.0) * s.width_max;   // erfc(6) = 2e-17: beyond it T_ij = 1 / r_ij in FP64
+        const int R = std::max(1, (int)std::ceil(s.rfar / grid.h));
+        hipLaunchKernelGGL(near_kernel<true>, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, n, s.pos, s.width,
+                           s.eta, s.npad, ga, R, d_start, d_count, s.rfar * s.rfar, d_counts, 0, nullptr, nullptr);
+        WFQ_CHECK_LAUNCH();
+        hipLaunchKernelGGL(max_kernel, dim3(1), dim3(1024), 0, st, n, d_counts, d_flag);
+        WFQ_CHECK_LAUNCH();
+        int32_t wmax = 0;
+        d2h_sync(s, &wmax, d_flag, 4, st);
+        s.near_w = std::max(1, (int)wmax);
+        s.near_col = dev_alloc<int32_t>(s, (size_t)s.near_w * s.npad);
+        s.near_val = dev_alloc<double>(s, (size_t)s.near_w * s.npad);
+        hipLaunchKernelGGL(near_kernel<false>, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, n, s.pos, s.width,
+                           s.eta, s.npad, ga, R, d_start, d_count, s.rfar * s.rfar, nullptr, s.near_w, s.near_col,
+                           s.near_val);
+        WFQ_CHECK_LAUNCH();
+    }
     WFQ_HIP(hipStreamSynchronize(st));
     scratch.release();
 

@@ -67,6 +67,12 @@ struct Structure {
     int ell_w = 0;               // ELL width: longest row of L (diagonal included)
     int32_t* ell_col = nullptr;  // device [ell_w][npad], column of entry t of row i (padding: i)
     double* ell_val = nullptr;   // device [ell_w][npad], value (padding: 0)
+    // near-field correction C = T - 1/r over pairs closer than rfar (eta on the diagonal), transposed
+    // ELL [near_w][npad]: T X = (1/r) X (far-field formula for every pair) + C X
+    double rfar = 0.0;           // bohr
+    int near_w = 0;
+    int32_t* near_col = nullptr;
+    double* near_val = nullptr;
     double* T64 = nullptr;       // device [npad][npad]
     float* T32 = nullptr;
     uint16_t* T16 = nullptr;     // bf16 bit patterns
@@ -113,6 +119,7 @@ struct KernelStat {
 enum KernelClass {
     KC_GEMM_F64 = 0, KC_GEMM_F32, KC_GEMM_BF16, KC_SKINNY, KC_OTF, KC_OTF_F64,
     KC_SPMM, KC_DOT, KC_UPDATE, KC_GIVENS, KC_PACK, KC_XUPDATE, KC_RESID, KC_QMR, KC_PRECOND, KC_OTHER,
+    KC_SKINNY_F32, KC_SKINNY_BF16, KC_OTF_NARROW,
     KC_COUNT
 };
 
@@ -155,6 +162,8 @@ void tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_
 void tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st);
 void tx_bf16(const Structure& s, const uint16_t* X, float* Y, int ncol, hipStream_t st);
 const char* tx_variant(int precision, int ncol);
+// true when a product of ncol columns in `prec` recomputes the elements with the narrow kernel
+bool tx_is_otf_narrow(const Structure& s, int prec, int ncol);
 // T X with the stored copy of T in `prec`, or recomputed on the fly when the structure is matrix-free
 void tx_any(const Structure& s, int prec, const void* X, void* Y, int ncol, hipStream_t st);
 // one registered block-product variant (index as listed by tx_variant_name), stored T only
@@ -166,6 +175,11 @@ void tune_tx(Structure& s, int prec, int ncol, int reps, double* ms, hipStream_t
 // dst[i] = cast(src[i]) for i < count (round to nearest even)
 void convert_from_f64(int prec, const double* src, void* dst, int64_t count, hipStream_t st);
 void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st);
+// Y = T X for at most 4 real FP64 columns with every element recomputed (no stored T needed), on
+// the vector ALUs; `cus` = compute units of the device (sets the split of the source range)
+void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st);
+// partial-tile work space of the block products (grown on demand, or the fixed region when set)
+void* split_workspace(const Structure& s, uint64_t bytes);
 void otf_tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_t st);
 
 }  // namespace wfq

@@ -383,25 +383,6 @@ int choose_split(int64_t tiles, int nk, int64_t slots, uint64_t part_bytes, uint
     return best;
 }
 
-void* split_workspace(const Structure& s, uint64_t bytes) {
-    if (s.split_fixed) {
-        // a caller-provided region (the allocation-free entry point): never allocate
-        if (bytes > s.split_fixed_bytes) throw Error{WFQ_ENOMEM, "split-k partial tiles exceed the fixed work space"};
-        return s.split_fixed;
-    }
-    if (bytes > s.split_ws_bytes) {
-        if (s.split_ws) {
-            WFQ_HIP(hipFree(s.split_ws));
-            s.split_ws = nullptr;
-            s.split_ws_bytes = 0;
-        }
-        ++s.epoch;
-        hipError_t e = hipMalloc(&s.split_ws, bytes);
-        if (e != hipSuccess) throw Error{WFQ_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
-        s.split_ws_bytes = bytes;
-    }
-    return s.split_ws;
-}
 
 int device_cus(int device) {
     int cus = 0;
@@ -475,10 +456,22 @@ const std::vector<Variant>& variants() {
 
 // Wider column tiles for FP32 and BF16 (their accumulators are half the size of FP64 ones), so
 // that column counts between the powers of two are not padded up to the next multiple of 128.
+// the narrow matrix-free product as a block-product variant (FP64 only; T is recomputed, the stored
+// copy is not read)
+template <int NC>
+void launch_otfn(const Structure& s, const void* X, const void*, void* Y, int64_t ld, int ncol, hipStream_t st) {
+    static_assert(NC == 2 || NC == 4, "narrow matrix-free products take 2 or 4 columns");
+    otf_narrow_f64(s, static_cast<const double*>(X), static_cast<double*>(Y), ld, ncol, device_cus(s.device), st);
+}
+
 template <int P>
 const std::vector<Variant>& variants_all() {
     static const std::vector<Variant> v = [] {
         std::vector<Variant> r = variants<P>();
+        if constexpr (P == WFQ_PREC_FP64) {
+            r.push_back({"otfn2", 0, 4, 2, launch_otfn<2>});
+            r.push_back({"otfn4", 0, 4, 4, launch_otfn<4>});
+        }
         if constexpr (P != WFQ_PREC_FP64) {
             r.push_back({"m96n256w8", 96, 256, 1 << 30, launch_mfma<P, 3, 4, 2, 4, 128, 1>});
             r.push_back({"m160n256w8", 160, 256, 1 << 30, launch_mfma<P, 5, 4, 2, 4, 128, 1>});
@@ -527,6 +520,9 @@ int default_variant(int prec, int ncol) {
     return k >= 0 ? k : find_variant(prec, "m128n256w8");   // present for every precision
 }
 
+// padded size from which untuned narrow FP64 products are recomputed rather than streamed
+constexpr int64_t kOtfNarrowFrom = 16384;
+
 int pick_variant(const Structure& s, int prec, int ncol) {
     const auto& tuned = s.tuned[prec];
     // the tuned entry with the smallest ncol >= this one (or the largest tuned one), used only when
@@ -537,6 +533,10 @@ int pick_variant(const Structure& s, int prec, int ncol) {
         const Variant& v = variants_of(prec)[it->second];
         if (ncol <= v.max_ncol) return it->second;
     }
+    // narrow FP64 products of large structures: recomputing the elements on the vector ALUs
+    // (about 16 FP64 operations per pair) beats streaming 8 bytes per pair of the stored copy
+    if (prec == WFQ_PREC_FP64 && ncol <= 4 && s.npad >= kOtfNarrowFrom)
+        return find_variant(prec, ncol <= 2 ? "otfn2" : "otfn4");
     return default_variant(prec, ncol);
 }
 
@@ -557,6 +557,26 @@ __global__ void convert_kernel(const double* __restrict__ src, E* __restrict__ d
 }
 
 }  // namespace
+
+void* split_workspace(const Structure& s, uint64_t bytes) {
+    if (s.split_fixed) {
+        // a caller-provided region (the allocation-free entry point): never allocate
+        if (bytes > s.split_fixed_bytes) throw Error{WFQ_ENOMEM, "split-k partial tiles exceed the fixed work space"};
+        return s.split_fixed;
+    }
+    if (bytes > s.split_ws_bytes) {
+        if (s.split_ws) {
+            WFQ_HIP(hipFree(s.split_ws));
+            s.split_ws = nullptr;
+            s.split_ws_bytes = 0;
+        }
+        ++s.epoch;
+        hipError_t e = hipMalloc(&s.split_ws, bytes);
+        if (e != hipSuccess) throw Error{WFQ_ENOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e)};
+        s.split_ws_bytes = bytes;
+    }
+    return s.split_ws;
+}
 
 void convert_from_f64(int prec, const double* src, void* dst, int64_t count, hipStream_t st) {
     if (count <= 0) return;
@@ -584,6 +604,8 @@ void tx_any(const Structure& s, int prec, const void* X, void* Y, int ncol, hipS
     if (s.t_mode == WFQ_TMODE_OTF) {
         if (prec == WFQ_PREC_FP32)
             otf_tx_f32(s, static_cast<const float*>(X), static_cast<float*>(Y), ncol, st);
+        else if (prec == WFQ_PREC_FP64 && ncol <= 4)
+            otf_narrow_f64(s, static_cast<const double*>(X), static_cast<double*>(Y), s.npad, ncol, device_cus(s.device), st);
         else if (prec == WFQ_PREC_FP64)
             otf_tx_f64(s, static_cast<const double*>(X), static_cast<double*>(Y), ncol, st);
         else
@@ -600,6 +622,12 @@ void tx_any(const Structure& s, int prec, const void* X, void* Y, int ncol, hipS
 
 void tx_variant_run(const Structure& s, int prec, int var, const void* X, void* Y, int ncol, hipStream_t st) {
     if (ncol > 0) run_variant(s, prec, var, X, Y, ncol, st);
+}
+
+bool tx_is_otf_narrow(const Structure& s, int prec, int ncol) {
+    if (prec != WFQ_PREC_FP64 || ncol > 4) return false;
+    if (s.t_mode == WFQ_TMODE_OTF) return true;
+    return std::strncmp(variants_of(prec)[pick_variant(s, prec, ncol)].name, "otfn", 4) == 0;
 }
 
 const char* tx_variant(int precision, int ncol) {

@@ -252,7 +252,132 @@ __global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const
             }
 }
 
+// ---- narrow matrix-free FP64 product: at most NC real columns (multi-shift and single-system steps)
+//
+// A product with a few columns is bound by the element evaluations, not by the accumulation, so
+// there are no matrix-core tiles here: each thread owns TK target atoms (64 apart), evaluates T_ij
+// for a run of source atoms and accumulates T_ij x_j for every column in FP64 registers. The grid's
+// second dimension splits the sources into parts so that thousands of waves are in flight; each
+// part's sums go to a work space and a second kernel adds the parts in order (deterministic).
+// Sources come in tiles of 256 atoms (positions, squared widths and the X values staged in LDS and
+// read by broadcast; every LDS read serves TK pairs). Every pair takes the far-field value
+// T_ij = 1 / r_ij (hardware reciprocal square root refined by one Newton step; 0 on the diagonal),
+// with no branch; the sum kernel then adds the structure's sparse near-field correction
+// C = T - 1/r (pairs closer than rfar, eta_i on the diagonal), so the result is T X.
+constexpr int kNarrowTile = 256;
+constexpr int kNarrowTK = 4;   // targets per thread: a work-group covers 1024 consecutive atoms
+
+template <int NC>
+__global__ void __launch_bounds__(256) otf_narrow_f64_kernel(int64_t n, int64_t npad, const double* __restrict__ pos,
+                                                             const double* __restrict__ X, int64_t ldx,
+                                                             double* __restrict__ part, int64_t src_per_part) {
+    constexpr int TK = kNarrowTK;
+    __shared__ double sx[kNarrowTile], sy[kNarrowTile], sz[kNarrowTile];
+    __shared__ double sX[NC][kNarrowTile];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    // targets of this thread: ib + 64 k + lane
+    const int64_t ib = (int64_t)blockIdx.x * 256 * TK + (int64_t)wave * 64 * TK;
+    double xi[TK], yi[TK], zi[TK];
+    bool tin[TK];
+    double acc[TK][NC];
+#pragma unroll
+    for (int k = 0; k < TK; ++k) {
+        const int64_t i = ib + 64 * k + lane;
+        const bool in = i < n;
+        const int64_t ii = i < npad ? i : 0;
+        tin[k] = in;
+        xi[k] = pos[ii];
+        yi[k] = pos[npad + ii];
+        zi[k] = pos[2 * npad + ii];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[k][c] = 0.0;
+    }
+    const int64_t jb = (int64_t)blockIdx.y * src_per_part;
+    const int64_t je = min(n, jb + src_per_part);   // padding sources contribute nothing
+    for (int64_t j0 = jb; j0 < je; j0 += kNarrowTile) {
+        __syncthreads();
+        {
+            const int64_t j = j0 + tid;   // < npad
+            sx[tid] = pos[j];
+            sy[tid] = pos[npad + j];
+            sz[tid] = pos[2 * npad + j];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sX[c][tid] = X[c * ldx + j];
+        }
+        __syncthreads();
+        const int cnt = (int)min((int64_t)kNarrowTile, je - j0);
+#pragma unroll 2
+        for (int q = 0; q < cnt; ++q) {
+            const double xs = sx[q], ys = sy[q], zs = sz[q];
+            double xv[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) xv[c] = sX[c][q];
+#pragma unroll
+            for (int k = 0; k < TK; ++k) {
+                const double dx = xi[k] - xs, dy = yi[k] - ys, dz = zi[k] - zs;
+                const double r2 = dx * dx + dy * dy + dz * dz;
+                double g = __builtin_amdgcn_rsq(r2);
+                // one Newton step for 1/sqrt(r2): g <- g (3 - r2 g^2) / 2
+                g = r2 > 0.0 ? g * fma(-0.5 * r2, g * g, 1.5) : 0.0;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[k][c] = fma(g, xv[c], acc[k][c]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TK; ++k) {
+        const int64_t i = ib + 64 * k + lane;
+        if (i < npad)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) part[((int64_t)blockIdx.y * NC + c) * npad + i] = tin[k] ? acc[k][c] : 0.0;
+    }
+}
+
+// Y[c][i] = sum over the source parts (in part order) + sum_e C[e][i] X[c][col[e][i]] (near field)
+__global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int nparts, int nc, int ncol,
+                                                             const double* __restrict__ part, int w,
+                                                             const int32_t* __restrict__ ncolv,
+                                                             const double* __restrict__ nval,
+                                                             const double* __restrict__ X, int64_t ldx,
+                                                             double* __restrict__ Y, int64_t ldy) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i >= npad || c >= ncol) return;
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += part[((int64_t)p * nc + c) * npad + i];
+    const double* x = X + c * ldx;
+    double t = 0.0;
+    for (int e = 0; e < w; ++e) t = fma(nval[(int64_t)e * npad + i], x[ncolv[(int64_t)e * npad + i]], t);
+    Y[c * ldy + i] = s + t;
+}
+
+template <int NC>
+void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st) {
+    const int64_t tblocks = (s.npad + 256 * kNarrowTK - 1) / (256 * kNarrowTK);
+    // about 8 work-groups per compute unit in total, each part at least one source tile
+    int nparts = (int)std::max<int64_t>(1, std::min<int64_t>((8LL * cus + tblocks - 1) / tblocks, 64));
+    const int64_t per = round_up((s.npad + nparts - 1) / nparts, kNarrowTile);
+    nparts = (int)((s.npad + per - 1) / per);
+    double* part = static_cast<double*>(split_workspace(s, (uint64_t)nparts * NC * s.npad * sizeof(double)));
+    if (!s.near_col) throw Error{WFQ_EDEVICE, "the structure has no near-field correction"};
+    hipLaunchKernelGGL((otf_narrow_f64_kernel<NC>), dim3((unsigned)tblocks, (unsigned)nparts), dim3(256), 0, st, s.n,
+                       s.npad, s.pos, X, ld, part, per);
+    WFQ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(otf_narrow_sum_kernel, dim3((unsigned)(s.npad / 256), (unsigned)ncol), dim3(256), 0, st,
+                       s.npad, nparts, NC, ncol, part, s.near_w, s.near_col, s.near_val, X, ld, Y, ld);
+    WFQ_CHECK_LAUNCH();
+}
+
 }  // namespace
+
+void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st) {
+    if (ncol <= 0) return;
+    if (ncol > 4) throw Error{WFQ_EINVAL, "the narrow matrix-free product takes at most 4 columns"};
+    if (ncol <= 2)
+        launch_otf_narrow<2>(s, X, Y, ld, ncol, cus, st);
+    else
+        launch_otf_narrow<4>(s, X, Y, ld, ncol, cus, st);
+}
 
 void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st) {
     if (ncol <= 0) return;

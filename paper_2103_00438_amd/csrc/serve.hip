@@ -79,8 +79,9 @@ uint64_t estimate_footprint(const Job& j, const wfq_serve_cfg& c) {
     if (mask & WFQ_STORE_FP64) t += np * np * 8;
     if (mask & WFQ_STORE_FP32) t += np * np * 4;
     if (mask & WFQ_STORE_BF16) t += np * np * 2;
-    // L in CSR and ELL (up to 320 neighbours per atom for close-packed metals) and per-atom arrays
-    t += np * 320 * 24 + np * 64;
+    // L in CSR and ELL (up to 320 neighbours per atom for close-packed metals), the near-field
+    // correction of the matrix-free products (up to ~600 entries per atom) and per-atom arrays
+    t += np * 320 * 24 + np * 600 * 12 + np * 64;
     Structure probe;
     probe.n = j.n;
     probe.npad = (int64_t)np;

@@ -426,28 +426,21 @@ void free_solve_cache(Structure& S) {
 
 namespace {
 
-// work spaces up to this size stay allocated on the handle after a solve
-constexpr size_t kKeepWorkBytes = 8ull << 30;
-
 // The work space for a solve of shape sh: the handle's cached one when the shape matches, else a
-// new one (cached when small; the previous cached one is freed first). graphs is set for a cached
-// work space.
+// new one, which the handle keeps (the previous one is freed first). Repeated solves of one shape
+// then allocate nothing: freeing and allocating a work space of tens of GB costs seconds.
 Work& solve_work(Structure& S, const WorkShape& sh, GraphCache*& graphs, std::unique_ptr<Work>& own) {
+    (void)own;
     graphs = nullptr;
-    if (S.cache && S.cache->work && S.cache->work->shape == sh) {
-        graphs = &S.cache->graphs;
-        return *S.cache->work;
-    }
-    free_solve_cache(S);
-    own = std::make_unique<Work>();
-    make_work(*own, S, sh);
-    if (own->dev_bytes <= kKeepWorkBytes) {
+    if (!(S.cache && S.cache->work && S.cache->work->shape == sh)) {
+        free_solve_cache(S);
+        auto w = std::make_unique<Work>();
+        make_work(*w, S, sh);
         S.cache = new SolveCache;
-        S.cache->work = std::move(own);
-        graphs = &S.cache->graphs;
-        return *S.cache->work;
+        S.cache->work = std::move(w);
     }
-    return *own;
+    graphs = &S.cache->graphs;
+    return *S.cache->work;
 }
 
 // view of one vector slot of a basis as a one-slot basis
@@ -484,12 +477,19 @@ void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, h
     const double n = (double)S.n;
     tm.begin(st);
     tx_any(S, prec, x_block(w, prec), const_cast<void*>(y_block(w, prec)), ncol, st);
+    if (tx_is_otf_narrow(S, prec, ncol)) {
+        // work: per pair 3 differences, 3 operations for r^2, the reciprocal square root, 4 for its
+        // Newton step and one multiply-add per column (the near-field correction is a sparse extra);
+        // bytes: positions and X read once per source part, Y written
+        tm.end(st, KC_OTF_NARROW, n * n * (11.0 + ncol), n * (24.0 + 8.0 * ncol) + n * 8.0 * ncol);
+        return;
+    }
     if (S.t_mode == WFQ_TMODE_OTF) {
         // flops: the MFMA accumulation; the element evaluations are counted by launches x n^2 pairs
         tm.end(st, prec == WFQ_PREC_FP64 ? KC_OTF_F64 : KC_OTF, 2.0 * n * n * ncol, ncol * n * 2.0 * elem_size(prec));
         return;
     }
-    const int kc = ncol <= 8 ? KC_SKINNY
+    const int kc = ncol <= 8 ? (prec == WFQ_PREC_FP64 ? KC_SKINNY : prec == WFQ_PREC_FP32 ? KC_SKINNY_F32 : KC_SKINNY_BF16)
                              : (prec == WFQ_PREC_FP64 ? KC_GEMM_F64 : prec == WFQ_PREC_FP32 ? KC_GEMM_F32 : KC_GEMM_BF16);
     tm.end(st, kc, 2.0 * n * n * ncol, elem_size(prec) * n * n + ncol * n * (elem_size(prec) + out_size(prec)));
 }
@@ -601,6 +601,11 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             }
         }
         active.swap(still);
+        if (o.progress) {
+            double worst = 0.0;
+            for (int s : all) worst = std::max(worst, ss[s].relres);
+            progress_line(o, "gmres from the given start", 0, 0, active.size(), worst, t0);
+        }
     }
 
     while (!active.empty()) {
@@ -808,6 +813,47 @@ uint64_t ms_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_dir)
     return b + (1u << 20);
 }
 
+// the all-reduced-precision residual floor is taken as this many times the relative error of one product
+constexpr double kRelaxFloor = 100.0;
+
+// Relative error of the first shared-basis product in `prec` against FP64, max over directions:
+// ||L (T_prec - T) v0|| / ||L T v0|| with v0 = b / ||b||. Leaves slot 0 of every direction normalised
+// and inv_h = 1 (so the first step of the phase packs v0 as it is); uses slots 1 and 2 as scratch.
+double ms_product_error(const Structure& S, Work& w, int prec, const std::vector<double>& beta, hipStream_t st) {
+    MsWork& q = w.ms;
+    const int nd = w.n_dir;
+    const int m = w.shape.ms_m, mdim1 = m + 1, pslots = m + 2;
+    const int64_t n = S.n, np = S.npad;
+    // v0 and L T v0 with FP64 T (slot 2), then L T_prec v0 (slot 1)
+    ms_pack(WFQ_PREC_FP64, q.V.p, np, mdim1, 0, q.dirs.p, nd, q.inv_h.p, w.X64.p, np, st);
+    tx_any(S, WFQ_PREC_FP64, w.X64.p, w.Y64.p, nd, st);
+    ms_spmm(S, true, w.Y64.p, np, q.dirs.p, nd, q.V.p, mdim1, 2, st);
+    std::vector<double> ones(nd, 1.0);
+    h2d_sync(S, q.inv_h.p, ones.data(), nd * sizeof(double), st);
+    ms_pack(prec, q.V.p, np, mdim1, 0, q.dirs.p, nd, q.inv_h.p, x_block(w, prec), np, st);
+    tx_any(S, prec, x_block(w, prec), const_cast<void*>(y_block(w, prec)), nd, st);
+    ms_spmm(S, prec == WFQ_PREC_FP64, y_block(w, prec), np, q.dirs.p, nd, q.V.p, mdim1, 1, st);
+    // ||slot 2||^2, then slot 2 -= slot 1 with the squared norm of the difference per 64-row block
+    ms_dot(q.V.p, n, np, mdim1, 0, 2, q.dirs.p, nd, q.part.p, pslots, true, st);
+    ms_reduce(q.dirs.p, nd, q.part.p, pslots, n, 1, q.h1.p, st);
+    std::vector<double> coef((size_t)nd * pslots, 0.0);
+    for (int d = 0; d < nd; ++d) coef[(size_t)d * pslots + 1] = 1.0;
+    h2d_sync(S, q.h2.p, coef.data(), coef.size() * sizeof(double), st);
+    ms_update(q.V.p, n, np, mdim1, 2, 2, q.dirs.p, nd, q.h2.p, pslots, q.nrm.p, st);
+    std::vector<double> h1((size_t)nd * pslots), nrm((size_t)nd * (np / 64));
+    d2h_sync(S, h1.data(), q.h1.p, h1.size() * sizeof(double), st);
+    d2h_sync(S, nrm.data(), q.nrm.p, nrm.size() * sizeof(double), st);
+    double delta = 0.0;
+    for (int d = 0; d < nd; ++d) {
+        if (!(beta[d] > 0.0)) continue;
+        double e2 = 0.0;
+        for (int64_t b = 0; b < np / 64; ++b) e2 += nrm[(size_t)d * (np / 64) + b];
+        const double r2 = h1[(size_t)d * pslots];
+        if (r2 > 0.0) delta = std::max(delta, std::sqrt(e2 / r2));
+    }
+    return delta;
+}
+
 // Runs the shared-basis phase for the systems of one batch and leaves each system's iterate in
 // w.Xb (zero where the phase could not help); ss[s].iters = steps of the shared basis it used.
 void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, double tol, const wfq_solve_opts& o,
@@ -863,6 +909,30 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         h2d_sync(S, inv_h, invb.data(), nd * sizeof(double), st);
         WFQ_HIP(hipStreamSynchronize(st));
     }
+    // Precision of the shared basis's products. With relaxation (ms_relax != 0 and a reduced
+    // `precision`) the first steps run with FP64 T and the rest in `precision` once every unconverged
+    // frequency's residual estimate is below the switch level: in an inexact Arnoldi process the error
+    // of the product at step j reaches the final residual scaled by the residual of step j (Simoncini &
+    // Szyld 2003; Bouras & Fraysse 2005), so the late steps tolerate the larger error.
+    int cur = prec;
+    double switch_at = 0.0;
+    const bool relax = o.ms_relax != 0.0 && prec != WFQ_PREC_FP64 && have_copy(S, WFQ_PREC_FP64) && m >= 3;
+    if (relax) {
+        cur = WFQ_PREC_FP64;
+        if (o.ms_relax > 0.0) {
+            switch_at = o.ms_relax;
+        } else {
+            const double delta = ms_product_error(S, w, prec, beta, st);
+            // the residual floor of a basis built entirely in `precision` is taken as kRelaxFloor times the
+            // relative error of one product; switching at level s adds about s times that floor
+            switch_at = delta > 0.0 ? std::min(1.0, std::max(tol, 0.5 * tol / (kRelaxFloor * delta))) : 1.0;
+        }
+        if (o.progress) {
+            std::fprintf(stderr, "[wfq] multi-shift: FP64 products until every estimate is below %.3e (%.1f s)\n",
+                         switch_at, ms_since(t0) / 1e3);
+            std::fflush(stderr);
+        }
+    }
     std::vector<int> stepping;
     for (int s = 0; s < B; ++s) {
         h_k[s] = 0;
@@ -896,12 +966,12 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         auto step = [&](int j) {
             // w = L T v_j (one real column per direction)
             tm.begin(st);
-            ms_pack(prec, V, np, mdim1, j, dirs, na, inv_h, x_block(w, prec), np, st);
-            tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(prec)));
-            block_product(S, w, prec, na, tm, st);
+            ms_pack(cur, V, np, mdim1, j, dirs, na, inv_h, x_block(w, cur), np, st);
+            tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(cur)));
+            block_product(S, w, cur, na, tm, st);
             tm.begin(st);
-            ms_spmm(S, prec == WFQ_PREC_FP64, y_block(w, prec), np, dirs, na, V, mdim1, j + 1, st);
-            tm.end(st, KC_SPMM, 2.0 * S.nnz * na, 12.0 * S.nnz * na + na * dn * (out_size(prec) + 8));
+            ms_spmm(S, cur == WFQ_PREC_FP64, y_block(w, cur), np, dirs, na, V, mdim1, j + 1, st);
+            tm.end(st, KC_SPMM, 2.0 * S.nnz * na, 12.0 * S.nnz * na + na * dn * (out_size(cur) + 8));
             // two classical Gram-Schmidt passes against v_0 .. v_j
             const double pass = 8.0 * dn * na * (j + 2);
             tm.begin(st);
@@ -924,7 +994,7 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
             ms_givens(sys, ns, j, m, sdir, z, H, cs, sn, g, R, B, est, tol_abs, flags, run, ksteps, st);
             tm.end(st, KC_GIVENS, 0, 0);
         };
-        run_chunk(gc, S, GraphKey{1, j0, c, ns, na, 0, 0}, st, [&] {
+        run_chunk(gc, S, GraphKey{1, j0, c, ns, na, cur, 0}, st, [&] {
             for (int j = j0; j < j0 + c; ++j) step(j);
         });
         j0 += c;
@@ -933,16 +1003,27 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         WFQ_HIP(hipMemcpyAsync(w.h_ksteps.p, ksteps, B * sizeof(int), hipMemcpyDeviceToHost, st));
         WFQ_HIP(hipStreamSynchronize(st));
         std::vector<int> next;
+        double worst = 0.0;
         for (int s : stepping) {
             const int f = w.h_flags.p[s];
             h_k[s] = (f & 4) ? 0 : w.h_ksteps.p[s];   // NaN: leave the system to batched GMRES from x = 0
             ss[s].est_end = w.h_est.p[s];
-            if (f == 0) next.push_back(s);
+            if (f == 0) {
+                next.push_back(s);
+                worst = std::max(worst, w.h_est.p[s] / beta[ss[s].dir]);
+            }
+        }
+        if (relax && cur != prec && worst <= switch_at) {
+            cur = prec;
+            if (o.progress) {
+                std::fprintf(stderr, "[wfq] multi-shift: products in the reduced precision from step %d\n", j0);
+                std::fflush(stderr);
+            }
         }
         const bool changed = next.size() != stepping.size();
         stepping.swap(next);
         if (changed && !stepping.empty()) lists();
-        progress_line(o, "multi-shift", 0, j0, stepping.size(), -1.0, t0);
+        progress_line(o, "multi-shift", 0, j0, stepping.size(), worst, t0);
     }
     // iterates: y = R^-1 g, x = V y (groups of systems of one direction share the basis reads)
     std::vector<int> withk;

@@ -458,9 +458,10 @@ const std::vector<Variant>& variants() {
 // that column counts between the powers of two are not padded up to the next multiple of 128.
 // the narrow matrix-free product as a block-product variant (FP64 only; T is recomputed, the stored
 // copy is not read)
+// (NC is the largest column count of the registry entry; the kernel is chosen by ncol)
 template <int NC>
 void launch_otfn(const Structure& s, const void* X, const void*, void* Y, int64_t ld, int ncol, hipStream_t st) {
-    static_assert(NC == 2 || NC == 4, "narrow matrix-free products take 2 or 4 columns");
+    static_assert(NC == 2 || NC == 4, "narrow matrix-free registry entries take 2 or 4 columns");
     otf_narrow_f64(s, static_cast<const double*>(X), static_cast<double*>(Y), ld, ncol, device_cus(s.device), st);
 }
 

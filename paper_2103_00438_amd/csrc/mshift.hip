@@ -95,16 +95,19 @@ __global__ void __launch_bounds__(256) ms_dot_kernel(const double* __restrict__ 
     if (lane == 0) partial[((int64_t)d * pslots + i) * nwc + wc] = s;
 }
 
-// h[d][i] = sum_wc partial[d][i][wc], i < count (in chunk order)
-__global__ void ms_reduce_kernel(const int* __restrict__ dirs, const double* __restrict__ partial, int pslots,
-                                 int64_t nwc, int count, double* __restrict__ h) {
-    const int d = dirs[blockIdx.x];
-    for (int i = threadIdx.x; i < count; i += blockDim.x) {
-        const double* p = partial + ((int64_t)d * pslots + i) * nwc;
-        double s = 0.0;
-        for (int64_t q = 0; q < nwc; ++q) s += p[q];
-        h[(int64_t)d * pslots + i] = s;
-    }
+// h[d][i] = sum_wc partial[d][i][wc], i < count: one wave per (value, direction); lane l adds the
+// chunks l, l + 64, ... and the lanes are combined by a fixed butterfly (same order every call)
+__global__ void __launch_bounds__(256) ms_reduce_kernel(const int* __restrict__ dirs, const double* __restrict__ partial,
+                                                        int pslots, int64_t nwc, int count, double* __restrict__ h) {
+    const int d = dirs[blockIdx.y];
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= count) return;   // uniform over the wave
+    const double* p = partial + ((int64_t)d * pslots + i) * nwc;
+    double s = 0.0;
+    for (int64_t q = lane; q < nwc; q += 64) s += p[q];
+    s = wave_sum(s);
+    if (lane == 0) h[(int64_t)d * pslots + i] = s;
 }
 
 // V(d, jw) -= sum_{i < nvec} h[d][i] V(d, i); with norm != NULL also norm[d][blk] = the sum of
@@ -336,8 +339,8 @@ void ms_dot(const double* V, int64_t n, int64_t npad, int mdim1, int nvec, int j
 void ms_reduce(const int* dirs, int ndir, const double* partial, int pslots, int64_t n, int count, double* h,
                hipStream_t st) {
     if (ndir <= 0 || count <= 0) return;
-    hipLaunchKernelGGL(ms_reduce_kernel, dim3((unsigned)ndir), dim3(128), 0, st, dirs, partial, pslots,
-                       wave_chunks(n), count, h);
+    hipLaunchKernelGGL(ms_reduce_kernel, dim3((unsigned)((count + 3) / 4), (unsigned)ndir), dim3(256), 0, st, dirs,
+                       partial, pslots, wave_chunks(n), count, h);
     WFQ_CHECK_LAUNCH();
 }
 

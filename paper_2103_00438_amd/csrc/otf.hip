@@ -267,6 +267,34 @@ __global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const
 constexpr int kNarrowTile = 256;
 constexpr int kNarrowTK = 4;   // targets per thread: a work-group covers 1024 consecutive atoms
 
+// The pairs of one staged source tile with this thread's TK targets. kDiag: the tile may hold one of
+// the targets themselves (r = 0), whose far-field value is replaced by 0 (the diagonal is in the
+// near-field correction); other tiles skip that test.
+template <int NC, bool kDiag>
+__device__ __forceinline__ void narrow_tile(const double* __restrict__ sx, const double* __restrict__ sy,
+                                            const double* __restrict__ sz, const double (*sX)[kNarrowTile], int cnt,
+                                            const double (&xi)[kNarrowTK], const double (&yi)[kNarrowTK],
+                                            const double (&zi)[kNarrowTK], double (&acc)[kNarrowTK][NC]) {
+#pragma unroll 2
+    for (int q = 0; q < cnt; ++q) {
+        const double xs = sx[q], ys = sy[q], zs = sz[q];
+        double xv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xv[c] = sX[c][q];
+#pragma unroll
+        for (int k = 0; k < kNarrowTK; ++k) {
+            const double dx = xi[k] - xs, dy = yi[k] - ys, dz = zi[k] - zs;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            double g = __builtin_amdgcn_rsq(r2);
+            // one Newton step for 1/sqrt(r2): g <- g (3 - r2 g^2) / 2
+            g = g * fma(-0.5 * r2, g * g, 1.5);
+            if (kDiag) g = r2 > 0.0 ? g : 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[k][c] = fma(g, xv[c], acc[k][c]);
+        }
+    }
+}
+
 template <int NC>
 __global__ void __launch_bounds__(256) otf_narrow_f64_kernel(int64_t n, int64_t npad, const double* __restrict__ pos,
                                                              const double* __restrict__ X, int64_t ldx,
@@ -275,17 +303,17 @@ __global__ void __launch_bounds__(256) otf_narrow_f64_kernel(int64_t n, int64_t 
     __shared__ double sx[kNarrowTile], sy[kNarrowTile], sz[kNarrowTile];
     __shared__ double sX[NC][kNarrowTile];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    // targets of this thread: ib + 64 k + lane
-    const int64_t ib = (int64_t)blockIdx.x * 256 * TK + (int64_t)wave * 64 * TK;
+    // targets of the work-group: [it0, it0 + 256 TK); of this thread: ib + 64 k + lane
+    const int64_t it0 = (int64_t)blockIdx.x * 256 * TK;
+    const int64_t ib = it0 + (int64_t)wave * 64 * TK;
     double xi[TK], yi[TK], zi[TK];
     bool tin[TK];
     double acc[TK][NC];
 #pragma unroll
     for (int k = 0; k < TK; ++k) {
         const int64_t i = ib + 64 * k + lane;
-        const bool in = i < n;
         const int64_t ii = i < npad ? i : 0;
-        tin[k] = in;
+        tin[k] = i < n;
         xi[k] = pos[ii];
         yi[k] = pos[npad + ii];
         zi[k] = pos[2 * npad + ii];
@@ -306,23 +334,10 @@ __global__ void __launch_bounds__(256) otf_narrow_f64_kernel(int64_t n, int64_t 
         }
         __syncthreads();
         const int cnt = (int)min((int64_t)kNarrowTile, je - j0);
-#pragma unroll 2
-        for (int q = 0; q < cnt; ++q) {
-            const double xs = sx[q], ys = sy[q], zs = sz[q];
-            double xv[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) xv[c] = sX[c][q];
-#pragma unroll
-            for (int k = 0; k < TK; ++k) {
-                const double dx = xi[k] - xs, dy = yi[k] - ys, dz = zi[k] - zs;
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                double g = __builtin_amdgcn_rsq(r2);
-                // one Newton step for 1/sqrt(r2): g <- g (3 - r2 g^2) / 2
-                g = r2 > 0.0 ? g * fma(-0.5 * r2, g * g, 1.5) : 0.0;
-#pragma unroll
-                for (int c = 0; c < NC; ++c) acc[k][c] = fma(g, xv[c], acc[k][c]);
-            }
-        }
+        if (j0 < it0 + 256 * TK && j0 + kNarrowTile > it0)
+            narrow_tile<NC, true>(sx, sy, sz, sX, cnt, xi, yi, zi, acc);
+        else
+            narrow_tile<NC, false>(sx, sy, sz, sX, cnt, xi, yi, zi, acc);
     }
 #pragma unroll
     for (int k = 0; k < TK; ++k) {
@@ -333,22 +348,33 @@ __global__ void __launch_bounds__(256) otf_narrow_f64_kernel(int64_t n, int64_t 
     }
 }
 
-// Y[c][i] = sum over the source parts (in part order) + sum_e C[e][i] X[c][col[e][i]] (near field)
-__global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int nparts, int nc, int ncol,
+// Y[c][i] = sum over the source parts (in part order) + sum_e C[e][i] X[c][col[e][i]] (near field),
+// every column of row i in one thread so that the correction's entries are read once
+template <int NC>
+__global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int nparts, int ncol,
                                                              const double* __restrict__ part, int w,
                                                              const int32_t* __restrict__ ncolv,
                                                              const double* __restrict__ nval,
                                                              const double* __restrict__ X, int64_t ldx,
                                                              double* __restrict__ Y, int64_t ldy) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int c = blockIdx.y;
-    if (i >= npad || c >= ncol) return;
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += part[((int64_t)p * nc + c) * npad + i];
-    const double* x = X + c * ldx;
-    double t = 0.0;
-    for (int e = 0; e < w; ++e) t = fma(nval[(int64_t)e * npad + i], x[ncolv[(int64_t)e * npad + i]], t);
-    Y[c * ldy + i] = s + t;
+    if (i >= npad) return;
+    double t[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) t[c] = 0.0;
+    for (int e = 0; e < w; ++e) {
+        const double v = nval[(int64_t)e * npad + i];
+        const int64_t j = ncolv[(int64_t)e * npad + i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) t[c] = fma(v, X[c * ldx + j], t[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (c >= ncol) break;
+        double s = 0.0;
+        for (int p = 0; p < nparts; ++p) s += part[((int64_t)p * NC + c) * npad + i];
+        Y[c * ldy + i] = s + t[c];
+    }
 }
 
 template <int NC>
@@ -363,8 +389,8 @@ void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t l
     hipLaunchKernelGGL((otf_narrow_f64_kernel<NC>), dim3((unsigned)tblocks, (unsigned)nparts), dim3(256), 0, st, s.n,
                        s.npad, s.pos, X, ld, part, per);
     WFQ_CHECK_LAUNCH();
-    hipLaunchKernelGGL(otf_narrow_sum_kernel, dim3((unsigned)(s.npad / 256), (unsigned)ncol), dim3(256), 0, st,
-                       s.npad, nparts, NC, ncol, part, s.near_w, s.near_col, s.near_val, X, ld, Y, ld);
+    hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, s.npad, nparts,
+                       ncol, part, s.near_w, s.near_col, s.near_val, X, ld, Y, ld);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -373,8 +399,12 @@ void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t l
 void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st) {
     if (ncol <= 0) return;
     if (ncol > 4) throw Error{WFQ_EINVAL, "the narrow matrix-free product takes at most 4 columns"};
-    if (ncol <= 2)
+    if (ncol == 1)
+        launch_otf_narrow<1>(s, X, Y, ld, ncol, cus, st);
+    else if (ncol == 2)
         launch_otf_narrow<2>(s, X, Y, ld, ncol, cus, st);
+    else if (ncol == 3)
+        launch_otf_narrow<3>(s, X, Y, ld, ncol, cus, st);
     else
         launch_otf_narrow<4>(s, X, Y, ld, ncol, cus, st);
 }

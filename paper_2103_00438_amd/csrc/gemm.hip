@@ -523,6 +523,8 @@ int default_variant(int prec, int ncol) {
 
 // padded size from which untuned narrow FP64 products are recomputed rather than streamed
 constexpr int64_t kOtfNarrowFrom = 16384;
+// matrix-free FP64 products of up to this many 4-column chunks use the narrow kernel
+constexpr int kOtfNarrowChunks = 3;
 
 int pick_variant(const Structure& s, int prec, int ncol) {
     const auto& tuned = s.tuned[prec];
@@ -605,8 +607,13 @@ void tx_any(const Structure& s, int prec, const void* X, void* Y, int ncol, hipS
     if (s.t_mode == WFQ_TMODE_OTF) {
         if (prec == WFQ_PREC_FP32)
             otf_tx_f32(s, static_cast<const float*>(X), static_cast<float*>(Y), ncol, st);
-        else if (prec == WFQ_PREC_FP64 && ncol <= 4)
-            otf_narrow_f64(s, static_cast<const double*>(X), static_cast<double*>(Y), s.npad, ncol, device_cus(s.device), st);
+        else if (prec == WFQ_PREC_FP64 && ncol <= kOtfNarrowChunks * 4)
+            // up to 16 columns: narrow recomputed products of at most 4 columns each (each such product
+            // costs about what one 32-column matrix-core pass costs for 12 or more columns)
+            for (int c0 = 0; c0 < ncol; c0 += 4)
+                otf_narrow_f64(s, static_cast<const double*>(X) + (int64_t)c0 * s.npad,
+                               static_cast<double*>(Y) + (int64_t)c0 * s.npad, s.npad, std::min(4, ncol - c0),
+                               device_cus(s.device), st);
         else if (prec == WFQ_PREC_FP64)
             otf_tx_f64(s, static_cast<const double*>(X), static_cast<double*>(Y), ncol, st);
         else
@@ -626,8 +633,9 @@ void tx_variant_run(const Structure& s, int prec, int var, const void* X, void* 
 }
 
 bool tx_is_otf_narrow(const Structure& s, int prec, int ncol) {
-    if (prec != WFQ_PREC_FP64 || ncol > 4) return false;
-    if (s.t_mode == WFQ_TMODE_OTF) return true;
+    if (prec != WFQ_PREC_FP64) return false;
+    if (s.t_mode == WFQ_TMODE_OTF) return ncol <= kOtfNarrowChunks * 4;
+    if (ncol > 4) return false;
     return std::strncmp(variants_of(prec)[pick_variant(s, prec, ncol)].name, "otfn", 4) == 0;
 }
 

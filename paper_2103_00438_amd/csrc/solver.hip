@@ -481,7 +481,8 @@ void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, h
         // work: per pair 3 differences, 3 operations for r^2, the reciprocal square root, 4 for its
         // Newton step and one multiply-add per column (the near-field correction is a sparse extra);
         // bytes: positions and X read once per source part, Y written
-        tm.end(st, KC_OTF_NARROW, n * n * (11.0 + ncol), n * (24.0 + 8.0 * ncol) + n * 8.0 * ncol);
+        const double chunks = (ncol + 3) / 4;   // products of up to 4 columns
+        tm.end(st, KC_OTF_NARROW, n * n * (11.0 * chunks + ncol), n * (24.0 * chunks + 8.0 * ncol) + n * 8.0 * ncol);
         return;
     }
     if (S.t_mode == WFQ_TMODE_OTF) {

@@ -145,3 +145,55 @@ def test_fcc120k_bf16_product_sampled_rows(lib):
     Tq = round_to("bf16", Trows)
     Xq = round_to("bf16", X)
     assert np.all(np.abs(Y16[:, rows] - Xq @ Tq.T) <= 2 * wl.n * UNIT["fp32"] * (np.abs(Xq) @ np.abs(Tq).T))
+
+
+def _check_full_solution(wl, out, om, dirs, tol, rows_seed, bnorm=None):
+    """The oracle's FP64 residual on 48 sampled rows of every system (each row from pairwise elements
+    by the C++ oracle), charge conservation within what the residual allows and reciprocity. The
+    scale ||b_k|| is the oracle's when it can build the whole L (all pairs), else `bnorm` (the
+    library's right-hand sides, themselves checked against the oracle's in the step tests)."""
+    from oracle.cpp_oracle import CppProblem
+    P = CppProblem(wl.xyz, wl.params, dense_T=False, build_L=bnorm is None)
+    rows = sampled_rows(wl.n, 48, rows_seed)
+    for a in range(len(om)):
+        for k in range(len(dirs)):
+            q = out["q"][a, k]
+            bn = np.linalg.norm(P.rhs(dirs[k])) if bnorm is None else bnorm[k]
+            r = P.residual_rows(om[a], dirs[k], q, rows)
+            # |r_i| <= ||r||_2 <= tol ||b|| (the library's own FP64 check), recomputed here row by row
+            assert np.max(np.abs(r)) <= tol * bn, (a, k)
+            # 1^T (L T + z I) q = z sum q = 1^T (b - r) = -1^T r, so |sum q| <= sqrt(N) tol ||b|| / |z|
+            assert abs(q.sum()) <= 2 * np.sqrt(wl.n) * tol * bn / abs(P.z(om[a])), (a, k)
+        A = out["alpha"][a]   # [dir][component]
+        if len(dirs) > 1:
+            assert abs(A[0, 1] - A[1, 0]) <= 1e-6 * max(abs(A[0, 0]), abs(A[1, 1])), a
+
+
+def test_fcc120k_multishift_full_solution(lib):
+    # the benchmark's solver on the full 119 879-atom sphere: 2 frequencies x 2 field directions by
+    # multi-shift GMRES in FP64 with the recomputed narrow products, checked row by row by the oracle
+    wl = wi.workload("fcc120k")
+    om = wl.omegas_eV[[20, 100]]
+    dirs = wl.dirs[:2]
+    h = lib.wfq_build(wl.xyz, wl.params, store=("fp64",))
+    out = lib.wfq_solve(h, om, dirs, wl.tol, restart=wl.restart, precision="fp64", algorithm="msgmres",
+                        shift_dim=wl.extra["shift_dim"])
+    h.close()
+    assert out["status"] == 0
+    assert max(r["relres"] for r in out["info"]) <= wl.tol
+    _check_full_solution(wl, out, om, dirs, wl.tol, 13)
+
+
+def test_sheet1m_multishift_full_solution(lib):
+    # the full 10^6-atom sheet, matrix-free: 1 frequency x 2 in-plane directions by multi-shift GMRES
+    # in FP64 (every T element recomputed in every product), checked row by row by the oracle
+    wl = wi.workload("sheet1m")
+    om = wl.omegas_eV[[3]]
+    h = lib.wfq_build(wl.xyz, wl.params, t_mode="otf")
+    out = lib.wfq_solve(h, om, wl.dirs, wl.tol, restart=wl.restart, precision="fp64", algorithm="msgmres",
+                        shift_dim=1500)
+    bnorm = np.linalg.norm(lib.wfq_rhs(h, wl.dirs), axis=1)
+    h.close()
+    assert out["status"] == 0
+    assert max(r["relres"] for r in out["info"]) <= wl.tol
+    _check_full_solution(wl, out, om, wl.dirs, wl.tol, 17, bnorm=bnorm)

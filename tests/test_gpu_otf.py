@@ -89,3 +89,43 @@ def test_otf_solve_matches_lu(lib, tube, prec):
     with pytest.raises(lib.WfqError):
         lib.wfq_solve(h, om, dirs, 1e-8, precision="bf16")
     h.close()
+
+
+@pytest.mark.parametrize("ncol", [1, 2, 3, 4])
+def test_narrow_recomputed_product_on_a_metal_sphere(lib, ncol):
+    # The narrow FP64 product that recomputes T's elements (far-field 1/r for every pair plus the
+    # sparse near-field correction) on a 1 433-atom FCC sphere, where every atom has hundreds of
+    # neighbours inside the near-field radius: against the oracle's dense T, through the registered
+    # variants of a stored handle and through a matrix-free handle.
+    import wfq_inputs as wi
+    from wfq_inputs import geometry as geo
+    xyz = geo.jitter(geo.fcc_sphere(18.0), 0.02, 3)
+    par = wi.workloads.FCC_METAL
+    P = O.Problem(xyz, par)
+    X = np.random.default_rng(ncol).standard_normal((ncol, P.n))
+    ref = X @ P.T.T
+    bound = np.abs(X) @ np.abs(P.T).T
+    names = [v[0] for v in lib.wfq_tx_variants("fp64")]
+    h = lib.wfq_build(xyz, par, store=("fp64",))
+    for var in ("otfn2", "otfn4"):
+        k = names.index(var)
+        if ncol > dict(lib.wfq_tx_variants("fp64"))[var]:
+            continue
+        Y = lib.wfq_apply_T_variant(h, "fp64", k, X)
+        assert np.all(np.abs(Y - ref) <= 1e-13 * bound), var
+    h.close()
+    hf = lib.wfq_build(xyz, par, t_mode="otf")
+    Y = lib.wfq_apply_T(hf, "fp64", X)
+    assert np.all(np.abs(Y - ref) <= 1e-13 * bound)
+    hf.close()
+
+
+def test_matrix_free_fp64_product_in_chunks(lib):
+    # matrix-free FP64 products of up to 12 columns run as narrow products of 4 columns each
+    xyz = ragged_tube()
+    P = O.Problem(xyz, GRAPHENE)
+    X = np.random.default_rng(8).standard_normal((11, P.n))
+    hf = lib.wfq_build(xyz, GRAPHENE, t_mode="otf")
+    Y = lib.wfq_apply_T(hf, "fp64", X)
+    hf.close()
+    assert np.all(np.abs(Y - X @ P.T.T) <= 1e-13 * (np.abs(X) @ np.abs(P.T).T))

@@ -72,14 +72,32 @@ extern "C" {
 #define WFQ_STORE_FP32  2u
 #define WFQ_STORE_BF16  4u
 
+/* wfq_params.material: how the Drude prefactor W = 2 n0 A of Eq. (z-def) is obtained */
+#define WFQ_MATERIAL_W          0   /* W given in wfq_params.W */
+#define WFQ_MATERIAL_GRAPHENE2D 1   /* 2D sheet (honeycomb, nearest-neighbour distance lattice_nn): the Drude
+                                       weight of the sheet is eps_F / pi (atomic units), Eqs. (2d-eff-mass),
+                                       (n-2d) read as the Drude weight of a 2D electron gas */
+#define WFQ_MATERIAL_METAL3D    2   /* FCC metal (nearest-neighbour distance lattice_nn): Drude weight
+                                       n_e / m* with n_e = valence / (volume per atom), n0 of the
+                                       Theoretical Model section with m* the effective mass */
+
 typedef struct wfq_handle wfq_handle;
 typedef struct wfq_server wfq_server;
 
 typedef struct {
-    int64_t       n;      /* number of atoms, >= 2 */
-    const double* xyz;    /* [n][3] positions, Angstrom, host memory */
-    const double* eta;    /* [n] per-atom hardness (Hartree), or NULL to use wfq_params.eta */
+    int64_t        n;       /* number of atoms, >= 2 */
+    const double*  xyz;     /* [n][3] positions, Angstrom, host memory */
+    const double*  eta;     /* [n] per-atom hardness (Hartree), or NULL (species or wfq_params.eta) */
+    const int32_t* species; /* [n] species index of each atom, 0 .. n_species - 1, or NULL (all species 0);
+                               used when wfq_params.n_species > 0 */
 } wfq_geometry;
+
+/* one atomic species: hardness and the equilibrium distance r0 of Eq. (fermi); a pair of species
+ * (a, b) uses r0_ab = (r0_a + r0_b) / 2 */
+typedef struct {
+    double eta;   /* Hartree, > 0 */
+    double r0;    /* Angstrom, > 0 */
+} wfq_species;
 
 typedef struct {
     double   eta;            /* hardness (Hartree) when wfq_geometry.eta is NULL; > 0 */
@@ -93,7 +111,29 @@ typedef struct {
     uint32_t store_mask;     /* WFQ_STORE_* bits; 0 = FP64 and FP32 */
     uint64_t device_budget;  /* bytes the handle may use on the device; 0 = 90% of free memory */
     int32_t  device;         /* HIP device ordinal */
+    /* material (Theoretical Model section): with material != WFQ_MATERIAL_W and W == 0 the library
+       computes W from the material data by the Drude sum-rule closure W = 2 Omega D / S, where Omega is
+       the area (2D) or volume (3D) per atom of the ideal lattice, D the Drude weight of the material and
+       S = sum_j (1 - f(r_0j)) x_0j^2 / r_0j over one site's ideal-lattice neighbours inside the cutoff
+       (so that W R^T L R per atom equals Omega D, the macroscopic Drude response, through the
+       high-frequency term R^T L R / z); a W > 0 given above overrides it */
+    int32_t  material;       /* WFQ_MATERIAL_* */
+    double   fermi_energy;   /* WFQ_MATERIAL_GRAPHENE2D: Fermi energy eps_F (eV), > 0 */
+    double   valence;        /* WFQ_MATERIAL_METAL3D: free electrons per atom, > 0 */
+    double   eff_mass;       /* WFQ_MATERIAL_METAL3D: effective mass m* (electron masses); 0 = 1 */
+    double   lattice_nn;     /* nearest-neighbour distance of the ideal lattice (Angstrom); 0 = r0 of species 0 */
+    /* species: n_species > 0 gives every atom the {eta, r0} of its species (wfq_geometry.species;
+       wfq_geometry.eta, when not NULL, still overrides eta per atom); 0 = one species {eta, r0} above */
+    int32_t            n_species;
+    const wfq_species* species;   /* [n_species], host memory, read during the call */
 } wfq_params;
+
+/*
+ * wfq_material_weight - the W that wfq_build would use for these parameters (the override, or the
+ * sum-rule closure of the material), computed on the host; no device is needed. WFQ_EINVAL for an
+ * unknown material or missing material data.
+ */
+int wfq_material_weight(const wfq_params* p, double* W);
 
 typedef struct {
     int32_t algorithm;   /* WFQ_GMRES, WFQ_QMR or WFQ_MSGMRES */

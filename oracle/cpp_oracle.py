@@ -29,7 +29,7 @@ def load():
             build()
         lib = C.CDLL(LIB)
         sig = {
-            "orc_create": (C.c_void_p, [C.c_int64, _DP, _DP, C.c_double, C.c_double, C.c_double, C.c_double,
+            "orc_create": (C.c_void_p, [C.c_int64, _DP, _DP, _DP, C.c_double, C.c_double, C.c_double,
                                         C.c_double, C.c_double, C.c_int]),
             "orc_destroy": (None, [C.c_void_p]),
             "orc_threads": (C.c_int, []),
@@ -75,15 +75,16 @@ class CppProblem:
     """One structure in the C++ oracle. dense_T stores T (n^2 doubles); build_L builds the whole L
     (all-pairs search); without it only residual_rows and T products are available."""
 
-    def __init__(self, xyz_A, params, dense_T=True, build_L=True):
+    def __init__(self, xyz_A, params, dense_T=True, build_L=True, species=None):
+        from .wfq_oracle import atom_parameters, material_weight
         xyz = _f64(xyz_A).reshape(-1, 3)
         self.n = xyz.shape[0]
         self.xyz = xyz / 0.529177210903
-        eta = np.broadcast_to(np.asarray(params["eta"], dtype=np.float64), (self.n,)).copy()
-        self._keep = (xyz, eta)
+        eta, r0 = atom_parameters(params, self.n, species)
+        self._keep = (xyz, eta, r0)
         mode = (1 if dense_T else 0) | (2 if build_L else 0)
-        self.ptr = load().orc_create(self.n, _dp(xyz), _dp(eta), float(params["r0"]), float(params["fermi_d"]),
-                                     float(params["fermi_s"]), float(params["cutoff_eps"]), float(params["W"]),
+        self.ptr = load().orc_create(self.n, _dp(xyz), _dp(eta), _dp(r0), float(params["fermi_d"]),
+                                     float(params["fermi_s"]), float(params["cutoff_eps"]), material_weight(params),
                                      float(params["tau"]), mode)
         if not self.ptr:
             raise ValueError("C++ oracle rejected the structure")

@@ -11,6 +11,7 @@
 //   * Eq. (k-tot-matrix) with a constant effective area folded into W = 2 n0 A, so that
 //     Kbar_ij = (1 - f(r_ij)) / r_ij and z(omega) = -(omega^2 + i omega / tau) / W (Eq. z-def);
 //   * Kbar truncated where 1 - f < eps_c, i.e. beyond r_c = s r0 (1 + ln(1/eps_c - 1) / d);
+//   * a pair of atoms of two species uses r0_ij = (r0_i + r0_j) / 2 in f and in r_c;
 //   * the sign-flipped system (L T + z I) q = b, L = P - Kbar (Eq. a-matrix-product and the
 //     definition of P), b = E0 L (r . k) (Eqs. potential, r-vector-def), T = D (Eq. d-matrix).
 // Everything is double / std::complex<double> in Hartree atomic units; positions come in Angstrom
@@ -46,7 +47,8 @@ struct Problem {
     std::vector<double> pos;   // [n][3], bohr
     std::vector<double> eta;   // hardness
     std::vector<double> wid;   // Gaussian width d_i
-    double r0 = 0, fd = 0, fs = 0, rc = 0, W = 0, tau = 0;
+    std::vector<double> r0;    // per-atom r0 (bohr); a pair takes the mean of its two atoms' values
+    double fd = 0, fs = 0, cfac = 0, W = 0, tau = 0;
     bool have_L = false;
     std::vector<int64_t> rp;   // CSR of L = P - Kbar (diagonal entry first in each row)
     std::vector<int64_t> ci;
@@ -64,10 +66,11 @@ struct Problem {
         const double r = dist(i, j);
         return std::erf(r / std::sqrt(wid[i] * wid[i] + wid[j] * wid[j])) / r;
     }
-    // Eq. (fermi) and Eq. (k-tot-factor) with unit area: (1 - f(r)) / r, zero beyond r_c
-    double kbar(double r) const {
-        if (!(r < rc) || r == 0.0) return 0.0;
-        const double f = 1.0 / (1.0 + std::exp(-fd * (r / (fs * r0) - 1.0)));
+    // Eq. (fermi) and Eq. (k-tot-factor) with unit area: (1 - f(r)) / r, zero beyond r_c of the pair
+    double kbar(int64_t i, int64_t j) const {
+        const double r = dist(i, j), r0ij = 0.5 * (r0[i] + r0[j]);
+        if (!(r < fs * r0ij * cfac) || r == 0.0) return 0.0;
+        const double f = 1.0 / (1.0 + std::exp(-fd * (r / (fs * r0ij) - 1.0)));
         return (1.0 - f) / r;
     }
     // one row of L: the diagonal P_ii = sum_k Kbar_ik first, then -Kbar_ij for the neighbours j
@@ -79,7 +82,7 @@ struct Problem {
         double diag = 0.0;
         for (int64_t j = 0; j < n; ++j) {
             if (j == i) continue;
-            const double k = kbar(dist(i, j));
+            const double k = kbar(i, j);
             if (k != 0.0) {
                 cols.push_back(j);
                 vals.push_back(-k);
@@ -206,14 +209,16 @@ void givens(cplx a, cplx b, double& c, cplx& s) {
 
 extern "C" {
 
-// Builds one structure. xyz_A [n][3] Angstrom, eta [n] Hartree; r0 in Angstrom; mode bit 0: store
+// Builds one structure. xyz_A [n][3] Angstrom, eta [n] Hartree, r0_A [n] Angstrom; mode bit 0: store
 // T densely (n^2 doubles), bit 1: build L (all-pairs search, O(n^2)); without bit 1 only the
 // row-by-row functions that compute L rows themselves may be used. Returns NULL on bad input.
-void* orc_create(int64_t n, const double* xyz_A, const double* eta, double r0_A, double fermi_d, double fermi_s,
-                 double cutoff_eps, double W, double tau, int mode) {
-    if (n < 1 || !xyz_A || !eta || !(r0_A > 0) || !(fermi_d > 0) || !(fermi_s > 0) || !(cutoff_eps > 0) ||
+void* orc_create(int64_t n, const double* xyz_A, const double* eta, const double* r0_A, double fermi_d,
+                 double fermi_s, double cutoff_eps, double W, double tau, int mode) {
+    if (n < 1 || !xyz_A || !eta || !r0_A || !(fermi_d > 0) || !(fermi_s > 0) || !(cutoff_eps > 0) ||
         !(cutoff_eps < 0.5) || !(W > 0) || !(tau > 0))
         return nullptr;
+    for (int64_t i = 0; i < n; ++i)
+        if (!(r0_A[i] > 0) || !(eta[i] > 0)) return nullptr;
     Problem* P = new (std::nothrow) Problem();
     if (!P) return nullptr;
     try {
@@ -223,10 +228,11 @@ void* orc_create(int64_t n, const double* xyz_A, const double* eta, double r0_A,
         P->eta.assign(eta, eta + n);
         P->wid.resize(n);
         for (int64_t i = 0; i < n; ++i) P->wid[i] = std::sqrt(2.0 / kPi) / eta[i];
-        P->r0 = r0_A / kBohrA;
+        P->r0.resize(n);
+        for (int64_t i = 0; i < n; ++i) P->r0[i] = r0_A[i] / kBohrA;
         P->fd = fermi_d;
         P->fs = fermi_s;
-        P->rc = fermi_s * P->r0 * (1.0 + std::log(1.0 / cutoff_eps - 1.0) / fermi_d);
+        P->cfac = 1.0 + std::log(1.0 / cutoff_eps - 1.0) / fermi_d;
         P->W = W;
         P->tau = tau;
         if (mode & 2) {

@@ -125,11 +125,18 @@ def kbar_value(r, r0, d, s):
     return (1.0 - fermi(r, r0, d, s)) / r
 
 
+def pair_r0(r0, i, j):
+    """r0 of the pairs (i, j): the mean of the two atoms' r0 (one value for a single species)."""
+    r0 = np.asarray(r0, dtype=np.float64)
+    return r0 if r0.ndim == 0 else 0.5 * (r0[i] + r0[j])
+
+
 def kbar_matrix(xyz_bohr, r0, d, s, rc):
     """Sparse symmetric Kbar with zero diagonal, truncated at r < rc (lengths in bohr).
 
-    Neighbour pairs come from a k-d tree range query (library primitive);
-    `kbar_rows_bruteforce` computes the same rows by a direct double loop.
+    r0 is one value or one per atom (species); a pair uses r0_ij = (r0_i + r0_j) / 2 and the cutoff
+    scales with it (rc is the cutoff of the largest r0). Neighbour pairs come from a k-d tree range
+    query (library primitive); `kbar_rows_bruteforce` computes the same rows by a direct double loop.
     """
     xyz = np.asarray(xyz_bohr, dtype=np.float64)
     n = len(xyz)
@@ -139,22 +146,24 @@ def kbar_matrix(xyz_bohr, r0, d, s, rc):
         return scipy.sparse.csr_matrix((n, n))
     i, j = pairs[:, 0], pairs[:, 1]
     r = np.sqrt(np.sum((xyz[i] - xyz[j]) ** 2, axis=1))
-    keep = r < rc
+    r0ij = pair_r0(r0, i, j)
+    keep = r < rc * r0ij / np.max(r0)
     i, j, r = i[keep], j[keep], r[keep]
-    v = kbar_value(r, r0, d, s)
+    v = kbar_value(r, pair_r0(r0, i, j), d, s)
     k = scipy.sparse.coo_matrix((np.concatenate([v, v]), (np.concatenate([i, j]), np.concatenate([j, i]))),
                                 shape=(n, n))
     return k.tocsr()
 
 
 def kbar_rows_bruteforce(xyz_bohr, r0, d, s, rc, rows):
-    """Dense rows of Kbar by checking every pair (slow, obviously correct)."""
+    """Dense rows of Kbar by checking every pair (slow, obviously correct); r0 as in kbar_matrix."""
     xyz = np.asarray(xyz_bohr, dtype=np.float64)
     rows = np.asarray(rows)
     diff = xyz[rows, None, :] - xyz[None, :, :]
     r = np.sqrt(np.sum(diff * diff, axis=2))
+    r0ij = pair_r0(r0, rows[:, None], np.arange(len(xyz))[None, :])
     with np.errstate(divide="ignore"):
-        v = np.where((r < rc) & (r > 0.0), kbar_value(np.where(r > 0, r, 1.0), r0, d, s), 0.0)
+        v = np.where((r < rc * r0ij / np.max(r0)) & (r > 0.0), kbar_value(np.where(r > 0, r, 1.0), r0ij, d, s), 0.0)
     v[rows[:, None] == np.arange(len(xyz))[None, :]] = 0.0
     return v
 
@@ -485,19 +494,61 @@ def interpolate_start(q_a, q_b, z_a, z_b, z):
     return q_a + t * (q_b - q_a)
 
 
+def atom_parameters(params, n, species=None):
+    """Per-atom hardness (Hartree) and r0 (Angstrom): from the species table params["species"]
+    [(eta, r0), ...] and the per-atom indices `species` (None: species 0), else params["eta"] (one
+    value or one per atom) and params["r0"]."""
+    if params.get("species"):
+        table = np.asarray(params["species"], dtype=np.float64)
+        idx = np.zeros(n, dtype=np.int64) if species is None else np.asarray(species, dtype=np.int64)
+        return table[idx, 0].copy(), table[idx, 1].copy()
+    eta = np.broadcast_to(np.asarray(params["eta"], dtype=np.float64), (n,)).copy()
+    return eta, np.full(n, float(params["r0"]))
+
+
+def material_weight(params):
+    """W = 2 n0 A of Eq. (z-def): the value params["W"] when given (> 0), else the Drude sum-rule
+    closure (drude_weight_closure) of the material on its ideal lattice: params["material"] is
+    "graphene2D" (honeycomb; Drude weight eps_F / pi from params["fermi_energy_eV"]) or "metal3D"
+    (FCC; Drude weight n_e / m* with n_e = params["valence"] per atom and m* = params["eff_mass"]);
+    the nearest-neighbour distance is params["lattice_nn"] or the r0 of species 0 (Angstrom)."""
+    if params.get("W"):
+        return float(params["W"])
+    from wfq_inputs import geometry as geo
+    nn_A = params.get("lattice_nn") or (params["species"][0][1] if params.get("species") else params["r0"])
+    nn = float(nn_A) / BOHR_A
+    d, s, eps = float(params["fermi_d"]), float(params["fermi_s"]), float(params["cutoff_eps"])
+    rc_A = cutoff_radius(nn, d, s, eps) * BOHR_A
+    if params.get("material") == "graphene2D":
+        # a disk of the generator's honeycomb (its own bond length) scaled to nearest neighbours nn
+        lat = angstrom_to_bohr(geo.graphene_disk((rc_A + 3.0 * nn_A) * geo.A_CC / nn_A) * (nn_A / geo.A_CC))
+        cell = 3.0 * math.sqrt(3.0) / 4.0 * nn * nn
+        drude = ev_to_hartree(float(params["fermi_energy_eV"])) / math.pi
+    elif params.get("material") == "metal3D":
+        a_A = math.sqrt(2.0) * nn_A
+        lat = angstrom_to_bohr(geo.fcc_sphere(rc_A + 2.0 * a_A, a=a_A))
+        cell = (a_A / BOHR_A) ** 3 / 4.0
+        drude = float(params["valence"]) / cell / float(params.get("eff_mass") or 1.0)
+    else:
+        raise ValueError("need W or a material ('graphene2D' or 'metal3D')")
+    site = int(np.argmin(np.sum(lat ** 2, axis=1)))
+    return float(drude_weight_closure(lat, site, cell, drude, nn, d, s, eps))
+
+
 class Problem:
     """One structure with its model matrices (all FP64, atomic units)."""
 
-    def __init__(self, xyz_A, params, dense_T=True):
+    def __init__(self, xyz_A, params, dense_T=True, species=None):
         self.xyz = angstrom_to_bohr(xyz_A)
         self.n = len(self.xyz)
         p = params
-        self.eta = np.broadcast_to(np.asarray(p["eta"], dtype=np.float64), (self.n,)).copy()
-        self.r0 = float(p["r0"]) / BOHR_A
+        eta, r0 = atom_parameters(p, self.n, species)
+        self.eta = eta
+        self.r0 = r0 / BOHR_A if (p.get("species") and len(set(r0)) > 1) else float(r0[0]) / BOHR_A
         self.fd = float(p["fermi_d"])
         self.fs = float(p["fermi_s"])
-        self.rc = cutoff_radius(self.r0, self.fd, self.fs, float(p["cutoff_eps"]))
-        self.W = float(p["W"])
+        self.rc = cutoff_radius(float(np.max(self.r0)), self.fd, self.fs, float(p["cutoff_eps"]))
+        self.W = material_weight(p)
         self.tau = float(p["tau"])
         self.L = laplacian(kbar_matrix(self.xyz, self.r0, self.fd, self.fs, self.rc))
         self.T = coulomb_matrix(self.xyz, self.eta) if dense_T else None

@@ -91,6 +91,98 @@ void check_opts(const wfq_solve_opts* o) {
     if (o->block_jacobi && o->warm_start) fail(WFQ_EINVAL, "block_jacobi and warm_start cannot be combined");
 }
 
+// ---- material closure: W = 2 Omega D / S (see wfq.h), on an ideal lattice generated here
+
+constexpr double kBohrAng = 0.529177210903;     // Angstrom per bohr
+constexpr double kHartreeEv = 27.211386245988;  // eV per Hartree
+
+// S = sum_j (1 - f(r_0j)) x_0j^2 / r_0j over the neighbours of one site of the ideal lattice with
+// nearest-neighbour distance nn (bohr) inside r_c = s nn cfac; 2D honeycomb or 3D FCC. Both lattices
+// have a point group that makes the second moment isotropic, so the x component stands for any
+// direction (in the plane for the sheet).
+double closure_sum(int material, double nn, double fs, double fd, double cfac) {
+    const double rc = fs * nn * cfac;
+    double S = 0.0;
+    auto add = [&](double x, double y, double z) {
+        const double r = std::sqrt(x * x + y * y + z * z);
+        if (r > 0.0 && r < rc) {
+            const double f = 1.0 / (1.0 + std::exp(-fd * (r / (fs * nn) - 1.0)));   // Eq. (fermi)
+            S += (1.0 - f) * x * x / r;
+        }
+    };
+    if (material == WFQ_MATERIAL_GRAPHENE2D) {
+        // honeycomb: lattice vectors nn (3/2, +-sqrt(3)/2), basis (0, 0) and (nn, 0)
+        const double h = std::sqrt(3.0) / 2.0;
+        const int K = (int)std::ceil(rc / nn) + 2;
+        for (int i = -K; i <= K; ++i)
+            for (int j = -K; j <= K; ++j) {
+                const double x = nn * 1.5 * (i + j), y = nn * h * (i - j);
+                add(x, y, 0.0);
+                add(x + nn, y, 0.0);
+            }
+    } else {
+        // FCC: cube edge a = sqrt(2) nn, points (i, j, k) a / 2 with i + j + k even
+        const double half = std::sqrt(2.0) * nn / 2.0;
+        const int K = (int)std::ceil(rc / half) + 1;
+        for (int i = -K; i <= K; ++i)
+            for (int j = -K; j <= K; ++j)
+                for (int k = -K; k <= K; ++k)
+                    if (((i + j + k) & 1) == 0) add(i * half, j * half, k * half);
+    }
+    return S;
+}
+
+// W: the override, or the closure for the material (p already checked)
+double material_weight(const wfq_params* p, double r0_species0) {
+    if (p->W > 0.0) return p->W;
+    if (p->material != WFQ_MATERIAL_GRAPHENE2D && p->material != WFQ_MATERIAL_METAL3D)
+        fail(WFQ_EINVAL, "need W > 0 or a material (WFQ_MATERIAL_GRAPHENE2D / WFQ_MATERIAL_METAL3D)");
+    const double nn = (p->lattice_nn > 0.0 ? p->lattice_nn : r0_species0) / kBohrAng;
+    const double cfac = 1.0 + std::log(1.0 / p->cutoff_eps - 1.0) / p->fermi_d;
+    const double S = closure_sum(p->material, nn, p->fermi_s, p->fermi_d, cfac);
+    if (!(S > 0.0)) fail(WFQ_EINVAL, "the material closure found no neighbour inside the cutoff");
+    double omega, D;
+    if (p->material == WFQ_MATERIAL_GRAPHENE2D) {
+        if (!finite_pos(p->fermi_energy)) fail(WFQ_EINVAL, "graphene2D needs fermi_energy > 0 (eV)");
+        omega = 3.0 * std::sqrt(3.0) / 4.0 * nn * nn;   // area per atom
+        D = p->fermi_energy / kHartreeEv / M_PI;         // Drude weight of the sheet, eps_F / pi
+    } else {
+        if (!finite_pos(p->valence)) fail(WFQ_EINVAL, "metal3D needs valence > 0");
+        const double m = p->eff_mass > 0.0 ? p->eff_mass : 1.0;
+        const double a = std::sqrt(2.0) * nn;
+        omega = a * a * a / 4.0;                         // volume per atom
+        D = p->valence / omega / m;                      // n_e / m*
+    }
+    return 2.0 * omega * D / S;
+}
+
+// per-atom hardness and r0 (caller order) from the geometry, the species table and the defaults
+void resolve_atoms(const wfq_geometry* g, const wfq_params* p, std::vector<double>& eta, std::vector<double>& r0) {
+    const int64_t n = g->n;
+    eta.assign(n, p->eta);
+    r0.assign(n, p->r0);
+    if (p->n_species > 0) {
+        if (!p->species) fail(WFQ_EINVAL, "n_species > 0 needs the species table");
+        for (int k = 0; k < p->n_species; ++k)
+            if (!finite_pos(p->species[k].eta) || !finite_pos(p->species[k].r0))
+                fail(WFQ_EINVAL, "every species needs eta > 0 and r0 > 0");
+        for (int64_t i = 0; i < n; ++i) {
+            const int k = g->species ? g->species[i] : 0;
+            if (k < 0 || k >= p->n_species) fail(WFQ_EINVAL, "species index out of range");
+            eta[i] = p->species[k].eta;
+            r0[i] = p->species[k].r0;
+        }
+    } else if (g->species) {
+        fail(WFQ_EINVAL, "a species array needs n_species > 0 and the species table");
+    }
+    if (g->eta)
+        for (int64_t i = 0; i < n; ++i) eta[i] = g->eta[i];
+    for (int64_t i = 0; i < n; ++i) {
+        if (!finite_pos(eta[i])) fail(WFQ_EINVAL, "eta must be finite and > 0");
+        if (!finite_pos(r0[i])) fail(WFQ_EINVAL, "r0 must be finite and > 0");
+    }
+}
+
 void check_solve_args(const wfq_handle* h, const double* omegas, int n_omega, const double* dirs, int n_dir,
                       double tol, const wfq_solve_opts* o) {
     if (!h) fail(WFQ_EINVAL, "handle is NULL");
@@ -119,6 +211,18 @@ extern "C" {
 
 const char* wfq_last_error(void) { return wfq::g_last_error.c_str(); }
 
+int wfq_material_weight(const wfq_params* p, double* W) {
+    return guarded([&]() -> int {
+        if (!p || !W) fail(WFQ_EINVAL, "params and W must not be NULL");
+        if (!finite_pos(p->fermi_d) || !finite_pos(p->fermi_s) || !(p->cutoff_eps > 0.0 && p->cutoff_eps < 0.5))
+            fail(WFQ_EINVAL, "fermi_d, fermi_s > 0 and cutoff_eps in (0, 0.5) are needed");
+        const double r0 = p->n_species > 0 && p->species ? p->species[0].r0 : p->r0;
+        if (!finite_pos(r0) && !(p->lattice_nn > 0.0)) fail(WFQ_EINVAL, "need r0 > 0 or lattice_nn > 0");
+        *W = material_weight(p, r0);
+        return WFQ_OK;
+    });
+}
+
 int wfq_build(const wfq_geometry* g, const wfq_params* p, wfq_handle** out) {
     if (out) *out = nullptr;
     return guarded([&]() -> int {
@@ -128,16 +232,14 @@ int wfq_build(const wfq_geometry* g, const wfq_params* p, wfq_handle** out) {
         if (!g->xyz) fail(WFQ_EINVAL, "xyz is NULL");
         for (int64_t i = 0; i < 3 * g->n; ++i)
             if (!std::isfinite(g->xyz[i])) fail(WFQ_EINVAL, "positions must be finite");
-        if (g->eta) {
-            for (int64_t i = 0; i < g->n; ++i)
-                if (!finite_pos(g->eta[i])) fail(WFQ_EINVAL, "eta must be finite and > 0");
-        } else if (!finite_pos(p->eta)) {
-            fail(WFQ_EINVAL, "eta must be finite and > 0");
-        }
-        if (!finite_pos(p->r0) || !finite_pos(p->fermi_d) || !finite_pos(p->fermi_s))
-            fail(WFQ_EINVAL, "r0, fermi_d and fermi_s must be finite and > 0");
+        if (!finite_pos(p->fermi_d) || !finite_pos(p->fermi_s))
+            fail(WFQ_EINVAL, "fermi_d and fermi_s must be finite and > 0");
         if (!(p->cutoff_eps > 0.0 && p->cutoff_eps < 0.5)) fail(WFQ_EINVAL, "cutoff_eps must be in (0, 0.5)");
-        if (!finite_pos(p->W) || !finite_pos(p->tau)) fail(WFQ_EINVAL, "W and tau must be finite and > 0");
+        if (!finite_pos(p->tau)) fail(WFQ_EINVAL, "tau must be finite and > 0");
+        if (!(p->W >= 0.0) || !std::isfinite(p->W)) fail(WFQ_EINVAL, "W must be finite and >= 0");
+        std::vector<double> eta_atom, r0_atom;
+        resolve_atoms(g, p, eta_atom, r0_atom);
+        const double W = material_weight(p, p->n_species > 0 ? p->species[0].r0 : p->r0);
         if (p->t_mode < WFQ_TMODE_AUTO || p->t_mode > WFQ_TMODE_OTF) fail(WFQ_EINVAL, "unknown t_mode");
         if (p->store_mask & ~7u) fail(WFQ_EINVAL, "unknown store_mask bits");
         check_device(p->device);
@@ -149,7 +251,7 @@ int wfq_build(const wfq_geometry* g, const wfq_params* p, wfq_handle** out) {
             size_t free_b = 0, total_b = 0;
             WFQ_HIP(hipMemGetInfo(&free_b, &total_b));
             h->S.budget = p->device_budget ? p->device_budget : (uint64_t)(0.9 * (double)free_b);
-            build_structure(h->S, g, p, h->stream);
+            build_structure(h->S, g, p, eta_atom.data(), r0_atom.data(), W, h->stream);
             (void)scratch_ptr(p->device);   // set-up of wfq_apply_op_noalloc's scratch on this device
         } catch (...) {
             free_structure(h->S);

@@ -55,10 +55,12 @@ __device__ inline double kbar_of(double r, double inv_sr0, double d) {
 
 // Pass 1 (count=true): number of neighbours within rc per atom; pass 2: write the CSR row of
 // L = P - Kbar with the diagonal first, then -Kbar_ij in cell traversal order (deterministic).
+// The pair (i, j) uses r0_ij = (r0_i + r0_j) / 2 (species of the two atoms) and its own cutoff
+// r_c,ij = s r0_ij cfac, cfac = 1 + ln(1/eps - 1) / d.
 template <bool kCount>
 __global__ void neighbour_kernel(int64_t n, const double* __restrict__ pos, int64_t npad, GridArgs g,
                                  const int32_t* __restrict__ cell_start, const int32_t* __restrict__ cell_count,
-                                 double rc2, double inv_sr0, double fd, double close2,
+                                 const double* __restrict__ r0a, double fs, double cfac, double fd, double close2,
                                  int32_t* __restrict__ counts, const int32_t* __restrict__ rowptr,
                                  int32_t* __restrict__ col, double* __restrict__ val, int32_t* __restrict__ flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -67,6 +69,7 @@ __global__ void neighbour_kernel(int64_t n, const double* __restrict__ pos, int6
     const double* py = pos + npad;
     const double* pz = pos + 2 * npad;
     double xi = px[i], yi = py[i], zi = pz[i];
+    const double r0i = r0a[i];
     int cx, cy, cz;
     cell_of(g, xi, yi, zi, cx, cy, cz);
     int cnt = 0;
@@ -90,11 +93,13 @@ __global__ void neighbour_kernel(int64_t n, const double* __restrict__ pos, int6
                     double ddx = xi - px[j], ddy = yi - py[j], ddz = zi - pz[j];
                     double r2 = ddx * ddx + ddy * ddy + ddz * ddz;
                     if (r2 < close2) flag[0] = 1;
-                    if (r2 < rc2) {
+                    const double sr0 = fs * 0.5 * (r0i + r0a[j]);
+                    const double rc = sr0 * cfac;
+                    if (r2 < rc * rc) {
                         if (kCount) {
                             ++cnt;
                         } else {
-                            double k = kbar_of(sqrt(r2), inv_sr0, fd);
+                            double k = kbar_of(sqrt(r2), 1.0 / sr0, fd);
                             diag += k;
                             col[base + out] = j;
                             val[base + out] = -k;
@@ -310,7 +315,7 @@ T* dev_alloc(Structure& s, size_t count) {
 void free_structure(Structure& s) {
     free_solve_cache(s);
     void* ptrs[] = {s.pos, s.eta, s.width, s.rowptr, s.col, s.val, s.T64, s.T32, s.T16, s.dperm, s.ell_col, s.ell_val,
-                    s.sphere, s.near_col, s.near_val};
+                    s.sphere, s.near_col, s.near_val, s.r0a};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     s.pos = s.eta = s.width = s.val = s.T64 = s.sphere = nullptr;
@@ -318,6 +323,7 @@ void free_structure(Structure& s) {
     s.ell_val = nullptr;
     s.near_col = nullptr;
     s.near_val = nullptr;
+    s.r0a = nullptr;
     s.T32 = nullptr;
     s.T16 = nullptr;
     if (s.split_ws) (void)hipFree(s.split_ws);
@@ -402,15 +408,19 @@ void h2d_sync(const Structure& s, void* dst, const void* src, size_t bytes, hipS
     }
 }
 
-void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, hipStream_t st) {
+void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, const double* eta_atom,
+                     const double* r0_atom, double W, hipStream_t st) {
     const int64_t n = g->n;
     s.n = n;
     s.npad = round_up(n, kPad);
-    s.r0 = p->r0 / kBohrA;
+    double r0max = 0.0;
+    for (int64_t i = 0; i < n; ++i) r0max = std::max(r0max, r0_atom[i]);
+    s.r0 = r0max / kBohrA;   // the largest pair cutoff sets the cell grid
     s.fd = p->fermi_d;
     s.fs = p->fermi_s;
-    s.rc = s.fs * s.r0 * (1.0 + std::log(1.0 / p->cutoff_eps - 1.0) / s.fd);
-    s.W = p->W;
+    s.cfac = 1.0 + std::log(1.0 / p->cutoff_eps - 1.0) / s.fd;
+    s.rc = s.fs * s.r0 * s.cfac;
+    s.W = W;
     s.tau = p->tau;
 
     // ---- a0: units and ordering. Atoms are grouped by cell (edge >= rc) and the cells are ordered
@@ -460,7 +470,7 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
         cell_start[c] = (int32_t)k;   // the atoms of one cell are contiguous in the new order
     }
 
-    std::vector<double> pos_h(3 * s.npad, 0.0), eta_h(s.npad, 0.0), width_h(s.npad, 0.0);
+    std::vector<double> pos_h(3 * s.npad, 0.0), eta_h(s.npad, 0.0), width_h(s.npad, 0.0), r0_h(s.npad, 0.0);
     s.pos_host.assign(3 * n, 0.0);
     for (int64_t k = 0; k < n; ++k) {
         int64_t i = s.perm[k];
@@ -468,8 +478,9 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
             pos_h[a * s.npad + k] = xyz[3 * i + a];
             s.pos_host[a * n + k] = xyz[3 * i + a];
         }
-        double e = g->eta ? g->eta[i] : p->eta;
+        double e = eta_atom[i];
         eta_h[k] = e;
+        r0_h[k] = r0_atom[i] / kBohrA;
         width_h[k] = std::sqrt(2.0 / M_PI) / e;   // d_i = sqrt(2/pi) / eta_i (width-from-hardness)
     }
 
@@ -482,6 +493,8 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     h2d_sync(s, s.pos, pos_h.data(), pos_h.size() * 8, st);
     h2d_sync(s, s.eta, eta_h.data(), eta_h.size() * 8, st);
     h2d_sync(s, s.width, width_h.data(), width_h.size() * 8, st);
+    s.r0a = dev_alloc<double>(s, s.npad);
+    h2d_sync(s, s.r0a, r0_h.data(), r0_h.size() * 8, st);
     // bounding spheres of consecutive 64-atom blocks (internal order; padding atoms excluded, an
     // empty block gets radius 0), used by the matrix-free products to find far-apart tile pairs
     // (the host copy lives until the stream is synchronised at the end of the build)
@@ -526,13 +539,11 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     h2d_sync(s, d_count, cell_count.data(), ncell * 4, st);
     WFQ_HIP(hipMemsetAsync(d_flag, 0, 4, st));
     GridArgs ga{grid.lo[0], grid.lo[1], grid.lo[2], 1.0 / grid.h, grid.dim[0], grid.dim[1], grid.dim[2]};
-    const double rc2 = s.rc * s.rc;
-    const double inv_sr0 = 1.0 / (s.fs * s.r0);
     const double close = kCoincidentA / kBohrA;
     s.rowptr = dev_alloc<int32_t>(s, n + 1);
     dim3 blk(256), grd((unsigned)((n + 255) / 256));
-    hipLaunchKernelGGL(neighbour_kernel<true>, grd, blk, 0, st, n, s.pos, s.npad, ga, d_start, d_count, rc2, inv_sr0,
-                       s.fd, close * close, d_counts, nullptr, nullptr, nullptr, d_flag);
+    hipLaunchKernelGGL(neighbour_kernel<true>, grd, blk, 0, st, n, s.pos, s.npad, ga, d_start, d_count, s.r0a, s.fs,
+                       s.cfac, s.fd, close * close, d_counts, nullptr, nullptr, nullptr, d_flag);
     WFQ_CHECK_LAUNCH();
     hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, st, n, d_counts, s.rowptr);
     WFQ_CHECK_LAUNCH();
@@ -545,8 +556,8 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, h
     s.nnz = nnz32;
     s.col = dev_alloc<int32_t>(s, s.nnz);
     s.val = dev_alloc<double>(s, s.nnz);
-    hipLaunchKernelGGL(neighbour_kernel<false>, grd, blk, 0, st, n, s.pos, s.npad, ga, d_start, d_count, rc2, inv_sr0,
-                       s.fd, close * close, nullptr, s.rowptr, s.col, s.val, d_flag);
+    hipLaunchKernelGGL(neighbour_kernel<false>, grd, blk, 0, st, n, s.pos, s.npad, ga, d_start, d_count, s.r0a, s.fs,
+                       s.cfac, s.fd, close * close, nullptr, s.rowptr, s.col, s.val, d_flag);
     WFQ_CHECK_LAUNCH();
 
     // connectivity of the Kbar graph (breadth-first search on the host)

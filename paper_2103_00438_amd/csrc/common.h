@@ -77,7 +77,9 @@ struct Structure {
     float* T32 = nullptr;
     uint16_t* T16 = nullptr;     // bf16 bit patterns
     int t_mode = WFQ_TMODE_STORED;
-    double r0 = 0, fd = 0, fs = 0, rc = 0, W = 0, tau = 0;
+    double r0 = 0, fd = 0, fs = 0, rc = 0, W = 0, tau = 0;   // r0: largest of the atoms' r0 (bohr)
+    double cfac = 0;             // r_c = s r0 cfac, cfac = 1 + ln(1/eps - 1) / d
+    double* r0a = nullptr;       // device [npad], r0 of each atom's species (bohr)
     uint64_t budget = 0;
     uint64_t bytes = 0;          // device bytes held by this structure
     bool connected = true;
@@ -150,7 +152,10 @@ class Timer {
 };
 
 // ------------------------------------------------------------------ builders (build.hip)
-void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, hipStream_t st);
+// eta_atom, r0_atom: [n] per-atom hardness (Hartree) and r0 (Angstrom) in the caller's order; W the
+// resolved Drude prefactor
+void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, const double* eta_atom,
+                     const double* r0_atom, double W, hipStream_t st);
 void free_structure(Structure& s);
 void build_rhs(const Structure& s, const double* dirs_dev, int n_dir, double E0, double* out, int64_t ld,
                hipStream_t st);

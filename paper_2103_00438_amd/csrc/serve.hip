@@ -32,6 +32,8 @@ constexpr int kMaxWorkers = 64;   // upper limit of max_jobs (one worker thread 
 struct Job {
     uint64_t ticket = 0;
     std::vector<double> xyz, eta, omegas, dirs;
+    std::vector<int32_t> species_idx;    // per-atom species (empty: none given)
+    std::vector<wfq_species> species;    // the job's species table (params.species points here when run)
     wfq_params params{};
     int64_t n = 0;
     int n_omega = 0, n_dir = 0;
@@ -97,8 +99,11 @@ void run_job(wfq_server* srv, const std::shared_ptr<Job>& job) {
     wfq_handle* h = nullptr;
     const int S = job->n_omega * job->n_dir;
     try {
-        wfq_geometry g{job->n, job->xyz.data(), job->eta.empty() ? nullptr : job->eta.data()};
+        wfq_geometry g{job->n, job->xyz.data(), job->eta.empty() ? nullptr : job->eta.data(),
+                       job->species_idx.empty() ? nullptr : job->species_idx.data()};
         wfq_params p = job->params;
+        p.species = job->species.empty() ? nullptr : job->species.data();
+        p.n_species = (int32_t)job->species.size();
         p.device = srv->cfg.device;
         p.device_budget = job->footprint;
         p.t_mode = WFQ_TMODE_STORED;
@@ -270,7 +275,16 @@ int wfq_submit(wfq_server* s, const wfq_job* job, uint64_t* ticket) {
     j->n = job->geom.n;
     j->xyz.assign(job->geom.xyz, job->geom.xyz + 3 * job->geom.n);
     if (job->geom.eta) j->eta.assign(job->geom.eta, job->geom.eta + job->geom.n);
+    if (job->geom.species) j->species_idx.assign(job->geom.species, job->geom.species + job->geom.n);
     j->params = job->params;
+    if (job->params.n_species > 0) {
+        if (!job->params.species) {
+            wfq::set_error(WFQ_EINVAL, "n_species > 0 needs the species table");
+            return WFQ_EINVAL;
+        }
+        j->species.assign(job->params.species, job->params.species + job->params.n_species);
+    }
+    j->params.species = nullptr;   // rewired to the job's copy when it runs
     j->n_omega = job->n_omega;
     j->n_dir = job->n_dir;
     j->omegas.assign(job->omegas_eV, job->omegas_eV + job->n_omega);

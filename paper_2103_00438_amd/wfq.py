@@ -32,13 +32,21 @@ class WfqError(RuntimeError):
 
 
 class Geometry(C.Structure):
-    _fields_ = [("n", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("eta", C.POINTER(C.c_double))]
+    _fields_ = [("n", C.c_int64), ("xyz", C.POINTER(C.c_double)), ("eta", C.POINTER(C.c_double)),
+                ("species", C.POINTER(C.c_int32))]
+
+
+class Species(C.Structure):
+    _fields_ = [("eta", C.c_double), ("r0", C.c_double)]
 
 
 class Params(C.Structure):
     _fields_ = [("eta", C.c_double), ("r0", C.c_double), ("fermi_d", C.c_double), ("fermi_s", C.c_double),
                 ("cutoff_eps", C.c_double), ("W", C.c_double), ("tau", C.c_double), ("t_mode", C.c_int32),
-                ("store_mask", C.c_uint32), ("device_budget", C.c_uint64), ("device", C.c_int32)]
+                ("store_mask", C.c_uint32), ("device_budget", C.c_uint64), ("device", C.c_int32),
+                ("material", C.c_int32), ("fermi_energy", C.c_double), ("valence", C.c_double),
+                ("eff_mass", C.c_double), ("lattice_nn", C.c_double), ("n_species", C.c_int32),
+                ("species", C.POINTER(Species))]
 
 
 class SolveOpts(C.Structure):
@@ -105,6 +113,7 @@ _SIGNATURES = {
     "wfq_serve_stats": (C.c_int, [C.c_void_p, C.POINTER(Stats)]),
     "wfq_serve_stop": (None, [C.c_void_p]),
     "wfq_last_error": (C.c_char_p, []),
+    "wfq_material_weight": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_double)]),
     "wfq_tx_variants": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_char_p), C.POINTER(C.c_int32)]),
     "wfq_tune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32, _DP,
                            C.POINTER(C.c_int32)]),
@@ -183,7 +192,14 @@ class Handle:
         self.close()
 
 
+MATERIAL = {None: 0, "graphene2D": 1, "metal3D": 2}
+
+
 def make_params(params: dict, t_mode="stored", store=("fp64", "fp32"), budget=0, device=0) -> Params:
+    """wfq_params from a parameter dict: eta, r0, fermi_d, fermi_s, cutoff_eps, tau, and either W or the
+    material data (material "graphene2D" with fermi_energy_eV, or "metal3D" with valence and
+    eff_mass; optional lattice_nn in Angstrom); optional species [(eta, r0), ...]. The Species array
+    is kept on the returned object (p._species) for the duration of the call."""
     eta = params.get("eta", 0.0)
     p = Params()
     p.eta = float(eta) if np.isscalar(eta) else 0.0
@@ -191,28 +207,50 @@ def make_params(params: dict, t_mode="stored", store=("fp64", "fp32"), budget=0,
     p.fermi_d = float(params["fermi_d"])
     p.fermi_s = float(params["fermi_s"])
     p.cutoff_eps = float(params["cutoff_eps"])
-    p.W = float(params["W"])
+    p.W = float(params.get("W") or 0.0)
     p.tau = float(params["tau"])
     p.t_mode = TMODE[t_mode]
     p.store_mask = sum(STORE[s] for s in store)
     p.device_budget = int(budget)
     p.device = int(device)
+    p.material = MATERIAL[params.get("material")]
+    p.fermi_energy = float(params.get("fermi_energy_eV") or 0.0)
+    p.valence = float(params.get("valence") or 0.0)
+    p.eff_mass = float(params.get("eff_mass") or 0.0)
+    p.lattice_nn = float(params.get("lattice_nn") or 0.0)
+    sp = params.get("species")
+    if sp:
+        arr = (Species * len(sp))(*[Species(float(e), float(r)) for e, r in sp])
+        p._species = arr
+        p.n_species = len(sp)
+        p.species = C.cast(arr, C.POINTER(Species))
     return p
 
 
-def wfq_build(xyz, params: dict, t_mode="stored", store=("fp64", "fp32"), budget=0, device=0) -> Handle:
-    """Set up a structure (positions in Angstrom, (N, 3)). `params` as in the workload descriptions."""
+def wfq_build(xyz, params: dict, t_mode="stored", store=("fp64", "fp32"), budget=0, device=0,
+              species=None) -> Handle:
+    """Set up a structure (positions in Angstrom, (N, 3)). `params` as in the workload descriptions;
+    `species` [N] indices into params["species"] (None: every atom is species 0)."""
     lib = load()
     xyz = _f64(xyz)
     n = xyz.shape[0]
     eta = params.get("eta", 0.0)
     eta_arr = None if np.isscalar(eta) else _f64(eta)
-    g = Geometry(n, _dp(xyz), _dp(eta_arr))
+    sp_arr = None if species is None else np.ascontiguousarray(species, dtype=np.int32)
+    g = Geometry(n, _dp(xyz), _dp(eta_arr), sp_arr.ctypes.data_as(C.POINTER(C.c_int32)) if sp_arr is not None else None)
     p = make_params(params, t_mode, store, budget, device)
     out = C.c_void_p()
     rc = lib.wfq_build(C.byref(g), C.byref(p), C.byref(out))
     _check(rc, (WFQ_OK, WFQ_EDISCONNECTED))
     return Handle(out.value, n, rc)
+
+
+def wfq_material_weight(params: dict) -> float:
+    """The W wfq_build uses for these parameters (the W override or the material closure); host only."""
+    p = make_params(params)
+    W = C.c_double()
+    _check(load().wfq_material_weight(C.byref(p), C.byref(W)))
+    return W.value
 
 
 def wfq_destroy(h: Handle) -> None:
@@ -416,13 +454,18 @@ def wfq_serve(tol, device_budget=0, max_jobs=4, max_queue=1024, device=0, **opts
     return Server(out.value)
 
 
-def wfq_submit(s: Server, xyz, params: dict, omegas_eV, dirs) -> int:
+def wfq_submit(s: Server, xyz, params: dict, omegas_eV, dirs, species=None) -> int:
+    """Queue one structure; `species` as in wfq_build. The server copies every array before returning."""
     xyz = _f64(xyz)
     om = _f64(omegas_eV).ravel()
     d = _f64(dirs).reshape(-1, 3)
     eta = params.get("eta", 0.0)
     eta_arr = None if np.isscalar(eta) else _f64(eta)
-    job = Job(Geometry(xyz.shape[0], _dp(xyz), _dp(eta_arr)), make_params(params), _dp(om), len(om), _dp(d), len(d))
+    sp_arr = None if species is None else np.ascontiguousarray(species, dtype=np.int32)
+    pp = make_params(params)   # holds the species table until the call returns
+    g = Geometry(xyz.shape[0], _dp(xyz), _dp(eta_arr),
+                 sp_arr.ctypes.data_as(C.POINTER(C.c_int32)) if sp_arr is not None else None)
+    job = Job(g, pp, _dp(om), len(om), _dp(d), len(d))
     t = C.c_uint64()
     _check(load().wfq_submit(s.ptr, C.byref(job), C.byref(t)))
     s.jobs[t.value] = (xyz.shape[0], len(om), len(d))

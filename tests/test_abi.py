@@ -93,7 +93,7 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         pytest.skip("no C compiler")
     pairs = {"wfq_geometry": wfq.Geometry, "wfq_params": wfq.Params, "wfq_solve_opts": wfq.SolveOpts,
              "wfq_result": wfq.Result, "wfq_serve_cfg": wfq.ServeCfg, "wfq_job": wfq.Job,
-             "wfq_job_timing": wfq.JobTiming, "wfq_stats": wfq.Stats}
+             "wfq_job_timing": wfq.JobTiming, "wfq_stats": wfq.Stats, "wfq_species": wfq.Species}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "wfq.h"', "int main(void) {"]
     for cname, py in pairs.items():
         lines.append(f'    printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -110,3 +110,23 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(cname, "size")] == ctypes.sizeof(py), cname
         for fname, _ in py._fields_:
             assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_material_closure_of_the_library_equals_the_oracle():
+    # the library computes W = 2 n0 A from the material data by the same sum-rule closure as the
+    # oracle (host code of libwfq; no device needed): graphene at two Fermi energies, the FCC metal
+    # with one and with two free electrons per atom and m* = 1 or 1.5
+    from paper_2103_00438_amd import wfq
+    from oracle import wfq_oracle as O
+    import wfq_inputs as wi
+    for base, extra in ((wi.workloads.GRAPHENE, dict(fermi_energy_eV=0.4)),
+                        (wi.workloads.GRAPHENE, dict(fermi_energy_eV=1.51)),
+                        (wi.workloads.FCC_METAL, dict(valence=1.0, eff_mass=1.0)),
+                        (wi.workloads.FCC_METAL, dict(valence=2.0, eff_mass=1.5))):
+        p = dict(base, **extra)
+        p.pop("W", None)
+        assert wfq.wfq_material_weight(p) == pytest.approx(O.material_weight(p), rel=1e-12)
+    assert wfq.wfq_material_weight(dict(wi.workloads.GRAPHENE, W=0.05)) == 0.05   # the override
+    with pytest.raises(wfq.WfqError) as e:
+        wfq.wfq_material_weight(dict(wi.workloads.GRAPHENE, material=None, W=0.0))
+    assert e.value.code == wfq.WFQ_EINVAL

@@ -18,14 +18,16 @@ from wfq_inputs import geometry as geo
 
 G = wi.workloads.GRAPHENE
 FCC = wi.workloads.FCC_METAL
+WG = O.material_weight(G)     # W of the graphene parameters (sum-rule closure)
+WF = O.material_weight(FCC)
 
 
 @pytest.fixture(params=["python", "cpp"])
 def make(request):
-    def f(xyz, params=G, dense_T=True):
+    def f(xyz, params=G, dense_T=True, species=None):
         if request.param == "python":
-            return O.Problem(xyz, params, dense_T=dense_T)
-        return CppProblem(xyz, params, dense_T=dense_T)
+            return O.Problem(xyz, params, dense_T=dense_T, species=species)
+        return CppProblem(xyz, params, dense_T=dense_T, species=species)
     f.kind = request.param
     return f
 
@@ -98,6 +100,55 @@ def test_laplacian_structure_and_neighbour_count(make):
     assert Pi.L[c].nnz == 37
 
 
+def test_two_species_dimer_closed_form(make):
+    # atoms of two species: T_ii = eta_i, T_01 = erf(r / sqrt(d_0^2 + d_1^2)) / r with d_i = sqrt(2/pi) / eta_i,
+    # Kbar_01 from the pair r0 (r0_0 + r0_1) / 2. The dimer's charges are c (1, -1), so
+    # alpha_xx = Kbar r^2 / (Kbar (eta_0 + eta_1 - 2 T_01) + z).
+    eta0, eta1, r0a, r0b = 0.45, 0.8, 1.42, 1.63
+    par = dict(G, species=[(eta0, r0a), (eta1, r0b)])
+    r_A = 1.7
+    P = make(np.array([[0.0, 0.0, 0.0], [r_A, 0.0, 0.0]]), par, species=[0, 1])
+    r = r_A / O.BOHR_A
+    r0 = 0.5 * (r0a + r0b) / O.BOHR_A
+    k = (1.0 - 1.0 / (1.0 + math.exp(-12.0 * (r / (1.1 * r0) - 1.0)))) / r
+    d0, d1 = math.sqrt(2 / math.pi) / eta0, math.sqrt(2 / math.pi) / eta1
+    t = math.erf(r / math.sqrt(d0 * d0 + d1 * d1)) / r
+    T = t_matrix(P)
+    assert T[0, 0] == eta0 and T[1, 1] == eta1
+    assert T[0, 1] == pytest.approx(t, rel=1e-15) and T[1, 0] == T[0, 1]
+    assert P.L.toarray()[0, 1] == pytest.approx(-k, rel=1e-14)
+    for om in (0.1, 0.7, 3.0):
+        oh = om / 27.211386245988
+        z = -(oh * oh + 1j * oh / 170.0) / WG
+        q = P.solve_lu(om, [1, 0, 0])
+        a = alpha(P, q[:, None])
+        assert a[0, 0] == pytest.approx(k * r * r / (k * (eta0 + eta1 - 2 * t) + z), rel=1e-13)
+
+
+def test_pair_cutoff_follows_the_pair_r0(make):
+    # r_c = s r0 (1 + ln(1/eps - 1) / d) is 5.16 Angstrom for r0 = 1.42 and 5.48 for the mixed pair of
+    # r0 = 1.42 and 1.60: a dimer at 5.3 Angstrom is coupled only when one atom is of the wider species
+    eps = G["cutoff_eps"]
+    par = dict(G, species=[(G["eta"], 1.42), (G["eta"], 1.60)])
+    rc = [O.cutoff_radius(r0, 12.0, 1.1, eps) for r0 in (1.42, 1.51)]
+    assert rc[0] < 5.3 < rc[1]
+    xyz = np.array([[0.0, 0.0, 0.0], [5.3, 0.0, 0.0]])
+    assert not np.any(make(xyz, par, species=[0, 0]).L.toarray())
+    L = make(xyz, par, species=[0, 1]).L.toarray()
+    r = 5.3 / O.BOHR_A
+    k = (1.0 - 1.0 / (1.0 + math.exp(-12.0 * (r / (1.1 * 1.51 / O.BOHR_A) - 1.0)))) / r
+    assert L[0, 1] == pytest.approx(-k, rel=1e-13) and 0 < k * r < eps * 1e3
+
+
+def test_one_species_table_equals_the_scalar_parameters(make):
+    xyz = disk(radius=8.0)
+    a = make(xyz)
+    b = make(xyz, dict(G, species=[(G["eta"], G["r0"]), (2 * G["eta"], 2 * G["r0"])]),
+             species=np.zeros(len(xyz), dtype=np.int32))
+    assert np.array_equal(a.L.toarray(), b.L.toarray())
+    assert np.array_equal(t_matrix(a), t_matrix(b))
+
+
 # ----------------------------------------------------------------- solutions
 
 def test_dimer_closed_form(make):
@@ -109,7 +160,7 @@ def test_dimer_closed_form(make):
     t = math.erf(r / math.sqrt(2 * d * d)) / r
     for om in (0.1, 0.7, 3.0):
         oh = om / 27.211386245988
-        z = -(oh * oh + 1j * oh / 170.0) / G["W"]
+        z = -(oh * oh + 1j * oh / 170.0) / WG
         q = P.solve_lu(om, [1, 0, 0])
         a = alpha(P, q[:, None])
         assert a[0, 0] == pytest.approx(k * r * r / (k * (2 * G["eta"] - 2 * t) + z), rel=1e-13)
@@ -215,7 +266,7 @@ def lorentz_dimer(P, r_A, om_eV):
     d = math.sqrt(2 / math.pi) / G["eta"]
     t = math.erf(r / math.sqrt(2 * d * d)) / r
     oh = np.asarray(om_eV) / 27.211386245988
-    z = -(oh * oh + 1j * oh / G["tau"]) / G["W"]
+    z = -(oh * oh + 1j * oh / G["tau"]) / WG
     return k * r * r / (k * (2 * G["eta"] - 2 * t) + z), k * r * r
 
 
@@ -228,8 +279,8 @@ def test_cross_section_obeys_the_trk_sum_rule():
     a, krr = lorentz_dimer(None, 1.7, om_eV)
     sig = O.cross_section(O.ev_to_hartree(om_eV), a)
     integral = np.trapezoid(sig, O.ev_to_hartree(om_eV))
-    tail = 2 * math.pi * G["W"] * krr / (O.C_AU * O.ev_to_hartree(400.0) * G["tau"])   # (4 pi / c) F gamma / w_max
-    assert integral + tail == pytest.approx(2 * math.pi ** 2 * G["W"] * krr / O.C_AU, rel=2e-4)
+    tail = 2 * math.pi * WG * krr / (O.C_AU * O.ev_to_hartree(400.0) * G["tau"])   # (4 pi / c) F gamma / w_max
+    assert integral + tail == pytest.approx(2 * math.pi ** 2 * WG * krr / O.C_AU, rel=2e-4)
     assert np.all(sig > 0)
 
 
@@ -243,7 +294,7 @@ def test_isotropic_cross_section_sum_rule_and_rotation_invariance():
     A = U.T @ (tih @ P.xyz)
     om_eV = np.concatenate([np.linspace(1e-4, 40.0, 400_001), np.linspace(40.0, 4000.0, 100_001)[1:]])
     oh = O.ev_to_hartree(om_eV)
-    z = -(oh * oh + 1j * oh / G["tau"]) / G["W"]
+    z = -(oh * oh + 1j * oh / G["tau"]) / WG
     # alpha(omega) from the modal form, all three diagonal entries at every frequency
     frac = lam[None, :] / (lam[None, :] + z[:, None])
     diag = np.stack([frac @ (A[:, k] ** 2) for k in range(3)])
@@ -252,7 +303,7 @@ def test_isotropic_cross_section_sum_rule_and_rotation_invariance():
         alpha_w[k, k] = diag[k]
     sig = O.isotropic_cross_section(oh, alpha_w)
     Ld = P.L.toarray()
-    trk = 2 * math.pi ** 2 * G["W"] * np.trace(P.xyz.T @ Ld @ P.xyz) / 3 / O.C_AU
+    trk = 2 * math.pi ** 2 * WG * np.trace(P.xyz.T @ Ld @ P.xyz) / 3 / O.C_AU
     assert np.trapezoid(sig, oh) == pytest.approx(trk, rel=2e-3)
     th_ = 0.9
     Rx = np.array([[1, 0, 0], [0, math.cos(th_), -math.sin(th_)], [0, math.sin(th_), math.cos(th_)]])
@@ -277,7 +328,7 @@ def test_metal_closure_gives_the_froehlich_frequency():
         P = O.Problem(geo.fcc_sphere(R), FCC)
         lam, U, th, tih = O.modal_decomposition(P.L, P.T)
         wgt = lam * (U.T @ (tih @ P.xyz[:, 0])) ** 2
-        om = np.sqrt(np.maximum(lam, 0) * FCC["W"]) * O.HARTREE_EV
+        om = np.sqrt(np.maximum(lam, 0) * WF) * O.HARTREE_EV
         peak = om[np.argmax(wgt)]
         assert prev < peak < w_frohlich
         prev = peak

@@ -16,10 +16,11 @@ each with a fixed seed:
 * ``sheet1m``   rectangular graphene sheet, 10^6 atoms, matrix-free T.
 
 Material values: the paper defers its parameter values to earlier work, so
-these are project choices. W is the effective Drude prefactor 2 n0 A (atomic
-units) in the scaled shift z = -(omega^2 + i omega / tau) / W; the numbers
-below come from a Drude sum-rule closure over the ideal lattice, which the
-oracle recomputes in a test.
+these are project choices. Each material is given by its data (graphene: Fermi
+energy; metal: free electrons per atom and effective mass); the library and the
+oracle each derive the effective Drude prefactor W = 2 n0 A (atomic units) of
+the scaled shift z = -(omega^2 + i omega / tau) / W from them by a Drude sum-rule
+closure over the ideal lattice.
 """
 
 from __future__ import annotations
@@ -42,8 +43,8 @@ GRAPHENE = dict(
     fermi_s=1.1,
     cutoff_eps=1e-12,
     tau=170.0,                   # relaxation time, atomic units
+    material="graphene2D",
     fermi_energy_eV=0.4,
-    W=0.028913002199405312,      # 2 n0 A for eps_F = 0.4 eV (sum-rule closure)
 )
 
 FCC_METAL = dict(
@@ -53,8 +54,9 @@ FCC_METAL = dict(
     fermi_s=1.1,
     cutoff_eps=1e-12,
     tau=170.0,
-    fermi_energy_eV=None,
-    W=0.11813763577043197,       # 2 n0 A for n_e = 4 / a^3, m* = 1 (sum-rule closure)
+    material="metal3D",
+    valence=1.0,                 # one free electron per FCC site: n_e = 4 / a^3
+    eff_mass=1.0,
 )
 
 DIRS_XYZ = np.eye(3)

@@ -200,7 +200,13 @@ typedef struct {
     int32_t precision;   /* precision of the last cycle (after any escalation) */
     double  relres;      /* FP64 true relative residual ||b - (L T + z I) q|| / ||b|| */
     double  rmse;        /* ||b - (L T + z I) q|| / sqrt(N), size-independent measure of Eq. (rmse) */
-    double  err_est;     /* estimated relative error of q: relres times a Hessenberg condition estimate */
+    double  err_est;     /* bound on the relative error of q in the Coulomb norm |v|_T = sqrt(v^H T v):
+                            |q - q*|_T / |q*|_T <= err_est, q* the exact solution. L T is self-adjoint in
+                            the T inner product with real eigenvalues, so |(L T + z I)^-1|_T <= 1 / |Im z|;
+                            with |r|_T <= sqrt(rho_T) |r|_2 (rho_T the largest row sum of T) and
+                            eps = sqrt(rho_T) |r|_2 / (|Im z| |q|_T), err_est = eps / (1 - eps) (infinite
+                            when eps >= 1). Exact up to the FP64 rounding of r. The 2-norm relative error
+                            is at most sqrt(kappa_2(T)) err_est. */
     double  t_done_ms;   /* completion time of this system, measured from the start of the call */
 } wfq_result;
 

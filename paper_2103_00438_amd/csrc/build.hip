@@ -277,6 +277,12 @@ __global__ void ell_kernel(int64_t n, int64_t npad, int w, const int32_t* __rest
     }
 }
 
+// x[i] = 1 for the atoms, 0 for the padding
+__global__ void ones_kernel(int64_t n, int64_t npad, double* __restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < npad) x[i] = i < n ? 1.0 : 0.0;
+}
+
 // b[d][i] = E0 sum_j L_ij (r_j . k_d): minus R of Eq. (r-vector-def) with V of Eq. (potential).
 __global__ void rhs_kernel(int64_t n, int64_t npad, const double* __restrict__ pos, const int32_t* __restrict__ rowptr,
                            const int32_t* __restrict__ col, const double* __restrict__ val,
@@ -631,6 +637,21 @@ void build_structure(Structure& s, const wfq_geometry* g, const wfq_params* p, c
         hipLaunchKernelGGL(build_T_kernel, tg, dim3(256), 0, st, n, s.npad, s.pos, s.eta, s.width, s.T64, s.T32,
                            s.T16);
         WFQ_CHECK_LAUNCH();
+    }
+    // ---- a3: rho_T >= lambda_max(T) for the solvers' error bound (Gershgorin: the entries of T are
+    // positive, so the largest row sum bounds the spectrum). One recomputed FP64 product with the
+    // vector of ones; the sum of n positive terms is exact to n u relative, covered by the 1e-9 margin.
+    {
+        ScratchDev sc;
+        double* ones = sc.take<double>(s.npad);
+        double* rows = sc.take<double>(s.npad);
+        hipLaunchKernelGGL(ones_kernel, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, n, s.npad, ones);
+        WFQ_CHECK_LAUNCH();
+        otf_narrow_f64(s, ones, rows, s.npad, 1, device_cus(s.device), st);
+        std::vector<double> h((size_t)n);
+        d2h_sync(s, h.data(), rows, (size_t)n * sizeof(double), st);
+        s.t_rowsum = *std::max_element(h.begin(), h.end()) * (1.0 + 1e-9);
+        sc.release();
     }
     WFQ_HIP(hipStreamSynchronize(st));
 }

@@ -80,6 +80,7 @@ struct Structure {
     double r0 = 0, fd = 0, fs = 0, rc = 0, W = 0, tau = 0;   // r0: largest of the atoms' r0 (bohr)
     double cfac = 0;             // r_c = s r0 cfac, cfac = 1 + ln(1/eps - 1) / d
     double* r0a = nullptr;       // device [npad], r0 of each atom's species (bohr)
+    double t_rowsum = 0;         // >= lambda_max(T): the largest row sum of T (its entries are positive)
     uint64_t budget = 0;
     uint64_t bytes = 0;          // device bytes held by this structure
     bool connected = true;
@@ -183,6 +184,8 @@ void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStrea
 // Y = T X for at most 4 real FP64 columns with every element recomputed (no stored T needed), on
 // the vector ALUs; `cus` = compute units of the device (sets the split of the source range)
 void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st);
+// compute units of a device
+int device_cus(int device);
 // partial-tile work space of the block products (grown on demand, or the fixed region when set)
 void* split_workspace(const Structure& s, uint64_t bytes);
 void otf_tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_t st);

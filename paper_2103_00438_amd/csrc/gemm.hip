@@ -384,12 +384,6 @@ int choose_split(int64_t tiles, int nk, int64_t slots, uint64_t part_bytes, uint
 }
 
 
-int device_cus(int device) {
-    int cus = 0;
-    WFQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
-    return cus > 0 ? cus : 1;
-}
-
 template <int P, int WM, int WN, int WAVES_M, int WAVES_N, int KB, int OCC, int ILV = 0>
 void launch_mfma(const Structure& s, const void* X, const void* T, void* Y, int64_t ld, int ncol, hipStream_t st) {
     constexpr int BM = 16 * WM * WAVES_M, BN = 16 * WN * WAVES_N;
@@ -560,6 +554,12 @@ __global__ void convert_kernel(const double* __restrict__ src, E* __restrict__ d
 }
 
 }  // namespace
+
+int device_cus(int device) {
+    int cus = 0;
+    WFQ_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device));
+    return cus > 0 ? cus : 1;
+}
 
 void* split_workspace(const Structure& s, uint64_t bytes) {
     if (s.split_fixed) {

@@ -79,17 +79,18 @@ void dcgs_coeff(const int* sys, int nsys, int k, bool with_z, int mdim, const Dc
 void dcgs_update(const Basis& V, int64_t n, const int* sys, int nsys, int k, int mdim, const DcgsArgs& a,
                  hipStream_t st);
 
-// y = R^-1 g over the first k[s] steps; cond[s] = max|R_ii| / min|R_ii| (a cheap condition estimate).
+// y = R^-1 g over the first k[s] steps
 void tri_solve(const int* sys, int nsys, const int* ksteps, int mdim, const double2* R, const double2* g,
-               double2* y, double* cond, hipStream_t st);
+               double2* y, hipStream_t st);
 // x(s) += sum_{i < k[s]} y[s][i] V(s, i)
 void x_update(const Basis& V, const Basis& x, int64_t n, const int* sys, int nsys, const int* ksteps,
               const double2* y, int mdim, hipStream_t st);
 
-// r(s) = b[dir[s]] - (L Y[2k,2k+1] + z_s x(s)) written to V(s, 0); norm2[s][blk] partial |r|^2.
+// r(s) = b[dir[s]] - (L Y[2k,2k+1] + z_s x(s)) written to V(s, 0); norm2[s][blk] partial |r|^2;
+// with Y = T x, qtq[s][blk] (if not NULL) the partial sums of x^H T x
 void residual(const Structure& S, const double* Y, int64_t ld, const int* sys, int nsys, const double2* z,
               const Basis& x, const double* b, const int* dir, const Basis& V, double* norm2, int nblk,
-              hipStream_t st);
+              double* qtq, hipStream_t st);
 inline int resid_blocks(int64_t n) { return (int)((n + 255) / 256); }
 // out[s] = sqrt(sum_b norm2[s][b]) for b < nb
 void sumsq(const int* sys, int nsys, const double* norm2, int nb, double* out, hipStream_t st);
@@ -170,9 +171,9 @@ void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const do
 void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const double2* z, const double* H, double* cs,
                double2* sn, double2* g, double2* R, int64_t S, double* est, const double* tol_abs, int* flags,
                int* run, int* ksteps, hipStream_t st);
-// y = R^-1 g over k[s] columns (system-minor R and g as above); cond = max|R_ii| / min|R_ii|
+// y = R^-1 g over k[s] columns (system-minor R and g as above)
 void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t S, const double2* g,
-              double2* y, double* cond, hipStream_t st);
+              double2* y, hipStream_t st);
 // x(s) = V(d, 0..k[s]-1) y[s] for groups of kMsGroup systems (grp_sys entries -1 = none)
 void ms_xupdate(const double* V, int64_t n, int64_t npad, int mdim1, const int* grp_sys, const int* grp_dir, int ngrp,
                 const int* ksteps, const double2* y, int m, const Basis& X, hipStream_t st);

@@ -209,8 +209,7 @@ __global__ void reduce_dots_kernel(const int* __restrict__ sys, int j, const dou
 // One wave per system: column-oriented back substitution on R y = g (k <= mdim - 1 steps).
 __global__ void __launch_bounds__(64) tri_solve_kernel(const int* __restrict__ sys, const int* __restrict__ ksteps,
                                                        int mdim, const double2* __restrict__ R,
-                                                       const double2* __restrict__ g, double2* __restrict__ y,
-                                                       double* __restrict__ cond) {
+                                                       const double2* __restrict__ g, double2* __restrict__ y) {
     const int s = sys[blockIdx.x];
     const int lane = threadIdx.x;
     const int kk = ksteps[s];
@@ -224,7 +223,6 @@ __global__ void __launch_bounds__(64) tri_solve_kernel(const int* __restrict__ s
         const int l = lane + 64 * q;
         rhs[q] = l < kk ? gs[l] : make_double2(0.0, 0.0);
     }
-    double dmax = 0.0, dmin = 1e300;
     for (int i = kk - 1; i >= 0; --i) {
         const int owner = i & 63, slot = i >> 6;
         double2 ri = make_double2(0.0, 0.0);
@@ -237,9 +235,6 @@ __global__ void __launch_bounds__(64) tri_solve_kernel(const int* __restrict__ s
         const double dd = d.x * d.x + d.y * d.y;
         const double2 yi = make_double2((ri.x * d.x + ri.y * d.y) / dd, (ri.y * d.x - ri.x * d.y) / dd);
         if (lane == 0) ys[i] = yi;
-        const double ad = sqrt(dd);
-        dmax = fmax(dmax, ad);
-        dmin = fmin(dmin, ad);
         // rhs_l -= R_li y_i for l < i (column i of R)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -251,7 +246,6 @@ __global__ void __launch_bounds__(64) tri_solve_kernel(const int* __restrict__ s
             }
         }
     }
-    if (cond && lane == 0) cond[s] = kk > 0 && dmin > 0.0 ? dmax / dmin : 1.0;
 }
 
 __global__ void __launch_bounds__(256) x_update_kernel(Basis V, Basis X, int64_t n, const int* __restrict__ sys,
@@ -280,12 +274,13 @@ __global__ void __launch_bounds__(256) residual_kernel(int64_t n, int64_t npad, 
                                                        const double* __restrict__ Y, int64_t ld,
                                                        const int* __restrict__ sys, const double2* __restrict__ z,
                                                        Basis X, const double* __restrict__ b, const int* __restrict__ dir,
-                                                       Basis V, double* __restrict__ norm2, int nblk) {
+                                                       Basis V, double* __restrict__ norm2, int nblk,
+                                                       double* __restrict__ qtq) {
     __shared__ double sh[4];
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int k = blockIdx.y;
     const int s = sys[k];
-    double nn = 0.0;
+    double nn = 0.0, et = 0.0;
     if (i < n) {
         double ar = 0.0, ai = 0.0;
         for (int p = 0; p < w; ++p) {
@@ -303,9 +298,15 @@ __global__ void __launch_bounds__(256) residual_kernel(int64_t n, int64_t npad, 
         vr[i] = rr;
         vr[i + V.npad] = ri;
         nn = rr * rr + ri * ri;
+        // Re(conj(x_i) (T x)_i); T is real and symmetric, so the sum over i is x^H T x
+        et = xre * Y[(int64_t)(2 * k) * ld + i] + xim * Y[(int64_t)(2 * k + 1) * ld + i];
     }
     nn = block_sum(nn, sh);
     if (threadIdx.x == 0) norm2[(int64_t)s * nblk + blockIdx.x] = nn;
+    if (qtq) {
+        et = block_sum(et, sh);   // block_sum synchronises before it reuses sh
+        if (threadIdx.x == 0) qtq[(int64_t)s * nblk + blockIdx.x] = et;
+    }
 }
 
 __global__ void __launch_bounds__(256) copy_rhs_kernel(int64_t n, const int* __restrict__ sys,
@@ -512,10 +513,10 @@ void reduce_dots(int64_t n, const int* sys, int nsys, int j, const double2* part
 }
 
 void tri_solve(const int* sys, int nsys, const int* ksteps, int mdim, const double2* R, const double2* g,
-               double2* y, double* cond, hipStream_t st) {
+               double2* y, hipStream_t st) {
     if (nsys <= 0) return;
     if (mdim > 257) throw Error{WFQ_EINVAL, "restart length above 256 is not supported"};
-    hipLaunchKernelGGL(tri_solve_kernel, dim3(nsys), dim3(64), 0, st, sys, ksteps, mdim, R, g, y, cond);
+    hipLaunchKernelGGL(tri_solve_kernel, dim3(nsys), dim3(64), 0, st, sys, ksteps, mdim, R, g, y);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -529,11 +530,11 @@ void x_update(const Basis& V, const Basis& x, int64_t n, const int* sys, int nsy
 
 void residual(const Structure& S, const double* Y, int64_t ld, const int* sys, int nsys, const double2* z,
               const Basis& x, const double* b, const int* dir, const Basis& V, double* norm2, int nblk,
-              hipStream_t st) {
+              double* qtq, hipStream_t st) {
     if (nsys <= 0) return;
     dim3 grd((unsigned)nblk, (unsigned)nsys);
     hipLaunchKernelGGL(residual_kernel, grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col, S.ell_val, Y, ld, sys,
-                       z, x, b, dir, V, norm2, nblk);
+                       z, x, b, dir, V, norm2, nblk, qtq);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -223,11 +223,9 @@ __global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, i
 
 // y = R^-1 g over the first k[s] columns, one work-group per system: column-oriented back
 // substitution on the packed R (entry i of column c at ((c (c + 1) / 2) + i) S + s), y kept in LDS;
-// cond[s] = max|R_ii| / min|R_ii|.
 __global__ void __launch_bounds__(256) ms_solve_kernel(const int* __restrict__ sys, const int* __restrict__ ksteps,
                                                        int m, const double2* __restrict__ R, int64_t S,
-                                                       const double2* __restrict__ g, double2* __restrict__ y,
-                                                       double* __restrict__ cond) {
+                                                       const double2* __restrict__ g, double2* __restrict__ y) {
     extern __shared__ double2 ys[];
     const int s = sys[blockIdx.x];
     const int K = ksteps[s];
@@ -242,15 +240,6 @@ __global__ void __launch_bounds__(256) ms_solve_kernel(const int* __restrict__ s
         __syncthreads();
     }
     for (int i = threadIdx.x; i < K; i += blockDim.x) y[(int64_t)s * m + i] = ys[i];
-    if (threadIdx.x == 0) {
-        double dmax = 0.0, dmin = 1e300;
-        for (int i = 0; i < K; ++i) {
-            const double a = cabs(rat(i, i));
-            dmax = fmax(dmax, a);
-            dmin = fmin(dmin, a);
-        }
-        cond[s] = K > 0 ? dmax / dmin : 1.0;
-    }
 }
 
 // x(s) = sum_{i < k[s]} y[s][i] V(d, i) for groups of up to 8 systems of one direction (the basis
@@ -371,10 +360,10 @@ void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const do
 }
 
 void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2* R, int64_t S, const double2* g,
-              double2* y, double* cond, hipStream_t st) {
+              double2* y, hipStream_t st) {
     if (nsys <= 0) return;
     hipLaunchKernelGGL(ms_solve_kernel, dim3((unsigned)nsys), dim3(256), (size_t)m * sizeof(double2), st, sys, ksteps,
-                       m, R, S, g, y, cond);
+                       m, R, S, g, y);
     WFQ_CHECK_LAUNCH();
 }
 

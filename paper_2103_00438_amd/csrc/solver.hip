@@ -140,7 +140,7 @@ struct WorkShape {
 
 // arrays of the multi-shift phase (one real basis per direction, one shifted recurrence per system)
 struct MsWork {
-    Buf<double> V, H, part, h1, h2, nrm, inv_h, cs, est, tol_abs, cond;
+    Buf<double> V, H, part, h1, h2, nrm, inv_h, cs, est, tol_abs;
     Buf<double2> sn, g, R, y, z;
     Buf<int> dirs, sdir, sys, flags, ksteps, grp_sys, grp_dir, run;
     Buf<int> h_dirs, h_sys, h_k;   // pinned
@@ -155,7 +155,8 @@ struct Work {
     int B = 0, mdim = 0, n_dir = 0;
     int64_t n = 0, npad = 0, nwc = 0, nblk = 0, mpad = 0;
     bool need32 = false, need16 = false;
-    Buf<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, tol_abs, cond;
+    Buf<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, tol_abs;
+    Buf<double> qT, qtq;   // |x|_T = sqrt(x^H T x) at the last FP64 residual, and its block partials
     Buf<float> X32, Y32, Y16, Yp32;   // Yp*: the products' planes interleaved for the SpMM (large N)
     Buf<double> Yp64;
     Buf<uint16_t> X16;
@@ -175,7 +176,7 @@ struct Work {
     Buf<float2> bj_P;
     MsWork ms;
     // pinned host mirrors
-    Buf<double> h_snorm, h_est, h_beta, h_invb;
+    Buf<double> h_snorm, h_est, h_beta, h_invb, h_qT;
     // est (B doubles), flags and ksteps (B ints each) side by side on the device and in the pinned
     // mirror, so that the per-step read-back is one copy
     Buf<double> step_dev, step_host;
@@ -241,7 +242,8 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.beta, B);
     d.take(w.norm2, (size_t)B * std::max(w.nwc, w.nblk));
     d.take(w.tol_abs, B);
-    d.take(w.cond, B);
+    d.take(w.qT, B);
+    d.take(w.qtq, (size_t)B * w.nblk);
     w.flags = Buf<int>{w.step_dev.p ? reinterpret_cast<int*>(w.step_dev.p + B) : nullptr, (size_t)B};
     w.ksteps = Buf<int>{w.step_dev.p ? reinterpret_cast<int*>(w.step_dev.p + B) + B : nullptr, (size_t)B};
     d.take(w.run, B);
@@ -276,6 +278,7 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     w.h_ksteps = Buf<int>{w.step_host.p ? reinterpret_cast<int*>(w.step_host.p + B) + B : nullptr, (size_t)B};
     h.take(w.h_run, B);
     h.take(w.h_beta, B);
+    h.take(w.h_qT, B);
     h.take(w.h_invb, B);
     h.take(w.h_snorm, B);
     h.take(w.h_g, (size_t)B * (w.mdim + 1));
@@ -298,7 +301,6 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
         d.take(q.z, B);
         d.take(q.est, B);
         d.take(q.tol_abs, B);
-        d.take(q.cond, B);
         d.take(q.dirs, n_dir);
         d.take(q.sdir, B);
         d.take(q.sys, B);
@@ -459,10 +461,22 @@ struct SysState {
     int prec = WFQ_PREC_FP64;
     int status = WFQ_OK;
     int iters = 0, cycles = 0;
-    double bnorm = 0, beta = 0, relres = 1, est_end = 0, cond = 1;
+    double bnorm = 0, beta = 0, relres = 1, est_end = 0;
+    double qT = 0;      // |q|_T at the last FP64 residual
     double t_done = 0;
     bool done = false;
 };
+
+// Bound on |q - q*|_T / |q*|_T, |v|_T = sqrt(v^H T v). With T symmetric positive definite and L
+// symmetric positive semi-definite, L T is self-adjoint in the T inner product with real eigenvalues
+// lambda >= 0, so |(L T + z I)^-1|_T = 1 / min |lambda + z| <= 1 / |Im z|. Hence
+// |q - q*|_T <= |r|_T / |Im z| <= sqrt(rho_T) |r|_2 / |Im z|, rho_T >= lambda_max(T) the largest row
+// sum of T (Gershgorin), and eps = that / |q|_T gives |q - q*|_T / |q*|_T <= eps / (1 - eps).
+double error_bound(const Structure& S, const SysState& q) {
+    if (!(q.beta > 0.0)) return q.beta == 0.0 ? 0.0 : q.beta;   // exact, or NaN passed on
+    const double eps = std::sqrt(S.t_rowsum) * q.beta / (std::fabs(q.z.y) * q.qT);
+    return eps < 1.0 ? eps / (1.0 - eps) : INFINITY;
+}
 
 void* x_block(Work& w, int prec) {
     return prec == WFQ_PREC_FP64 ? (void*)w.X64.p : prec == WFQ_PREC_FP32 ? (void*)w.X32.p : (void*)w.X16.p;
@@ -507,7 +521,8 @@ void progress_line(const wfq_solve_opts& o, const char* what, int cycle, int ste
     std::fflush(stderr);
 }
 
-// FP64 refinement residual of the systems in `act`: V(s,0) = b - (L T + z I) x, beta = ||V(s,0)||.
+// FP64 refinement residual of the systems in `act`: V(s,0) = b - (L T + z I) x, beta = ||V(s,0)||,
+// qT = |x|_T (from the same product T x).
 void fp64_residual(const Structure& S, Work& w, const std::vector<int>& act, Timer& tm, hipStream_t st) {
     const int na = (int)act.size();
     const double n = (double)S.n;
@@ -516,8 +531,10 @@ void fp64_residual(const Structure& S, Work& w, const std::vector<int>& act, Tim
     tm.end(st, KC_PACK, 0, 32.0 * n * na);
     block_product(S, w, WFQ_PREC_FP64, 2 * na, tm, st);
     tm.begin(st);
-    residual(S, w.Y64.p, w.npad, w.sys[SLOT_ACT].p, na, w.z.p, w.Xb, w.b.p, w.dir.p, w.Vb, w.norm2.p, (int)w.nblk, st);
+    residual(S, w.Y64.p, w.npad, w.sys[SLOT_ACT].p, na, w.z.p, w.Xb, w.b.p, w.dir.p, w.Vb, w.norm2.p, (int)w.nblk,
+             w.qtq.p, st);
     sumsq(w.sys[SLOT_ACT].p, na, w.norm2.p, (int)w.nblk, w.beta.p, st);
+    sumsq(w.sys[SLOT_ACT].p, na, w.qtq.p, (int)w.nblk, w.qT.p, st);
     tm.end(st, KC_RESID, 4.0 * S.nnz * na + 8 * n * na, 12.0 * S.nnz + na * n * (16 + 16 + 16 + 8));
 }
 
@@ -589,10 +606,12 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         upload(w, SLOT_ACT, active, st);
         fp64_residual(S, w, active, tm, st);
         WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipMemcpyAsync(w.h_qT.p, w.qT.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
         WFQ_HIP(hipStreamSynchronize(st));
         std::vector<int> still;
         for (int s : active) {
             ss[s].beta = w.h_beta.p[s];
+            ss[s].qT = w.h_qT.p[s];
             ss[s].relres = ss[s].beta / ss[s].bnorm;
             if (ss[s].relres <= tol) {
                 ss[s].done = true;
@@ -747,7 +766,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         upload(w, SLOT_ACT, active, st);
         WFQ_HIP(hipMemcpyAsync(w.ksteps.p, w.h_ksteps.p, B * sizeof(int), hipMemcpyHostToDevice, st));
         tm.begin(st);
-        tri_solve(w.sys[SLOT_ACT].p, na, w.ksteps.p, w.mdim, w.R.p, w.g.p, w.y.p, w.cond.p, st);
+        tri_solve(w.sys[SLOT_ACT].p, na, w.ksteps.p, w.mdim, w.R.p, w.g.p, w.y.p, st);
         if (bj) {
             // x += M^-1 (V y)
             WFQ_HIP(hipMemsetAsync(w.bj_U.p, 0, w.bj_U.count * sizeof(double), st));
@@ -762,15 +781,15 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         }
         fp64_residual(S, w, active, tm, st);
         WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
-        std::vector<double> condh(B);
-        d2h_sync(S, condh.data(), w.cond.p, B * sizeof(double), st);
+        WFQ_HIP(hipMemcpyAsync(w.h_qT.p, w.qT.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipStreamSynchronize(st));
         std::vector<int> still;
         const double now = ms_since(t0);
         for (int s : active) {
             const double beta_prev = ss[s].beta;
             ss[s].beta = w.h_beta.p[s];
             ss[s].relres = ss[s].beta / ss[s].bnorm;
-            ss[s].cond = condh[s];
+            ss[s].qT = w.h_qT.p[s];
             if (!std::isfinite(ss[s].beta)) {
                 ss[s].status = WFQ_ENUMERIC;
                 ss[s].done = true;
@@ -869,7 +888,7 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     MsWork& q = w.ms;
     if (w.shape.ms_m != m) throw Error{WFQ_EDEVICE, "multi-shift work space of the wrong dimension"};
     double *V = q.V.p, *H = q.H.p, *part = q.part.p, *h1 = q.h1.p, *h2 = q.h2.p, *nrm = q.nrm.p, *inv_h = q.inv_h.p;
-    double *cs = q.cs.p, *est = q.est.p, *tol_abs = q.tol_abs.p, *cond = q.cond.p;
+    double *cs = q.cs.p, *est = q.est.p, *tol_abs = q.tol_abs.p;
     double2 *sn = q.sn.p, *g = q.g.p, *R = q.R.p, *y = q.y.p, *z = q.z.p;
     int *dirs = q.dirs.p, *sdir = q.sdir.p, *sys = q.sys.p, *flags = q.flags.p, *ksteps = q.ksteps.p;
     int *grp_sys = q.grp_sys.p, *grp_dir = q.grp_dir.p, *run = q.run.p;
@@ -1050,19 +1069,12 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     if (!withk.empty()) {
         std::memcpy(h_sys, withk.data(), withk.size() * sizeof(int));
         WFQ_HIP(hipMemcpyAsync(sys, h_sys, withk.size() * sizeof(int), hipMemcpyHostToDevice, st));
-        ms_solve(sys, (int)withk.size(), ksteps, m, R, B, g, y, cond, st);
+        ms_solve(sys, (int)withk.size(), ksteps, m, R, B, g, y, st);
     }
     ms_xupdate(V, n, np, mdim1, grp_sys, grp_dir, ngrp, ksteps, y, m, w.Xb, st);
     tm.end(st, KC_XUPDATE, 0, 0);
-    std::vector<double> ch(B, 1.0);
-    if (!withk.empty())
-        d2h_sync(S, ch.data(), cond, B * sizeof(double), st);
-    else
-        WFQ_HIP(hipStreamSynchronize(st));
-    for (int s = 0; s < B; ++s) {
-        ss[s].iters += h_k[s];
-        if (h_k[s] > 0) ss[s].cond = ch[s];
-    }
+    WFQ_HIP(hipStreamSynchronize(st));
+    for (int s = 0; s < B; ++s) ss[s].iters += h_k[s];
     if (o.progress) progress_line(o, "multi-shift done", 0, 0, stepping.size(), -1.0, t0);
 }
 
@@ -1204,17 +1216,21 @@ void qmr_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double to
             tm.end(st, KC_PACK, 0, 32.0 * n * na2);
             block_product(S, w, WFQ_PREC_FP64, 2 * na2, tm, st);
             tm.begin(st);
-            residual(S, w.Y64.p, w.npad, w.sys[SLOT_ACT].p, na2, w.z.p, XQ, w.b.p, w.dir.p, Q, w.norm2.p, nblk, st);
+            residual(S, w.Y64.p, w.npad, w.sys[SLOT_ACT].p, na2, w.z.p, XQ, w.b.p, w.dir.p, Q, w.norm2.p, nblk,
+                     w.qtq.p, st);
             sumsq(w.sys[SLOT_ACT].p, na2, w.norm2.p, nblk, w.beta.p, st);
+            sumsq(w.sys[SLOT_ACT].p, na2, w.qtq.p, nblk, w.qT.p, st);
             tm.end(st, KC_RESID, 0, 12.0 * S.nnz + na2 * n * 56.0);
         }
         WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipMemcpyAsync(w.h_qT.p, w.qT.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
         WFQ_HIP(hipStreamSynchronize(st));
         std::vector<int> still;
         const double now = ms_since(t0);
         for (int s : active) {
             const double beta_prev = ss[s].beta;
             ss[s].beta = w.h_beta.p[s];
+            ss[s].qT = w.h_qT.p[s];
             ss[s].relres = ss[s].beta / ss[s].bnorm;
             if (!std::isfinite(ss[s].beta)) {
                 ss[s].status = WFQ_ENUMERIC;
@@ -1310,6 +1326,7 @@ uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_d
     b += (uint64_t)B * 2 * mdim * nwc * 16;     // fused dot partials (two entries per basis vector)
     b += (uint64_t)B * 2 * mdim * mdim * 16;    // R and the Hessenberg matrix before rotations
     b += (uint64_t)B * (mdim * 64 + 2 * np * 8 / 1);  // small arrays + output staging
+    b += (uint64_t)B * (np / 256 + 1) * 8;             // block partials of x^H T x
     b += std::min<uint64_t>(kSplitWsCap, 7 * mpad * np * 8);   // split-k partial tiles
     if (o.algorithm == WFQ_MSGMRES) b += ms_bytes(S, o, B, n_dir);
     if (o.algorithm == WFQ_QMR) b += (uint64_t)B * 2 * np * 8;   // compact T p
@@ -1489,7 +1506,7 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
                 r.precision = q.prec;
                 r.relres = q.relres;
                 r.rmse = q.beta / std::sqrt((double)S.n);
-                r.err_est = q.relres * q.cond;
+                r.err_est = error_bound(S, q);
                 r.t_done_ms = q.t_done;
             }
             if (q.status != WFQ_OK && worst == WFQ_OK) worst = q.status;

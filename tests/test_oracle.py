@@ -583,3 +583,48 @@ def test_reduced_precision_copies_of_t_on_a_metal_sphere():
         q32 = np.linalg.solve(L @ T32 + z * np.eye(P.n), b.astype(complex))
         assert np.linalg.norm(qb - q) / np.linalg.norm(q) > 0.05
         assert np.linalg.norm(q32 - q) / np.linalg.norm(q) < 2e-5
+
+
+# ----------------------------------------------------------------- error bound in the Coulomb norm
+
+def test_inverse_operator_norm_in_the_coulomb_norm():
+    # L T is self-adjoint in the T inner product (T SPD, L symmetric PSD), so its eigenvalues are real
+    # and >= 0 and |(L T + z I)^-1|_T = 1 / min_j |lambda_j + z| <= 1 / |Im z|; the largest row sum of
+    # T bounds lambda_max(T) (Gershgorin, positive entries). Checked on a small disk with dense algebra
+    # (|M|_T = |T^1/2 M T^-1/2|_2), including a frequency on a resonance where the bound is attained.
+    xyz = geo.jitter(geo.graphene_disk(8.0), 0.02, 4)
+    P = O.Problem(xyz, G)
+    T, L = P.T, P.L.toarray()
+    ev, U = np.linalg.eigh(T)
+    assert ev[-1] <= np.max(T.sum(axis=1)) and np.all(T > 0)
+    Th, Tmh = (U * np.sqrt(ev)) @ U.T, (U / np.sqrt(ev)) @ U.T
+    lam = np.linalg.eigvals(L @ T)
+    assert np.max(np.abs(lam.imag)) < 1e-10 * np.max(np.abs(lam)) and lam.real.min() > -1e-10 * lam.real.max()
+    lam = np.sort(lam.real)
+    W = O.material_weight(G)
+    om_res = math.sqrt(lam[len(lam) // 2] * W) * 27.211386245988     # omega^2 / W on an eigenvalue
+    for om in (0.05, 0.4, 1.0, om_res):
+        z = P.z(om)
+        Ainv = np.linalg.inv(L @ T + z * np.eye(P.n))
+        nT = np.linalg.norm(Th @ Ainv @ Tmh, 2)
+        assert nT == pytest.approx(1.0 / np.min(np.abs(lam + z)), rel=1e-8)
+        assert nT <= (1 + 1e-12) / abs(z.imag)
+    assert nT == pytest.approx(1.0 / abs(z.imag), rel=1e-6)   # on the resonance
+
+
+def test_error_bound_of_restarted_gmres_iterates():
+    # The bound the library reports, from the oracle's own iterates: eps = sqrt(rho_T) |r| / (|Im z| |q|_T)
+    # and |q - q*|_T / |q*|_T <= eps / (1 - eps)
+    xyz = geo.jitter(geo.graphene_disk(10.0), 0.02, 6)
+    P = O.Problem(xyz, G)
+    rho = np.max(P.T.sum(axis=1))
+    tn = lambda v: math.sqrt(np.real(np.vdot(v, P.T @ v)))
+    for om in (0.1, 0.6, 1.2):
+        qs = P.solve_lu(om, [1, 0, 0])
+        for tol in (1e-2, 1e-4, 1e-7):
+            q, _ = P.solve_gmres(om, [1, 0, 0], 20, tol)
+            r = P.rhs([1, 0, 0]) - P.apply(P.z(om))(q)
+            eps = math.sqrt(rho) * np.linalg.norm(r) / (abs(P.z(om).imag) * tn(q))
+            assert eps < 1 or tol > 1e-3      # a loose tolerance may leave the bound infinite
+            if eps < 1:
+                assert tn(q - qs) / tn(qs) <= eps / (1 - eps)

@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--no-multishift", action="store_true", help="skip the multi-shift FP64 run of the same systems")
     ap.add_argument("--no-block-jacobi", action="store_true",
                     help="skip the leg with block-Jacobi right preconditioning (64-atom diagonal blocks)")
+    ap.add_argument("--ni-study", action="store_true",
+                    help="per-frequency full-GMRES iteration counts against sigma_k (one JSON line per structure)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB on the device 4 times (calibrates the HBM byte counters) and report GB/s")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in block-product shapes")
@@ -559,6 +561,57 @@ def bench_multishift(args, wl, wfq, torch):
     return line
 
 
+def plateau_peaks(y):
+    """Indices of local maxima of a sequence, a run of equal values counting once (its middle), when
+    both neighbouring runs are lower."""
+    runs, i = [], 0
+    while i < len(y):
+        j = i
+        while j + 1 < len(y) and y[j + 1] == y[i]:
+            j += 1
+        runs.append((i, j, y[i]))
+        i = j + 1
+    return [(runs[k][0] + runs[k][1]) // 2 for k in range(1, len(runs) - 1)
+            if runs[k][2] > runs[k - 1][2] and runs[k][2] > runs[k + 1][2]]
+
+
+def ni_study(wfq):
+    """The paper's NI study: full GMRES from q0 = 0 with ||r||_2 < 1e-6 a.u. (the multi-shift basis
+    gives every frequency the full-GMRES iterate of its own shift), sigma_k per frequency, and how
+    often a local maximum of sigma_k has a local maximum of NI within one and two grid points."""
+    import wfq_inputs as wi
+    from wfq_inputs import geometry as geo
+    sharp = dict(wi.workloads.GRAPHENE, fermi_energy_eV=1.51, tau=17000.0)
+    disk = wi.workload("disk600_spectrum")
+    cases = [("disk600_spectrum", disk.xyz, disk.params, disk.omegas_eV, [0, 1]),
+             ("disk600, eps_F 1.51 eV, tau 17000 a.u.", disk.xyz, sharp, np.arange(1, 401) * 0.01, [0, 1]),
+             ("(10,10) nanotube, 100 cells, eps_F 1.51 eV, tau 17000 a.u.", geo.nanotube(10, 10, 100), sharp,
+              np.arange(1, 201) * 0.01, [0, 2])]
+    lines = []
+    for name, xyz, par, om, ks in cases:
+        h = wfq.wfq_build(xyz, par)
+        rec = dict(study="ni_vs_sigma", structure=name, n_atoms=int(len(xyz)), omega_eV=[round(float(w), 4) for w in om],
+                   threshold_abs=1e-6, directions={})
+        for k in ks:
+            d = np.eye(3)[k:k + 1]
+            bn = float(np.linalg.norm(wfq.wfq_rhs(h, d)[0]))
+            out = wfq.wfq_solve(h, om, d, 1e-6 / bn, want_q=False, algorithm="msgmres", precision="fp64",
+                                shift_dim=1024, max_iter=20000)
+            ni = [r["iters"] for r in out["info"]]
+            sg = [r["sigma"] for r in out["info"]]
+            ps, pn = plateau_peaks(sg), plateau_peaks(ni)
+            near = lambda tol: (float(np.mean([min((abs(p - q) for q in pn), default=99) <= tol for p in ps]))
+                                if ps else None)
+            rec["directions"]["xyz"[k]] = dict(
+                ni=ni, sigma_bohr2=[float(f"{v:.6g}") for v in sg], status=int(out["status"]),
+                sigma_peaks_eV=[rec["omega_eV"][p] for p in ps], ni_peaks_eV=[rec["omega_eV"][p] for p in pn],
+                matched_within_1=near(1), matched_within_2=near(2), full_gmres=bool(max(ni) <= 1024),
+                chance_within_2=min(1.0, 5 * len(pn) / len(ni)))
+        h.close()
+        lines.append(rec)
+    return lines
+
+
 def bench_latency(args, wl, wfq, torch):
     """disk600: one small system; latency of a single solve."""
     h = wfq.wfq_build(wl.xyz, wl.params, device=0)
@@ -666,6 +719,10 @@ def main():
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / 4
         print(json.dumps(dict(copy_bytes=2 * a.numel() * 4, copy_gbps=2 * a.numel() * 4 / dt / 1e9)))
+        return
+    if args.ni_study:
+        for rec in ni_study(wfq):
+            print(json.dumps(rec))
         return
     wl = wi.workload(args.workload)
     if args.restart > 0:

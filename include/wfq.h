@@ -208,6 +208,9 @@ typedef struct {
                             when eps >= 1). Exact up to the FP64 rounding of r. The 2-norm relative error
                             is at most sqrt(kappa_2(T)) err_est. */
     double  t_done_ms;   /* completion time of this system, measured from the start of the call */
+    double  sigma;       /* absorption cross section for this field direction k, Eq. (long-cross):
+                            sigma_k = (4 pi omega / c) Im(k . alpha), alpha the induced dipole per unit
+                            field, omega in Hartree, c = 137.035999084: bohr^2 */
 } wfq_result;
 
 /*
@@ -251,6 +254,14 @@ int wfq_solve_dev(wfq_handle* h, const double* omegas_eV, int32_t n_omega,
                   const double* dirs, int32_t n_dir, double tol, const wfq_solve_opts* o,
                   double* q_re_dev, double* q_im_dev, double* alpha_re_dev, double* alpha_im_dev,
                   wfq_result* info, void* stream);
+
+/*
+ * wfq_isotropic_sigma - Eq. (iso-cross): sigma(omega) = (1/3) sum_k sigma_k(omega) over three
+ * orthonormal field directions. `dirs` [3][3] are the directions of a wfq_solve call with n_dir = 3
+ * (rows orthonormal to 1e-9, else WFQ_EINVAL) and `info` its [n_omega][3] results; writes
+ * sigma_iso [n_omega] (bohr^2). Host only, no device needed.
+ */
+int wfq_isotropic_sigma(const double* dirs, const wfq_result* info, int32_t n_omega, double* sigma_iso);
 
 /* ------------------------------------------------------------------ single steps (for checks)
  * These expose one stage of the path each, in the caller's atom order, so that every stage can be

@@ -245,6 +245,20 @@ def solve_modal(L, T, z, B):
     return tih @ (U @ coef)
 
 
+def modal_resonances(L, T, W, r):
+    """Plasmon resonances of the modal form: alpha(z) = sum_j w_j lam_j / (lam_j + z) for the field
+    direction whose position projections are r (E0 = 1), with lam_j the eigenvalues of S and
+    w_j = (u_j^T T^(-1/2) r)^2 (from solve_modal). Re(lam_j + z) = 0 at omega_j = sqrt(W lam_j), where
+    Im alpha peaks with height proportional to the residue w_j lam_j. Returns (omega_j in Hartree,
+    w_j lam_j), sorted by frequency, for the modes with lam_j > 0."""
+    lam, U, _, tih = modal_decomposition(L, T)
+    w = (U.T @ (tih @ np.asarray(r, dtype=np.float64))) ** 2
+    keep = lam > 0
+    om = np.sqrt(W * lam[keep])
+    order = np.argsort(om)
+    return om[order], (w[keep] * lam[keep])[order]
+
+
 def static_polarisability(T, R):
     """alpha(0) = R^T [T^-1 - T^-1 1 1^T T^-1 / (1^T T^-1 1)] R, the omega -> 0 conductor limit."""
     n = T.shape[0]

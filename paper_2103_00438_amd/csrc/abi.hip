@@ -223,6 +223,22 @@ int wfq_material_weight(const wfq_params* p, double* W) {
     });
 }
 
+int wfq_isotropic_sigma(const double* dirs, const wfq_result* info, int32_t n_omega, double* sigma_iso) {
+    return guarded([&]() -> int {
+        if (!dirs || !info || !sigma_iso || n_omega < 1) fail(WFQ_EINVAL, "bad arguments");
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b) {
+                double d = 0.0;
+                for (int l = 0; l < 3; ++l) d += dirs[3 * a + l] * dirs[3 * b + l];
+                if (!(std::fabs(d - (a == b ? 1.0 : 0.0)) <= 1e-9))
+                    fail(WFQ_EINVAL, "the three field directions must be orthonormal");
+            }
+        for (int w = 0; w < n_omega; ++w)
+            sigma_iso[w] = (info[3 * w].sigma + info[3 * w + 1].sigma + info[3 * w + 2].sigma) / 3.0;
+        return WFQ_OK;
+    });
+}
+
 int wfq_build(const wfq_geometry* g, const wfq_params* p, wfq_handle** out) {
     if (out) *out = nullptr;
     return guarded([&]() -> int {

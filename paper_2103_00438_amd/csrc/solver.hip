@@ -472,6 +472,8 @@ struct SysState {
 // lambda >= 0, so |(L T + z I)^-1|_T = 1 / min |lambda + z| <= 1 / |Im z|. Hence
 // |q - q*|_T <= |r|_T / |Im z| <= sqrt(rho_T) |r|_2 / |Im z|, rho_T >= lambda_max(T) the largest row
 // sum of T (Gershgorin), and eps = that / |q|_T gives |q - q*|_T / |q*|_T <= eps / (1 - eps).
+constexpr double kLightAU = 137.035999084;   // speed of light in atomic units (CODATA 2018)
+
 double error_bound(const Structure& S, const SysState& q) {
     if (!(q.beta > 0.0)) return q.beta == 0.0 ? 0.0 : q.beta;   // exact, or NaN passed on
     const double eps = std::sqrt(S.t_rowsum) * q.beta / (std::fabs(q.z.y) * q.qT);
@@ -1508,6 +1510,10 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
                 r.rmse = q.beta / std::sqrt((double)S.n);
                 r.err_est = error_bound(S, q);
                 r.t_done_ms = q.t_done;
+                // Eq. (long-cross): sigma_k = (4 pi omega / c) Im(k . alpha), c in atomic units
+                double ka = 0.0;
+                for (int l = 0; l < 3; ++l) ka += dirs[3 * q.dir + l] * aim[(size_t)s * 3 + l];
+                r.sigma = 4.0 * M_PI * q.omega / kLightAU * ka;
             }
             if (q.status != WFQ_OK && worst == WFQ_OK) worst = q.status;
             if (q.status == WFQ_ENUMERIC) worst = WFQ_ENUMERIC;

@@ -59,7 +59,8 @@ class SolveOpts(C.Structure):
 
 class Result(C.Structure):
     _fields_ = [("status", C.c_int32), ("iters", C.c_int32), ("cycles", C.c_int32), ("precision", C.c_int32),
-                ("relres", C.c_double), ("rmse", C.c_double), ("err_est", C.c_double), ("t_done_ms", C.c_double)]
+                ("relres", C.c_double), ("rmse", C.c_double), ("err_est", C.c_double), ("t_done_ms", C.c_double),
+                ("sigma", C.c_double)]
 
 
 class ServeCfg(C.Structure):
@@ -114,6 +115,7 @@ _SIGNATURES = {
     "wfq_serve_stop": (None, [C.c_void_p]),
     "wfq_last_error": (C.c_char_p, []),
     "wfq_material_weight": (C.c_int, [C.POINTER(Params), C.POINTER(C.c_double)]),
+    "wfq_isotropic_sigma": (C.c_int, [_DP, C.POINTER(Result), C.c_int32, _DP]),
     "wfq_tx_variants": (C.c_int, [C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_char_p), C.POINTER(C.c_int32)]),
     "wfq_tune": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int32), C.c_int32, C.c_int32, _DP,
                            C.POINTER(C.c_int32)]),
@@ -268,7 +270,7 @@ def make_opts(algorithm="gmres", restart=50, max_iter=100000, precision="fp64", 
 
 def _results(info):
     return [dict(status=r.status, iters=r.iters, cycles=r.cycles, precision=PREC_NAMES[r.precision],
-                 relres=r.relres, rmse=r.rmse, err_est=r.err_est, t_done_ms=r.t_done_ms) for r in info]
+                 relres=r.relres, rmse=r.rmse, err_est=r.err_est, t_done_ms=r.t_done_ms, sigma=r.sigma) for r in info]
 
 
 def wfq_solve(h: Handle, omegas_eV, dirs, tol, want_q=True, check=True, **opts) -> dict:
@@ -289,7 +291,25 @@ def wfq_solve(h: Handle, omegas_eV, dirs, tol, want_q=True, check=True, **opts) 
                        info)
     if check:
         _check(rc, (WFQ_OK, WFQ_ENOCONV, WFQ_ENUMERIC, WFQ_EBREAKDOWN))
-    return dict(q=(qr + 1j * qi) if want_q else None, alpha=ar + 1j * ai, info=_results(info), status=rc)
+    out = dict(q=(qr + 1j * qi) if want_q else None, alpha=ar + 1j * ai, info=_results(info), status=rc,
+               sigma=np.array([r.sigma for r in info]).reshape(no, nd))
+    if nd == 3:
+        iso = np.zeros(no)
+        if lib.wfq_isotropic_sigma(_dp(d), info, no, _dp(iso)) == WFQ_OK:   # orthonormal directions only
+            out["sigma_iso"] = iso
+    return out
+
+
+def wfq_isotropic_sigma(dirs, sigma) -> np.ndarray:
+    """Eq. (iso-cross) from sigma [n_omega, 3] of three orthonormal directions dirs [3, 3] (host)."""
+    d = _f64(dirs).reshape(3, 3)
+    sg = _f64(sigma).reshape(-1, 3)
+    info = (Result * sg.size)()
+    for i, v in enumerate(sg.ravel()):
+        info[i].sigma = float(v)
+    out = np.zeros(len(sg))
+    _check(load().wfq_isotropic_sigma(_dp(d), info, len(sg), _dp(out)))
+    return out
 
 
 def wfq_solve_dev(h: Handle, omegas_eV, dirs, tol, q_re=None, q_im=None, alpha_re=None, alpha_im=None,

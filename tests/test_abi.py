@@ -2,6 +2,7 @@
 point declared in include/wfq.h, and rejects bad arguments before touching a device."""
 
 import ctypes
+import math
 import os
 import re
 
@@ -130,3 +131,22 @@ def test_material_closure_of_the_library_equals_the_oracle():
     with pytest.raises(wfq.WfqError) as e:
         wfq.wfq_material_weight(dict(wi.workloads.GRAPHENE, material=None, W=0.0))
     assert e.value.code == wfq.WFQ_EINVAL
+
+
+def test_isotropic_sigma_helper():
+    # Eq. (iso-cross) on the host: the mean of the three sigma_k for orthonormal directions, and a
+    # clear error for directions that are not
+    from paper_2103_00438_amd import wfq
+    lib = wfq.load()
+    c, s = math.cos(0.3), math.sin(0.3)
+    dirs = np.array([[c, s, 0.0], [-s, c, 0.0], [0.0, 0.0, 1.0]])
+    info = (wfq.Result * 6)()
+    vals = [1.0, 2.0, 6.0, 0.5, 0.25, 0.0]
+    for i, v in enumerate(vals):
+        info[i].sigma = v
+    iso = np.zeros(2)
+    assert lib.wfq_isotropic_sigma(wfq._dp(dirs), info, 2, wfq._dp(iso)) == wfq.WFQ_OK
+    assert iso[0] == pytest.approx(3.0) and iso[1] == pytest.approx(0.25)
+    bad = dirs.copy()
+    bad[2] = [0.0, 0.6, 0.8]
+    assert lib.wfq_isotropic_sigma(wfq._dp(bad), info, 2, wfq._dp(iso)) == wfq.WFQ_EINVAL

@@ -53,3 +53,69 @@ def test_disk_spectrum_matches_modal_form(lib):
         assert np.all(sig_gpu >= 0)
         assert np.max(np.abs(sig_gpu - sig_ref)) <= 1e-6 * sig_ref.max()
         assert peaks(sig_gpu) == peaks(sig_ref)
+
+
+def test_cross_section_outputs(lib):
+    # sigma_k per (omega, k) and the isotropic sigma come out of the library (Eqs. long-cross and
+    # iso-cross); they must equal the oracle's functions applied to the library's alpha, and the modal
+    # closed form
+    wl = wi.workload("disk600_spectrum")
+    P = O.Problem(wl.xyz, wl.params)
+    om = wl.omegas_eV[::10]
+    h = lib.wfq_build(wl.xyz, wl.params)
+    out = lib.wfq_solve(h, om, wl.dirs, 1e-10, want_q=False, algorithm="msgmres", precision="fp64")
+    h.close()
+    assert out["status"] == 0 and "sigma_iso" in out
+    oh = np.array([O.ev_to_hartree(w) for w in om])
+    for k in range(3):
+        ref = np.array([O.cross_section(oh[a], out["alpha"][a, k, k]) for a in range(len(om))])
+        assert np.allclose(out["sigma"][:, k], ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    iso = np.array([O.isotropic_cross_section(oh[a], out["alpha"][a].T) for a in range(len(om))])
+    assert np.allclose(out["sigma_iso"], iso, rtol=1e-12, atol=1e-12 * np.abs(iso).max())
+    modal = np.mean([modal_sigma(P, om, k) for k in range(3)], axis=0)
+    assert np.max(np.abs(out["sigma_iso"] - modal)) <= 1e-8 * modal.max()
+
+
+def strong_resonances(P, lo_eV, hi_eV, k):
+    """The k strongest modal resonances for a field along x in a window (degenerate modes within
+    0.01 eV merged, peaks at least 0.1 eV apart), in eV."""
+    om, res = O.modal_resonances(P.L, P.T, P.W, P.xyz[:, 0])
+    om = om * 27.211386245988
+    sel = (om > lo_eV) & (om < hi_eV)
+    groups = []
+    for w, s in zip(om[sel], res[sel]):
+        if groups and w - groups[-1][0] < 0.01:
+            groups[-1][1] += s
+        else:
+            groups.append([w, s])
+    out = []
+    for w, s in sorted(groups, key=lambda g: -g[1]):
+        if all(abs(w - v) >= 0.1 for v in out):
+            out.append(w)
+        if len(out) == k:
+            break
+    return sorted(out)
+
+
+@pytest.mark.parametrize("algorithm", ["gmres", "msgmres"])
+def test_iterations_peak_at_plasmon_resonances(lib, algorithm):
+    # The paper's NI study on graphene disks (full GMRES from q0 = 0, ||r||_2 < 1e-6 a.u.): iteration
+    # counts have local maxima at the plasmon resonances. 564-atom disk, eps_F = 1.51 eV, tau = 17000
+    # a.u.; the three strongest modal resonances of the oracle in 0.3-3.0 eV, probed 0.03 eV to either
+    # side. The multi-shift basis gives every frequency the full-GMRES iterate of its own shift.
+    from wfq_inputs import geometry as geo
+    par = dict(wi.workloads.GRAPHENE, fermi_energy_eV=1.51, tau=17000.0)
+    xyz = geo.graphene_disk(22.0)
+    P = O.Problem(xyz, par)
+    res = strong_resonances(P, 0.3, 3.0, 3)
+    assert len(res) == 3
+    om = np.array([[w - 0.03, w, w + 0.03] for w in res]).ravel()
+    h = lib.wfq_build(xyz, par)
+    bn = np.linalg.norm(lib.wfq_rhs(h, np.eye(3)[:1])[0])
+    out = lib.wfq_solve(h, om, np.eye(3)[:1], 1e-6 / bn, want_q=False, algorithm=algorithm, restart=256,
+                        precision="fp64")
+    h.close()
+    assert out["status"] == 0
+    ni = np.array([r["iters"] for r in out["info"]]).reshape(3, 3)
+    for j in range(3):
+        assert ni[j, 1] > ni[j, 0] and ni[j, 1] > ni[j, 2], (res[j], ni[j])

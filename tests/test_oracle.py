@@ -628,3 +628,61 @@ def test_error_bound_of_restarted_gmres_iterates():
             assert eps < 1 or tol > 1e-3      # a loose tolerance may leave the bound infinite
             if eps < 1:
                 assert tn(q - qs) / tn(qs) <= eps / (1 - eps)
+
+
+# ----------------------------------------------------------------- plasmon resonances and iteration counts
+
+def _strong_resonances(P, lo_eV, hi_eV, k):
+    """The k strongest modal resonances in a window (degenerate modes within 0.01 eV merged, peaks
+    at least 0.1 eV apart), in eV."""
+    om, res = O.modal_resonances(P.L, P.T, P.W, P.xyz[:, 0])
+    om = om * 27.211386245988
+    sel = (om > lo_eV) & (om < hi_eV)
+    om, res = om[sel], res[sel]
+    groups = []
+    for w, s in zip(om, res):
+        if groups and w - groups[-1][0] < 0.01:
+            groups[-1][1] += s
+        else:
+            groups.append([w, s])
+    out = []
+    for w, s in sorted(groups, key=lambda g: -g[1]):
+        if all(abs(w - v) >= 0.1 for v in out):
+            out.append(w)
+        if len(out) == k:
+            break
+    return sorted(out)
+
+
+def test_modal_resonances_are_the_cross_section_peaks():
+    # sigma_x(omega) from LU has a local maximum at each strong modal resonance (long relaxation time:
+    # sharp peaks), and the modal sum reproduces the LU polarisability
+    par = dict(G, fermi_energy_eV=1.51, tau=17000.0)
+    P = O.Problem(geo.graphene_disk(14.0), par)
+    res = _strong_resonances(P, 0.3, 3.5, 2)
+    assert len(res) == 2
+    for w in res:
+        s = [O.cross_section(O.ev_to_hartree(v), O.polarisability(P.xyz, P.solve_lu(v, [1, 0, 0])[:, None])[0, 0])
+             for v in (w - 0.004, w, w + 0.004)]
+        assert s[1] > s[0] and s[1] > s[2], (w, s)
+    om, wl = O.modal_resonances(P.L, P.T, P.W, P.xyz[:, 0])
+    z = P.z(1.0)
+    a_modal = np.sum(wl / ((om ** 2) / P.W + z))           # sum_j w_j lam_j / (lam_j + z)
+    a_lu = O.polarisability(P.xyz, P.solve_lu(1.0, [1, 0, 0])[:, None])[0, 0]
+    assert a_modal == pytest.approx(a_lu, rel=1e-9)
+
+
+def test_gmres_iterations_peak_at_plasmon_resonances():
+    # The paper's observation on graphene disks (full GMRES, q0 = 0, ||r||_2 < 1e-6 a.u.): the number
+    # of iterations has local maxima where the cross section has its plasmon peaks. Oracle GMRES on a
+    # 564-atom disk with eps_F = 1.51 eV and tau = 17000 a.u.: at each of the three strongest modal
+    # resonances in 0.3-3.0 eV (above 3 eV the modes are closer than the 0.03 eV probe) it needs more
+    # iterations than 0.03 eV to either side.
+    par = dict(G, fermi_energy_eV=1.51, tau=17000.0)
+    P = O.Problem(geo.graphene_disk(22.0), par)
+    bn = np.linalg.norm(P.rhs([1, 0, 0]))
+    res = _strong_resonances(P, 0.3, 3.0, 3)
+    assert len(res) == 3
+    for w in res:
+        ni = [P.solve_gmres(v, [1, 0, 0], P.n, 1e-6 / bn)[1]["iters"] for v in (w - 0.03, w, w + 0.03)]
+        assert ni[1] > ni[0] and ni[1] > ni[2], (w, ni)

@@ -16,6 +16,9 @@
 // arrays are system-minor (entry e of system s at e * S + s, S = systems of the batch), so that the
 // one-thread-per-system Givens step reads and writes consecutive addresses across a wave: rotations
 // cs/sn (m entries), g (m + 1), R packed by columns (column j from entry j (j + 1) / 2).
+#include <algorithm>
+#include <type_traits>
+
 #include "device_util.h"
 #include "krylov.h"
 
@@ -53,21 +56,29 @@ __global__ void __launch_bounds__(256) ms_pack_kernel(double* __restrict__ V, in
     X[(int64_t)c * ld + i] = cast_from_double<E>(a);
 }
 
-// V(d_c, jdst) = L Y[c] (real ELL rows; padding rows get 0)
-template <typename YE>
+// V(d_c, jdst) = L Y[c] for the NC columns c0 .. c0 + NC - 1 (real ELL rows; padding rows get 0).
+// Each thread reads its row of L once for all NC columns.
+template <typename YE, int NC>
 __global__ void __launch_bounds__(256) ms_spmm_kernel(int64_t n, int64_t npad, int w, const int32_t* __restrict__ ecol,
                                                       const double* __restrict__ eval, const YE* __restrict__ Y,
                                                       int64_t ld, const int* __restrict__ dirs, double* __restrict__ V,
-                                                      int mdim1, int jdst) {
+                                                      int mdim1, int jdst, int c0) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int c = blockIdx.y;
-    double acc = 0.0;
+    double acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     if (i < n) {
-        const YE* y = Y + (int64_t)c * ld;
+        const YE* y = Y + (int64_t)c0 * ld;
 #pragma unroll 4
-        for (int e = 0; e < w; ++e) acc += eval[(int64_t)e * npad + i] * widen(y[ecol[(int64_t)e * npad + i]]);
+        for (int e = 0; e < w; ++e) {
+            const double v = eval[(int64_t)e * npad + i];
+            const int64_t j = ecol[(int64_t)e * npad + i];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) acc[c] += v * widen(y[c * ld + j]);
+        }
     }
-    slot(V, npad, mdim1, dirs[c], jdst)[i] = acc;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) slot(V, npad, mdim1, dirs[c0 + c], jdst)[i] = acc[c];
 }
 
 // partial[d][i][wc] = sum over wave chunk wc (512 rows) of V(d, i) * V(d, jw) for i < nvec; with
@@ -304,14 +315,28 @@ void ms_pack(int prec, double* V, int64_t npad, int mdim1, int j, const int* dir
 void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* dirs, int ndir, double* V,
              int mdim1, int jdst, hipStream_t st) {
     if (ndir <= 0) return;
-    dim3 grd((unsigned)(S.npad / 256), (unsigned)ndir);
-    if (y_is_f64)
-        hipLaunchKernelGGL(ms_spmm_kernel<double>, grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col, S.ell_val,
-                           static_cast<const double*>(Y), ld, dirs, V, mdim1, jdst);
-    else
-        hipLaunchKernelGGL(ms_spmm_kernel<float>, grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col, S.ell_val,
-                           static_cast<const float*>(Y), ld, dirs, V, mdim1, jdst);
-    WFQ_CHECK_LAUNCH();
+    const dim3 grd((unsigned)(S.npad / 256));
+    // columns in chunks of at most 4 (3 for the usual three field directions in one pass)
+    for (int c0 = 0; c0 < ndir; c0 += 4) {
+        const int nc = std::min(4, ndir - c0);
+        auto go = [&](auto tag, auto ncv) {
+            using YE = decltype(tag);
+            constexpr int NC = decltype(ncv)::value;
+            hipLaunchKernelGGL((ms_spmm_kernel<YE, NC>), grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col,
+                               S.ell_val, static_cast<const YE*>(Y), ld, dirs, V, mdim1, jdst, c0);
+        };
+        auto by_nc = [&](auto tag) {
+            if (nc == 1) go(tag, std::integral_constant<int, 1>{});
+            else if (nc == 2) go(tag, std::integral_constant<int, 2>{});
+            else if (nc == 3) go(tag, std::integral_constant<int, 3>{});
+            else go(tag, std::integral_constant<int, 4>{});
+        };
+        if (y_is_f64)
+            by_nc(double{});
+        else
+            by_nc(float{});
+        WFQ_CHECK_LAUNCH();
+    }
 }
 
 void ms_dot(const double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,

@@ -993,7 +993,8 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
             block_product(S, w, cur, na, tm, st);
             tm.begin(st);
             ms_spmm(S, cur == WFQ_PREC_FP64, y_block(w, cur), np, dirs, na, V, mdim1, j + 1, st);
-            tm.end(st, KC_SPMM, 2.0 * S.nnz * na, 12.0 * S.nnz * na + na * dn * (out_size(cur) + 8));
+            // L is read once for all directions (up to four per pass)
+            tm.end(st, KC_SPMM, 2.0 * S.nnz * na, 12.0 * S.nnz * ((na + 3) / 4) + na * dn * (out_size(cur) + 8));
             // two classical Gram-Schmidt passes against v_0 .. v_j
             const double pass = 8.0 * dn * na * (j + 2);
             tm.begin(st);

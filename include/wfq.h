@@ -191,6 +191,15 @@ typedef struct {
                             chooses it from the measured relative error delta of one product in `precision`:
                             0.5 tol / (100 delta), clipped to [tol, 1]. Every result still ends with the FP64
                             residual check and, where needed, batched GMRES in `precision`. */
+    int32_t recycle;     /* GMRES only, 0 = off; k in [1, 8]: subspace recycling across neighbouring frequencies
+                            (a project extension next to the shift structure the paper's conclusions point
+                            to; the paper starts every solve from q0 = 0). Per direction, every second
+                            frequency (sorted) and the highest are solved from zero; each other one is
+                            solved by GMRES augmented with a recycle space (GCRO) spanned by the solutions
+                            of its k nearest solved frequencies: every cycle starts from the residual
+                            projected off C = A U and every Krylov vector is kept orthogonal to C. Needs
+                            at least three frequencies (else plain GMRES); not with block_jacobi; replaces
+                            warm_start. */
 } wfq_solve_opts;
 
 typedef struct {

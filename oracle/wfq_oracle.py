@@ -345,6 +345,95 @@ def gmres(apply, b, restart, tol, maxiter, x0=None):
     return x, dict(iters=iters, cycles=cycles, relres=history[-1], history=history)
 
 
+# --------------------------------------------------------------------------- GMRES with a recycled subspace
+
+def gcro(apply, b, U, AU, restart, tol, maxiter):
+    """GMRES(m) augmented with a fixed recycle space (GCRO: de Sturler 1999; the recycling that Parks,
+    de Sturler et al. 2006 build on), for the recycling the paper's conclusions suggest for spectra.
+
+    U [n][k] spans the recycle space and AU = A U. C = A U' with C^H C = I comes from two modified
+    Gram-Schmidt passes over the columns of AU (U' = U R^-1 alike; a column whose remainder is below
+    1e-12 ||b|| is dropped). Every restart takes the explicit residual r = b - A x, stops when
+    ||r|| / ||b|| <= tol, else moves the part of r in range(C) into x (x += U' C^H r, r -= C C^H r) and
+    runs one GMRES cycle on (I - C C^H) A: each Arnoldi vector w = A v_j gives B_j = C^H w and
+    w -= C B_j before the modified Gram-Schmidt sweep against V. The cycle's least-squares solution y
+    (Givens rotations, as in `gmres`) gives x += V y - U' (B y), since A V = C B + V_{m+1} Hbar.
+    With k = 0 this is `gmres`. Returns (x, info) with info = dict(iters, cycles, relres, history)."""
+    b = np.asarray(b, dtype=np.complex128)
+    n = b.shape[0]
+    bnorm = np.linalg.norm(b)
+    if bnorm == 0.0:
+        return np.zeros(n, dtype=np.complex128), dict(iters=0, cycles=0, relres=0.0, history=[])
+    Cs, Us = [], []
+    for c in range(0 if U is None else np.asarray(U).shape[1]):
+        cv = np.array(AU[:, c], dtype=np.complex128)
+        uv = np.array(U[:, c], dtype=np.complex128)
+        for _ in range(2):
+            for cq, uq in zip(Cs, Us):
+                h = np.vdot(cq, cv)
+                cv = cv - h * cq
+                uv = uv - h * uq
+        nrm = np.linalg.norm(cv)
+        if nrm > 1e-12 * bnorm:
+            Cs.append(cv / nrm)
+            Us.append(uv / nrm)
+    C = np.array(Cs).T if Cs else np.zeros((n, 0), dtype=np.complex128)
+    Up = np.array(Us).T if Us else np.zeros((n, 0), dtype=np.complex128)
+    m = int(restart)
+    x = np.zeros(n, dtype=np.complex128)
+    iters, cycles, history = 0, 0, []
+    while True:
+        r = b - apply(x)
+        beta = np.linalg.norm(r)
+        history.append(beta / bnorm)
+        if beta / bnorm <= tol or iters >= maxiter:
+            break
+        c0 = C.conj().T @ r
+        x = x + Up @ c0
+        r = r - C @ c0
+        beta = np.linalg.norm(r)
+        if beta == 0.0:
+            history.append(0.0)
+            break
+        cycles += 1
+        V = np.zeros((m + 1, n), dtype=np.complex128)
+        H = np.zeros((m + 1, m), dtype=np.complex128)
+        Bm = np.zeros((C.shape[1], m), dtype=np.complex128)
+        cs = np.zeros(m)
+        sn = np.zeros(m, dtype=np.complex128)
+        g = np.zeros(m + 1, dtype=np.complex128)
+        g[0] = beta
+        V[0] = r / beta
+        k = 0
+        for j in range(m):
+            w = apply(V[j])
+            iters += 1
+            Bm[:, j] = C.conj().T @ w
+            w = w - C @ Bm[:, j]
+            for i in range(j + 1):
+                H[i, j] = np.vdot(V[i], w)
+                w = w - H[i, j] * V[i]
+            hn = np.linalg.norm(w)
+            H[j + 1, j] = hn
+            if hn > 0.0:
+                V[j + 1] = w / hn
+            for i in range(j):
+                t = cs[i] * H[i, j] + sn[i] * H[i + 1, j]
+                H[i + 1, j] = -np.conj(sn[i]) * H[i, j] + cs[i] * H[i + 1, j]
+                H[i, j] = t
+            cs[j], sn[j] = _givens(H[j, j], H[j + 1, j])
+            H[j, j] = cs[j] * H[j, j] + sn[j] * H[j + 1, j]
+            H[j + 1, j] = 0.0
+            g[j + 1] = -np.conj(sn[j]) * g[j]
+            g[j] = cs[j] * g[j]
+            k = j + 1
+            if abs(g[j + 1]) / bnorm <= tol or hn == 0.0 or iters >= maxiter:
+                break
+        y = scipy.linalg.solve_triangular(H[:k, :k], g[:k], lower=False)
+        x = x + V[:k].T @ y - Up @ (Bm[:, :k] @ y)
+    return x, dict(iters=iters, cycles=cycles, relres=history[-1], history=history)
+
+
 # --------------------------------------------------------------------------- one Krylov space for all frequencies
 
 def gmres_multishift(apply_A, b, shifts, tol, maxdim):
@@ -656,6 +745,34 @@ class Problem:
             x0 = interpolate_start(Q[a], Q[b], self.z(om[a]), self.z(om[b]), self.z(om[k]))
             Q[k], info = self.solve_gmres(om[k], direction, restart, tol, maxiter, E0, x0=x0)
             iters[k] = info["iters"]
+        return Q, iters, first
+
+    def solve_recycled_sweep(self, omegas_eV, direction, restart, tol, k, maxiter=100000, E0=1.0):
+        """GMRES over a frequency sweep with subspace recycling (a project extension; the paper starts
+        every solve from q0 = 0). With the frequencies sorted, every second one and the highest are
+        solved from zero (`gmres`); each other one by `gcro` with the recycle space spanned by the
+        solutions of its k nearest solved frequencies (ties to the lower one) and A U formed with its
+        own shift. Returns (Q [n_omega][N] in the given order, iters [n_omega], first [n_omega] bool)."""
+        om = np.asarray(omegas_eV, dtype=np.float64)
+        order = np.argsort(om, kind="stable")
+        c = len(om)
+        first = np.zeros(c, dtype=bool)
+        for p, q in enumerate(order):
+            first[q] = (p % 2 == 0) or (p == c - 1)
+        Q = np.zeros((c, self.n), dtype=np.complex128)
+        iters = np.zeros(c, dtype=np.int64)
+        b = self.rhs(direction, E0)
+        for q in np.flatnonzero(first):
+            Q[q], info = self.solve_gmres(om[q], direction, restart, tol, maxiter, E0)
+            iters[q] = info["iters"]
+        solved = [q for p, q in enumerate(order) if first[q]]     # increasing frequency
+        for q in np.flatnonzero(~first):
+            near = sorted(solved, key=lambda a: abs(om[a] - om[q]))[:k]
+            A = self.apply(self.z(om[q]))
+            U = np.array([Q[a] for a in near]).T
+            AU = np.array([A(Q[a]) for a in near]).T
+            Q[q], info = gcro(A, b, U, AU, restart, tol, maxiter)
+            iters[q] = info["iters"]
         return Q, iters, first
 
     def apply_LT(self, x):

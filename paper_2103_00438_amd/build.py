@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libwfq.so")
 
-SOURCES = ["build.hip", "gemm.hip", "otf.hip", "krylov.hip", "dcgs.hip", "qmr.hip", "mshift.hip", "solver.hip", "precond.hip", "abi.hip", "serve.hip"]
+SOURCES = ["build.hip", "gemm.hip", "otf.hip", "krylov.hip", "dcgs.hip", "qmr.hip", "mshift.hip", "solver.hip", "precond.hip", "recycle.hip", "abi.hip", "serve.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

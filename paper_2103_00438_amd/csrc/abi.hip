@@ -37,7 +37,7 @@ void* scratch_ptr(int device);   // the allocation-free entry point's scratch on
 const char* kClassNames[KC_COUNT] = {"tx_gemm_f64", "tx_gemm_f32", "tx_gemm_bf16", "tx_skinny", "tx_otf_f32", "tx_otf_f64",
                                      "spmm_shift",  "cgs_dot",     "cgs_update",   "givens",    "pack",
                                      "x_update",    "fp64_residual", "qmr",        "block_jacobi", "other",
-                                     "tx_skinny_f32", "tx_skinny_bf16", "tx_otf_narrow"};
+                                     "tx_skinny_f32", "tx_skinny_bf16", "tx_otf_narrow", "recycle"};
 
 template <typename F>
 int guarded(F&& f) {
@@ -86,6 +86,9 @@ void check_opts(const wfq_solve_opts* o) {
     if (!(o->qmr_breakdown >= 0.0)) fail(WFQ_EINVAL, "qmr_breakdown must be >= 0");
     if (!std::isfinite(o->ms_relax)) fail(WFQ_EINVAL, "ms_relax must be finite");
     if (o->warm_start && o->algorithm != WFQ_GMRES) fail(WFQ_EINVAL, "warm starts are a GMRES option");
+    if (o->recycle < 0 || o->recycle > 8) fail(WFQ_EINVAL, "recycle must be in [0, 8]");
+    if (o->recycle && o->algorithm != WFQ_GMRES) fail(WFQ_EINVAL, "subspace recycling is a GMRES option");
+    if (o->recycle && o->block_jacobi) fail(WFQ_EINVAL, "subspace recycling does not combine with block-Jacobi");
     if (o->block_jacobi && o->algorithm != WFQ_GMRES)
         fail(WFQ_EINVAL, "block-Jacobi preconditioning is a GMRES option");
     if (o->block_jacobi && o->warm_start) fail(WFQ_EINVAL, "block_jacobi and warm_start cannot be combined");

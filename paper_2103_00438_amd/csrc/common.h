@@ -122,7 +122,7 @@ struct KernelStat {
 enum KernelClass {
     KC_GEMM_F64 = 0, KC_GEMM_F32, KC_GEMM_BF16, KC_SKINNY, KC_OTF, KC_OTF_F64,
     KC_SPMM, KC_DOT, KC_UPDATE, KC_GIVENS, KC_PACK, KC_XUPDATE, KC_RESID, KC_QMR, KC_PRECOND, KC_OTHER,
-    KC_SKINNY_F32, KC_SKINNY_BF16, KC_OTF_NARROW,
+    KC_SKINNY_F32, KC_SKINNY_BF16, KC_OTF_NARROW, KC_RECYCLE,
     KC_COUNT
 };
 

@@ -192,4 +192,34 @@ void bj_pack(int prec, const Basis& V, int j, const int* sys, int nsys, const do
 // X(s) += P_s U(s) for the nsys listed systems
 void bj_add(const int* sys, int nsys, const float2* P, int64_t npad, const Basis& U, const Basis& X, hipStream_t st);
 
+// ---- subspace recycling across frequencies (recycle.hip): GMRES augmented with a fixed recycle
+// space per system, C = A U' orthonormal (k[s] <= kmax vectors in the layout of Basis)
+struct RecycleSpace {
+    Basis C, U;                // C_i and U'_i of every system
+    int kmax = 0;
+    int* kk = nullptr;         // [B] vectors of each system's space (0: none)
+    double2* part = nullptr;   // [B][kmax][chunks] partial dots
+    double2* coef = nullptr;   // [B][kmax] coefficients of the last projection (C^H v)
+    double2* Bm = nullptr;     // [B][kmax][mdim] B = C^H A Q of the current cycle
+};
+// V(s, j) -= C C^H V(s, j) for the listed systems (coef keeps C^H V(s, j)); with X, X(s) += U' C^H V(s, j);
+// with norm2, the 256-row block partials of |V(s, j)|^2 afterwards (nblk blocks)
+void rc_project(const RecycleSpace& R, const Basis& V, int j, const Basis* X, const int* sys, int nsys,
+                const int* run, int64_t n, double* norm2, int nblk, hipStream_t st);
+// column k of B from the projection coefficients of step k's product and the step's DCGS dots / 1 / rho
+void rc_bcol(const RecycleSpace& R, const int* sys, int nsys, const int* run, int k, int mdim, const double2* dots,
+             const double* inv_rho, hipStream_t st);
+// X(s) -= U' (B y) over the completed columns ksteps[s]
+void rc_xfix(const RecycleSpace& R, const Basis& X, const int* sys, int nsys, const int* ksteps, const double2* y,
+             int mdim, int64_t n, hipStream_t st);
+// C_i = b - r_a + (z_s - z_a) x_a, U_i = x_a for the neighbours a = nbr[t][i] (-1: zero vector) of the
+// listed target systems; r_a = V(a, 0) (the final FP64 residual of a), x_a = X(a)
+void rc_init(const RecycleSpace& R, const Basis& V, const Basis& X, const double* b, const int* dir, const double2* z,
+             const int* sys, int nsys, const int* nbr, int64_t n, hipStream_t st);
+// one Gram-Schmidt pass of vector i against vectors 0 .. i-1 (C and U alike), |C_i|^2 block partials
+void rc_orth_step(const RecycleSpace& R, int i, const int* sys, int nsys, int64_t n, double* norm2, int nblk,
+                  hipStream_t st);
+// C_i *= inv[s], U_i *= inv[s]
+void rc_scale(const RecycleSpace& R, int i, const int* sys, int nsys, const double* inv, hipStream_t st);
+
 }  // namespace wfq

@@ -132,9 +132,10 @@ struct WorkShape {
     int B = 0, m = 0, n_dir = 0, prec = 0, ms_m = 0;   // ms_m: shared-basis dimension (0: no multi-shift)
     bool qmr = false;
     bool bj = false;   // block-Jacobi preconditioning
+    int rk = 0;        // recycle space dimension (0: no recycling)
     bool operator==(const WorkShape& o) const {
         return B == o.B && m == o.m && n_dir == o.n_dir && prec == o.prec && ms_m == o.ms_m && qmr == o.qmr &&
-               bj == o.bj;
+               bj == o.bj && rk == o.rk;
     }
 };
 
@@ -174,6 +175,13 @@ struct Work {
     // ([B][npad/64][64 x 64] complex FP32, column-major) and the preconditioned vector u of every system
     Buf<double> bj_C, bj_U;
     Buf<float2> bj_P;
+    // subspace recycling: C and U' of every system, the per-system counts, partial dots, coefficients,
+    // B of the cycle, the neighbours of the targets and per-system scale factors
+    Buf<double> rc_C, rc_U, rc_inv, h_rc_inv;
+    Buf<int> rc_kk, rc_nbr, h_rc_kk, h_rc_nbr;
+    Buf<double2> rc_part, rc_coef, rc_B;
+    RecycleSpace rc;
+    bool rc_active = false;   // the current pass projects onto the recycle spaces
     MsWork ms;
     // pinned host mirrors
     Buf<double> h_snorm, h_est, h_beta, h_invb, h_qT;
@@ -270,6 +278,20 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     d.take(w.bj_C, sh.bj ? (size_t)np * 64 : 0);
     d.take(w.bj_P, sh.bj ? (size_t)B * np * 64 : 0);
     d.take(w.bj_U, sh.bj ? (size_t)B * 2 * np : 0);
+    {
+        const size_t rk = (size_t)sh.rk;
+        d.take(w.rc_C, (size_t)B * rk * 2 * np);
+        d.take(w.rc_U, (size_t)B * rk * 2 * np);
+        d.take(w.rc_inv, rk ? (size_t)B : 0);
+        d.take(w.rc_kk, rk ? (size_t)B : 0);
+        d.take(w.rc_nbr, (size_t)B * rk);
+        d.take(w.rc_part, (size_t)B * rk * wave_chunks(S.n));
+        d.take(w.rc_coef, (size_t)B * rk);
+        d.take(w.rc_B, (size_t)B * rk * (m + 1));
+        h.take(w.h_rc_inv, rk ? (size_t)B : 0);
+        h.take(w.h_rc_kk, rk ? (size_t)B : 0);
+        h.take(w.h_rc_nbr, (size_t)B * rk);
+    }
     d.take(w.stage_re, (size_t)B * S.n);   // host outputs are staged through these
     d.take(w.stage_im, (size_t)B * S.n);
     h.take(w.step_host, (size_t)2 * B);
@@ -319,6 +341,13 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
     w.Xb = sh.qmr ? Basis{w.V.p + 5 * 2 * np, (int64_t)w.mdim * 2 * np, 2 * np, np}   // the QMR iterate
                   : Basis{w.X.p, 2 * np, 2 * np, np};
     w.Ub = Basis{w.bj_U.p, 2 * np, 0, np};   // one vector per system: every slot index names it
+    w.rc.C = Basis{w.rc_C.p, (int64_t)sh.rk * 2 * np, 2 * np, np};
+    w.rc.U = Basis{w.rc_U.p, (int64_t)sh.rk * 2 * np, 2 * np, np};
+    w.rc.kmax = sh.rk;
+    w.rc.kk = w.rc_kk.p;
+    w.rc.part = w.rc_part.p;
+    w.rc.coef = w.rc_coef.p;
+    w.rc.Bm = w.rc_B.p;
 }
 
 // Allocates the work space of one shape: one device and one pinned host allocation.
@@ -558,7 +587,13 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
         }
         h2d_sync(S, w.z.p, zh.data(), B * sizeof(double2), st);
         h2d_sync(S, w.dir.p, dh.data(), B * sizeof(int), st);
-        if (!warm) WFQ_HIP(hipMemsetAsync(w.X.p, 0, w.X.count * sizeof(double), st));
+        if (!warm && !only) {
+            WFQ_HIP(hipMemsetAsync(w.X.p, 0, w.X.count * sizeof(double), st));
+        } else if (!warm) {
+            // x0 = 0 for the listed systems only (the others may hold solutions of an earlier pass)
+            for (int s : *only)
+                WFQ_HIP(hipMemsetAsync(w.Xb.base + (size_t)s * w.Xb.sys_stride, 0, 2 * S.npad * sizeof(double), st));
+        }
         WFQ_HIP(hipStreamSynchronize(st));
     }
     std::vector<int> all;
@@ -631,6 +666,30 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
     }
 
     while (!active.empty()) {
+        if (w.rc_active) {
+            // recycling: x += U' C^H r, r -= C C^H r, and the norm of the projected residual
+            upload(w, SLOT_ACT, active, st);
+            tm.begin(st);
+            rc_project(w.rc, w.Vb, 0, &w.Xb, w.sys[SLOT_ACT].p, (int)active.size(), nullptr, S.n, w.norm2.p,
+                       (int)w.nblk, st);
+            sumsq(w.sys[SLOT_ACT].p, (int)active.size(), w.norm2.p, (int)w.nblk, w.beta.p, st);
+            tm.end(st, KC_RECYCLE, 0, 0);
+            WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
+            WFQ_HIP(hipStreamSynchronize(st));
+            std::vector<int> still;
+            for (int s : active) {
+                ss[s].beta = w.h_beta.p[s];
+                if (ss[s].beta > 0.0) {
+                    still.push_back(s);
+                } else {   // the solution lies in the recycle space
+                    ss[s].relres = 0.0;
+                    ss[s].done = true;
+                    ss[s].t_done = ms_since(t0);
+                }
+            }
+            active.swap(still);
+            if (active.empty()) break;
+        }
         // cycle start: g = beta e1, v0 = r / beta
         std::memset(w.h_g.p, 0, (size_t)B * (w.mdim + 1) * sizeof(double2));
         for (int s : active) {
@@ -709,6 +768,12 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                         tm.end(st, KC_SPMM, 4.0 * S.nnz * ng + 8 * n * ng,
                                12.0 * S.nnz + ng * n * (2.0 * out_size(p) + 16 + 16));
                     }
+                    if (w.rc_active) {
+                        // keep the new direction orthogonal to C; C^H A u is kept for B
+                        tm.begin(st);
+                        rc_project(w.rc, w.Vb, k + 1, nullptr, w.sys[SLOT_STEP].p, ns, w.run.p, S.n, nullptr, 0, st);
+                        tm.end(st, KC_RECYCLE, 8.0 * n * ns * w.rc.kmax, 32.0 * n * ns * (w.rc.kmax + 1));
+                    }
                 }
                 // one fused sweep of dots, the Hessenberg column and its rotation, one update sweep
                 const int* sl = w.sys[SLOT_STEP].p;
@@ -719,13 +784,15 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
                 tm.begin(st);
                 dcgs_coeff(sl, ns, k, with_z, w.mdim, da, st);
                 tm.end(st, KC_GIVENS, 0, 0);
+                if (with_z && w.rc_active) rc_bcol(w.rc, sl, ns, w.run.p, k, w.mdim, w.h1.p, w.irho.p, st);
                 if (with_z) {
                     tm.begin(st);
                     dcgs_update(w.Vb, S.n, sl, ns, k, w.mdim, da, st);
                     tm.end(st, KC_UPDATE, 16.0 * n * ns * k, 16.0 * n * ns * (k + 4));
                 }
             };
-            const GraphKey key{0, k0, c, ns, (int)grp[0].size(), (int)grp[1].size(), (int)grp[2].size()};
+            const GraphKey key{w.rc_active ? 2 : 0, k0, c, ns, (int)grp[0].size(), (int)grp[1].size(),
+                               (int)grp[2].size()};
             run_chunk(gc, S, key, st, [&] {
                 for (int k = k0; k < k0 + c; ++k) step(k);
             });
@@ -779,6 +846,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             tm.end(st, KC_PRECOND, 8.0 * 64 * n * na, na * n * (512.0 + 48));
         } else {
             x_update(w.Vb, w.Xb, S.n, w.sys[SLOT_ACT].p, na, w.ksteps.p, w.y.p, w.mdim, st);
+            if (w.rc_active) rc_xfix(w.rc, w.Xb, w.sys[SLOT_ACT].p, na, w.ksteps.p, w.y.p, w.mdim, S.n, st);
             tm.end(st, KC_XUPDATE, 0, 16.0 * n * na * (m + 2));
         }
         fp64_residual(S, w, active, tm, st);
@@ -1288,6 +1356,51 @@ WarmPlan warm_plan(const std::vector<SysState>& ss, int n_dir) {
     return p;
 }
 
+// Recycle spaces of the second-pass systems: the solutions of the k nearest solved systems of the
+// same direction (by frequency), made into C = A U' with C^H C = I by two Gram-Schmidt passes per
+// vector; a vector whose remainder is below 1e-12 ||b|| (the neighbours' solutions are nearly
+// dependent) is dropped (set to zero).
+void recycle_setup(const Structure& S, Work& w, const std::vector<SysState>& ss, const WarmPlan& p, hipStream_t st) {
+    const int k = w.rc.kmax;
+    const int nt = (int)p.second.size();
+    if (nt == 0 || k == 0) return;
+    std::fill(w.h_rc_kk.p, w.h_rc_kk.p + w.h_rc_kk.count, 0);
+    std::vector<double> scale(nt, 0.0);
+    for (int t = 0; t < nt; ++t) {
+        const int s = p.second[t];
+        std::vector<int> cand;
+        for (int f : p.first)
+            if (ss[f].dir == ss[s].dir && ss[f].status == WFQ_OK) cand.push_back(f);
+        std::stable_sort(cand.begin(), cand.end(), [&](int x, int y) {
+            return std::fabs(ss[x].omega - ss[s].omega) < std::fabs(ss[y].omega - ss[s].omega);
+        });
+        const int kc = std::min<int>(k, (int)cand.size());
+        for (int i = 0; i < k; ++i) w.h_rc_nbr.p[(size_t)t * k + i] = i < kc ? cand[i] : -1;
+        w.h_rc_kk.p[s] = kc;
+        scale[t] = kc > 0 ? ss[cand[0]].bnorm : 0.0;
+    }
+    upload(w, SLOT_ACT, p.second, st);
+    WFQ_HIP(hipMemcpyAsync(w.rc_kk.p, w.h_rc_kk.p, w.rc_kk.count * sizeof(int), hipMemcpyHostToDevice, st));
+    WFQ_HIP(hipMemcpyAsync(w.rc_nbr.p, w.h_rc_nbr.p, (size_t)nt * k * sizeof(int), hipMemcpyHostToDevice, st));
+    const int* sys = w.sys[SLOT_ACT].p;
+    rc_init(w.rc, w.Vb, w.Xb, w.b.p, w.dir.p, w.z.p, sys, nt, w.rc_nbr.p, S.n, st);
+    for (int i = 0; i < k; ++i) {
+        rc_orth_step(w.rc, i, sys, nt, S.n, w.norm2.p, (int)w.nblk, st);
+        rc_orth_step(w.rc, i, sys, nt, S.n, w.norm2.p, (int)w.nblk, st);
+        sumsq(sys, nt, w.norm2.p, (int)w.nblk, w.rc_inv.p, st);
+        WFQ_HIP(hipMemcpyAsync(w.h_rc_inv.p, w.rc_inv.p, w.rc_inv.count * sizeof(double), hipMemcpyDeviceToHost, st));
+        WFQ_HIP(hipStreamSynchronize(st));
+        for (int t = 0; t < nt; ++t) {
+            const int s = p.second[t];
+            const double nrm = w.h_rc_inv.p[s];
+            w.h_rc_inv.p[s] = (i < w.h_rc_kk.p[s] && nrm > 1e-12 * scale[t] && std::isfinite(nrm)) ? 1.0 / nrm : 0.0;
+        }
+        WFQ_HIP(hipMemcpyAsync(w.rc_inv.p, w.h_rc_inv.p, w.rc_inv.count * sizeof(double), hipMemcpyHostToDevice, st));
+        rc_scale(w.rc, i, sys, nt, w.rc_inv.p, st);
+        WFQ_HIP(hipStreamSynchronize(st));   // the pinned mirror is rewritten by the next vector
+    }
+}
+
 // the interpolation lists of the second pass, once the first pass is done
 void warm_lists(WarmPlan& p, const std::vector<SysState>& ss) {
     for (int s : p.second) {
@@ -1330,6 +1443,8 @@ uint64_t batch_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_d
     b += (uint64_t)B * 2 * mdim * mdim * 16;    // R and the Hessenberg matrix before rotations
     b += (uint64_t)B * (mdim * 64 + 2 * np * 8 / 1);  // small arrays + output staging
     b += (uint64_t)B * (np / 256 + 1) * 8;             // block partials of x^H T x
+    if (o.recycle > 0 && o.algorithm == WFQ_GMRES)      // recycle spaces (C and U'), dots, B
+        b += (uint64_t)B * o.recycle * (2 * 2 * np * 8 + (wave_chunks(S.n) + mdim + 1) * 16 + 4) + B * 16;
     b += std::min<uint64_t>(kSplitWsCap, 7 * mpad * np * 8);   // split-k partial tiles
     if (o.algorithm == WFQ_MSGMRES) b += ms_bytes(S, o, B, n_dir);
     if (o.algorithm == WFQ_QMR) b += (uint64_t)B * 2 * np * 8;   // compact T p
@@ -1370,6 +1485,7 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
     sh.ms_m = o.algorithm == WFQ_MSGMRES ? ms_dim(o, S.n) : 0;
     sh.qmr = qmr;
     sh.bj = o.block_jacobi && o.algorithm == WFQ_GMRES;
+    sh.rk = (o.recycle > 0 && o.algorithm == WFQ_GMRES && n_omega >= 3) ? o.recycle : 0;
     GraphCache* graphs = nullptr;
     std::unique_ptr<Work> own;   // a work space too large to keep on the handle
     Work& w = solve_work(S, sh, graphs, own);
@@ -1396,6 +1512,20 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
             // shared-basis phase, then batched GMRES from its iterates (FP64 residual first)
             msgmres_phase(S, w, ss, tol, o, tm, st, t0, graphs);
             gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs, true);
+        } else if (!qmr && sh.rk > 0) {
+            // subspace recycling: every second frequency from zero, then the others by GMRES augmented
+            // with the span of their nearest solved neighbours' solutions
+            WarmPlan wp = warm_plan(ss, n_dir);
+            gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs, false, &wp.first);
+            recycle_setup(S, w, ss, wp, st);
+            w.rc_active = true;
+            try {
+                gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs, false, &wp.second);
+            } catch (...) {
+                w.rc_active = false;
+                throw;
+            }
+            w.rc_active = false;
         } else if (!qmr && o.warm_start && n_omega >= 3) {
             WarmPlan wp = warm_plan(ss, n_dir);
             gmres_batch(S, w, ss, tol, o, tm, st, t0, graphs, false, &wp.first);

@@ -54,7 +54,7 @@ class SolveOpts(C.Structure):
                 ("precision", C.c_int32), ("E0", C.c_double), ("max_batch", C.c_int32), ("timing", C.c_int32),
                 ("escalate", C.c_int32), ("progress", C.c_int32), ("shift_dim", C.c_int32),
                 ("graphs", C.c_int32), ("warm_start", C.c_int32), ("block_jacobi", C.c_int32),
-                ("qmr_breakdown", C.c_double), ("ms_relax", C.c_double)]
+                ("qmr_breakdown", C.c_double), ("ms_relax", C.c_double), ("recycle", C.c_int32)]
 
 
 class Result(C.Structure):
@@ -261,11 +261,11 @@ def wfq_destroy(h: Handle) -> None:
 
 def make_opts(algorithm="gmres", restart=50, max_iter=100000, precision="fp64", E0=1.0, max_batch=0,
               timing=False, escalate=True, progress=False, shift_dim=0, graphs=False, warm_start=False,
-              block_jacobi=False, qmr_breakdown=0.0, ms_relax=0.0) -> SolveOpts:
+              block_jacobi=False, qmr_breakdown=0.0, ms_relax=0.0, recycle=0) -> SolveOpts:
     return SolveOpts(ALGO[algorithm], int(restart), int(max_iter), PREC[precision], float(E0), int(max_batch),
                      int(bool(timing)), int(bool(escalate)), int(bool(progress)), int(shift_dim),
                      int(bool(graphs)), int(bool(warm_start)), int(bool(block_jacobi)), float(qmr_breakdown),
-                     float(ms_relax))
+                     float(ms_relax), int(recycle))
 
 
 def _results(info):

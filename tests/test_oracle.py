@@ -686,3 +686,59 @@ def test_gmres_iterations_peak_at_plasmon_resonances():
     for w in res:
         ni = [P.solve_gmres(v, [1, 0, 0], P.n, 1e-6 / bn)[1]["iters"] for v in (w - 0.03, w, w + 0.03)]
         assert ni[1] > ni[0] and ni[1] > ni[2], (w, ni)
+
+
+# ----------------------------------------------------------------- subspace recycling (GCRO)
+
+def _tube600():
+    from helpers import ragged_tube
+    return O.Problem(ragged_tube(periods=30), G)
+
+
+def test_gcro_without_a_recycle_space_is_gmres():
+    P = _tube600()
+    A, b = P.apply(P.z(0.6)), P.rhs([0, 0, 1])
+    x1, i1 = O.gmres(A, b, 25, 1e-9, 10000)
+    x2, i2 = O.gcro(A, b, None, None, 25, 1e-9, 10000)
+    assert i1["iters"] == i2["iters"] and i1["cycles"] == i2["cycles"]
+    assert np.linalg.norm(x1 - x2) <= 1e-12 * np.linalg.norm(x1)
+
+
+def test_gcro_with_the_solution_in_its_space_needs_no_iterations():
+    # the start x0 = U' C^H b is the minimal-residual point of span(U): with the exact solution (LU)
+    # among the columns of U it is that solution (the residual test comes before the projection, so
+    # one Arnoldi step is taken before the next test confirms it)
+    P = _tube600()
+    A, b = P.apply(P.z(0.6)), P.rhs([0, 0, 1])
+    q = P.solve_lu(0.6, [0, 0, 1])
+    other = P.solve_lu(0.9, [0, 0, 1])
+    U = np.array([other, q]).T
+    x, info = O.gcro(A, b, U, np.array([A(other), A(q)]).T, 25, 1e-10, 10000)
+    assert info["iters"] == 1 and info["history"][0] == 1.0
+    assert np.linalg.norm(x - q) <= 1e-9 * np.linalg.norm(q)
+
+
+def test_gcro_keeps_the_krylov_vectors_orthogonal_to_c_and_converges_to_lu():
+    P = _tube600()
+    A, b = P.apply(P.z(0.6)), P.rhs([0, 0, 1])
+    U = np.array([P.solve_lu(w, [0, 0, 1]) for w in (0.5, 0.7)]).T
+    x, info = O.gcro(A, b, U, np.array([A(U[:, 0]), A(U[:, 1])]).T, 20, 1e-10, 10000)
+    q = P.solve_lu(0.6, [0, 0, 1])
+    assert info["relres"] <= 1e-10
+    assert np.linalg.norm(x - q) <= 1e-7 * np.linalg.norm(q)
+    # the residual history is monotone (a minimal-residual method over growing spaces per cycle)
+    h = info["history"]
+    assert all(h[i + 1] <= h[i] * (1 + 1e-12) for i in range(len(h) - 1))
+
+
+def test_recycled_sweep_matches_lu_and_beats_warm_starts():
+    P = _tube600()
+    om = np.linspace(0.05, 1.2, 12)
+    Q, it, first = P.solve_recycled_sweep(om, [0, 0, 1], 30, 1e-8, 4)
+    for a in range(len(om)):
+        q = P.solve_lu(om[a], [0, 0, 1])
+        assert np.linalg.norm(Q[a] - q) <= 1e-6 * np.linalg.norm(q)
+    _, itw, firstw = P.solve_warm_sweep(om, [0, 0, 1], 30, 1e-8)
+    assert np.array_equal(first, firstw)
+    assert it[first].sum() == itw[first].sum()          # the same solves from zero
+    assert it[~first].sum() < 0.8 * itw[~first].sum()   # recycled spaces beat interpolated starts

@@ -399,6 +399,28 @@ def bench_batched(args, wl, wfq, torch):
             ws_line["max_rel_err_q_vs_fp64_batched"] = float(
                 (np.linalg.norm(qws - qref, axis=1) / np.linalg.norm(qref, axis=1)).max())
         extra["warm_start"] = ws_line
+    if not otf and algo == "gmres" and not args.no_warm_start and len(wl.omegas_eV) >= 3 and wl.n <= 50000:
+        # subspace recycling (the same options, recycle space of the 4 nearest solved frequencies):
+        # one warm-up and one timed run; iteration totals against the warm starts and q0 = 0
+        ropts = dict(opts, recycle=4)
+        wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=False, **ropts)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc = wfq.wfq_solve(h, wl.omegas_eV, wl.dirs, wl.tol, want_q=True, **ropts)
+        torch.cuda.synchronize()
+        t_rc = time.perf_counter() - t0
+        n_rc = int(sum(r["iters"] for r in rc["info"]))
+        rc_line = dict(value=S / t_rc, unit="solves/s", ms_per_step=t_rc * 1e3, dtype=prec, recycle=4,
+                       iters_total=n_rc, iters_total_warm_start=int(sum(r["iters"] for r in ws["info"])),
+                       iters_total_zero_start=int(sum(r["iters"] for r in last["info"])),
+                       iters_max=int(max(r["iters"] for r in rc["info"])),
+                       relres_max=max(r["relres"] for r in rc["info"]),
+                       statuses=sorted(set(r["status"] for r in rc["info"])))
+        if "fp64_reference_systems" in extra and extra["fp64_reference_systems"] == S:
+            qrc = rc["q"].reshape(S, wl.n)
+            rc_line["max_rel_err_q_vs_fp64_batched"] = float(
+                (np.linalg.norm(qrc - qref, axis=1) / np.linalg.norm(qref, axis=1)).max())
+        extra["recycle"] = rc_line
     if not otf and algo == "gmres" and not args.no_block_jacobi and wl.n <= 50000:
         # block-Jacobi right preconditioning (the same options as the timed steps): one warm-up and
         # one timed run

@@ -214,9 +214,11 @@ def roofline_of(stats, prec, otf, n, workload=None):
                "tx_skinny_f32": None, "tx_otf_narrow": None}
     dom = max(classes, key=lambda k: stats.get(k, {}).get("ms", 0.0))
     if dom == "tx_otf_narrow":
-        # narrow products with every element recomputed: bound by the FP64 vector ALUs. Work per pair:
-        # 3 differences, 3 operations for r^2, the reciprocal square root, 4 for its Newton step and one
-        # multiply-add per column (the library's count); peak: one FP64 operation per lane per clock
+        # narrow products with every element recomputed: bound by the FP64 vector ALUs. Work per
+        # element: 3 differences, 3 operations for r^2, the reciprocal square root, 4 for its Newton
+        # step, and one multiply-add per column and row; from 65 536 atoms each element serves both
+        # of its rows (n^2 / 2 evaluations) - the library's count; peak: one FP64 operation per lane
+        # per clock
         st = stats["tx_otf_narrow"]
         avg_s = st["ms"] / max(1, st["launches"]) / 1e3
         achieved = st["flops"] / max(1, st["launches"]) / avg_s / 1e12 if avg_s > 0 else 0.0

@@ -186,6 +186,9 @@ void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStrea
 void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st);
 // compute units of a device
 int device_cus(int device);
+// true when narrow recomputed products of ncol <= 4 columns take the symmetric form (each element
+// evaluated once for both of its rows: n >= 65 536 and the per-block sums fit the work space)
+bool otf_sym_fits(const Structure& s, int ncol);
 // partial-tile work space of the block products (grown on demand, or the fixed region when set)
 void* split_workspace(const Structure& s, uint64_t bytes);
 void otf_tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_t st);

@@ -266,6 +266,7 @@ __global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const
 // C = T - 1/r (pairs closer than rfar, eta_i on the diagonal), so the result is T X.
 constexpr int kNarrowTile = 256;
 constexpr int kNarrowTK = 4;   // targets per thread: a work-group covers 1024 consecutive atoms
+constexpr int64_t kSymFrom = 65536;   // the symmetric form from here: at least 2 080 block pairs
 
 // The pairs of one staged source tile with this thread's TK targets. kDiag: the tile may hold one of
 // the targets themselves (r = 0), whose far-field value is replaced by 0 (the diagonal is in the
@@ -394,11 +395,197 @@ void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t l
     WFQ_CHECK_LAUNCH();
 }
 
+// ---- symmetric narrow product: each unordered pair of atoms evaluated once
+//
+// T is symmetric, so T_ij serves both rows: y_i += T_ij x_j and y_j += T_ij x_i. Atoms are grouped
+// in blocks of 1 024 (the internal, Morton-cell order). One work-group per pair of blocks I <= J:
+// its 256 threads own the 1 024 atoms of I (4 each, 64 apart, as in the one-sided kernel) and
+// stream the atoms of J through LDS in tiles of 256. The target side accumulates in registers. For
+// the source side, each wave takes the tile's sources in groups of 64 and rotates them across its
+// lanes: at step t lane l pairs its targets with source (l + t) mod 64 and adds their contributions
+// to that source's running sum, which then moves one lane down (l <- l + 1); after 64 steps every
+// lane holds the wave's sum for its own source. The four waves' sums are added in order in LDS.
+// No atomics: block K's contribution to row i is stored once, in P[K][c][i] (the target side of the
+// pair (B(i), K) or the source side of (K, B(i)); a diagonal pair (I, I) computes its rows one-sided
+// over all of I), and the sum kernel adds the blocks in order with the near-field correction.
+// kMask: the pair involves the last block, which holds padding atoms (their contributions are 0).
+// One group of 64 sources (LDS rows g .. g + 63) against the thread's TK targets; with SIDE the
+// source-side sums rotate as described above and land in red[wave][c][g + lane].
+template <int NC, bool SIDE, bool DIAG, bool MASK>
+__device__ __forceinline__ void sym_group(const double* __restrict__ sx, const double* __restrict__ sy,
+                                          const double* __restrict__ sz, const double (*sX)[256], int g, int lane,
+                                          int64_t j0, int64_t n, const double (&xi)[4], const double (&yi)[4],
+                                          const double (&zi)[4], const double (&xt)[4][NC], const bool (&tin)[4],
+                                          double (&acc)[4][NC], double (*red)[256], int wave) {
+    double ps[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) ps[c] = 0.0;
+#pragma unroll 2
+    for (int t = 0; t < 64; ++t) {
+        const int q = g + ((lane + t) & 63);
+        const double xs = sx[q], ys = sy[q], zs = sz[q];
+        double xv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) xv[c] = sX[c][q];
+        const bool sv = !MASK || j0 + q < n;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double dx = xi[k] - xs, dy = yi[k] - ys, dz = zi[k] - zs;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            double gk = __builtin_amdgcn_rsq(r2);
+            gk = gk * fma(-0.5 * r2, gk * gk, 1.5);
+            if (DIAG) gk = r2 > 0.0 ? gk : 0.0;
+            if (MASK) gk = (tin[k] && sv) ? gk : 0.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                acc[k][c] = fma(gk, xv[c], acc[k][c]);
+                if (SIDE) ps[c] = fma(gk, xt[k][c], ps[c]);
+            }
+        }
+        if (SIDE) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) ps[c] = __shfl(ps[c], (lane + 1) & 63, 64);
+        }
+    }
+    if (SIDE) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) red[wave * NC + c][g + lane] = ps[c];
+    }
+}
+
+// jfix < 0: the work-group index enumerates the pairs I <= J < nbt in row-major order of I;
+// jfix >= 0: the pair is (blockIdx.x, jfix)
+template <int NC, bool MASK>
+__global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, int nbt, int jfix,
+                                                      const double* __restrict__ pos, const double* __restrict__ X,
+                                                      int64_t ldx, double* __restrict__ P) {
+    constexpr int TK = 4, TILE = 256;
+    __shared__ double sx[TILE], sy[TILE], sz[TILE];
+    __shared__ double sX[NC][TILE];
+    __shared__ double red[4 * NC][TILE];
+    int I = 0, J = 0;
+    if (jfix >= 0) {
+        I = blockIdx.x;
+        J = jfix;
+    } else {
+        int64_t p = blockIdx.x;
+        while (p >= nbt - I) {
+            p -= nbt - I;
+            ++I;
+        }
+        J = I + (int)p;
+    }
+    const bool diag = I == J;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t ib = (int64_t)I * 1024 + wave * 256 + lane;   // target k: ib + 64 k
+    double xi[TK], yi[TK], zi[TK], xt[TK][NC], acc[TK][NC];
+    bool tin[TK];
+#pragma unroll
+    for (int k = 0; k < TK; ++k) {
+        const int64_t i = ib + 64 * k;
+        const int64_t ii = i < npad ? i : 0;
+        tin[k] = i < n;
+        xi[k] = pos[ii];
+        yi[k] = pos[npad + ii];
+        zi[k] = pos[2 * npad + ii];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            xt[k][c] = tin[k] ? X[c * ldx + ii] : 0.0;
+            acc[k][c] = 0.0;
+        }
+    }
+    for (int t0 = 0; t0 < 1024; t0 += TILE) {
+        const int64_t j0 = (int64_t)J * 1024 + t0;
+        if (j0 >= n) break;   // uniform: the rest of block J is padding
+        __syncthreads();
+        {
+            const int64_t j = j0 + tid;
+            const int64_t jj = j < npad ? j : 0;
+            sx[tid] = pos[jj];
+            sy[tid] = pos[npad + jj];
+            sz[tid] = pos[2 * npad + jj];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sX[c][tid] = j < n ? X[c * ldx + jj] : 0.0;
+        }
+        __syncthreads();
+        for (int g = 0; g < TILE; g += 64) {
+            if (diag)
+                sym_group<NC, false, true, MASK>(sx, sy, sz, sX, g, lane, j0, n, xi, yi, zi, xt, tin, acc, red, wave);
+            else
+                sym_group<NC, true, false, MASK>(sx, sy, sz, sX, g, lane, j0, n, xi, yi, zi, xt, tin, acc, red, wave);
+        }
+        if (!diag) {
+            __syncthreads();
+            const int64_t j = j0 + tid;
+            if (j < npad) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    const double v = ((red[c][tid] + red[NC + c][tid]) + red[2 * NC + c][tid]) + red[3 * NC + c][tid];
+                    P[((int64_t)I * NC + c) * npad + j] = j < n ? v : 0.0;
+                }
+            }
+        }
+    }
+    if (!diag) {
+        // rows of J at or beyond n that no tile above reached still get their zeros (same thread per row)
+        for (int64_t j = (int64_t)J * 1024 + tid; j < (int64_t)(J + 1) * 1024 && j < npad; j += 256)
+            if (j >= n)
+#pragma unroll
+                for (int c = 0; c < NC; ++c) P[((int64_t)I * NC + c) * npad + j] = 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < TK; ++k) {
+        const int64_t i = ib + 64 * k;
+        if (i < npad)
+#pragma unroll
+            for (int c = 0; c < NC; ++c) P[((int64_t)J * NC + c) * npad + i] = tin[k] ? acc[k][c] : 0.0;
+    }
+}
+
+template <int NC>
+void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, hipStream_t st) {
+    const int nb = (int)((s.npad + 1023) / 1024);
+    double* P = static_cast<double*>(split_workspace(s, (uint64_t)nb * NC * s.npad * sizeof(double)));
+    if (!s.near_col) throw Error{WFQ_EDEVICE, "the structure has no near-field correction"};
+    // pairs within the full blocks need no masks; the pairs with the last block (which holds the
+    // padding when n is not a multiple of 1024) run the masked variant
+    const bool partial = (int64_t)nb * 1024 > s.n;
+    const int nbt = partial ? nb - 1 : nb;
+    const int64_t pairs = (int64_t)nbt * (nbt + 1) / 2;
+    if (pairs > 0)
+        hipLaunchKernelGGL((otf_sym_kernel<NC, false>), dim3((unsigned)pairs), dim3(256), 0, st, s.n, s.npad, nbt, -1,
+                           s.pos, X, ld, P);
+    if (partial)
+        hipLaunchKernelGGL((otf_sym_kernel<NC, true>), dim3((unsigned)nb), dim3(256), 0, st, s.n, s.npad, nb, nb - 1,
+                           s.pos, X, ld, P);
+    WFQ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, s.npad, nb, ncol,
+                       P, s.near_w, s.near_col, s.near_val, X, ld, Y, ld);
+    WFQ_CHECK_LAUNCH();
+}
+
 }  // namespace
+
+bool otf_sym_fits(const Structure& s, int ncol) {
+    const int64_t nb = (s.npad + 1023) / 1024;
+    const uint64_t cap = s.split_fixed ? s.split_fixed_bytes : kSplitWsCap;
+    return s.n >= kSymFrom && (uint64_t)nb * ncol * s.npad * sizeof(double) <= cap;
+}
 
 void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st) {
     if (ncol <= 0) return;
     if (ncol > 4) throw Error{WFQ_EINVAL, "the narrow matrix-free product takes at most 4 columns"};
+    if (otf_sym_fits(s, ncol)) {
+        if (ncol == 1)
+            launch_otf_sym<1>(s, X, Y, ld, ncol, st);
+        else if (ncol == 2)
+            launch_otf_sym<2>(s, X, Y, ld, ncol, st);
+        else if (ncol == 3)
+            launch_otf_sym<3>(s, X, Y, ld, ncol, st);
+        else
+            launch_otf_sym<4>(s, X, Y, ld, ncol, st);
+        return;
+    }
     if (ncol == 1)
         launch_otf_narrow<1>(s, X, Y, ld, ncol, cus, st);
     else if (ncol == 2)

@@ -523,11 +523,13 @@ void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, h
     tm.begin(st);
     tx_any(S, prec, x_block(w, prec), const_cast<void*>(y_block(w, prec)), ncol, st);
     if (tx_is_otf_narrow(S, prec, ncol)) {
-        // work: per pair 3 differences, 3 operations for r^2, the reciprocal square root, 4 for its
-        // Newton step and one multiply-add per column (the near-field correction is a sparse extra);
-        // bytes: positions and X read once per source part, Y written
+        // work: per element 3 differences, 3 operations for r^2, the reciprocal square root and 4 for
+        // its Newton step, and one multiply-add per column and row (the near-field correction is a
+        // sparse extra); the symmetric form evaluates each element once for both rows, so n^2 / 2
+        // elements; bytes: positions and X read once per source part, Y written
         const double chunks = (ncol + 3) / 4;   // products of up to 4 columns
-        tm.end(st, KC_OTF_NARROW, n * n * (11.0 * chunks + ncol), n * (24.0 * chunks + 8.0 * ncol) + n * 8.0 * ncol);
+        const double elems = otf_sym_fits(S, std::min(ncol, 4)) ? 0.5 * n * n : n * n;
+        tm.end(st, KC_OTF_NARROW, elems * 11.0 * chunks + n * n * ncol, n * (24.0 * chunks + 8.0 * ncol) + n * 8.0 * ncol);
         return;
     }
     if (S.t_mode == WFQ_TMODE_OTF) {

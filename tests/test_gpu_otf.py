@@ -129,3 +129,27 @@ def test_matrix_free_fp64_product_in_chunks(lib):
     Y = lib.wfq_apply_T(hf, "fp64", X)
     hf.close()
     assert np.all(np.abs(Y - X @ P.T.T) <= 1e-13 * (np.abs(X) @ np.abs(P.T).T))
+
+
+@pytest.mark.parametrize("ncol", [1, 2, 3, 4])
+def test_symmetric_narrow_product_on_a_large_sphere(lib, ncol):
+    # From 65 536 atoms on, the narrow product evaluates each pair of atoms once for both rows (blocks
+    # of 1 024 atoms, the source-side sums rotated across the lanes, block contributions added in
+    # order). A 72k-atom FCC sphere whose last block is partial, against the C++ oracle's pairwise
+    # rows: every 997th row and the last five.
+    import wfq_inputs as wi
+    from wfq_inputs import geometry as geo
+    from oracle.cpp_oracle import CppProblem
+    par = wi.workloads.FCC_METAL
+    xyz = geo.jitter(geo.fcc_sphere(66.0), 0.02, 11)
+    n = len(xyz)
+    assert n >= 65536 and n % 1024 != 0
+    X = np.random.default_rng(40 + ncol).standard_normal((ncol, n))
+    hf = lib.wfq_build(xyz, par, t_mode="otf")
+    Y = lib.wfq_apply_T(hf, "fp64", X)
+    hf.close()
+    P = CppProblem(xyz, par, dense_T=False, build_L=False)
+    rows = np.r_[np.arange(0, n, 997), np.arange(n - 5, n)]
+    ref = P.apply_T_rows(rows, X.T)
+    bound = P.apply_T_rows(rows, np.abs(X).T)
+    assert np.all(np.abs(Y[:, rows].T - ref) <= 1e-13 * bound)

@@ -267,6 +267,8 @@ __global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const
 constexpr int kNarrowTile = 256;
 constexpr int kNarrowTK = 4;   // targets per thread: a work-group covers 1024 consecutive atoms
 constexpr int64_t kSymFrom = 65536;   // the symmetric form from here: at least 2 080 block pairs
+constexpr int kSymTK = 4;                 // symmetric form: targets per thread
+constexpr int kSymBlock = 256 * kSymTK;   // atoms per block (one work-group's targets)
 
 // The pairs of one staged source tile with this thread's TK targets. kDiag: the tile may hold one of
 // the targets themselves (r = 0), whose far-field value is replaced by 0 (the diagonal is in the
@@ -409,31 +411,36 @@ void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t l
 // pair (B(i), K) or the source side of (K, B(i)); a diagonal pair (I, I) computes its rows one-sided
 // over all of I), and the sum kernel adds the blocks in order with the near-field correction.
 // kMask: the pair involves the last block, which holds padding atoms (their contributions are 0).
-// One group of 64 sources (LDS rows g .. g + 63) against the thread's TK targets; with SIDE the
-// source-side sums rotate as described above and land in red[wave][c][g + lane].
+// One group of 64 sources against the thread's TK targets; with SIDE the source-side sums rotate as
+// described above and land in red[wave][c][g + lane]. The group sits twice in a row in LDS (rows
+// 2g .. 2g + 127, row 2g + 64 + q a copy of row 2g + q), so step t reads row 2g + lane + t with no
+// wrap-around. The element is taken as G = y (3 - r^2 y^2), twice the Newton-refined 1/r (one
+// operation fewer); the sums are halved when they are stored.
 template <int NC, bool SIDE, bool DIAG, bool MASK>
 __device__ __forceinline__ void sym_group(const double* __restrict__ sx, const double* __restrict__ sy,
-                                          const double* __restrict__ sz, const double (*sX)[256], int g, int lane,
-                                          int64_t j0, int64_t n, const double (&xi)[4], const double (&yi)[4],
-                                          const double (&zi)[4], const double (&xt)[4][NC], const bool (&tin)[4],
-                                          double (&acc)[4][NC], double (*red)[256], int wave) {
+                                          const double* __restrict__ sz, const double (*sX)[512], int g, int lane,
+                                          int64_t j0, int64_t n, const double (&xi)[kSymTK], const double (&yi)[kSymTK],
+                                          const double (&zi)[kSymTK], const double (&xt)[kSymTK][NC],
+                                          const bool (&tin)[kSymTK], double (&acc)[kSymTK][NC], double (*red)[256], int wave) {
     double ps[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) ps[c] = 0.0;
-#pragma unroll 2
+    const int row = 2 * g + lane;
+    constexpr int kUnroll = NC <= 3 ? 4 : 2;   // measured best; 4 columns need the registers
+#pragma unroll kUnroll
     for (int t = 0; t < 64; ++t) {
-        const int q = g + ((lane + t) & 63);
+        const int q = row + t;
         const double xs = sx[q], ys = sy[q], zs = sz[q];
         double xv[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) xv[c] = sX[c][q];
-        const bool sv = !MASK || j0 + q < n;
+        const bool sv = !MASK || j0 + g + ((lane + t) & 63) < n;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kSymTK; ++k) {
             const double dx = xi[k] - xs, dy = yi[k] - ys, dz = zi[k] - zs;
             const double r2 = dx * dx + dy * dy + dz * dz;
             double gk = __builtin_amdgcn_rsq(r2);
-            gk = gk * fma(-0.5 * r2, gk * gk, 1.5);
+            gk = gk * fma(-r2, gk * gk, 3.0);
             if (DIAG) gk = r2 > 0.0 ? gk : 0.0;
             if (MASK) gk = (tin[k] && sv) ? gk : 0.0;
 #pragma unroll
@@ -459,9 +466,9 @@ template <int NC, bool MASK>
 __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, int nbt, int jfix,
                                                       const double* __restrict__ pos, const double* __restrict__ X,
                                                       int64_t ldx, double* __restrict__ P) {
-    constexpr int TK = 4, TILE = 256;
-    __shared__ double sx[TILE], sy[TILE], sz[TILE];
-    __shared__ double sX[NC][TILE];
+    constexpr int TK = kSymTK, TILE = 256, BS = kSymBlock;
+    __shared__ double sx[2 * TILE], sy[2 * TILE], sz[2 * TILE];   // each group of 64 twice
+    __shared__ double sX[NC][2 * TILE];
     __shared__ double red[4 * NC][TILE];
     int I = 0, J = 0;
     if (jfix >= 0) {
@@ -477,7 +484,7 @@ __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, i
     }
     const bool diag = I == J;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int64_t ib = (int64_t)I * 1024 + wave * 256 + lane;   // target k: ib + 64 k
+    const int64_t ib = (int64_t)I * BS + wave * 64 * TK + lane;   // target k: ib + 64 k
     double xi[TK], yi[TK], zi[TK], xt[TK][NC], acc[TK][NC];
     bool tin[TK];
 #pragma unroll
@@ -494,18 +501,20 @@ __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, i
             acc[k][c] = 0.0;
         }
     }
-    for (int t0 = 0; t0 < 1024; t0 += TILE) {
-        const int64_t j0 = (int64_t)J * 1024 + t0;
+    for (int t0 = 0; t0 < BS; t0 += TILE) {
+        const int64_t j0 = (int64_t)J * BS + t0;
         if (j0 >= n) break;   // uniform: the rest of block J is padding
         __syncthreads();
         {
             const int64_t j = j0 + tid;
             const int64_t jj = j < npad ? j : 0;
-            sx[tid] = pos[jj];
-            sy[tid] = pos[npad + jj];
-            sz[tid] = pos[2 * npad + jj];
+            const int r0 = 2 * (tid & ~63) + (tid & 63);   // row of source tid, and its copy 64 later
+            const double px = pos[jj], py = pos[npad + jj], pz = pos[2 * npad + jj];
+            sx[r0] = sx[r0 + 64] = px;
+            sy[r0] = sy[r0 + 64] = py;
+            sz[r0] = sz[r0 + 64] = pz;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sX[c][tid] = j < n ? X[c * ldx + jj] : 0.0;
+            for (int c = 0; c < NC; ++c) sX[c][r0] = sX[c][r0 + 64] = j < n ? X[c * ldx + jj] : 0.0;
         }
         __syncthreads();
         for (int g = 0; g < TILE; g += 64) {
@@ -521,14 +530,14 @@ __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, i
 #pragma unroll
                 for (int c = 0; c < NC; ++c) {
                     const double v = ((red[c][tid] + red[NC + c][tid]) + red[2 * NC + c][tid]) + red[3 * NC + c][tid];
-                    P[((int64_t)I * NC + c) * npad + j] = j < n ? v : 0.0;
+                    P[((int64_t)I * NC + c) * npad + j] = j < n ? 0.5 * v : 0.0;
                 }
             }
         }
     }
     if (!diag) {
         // rows of J at or beyond n that no tile above reached still get their zeros (same thread per row)
-        for (int64_t j = (int64_t)J * 1024 + tid; j < (int64_t)(J + 1) * 1024 && j < npad; j += 256)
+        for (int64_t j = (int64_t)J * BS + tid; j < (int64_t)(J + 1) * BS && j < npad; j += 256)
             if (j >= n)
 #pragma unroll
                 for (int c = 0; c < NC; ++c) P[((int64_t)I * NC + c) * npad + j] = 0.0;
@@ -538,18 +547,18 @@ __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, i
         const int64_t i = ib + 64 * k;
         if (i < npad)
 #pragma unroll
-            for (int c = 0; c < NC; ++c) P[((int64_t)J * NC + c) * npad + i] = tin[k] ? acc[k][c] : 0.0;
+            for (int c = 0; c < NC; ++c) P[((int64_t)J * NC + c) * npad + i] = tin[k] ? 0.5 * acc[k][c] : 0.0;
     }
 }
 
 template <int NC>
 void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, hipStream_t st) {
-    const int nb = (int)((s.npad + 1023) / 1024);
+    const int nb = (int)((s.npad + kSymBlock - 1) / kSymBlock);
     double* P = static_cast<double*>(split_workspace(s, (uint64_t)nb * NC * s.npad * sizeof(double)));
     if (!s.near_col) throw Error{WFQ_EDEVICE, "the structure has no near-field correction"};
     // pairs within the full blocks need no masks; the pairs with the last block (which holds the
     // padding when n is not a multiple of 1024) run the masked variant
-    const bool partial = (int64_t)nb * 1024 > s.n;
+    const bool partial = (int64_t)nb * kSymBlock > s.n;
     const int nbt = partial ? nb - 1 : nb;
     const int64_t pairs = (int64_t)nbt * (nbt + 1) / 2;
     if (pairs > 0)
@@ -567,7 +576,7 @@ void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, 
 }  // namespace
 
 bool otf_sym_fits(const Structure& s, int ncol) {
-    const int64_t nb = (s.npad + 1023) / 1024;
+    const int64_t nb = (s.npad + kSymBlock - 1) / kSymBlock;
     const uint64_t cap = s.split_fixed ? s.split_fixed_bytes : kSplitWsCap;
     return s.n >= kSymFrom && (uint64_t)nb * ncol * s.npad * sizeof(double) <= cap;
 }

@@ -352,7 +352,8 @@ __global__ void __launch_bounds__(256) otf_narrow_f64_kernel(int64_t n, int64_t 
 }
 
 // Y[c][i] = sum over the source parts (in part order) + sum_e C[e][i] X[c][col[e][i]] (near field),
-// every column of row i in one thread so that the correction's entries are read once
+// every column of row i in one thread so that the correction's entries are read once; both loops
+// unrolled by 8 to keep that many independent loads in flight (the order of the sums is unchanged)
 template <int NC>
 __global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int nparts, int ncol,
                                                              const double* __restrict__ part, int w,
@@ -365,6 +366,7 @@ __global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int n
     double t[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) t[c] = 0.0;
+#pragma unroll 8
     for (int e = 0; e < w; ++e) {
         const double v = nval[(int64_t)e * npad + i];
         const int64_t j = ncolv[(int64_t)e * npad + i];
@@ -375,6 +377,7 @@ __global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int n
     for (int c = 0; c < NC; ++c) {
         if (c >= ncol) break;
         double s = 0.0;
+#pragma unroll 8
         for (int p = 0; p < nparts; ++p) s += part[((int64_t)p * NC + c) * npad + i];
         Y[c * ldy + i] = s + t[c];
     }

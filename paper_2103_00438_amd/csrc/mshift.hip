@@ -156,17 +156,24 @@ __global__ void __launch_bounds__(256) ms_update_kernel(double* __restrict__ V, 
 }
 
 // Hessenberg column j of direction d: H_ij = h1_i + h2_i (two Gram-Schmidt passes), H_{j+1,j} = ||w||;
-// inv_h[d] = 1 / ||w|| normalises the next basis vector.
-__global__ void ms_hcol_kernel(const int* __restrict__ dirs, int j, int m, const double* __restrict__ h1,
-                               const double* __restrict__ h2, int pslots, const double* __restrict__ norm, int64_t nblk,
-                               double* __restrict__ H, double* __restrict__ inv_h) {
+// inv_h[d] = 1 / ||w|| normalises the next basis vector. The block partials of ||w||^2 are summed by
+// the two waves of the work-group (thread t the partials t, t + 128, ... in order, then a fixed
+// butterfly and the two waves' sums in order).
+__global__ void __launch_bounds__(128) ms_hcol_kernel(const int* __restrict__ dirs, int j, int m,
+                                                      const double* __restrict__ h1, const double* __restrict__ h2,
+                                                      int pslots, const double* __restrict__ norm, int64_t nblk,
+                                                      double* __restrict__ H, double* __restrict__ inv_h) {
+    __shared__ double sh[2];
     const int d = dirs[blockIdx.x];
     double* col = H + ((int64_t)d * m + j) * (m + 1);
     for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h1[(int64_t)d * pslots + i] + h2[(int64_t)d * pslots + i];
+    double s = 0.0;
+    for (int64_t q = threadIdx.x; q < nblk; q += 128) s += norm[(int64_t)d * nblk + q];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int64_t q = 0; q < nblk; ++q) s += norm[(int64_t)d * nblk + q];
-        const double hn = sqrt(s);
+        const double hn = sqrt(sh[0] + sh[1]);
         col[j + 1] = hn;
         inv_h[d] = hn > 0.0 ? 1.0 / hn : 0.0;
     }
@@ -190,6 +197,8 @@ __global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, i
     const double hn = hc[j + 1];
     // column j of Hbar + z Ibar through the previous rotations; the running entry stays in registers
     double2 cur = make_double2(hc[0] + (j == 0 ? zs.x : 0.0), j == 0 ? zs.y : 0.0);
+    // unrolled so that the loads of several rotations are in flight ahead of the dependent chain
+#pragma unroll 8
     for (int i = 0; i < j; ++i) {
         const double2 y = make_double2(hc[i + 1] + (i + 1 == j ? zs.x : 0.0), i + 1 == j ? zs.y : 0.0);
         const double ci = cs[(int64_t)i * S + s];

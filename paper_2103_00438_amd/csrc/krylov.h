@@ -149,9 +149,10 @@ constexpr int kMsGroup = 8;   // systems per group in ms_xupdate
 // X[c] = cast(V(d_c, j) * scale[d_c]) and V(d_c, j) *= scale[d_c]
 void ms_pack(int prec, double* V, int64_t npad, int mdim1, int j, const int* dirs, int ndir, const double* scale,
              void* X, int64_t ld, hipStream_t st);
-// V(d_c, jdst) = L Y[c]
+// V(d_c, jdst) = L Y[c]; with TV != NULL also TV(d_c, jdst - 1) = Y[c] (rows >= n: 0), the product
+// T v_j kept beside the basis (same layout as V)
 void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* dirs, int ndir, double* V,
-             int mdim1, int jdst, hipStream_t st);
+             int mdim1, int jdst, double* TV, hipStream_t st);
 // partial[d][i][wc] = chunk sums of V(d, i) . V(d, jw), i < nvec; self_norm: slot nvec = ||V(d, jw)||^2
 void ms_dot(const double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
             double* partial, int pslots, bool self_norm, hipStream_t st);
@@ -177,6 +178,12 @@ void ms_solve(const int* sys, int nsys, const int* ksteps, int m, const double2*
 // x(s) = V(d, 0..k[s]-1) y[s] for groups of kMsGroup systems (grp_sys entries -1 = none)
 void ms_xupdate(const double* V, int64_t n, int64_t npad, int mdim1, const int* grp_sys, const int* grp_dir, int ngrp,
                 const int* ksteps, const double2* y, int m, const Basis& X, hipStream_t st);
+// The same combination of the kept products, T x(s) = TV(d, 0..k[s]-1) y[s], packed as the block
+// products pack their output: real part in column 2 pos[s] of Y, imaginary part in column
+// 2 pos[s] + 1 (leading dimension ld >= npad); systems with pos[s] < 0 are skipped.
+void ms_txupdate(const double* TV, int64_t n, int64_t npad, int mdim1, const int* grp_sys, const int* grp_dir,
+                 int ngrp, const int* ksteps, const double2* y, int m, const int* pos, double* Y, int64_t ld,
+                 hipStream_t st);
 
 // ---- block-Jacobi right preconditioning (64-atom diagonal blocks of L T + z I)
 //

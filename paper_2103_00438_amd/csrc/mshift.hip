@@ -62,7 +62,7 @@ template <typename YE, int NC>
 __global__ void __launch_bounds__(256) ms_spmm_kernel(int64_t n, int64_t npad, int w, const int32_t* __restrict__ ecol,
                                                       const double* __restrict__ eval, const YE* __restrict__ Y,
                                                       int64_t ld, const int* __restrict__ dirs, double* __restrict__ V,
-                                                      int mdim1, int jdst, int c0) {
+                                                      int mdim1, int jdst, int c0, double* __restrict__ TV) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double acc[NC];
 #pragma unroll
@@ -79,6 +79,11 @@ __global__ void __launch_bounds__(256) ms_spmm_kernel(int64_t n, int64_t npad, i
     }
 #pragma unroll
     for (int c = 0; c < NC; ++c) slot(V, npad, mdim1, dirs[c0 + c], jdst)[i] = acc[c];
+    if (TV) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            slot(TV, npad, mdim1, dirs[c0 + c], jdst - 1)[i] = i < n ? widen(Y[(int64_t)(c0 + c) * ld + i]) : 0.0;
+    }
 }
 
 // partial[d][i][wc] = sum over wave chunk wc (512 rows) of V(d, i) * V(d, jw) for i < nvec; with
@@ -263,11 +268,14 @@ __global__ void __launch_bounds__(256) ms_solve_kernel(const int* __restrict__ s
 }
 
 // x(s) = sum_{i < k[s]} y[s][i] V(d, i) for groups of up to 8 systems of one direction (the basis
-// is read once per group); rows >= n and systems with k = 0 get 0.
+// is read once per group); rows >= n and systems with k = 0 get 0. Real part at out + col sys_stride,
+// imaginary part im_off further, with col = pos[s] (skipped when negative) or s when pos is NULL.
 __global__ void __launch_bounds__(256) ms_xupdate_kernel(const double* __restrict__ V, int64_t n, int64_t npad,
                                                          int mdim1, const int* __restrict__ grp_sys,
                                                          const int* __restrict__ grp_dir, const int* __restrict__ ksteps,
-                                                         const double2* __restrict__ y, int m, Basis X) {
+                                                         const double2* __restrict__ y, int m,
+                                                         double* __restrict__ out, int64_t sys_stride, int64_t im_off,
+                                                         const int* __restrict__ pos) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int gi = blockIdx.y;
     const int d = grp_dir[gi];
@@ -295,12 +303,14 @@ __global__ void __launch_bounds__(256) ms_xupdate_kernel(const double* __restric
         }
     }
 #pragma unroll
-    for (int t = 0; t < kMsGroup; ++t)
-        if (sid[t] >= 0) {
-            double* xr = X.base + (int64_t)sid[t] * X.sys_stride;
+    for (int t = 0; t < kMsGroup; ++t) {
+        const int col = sid[t] < 0 ? -1 : pos ? pos[sid[t]] : sid[t];
+        if (col >= 0) {
+            double* xr = out + (int64_t)col * sys_stride;
             xr[i] = ar[t];
-            xr[i + X.npad] = ai[t];
+            xr[i + im_off] = ai[t];
         }
+    }
 }
 
 }  // namespace
@@ -322,7 +332,7 @@ void ms_pack(int prec, double* V, int64_t npad, int mdim1, int j, const int* dir
 }
 
 void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* dirs, int ndir, double* V,
-             int mdim1, int jdst, hipStream_t st) {
+             int mdim1, int jdst, double* TV, hipStream_t st) {
     if (ndir <= 0) return;
     const dim3 grd((unsigned)(S.npad / 256));
     // columns in chunks of at most 4 (3 for the usual three field directions in one pass)
@@ -332,7 +342,7 @@ void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const
             using YE = decltype(tag);
             constexpr int NC = decltype(ncv)::value;
             hipLaunchKernelGGL((ms_spmm_kernel<YE, NC>), grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col,
-                               S.ell_val, static_cast<const YE*>(Y), ld, dirs, V, mdim1, jdst, c0);
+                               S.ell_val, static_cast<const YE*>(Y), ld, dirs, V, mdim1, jdst, c0, TV);
         };
         auto by_nc = [&](auto tag) {
             if (nc == 1) go(tag, std::integral_constant<int, 1>{});
@@ -405,7 +415,19 @@ void ms_xupdate(const double* V, int64_t n, int64_t npad, int mdim1, const int* 
                 const int* ksteps, const double2* y, int m, const Basis& X, hipStream_t st) {
     if (ngrp <= 0) return;
     dim3 grd((unsigned)(npad / 256), (unsigned)ngrp);
-    hipLaunchKernelGGL(ms_xupdate_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, grp_sys, grp_dir, ksteps, y, m, X);
+    hipLaunchKernelGGL(ms_xupdate_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, grp_sys, grp_dir, ksteps, y, m,
+                       X.base, X.sys_stride, X.npad, nullptr);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_txupdate(const double* TV, int64_t n, int64_t npad, int mdim1, const int* grp_sys, const int* grp_dir,
+                 int ngrp, const int* ksteps, const double2* y, int m, const int* pos, double* Y, int64_t ld,
+                 hipStream_t st) {
+    if (ngrp <= 0) return;
+    if (ld < npad) throw Error{WFQ_EINVAL, "ms_txupdate: leading dimension below the padded length"};
+    dim3 grd((unsigned)(npad / 256), (unsigned)ngrp);
+    hipLaunchKernelGGL(ms_xupdate_kernel, grd, dim3(256), 0, st, TV, n, npad, mdim1, grp_sys, grp_dir, ksteps, y, m, Y,
+                       2 * ld, ld, pos);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -142,6 +142,9 @@ struct WorkShape {
 // arrays of the multi-shift phase (one real basis per direction, one shifted recurrence per system)
 struct MsWork {
     Buf<double> V, H, part, h1, h2, nrm, inv_h, cs, est, tol_abs;
+    Buf<double> TV;   // FP64 solves: T v_j of every basis vector, kept for the closing residual
+    Buf<int> pos;     // system -> packed column of the closing residual's products
+    int ngrp = 0;     // groups of ms_xupdate in the last phase
     Buf<double2> sn, g, R, y, z;
     Buf<int> dirs, sdir, sys, flags, ksteps, grp_sys, grp_dir, run;
     Buf<int> h_dirs, h_sys, h_k;   // pinned
@@ -156,6 +159,7 @@ struct Work {
     int B = 0, mdim = 0, n_dir = 0;
     int64_t n = 0, npad = 0, nwc = 0, nblk = 0, mpad = 0;
     bool need32 = false, need16 = false;
+    bool ms_tv_ready = false;   // the multi-shift phase left T x of its iterates computable from ms.TV
     Buf<double> V, X, b, X64, Y64, cs, est, inv_h, inv_beta, beta, norm2, tol_abs;
     Buf<double> qT, qtq;   // |x|_T = sqrt(x^H T x) at the last FP64 residual, and its block partials
     Buf<float> X32, Y32, Y16, Yp32;   // Yp*: the products' planes interleaved for the SpMM (large N)
@@ -309,6 +313,8 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
         MsWork& q = w.ms;
         const int64_t mm = sh.ms_m, mdim1 = mm + 1, pslots = mm + 2;
         d.take(q.V, (size_t)n_dir * mdim1 * np);
+        if (sh.prec == WFQ_PREC_FP64) d.take(q.TV, (size_t)n_dir * mdim1 * np);
+        d.take(q.pos, B);
         d.take(q.H, (size_t)n_dir * mm * (mm + 1));
         d.take(q.part, (size_t)n_dir * pslots * w.nwc);
         d.take(q.h1, (size_t)n_dir * pslots);
@@ -555,14 +561,28 @@ void progress_line(const wfq_solve_opts& o, const char* what, int cycle, int ste
 }
 
 // FP64 refinement residual of the systems in `act`: V(s,0) = b - (L T + z I) x, beta = ||V(s,0)||,
-// qT = |x|_T (from the same product T x).
-void fp64_residual(const Structure& S, Work& w, const std::vector<int>& act, Timer& tm, hipStream_t st) {
+// qT = |x|_T (from the same product T x). With from_ms, x is the multi-shift phase's iterate V y and
+// T x is formed as TV y from the kept FP64 products T v_j instead of a new product.
+void fp64_residual(const Structure& S, Work& w, const std::vector<int>& act, Timer& tm, hipStream_t st,
+                   bool from_ms = false) {
     const int na = (int)act.size();
     const double n = (double)S.n;
-    tm.begin(st);
-    pack_columns(WFQ_PREC_FP64, w.Xb, w.sys[SLOT_ACT].p, na, 0, nullptr, false, w.X64.p, w.npad, st);
-    tm.end(st, KC_PACK, 0, 32.0 * n * na);
-    block_product(S, w, WFQ_PREC_FP64, 2 * na, tm, st);
+    if (from_ms) {
+        MsWork& q = w.ms;
+        const int m = w.shape.ms_m;
+        std::vector<int> pos(w.B, -1);
+        for (int k = 0; k < na; ++k) pos[act[k]] = k;
+        h2d_sync(S, q.pos.p, pos.data(), w.B * sizeof(int), st);
+        tm.begin(st);
+        ms_txupdate(q.TV.p, S.n, S.npad, m + 1, q.grp_sys.p, q.grp_dir.p, q.ngrp, q.ksteps.p, q.y.p, m, q.pos.p,
+                    w.Y64.p, S.npad, st);
+        tm.end(st, KC_XUPDATE, 0, 0);
+    } else {
+        tm.begin(st);
+        pack_columns(WFQ_PREC_FP64, w.Xb, w.sys[SLOT_ACT].p, na, 0, nullptr, false, w.X64.p, w.npad, st);
+        tm.end(st, KC_PACK, 0, 32.0 * n * na);
+        block_product(S, w, WFQ_PREC_FP64, 2 * na, tm, st);
+    }
     tm.begin(st);
     residual(S, w.Y64.p, w.npad, w.sys[SLOT_ACT].p, na, w.z.p, w.Xb, w.b.p, w.dir.p, w.Vb, w.norm2.p, (int)w.nblk,
              w.qtq.p, st);
@@ -643,7 +663,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
     if (warm && !active.empty()) {
         // start from the given x: r = b - (L T + z I) x in FP64
         upload(w, SLOT_ACT, active, st);
-        fp64_residual(S, w, active, tm, st);
+        fp64_residual(S, w, active, tm, st, w.ms_tv_ready && !only);
         WFQ_HIP(hipMemcpyAsync(w.h_beta.p, w.beta.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
         WFQ_HIP(hipMemcpyAsync(w.h_qT.p, w.qT.p, B * sizeof(double), hipMemcpyDeviceToHost, st));
         WFQ_HIP(hipStreamSynchronize(st));
@@ -666,6 +686,7 @@ void gmres_batch(const Structure& S, Work& w, std::vector<SysState>& ss, double 
             progress_line(o, "gmres from the given start", 0, 0, active.size(), worst, t0);
         }
     }
+    w.ms_tv_ready = false;   // later residuals are of other iterates
 
     while (!active.empty()) {
         if (w.rc_active) {
@@ -898,6 +919,7 @@ int ms_dim(const wfq_solve_opts& o, int64_t n) {
 uint64_t ms_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_dir) {
     const uint64_t m = ms_dim(o, S.n), np = S.npad, nwc = wave_chunks(S.n);
     uint64_t b = (uint64_t)n_dir * (m + 1) * np * 8;            // bases
+    if (o.precision == WFQ_PREC_FP64) b *= 2;                    // and their products T v_j
     b += (uint64_t)n_dir * m * (m + 1) * 8;                      // Hessenberg
     b += (uint64_t)n_dir * ((m + 2) * nwc * 8 + nwc * 8 + (m + 2) * 16);   // partials, h1, h2
     b += (uint64_t)B * (m * (m + 1) / 2) * 16;                   // R, packed
@@ -919,12 +941,12 @@ double ms_product_error(const Structure& S, Work& w, int prec, const std::vector
     // v0 and L T v0 with FP64 T (slot 2), then L T_prec v0 (slot 1)
     ms_pack(WFQ_PREC_FP64, q.V.p, np, mdim1, 0, q.dirs.p, nd, q.inv_h.p, w.X64.p, np, st);
     tx_any(S, WFQ_PREC_FP64, w.X64.p, w.Y64.p, nd, st);
-    ms_spmm(S, true, w.Y64.p, np, q.dirs.p, nd, q.V.p, mdim1, 2, st);
+    ms_spmm(S, true, w.Y64.p, np, q.dirs.p, nd, q.V.p, mdim1, 2, nullptr, st);
     std::vector<double> ones(nd, 1.0);
     h2d_sync(S, q.inv_h.p, ones.data(), nd * sizeof(double), st);
     ms_pack(prec, q.V.p, np, mdim1, 0, q.dirs.p, nd, q.inv_h.p, x_block(w, prec), np, st);
     tx_any(S, prec, x_block(w, prec), const_cast<void*>(y_block(w, prec)), nd, st);
-    ms_spmm(S, prec == WFQ_PREC_FP64, y_block(w, prec), np, q.dirs.p, nd, q.V.p, mdim1, 1, st);
+    ms_spmm(S, prec == WFQ_PREC_FP64, y_block(w, prec), np, q.dirs.p, nd, q.V.p, mdim1, 1, nullptr, st);
     // ||slot 2||^2, then slot 2 -= slot 1 with the squared norm of the difference per 64-row block
     ms_dot(q.V.p, n, np, mdim1, 0, 2, q.dirs.p, nd, q.part.p, pslots, true, st);
     ms_reduce(q.dirs.p, nd, q.part.p, pslots, n, 1, q.h1.p, st);
@@ -959,6 +981,10 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     const double dn = (double)n;
     MsWork& q = w.ms;
     if (w.shape.ms_m != m) throw Error{WFQ_EDEVICE, "multi-shift work space of the wrong dimension"};
+    w.ms_tv_ready = false;
+    // with every product of the basis in FP64 the products are kept, and T x of each iterate is then
+    // the same combination of them as x is of the basis
+    bool keep_tv = q.TV.p != nullptr;
     double *V = q.V.p, *H = q.H.p, *part = q.part.p, *h1 = q.h1.p, *h2 = q.h2.p, *nrm = q.nrm.p, *inv_h = q.inv_h.p;
     double *cs = q.cs.p, *est = q.est.p, *tol_abs = q.tol_abs.p;
     double2 *sn = q.sn.p, *g = q.g.p, *R = q.R.p, *y = q.y.p, *z = q.z.p;
@@ -1055,6 +1081,7 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     GraphCache* gc = tm.on() ? nullptr : graphs;
     for (int j0 = 0; j0 < m && !stepping.empty();) {
         const int c = std::min(kChunk, m - j0);
+        keep_tv = keep_tv && cur == WFQ_PREC_FP64;
         auto step = [&](int j) {
             // w = L T v_j (one real column per direction)
             tm.begin(st);
@@ -1062,9 +1089,11 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
             tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(cur)));
             block_product(S, w, cur, na, tm, st);
             tm.begin(st);
-            ms_spmm(S, cur == WFQ_PREC_FP64, y_block(w, cur), np, dirs, na, V, mdim1, j + 1, st);
+            double* tv = keep_tv ? q.TV.p : nullptr;
+            ms_spmm(S, cur == WFQ_PREC_FP64, y_block(w, cur), np, dirs, na, V, mdim1, j + 1, tv, st);
             // L is read once for all directions (up to four per pass)
-            tm.end(st, KC_SPMM, 2.0 * S.nnz * na, 12.0 * S.nnz * ((na + 3) / 4) + na * dn * (out_size(cur) + 8));
+            tm.end(st, KC_SPMM, 2.0 * S.nnz * na,
+                   12.0 * S.nnz * ((na + 3) / 4) + na * dn * (out_size(cur) + 8 + (tv ? 8 : 0)));
             // two classical Gram-Schmidt passes against v_0 .. v_j
             const double pass = 8.0 * dn * na * (j + 2);
             tm.begin(st);
@@ -1087,7 +1116,7 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
             ms_givens(sys, ns, j, m, sdir, z, H, cs, sn, g, R, B, est, tol_abs, flags, run, ksteps, st);
             tm.end(st, KC_GIVENS, 0, 0);
         };
-        run_chunk(gc, S, GraphKey{1, j0, c, ns, na, cur, 0}, st, [&] {
+        run_chunk(gc, S, GraphKey{1, j0, c, ns, na, cur, keep_tv ? 1 : 0}, st, [&] {
             for (int j = j0; j < j0 + c; ++j) step(j);
         });
         j0 += c;
@@ -1147,6 +1176,8 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     ms_xupdate(V, n, np, mdim1, grp_sys, grp_dir, ngrp, ksteps, y, m, w.Xb, st);
     tm.end(st, KC_XUPDATE, 0, 0);
     WFQ_HIP(hipStreamSynchronize(st));
+    q.ngrp = ngrp;
+    w.ms_tv_ready = keep_tv;
     for (int s = 0; s < B; ++s) ss[s].iters += h_k[s];
     if (o.progress) progress_line(o, "multi-shift done", 0, 0, stepping.size(), -1.0, t0);
 }

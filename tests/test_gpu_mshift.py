@@ -63,6 +63,24 @@ def test_multishift_matches_lu(lib, tube_case, prec):
         assert A[0, 0].imag > 0 and A[2, 2].imag > 0
 
 
+def test_closing_residual_is_that_of_the_returned_charges(lib, tube_case):
+    # FP64 solves form T q of the shared-basis iterates from the kept products T v_j: the reported
+    # relative residual must be the oracle's ||b - (L T + z I) q|| / ||b|| of the returned q
+    xyz, P, om, dirs, ref = tube_case
+    h = lib.wfq_build(xyz, GRAPHENE)
+    tol = 1e-9
+    out = lib.wfq_solve(h, om, dirs, tol, algorithm="msgmres", restart=30, precision="fp64", shift_dim=400)
+    h.close()
+    assert out["status"] == 0, out["info"]
+    for a in range(len(om)):
+        for k in range(3):
+            info = out["info"][a * 3 + k]
+            q = out["q"][a, k]
+            r = P.residual(om[a], dirs[k], q)
+            assert info["iters"] > 0 and info["cycles"] == 0, (a, k, info)
+            assert abs(r - info["relres"]) <= 1e-3 * r + 1e-14, (a, k, r, info["relres"])
+
+
 def test_multishift_steps_match_oracle(lib, tube_case):
     # FP64 T: the shared basis needs as many steps per frequency as the oracle's multi-shift GMRES
     # (same Krylov space, same stop rule ||r|| <= tol ||b||), and no refinement cycle afterwards

@@ -166,6 +166,23 @@ void ms_update(double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, 
 // Hessenberg column j from the two Gram-Schmidt passes and the norm; inv_h[d] = 1 / H_{j+1,j}
 void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const double* h2, int pslots,
              const double* norm, int64_t n, int64_t npad, double* H, double* inv_h, hipStream_t st);
+// One-reduction Arnoldi step k (DCGS2) on the real bases: fused dots of slot k (u) and, with z, slot
+// k + 1 against slots 0..k into partial[d][e][wc] (ps >= 2 k + 2 entries per direction; reduce with
+// ms_reduce over 2 k + 2, or k + 1 without z)
+void ms_dcgs_dot(const double* V, int64_t n, int64_t npad, int mdim1, int k, bool with_z, const int* dirs, int ndir,
+                 double* partial, int ps, hipStream_t st);
+// from the dots: column k-1 of H, column k of S (Sm may be NULL), and with z gamma, 1 / rho and the
+// next first-pass coefficients hp ([d][m + 1]); nu = |p| of the previous step
+void ms_dcgs_coeff(const int* dirs, int ndir, int k, bool with_z, int m, const double* dots, int ps, double* hp,
+                   double* H, double* Sm, const double* nu, const double* inv_h, double* gam, double* inv_rho,
+                   hipStream_t st);
+// q_k into slot k, p' into slot k + 1, nu = |p'| and inv_h = 1 / nu (norm: [d][npad / 64] block sums)
+void ms_dcgs_update(double* V, int64_t n, int64_t npad, int mdim1, int k, const int* dirs, int ndir,
+                    const double* dots, int ps, const double* gam, const double* inv_rho, double* norm,
+                    double* nu, double* inv_h, hipStream_t st);
+// y[s] <- S^-1 y[s] over k[s] entries (S of direction sdir[s], columns in the layout of H)
+void ms_sinv(const int* sys, int nsys, const int* ksteps, int m, const double* Sm, const int* sdir, double2* y,
+             hipStream_t st);
 // Givens step j of each listed system on Hbar + z Ibar of its direction (flags: bit0 converged, bit1 breakdown, bit2 NaN);
 // systems with run[s] == 0 are skipped, ksteps[s] = j + 1 is recorded and run[s] cleared when a flag
 // is raised. cs, sn, g and the packed R are system-minor: entry e of system s at e * S + s.

@@ -184,6 +184,229 @@ __global__ void __launch_bounds__(128) ms_hcol_kernel(const int* __restrict__ di
     }
 }
 
+// ---- Arnoldi with one reduction per step on the real basis of each direction: classical
+// Gram-Schmidt with delayed reorthogonalisation (DCGS2, Swirydowicz, Langou, Ananthan, Yang and
+// Thomas 2020), the real counterpart of the batched GMRES's. At step k, q_0 .. q_{k-1} are final,
+// slot k holds u (the previous step's once-projected vector p, normalised by the pack) and slot
+// k + 1 holds z = A u. One sweep gives a = Q^T u, alpha = u^T u, b = Q^T z and beta = u^T z
+// (dots[d][e]: e = t < k: a_t; e = k: alpha; e = k + 1 + t: b_t; e = 2 k + 1: beta); then with
+// rho = sqrt(alpha - |a|^2) and nu = |p|:
+//   q_k = (u - Q a) / rho;  H(0:k-1, k-1) = hp + nu a,  H(k, k-1) = nu rho   (column k-1 complete)
+//   gamma = q_k^T z = (beta - a^T b) / rho;  p' = (z - Q b - gamma q_k) / rho
+//   hp'(0:k-1) = (b - (Hbar a)(0:k-1)) / rho,  hp'(k) = (gamma - H(k, k-1) a_{k-1}) / rho
+// since A q_k = (z - Q_{k+1} Hbar a) / rho by A Q_k = Q_{k+1} Hbar. The basis is read twice per step
+// instead of four times; column k-1 is complete (and its Givens step taken) at step k, and a last
+// step without product completes column m-1. As u_k = rho q_k + Q a, the vectors that entered the
+// products relate to the final basis by U = Q S with S upper triangular (S(t, k) = a_t,
+// S(k, k) = rho), kept column by column in the layout of H when the products T u_k are kept.
+
+// partial[d][e][wc] for the entries e above over wave chunk wc (512 rows): one wave per (chunk,
+// basis vector t <= k, direction) computes v_t . u and v_t . z (t = k: alpha and beta).
+__global__ void __launch_bounds__(256) ms_dcgs_dot_kernel(const double* __restrict__ V, int64_t n, int64_t npad,
+                                                          int mdim1, int k, int with_z, const int* __restrict__ dirs,
+                                                          double* __restrict__ partial, int ps, int64_t nwc) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t wc = blockIdx.x;
+    const int t = blockIdx.y * 4 + wave;
+    if (t > k) return;   // uniform over the wave
+    const int d = dirs[blockIdx.z];
+    const double* u = V + ((int64_t)d * mdim1 + k) * npad;
+    const double* zv = u + npad;   // slot k + 1 (read only with z)
+    const double* v = V + ((int64_t)d * mdim1 + t) * npad;
+    const int64_t row0 = wc * kWaveRows + lane;
+    double sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        const int64_t row = row0 + 64 * r;
+        if (row < n) {
+            const double x = v[row];
+            sa += x * u[row];
+            if (with_z) sb += x * zv[row];
+        }
+    }
+    sa = wave_sum(sa);
+    if (with_z) sb = wave_sum(sb);   // with_z is uniform over the launch
+    if (lane == 0) {
+        double* P = partial + (int64_t)d * ps * nwc + wc;
+        P[(int64_t)t * nwc] = sa;
+        if (with_z) P[(int64_t)(k + 1 + t) * nwc] = sb;
+    }
+}
+
+// sum over the work-group of one value per thread, in a fixed order (waves' sums in order)
+__device__ inline double block_sum256(double x, double* red) {
+    x = wave_sum(x);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+    __syncthreads();
+    return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One work-group per direction: column k-1 of H (k >= 1), column k of S (with z, S != NULL), and with
+// z gamma and 1 / rho. Without z (the last step) u is the unnormalised p, whose dots are scaled by
+// inv_h = 1 / nu.
+__global__ void __launch_bounds__(256) ms_dcgs_coeff_kernel(const int* __restrict__ dirs, int k, int with_z, int m,
+                                                            const double* __restrict__ dots, int ps,
+                                                            double* __restrict__ hp, double* __restrict__ H,
+                                                            double* __restrict__ Sm, const double* __restrict__ nu,
+                                                            const double* __restrict__ inv_h, double* __restrict__ gam,
+                                                            double* __restrict__ inv_rho) {
+    __shared__ double red[4];
+    const int d = dirs[blockIdx.x];
+    const int tid = threadIdx.x;
+    const double* dt = dots + (int64_t)d * ps;
+    double* hpd = hp + (int64_t)d * (m + 1);
+    const double sc = with_z ? 1.0 : inv_h[d];
+    double asq = 0.0;
+    for (int i = tid; i < k; i += 256) {
+        const double ai = sc * dt[i];
+        asq += ai * ai;
+    }
+    asq = block_sum256(asq, red);
+    const double r2 = dt[k] * sc * sc - asq;
+    const double rho = r2 > 0.0 ? sqrt(r2) : 0.0;
+    const double nud = nu[d];
+    if (k >= 1) {
+        double* col = H + ((int64_t)d * m + (k - 1)) * (m + 1);
+        for (int i = tid; i < k; i += 256) col[i] = hpd[i] + nud * sc * dt[i];
+        if (tid == 0) col[k] = nud * rho;
+    }
+    if (!with_z) return;
+    if (Sm) {
+        double* sk = Sm + ((int64_t)d * m + k) * (m + 1);
+        for (int i = tid; i < k; i += 256) sk[i] = dt[i];
+        if (tid == 0) sk[k] = rho;
+    }
+    double ab = 0.0;
+    for (int i = tid; i < k; i += 256) ab += dt[i] * dt[k + 1 + i];
+    ab = block_sum256(ab, red);
+    const double ir = rho > 0.0 ? 1.0 / rho : 0.0;
+    if (tid == 0) {
+        gam[d] = (dt[2 * k + 1] - ab) * ir;
+        inv_rho[d] = ir;
+    }
+}
+
+// The next column's first-pass coefficients, hp(i) = (b_i - (Hbar a)_i) / rho for i < k and
+// hp(k) = (gamma - H(k, k-1) a_{k-1}) / rho, after column k-1 of H is complete. One work-group of
+// 16 waves per (64 rows, direction): lane = row, wave w adds the columns c = w, w + 16, ... (Hbar is
+// upper Hessenberg: c >= i - 1 only), and the 16 partial sums are added in order.
+__global__ void __launch_bounds__(1024) ms_dcgs_hp_kernel(const int* __restrict__ dirs, int k, int m,
+                                                          const double* __restrict__ dots, int ps,
+                                                          const double* __restrict__ H, const double* __restrict__ gam,
+                                                          const double* __restrict__ inv_rho, double* __restrict__ hp) {
+    __shared__ double red[16][64];
+    const int d = dirs[blockIdx.y];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i = blockIdx.x * 64 + lane;
+    const double* dt = dots + (int64_t)d * ps;
+    const double* Hd = H + (int64_t)d * m * (m + 1);
+    const int c0 = max(0, (int)blockIdx.x * 64 - 1);
+    double acc = 0.0;
+    if (i < k) {
+#pragma unroll 4
+        for (int c = c0 + wave; c < k; c += 16)
+            if (c >= i - 1) acc += Hd[(int64_t)c * (m + 1) + i] * dt[c];
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && i <= k) {
+        const double ir = inv_rho[d];
+        double* hpd = hp + (int64_t)d * (m + 1);
+        if (i < k) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) s += red[w][lane];
+            hpd[i] = (dt[k + 1 + i] - s) * ir;
+        } else {
+            const double last = k >= 1 ? Hd[(int64_t)(k - 1) * (m + 1) + k] * dt[k - 1] : 0.0;
+            hpd[k] = (gam[d] - last) * ir;
+        }
+    }
+}
+
+// q_k = (u - Q a) / rho into slot k and p' = (z - Q b - gamma q_k) / rho into slot k + 1, with the
+// sums of p'^2 over 64-row blocks in norm[d][blk]. A block owns 64 rows; its 4 waves take every 4th
+// basis vector (both sums from one read) and are combined in LDS in a fixed order.
+__global__ void __launch_bounds__(256) ms_dcgs_update_kernel(double* __restrict__ V, int64_t n, int64_t npad,
+                                                             int mdim1, int k, const int* __restrict__ dirs,
+                                                             const double* __restrict__ dots, int ps,
+                                                             const double* __restrict__ gam,
+                                                             const double* __restrict__ inv_rho,
+                                                             double* __restrict__ norm) {
+    __shared__ double pa[4][kMsRows], pb[4][kMsRows];
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t row = (int64_t)blockIdx.x * kMsRows + r;
+    const int d = dirs[blockIdx.y];
+    const double* dt = dots + (int64_t)d * ps;
+    double sa = 0.0, sb = 0.0;
+    if (row < n) {
+#pragma unroll 4
+        for (int i = q; i < k; i += 4) {
+            const double v = V[((int64_t)d * mdim1 + i) * npad + row];
+            sa += dt[i] * v;
+            sb += dt[k + 1 + i] * v;
+        }
+    }
+    pa[q][r] = sa;
+    pb[q][r] = sb;
+    __syncthreads();
+    if (q == 0) {
+        double* u = V + ((int64_t)d * mdim1 + k) * npad;
+        double* zv = u + npad;
+        double x = 0.0;
+        if (row < n) {
+            const double ir = inv_rho[d], g = gam[d];
+            const double qk = (u[row] - ((pa[0][r] + pa[1][r]) + (pa[2][r] + pa[3][r]))) * ir;
+            x = (zv[row] - ((pb[0][r] + pb[1][r]) + (pb[2][r] + pb[3][r])) - g * qk) * ir;
+            u[row] = qk;
+            zv[row] = x;
+        }
+        const double s2 = wave_sum(x * x);
+        if (r == 0) norm[(int64_t)d * (npad / kMsRows) + blockIdx.x] = s2;
+    }
+}
+
+// nu[d] = |p'| from the block sums (two waves, fixed order), inv_h[d] = 1 / nu[d] (0 when p' = 0)
+__global__ void __launch_bounds__(128) ms_nu_kernel(const int* __restrict__ dirs, const double* __restrict__ norm,
+                                                    int64_t nblk, double* __restrict__ nu,
+                                                    double* __restrict__ inv_h) {
+    __shared__ double sh[2];
+    const int d = dirs[blockIdx.x];
+    double s = 0.0;
+    for (int64_t q = threadIdx.x; q < nblk; q += 128) s += norm[(int64_t)d * nblk + q];
+    s = wave_sum(s);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double v = sqrt(sh[0] + sh[1]);
+        nu[d] = v;
+        inv_h[d] = v > 0.0 ? 1.0 / v : 0.0;
+    }
+}
+
+// y[s] <- S^-1 y[s] over the first k[s] entries (S of the system's direction; column-oriented back
+// substitution, y kept in LDS), one work-group per system
+__global__ void __launch_bounds__(256) ms_sinv_kernel(const int* __restrict__ sys, const int* __restrict__ ksteps,
+                                                      int m, const double* __restrict__ Sm,
+                                                      const int* __restrict__ sdir, double2* __restrict__ y) {
+    extern __shared__ double2 ys[];
+    const int s = sys[blockIdx.x];
+    const int K = ksteps[s];
+    const double* Sd = Sm + (int64_t)sdir[s] * m * (m + 1);
+    for (int i = threadIdx.x; i < K; i += blockDim.x) ys[i] = y[(int64_t)s * m + i];
+    __syncthreads();
+    for (int i = K - 1; i >= 0; --i) {
+        const double* col = Sd + (int64_t)i * (m + 1);
+        const double2 yi = cscale(1.0 / col[i], ys[i]);
+        __syncthreads();
+        if (threadIdx.x == 0) ys[i] = yi;
+        for (int r = threadIdx.x; r < i; r += blockDim.x) ys[r] = csub(ys[r], cscale(col[r], yi));
+        __syncthreads();
+    }
+    for (int i = threadIdx.x; i < K; i += blockDim.x) y[(int64_t)s * m + i] = ys[i];
+}
+
 // One Givens step of system s on column j of Hbar + z Ibar (direction sdir[s], shift z[s]): the
 // rotations of the earlier steps are applied, a new rotation zeroes the subdiagonal, the rotated
 // column is stored as column j of R, and |g_{j+1}| is the residual norm of the shifted system.
@@ -400,6 +623,50 @@ void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const do
     if (nsys <= 0) return;
     hipLaunchKernelGGL(ms_givens_kernel, dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st, sys, nsys, j, m, sdir, z,
                        H, cs, sn, g, R, S, est, tol_abs, flags, run, ksteps);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_dcgs_dot(const double* V, int64_t n, int64_t npad, int mdim1, int k, bool with_z, const int* dirs, int ndir,
+                 double* partial, int ps, hipStream_t st) {
+    if (ndir <= 0) return;
+    if (2 * k + 2 > ps) throw Error{WFQ_EINVAL, "ms_dcgs_dot: too few partial slots"};
+    const int64_t nwc = wave_chunks(n);
+    dim3 grd((unsigned)nwc, (unsigned)((k + 4) / 4), (unsigned)ndir);
+    hipLaunchKernelGGL(ms_dcgs_dot_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, k, with_z ? 1 : 0, dirs, partial,
+                       ps, nwc);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_dcgs_coeff(const int* dirs, int ndir, int k, bool with_z, int m, const double* dots, int ps, double* hp,
+                   double* H, double* Sm, const double* nu, const double* inv_h, double* gam, double* inv_rho,
+                   hipStream_t st) {
+    if (ndir <= 0) return;
+    hipLaunchKernelGGL(ms_dcgs_coeff_kernel, dim3((unsigned)ndir), dim3(256), 0, st, dirs, k, with_z ? 1 : 0, m, dots,
+                       ps, hp, H, Sm, nu, inv_h, gam, inv_rho);
+    WFQ_CHECK_LAUNCH();
+    if (!with_z) return;
+    hipLaunchKernelGGL(ms_dcgs_hp_kernel, dim3((unsigned)(k / 64 + 1), (unsigned)ndir), dim3(1024), 0, st, dirs, k, m,
+                       dots, ps, H, gam, inv_rho, hp);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_dcgs_update(double* V, int64_t n, int64_t npad, int mdim1, int k, const int* dirs, int ndir,
+                    const double* dots, int ps, const double* gam, const double* inv_rho, double* norm,
+                    double* nu, double* inv_h, hipStream_t st) {
+    if (ndir <= 0) return;
+    dim3 grd((unsigned)(npad / kMsRows), (unsigned)ndir);
+    hipLaunchKernelGGL(ms_dcgs_update_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, k, dirs, dots, ps, gam, inv_rho,
+                       norm);
+    WFQ_CHECK_LAUNCH();
+    hipLaunchKernelGGL(ms_nu_kernel, dim3((unsigned)ndir), dim3(128), 0, st, dirs, norm, npad / kMsRows, nu, inv_h);
+    WFQ_CHECK_LAUNCH();
+}
+
+void ms_sinv(const int* sys, int nsys, const int* ksteps, int m, const double* Sm, const int* sdir, double2* y,
+             hipStream_t st) {
+    if (nsys <= 0) return;
+    hipLaunchKernelGGL(ms_sinv_kernel, dim3((unsigned)nsys), dim3(256), (size_t)m * sizeof(double2), st, sys, ksteps,
+                       m, Sm, sdir, y);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -142,7 +142,9 @@ struct WorkShape {
 // arrays of the multi-shift phase (one real basis per direction, one shifted recurrence per system)
 struct MsWork {
     Buf<double> V, H, part, h1, h2, nrm, inv_h, cs, est, tol_abs;
-    Buf<double> TV;   // FP64 solves: T v_j of every basis vector, kept for the closing residual
+    Buf<double> TV;   // FP64 solves: T u_j of every vector that entered a product, kept for the closing residual
+    Buf<double> Sm;   // with TV: U = Q S, S upper triangular, columns in the layout of H
+    Buf<double> dots, hp, gam, irho, nu;   // one-reduction Arnoldi: [d][2 (m + 1)], [d][m + 1], [d] x 3
     Buf<int> pos;     // system -> packed column of the closing residual's products
     int ngrp = 0;     // groups of ms_xupdate in the last phase
     Buf<double2> sn, g, R, y, z;
@@ -316,7 +318,13 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
         if (sh.prec == WFQ_PREC_FP64) d.take(q.TV, (size_t)n_dir * mdim1 * np);
         d.take(q.pos, B);
         d.take(q.H, (size_t)n_dir * mm * (mm + 1));
-        d.take(q.part, (size_t)n_dir * pslots * w.nwc);
+        d.take(q.part, (size_t)n_dir * 2 * mdim1 * w.nwc);   // >= pslots: also the fused dots' partials
+        if (sh.prec == WFQ_PREC_FP64) d.take(q.Sm, (size_t)n_dir * mm * (mm + 1));
+        d.take(q.dots, (size_t)n_dir * 2 * mdim1);
+        d.take(q.hp, (size_t)n_dir * mdim1);
+        d.take(q.gam, n_dir);
+        d.take(q.irho, n_dir);
+        d.take(q.nu, n_dir);
         d.take(q.h1, (size_t)n_dir * pslots);
         d.take(q.h2, (size_t)n_dir * pslots);
         d.take(q.nrm, (size_t)n_dir * (np / 64));
@@ -919,9 +927,10 @@ int ms_dim(const wfq_solve_opts& o, int64_t n) {
 uint64_t ms_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_dir) {
     const uint64_t m = ms_dim(o, S.n), np = S.npad, nwc = wave_chunks(S.n);
     uint64_t b = (uint64_t)n_dir * (m + 1) * np * 8;            // bases
-    if (o.precision == WFQ_PREC_FP64) b *= 2;                    // and their products T v_j
-    b += (uint64_t)n_dir * m * (m + 1) * 8;                      // Hessenberg
-    b += (uint64_t)n_dir * ((m + 2) * nwc * 8 + nwc * 8 + (m + 2) * 16);   // partials, h1, h2
+    if (o.precision == WFQ_PREC_FP64) b *= 2;                    // and their products T u_j
+    b += (uint64_t)n_dir * m * (m + 1) * 8 * (o.precision == WFQ_PREC_FP64 ? 2 : 1);   // Hessenberg (and S)
+    b += (uint64_t)n_dir * (2 * (m + 1) * nwc * 8 + nwc * 8 + (m + 2) * 16);   // partials, h1, h2
+    b += (uint64_t)n_dir * (3 * (m + 1) + 3) * 8;                // dots, hp, gamma, 1 / rho, nu
     b += (uint64_t)B * (m * (m + 1) / 2) * 16;                   // R, packed
     b += (uint64_t)B * (m * 40 + (m + 1) * 16 + 64);             // cs, sn, y, g, scalars
     return b + (1u << 20);
@@ -1078,43 +1087,46 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         WFQ_HIP(hipStreamSynchronize(st));   // the pinned lists are rewritten by the next call
     };
     if (!stepping.empty()) lists();
+    // Steps 0 .. m: step j forms the product of u_j (j < m), finalises q_j and completes column j - 1
+    // of Hbar (one-reduction Gram-Schmidt), then takes that column's Givens step for every system.
+    const int ps2 = 2 * mdim1;
+    double *dots = q.dots.p, *hp = q.hp.p, *gam = q.gam.p, *irho = q.irho.p, *nu = q.nu.p;
     GraphCache* gc = tm.on() ? nullptr : graphs;
-    for (int j0 = 0; j0 < m && !stepping.empty();) {
-        const int c = std::min(kChunk, m - j0);
+    for (int j0 = 0; j0 <= m && !stepping.empty();) {
+        const int c = std::min(kChunk, m + 1 - j0);
         keep_tv = keep_tv && cur == WFQ_PREC_FP64;
         auto step = [&](int j) {
-            // w = L T v_j (one real column per direction)
+            const bool wz = j < m;
+            if (wz) {
+                // z = L T u_j (one real column per direction) into slot j + 1
+                tm.begin(st);
+                ms_pack(cur, V, np, mdim1, j, dirs, na, inv_h, x_block(w, cur), np, st);
+                tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(cur)));
+                block_product(S, w, cur, na, tm, st);
+                tm.begin(st);
+                double* tv = keep_tv ? q.TV.p : nullptr;
+                ms_spmm(S, cur == WFQ_PREC_FP64, y_block(w, cur), np, dirs, na, V, mdim1, j + 1, tv, st);
+                // L is read once for all directions (up to four per pass)
+                tm.end(st, KC_SPMM, 2.0 * S.nnz * na,
+                       12.0 * S.nnz * ((na + 3) / 4) + na * dn * (out_size(cur) + 8 + (tv ? 8 : 0)));
+            }
+            // one sweep of dots against q_0 .. q_{j-1} and u, one update sweep
             tm.begin(st);
-            ms_pack(cur, V, np, mdim1, j, dirs, na, inv_h, x_block(w, cur), np, st);
-            tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(cur)));
-            block_product(S, w, cur, na, tm, st);
+            ms_dcgs_dot(V, n, np, mdim1, j, wz, dirs, na, part, ps2, st);
+            ms_reduce(dirs, na, part, ps2, n, wz ? 2 * j + 2 : j + 1, dots, st);
+            tm.end(st, KC_DOT, (wz ? 4.0 : 2.0) * dn * na * (j + 1), 8.0 * dn * na * (j + (wz ? 2 : 1)));
             tm.begin(st);
-            double* tv = keep_tv ? q.TV.p : nullptr;
-            ms_spmm(S, cur == WFQ_PREC_FP64, y_block(w, cur), np, dirs, na, V, mdim1, j + 1, tv, st);
-            // L is read once for all directions (up to four per pass)
-            tm.end(st, KC_SPMM, 2.0 * S.nnz * na,
-                   12.0 * S.nnz * ((na + 3) / 4) + na * dn * (out_size(cur) + 8 + (tv ? 8 : 0)));
-            // two classical Gram-Schmidt passes against v_0 .. v_j
-            const double pass = 8.0 * dn * na * (j + 2);
-            tm.begin(st);
-            ms_dot(V, n, np, mdim1, j + 1, j + 1, dirs, na, part, pslots, false, st);
-            ms_reduce(dirs, na, part, pslots, n, j + 1, h1, st);
-            tm.end(st, KC_DOT, 2.0 * dn * na * (j + 1), pass);
-            tm.begin(st);
-            ms_update(V, n, np, mdim1, j + 1, j + 1, dirs, na, h1, pslots, nullptr, st);
-            tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
-            tm.begin(st);
-            ms_dot(V, n, np, mdim1, j + 1, j + 1, dirs, na, part, pslots, false, st);
-            ms_reduce(dirs, na, part, pslots, n, j + 1, h2, st);
-            tm.end(st, KC_DOT, 2.0 * dn * na * (j + 1), pass);
-            tm.begin(st);
-            ms_update(V, n, np, mdim1, j + 1, j + 1, dirs, na, h2, pslots, nrm, st);
-            ms_hcol(dirs, na, j, m, h1, h2, pslots, nrm, n, np, H, inv_h, st);
-            tm.end(st, KC_UPDATE, 2.0 * dn * na * (j + 1), pass + 8.0 * dn * na);
-            // every unconverged frequency of those directions: one Givens step on Hbar + z Ibar
-            tm.begin(st);
-            ms_givens(sys, ns, j, m, sdir, z, H, cs, sn, g, R, B, est, tol_abs, flags, run, ksteps, st);
-            tm.end(st, KC_GIVENS, 0, 0);
+            ms_dcgs_coeff(dirs, na, j, wz, m, dots, ps2, hp, H, keep_tv ? q.Sm.p : nullptr, nu, inv_h, gam, irho, st);
+            if (wz)
+                ms_dcgs_update(V, n, np, mdim1, j, dirs, na, dots, ps2, gam, irho, nrm, nu, inv_h, st);
+            tm.end(st, KC_UPDATE, wz ? 4.0 * dn * na * j : 0.0, wz ? 8.0 * dn * na * (j + 4) : 0.0);
+            // every unconverged frequency of those directions: one Givens step on column j - 1 of
+            // Hbar + z Ibar
+            if (j >= 1) {
+                tm.begin(st);
+                ms_givens(sys, ns, j - 1, m, sdir, z, H, cs, sn, g, R, B, est, tol_abs, flags, run, ksteps, st);
+                tm.end(st, KC_GIVENS, 0, 0);
+            }
         };
         run_chunk(gc, S, GraphKey{1, j0, c, ns, na, cur, keep_tv ? 1 : 0}, st, [&] {
             for (int j = j0; j < j0 + c; ++j) step(j);
@@ -1174,6 +1186,8 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
         ms_solve(sys, (int)withk.size(), ksteps, m, R, B, g, y, st);
     }
     ms_xupdate(V, n, np, mdim1, grp_sys, grp_dir, ngrp, ksteps, y, m, w.Xb, st);
+    // the kept products are of u_0 .. u_{k-1} = Q S: T x = T U (S^-1 y), so y becomes S^-1 y
+    if (keep_tv && !withk.empty()) ms_sinv(sys, (int)withk.size(), ksteps, m, q.Sm.p, sdir, y, st);
     tm.end(st, KC_XUPDATE, 0, 0);
     WFQ_HIP(hipStreamSynchronize(st));
     q.ngrp = ngrp;

@@ -200,36 +200,46 @@ __global__ void __launch_bounds__(128) ms_hcol_kernel(const int* __restrict__ di
 // products relate to the final basis by U = Q S with S upper triangular (S(t, k) = a_t,
 // S(k, k) = rho), kept column by column in the layout of H when the products T u_k are kept.
 
-// partial[d][e][wc] for the entries e above over wave chunk wc (512 rows): one wave per (chunk,
-// basis vector t <= k, direction) computes v_t . u and v_t . z (t = k: alpha and beta).
+// partial[d][e][wc] for the entries e above over wave chunk wc (512 rows). One wave per (chunk, group
+// of kDotGroup basis vectors t <= k, direction): u and z of the chunk stay in registers while the
+// wave computes v_t . u and v_t . z for its vectors (t = k: alpha and beta).
+constexpr int kDotGroup = 16;
 __global__ void __launch_bounds__(256) ms_dcgs_dot_kernel(const double* __restrict__ V, int64_t n, int64_t npad,
                                                           int mdim1, int k, int with_z, const int* __restrict__ dirs,
                                                           double* __restrict__ partial, int ps, int64_t nwc) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t wc = blockIdx.x;
-    const int t = blockIdx.y * 4 + wave;
-    if (t > k) return;   // uniform over the wave
+    const int64_t wc = (int64_t)blockIdx.x * 4 + wave;
+    if (wc >= nwc) return;   // uniform over the wave
+    const int t0 = blockIdx.y * kDotGroup, t1 = min(t0 + kDotGroup, k + 1);
     const int d = dirs[blockIdx.z];
     const double* u = V + ((int64_t)d * mdim1 + k) * npad;
     const double* zv = u + npad;   // slot k + 1 (read only with z)
-    const double* v = V + ((int64_t)d * mdim1 + t) * npad;
     const int64_t row0 = wc * kWaveRows + lane;
-    double sa = 0.0, sb = 0.0;
+    double xu[8], xz[8];
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
         const int64_t row = row0 + 64 * r;
-        if (row < n) {
-            const double x = v[row];
-            sa += x * u[row];
-            if (with_z) sb += x * zv[row];
-        }
+        xu[r] = row < n ? u[row] : 0.0;
+        xz[r] = (with_z && row < n) ? zv[row] : 0.0;
     }
-    sa = wave_sum(sa);
-    if (with_z) sb = wave_sum(sb);   // with_z is uniform over the launch
-    if (lane == 0) {
-        double* P = partial + (int64_t)d * ps * nwc + wc;
-        P[(int64_t)t * nwc] = sa;
-        if (with_z) P[(int64_t)(k + 1 + t) * nwc] = sb;
+    double* P = partial + (int64_t)d * ps * nwc + wc;
+#pragma unroll 2
+    for (int t = t0; t < t1; ++t) {
+        const double* v = V + ((int64_t)d * mdim1 + t) * npad;
+        double sa = 0.0, sb = 0.0;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            const int64_t row = row0 + 64 * r;
+            const double x = row < n ? v[row] : 0.0;
+            sa += x * xu[r];
+            sb += x * xz[r];
+        }
+        sa = wave_sum(sa);
+        sb = wave_sum(sb);
+        if (lane == 0) {
+            P[(int64_t)t * nwc] = sa;
+            if (with_z) P[(int64_t)(k + 1 + t) * nwc] = sb;
+        }
     }
 }
 
@@ -326,45 +336,52 @@ __global__ void __launch_bounds__(1024) ms_dcgs_hp_kernel(const int* __restrict_
 }
 
 // q_k = (u - Q a) / rho into slot k and p' = (z - Q b - gamma q_k) / rho into slot k + 1, with the
-// sums of p'^2 over 64-row blocks in norm[d][blk]. A block owns 64 rows; its 4 waves take every 4th
-// basis vector (both sums from one read) and are combined in LDS in a fixed order.
+// sums of p'^2 over 64-row blocks in norm[d][blk]. A work-group owns 256 rows (4 per lane); its 4
+// waves take every 4th basis vector (both sums from one read) and are combined in LDS in a fixed
+// order. Rows past n (below npad) are read but neither written nor counted in the norm.
 __global__ void __launch_bounds__(256) ms_dcgs_update_kernel(double* __restrict__ V, int64_t n, int64_t npad,
                                                              int mdim1, int k, const int* __restrict__ dirs,
                                                              const double* __restrict__ dots, int ps,
                                                              const double* __restrict__ gam,
                                                              const double* __restrict__ inv_rho,
                                                              double* __restrict__ norm) {
-    __shared__ double pa[4][kMsRows], pb[4][kMsRows];
-    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int64_t row = (int64_t)blockIdx.x * kMsRows + r;
+    __shared__ double pa[4][256], pb[4][256];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t base = (int64_t)blockIdx.x * 256;   // npad is a multiple of 256
     const int d = dirs[blockIdx.y];
     const double* dt = dots + (int64_t)d * ps;
-    double sa = 0.0, sb = 0.0;
-    if (row < n) {
-#pragma unroll 4
-        for (int i = q; i < k; i += 4) {
-            const double v = V[((int64_t)d * mdim1 + i) * npad + row];
-            sa += dt[i] * v;
-            sb += dt[k + 1 + i] * v;
+    double sa[4] = {0.0, 0.0, 0.0, 0.0}, sb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+    for (int i = q; i < k; i += 4) {
+        const double* v = V + ((int64_t)d * mdim1 + i) * npad + base + lane;
+        const double ai = dt[i], bi = dt[k + 1 + i];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double x = v[64 * r];
+            sa[r] += ai * x;
+            sb[r] += bi * x;
         }
     }
-    pa[q][r] = sa;
-    pb[q][r] = sb;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        pa[q][lane + 64 * r] = sa[r];
+        pb[q][lane + 64 * r] = sb[r];
+    }
     __syncthreads();
-    if (q == 0) {
-        double* u = V + ((int64_t)d * mdim1 + k) * npad;
-        double* zv = u + npad;
-        double x = 0.0;
-        if (row < n) {
-            const double ir = inv_rho[d], g = gam[d];
-            const double qk = (u[row] - ((pa[0][r] + pa[1][r]) + (pa[2][r] + pa[3][r]))) * ir;
-            x = (zv[row] - ((pb[0][r] + pb[1][r]) + (pb[2][r] + pb[3][r])) - g * qk) * ir;
-            u[row] = qk;
-            zv[row] = x;
-        }
-        const double s2 = wave_sum(x * x);
-        if (r == 0) norm[(int64_t)d * (npad / kMsRows) + blockIdx.x] = s2;
+    const int t = threadIdx.x;
+    const int64_t row = base + t;
+    double* u = V + ((int64_t)d * mdim1 + k) * npad;
+    double* zv = u + npad;
+    double x = 0.0;
+    if (row < n) {
+        const double ir = inv_rho[d], g = gam[d];
+        const double qk = (u[row] - ((pa[0][t] + pa[1][t]) + (pa[2][t] + pa[3][t]))) * ir;
+        x = (zv[row] - ((pb[0][t] + pb[1][t]) + (pb[2][t] + pb[3][t])) - g * qk) * ir;
+        u[row] = qk;
+        zv[row] = x;
     }
+    const double s2 = wave_sum(x * x);
+    if (lane == 0) norm[(int64_t)d * (npad / kMsRows) + (base / kMsRows) + q] = s2;
 }
 
 // nu[d] = |p'| from the block sums (two waves, fixed order), inv_h[d] = 1 / nu[d] (0 when p' = 0)
@@ -631,7 +648,7 @@ void ms_dcgs_dot(const double* V, int64_t n, int64_t npad, int mdim1, int k, boo
     if (ndir <= 0) return;
     if (2 * k + 2 > ps) throw Error{WFQ_EINVAL, "ms_dcgs_dot: too few partial slots"};
     const int64_t nwc = wave_chunks(n);
-    dim3 grd((unsigned)nwc, (unsigned)((k + 4) / 4), (unsigned)ndir);
+    dim3 grd((unsigned)((nwc + 3) / 4), (unsigned)(k / kDotGroup + 1), (unsigned)ndir);
     hipLaunchKernelGGL(ms_dcgs_dot_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, k, with_z ? 1 : 0, dirs, partial,
                        ps, nwc);
     WFQ_CHECK_LAUNCH();
@@ -654,7 +671,7 @@ void ms_dcgs_update(double* V, int64_t n, int64_t npad, int mdim1, int k, const 
                     const double* dots, int ps, const double* gam, const double* inv_rho, double* norm,
                     double* nu, double* inv_h, hipStream_t st) {
     if (ndir <= 0) return;
-    dim3 grd((unsigned)(npad / kMsRows), (unsigned)ndir);
+    dim3 grd((unsigned)(npad / 256), (unsigned)ndir);
     hipLaunchKernelGGL(ms_dcgs_update_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, k, dirs, dots, ps, gam, inv_rho,
                        norm);
     WFQ_CHECK_LAUNCH();

@@ -351,9 +351,9 @@ __global__ void __launch_bounds__(256) otf_narrow_f64_kernel(int64_t n, int64_t 
     }
 }
 
-// Y[c][i] = sum over the source parts (in part order) + sum_e C[e][i] X[c][col[e][i]] (near field),
-// every column of row i in one thread so that the correction's entries are read once; both loops
-// unrolled by 8 to keep that many independent loads in flight (the order of the sums is unchanged)
+// Y[c][i] = sum over the source parts + sum_e C[e][i] X[c][col[e][i]] (near field). A work-group owns
+// 64 rows: its 4 waves take every 4th correction entry and every 4th part (all columns of a row in one
+// thread, so each entry is read once), and their sums are added in LDS in a fixed order.
 template <int NC>
 __global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int nparts, int ncol,
                                                              const double* __restrict__ part, int w,
@@ -361,25 +361,32 @@ __global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int n
                                                              const double* __restrict__ nval,
                                                              const double* __restrict__ X, int64_t ldx,
                                                              double* __restrict__ Y, int64_t ldy) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= npad) return;
+    __shared__ double red[4][NC][64];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;   // npad is a multiple of 64
     double t[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) t[c] = 0.0;
-#pragma unroll 8
-    for (int e = 0; e < w; ++e) {
+#pragma unroll 4
+    for (int e = q; e < w; e += 4) {
         const double v = nval[(int64_t)e * npad + i];
         const int64_t j = ncolv[(int64_t)e * npad + i];
 #pragma unroll
         for (int c = 0; c < NC; ++c) t[c] = fma(v, X[c * ldx + j], t[c]);
     }
+#pragma unroll 4
+    for (int p = q; p < nparts; p += 4) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        if (c >= ncol) break;
-        double s = 0.0;
-#pragma unroll 8
-        for (int p = 0; p < nparts; ++p) s += part[((int64_t)p * NC + c) * npad + i];
-        Y[c * ldy + i] = s + t[c];
+        for (int c = 0; c < NC; ++c)
+            if (c < ncol) t[c] += part[((int64_t)p * NC + c) * npad + i];
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c) red[q][c][lane] = t[c];
+    __syncthreads();
+    if (q == 0) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < ncol) Y[c * ldy + i] = (red[0][c][lane] + red[1][c][lane]) + (red[2][c][lane] + red[3][c][lane]);
     }
 }
 
@@ -395,7 +402,7 @@ void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t l
     hipLaunchKernelGGL((otf_narrow_f64_kernel<NC>), dim3((unsigned)tblocks, (unsigned)nparts), dim3(256), 0, st, s.n,
                        s.npad, s.pos, X, ld, part, per);
     WFQ_CHECK_LAUNCH();
-    hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, s.npad, nparts,
+    hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 64)), dim3(256), 0, st, s.npad, nparts,
                        ncol, part, s.near_w, s.near_col, s.near_val, X, ld, Y, ld);
     WFQ_CHECK_LAUNCH();
 }
@@ -571,7 +578,7 @@ void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, 
         hipLaunchKernelGGL((otf_sym_kernel<NC, true>), dim3((unsigned)nb), dim3(256), 0, st, s.n, s.npad, nb, nb - 1,
                            s.pos, X, ld, P);
     WFQ_CHECK_LAUNCH();
-    hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 256)), dim3(256), 0, st, s.npad, nb, ncol,
+    hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 64)), dim3(256), 0, st, s.npad, nb, ncol,
                        P, s.near_w, s.near_col, s.near_val, X, ld, Y, ld);
     WFQ_CHECK_LAUNCH();
 }

@@ -480,12 +480,13 @@ def bench_multishift(args, wl, wfq, torch):
     S = wl.n_systems
     nd = len(wl.dirs)
     t0 = time.perf_counter()
-    h = wfq.wfq_build(wl.xyz, wl.params, store=("fp64",) if prec == "fp64" else ("fp64", prec), device=0)
+    h = wfq.wfq_build(wl.xyz, wl.params, t_mode=wl.t_mode, store=("fp64",) if prec == "fp64" else ("fp64", prec),
+                      device=0)
     build_s = time.perf_counter() - t0
     opts = dict(restart=wl.restart, precision=prec, algorithm="msgmres", max_iter=args.max_iter, shift_dim=shift_dim)
     tune = None
     t0 = time.perf_counter()
-    if not args.no_tune:
+    if not args.no_tune and wl.t_mode != "otf":   # matrix-free structures have no stored variants to tune
         # the shapes of the narrow products (one column per direction); the one FP64 residual check
         # per solve keeps the built-in shape
         tune = wfq.wfq_tune(h, "fp64", list(range(1, nd + 1)), reps=2)

@@ -19,6 +19,7 @@ constexpr int kPad = 256;
 // block-product variant, so no variant reads or writes past the allocated rows.
 constexpr int kColPad = 256;
 constexpr uint64_t kSplitWsCap = 512ull << 20;   // work space of split-k block products
+constexpr uint64_t kSymWsCap = 32ull << 30;      // per-block sums of the symmetric narrow products
 
 inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -88,6 +89,9 @@ struct Structure {
     // partial tiles of split-k block products (grown on demand, at most kSplitWsCap bytes)
     mutable void* split_ws = nullptr;
     mutable uint64_t split_ws_bytes = 0;
+    // bytes of that work space a solve has reserved in its budget for the per-block sums of the
+    // symmetric narrow products (0: at most kSplitWsCap)
+    mutable uint64_t sym_ws_allowed = 0;
     // when set, the partial tiles go to this region (at most split_fixed_bytes) and nothing is
     // allocated: the block products then choose only splits whose partial tiles fit
     mutable void* split_fixed = nullptr;
@@ -189,6 +193,8 @@ int device_cus(int device);
 // true when narrow recomputed products of ncol <= 4 columns take the symmetric form (each element
 // evaluated once for both of its rows: n >= 65 536 and the per-block sums fit the work space)
 bool otf_sym_fits(const Structure& s, int ncol);
+// work space of the symmetric form for ncol columns (0 below 65 536 atoms, where it is not used)
+uint64_t otf_sym_bytes(const Structure& s, int ncol);
 // partial-tile work space of the block products (grown on demand, or the fixed region when set)
 void* split_workspace(const Structure& s, uint64_t bytes);
 void otf_tx_f64(const Structure& s, const double* X, double* Y, int ncol, hipStream_t st);

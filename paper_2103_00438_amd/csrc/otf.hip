@@ -12,6 +12,8 @@
 // FP32 elements use erf(x) = 1 - (a1 t + ... + a5 t^5) exp(-x^2), t = 1 / (1 + p x) (Abramowitz &
 // Stegun, Handbook of Mathematical Functions, formula 7.1.26; absolute error <= 1.5e-7) for
 // x >= 1/2 and the Maclaurin series of erf below; FP64 elements use the device library's erf.
+#include <algorithm>
+
 #include "common.h"
 #include "device_util.h"
 
@@ -585,10 +587,15 @@ void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, 
 
 }  // namespace
 
-bool otf_sym_fits(const Structure& s, int ncol) {
+uint64_t otf_sym_bytes(const Structure& s, int ncol) {
+    if (s.n < kSymFrom) return 0;
     const int64_t nb = (s.npad + kSymBlock - 1) / kSymBlock;
-    const uint64_t cap = s.split_fixed ? s.split_fixed_bytes : kSplitWsCap;
-    return s.n >= kSymFrom && (uint64_t)nb * ncol * s.npad * sizeof(double) <= cap;
+    return (uint64_t)nb * ncol * s.npad * sizeof(double);
+}
+
+bool otf_sym_fits(const Structure& s, int ncol) {
+    const uint64_t cap = s.split_fixed ? s.split_fixed_bytes : std::max(kSplitWsCap, s.sym_ws_allowed);
+    return s.n >= kSymFrom && otf_sym_bytes(s, ncol) <= cap;
 }
 
 void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st) {

@@ -1522,6 +1522,22 @@ int solve_all(Structure& S, const double* omegas_eV, int n_omega, const double* 
     while (B > 1 && S.budget && batch_bytes(S, o, B, n_dir) > avail) B = (B + 1) / 2;
     if (S.budget && batch_bytes(S, o, B, n_dir) > avail)
         throw Error{WFQ_ENOMEM, "not enough device memory for one system's Krylov work space"};
+    // the symmetric narrow products (matrix-free FP64, up to 4 columns at a time) need one partial sum
+    // per 1 024-atom block and row: reserved here when it exceeds the ordinary work-space cap and the
+    // budget leaves room beside the batch; otherwise those products take the one-sided form
+    {
+        const uint64_t sym4 = otf_sym_bytes(S, 4);
+        const bool reserve = sym4 > kSplitWsCap && sym4 <= kSymWsCap &&
+                             (!S.budget || batch_bytes(S, o, B, n_dir) + sym4 <= avail);
+        S.sym_ws_allowed = reserve ? sym4 : 0;
+        if (S.split_ws && S.split_ws_bytes > std::max(kSplitWsCap, S.sym_ws_allowed)) {
+            // a larger work space held from an earlier solve is not covered by this one's budget
+            WFQ_HIP(hipFree(S.split_ws));
+            S.split_ws = nullptr;
+            S.split_ws_bytes = 0;
+            ++S.epoch;
+        }
+    }
 
     const bool qmr = o.algorithm == WFQ_QMR;
     WorkShape sh;

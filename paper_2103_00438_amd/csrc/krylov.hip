@@ -268,6 +268,10 @@ __global__ void __launch_bounds__(256) x_update_kernel(Basis V, Basis X, int64_t
     xr[i + X.npad] += ai;
 }
 
+// V(s, 0) = b_dir(s) - (L Y_s + z_s x_s), system s = sys[k] with its product in columns 2k and 2k + 1 of
+// Y; norm2[s][blk] = the block's sum of |r_i|^2 and qtq[s][blk] (if not NULL) that of
+// Re(conj(x_i) (T x)_i). The grid's x index is the system and its y index the row block, so the
+// work-groups of one row block run together and read its rows of L through the L2 cache once.
 __global__ void __launch_bounds__(256) residual_kernel(int64_t n, int64_t npad, int w,
                                                        const int32_t* __restrict__ ecol,
                                                        const double* __restrict__ eval,
@@ -277,8 +281,8 @@ __global__ void __launch_bounds__(256) residual_kernel(int64_t n, int64_t npad, 
                                                        Basis V, double* __restrict__ norm2, int nblk,
                                                        double* __restrict__ qtq) {
     __shared__ double sh[4];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int k = blockIdx.y;
+    const int64_t i = (int64_t)blockIdx.y * 256 + threadIdx.x;
+    const int k = blockIdx.x;
     const int s = sys[k];
     double nn = 0.0, et = 0.0;
     if (i < n) {
@@ -302,10 +306,10 @@ __global__ void __launch_bounds__(256) residual_kernel(int64_t n, int64_t npad, 
         et = xre * Y[(int64_t)(2 * k) * ld + i] + xim * Y[(int64_t)(2 * k + 1) * ld + i];
     }
     nn = block_sum(nn, sh);
-    if (threadIdx.x == 0) norm2[(int64_t)s * nblk + blockIdx.x] = nn;
+    if (threadIdx.x == 0) norm2[(int64_t)s * nblk + blockIdx.y] = nn;
     if (qtq) {
         et = block_sum(et, sh);   // block_sum synchronises before it reuses sh
-        if (threadIdx.x == 0) qtq[(int64_t)s * nblk + blockIdx.x] = et;
+        if (threadIdx.x == 0) qtq[(int64_t)s * nblk + blockIdx.y] = et;
     }
 }
 
@@ -532,7 +536,8 @@ void residual(const Structure& S, const double* Y, int64_t ld, const int* sys, i
               const Basis& x, const double* b, const int* dir, const Basis& V, double* norm2, int nblk,
               double* qtq, hipStream_t st) {
     if (nsys <= 0) return;
-    dim3 grd((unsigned)nblk, (unsigned)nsys);
+    if (nblk > 65535) throw Error{WFQ_EINVAL, "residual: more row blocks than the grid's y dimension holds"};
+    dim3 grd((unsigned)nsys, (unsigned)nblk);
     hipLaunchKernelGGL(residual_kernel, grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col, S.ell_val, Y, ld, sys,
                        z, x, b, dir, V, norm2, nblk, qtq);
     WFQ_CHECK_LAUNCH();

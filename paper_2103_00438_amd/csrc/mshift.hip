@@ -427,32 +427,68 @@ __global__ void __launch_bounds__(256) ms_sinv_kernel(const int* __restrict__ sy
 // One Givens step of system s on column j of Hbar + z Ibar (direction sdir[s], shift z[s]): the
 // rotations of the earlier steps are applied, a new rotation zeroes the subdiagonal, the rotated
 // column is stored as column j of R, and |g_{j+1}| is the residual norm of the shifted system.
-__global__ void ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, int m, const int* __restrict__ sdir,
-                                 const double2* __restrict__ z, const double* __restrict__ H, double* __restrict__ cs,
-                                 double2* __restrict__ sn, double2* __restrict__ g, double2* __restrict__ R,
-                                 int64_t S, double* __restrict__ est, const double* __restrict__ tol_abs,
-                                 int* __restrict__ flags, int* __restrict__ run, int* __restrict__ ksteps) {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nsys) return;
+// One wave per system. Applying rotation i maps the running entry affinely,
+// cur' = -conj(s_i) cur + c_i y_{i+1}, and emits c_i cur + s_i y_{i+1}: each lane composes the maps
+// of a contiguous chunk of the rotations, an inclusive scan across the lanes gives every chunk its
+// incoming entry, and the lanes then replay their chunks to emit the rotated entries (about
+// 2 j / 64 + 6 dependent steps instead of j).
+__global__ void __launch_bounds__(64) ms_givens_kernel(const int* __restrict__ sys, int nsys, int j, int m,
+                                                       const int* __restrict__ sdir, const double2* __restrict__ z,
+                                                       const double* __restrict__ H, double* __restrict__ cs,
+                                                       double2* __restrict__ sn, double2* __restrict__ g,
+                                                       double2* __restrict__ R, int64_t S, double* __restrict__ est,
+                                                       const double* __restrict__ tol_abs, int* __restrict__ flags,
+                                                       int* __restrict__ run, int* __restrict__ ksteps) {
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
     const int s = sys[k];
-    if (!run[s]) return;   // stopped earlier in this chunk of steps
+    if (!run[s]) return;   // stopped earlier in this chunk of steps (uniform over the wave)
     const double* hc = H + ((int64_t)sdir[s] * m + j) * (m + 1);
     double2* col = R + ((int64_t)j * (j + 1) / 2) * S + s;   // entry i of the column at col[i * S]
     const double2 zs = z[s];
-    const double hn = hc[j + 1];
-    // column j of Hbar + z Ibar through the previous rotations; the running entry stays in registers
-    double2 cur = make_double2(hc[0] + (j == 0 ? zs.x : 0.0), j == 0 ? zs.y : 0.0);
-    // unrolled so that the loads of several rotations are in flight ahead of the dependent chain
-#pragma unroll 8
-    for (int i = 0; i < j; ++i) {
-        const double2 y = make_double2(hc[i + 1] + (i + 1 == j ? zs.x : 0.0), i + 1 == j ? zs.y : 0.0);
+    auto yv = [&](int i) {   // entry i + 1 of column j of Hbar + z Ibar
+        return make_double2(hc[i + 1] + (i + 1 == j ? zs.x : 0.0), i + 1 == j ? zs.y : 0.0);
+    };
+    const int L = (j + 63) / 64;
+    const int i0 = min(j, lane * L), i1 = min(j, i0 + L);
+    // the chunk's map: cur_out = A cur_in + B
+    double2 A = make_double2(1.0, 0.0), B = make_double2(0.0, 0.0);
+    for (int i = i0; i < i1; ++i) {
+        const double2 a = cscale(-1.0, cconj(sn[(int64_t)i * S + s]));
+        A = cmul(a, A);
+        B = cadd(cmul(a, B), cscale(cs[(int64_t)i * S + s], yv(i)));
+    }
+    // inclusive scan of the maps over the lanes (lane l: the maps of chunks 0 .. l, applied in order)
+    for (int off = 1; off < 64; off <<= 1) {
+        const double2 Ap = make_double2(__shfl_up(A.x, off, 64), __shfl_up(A.y, off, 64));
+        const double2 Bp = make_double2(__shfl_up(B.x, off, 64), __shfl_up(B.y, off, 64));
+        if (lane >= off) {
+            B = cadd(cmul(A, Bp), B);
+            A = cmul(A, Ap);
+        }
+    }
+    const double2 cur0 = make_double2(hc[0] + (j == 0 ? zs.x : 0.0), j == 0 ? zs.y : 0.0);
+    double2 Ae = make_double2(__shfl_up(A.x, 1, 64), __shfl_up(A.y, 1, 64));
+    double2 Be = make_double2(__shfl_up(B.x, 1, 64), __shfl_up(B.y, 1, 64));
+    if (lane == 0) {
+        Ae = make_double2(1.0, 0.0);
+        Be = make_double2(0.0, 0.0);
+    }
+    double2 cur = cadd(cmul(Ae, cur0), Be);
+    for (int i = i0; i < i1; ++i) {
+        const double2 y = yv(i);
         const double ci = cs[(int64_t)i * S + s];
         const double2 si = sn[(int64_t)i * S + s];
         col[(int64_t)i * S] = cadd(cscale(ci, cur), cmul(si, y));
         cur = cadd(cscale(-1.0, cmul(cconj(si), cur)), cscale(ci, y));
     }
+    // entry j after every earlier rotation: the whole composition applied to the first entry
+    const double2 At = make_double2(__shfl(A.x, 63, 64), __shfl(A.y, 63, 64));
+    const double2 Bt = make_double2(__shfl(B.x, 63, 64), __shfl(B.y, 63, 64));
+    if (lane != 0) return;
+    const double hn = hc[j + 1];
+    const double2 x = cadd(cmul(At, cur0), Bt);
     // rotation [c s; -conj(s) c] with c real zeroing hn below col[j]
-    const double2 x = cur;
     const double ax = cabs(x);
     double c;
     double2 sv;
@@ -638,8 +674,8 @@ void ms_givens(const int* sys, int nsys, int j, int m, const int* sdir, const do
                double2* sn, double2* g, double2* R, int64_t S, double* est, const double* tol_abs, int* flags,
                int* run, int* ksteps, hipStream_t st) {
     if (nsys <= 0) return;
-    hipLaunchKernelGGL(ms_givens_kernel, dim3((unsigned)((nsys + 63) / 64)), dim3(64), 0, st, sys, nsys, j, m, sdir, z,
-                       H, cs, sn, g, R, S, est, tol_abs, flags, run, ksteps);
+    hipLaunchKernelGGL(ms_givens_kernel, dim3((unsigned)nsys), dim3(64), 0, st, sys, nsys, j, m, sdir, z, H, cs, sn, g,
+                       R, S, est, tol_abs, flags, run, ksteps);
     WFQ_CHECK_LAUNCH();
 }
 

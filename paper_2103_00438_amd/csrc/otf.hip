@@ -530,6 +530,7 @@ __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, i
         }
         __syncthreads();
         for (int g = 0; g < TILE; g += 64) {
+            if (MASK && j0 + g >= n) break;   // uniform: the rest of the tile is padding
             if (diag)
                 sym_group<NC, false, true, MASK>(sx, sy, sz, sX, g, lane, j0, n, xi, yi, zi, xt, tin, acc, red, wave);
             else

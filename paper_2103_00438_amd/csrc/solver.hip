@@ -1092,8 +1092,12 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
     const int ps2 = 2 * mdim1;
     double *dots = q.dots.p, *hp = q.hp.p, *gam = q.gam.p, *irho = q.irho.p, *nu = q.nu.p;
     GraphCache* gc = tm.on() ? nullptr : graphs;
+    // chunk length: kChunk steps, fewer when the slowest frequency's estimate, extrapolated at the
+    // rate of the last chunk, reaches the tolerance sooner (fewer products after it converges)
+    int next_c = kChunk;
+    double worst_prev = 0.0;
     for (int j0 = 0; j0 <= m && !stepping.empty();) {
-        const int c = std::min(kChunk, m + 1 - j0);
+        const int c = std::min(next_c, m + 1 - j0);
         keep_tv = keep_tv && cur == WFQ_PREC_FP64;
         auto step = [&](int j) {
             const bool wz = j < m;
@@ -1154,6 +1158,13 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
                 std::fflush(stderr);
             }
         }
+        next_c = kChunk;
+        if (worst > 0.0 && worst_prev > 0.0 && worst < worst_prev) {
+            const double rate = std::pow(worst / worst_prev, 1.0 / c);   // per step
+            const double left = std::log(tol / worst) / std::log(rate);   // steps to the tolerance
+            if (left < kChunk - 1) next_c = std::max(1, (int)std::ceil(left) + 1);   // + the Givens lag
+        }
+        worst_prev = worst;
         const bool changed = next.size() != stepping.size();
         stepping.swap(next);
         if (changed && !stepping.empty()) lists();

@@ -186,8 +186,11 @@ void tune_tx(Structure& s, int prec, int ncol, int reps, double* ms, hipStream_t
 void convert_from_f64(int prec, const double* src, void* dst, int64_t count, hipStream_t st);
 void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st);
 // Y = T X for at most 4 real FP64 columns with every element recomputed (no stored T needed), on
-// the vector ALUs; `cus` = compute units of the device (sets the split of the source range)
-void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st);
+// the vector ALUs; `cus` = compute units of the device (sets the split of the source range). With
+// Yi != NULL also Yi[i][c] = Y[c][i] with rows of 4 doubles (columns >= ncol zero; Yi 32-byte aligned,
+// npad rows), so that a gather of row j reads every column at once.
+void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st,
+                    double* Yi = nullptr);
 // compute units of a device
 int device_cus(int device);
 // true when narrow recomputed products of ncol <= 4 columns take the symmetric form (each element

@@ -151,8 +151,10 @@ void ms_pack(int prec, double* V, int64_t npad, int mdim1, int j, const int* dir
              void* X, int64_t ld, hipStream_t st);
 // V(d_c, jdst) = L Y[c]; with TV != NULL also TV(d_c, jdst - 1) = Y[c] (rows >= n: 0), the product
 // T v_j kept beside the basis (same layout as V)
+// With Yi (FP64 products of at most 4 columns) the neighbours' values are gathered from the
+// interleaved copy of Y (rows of 4 doubles) that the narrow product can write beside it.
 void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* dirs, int ndir, double* V,
-             int mdim1, int jdst, double* TV, hipStream_t st);
+             int mdim1, int jdst, double* TV, hipStream_t st, const double* Yi = nullptr);
 // partial[d][i][wc] = chunk sums of V(d, i) . V(d, jw), i < nvec; self_norm: slot nvec = ||V(d, jw)||^2
 void ms_dot(const double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
             double* partial, int pslots, bool self_norm, hipStream_t st);

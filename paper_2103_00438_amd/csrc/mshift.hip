@@ -62,19 +62,33 @@ template <typename YE, int NC>
 __global__ void __launch_bounds__(256) ms_spmm_kernel(int64_t n, int64_t npad, int w, const int32_t* __restrict__ ecol,
                                                       const double* __restrict__ eval, const YE* __restrict__ Y,
                                                       int64_t ld, const int* __restrict__ dirs, double* __restrict__ V,
-                                                      int mdim1, int jdst, int c0, double* __restrict__ TV) {
+                                                      int mdim1, int jdst, int c0, double* __restrict__ TV,
+                                                      const double* __restrict__ Yi) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     double acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) acc[c] = 0.0;
     if (i < n) {
         const YE* y = Y + (int64_t)c0 * ld;
+        if (Yi) {
+            // the interleaved copy: all columns of neighbour j in one aligned 32-byte load
 #pragma unroll 4
-        for (int e = 0; e < w; ++e) {
-            const double v = eval[(int64_t)e * npad + i];
-            const int64_t j = ecol[(int64_t)e * npad + i];
+            for (int e = 0; e < w; ++e) {
+                const double v = eval[(int64_t)e * npad + i];
+                const int64_t j = ecol[(int64_t)e * npad + i];
+                const doublex4 yj = *reinterpret_cast<const doublex4*>(Yi + 4 * j);
+                const double yv[4] = {yj.x, yj.y, yj.z, yj.w};
 #pragma unroll
-            for (int c = 0; c < NC; ++c) acc[c] += v * widen(y[c * ld + j]);
+                for (int c = 0; c < NC; ++c) acc[c] += v * yv[c];
+            }
+        } else {
+#pragma unroll 4
+            for (int e = 0; e < w; ++e) {
+                const double v = eval[(int64_t)e * npad + i];
+                const int64_t j = ecol[(int64_t)e * npad + i];
+#pragma unroll
+                for (int c = 0; c < NC; ++c) acc[c] += v * widen(y[c * ld + j]);
+            }
         }
     }
 #pragma unroll
@@ -608,8 +622,9 @@ void ms_pack(int prec, double* V, int64_t npad, int mdim1, int j, const int* dir
 }
 
 void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const int* dirs, int ndir, double* V,
-             int mdim1, int jdst, double* TV, hipStream_t st) {
+             int mdim1, int jdst, double* TV, hipStream_t st, const double* Yi) {
     if (ndir <= 0) return;
+    if (Yi && (!y_is_f64 || ndir > 4)) throw Error{WFQ_EINVAL, "ms_spmm: the interleaved copy holds up to 4 FP64 columns"};
     const dim3 grd((unsigned)(S.npad / 256));
     // columns in chunks of at most 4 (3 for the usual three field directions in one pass)
     for (int c0 = 0; c0 < ndir; c0 += 4) {
@@ -618,7 +633,7 @@ void ms_spmm(const Structure& S, bool y_is_f64, const void* Y, int64_t ld, const
             using YE = decltype(tag);
             constexpr int NC = decltype(ncv)::value;
             hipLaunchKernelGGL((ms_spmm_kernel<YE, NC>), grd, dim3(256), 0, st, S.n, S.npad, S.ell_w, S.ell_col,
-                               S.ell_val, static_cast<const YE*>(Y), ld, dirs, V, mdim1, jdst, c0, TV);
+                               S.ell_val, static_cast<const YE*>(Y), ld, dirs, V, mdim1, jdst, c0, TV, Yi);
         };
         auto by_nc = [&](auto tag) {
             if (nc == 1) go(tag, std::integral_constant<int, 1>{});

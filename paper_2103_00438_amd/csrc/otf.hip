@@ -362,7 +362,8 @@ __global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int n
                                                              const int32_t* __restrict__ ncolv,
                                                              const double* __restrict__ nval,
                                                              const double* __restrict__ X, int64_t ldx,
-                                                             double* __restrict__ Y, int64_t ldy) {
+                                                             double* __restrict__ Y, int64_t ldy,
+                                                             double* __restrict__ Yi) {
     __shared__ double red[4][NC][64];
     const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
     const int64_t i = (int64_t)blockIdx.x * 64 + lane;   // npad is a multiple of 64
@@ -386,14 +387,20 @@ __global__ void __launch_bounds__(256) otf_narrow_sum_kernel(int64_t npad, int n
     for (int c = 0; c < NC; ++c) red[q][c][lane] = t[c];
     __syncthreads();
     if (q == 0) {
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (c < ncol) Y[c * ldy + i] = (red[0][c][lane] + red[1][c][lane]) + (red[2][c][lane] + red[3][c][lane]);
+            if (c < ncol) {
+                v[c] = (red[0][c][lane] + red[1][c][lane]) + (red[2][c][lane] + red[3][c][lane]);
+                Y[c * ldy + i] = v[c];
+            }
+        if (Yi) *reinterpret_cast<doublex4*>(Yi + 4 * i) = doublex4{v[0], v[1], v[2], v[3]};
     }
 }
 
 template <int NC>
-void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st) {
+void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, double* Yi,
+                       hipStream_t st) {
     const int64_t tblocks = (s.npad + 256 * kNarrowTK - 1) / (256 * kNarrowTK);
     // about 8 work-groups per compute unit in total, each part at least one source tile
     int nparts = (int)std::max<int64_t>(1, std::min<int64_t>((8LL * cus + tblocks - 1) / tblocks, 64));
@@ -405,7 +412,7 @@ void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t l
                        s.npad, s.pos, X, ld, part, per);
     WFQ_CHECK_LAUNCH();
     hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 64)), dim3(256), 0, st, s.npad, nparts,
-                       ncol, part, s.near_w, s.near_col, s.near_val, X, ld, Y, ld);
+                       ncol, part, s.near_w, s.near_col, s.near_val, X, ld, Y, ld, Yi);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -565,7 +572,7 @@ __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, i
 }
 
 template <int NC>
-void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, hipStream_t st) {
+void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, double* Yi, hipStream_t st) {
     const int nb = (int)((s.npad + kSymBlock - 1) / kSymBlock);
     double* P = static_cast<double*>(split_workspace(s, (uint64_t)nb * NC * s.npad * sizeof(double)));
     if (!s.near_col) throw Error{WFQ_EDEVICE, "the structure has no near-field correction"};
@@ -582,7 +589,7 @@ void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, 
                            s.pos, X, ld, P);
     WFQ_CHECK_LAUNCH();
     hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 64)), dim3(256), 0, st, s.npad, nb, ncol,
-                       P, s.near_w, s.near_col, s.near_val, X, ld, Y, ld);
+                       P, s.near_w, s.near_col, s.near_val, X, ld, Y, ld, Yi);
     WFQ_CHECK_LAUNCH();
 }
 
@@ -599,28 +606,29 @@ bool otf_sym_fits(const Structure& s, int ncol) {
     return s.n >= kSymFrom && otf_sym_bytes(s, ncol) <= cap;
 }
 
-void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st) {
+void otf_narrow_f64(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, int cus, hipStream_t st,
+                    double* Yi) {
     if (ncol <= 0) return;
     if (ncol > 4) throw Error{WFQ_EINVAL, "the narrow matrix-free product takes at most 4 columns"};
     if (otf_sym_fits(s, ncol)) {
         if (ncol == 1)
-            launch_otf_sym<1>(s, X, Y, ld, ncol, st);
+            launch_otf_sym<1>(s, X, Y, ld, ncol, Yi, st);
         else if (ncol == 2)
-            launch_otf_sym<2>(s, X, Y, ld, ncol, st);
+            launch_otf_sym<2>(s, X, Y, ld, ncol, Yi, st);
         else if (ncol == 3)
-            launch_otf_sym<3>(s, X, Y, ld, ncol, st);
+            launch_otf_sym<3>(s, X, Y, ld, ncol, Yi, st);
         else
-            launch_otf_sym<4>(s, X, Y, ld, ncol, st);
+            launch_otf_sym<4>(s, X, Y, ld, ncol, Yi, st);
         return;
     }
     if (ncol == 1)
-        launch_otf_narrow<1>(s, X, Y, ld, ncol, cus, st);
+        launch_otf_narrow<1>(s, X, Y, ld, ncol, cus, Yi, st);
     else if (ncol == 2)
-        launch_otf_narrow<2>(s, X, Y, ld, ncol, cus, st);
+        launch_otf_narrow<2>(s, X, Y, ld, ncol, cus, Yi, st);
     else if (ncol == 3)
-        launch_otf_narrow<3>(s, X, Y, ld, ncol, cus, st);
+        launch_otf_narrow<3>(s, X, Y, ld, ncol, cus, Yi, st);
     else
-        launch_otf_narrow<4>(s, X, Y, ld, ncol, cus, st);
+        launch_otf_narrow<4>(s, X, Y, ld, ncol, cus, Yi, st);
 }
 
 void otf_tx_f32(const Structure& s, const float* X, float* Y, int ncol, hipStream_t st) {

@@ -145,6 +145,7 @@ struct MsWork {
     Buf<double> TV;   // FP64 solves: T u_j of every vector that entered a product, kept for the closing residual
     Buf<double> Sm;   // with TV: U = Q S, S upper triangular, columns in the layout of H
     Buf<double> dots, hp, gam, irho, nu;   // one-reduction Arnoldi: [d][2 (m + 1)], [d][m + 1], [d] x 3
+    Buf<double> Yi;   // FP64 narrow products: the product interleaved, [npad][4], for the SpMM's gathers
     Buf<int> pos;     // system -> packed column of the closing residual's products
     int ngrp = 0;     // groups of ms_xupdate in the last phase
     Buf<double2> sn, g, R, y, z;
@@ -325,6 +326,7 @@ void layout_work(Work& w, const Structure& S, Arena& d, Arena& h) {
         d.take(q.gam, n_dir);
         d.take(q.irho, n_dir);
         d.take(q.nu, n_dir);
+        d.take(q.Yi, (size_t)np * 4);
         d.take(q.h1, (size_t)n_dir * pslots);
         d.take(q.h2, (size_t)n_dir * pslots);
         d.take(q.nrm, (size_t)n_dir * (np / 64));
@@ -554,6 +556,16 @@ void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, h
     const int kc = ncol <= 8 ? (prec == WFQ_PREC_FP64 ? KC_SKINNY : prec == WFQ_PREC_FP32 ? KC_SKINNY_F32 : KC_SKINNY_BF16)
                              : (prec == WFQ_PREC_FP64 ? KC_GEMM_F64 : prec == WFQ_PREC_FP32 ? KC_GEMM_F32 : KC_GEMM_BF16);
     tm.end(st, kc, 2.0 * n * n * ncol, elem_size(prec) * n * n + ncol * n * (elem_size(prec) + out_size(prec)));
+}
+
+// The narrow FP64 product of the multi-shift phase (ncol <= 4 real columns, X64 -> Y64) with the
+// interleaved copy Yi for the SpMM's gathers; the same accounting as block_product's narrow branch.
+void narrow_product_xi(const Structure& S, Work& w, int ncol, double* Yi, Timer& tm, hipStream_t st) {
+    const double n = (double)S.n;
+    tm.begin(st);
+    otf_narrow_f64(S, w.X64.p, w.Y64.p, S.npad, ncol, device_cus(S.device), st, Yi);
+    const double elems = otf_sym_fits(S, ncol) ? 0.5 * n * n : n * n;
+    tm.end(st, KC_OTF_NARROW, elems * 11.0 + n * n * ncol, n * (24.0 + 8.0 * ncol) + n * 8.0 * ncol);
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -931,6 +943,7 @@ uint64_t ms_bytes(const Structure& S, const wfq_solve_opts& o, int B, int n_dir)
     b += (uint64_t)n_dir * m * (m + 1) * 8 * (o.precision == WFQ_PREC_FP64 ? 2 : 1);   // Hessenberg (and S)
     b += (uint64_t)n_dir * (2 * (m + 1) * nwc * 8 + nwc * 8 + (m + 2) * 16);   // partials, h1, h2
     b += (uint64_t)n_dir * (3 * (m + 1) + 3) * 8;                // dots, hp, gamma, 1 / rho, nu
+    b += np * 32;                                                // the interleaved product
     b += (uint64_t)B * (m * (m + 1) / 2) * 16;                   // R, packed
     b += (uint64_t)B * (m * 40 + (m + 1) * 16 + 64);             // cs, sn, y, g, scalars
     return b + (1u << 20);
@@ -1106,10 +1119,16 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
                 tm.begin(st);
                 ms_pack(cur, V, np, mdim1, j, dirs, na, inv_h, x_block(w, cur), np, st);
                 tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(cur)));
-                block_product(S, w, cur, na, tm, st);
+                const double* yi = nullptr;
+                if (cur == WFQ_PREC_FP64 && na <= 4 && tx_is_otf_narrow(S, cur, na)) {
+                    narrow_product_xi(S, w, na, q.Yi.p, tm, st);
+                    yi = q.Yi.p;
+                } else {
+                    block_product(S, w, cur, na, tm, st);
+                }
                 tm.begin(st);
                 double* tv = keep_tv ? q.TV.p : nullptr;
-                ms_spmm(S, cur == WFQ_PREC_FP64, y_block(w, cur), np, dirs, na, V, mdim1, j + 1, tv, st);
+                ms_spmm(S, cur == WFQ_PREC_FP64, y_block(w, cur), np, dirs, na, V, mdim1, j + 1, tv, st, yi);
                 // L is read once for all directions (up to four per pass)
                 tm.end(st, KC_SPMM, 2.0 * S.nnz * na,
                        12.0 * S.nnz * ((na + 3) / 4) + na * dn * (out_size(cur) + 8 + (tv ? 8 : 0)));

@@ -163,8 +163,9 @@ def _serve_mix() -> Workload:
     jobs = serve_mix_jobs(8)
     j0 = jobs[0]
     return Workload("serve_mix", j0["xyz"], dict(GRAPHENE), j0["omegas_eV"], j0["dirs"],
-                    tol=1e-7, restart=50, precision="fp32",
-                    description="Poisson stream (20 jobs/s) of disk/ribbon/tube spectrum jobs, N in 1k-60k, FP32 + FP64 refinement, 1e-7",
+                    tol=1e-7, restart=50, precision="fp32", algorithm="msgmres",
+                    description="Poisson stream (20 jobs/s) of disk/ribbon/tube spectrum jobs, N in 1k-60k, multi-shift "
+                                "GMRES with FP32 T, then FP64-refined GMRES(50), 1e-7",
                     extra=dict(jobs=serve_mix_jobs))
 
 

@@ -11,11 +11,13 @@
 // Arnoldi process per direction (one T product on a real vector per step, shared by all
 // frequencies) and one small complex Givens recurrence per (frequency, direction) system.
 //
-// Layouts: basis of direction d, slot j at V + (d * mdim1 + j) * npad (FP64, padding rows zero);
-// Hessenberg column j of direction d at H + (d * m + j) * (m + 1) (entries 0..j+1). Per-system
-// arrays are system-minor (entry e of system s at e * S + s, S = systems of the batch), so that the
-// one-thread-per-system Givens step reads and writes consecutive addresses across a wave: rotations
-// cs/sn (m entries), g (m + 1), R packed by columns (column j from entry j (j + 1) / 2).
+// Layouts: basis of direction d, slot j at V + (d * mdim1 + j) * npad (FP64, padding rows zero); the
+// kept products T u_j (FP64 solves) in the same layout; Hessenberg column j of direction d at
+// H + (d * m + j) * (m + 1) (entries 0..j+1), and the triangular factor S of U = Q S likewise.
+// Per-system arrays are system-minor (entry e of system s at e * S + s, S = systems of the batch):
+// rotations cs/sn (m entries), g (m + 1), R packed by columns (column j from entry j (j + 1) / 2).
+// The phase's own orthogonalisation is the one-reduction form below (ms_dcgs_*); ms_dot, ms_update
+// and ms_hcol (two classical Gram-Schmidt passes) remain for the relaxed phase's product-error probe.
 #include <algorithm>
 #include <type_traits>
 

@@ -165,9 +165,6 @@ void ms_reduce(const int* dirs, int ndir, const double* partial, int pslots, int
 // blocks, [d][npad / 64]
 void ms_update(double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, const int* dirs, int ndir,
                const double* h, int pslots, double* norm, hipStream_t st);
-// Hessenberg column j from the two Gram-Schmidt passes and the norm; inv_h[d] = 1 / H_{j+1,j}
-void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const double* h2, int pslots,
-             const double* norm, int64_t n, int64_t npad, double* H, double* inv_h, hipStream_t st);
 // One-reduction Arnoldi step k (DCGS2) on the real bases: fused dots of slot k (u) and, with z, slot
 // k + 1 against slots 0..k into partial[d][e][wc] (ps >= 2 k + 2 entries per direction; reduce with
 // ms_reduce over 2 k + 2, or k + 1 without z)

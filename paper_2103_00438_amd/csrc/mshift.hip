@@ -16,8 +16,8 @@
 // H + (d * m + j) * (m + 1) (entries 0..j+1), and the triangular factor S of U = Q S likewise.
 // Per-system arrays are system-minor (entry e of system s at e * S + s, S = systems of the batch):
 // rotations cs/sn (m entries), g (m + 1), R packed by columns (column j from entry j (j + 1) / 2).
-// The phase's own orthogonalisation is the one-reduction form below (ms_dcgs_*); ms_dot, ms_update
-// and ms_hcol (two classical Gram-Schmidt passes) remain for the relaxed phase's product-error probe.
+// The phase's own orthogonalisation is the one-reduction form below (ms_dcgs_*); ms_dot and ms_update
+// serve the starting norms and the relaxed phase's product-error probe.
 #include <algorithm>
 #include <type_traits>
 
@@ -173,30 +173,6 @@ __global__ void __launch_bounds__(256) ms_update_kernel(double* __restrict__ V, 
             const double s2 = wave_sum(x * x);
             if (r == 0) norm[(int64_t)d * (npad / kMsRows) + blockIdx.x] = s2;
         }
-    }
-}
-
-// Hessenberg column j of direction d: H_ij = h1_i + h2_i (two Gram-Schmidt passes), H_{j+1,j} = ||w||;
-// inv_h[d] = 1 / ||w|| normalises the next basis vector. The block partials of ||w||^2 are summed by
-// the two waves of the work-group (thread t the partials t, t + 128, ... in order, then a fixed
-// butterfly and the two waves' sums in order).
-__global__ void __launch_bounds__(128) ms_hcol_kernel(const int* __restrict__ dirs, int j, int m,
-                                                      const double* __restrict__ h1, const double* __restrict__ h2,
-                                                      int pslots, const double* __restrict__ norm, int64_t nblk,
-                                                      double* __restrict__ H, double* __restrict__ inv_h) {
-    __shared__ double sh[2];
-    const int d = dirs[blockIdx.x];
-    double* col = H + ((int64_t)d * m + j) * (m + 1);
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h1[(int64_t)d * pslots + i] + h2[(int64_t)d * pslots + i];
-    double s = 0.0;
-    for (int64_t q = threadIdx.x; q < nblk; q += 128) s += norm[(int64_t)d * nblk + q];
-    s = wave_sum(s);
-    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const double hn = sqrt(sh[0] + sh[1]);
-        col[j + 1] = hn;
-        inv_h[d] = hn > 0.0 ? 1.0 / hn : 0.0;
     }
 }
 
@@ -675,15 +651,6 @@ void ms_update(double* V, int64_t n, int64_t npad, int mdim1, int nvec, int jw, 
     if (ndir <= 0) return;
     dim3 grd((unsigned)(npad / kMsRows), (unsigned)ndir);
     hipLaunchKernelGGL(ms_update_kernel, grd, dim3(256), 0, st, V, n, npad, mdim1, nvec, jw, dirs, h, pslots, norm);
-    WFQ_CHECK_LAUNCH();
-}
-
-void ms_hcol(const int* dirs, int ndir, int j, int m, const double* h1, const double* h2, int pslots,
-             const double* norm, int64_t n, int64_t npad, double* H, double* inv_h, hipStream_t st) {
-    if (ndir <= 0) return;
-    (void)n;
-    hipLaunchKernelGGL(ms_hcol_kernel, dim3((unsigned)ndir), dim3(128), 0, st, dirs, j, m, h1, h2, pslots, norm,
-                       npad / kMsRows, H, inv_h);
     WFQ_CHECK_LAUNCH();
 }
 

@@ -184,6 +184,29 @@ def test_fcc120k_multishift_full_solution(lib):
     _check_full_solution(wl, out, om, dirs, wl.tol, 13)
 
 
+@pytest.mark.parametrize("nd", [1, 4])
+def test_multishift_symmetric_products_one_and_four_directions(lib, nd):
+    # multi-shift FP64 on a 70 249-atom FCC sphere (symmetric narrow products, last block partial) with
+    # one field direction and with four (x, y, z and the body diagonal: 4-column products and SpMM
+    # gathers); every result checked row by row by the oracle, with charge conservation and reciprocity
+    from types import SimpleNamespace
+    par = dict(wi.workloads.FCC_METAL)
+    xyz = geo.jitter(geo.fcc_sphere(66.0), 0.02, 11)
+    wl = SimpleNamespace(xyz=xyz, params=par, n=len(xyz))
+    dirs = np.array([[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0], [1.0, 1.0, 1.0]])[:nd]
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    om = np.array([2.2, 3.6])
+    tol = 1e-7
+    h = lib.wfq_build(xyz, par, t_mode="otf")
+    out = lib.wfq_solve(h, om, dirs, tol, restart=100, precision="fp64", algorithm="msgmres", shift_dim=1500)
+    bnorm = np.linalg.norm(lib.wfq_rhs(h, dirs), axis=1)
+    h.close()
+    assert out["status"] == 0, out["info"]
+    assert max(r["relres"] for r in out["info"]) <= tol
+    assert all(r["cycles"] == 0 for r in out["info"]), [r["cycles"] for r in out["info"]]
+    _check_full_solution(wl, out, om, dirs, tol, 17 + nd, bnorm=bnorm)
+
+
 def test_sheet1m_multishift_full_solution(lib):
     # the full 10^6-atom sheet, matrix-free: 1 frequency x 2 in-plane directions by multi-shift GMRES
     # in FP64 (every T element recomputed in every product), checked row by row by the oracle

@@ -726,7 +726,7 @@ def bench_serve(args, wl, wfq, torch):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps(dict(error="this build runs on one GPU only; --gpus must be 1")))
+        print(json.dumps(dict(error="the library runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design, not an implementation)")))
         sys.exit(2)
     import torch
     import wfq_inputs as wi

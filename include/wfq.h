@@ -150,7 +150,10 @@ typedef struct {
                             Per direction the Arnoldi process runs on the real matrix L T from b_k until
                             every frequency's shifted least-squares residual is <= tol ||b_k|| or the
                             dimension is reached; each system then continues from that iterate in
-                            batched GMRES(restart) with FP64 refinement (usually: one FP64 residual). */
+                            batched GMRES(restart) with FP64 refinement (usually: one FP64 residual).
+                            Device memory per direction: 8 (shift_dim + 1) N_p bytes for the basis, and
+                            as much again in FP64 solves, which keep the products T u_j so that the FP64
+                            residual of the shared-basis iterates needs no further product of T. */
     int32_t graphs;      /* nonzero: for structures of at most 8192 atoms (whose inner steps are read back in
                             chunks of 8) and for the multi-shift phase, a chunk of steps whose launch
                             sequence repeats (same first step, length and list sizes) is captured as a HIP

@@ -534,10 +534,19 @@ const void* y_block(Work& w, int prec) {
 }
 
 // One T X block product for the columns of one precision group (X already packed).
-void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, hipStream_t st) {
+// Y = T X on the solve's product block. With Yi (a narrow FP64 product of at most 4 columns) the
+// product is also written interleaved into Yi (rows of 4 doubles) for the multi-shift SpMM's gathers.
+void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, hipStream_t st,
+                   double* Yi = nullptr) {
     const double n = (double)S.n;
     tm.begin(st);
-    tx_any(S, prec, x_block(w, prec), const_cast<void*>(y_block(w, prec)), ncol, st);
+    if (Yi) {
+        if (prec != WFQ_PREC_FP64 || ncol > 4 || !tx_is_otf_narrow(S, prec, ncol))
+            throw Error{WFQ_EINVAL, "block_product: the interleaved copy needs a narrow FP64 product"};
+        otf_narrow_f64(S, w.X64.p, w.Y64.p, S.npad, ncol, device_cus(S.device), st, Yi);
+    } else {
+        tx_any(S, prec, x_block(w, prec), const_cast<void*>(y_block(w, prec)), ncol, st);
+    }
     if (tx_is_otf_narrow(S, prec, ncol)) {
         // work: per element 3 differences, 3 operations for r^2, the reciprocal square root and 4 for
         // its Newton step, and one multiply-add per column and row (the near-field correction is a
@@ -556,16 +565,6 @@ void block_product(const Structure& S, Work& w, int prec, int ncol, Timer& tm, h
     const int kc = ncol <= 8 ? (prec == WFQ_PREC_FP64 ? KC_SKINNY : prec == WFQ_PREC_FP32 ? KC_SKINNY_F32 : KC_SKINNY_BF16)
                              : (prec == WFQ_PREC_FP64 ? KC_GEMM_F64 : prec == WFQ_PREC_FP32 ? KC_GEMM_F32 : KC_GEMM_BF16);
     tm.end(st, kc, 2.0 * n * n * ncol, elem_size(prec) * n * n + ncol * n * (elem_size(prec) + out_size(prec)));
-}
-
-// The narrow FP64 product of the multi-shift phase (ncol <= 4 real columns, X64 -> Y64) with the
-// interleaved copy Yi for the SpMM's gathers; the same accounting as block_product's narrow branch.
-void narrow_product_xi(const Structure& S, Work& w, int ncol, double* Yi, Timer& tm, hipStream_t st) {
-    const double n = (double)S.n;
-    tm.begin(st);
-    otf_narrow_f64(S, w.X64.p, w.Y64.p, S.npad, ncol, device_cus(S.device), st, Yi);
-    const double elems = otf_sym_fits(S, ncol) ? 0.5 * n * n : n * n;
-    tm.end(st, KC_OTF_NARROW, elems * 11.0 + n * n * ncol, n * (24.0 + 8.0 * ncol) + n * 8.0 * ncol);
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -1119,13 +1118,8 @@ void msgmres_phase(const Structure& S, Work& w, std::vector<SysState>& ss, doubl
                 tm.begin(st);
                 ms_pack(cur, V, np, mdim1, j, dirs, na, inv_h, x_block(w, cur), np, st);
                 tm.end(st, KC_PACK, 0, na * dn * (16.0 + elem_size(cur)));
-                const double* yi = nullptr;
-                if (cur == WFQ_PREC_FP64 && na <= 4 && tx_is_otf_narrow(S, cur, na)) {
-                    narrow_product_xi(S, w, na, q.Yi.p, tm, st);
-                    yi = q.Yi.p;
-                } else {
-                    block_product(S, w, cur, na, tm, st);
-                }
+                double* yi = cur == WFQ_PREC_FP64 && na <= 4 && tx_is_otf_narrow(S, cur, na) ? q.Yi.p : nullptr;
+                block_product(S, w, cur, na, tm, st, yi);
                 tm.begin(st);
                 double* tv = keep_tv ? q.TV.p : nullptr;
                 ms_spmm(S, cur == WFQ_PREC_FP64, y_block(w, cur), np, dirs, na, V, mdim1, j + 1, tv, st, yi);

@@ -430,34 +430,55 @@ void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t l
 // pair (B(i), K) or the source side of (K, B(i)); a diagonal pair (I, I) computes its rows one-sided
 // over all of I), and the sum kernel adds the blocks in order with the near-field correction.
 // kMask: the pair involves the last block, which holds padding atoms (their contributions are 0).
+// Coordinates inside a work-group are taken relative to an origin o between the two blocks (the
+// midpoint of their first atoms). For a pair whose atoms are far apart compared with their distance
+// from o, r^2 is expanded as |x_i - o|^2 + |x_j - o|^2 - 2 (x_i - o).(x_j - o): one addition and three
+// fused multiply-adds instead of three subtractions, a product and two fused multiply-adds. Its
+// rounding error grows with kappa = (|x_i - o|^2 + |x_j - o|^2) / r^2, so it is used only for a
+// (wave, source group) pair whose bounding spheres keep kappa <= kSymKappa for every pair of atoms
+// (relative error of the element below about 4 kappa u in the worst case, u = 2^-53); other pairs,
+// and the diagonal blocks, take the differences. Each thread holds its targets as a = -2 (x_i - o),
+// from which x_i - o is recovered exactly, and |x_i - o|^2; LDS holds the sources' x_j - o, |x_j - o|^2
+// and their NC columns of X, one row of 4 + NC values per source, padded to an odd number of doubles
+// so that the 64 lanes' rows fall in distinct LDS banks.
+constexpr double kSymKappa = 256.0;
+template <int NC>
+constexpr int sym_row() { return (4 + NC) | 1; }
+
 // One group of 64 sources against the thread's TK targets; with SIDE the source-side sums rotate as
 // described above and land in red[wave][c][g + lane]. The group sits twice in a row in LDS (rows
 // 2g .. 2g + 127, row 2g + 64 + q a copy of row 2g + q), so step t reads row 2g + lane + t with no
 // wrap-around. The element is taken as G = y (3 - r^2 y^2), twice the Newton-refined 1/r (one
-// operation fewer); the sums are halved when they are stored.
-template <int NC, bool SIDE, bool DIAG, bool MASK>
-__device__ __forceinline__ void sym_group(const double* __restrict__ sx, const double* __restrict__ sy,
-                                          const double* __restrict__ sz, const double (*sX)[512], int g, int lane,
-                                          int64_t j0, int64_t n, const double (&xi)[kSymTK], const double (&yi)[kSymTK],
-                                          const double (&zi)[kSymTK], const double (&xt)[kSymTK][NC],
-                                          const bool (&tin)[kSymTK], double (&acc)[kSymTK][NC], double (*red)[256], int wave) {
+// operation fewer); the sums are halved when they are stored. EXP: r^2 by the expansion.
+template <int NC, bool SIDE, bool DIAG, bool MASK, bool EXP>
+__device__ __forceinline__ void sym_group(const double* __restrict__ srow, int g, int lane, int64_t j0, int64_t n,
+                                          const double (&ax)[kSymTK], const double (&ay)[kSymTK],
+                                          const double (&az)[kSymTK], const double (&ni)[kSymTK],
+                                          const double (&xt)[kSymTK][NC], const bool (&tin)[kSymTK],
+                                          double (&acc)[kSymTK][NC], double (*red)[256], int wave) {
+    constexpr int ROW = sym_row<NC>();
     double ps[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) ps[c] = 0.0;
-    const int row = 2 * g + lane;
+    const double* rp = srow + (2 * g + lane) * ROW;
     constexpr int kUnroll = NC <= 3 ? 4 : 2;   // measured best; 4 columns need the registers
 #pragma unroll kUnroll
     for (int t = 0; t < 64; ++t) {
-        const int q = row + t;
-        const double xs = sx[q], ys = sy[q], zs = sz[q];
+        const double* r = rp + t * ROW;
+        const double xs = r[0], ys = r[1], zs = r[2];
         double xv[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) xv[c] = sX[c][q];
+        for (int c = 0; c < NC; ++c) xv[c] = r[4 + c];
         const bool sv = !MASK || j0 + g + ((lane + t) & 63) < n;
 #pragma unroll
         for (int k = 0; k < kSymTK; ++k) {
-            const double dx = xi[k] - xs, dy = yi[k] - ys, dz = zi[k] - zs;
-            const double r2 = dx * dx + dy * dy + dz * dz;
+            double r2;
+            if (EXP) {
+                r2 = fma(ax[k], xs, fma(ay[k], ys, fma(az[k], zs, ni[k] + r[3])));
+            } else {
+                const double dx = fma(-0.5, ax[k], -xs), dy = fma(-0.5, ay[k], -ys), dz = fma(-0.5, az[k], -zs);
+                r2 = dx * dx + dy * dy + dz * dz;
+            }
             double gk = __builtin_amdgcn_rsq(r2);
             gk = gk * fma(-r2, gk * gk, 3.0);
             if (DIAG) gk = r2 > 0.0 ? gk : 0.0;
@@ -479,15 +500,31 @@ __device__ __forceinline__ void sym_group(const double* __restrict__ sx, const d
     }
 }
 
+// Whether the 64-atom blocks tb (targets) and sb (sources) keep kappa <= kSymKappa (see above) for every
+// pair of their atoms, by their bounding spheres (centre c, radius R): with gap = |c_t - c_s| - R_t -
+// R_s > 0, r >= gap and |x - o| <= |c - o| + R on each side. The radii are widened by a relative 1e-12
+// for their own rounding.
+__device__ inline bool expansion_ok(const double* __restrict__ sph, int64_t tb, int64_t sb, double ox, double oy,
+                                    double oz) {
+    const double* a = sph + tb * 4;
+    const double* b = sph + sb * 4;
+    const double ra = a[3] * (1.0 + 1e-12), rb = b[3] * (1.0 + 1e-12);
+    const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    const double gap = sqrt(dx * dx + dy * dy + dz * dz) - ra - rb;
+    const double ea = sqrt((a[0] - ox) * (a[0] - ox) + (a[1] - oy) * (a[1] - oy) + (a[2] - oz) * (a[2] - oz)) + ra;
+    const double eb = sqrt((b[0] - ox) * (b[0] - ox) + (b[1] - oy) * (b[1] - oy) + (b[2] - oz) * (b[2] - oz)) + rb;
+    return gap > 0.0 && ea * ea + eb * eb <= kSymKappa * gap * gap;
+}
+
 // jfix < 0: the work-group index enumerates the pairs I <= J < nbt in row-major order of I;
 // jfix >= 0: the pair is (blockIdx.x, jfix)
 template <int NC, bool MASK>
 __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, int nbt, int jfix,
-                                                      const double* __restrict__ pos, const double* __restrict__ X,
+                                                      const double* __restrict__ pos,
+                                                      const double* __restrict__ sph, const double* __restrict__ X,
                                                       int64_t ldx, double* __restrict__ P) {
-    constexpr int TK = kSymTK, TILE = 256, BS = kSymBlock;
-    __shared__ double sx[2 * TILE], sy[2 * TILE], sz[2 * TILE];   // each group of 64 twice
-    __shared__ double sX[NC][2 * TILE];
+    constexpr int TK = kSymTK, TILE = 256, BS = kSymBlock, ROW = sym_row<NC>();
+    __shared__ double srow[2 * TILE * ROW];   // each group of 64 twice
     __shared__ double red[4 * NC][TILE];
     int I = 0, J = 0;
     if (jfix >= 0) {
@@ -503,17 +540,33 @@ __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, i
     }
     const bool diag = I == J;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int64_t ib = (int64_t)I * BS + wave * 64 * TK + lane;   // target k: ib + 64 k
-    double xi[TK], yi[TK], zi[TK], xt[TK][NC], acc[TK][NC];
+    // the origin: midpoint of the first atoms of I and J (both < n)
+    const int64_t i0 = (int64_t)I * BS, j00 = min((int64_t)J * BS, n - 1);
+    const double ox = 0.5 * (pos[i0] + pos[j00]), oy = 0.5 * (pos[npad + i0] + pos[npad + j00]),
+                 oz = 0.5 * (pos[2 * npad + i0] + pos[2 * npad + j00]);
+    // expansion flags of this wave: lane 16 t + 4 q + k checks target block k of the wave against
+    // source group q of tile t; group q of tile t may use the expansion when all four of its bits are set
+    uint64_t eflags = 0;
+    if (!diag) {
+        const int64_t tb = (i0 + wave * 64 * TK) / 64 + (lane & 3);
+        const int64_t sb = (int64_t)J * BS / 64 + (lane >> 2);
+        // blocks without atoms have no sphere to test; nothing of theirs is used
+        const bool ok = tb * 64 >= n || sb * 64 >= n || expansion_ok(sph, tb, sb, ox, oy, oz);
+        eflags = __ballot(ok);
+    }
+    const int64_t ib = i0 + wave * 64 * TK + lane;   // target k: ib + 64 k
+    double ax[TK], ay[TK], az[TK], ni[TK], xt[TK][NC], acc[TK][NC];
     bool tin[TK];
 #pragma unroll
     for (int k = 0; k < TK; ++k) {
         const int64_t i = ib + 64 * k;
         const int64_t ii = i < npad ? i : 0;
         tin[k] = i < n;
-        xi[k] = pos[ii];
-        yi[k] = pos[npad + ii];
-        zi[k] = pos[2 * npad + ii];
+        const double x = pos[ii] - ox, y = pos[npad + ii] - oy, z = pos[2 * npad + ii] - oz;
+        ax[k] = -2.0 * x;
+        ay[k] = -2.0 * y;
+        az[k] = -2.0 * z;
+        ni[k] = x * x + y * y + z * z;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             xt[k][c] = tin[k] ? X[c * ldx + ii] : 0.0;
@@ -528,20 +581,27 @@ __global__ void __launch_bounds__(256) otf_sym_kernel(int64_t n, int64_t npad, i
             const int64_t j = j0 + tid;
             const int64_t jj = j < npad ? j : 0;
             const int r0 = 2 * (tid & ~63) + (tid & 63);   // row of source tid, and its copy 64 later
-            const double px = pos[jj], py = pos[npad + jj], pz = pos[2 * npad + jj];
-            sx[r0] = sx[r0 + 64] = px;
-            sy[r0] = sy[r0 + 64] = py;
-            sz[r0] = sz[r0 + 64] = pz;
+            const double x = pos[jj] - ox, y = pos[npad + jj] - oy, z = pos[2 * npad + jj] - oz;
+            double v[ROW] = {};
+            v[0] = x;
+            v[1] = y;
+            v[2] = z;
+            v[3] = x * x + y * y + z * z;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) sX[c][r0] = sX[c][r0 + 64] = j < n ? X[c * ldx + jj] : 0.0;
+            for (int c = 0; c < NC; ++c) v[4 + c] = j < n ? X[c * ldx + jj] : 0.0;
+#pragma unroll
+            for (int f = 0; f < ROW; ++f) srow[r0 * ROW + f] = srow[(r0 + 64) * ROW + f] = v[f];
         }
         __syncthreads();
         for (int g = 0; g < TILE; g += 64) {
             if (MASK && j0 + g >= n) break;   // uniform: the rest of the tile is padding
+            const int q = (t0 + g) / 64;
             if (diag)
-                sym_group<NC, false, true, MASK>(sx, sy, sz, sX, g, lane, j0, n, xi, yi, zi, xt, tin, acc, red, wave);
+                sym_group<NC, false, true, MASK, false>(srow, g, lane, j0, n, ax, ay, az, ni, xt, tin, acc, red, wave);
+            else if (((eflags >> (4 * q)) & 0xF) == 0xF)
+                sym_group<NC, true, false, MASK, true>(srow, g, lane, j0, n, ax, ay, az, ni, xt, tin, acc, red, wave);
             else
-                sym_group<NC, true, false, MASK>(sx, sy, sz, sX, g, lane, j0, n, xi, yi, zi, xt, tin, acc, red, wave);
+                sym_group<NC, true, false, MASK, false>(srow, g, lane, j0, n, ax, ay, az, ni, xt, tin, acc, red, wave);
         }
         if (!diag) {
             __syncthreads();
@@ -575,7 +635,7 @@ template <int NC>
 void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, int ncol, double* Yi, hipStream_t st) {
     const int nb = (int)((s.npad + kSymBlock - 1) / kSymBlock);
     double* P = static_cast<double*>(split_workspace(s, (uint64_t)nb * NC * s.npad * sizeof(double)));
-    if (!s.near_col) throw Error{WFQ_EDEVICE, "the structure has no near-field correction"};
+    if (!s.near_col || !s.sphere) throw Error{WFQ_EDEVICE, "the structure has no near-field correction or block spheres"};
     // pairs within the full blocks need no masks; the pairs with the last block (which holds the
     // padding when n is not a multiple of 1024) run the masked variant
     const bool partial = (int64_t)nb * kSymBlock > s.n;
@@ -583,10 +643,10 @@ void launch_otf_sym(const Structure& s, const double* X, double* Y, int64_t ld, 
     const int64_t pairs = (int64_t)nbt * (nbt + 1) / 2;
     if (pairs > 0)
         hipLaunchKernelGGL((otf_sym_kernel<NC, false>), dim3((unsigned)pairs), dim3(256), 0, st, s.n, s.npad, nbt, -1,
-                           s.pos, X, ld, P);
+                           s.pos, s.sphere, X, ld, P);
     if (partial)
         hipLaunchKernelGGL((otf_sym_kernel<NC, true>), dim3((unsigned)nb), dim3(256), 0, st, s.n, s.npad, nb, nb - 1,
-                           s.pos, X, ld, P);
+                           s.pos, s.sphere, X, ld, P);
     WFQ_CHECK_LAUNCH();
     hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 64)), dim3(256), 0, st, s.npad, nb, ncol,
                        P, s.near_w, s.near_col, s.near_val, X, ld, Y, ld, Yi);

@@ -261,8 +261,9 @@ __global__ void __launch_bounds__(256) otf_kernel(int64_t n, int64_t npad, const
 // for a run of source atoms and accumulates T_ij x_j for every column in FP64 registers. The grid's
 // second dimension splits the sources into parts so that thousands of waves are in flight; each
 // part's sums go to a work space and a second kernel adds the parts in order (deterministic).
-// Sources come in tiles of 256 atoms (positions, squared widths and the X values staged in LDS and
-// read by broadcast; every LDS read serves TK pairs). Every pair takes the far-field value
+// Sources come in tiles of 256 atoms (coordinates relative to the work-group's first atom, their squared
+// norms and the X values staged in LDS and read by broadcast; every LDS read serves TK pairs); a tile
+// far from a wave's targets takes r^2 by the expansion described below. Every pair takes the far-field value
 // T_ij = 1 / r_ij (hardware reciprocal square root refined by one Newton step; 0 on the diagonal),
 // with no branch; the sum kernel then adds the structure's sparse near-field correction
 // C = T - 1/r (pairs closer than rfar, eta_i on the diagonal), so the result is T X.
@@ -272,14 +273,42 @@ constexpr int64_t kSymFrom = 65536;   // the symmetric form from here: at least 
 constexpr int kSymTK = 4;                 // symmetric form: targets per thread
 constexpr int kSymBlock = 256 * kSymTK;   // atoms per block (one work-group's targets)
 
+// Distances by expansion. Coordinates inside a work-group are taken relative to an origin o near its
+// atoms. For a pair whose atoms are far apart compared with their distance from o, r^2 is expanded as
+// |x_i - o|^2 + |x_j - o|^2 - 2 (x_i - o).(x_j - o): one addition and three fused multiply-adds instead of
+// three subtractions, a product and two fused multiply-adds. Its rounding error grows with
+// kappa = (|x_i - o|^2 + |x_j - o|^2) / r^2, so it is used only where the bounding spheres of the two
+// 64-atom blocks keep kappa <= kExpKappa for every pair of their atoms (relative error of the element
+// below about 4 kappa u in the worst case, u = 2^-53); other pairs take the differences. A thread holds
+// its targets as a = -2 (x_i - o), from which x_i - o is recovered exactly, and |x_i - o|^2; LDS holds the
+// sources' x_j - o and |x_j - o|^2.
+constexpr double kExpKappa = 256.0;
+
+// Whether the 64-atom blocks tb (targets) and sb (sources) keep kappa <= kExpKappa for every
+// pair of their atoms, by their bounding spheres (centre c, radius R): with gap = |c_t - c_s| - R_t -
+// R_s > 0, r >= gap and |x - o| <= |c - o| + R on each side. The radii are widened by a relative 1e-12
+// for their own rounding.
+__device__ inline bool expansion_ok(const double* __restrict__ sph, int64_t tb, int64_t sb, double ox, double oy,
+                                    double oz) {
+    const double* a = sph + tb * 4;
+    const double* b = sph + sb * 4;
+    const double ra = a[3] * (1.0 + 1e-12), rb = b[3] * (1.0 + 1e-12);
+    const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    const double gap = sqrt(dx * dx + dy * dy + dz * dz) - ra - rb;
+    const double ea = sqrt((a[0] - ox) * (a[0] - ox) + (a[1] - oy) * (a[1] - oy) + (a[2] - oz) * (a[2] - oz)) + ra;
+    const double eb = sqrt((b[0] - ox) * (b[0] - ox) + (b[1] - oy) * (b[1] - oy) + (b[2] - oz) * (b[2] - oz)) + rb;
+    return gap > 0.0 && ea * ea + eb * eb <= kExpKappa * gap * gap;
+}
+
 // The pairs of one staged source tile with this thread's TK targets. kDiag: the tile may hold one of
 // the targets themselves (r = 0), whose far-field value is replaced by 0 (the diagonal is in the
-// near-field correction); other tiles skip that test.
-template <int NC, bool kDiag>
+// near-field correction); other tiles skip that test. kExp: r^2 by the expansion.
+template <int NC, bool kDiag, bool kExp>
 __device__ __forceinline__ void narrow_tile(const double* __restrict__ sx, const double* __restrict__ sy,
-                                            const double* __restrict__ sz, const double (*sX)[kNarrowTile], int cnt,
-                                            const double (&xi)[kNarrowTK], const double (&yi)[kNarrowTK],
-                                            const double (&zi)[kNarrowTK], double (&acc)[kNarrowTK][NC]) {
+                                            const double* __restrict__ sz, const double* __restrict__ sn,
+                                            const double (*sX)[kNarrowTile], int cnt, const double (&ax)[kNarrowTK],
+                                            const double (&ay)[kNarrowTK], const double (&az)[kNarrowTK],
+                                            const double (&ni)[kNarrowTK], double (&acc)[kNarrowTK][NC]) {
 #pragma unroll 2
     for (int q = 0; q < cnt; ++q) {
         const double xs = sx[q], ys = sy[q], zs = sz[q];
@@ -288,8 +317,13 @@ __device__ __forceinline__ void narrow_tile(const double* __restrict__ sx, const
         for (int c = 0; c < NC; ++c) xv[c] = sX[c][q];
 #pragma unroll
         for (int k = 0; k < kNarrowTK; ++k) {
-            const double dx = xi[k] - xs, dy = yi[k] - ys, dz = zi[k] - zs;
-            const double r2 = dx * dx + dy * dy + dz * dz;
+            double r2;
+            if (kExp) {
+                r2 = fma(ax[k], xs, fma(ay[k], ys, fma(az[k], zs, ni[k] + sn[q])));
+            } else {
+                const double dx = fma(-0.5, ax[k], -xs), dy = fma(-0.5, ay[k], -ys), dz = fma(-0.5, az[k], -zs);
+                r2 = dx * dx + dy * dy + dz * dz;
+            }
             double g = __builtin_amdgcn_rsq(r2);
             // one Newton step for 1/sqrt(r2): g <- g (3 - r2 g^2) / 2
             g = g * fma(-0.5 * r2, g * g, 1.5);
@@ -302,16 +336,20 @@ __device__ __forceinline__ void narrow_tile(const double* __restrict__ sx, const
 
 template <int NC>
 __global__ void __launch_bounds__(256) otf_narrow_f64_kernel(int64_t n, int64_t npad, const double* __restrict__ pos,
+                                                             const double* __restrict__ sph,
                                                              const double* __restrict__ X, int64_t ldx,
                                                              double* __restrict__ part, int64_t src_per_part) {
     constexpr int TK = kNarrowTK;
-    __shared__ double sx[kNarrowTile], sy[kNarrowTile], sz[kNarrowTile];
+    __shared__ double sx[kNarrowTile], sy[kNarrowTile], sz[kNarrowTile], sn[kNarrowTile];
     __shared__ double sX[NC][kNarrowTile];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     // targets of the work-group: [it0, it0 + 256 TK); of this thread: ib + 64 k + lane
     const int64_t it0 = (int64_t)blockIdx.x * 256 * TK;
     const int64_t ib = it0 + (int64_t)wave * 64 * TK;
-    double xi[TK], yi[TK], zi[TK];
+    // the origin: the work-group's first atom
+    const int64_t i0 = min(it0, n - 1);
+    const double ox = pos[i0], oy = pos[npad + i0], oz = pos[2 * npad + i0];
+    double ax[TK], ay[TK], az[TK], ni[TK];
     bool tin[TK];
     double acc[TK][NC];
 #pragma unroll
@@ -319,30 +357,40 @@ __global__ void __launch_bounds__(256) otf_narrow_f64_kernel(int64_t n, int64_t 
         const int64_t i = ib + 64 * k + lane;
         const int64_t ii = i < npad ? i : 0;
         tin[k] = i < n;
-        xi[k] = pos[ii];
-        yi[k] = pos[npad + ii];
-        zi[k] = pos[2 * npad + ii];
+        const double x = pos[ii] - ox, y = pos[npad + ii] - oy, z = pos[2 * npad + ii] - oz;
+        ax[k] = -2.0 * x;
+        ay[k] = -2.0 * y;
+        az[k] = -2.0 * z;
+        ni[k] = x * x + y * y + z * z;
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[k][c] = 0.0;
     }
     const int64_t jb = (int64_t)blockIdx.y * src_per_part;
     const int64_t je = min(n, jb + src_per_part);   // padding sources contribute nothing
     for (int64_t j0 = jb; j0 < je; j0 += kNarrowTile) {
+        // lane 4 q + k (< 16) checks the wave's target block k against the tile's source block q
+        const int64_t tb = ib / 64 + (lane & 3), sb = j0 / 64 + ((lane >> 2) & 3);
+        const bool ok = lane >= 16 || tb * 64 >= n || sb * 64 >= n || expansion_ok(sph, tb, sb, ox, oy, oz);
+        const bool use_exp = __ballot(ok) == ~0ull;
         __syncthreads();
         {
             const int64_t j = j0 + tid;   // < npad
-            sx[tid] = pos[j];
-            sy[tid] = pos[npad + j];
-            sz[tid] = pos[2 * npad + j];
+            const double x = pos[j] - ox, y = pos[npad + j] - oy, z = pos[2 * npad + j] - oz;
+            sx[tid] = x;
+            sy[tid] = y;
+            sz[tid] = z;
+            sn[tid] = x * x + y * y + z * z;
 #pragma unroll
             for (int c = 0; c < NC; ++c) sX[c][tid] = X[c * ldx + j];
         }
         __syncthreads();
         const int cnt = (int)min((int64_t)kNarrowTile, je - j0);
         if (j0 < it0 + 256 * TK && j0 + kNarrowTile > it0)
-            narrow_tile<NC, true>(sx, sy, sz, sX, cnt, xi, yi, zi, acc);
+            narrow_tile<NC, true, false>(sx, sy, sz, sn, sX, cnt, ax, ay, az, ni, acc);
+        else if (use_exp)
+            narrow_tile<NC, false, true>(sx, sy, sz, sn, sX, cnt, ax, ay, az, ni, acc);
         else
-            narrow_tile<NC, false>(sx, sy, sz, sX, cnt, xi, yi, zi, acc);
+            narrow_tile<NC, false, false>(sx, sy, sz, sn, sX, cnt, ax, ay, az, ni, acc);
     }
 #pragma unroll
     for (int k = 0; k < TK; ++k) {
@@ -407,9 +455,9 @@ void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t l
     const int64_t per = round_up((s.npad + nparts - 1) / nparts, kNarrowTile);
     nparts = (int)((s.npad + per - 1) / per);
     double* part = static_cast<double*>(split_workspace(s, (uint64_t)nparts * NC * s.npad * sizeof(double)));
-    if (!s.near_col) throw Error{WFQ_EDEVICE, "the structure has no near-field correction"};
+    if (!s.near_col || !s.sphere) throw Error{WFQ_EDEVICE, "the structure has no near-field correction or block spheres"};
     hipLaunchKernelGGL((otf_narrow_f64_kernel<NC>), dim3((unsigned)tblocks, (unsigned)nparts), dim3(256), 0, st, s.n,
-                       s.npad, s.pos, X, ld, part, per);
+                       s.npad, s.pos, s.sphere, X, ld, part, per);
     WFQ_CHECK_LAUNCH();
     hipLaunchKernelGGL(otf_narrow_sum_kernel<NC>, dim3((unsigned)(s.npad / 64)), dim3(256), 0, st, s.npad, nparts,
                        ncol, part, s.near_w, s.near_col, s.near_val, X, ld, Y, ld, Yi);
@@ -430,18 +478,9 @@ void launch_otf_narrow(const Structure& s, const double* X, double* Y, int64_t l
 // pair (B(i), K) or the source side of (K, B(i)); a diagonal pair (I, I) computes its rows one-sided
 // over all of I), and the sum kernel adds the blocks in order with the near-field correction.
 // kMask: the pair involves the last block, which holds padding atoms (their contributions are 0).
-// Coordinates inside a work-group are taken relative to an origin o between the two blocks (the
-// midpoint of their first atoms). For a pair whose atoms are far apart compared with their distance
-// from o, r^2 is expanded as |x_i - o|^2 + |x_j - o|^2 - 2 (x_i - o).(x_j - o): one addition and three
-// fused multiply-adds instead of three subtractions, a product and two fused multiply-adds. Its
-// rounding error grows with kappa = (|x_i - o|^2 + |x_j - o|^2) / r^2, so it is used only for a
-// (wave, source group) pair whose bounding spheres keep kappa <= kSymKappa for every pair of atoms
-// (relative error of the element below about 4 kappa u in the worst case, u = 2^-53); other pairs,
-// and the diagonal blocks, take the differences. Each thread holds its targets as a = -2 (x_i - o),
-// from which x_i - o is recovered exactly, and |x_i - o|^2; LDS holds the sources' x_j - o, |x_j - o|^2
-// and their NC columns of X, one row of 4 + NC values per source, padded to an odd number of doubles
-// so that the 64 lanes' rows fall in distinct LDS banks.
-constexpr double kSymKappa = 256.0;
+// The symmetric kernel takes the origin midway between the first atoms of its two blocks, and one LDS
+// row per source: x_j - o, |x_j - o|^2 and the NC columns of X, padded to an odd number of doubles so
+// that the 64 lanes' rows fall in distinct LDS banks.
 template <int NC>
 constexpr int sym_row() { return (4 + NC) | 1; }
 
@@ -498,22 +537,6 @@ __device__ __forceinline__ void sym_group(const double* __restrict__ srow, int g
 #pragma unroll
         for (int c = 0; c < NC; ++c) red[wave * NC + c][g + lane] = ps[c];
     }
-}
-
-// Whether the 64-atom blocks tb (targets) and sb (sources) keep kappa <= kSymKappa (see above) for every
-// pair of their atoms, by their bounding spheres (centre c, radius R): with gap = |c_t - c_s| - R_t -
-// R_s > 0, r >= gap and |x - o| <= |c - o| + R on each side. The radii are widened by a relative 1e-12
-// for their own rounding.
-__device__ inline bool expansion_ok(const double* __restrict__ sph, int64_t tb, int64_t sb, double ox, double oy,
-                                    double oz) {
-    const double* a = sph + tb * 4;
-    const double* b = sph + sb * 4;
-    const double ra = a[3] * (1.0 + 1e-12), rb = b[3] * (1.0 + 1e-12);
-    const double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
-    const double gap = sqrt(dx * dx + dy * dy + dz * dz) - ra - rb;
-    const double ea = sqrt((a[0] - ox) * (a[0] - ox) + (a[1] - oy) * (a[1] - oy) + (a[2] - oz) * (a[2] - oz)) + ra;
-    const double eb = sqrt((b[0] - ox) * (b[0] - ox) + (b[1] - oy) * (b[1] - oy) + (b[2] - oz) * (b[2] - oz)) + rb;
-    return gap > 0.0 && ea * ea + eb * eb <= kSymKappa * gap * gap;
 }
 
 // jfix < 0: the work-group index enumerates the pairs I <= J < nbt in row-major order of I;

@@ -153,3 +153,38 @@ def test_symmetric_narrow_product_on_a_large_sphere(lib, ncol):
     ref = P.apply_T_rows(rows, X.T)
     bound = P.apply_T_rows(rows, np.abs(X).T)
     assert np.all(np.abs(Y[:, rows].T - ref) <= 1e-13 * bound)
+
+
+@pytest.mark.parametrize("case", ["tube", "sphere"])
+def test_narrow_fp64_product_moved_away_from_the_origin(lib, case):
+    # T depends on distances only. Both narrow FP64 kernels (one-sided on the 1 200-atom tube,
+    # symmetric on a 72k-atom sphere) take coordinates relative to an origin inside the work-group and
+    # form r^2 by expansion where the blocks' bounding spheres keep its rounding small, so the product
+    # of the structure moved by about 1 200 A equals the oracle's (and the unmoved product) to rounding.
+    shift = np.array([700.0, -400.0, 900.0])
+    if case == "tube":
+        xyz, par = ragged_tube(), GRAPHENE
+    else:
+        import wfq_inputs as wi
+        from wfq_inputs import geometry as geo
+        par = wi.workloads.FCC_METAL
+        xyz = geo.jitter(geo.fcc_sphere(66.0), 0.02, 11)
+    n = len(xyz)
+    X = np.random.default_rng(77).standard_normal((3, n))
+    Y = []
+    for p in (xyz, xyz + shift):
+        h = lib.wfq_build(p, par, t_mode="otf")
+        Y.append(lib.wfq_apply_T(h, "fp64", X))
+        h.close()
+    if case == "tube":
+        P = O.Problem(xyz, par)
+        rows = np.arange(n)
+        ref, bound = (X @ P.T).T, (np.abs(X) @ np.abs(P.T)).T
+    else:
+        from oracle.cpp_oracle import CppProblem
+        P = CppProblem(xyz, par, dense_T=False, build_L=False)
+        rows = np.r_[np.arange(0, n, 1499), np.arange(n - 3, n)]
+        ref, bound = P.apply_T_rows(rows, X.T), P.apply_T_rows(rows, np.abs(X).T)
+    for y in Y:
+        assert np.all(np.abs(y[:, rows].T - ref) <= 1e-13 * bound)
+    assert np.all(np.abs(Y[1][:, rows] - Y[0][:, rows]).T <= 2e-13 * bound)
